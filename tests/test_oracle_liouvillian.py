@@ -1,0 +1,214 @@
+"""Oracle pins for the Liouvillian, its start vectors and the Lanczos chains.
+
+Independent references: the transition-space construction (sum over
+transitions with pair densities), the textbook K = 0 Kubo sum from full
+diagonalisations, the spin commutator identity behind the sum rule, the
+Goldstone zero mode, time reversal applied literally, Krylov moments.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chi, dense, grid, lanczos, liouvillian as lv
+
+
+@pytest.fixture(scope="module")
+def tiny_prob(tiny_gs, tiny_q):
+    return lv.build_problem(tiny_gs, tiny_q)
+
+
+@pytest.fixture(scope="module")
+def tiny_ts(tiny_prob):
+    return dense.TransitionSpace(tiny_prob)
+
+
+def test_scf_converged(tiny_gs, cfg1_gs):
+    assert tiny_gs.residual < 1e-12
+    assert cfg1_gs.residual < 1e-10
+    assert cfg1_gs.gaps[0] >= 0.02
+    assert np.linalg.norm(cfg1_gs.magnetization) >= 0.5
+
+
+def test_matrix_free_equals_transition_space(tiny_ts):
+    """P4: the grid-based Liouvillian equals J(D + P^dag F P) column by column."""
+    Lmf = tiny_ts.matrix_free_columns()
+    Ld = tiny_ts.liouvillian()
+    assert np.abs(Lmf - Ld).max() <= 1e-12 * np.abs(Ld).max()
+    Lmf0 = tiny_ts.matrix_free_columns(kernel=False)
+    assert np.abs(Lmf0 - tiny_ts.liouvillian(kernel=False)).max() <= 1e-12 * np.abs(Ld).max()
+
+
+def test_pseudo_hermitian_structure(tiny_ts, tiny_prob):
+    """P5: JL is Hermitian; matrix-free probes a^dag J L b = conj(b^dag J L a)."""
+    Ld = tiny_ts.liouvillian()
+    JL = tiny_ts.Jdiag[:, None] * Ld
+    assert np.abs(JL - JL.conj().T).max() <= 1e-13 * np.abs(JL).max()
+    a = tiny_prob.random_projected(1)
+    b = tiny_prob.random_projected(2)
+    lhs = tiny_prob.dot(a, tiny_prob.J(tiny_prob.apply(b)))
+    rhs = np.conj(tiny_prob.dot(b, tiny_prob.J(tiny_prob.apply(a))))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_output_orthogonal_to_occupied(tiny_prob):
+    y = tiny_prob.apply(tiny_prob.random_projected(5))
+    assert tiny_prob.occupied_overlap(y) < 1e-12 * np.abs(y).max()
+
+
+@pytest.mark.parametrize("lam,mu", [("x", "x"), ("x", "y"), ("y", "x"), ("z", "z"), ("x", "z")])
+def test_k0_matches_kubo_sum(tiny_gs, tiny_prob, tiny_ts, lam, mu):
+    """P2: with the kernel off, (u, (w - L)^{-1} v) is the textbook Kubo sum."""
+    om = np.linspace(-2.0, 2.0, 41)
+    L0 = tiny_ts.liouvillian(kernel=False)
+    cd = tiny_ts.chi_dense(L0, tiny_prob.u_vector(lam), tiny_prob.v_vector(mu), om, 0.05)
+    ck = chi.kubo_k0(tiny_gs, tiny_prob, lam, mu, om, 0.05)
+    scale = max(np.abs(ck).max(), 1.0)
+    assert np.abs(cd - ck).max() <= 1e-12 * scale
+
+
+def test_sum_over_transitions_equals_resolvent(tiny_prob, tiny_ts):
+    om = np.linspace(-1.0, 1.0, 21)
+    L = tiny_ts.liouvillian()
+    u, v = tiny_prob.u_vector("y"), tiny_prob.v_vector("+")
+    cs, lam = tiny_ts.chi_sot(L, u, v, om, 0.05)
+    cd = tiny_ts.chi_dense(L, u, v, om, 0.05)
+    assert np.abs(cs - cd).max() <= 1e-10 * np.abs(cd).max()
+
+
+def test_sum_rule_identity_at_q0(tiny_gs):
+    """P6: (u^l, v^m) = 2 i eps_lmn M_n (the commutator [s_l, s_m] = 2i eps s_n)."""
+    prob = lv.build_problem(tiny_gs, np.zeros(3))
+    # moment of the occupied states themselves (the SCF density differs by its residual)
+    _, evc, _ = prob.point_states[0]
+    M = np.array([np.einsum("nsg,st,ntg->", evc.conj(), lv.DIRECTIONS[c], evc).real for c in "xyz"])
+    assert np.allclose(M, tiny_gs.magnetization, atol=1e-10)
+    eps = np.zeros((3, 3, 3))
+    eps[0, 1, 2] = eps[1, 2, 0] = eps[2, 0, 1] = 1
+    eps[0, 2, 1] = eps[2, 1, 0] = eps[1, 0, 2] = -1
+    for i, l in enumerate("xyz"):
+        for j, m in enumerate("xyz"):
+            val = prob.dot(prob.u_vector(l), prob.v_vector(m))
+            assert abs(val - 2j * eps[i, j] @ M) < 1e-12
+
+
+def test_sum_rule_frequency_integral(tiny_prob):
+    """P6 (integral form): int chi_lm dw = -i pi (u^l, v^m) for any M and eta;
+    checked by numerical quadrature of the Lanczos chi over a wide window."""
+    res = lanczos.run(tiny_prob, "y", "nH", 30)
+    om = np.concatenate([np.linspace(-400, -10, 40001), np.linspace(-10, 10, 200001)[1:-1],
+                         np.linspace(10, 400, 40001)])
+    c = chi.chi_lanczos(res, om, 0.5)
+    integ = np.trapezoid(c[0], om)
+    target = -1j * np.pi * tiny_prob.dot(tiny_prob.u_vector("x"), tiny_prob.v_vector("y"))
+    assert abs(integ - target) <= 0.01 * abs(target)
+
+
+def test_goldstone_zero_mode(tiny_gs_nosoc):
+    """P7: at q = 0 without SOC, the rigid-rotation vectors v^x, v^y are zero modes."""
+    prob = lv.build_problem(tiny_gs_nosoc, np.zeros(3))
+    M = tiny_gs_nosoc.magnetization
+    assert abs(M[0]) < 1e-10 and abs(M[1]) < 1e-10 and abs(M[2]) > 0.5
+    r = prob.random_projected(3)
+    r *= np.linalg.norm(prob.v_vector("x")) / np.linalg.norm(r)
+    ref = np.linalg.norm(prob.apply(r))
+    for mu in "xy":
+        v = prob.v_vector(mu)
+        assert np.linalg.norm(v) > 0.1
+        assert np.linalg.norm(prob.apply(v)) < 1e-8 * ref
+    # exact breakdown of the two-sided chain right at the first step
+    res = lanczos.run(prob, "x", "nH", 5)
+    assert res["breakdown"] and res["steps_done"] == 1
+
+
+def test_time_reversal_shortcut(tiny_gs, tiny_q):
+    """P13: T H_{-k-q} T^{-1} equals H_{k+q} with the B field reversed."""
+    kq = tiny_q
+    m_kq = synth.sphere(tiny_gs.sysd, kq)
+    m_m = synth.sphere(tiny_gs.sysd, -kq)
+    Hp = tiny_gs.hamiltonian(kq, m_kq, bsign=-1.0)
+    Hm = tiny_gs.hamiltonian(-kq, m_m)
+    rng = np.random.default_rng(4)
+    psi = rng.standard_normal((2, len(m_kq))) + 1j * rng.standard_normal((2, len(m_kq)))
+    # T^{-1} = -T for spin 1/2
+    tinv = -grid.time_reverse(m_kq, psi, m_m)
+    h = (Hm @ tinv.ravel()).reshape(2, -1)
+    lhs = grid.time_reverse(m_m, h, m_kq)
+    rhs = (Hp @ psi.ravel()).reshape(2, -1)
+    assert np.abs(lhs - rhs).max() <= 1e-12 * np.abs(rhs).max()
+
+
+@pytest.mark.parametrize("flavour,mu", [("pH", "z"), ("nH", "+"), ("nH", "z")])
+def test_lanczos_moments(tiny_prob, flavour, mu):
+    """P10: (u, L^k v) = n1 z^T T^k e1 for k < M (any Krylov method)."""
+    M = 8
+    res = lanczos.run(tiny_prob, mu, flavour, M)
+    assert res["steps_done"] == M
+    T = chi.tridiag(res, M)
+    v = tiny_prob.v_vector(mu)
+    Lkv = v.copy()
+    e = np.zeros(M, dtype=complex)
+    e[0] = 1
+    for k in range(M - 1):
+        for l, lam in enumerate("xyz"):
+            lhs = tiny_prob.dot(tiny_prob.u_vector(lam), Lkv)
+            rhs = res["n1"] * res["z"][l] @ e
+            scale = np.linalg.norm(Lkv) * np.linalg.norm(tiny_prob.u_vector(lam)) / tiny_prob.nk
+            assert abs(lhs - rhs) <= 1e-11 * scale
+        Lkv = tiny_prob.apply(Lkv)
+        e = T @ e
+
+
+def test_flavours_agree_with_dense(tiny_prob, tiny_ts):
+    """P11: pseudo-Hermitian and non-Hermitian chi converge to the dense resolvent."""
+    om = np.linspace(-3.0, 3.0, 61)
+    L = tiny_ts.liouvillian()
+    v = tiny_prob.v_vector("z")
+    cd = np.array([tiny_ts.chi_dense(L, tiny_prob.u_vector(l), v, om, 0.3) for l in "xyz"])
+    for fl in ("pH", "nH"):
+        res = lanczos.run(tiny_prob, "z", fl, 60)
+        cl = chi.chi_lanczos(res, om, 0.3)
+        assert np.abs(cl - cd).max() <= 1e-6 * np.abs(cd).max(), fl
+    res = lanczos.run(tiny_prob, "+", "nH", 60)
+    cl = chi.chi_lanczos(res, om, 0.3)
+    cd = np.array([tiny_ts.chi_dense(L, tiny_prob.u_vector(l), tiny_prob.v_vector("+"), om, 0.3)
+                   for l in "xyz"])
+    assert np.abs(cl - cd).max() <= 1e-6 * np.abs(cd).max()
+
+
+def test_symmetry_zeros_without_transverse_coupling(tiny_prob):
+    """P9: H commutes with S_z here, so longitudinal and transverse sectors decouple:
+    z^{x,z} = z^{y,z} = 0 and chi_xy = -chi_yx."""
+    res = lanczos.run(tiny_prob, "z", "pH", 20)
+    assert np.abs(res["z"][0]).max() < 1e-13 and np.abs(res["z"][1]).max() < 1e-13
+    om = np.linspace(-1, 1, 11)
+    rx = lanczos.run(tiny_prob, "x", "nH", 40)
+    ry = lanczos.run(tiny_prob, "y", "nH", 40)
+    cxy = chi.chi_lanczos(ry, om, 0.2)[0]
+    cyx = chi.chi_lanczos(rx, om, 0.2)[1]
+    assert np.abs(cxy + cyx).max() <= 1e-6 * np.abs(cxy).max()
+
+
+def test_chi_solvers_agree(tiny_prob):
+    """P14: zgtsv vs continued fraction vs pole-residue."""
+    res = lanczos.run(tiny_prob, "+", "nH", 25)
+    om = np.linspace(-2, 2, 31)
+    c1 = chi.chi_lanczos(res, om, 0.1)
+    c2 = chi.chi_pole_residue(res, om, 0.1)
+    assert np.abs(c1 - c2).max() <= 1e-10 * np.abs(c1).max()
+    cf = chi.continued_fraction_11(res, om, 0.1)
+    z1 = np.zeros_like(res["z"])
+    z1[:, 0] = res["z"][:, 0]
+    c3 = chi.chi_lanczos(dict(res, z=z1), om, 0.1)
+    assert np.abs(c3[0] - res["n1"] * res["z"][0, 0] * cf).max() <= 1e-12 * np.abs(c3[0]).max()
+
+
+def test_cfg1_pseudo_hermitian_probe_and_chain(cfg1_gs, cfg1_q):
+    """cfg1: JL symmetric on random probes; a short pH chain runs without breakdown."""
+    prob = lv.build_problem(cfg1_gs, cfg1_q)
+    a, b = prob.random_projected(11), prob.random_projected(12)
+    lhs = prob.dot(a, prob.J(prob.apply(b)))
+    rhs = np.conj(prob.dot(b, prob.J(prob.apply(a))))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    res = lanczos.run(prob, "+", "pH", 6)
+    assert res["steps_done"] == 6 and not res["breakdown"]
+    assert np.all(res["beta"][:6] > 0)
