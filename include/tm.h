@@ -1,0 +1,200 @@
+/*
+ * tm.h -- C ABI of the MI355X Liouville-Lanczos magnon library (libtm).
+ *
+ * Method: Liouville-Lanczos time-dependent density-functional perturbation
+ * theory for spin-wave spectra, arXiv:2203.01120 (Gorni, Baseggio, Delugas,
+ * Baroni, Timrov).  The library computes, on one AMD Instinct MI355X
+ * (gfx950), the Liouvillian-times-vector product of Sec. 2.4
+ * (Eqs. Liouvillian_BR_q and liouvillian_blocks), the two Lanczos recursions
+ * of Sec. 2.5 built on it, and the susceptibility of Eqs.
+ * resolvent_Liouvillian_Lanczos_q and post_processing.
+ *
+ * Units: Hartree atomic units (bohr, Ha), as in Sec. 2.1.  Spin density
+ * m = psi^dag sigma psi (mu_B = 1).
+ *
+ * Conventions shared by every call:
+ *   - complex numbers are two consecutive doubles (re, im);
+ *   - a lattice-periodic spinor component is
+ *       U(r) = Omega^{-1/2} sum_G c(G) exp(i G.r),  G = m1 b1 + m2 b2 + m3 b3,
+ *     with coefficient arrays laid out [band][spin][G] (spin 0 = up) in the
+ *     order of the Miller list given for that point;
+ *   - grid fields are C-order [n1][n2][n3] on r = (i1/n1) a1 + (i2/n2) a2 + (i3/n3) a3;
+ *   - a batch-representation (BR) vector of q-set iq is complex
+ *       [2 sides][nk][nbnd][2 spins][npw_pad]
+ *     (side 0 = X, side 1 = Y of Eq. batch_rho), each (side, k) block on the
+ *     plane-wave sphere of the point k+q of mesh point k, in the Miller order
+ *     of that point, zero-padded to npw_pad (see tm_qset_info);
+ *   - inner product (a, b) = (1/nk) sum conj(a) b.
+ *
+ * Errors: every call returns an int, TM_OK (0) on success and a negative
+ * code otherwise; tm_last_error() gives a message for the calling thread.
+ * Nothing here falls back to the CPU: a missing or unusable GPU is TM_EDEVICE.
+ */
+#ifndef TM_H
+#define TM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TM_OK = 0,
+    TM_EINVAL = -1,       /* invalid argument or inconsistent input data        */
+    TM_ENOMEM = -2,       /* device allocation failed                           */
+    TM_EDEVICE = -3,      /* HIP runtime or kernel launch error                 */
+    TM_EBREAKDOWN = -4,   /* Lanczos breakdown: result holds the valid prefix   */
+    TM_EUNSUPPORTED = -5  /* size outside what the kernels support (e.g. grid
+                             length with a prime factor other than 2, 3, 5)     */
+};
+
+typedef enum { TM_FP64 = 0, TM_FP32 = 1 } tm_precision;
+
+/* Direction of the perturbing field (Sec. 2.5, Eq. off-diag-resolvent):
+ * sigma^mu = sigma_x, sigma_y, sigma_z, sigma_x + i sigma_y, sigma_x - i sigma_y. */
+typedef enum { TM_DIR_X = 0, TM_DIR_Y = 1, TM_DIR_Z = 2, TM_DIR_PLUS = 3, TM_DIR_MINUS = 4 } tm_dir;
+
+/* Lanczos flavour (Sec. 2.5): non-Hermitian biorthogonalisation (two
+ * applications of L per step) or pseudo-Hermitian (one per step). */
+typedef enum { TM_NONHERMITIAN = 0, TM_PSEUDOHERMITIAN = 1 } tm_flavour;
+
+typedef struct tm_system tm_system;
+
+/*
+ * Description of one system: the ground state of Secs. 2.2 and 3.1 and the
+ * q-points to study.  All pointers are host memory owned by the caller; they
+ * are read during tm_system_create only and may be freed afterwards.
+ *
+ * Ground-state points: every k-related point that any q-set needs (k, -k,
+ * k+q, -k-q of Sec. 5.7's "sister points") carries its occupied spinors
+ * U_{n,p} (all nbnd of them, the lowest), eigenvalues and projector table.
+ */
+typedef struct {
+    double cell[9];             /* lattice vectors a1, a2, a3 as rows (bohr)              */
+    int fft[3];                 /* n1, n2, n3: lengths with prime factors 2, 3, 5 only    */
+    int nbnd;                   /* occupied spinor bands per k                            */
+
+    int npts;                   /* number of ground-state points                          */
+    const double* xk;           /* [npts][3] Cartesian point vectors (bohr^-1)            */
+    const int* npw;             /* [npts] sphere sizes                                    */
+    const int* const* mill;     /* [npts] -> [npw][3] Miller indices                      */
+    const double* const* evc;   /* [npts] -> complex [nbnd][2][npw] occupied spinors      */
+    const double* const* et;    /* [npts] -> [nbnd] eigenvalues (Ha)                      */
+
+    const double* vrs;          /* [4][n1 n2 n3]: v_eff, B_x, B_y, B_z of Eq. H0_k_plus_q,
+                                   with the Hamiltonian's magnetic term written +B.sigma  */
+    const double* rho;          /* [4][n1 n2 n3]: ground-state n, m_x, m_y, m_z            */
+
+    int nproj;                  /* Kleinman-Bylander projectors in the cell                */
+    const double* const* vkb;   /* [npts] -> complex [nproj][npw]: beta_i(p+G)            */
+    const double* dvan;         /* complex [nproj][nproj][2][2]: spinor D matrix; must be
+                                   Hermitian and time-reversal invariant (Sec. 2.2)       */
+
+    int nq;                     /* number of q-sets                                       */
+    const double* xq;           /* [nq][3] Cartesian q (bohr^-1)                           */
+    int nk;                     /* mesh points per q-set (weights 1/nk)                   */
+    const int* roles;           /* [nq][nk][4]: point index of k, -k, k+q, -k-q            */
+    const int* shifts;          /* [nq][nk][4][3] or NULL: integer g with
+                                   role vector = xk[point] + g.b; the point's
+                                   coefficients then sit on Miller indices m - g          */
+} tm_system_desc;
+
+/* Per-q-set shape information for sizing BR vectors. */
+typedef struct {
+    int nk;                     /* mesh points                                            */
+    int nbnd;                   /* bands                                                  */
+    int npw_pad;                /* padded sphere length of every (side, k) block          */
+    long long nelem;            /* complex elements of one BR vector = 2 nk nbnd 2 npw_pad */
+    double lam;                 /* scale of L used by the breakdown rule: the largest
+                                   |k+q+G|^2/2 on the response spheres (Ha)               */
+} tm_qset_info;
+
+/*
+ * tm_system_create: upload a system to the current HIP device and build the
+ * G-vector maps, FFT column tables, time-reversed partners (T = i sigma_y K,
+ * Sec. 2.2), the ALSDA kernel fields (Eqs. v_XC_q, b_XC_q) and the Coulomb
+ * multipliers 4 pi / |G+q|^2 (Eq. v_H_q).
+ * Returns TM_EINVAL for inconsistent input (e.g. the sphere of -k-q is not the
+ * negative of the sphere of k+q), TM_EUNSUPPORTED for unsupported grid sizes,
+ * TM_ENOMEM / TM_EDEVICE for device failures.  *out owns all device memory.
+ */
+int tm_system_create(const tm_system_desc* desc, tm_system** out);
+
+/* Free everything tm_system_create allocated.  NULL is allowed. */
+int tm_system_destroy(tm_system* sys);
+
+/* Shape of the BR vectors of q-set iq. */
+int tm_qset_info_get(const tm_system* sys, int iq, tm_qset_info* info);
+
+/*
+ * tm_liouvillian_apply: xy_out = L_q xy_in (Eqs. Liouvillian_BR_q and
+ * liouvillian_blocks; one projector P, P+ applied to the sum of the D and K
+ * parts, lower row multiplied by -1).
+ * xy_in, xy_out: device pointers to BR vectors of q-set iq (see tm_qset_info),
+ * owned by the caller; they must not overlap (TM_EINVAL).  The padding of
+ * xy_in must be zero; xy_out's padding is written as zero.  The input should
+ * be orthogonal to the occupied manifold (X side to U_{k+q}, Y side to
+ * T U_{-k-q}); the output always is.
+ * stream: a hipStream_t (NULL = default stream); the call is asynchronous.
+ * prec: TM_FP64 (TM_FP32 returns TM_EUNSUPPORTED in this version).
+ */
+int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out,
+                         tm_precision prec, void* stream);
+
+/*
+ * tm_start_vectors: the BR vectors of Sec. 2.5 (below Eq. off-diag-resolvent):
+ *   u^dir = ( sigma U~_{n,k}, -sigma T U~_{n,-k} ),
+ *   v^dir = ( P sigma U~_{n,k}, P+ sigma T U~_{n,-k} ),
+ * U~ = coefficients restricted to the sphere of k+q.  u, v: device BR vectors
+ * (either may be NULL).  Asynchronous on stream.
+ */
+int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void* stream);
+
+/*
+ * Lanczos coefficients (Sec. 2.5).  All arrays are host memory owned by the
+ * caller with room for `capacity` steps.  For 0-based step j:
+ *   alpha[j] = T[j][j], beta[j] = T[j+1][j], gamma[j] = T[j][j+1],
+ *   z[l][j] = (u^l, q_j) for l = x, y, z;
+ * the last beta/gamma is the residual coupling beyond the M x M matrix.
+ * For the pseudo-Hermitian flavour beta = gamma (real) and alpha is real.
+ */
+typedef struct {
+    int capacity;               /* in: room for this many steps                          */
+    int steps_done;             /* out: steps whose alpha and z are valid                */
+    double n1;                  /* out: norm of the start vector used (Sec. 2.5)         */
+    double* alpha;              /* complex [capacity]                                    */
+    double* beta;               /* real    [capacity]                                    */
+    double* gamma;              /* complex [capacity]                                    */
+    double* z;                  /* complex [3][capacity]                                 */
+} tm_coeffs;
+
+/*
+ * tm_lanczos_run: one chain for field direction dir on q-set iq, nsteps
+ * steps (nsteps <= out->capacity), flavour f.  Synchronous.  Breakdown rule
+ * (scale Lam from tm_qset_info, eps = 1e-10):
+ *   non-Hermitian: |(p^, q^)| <= eps Lam^2 ||p_i|| ||q_i||;
+ *   pseudo-Hermitian start: v^dag J L v <= eps Lam (v, v);
+ *   pseudo-Hermitian step:  r^dag J L r <= eps Lam (r, r) or (r, r) <= eps^2 Lam^2 (q_i, q_i).
+ * On breakdown the call returns TM_EBREAKDOWN with steps_done < nsteps and
+ * the coefficients of the completed steps valid.
+ */
+int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
+                   tm_precision prec, tm_coeffs* out);
+
+/*
+ * tm_chi: chi_l(omega_j) = n1 sum_i z[l][i] eta_i with
+ *   ((omega_j + i eta) I - T) eta = e_1            (Eq. post_processing)
+ * over the first m_use steps (m_use <= c->steps_done), l = x, y, z.
+ * omega: host [nomega] (Ha); chi: host complex [3][nomega], caller-owned.
+ * Runs on the current device (one tridiagonal solve with partial pivoting per
+ * frequency); synchronous.
+ */
+int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, double eta,
+           double* chi);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* tm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TM_H */

@@ -1,0 +1,11 @@
+"""MI355X-native Liouville-Lanczos magnon library (arXiv:2203.01120).
+
+The compute path is the HIP library ``libtm.so`` (C ABI in include/tm.h);
+``binding`` marshals arguments to it.  PyTorch supplies device memory and
+streams only.
+"""
+from .binding import (  # noqa: F401
+    DIRS, FLAVOURS, TM_EBREAKDOWN, TM_EINVAL, TM_FP32, TM_FP64, TM_OK, Point, SystemDesc, TmError, load,
+    tm_chi, tm_lanczos_run, tm_liouvillian_apply, tm_qset_info_get, tm_start_vectors, tm_system_create,
+    tm_system_destroy,
+)

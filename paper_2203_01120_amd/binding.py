@@ -1,0 +1,256 @@
+"""Thin ctypes binding of libtm (include/tm.h): argument marshalling only.
+
+Every step of the Liouvillian, the Lanczos recursions and chi runs inside the
+HIP library; this module only packs host arrays into the C structs, passes
+device pointers of torch tensors and the current HIP stream, and turns error
+codes into exceptions.  There is no CPU fallback: if the library is missing or
+no GPU is visible the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtm.so")
+
+TM_OK, TM_EINVAL, TM_ENOMEM, TM_EDEVICE, TM_EBREAKDOWN, TM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+TM_FP64, TM_FP32 = 0, 1
+DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4}
+FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
+
+EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_liouvillian_apply",
+            "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_last_error"]
+
+
+class TmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libtm error {code}: {msg}")
+        self.code = code
+
+
+class _Desc(C.Structure):
+    _fields_ = [
+        ("cell", C.c_double * 9), ("fft", C.c_int * 3), ("nbnd", C.c_int),
+        ("npts", C.c_int), ("xk", C.POINTER(C.c_double)), ("npw", C.POINTER(C.c_int)),
+        ("mill", C.POINTER(C.POINTER(C.c_int))), ("evc", C.POINTER(C.POINTER(C.c_double))),
+        ("et", C.POINTER(C.POINTER(C.c_double))),
+        ("vrs", C.POINTER(C.c_double)), ("rho", C.POINTER(C.c_double)),
+        ("nproj", C.c_int), ("vkb", C.POINTER(C.POINTER(C.c_double))), ("dvan", C.POINTER(C.c_double)),
+        ("nq", C.c_int), ("xq", C.POINTER(C.c_double)), ("nk", C.c_int),
+        ("roles", C.POINTER(C.c_int)), ("shifts", C.POINTER(C.c_int)),
+    ]
+
+
+class _QInfo(C.Structure):
+    _fields_ = [("nk", C.c_int), ("nbnd", C.c_int), ("npw_pad", C.c_int), ("nelem", C.c_longlong),
+                ("lam", C.c_double)]
+
+
+class _Coeffs(C.Structure):
+    _fields_ = [("capacity", C.c_int), ("steps_done", C.c_int), ("n1", C.c_double),
+                ("alpha", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double)),
+                ("gamma", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libtm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with paper_2203_01120_amd.build_lib.build()")
+    lib = C.CDLL(path)
+    lib.tm_system_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]
+    lib.tm_system_destroy.argtypes = [C.c_void_p]
+    lib.tm_qset_info_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(_QInfo)]
+    lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+    lib.tm_lanczos_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_Coeffs)]
+    lib.tm_chi.argtypes = [C.POINTER(_Coeffs), C.c_int, C.POINTER(C.c_double), C.c_int, C.c_double,
+                           C.POINTER(C.c_double)]
+    lib.tm_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        getattr(lib, name).restype = C.c_int if name != "tm_last_error" else C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow=()):
+    if rc != TM_OK and rc not in allow:
+        raise TmError(rc, load().tm_last_error().decode())
+    return rc
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _iptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+@dataclass
+class Point:
+    """Ground-state data of one k-related point."""
+    xk: np.ndarray          # (3,) Cartesian
+    mill: np.ndarray        # (npw, 3) int
+    evc: np.ndarray         # (nbnd, 2, npw) complex128
+    et: np.ndarray          # (nbnd,)
+    vkb: Optional[np.ndarray] = None  # (nproj, npw) complex128
+
+
+@dataclass
+class SystemDesc:
+    cell: np.ndarray
+    fft: Sequence[int]
+    nbnd: int
+    points: List[Point]
+    vrs: np.ndarray          # (4, n1, n2, n3): v_eff, B_x, B_y, B_z
+    rho: np.ndarray          # (4, n1, n2, n3): n, m_x, m_y, m_z
+    dvan: Optional[np.ndarray]   # (nproj, nproj, 2, 2) complex128
+    xq: np.ndarray           # (nq, 3)
+    roles: np.ndarray        # (nq, nk, 4) int
+    shifts: Optional[np.ndarray] = None   # (nq, nk, 4, 3) int
+    keep: list = field(default_factory=list)
+
+
+def tm_system_create(d: SystemDesc):
+    """Upload a system; returns an opaque handle (int)."""
+    lib = load()
+    keep = []
+
+    def c(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a
+
+    npts = len(d.points)
+    nproj = 0 if d.dvan is None else int(d.dvan.shape[0])
+    desc = _Desc()
+    desc.cell[:] = list(np.asarray(d.cell, dtype=float).ravel())
+    desc.fft[:] = [int(x) for x in d.fft]
+    desc.nbnd = int(d.nbnd)
+    desc.npts = npts
+    xk = c(np.array([p.xk for p in d.points]), np.float64)
+    desc.xk = _dptr(xk)
+    npw = c(np.array([p.mill.shape[0] for p in d.points]), np.int32)
+    desc.npw = _iptr(npw)
+    mills = [c(p.mill, np.int32) for p in d.points]
+    evcs = [c(p.evc, np.complex128) for p in d.points]
+    ets = [c(p.et[:d.nbnd], np.float64) for p in d.points]
+    MP = C.POINTER(C.c_int) * npts
+    DP = C.POINTER(C.c_double) * npts
+    mill_arr = MP(*[_iptr(m) for m in mills])
+    evc_arr = DP(*[e.ctypes.data_as(C.POINTER(C.c_double)) for e in evcs])
+    et_arr = DP(*[_dptr(e) for e in ets])
+    keep += [mill_arr, evc_arr, et_arr]
+    desc.mill = C.cast(mill_arr, C.POINTER(C.POINTER(C.c_int)))
+    desc.evc = C.cast(evc_arr, C.POINTER(C.POINTER(C.c_double)))
+    desc.et = C.cast(et_arr, C.POINTER(C.POINTER(C.c_double)))
+    vrs = c(d.vrs, np.float64)
+    rho = c(d.rho, np.float64)
+    desc.vrs = _dptr(vrs)
+    desc.rho = _dptr(rho)
+    desc.nproj = nproj
+    if nproj:
+        vkbs = [c(p.vkb, np.complex128) for p in d.points]
+        vkb_arr = DP(*[v.ctypes.data_as(C.POINTER(C.c_double)) for v in vkbs])
+        keep.append(vkb_arr)
+        desc.vkb = C.cast(vkb_arr, C.POINTER(C.POINTER(C.c_double)))
+        dv = c(d.dvan, np.complex128)
+        desc.dvan = dv.ctypes.data_as(C.POINTER(C.c_double))
+    xq = c(np.atleast_2d(d.xq), np.float64)
+    desc.nq = xq.shape[0]
+    desc.xq = _dptr(xq)
+    roles = c(d.roles, np.int32)
+    desc.nk = roles.shape[1]
+    desc.roles = _iptr(roles)
+    if d.shifts is not None:
+        sh = c(d.shifts, np.int32)
+        desc.shifts = _iptr(sh)
+    h = C.c_void_p()
+    _check(lib.tm_system_create(C.byref(desc), C.byref(h)))
+    return h.value
+
+
+def tm_system_destroy(h):
+    if h:
+        _check(load().tm_system_destroy(C.c_void_p(h)))
+
+
+def tm_qset_info_get(h, iq: int = 0) -> dict:
+    info = _QInfo()
+    _check(load().tm_qset_info_get(C.c_void_p(h), iq, C.byref(info)))
+    return dict(nk=info.nk, nbnd=info.nbnd, npw_pad=info.npw_pad, nelem=info.nelem, lam=info.lam)
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check_tensor(t, nelem):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous() and t.numel() == nelem):
+        raise ValueError(f"expected a contiguous complex128 CUDA tensor with {nelem} elements")
+
+
+def tm_liouvillian_apply(h, iq: int, xy_in, xy_out, prec: int = TM_FP64, stream=None):
+    """xy_out = L xy_in on the device (torch complex128 tensors of BR shape)."""
+    nelem = tm_qset_info_get(h, iq)["nelem"]
+    _check_tensor(xy_in, nelem)
+    _check_tensor(xy_out, nelem)
+    _check(load().tm_liouvillian_apply(C.c_void_p(h), iq, C.c_void_p(xy_in.data_ptr()),
+                                       C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
+
+
+def tm_start_vectors(h, iq: int, direction: str, u=None, v=None, stream=None):
+    nelem = tm_qset_info_get(h, iq)["nelem"]
+    for t in (u, v):
+        if t is not None:
+            _check_tensor(t, nelem)
+    _check(load().tm_start_vectors(C.c_void_p(h), iq, DIRS[direction],
+                                   C.c_void_p(u.data_ptr() if u is not None else 0),
+                                   C.c_void_p(v.data_ptr() if v is not None else 0), _stream(stream)))
+
+
+def tm_lanczos_run(h, iq: int, direction: str, flavour: str, nsteps: int, prec: int = TM_FP64) -> dict:
+    """Run one chain; returns dict(alpha, beta, gamma, z[3], n1, steps_done, breakdown)."""
+    cap = int(nsteps)
+    alpha = np.zeros(cap, dtype=np.complex128)
+    beta = np.zeros(cap)
+    gamma = np.zeros(cap, dtype=np.complex128)
+    z = np.zeros((3, cap), dtype=np.complex128)
+    co = _Coeffs(cap, 0, 0.0, alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
+                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
+    rc = _check(load().tm_lanczos_run(C.c_void_p(h), iq, DIRS[direction], FLAVOURS[flavour], cap, prec,
+                                      C.byref(co)), allow=(TM_EBREAKDOWN,))
+    return dict(alpha=alpha, beta=beta, gamma=gamma, z=z, n1=co.n1, steps_done=co.steps_done,
+                breakdown=rc == TM_EBREAKDOWN)
+
+
+def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:
+    """chi[l][w] for l = x, y, z from the Lanczos coefficients (runs on the GPU)."""
+    alpha = np.ascontiguousarray(coeffs["alpha"], dtype=np.complex128)
+    beta = np.ascontiguousarray(coeffs["beta"], dtype=np.float64)
+    gamma = np.ascontiguousarray(coeffs["gamma"], dtype=np.complex128)
+    z = np.ascontiguousarray(coeffs["z"], dtype=np.complex128)
+    cap = alpha.shape[0]
+    co = _Coeffs(cap, int(coeffs["steps_done"]), float(coeffs["n1"]),
+                 alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
+                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros((3, om.shape[0]), dtype=np.complex128)
+    _check(load().tm_chi(C.byref(co), int(m_use), _dptr(om), om.shape[0], float(eta),
+                         out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out

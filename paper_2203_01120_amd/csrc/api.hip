@@ -1,0 +1,773 @@
+// C ABI of libtm: system set-up, the Liouvillian apply, the Lanczos driver and
+// the susceptibility.  See include/tm.h for the contract of every call.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+#include "lanczos_dev.h"
+
+namespace tml {
+
+void launch_kin(const System& s, double* kin, const int* d_mill, int npw, int npw_pad, const double* p, hipStream_t st);
+void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st);
+size_t gemm_partial_elems(int nbatch, int M, int Nn, int K);
+void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int cap, int M,
+                double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
+                hipStream_t st);
+
+static thread_local std::string g_err;
+void set_error(const std::string& m) { g_err = m; }
+
+void check_launch(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw Error{TM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+bool make_radices(int n, FFTPlan& p) {
+    p.n = n;
+    p.nrad = 0;
+    int m = n;
+    const int order[4] = {4, 5, 3, 2};
+    for (int r : order) {
+        while (m % r == 0) {
+            if (p.nrad >= kMaxRadices) return false;
+            p.rad[p.nrad++] = r;
+            m /= r;
+        }
+    }
+    return m == 1 && n > 0;
+}
+
+namespace {
+
+inline long long mkey(int a, int b, int c) {
+    return ((long long)(a + (1 << 20)) << 42) | ((long long)(b + (1 << 20)) << 21) | (long long)(c + (1 << 20));
+}
+
+// start vectors: su = sigma^dir (U~_k) on side 0, sigma^dir (T U~_-k) on side 1
+__global__ void k_start(const double2* const* ucoef, const int* npw_u, const int* const* maps, int nk, int nb,
+                        int npw_pad, int dir, double usign_y, double2* u, double2* v) {
+    const int b = blockIdx.z;
+    const int n = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw_pad) return;
+    const int side = b >= nk;
+    const int* map = maps[b];
+    const double2* U = ucoef[b];
+    const int nu = npw_u[b];
+    double2 a = cmk(0, 0), c = cmk(0, 0);
+    int j = map[g];
+    if (j >= 0) {
+        double2 up = U[((long long)n * 2 + 0) * nu + j], dn = U[((long long)n * 2 + 1) * nu + j];
+        if (side == 0) {
+            a = up;
+            c = dn;
+        } else {  // T = i sigma_y K at -G: (conj dn, -conj up)
+            a = cconj(dn);
+            c = cmk(-up.x, up.y);
+        }
+    }
+    double2 ra, rc;
+    switch (dir) {
+        case TM_DIR_X: ra = c; rc = a; break;
+        case TM_DIR_Y: ra = cmk(c.y, -c.x); rc = cmk(-a.y, a.x); break;  // (-i c, i a)
+        case TM_DIR_Z: ra = a; rc = cmk(-c.x, -c.y); break;
+        case TM_DIR_PLUS: ra = cscale(c, 2.0); rc = cmk(0, 0); break;
+        default: ra = cmk(0, 0); rc = cscale(a, 2.0); break;
+    }
+    long long off = (((long long)b * nb + n) * 2) * npw_pad + g;
+    if (v) {
+        v[off] = ra;
+        v[off + npw_pad] = rc;
+    }
+    if (u) {
+        double sg = side ? usign_y : 1.0;
+        u[off] = cscale(ra, sg);
+        u[off + npw_pad] = cscale(rc, sg);
+    }
+}
+
+// occupied partner on the k+q sphere: side 0 copies U_{k+q}, side 1 builds T U_{-k-q} at -G
+__global__ void k_occ(const double2* src, int npw_src, const int* map, int npw, int npw_pad, int nb, int tr,
+                      double2* dst) {
+    const int n = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw_pad) return;
+    double2 a = cmk(0, 0), c = cmk(0, 0);
+    if (g < npw) {
+        int j = map ? map[g] : g;
+        double2 up = src[((long long)n * 2) * npw_src + j], dn = src[((long long)n * 2 + 1) * npw_src + j];
+        if (tr) {
+            a = cconj(dn);
+            c = cmk(-up.x, up.y);
+        } else {
+            a = up;
+            c = dn;
+        }
+    }
+    dst[((long long)n * 2) * npw_pad + g] = a;
+    dst[((long long)n * 2 + 1) * npw_pad + g] = c;
+}
+
+__global__ void k_pad_copy(const double2* src, int npw, int npw_pad, int rows, double2* dst) {
+    const int r = blockIdx.y;
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npw_pad || r >= rows) return;
+    dst[(long long)r * npw_pad + g] = g < npw ? src[(long long)r * npw + g] : cmk(0, 0);
+}
+
+void build_sphere_map(System& s, SphereMap& m, const std::vector<int>& mill3, int npw) {
+    m.npw = npw;
+    std::unordered_map<int, int> colid;
+    std::vector<int> colpos;
+    std::vector<std::vector<int>> ents;
+    std::unordered_map<long long, int> seen;
+    for (int g = 0; g < npw; ++g) {
+        int m1 = mill3[3 * g], m2 = mill3[3 * g + 1], m3 = mill3[3 * g + 2];
+        TM_CHECK(2 * std::abs(m1) < s.n1 && 2 * std::abs(m2) < s.n2 && 2 * std::abs(m3) < s.n3, TM_EINVAL,
+                 "a plane-wave sphere does not fit inside the FFT grid");
+        int i1 = ((m1 % s.n1) + s.n1) % s.n1, i2 = ((m2 % s.n2) + s.n2) % s.n2;
+        int pos = i1 * s.n2 + i2;
+        TM_CHECK(seen.emplace(mkey(m1, m2, m3), g).second, TM_EINVAL, "duplicate Miller index in a sphere");
+        auto it = colid.find(pos);
+        int c;
+        if (it == colid.end()) {
+            c = (int)colpos.size();
+            colid[pos] = c;
+            colpos.push_back(pos);
+            ents.emplace_back();
+        } else {
+            c = it->second;
+        }
+        ents[c].push_back(g);
+    }
+    m.ncol = (int)colpos.size();
+    std::vector<int> ptr(m.ncol + 1, 0), eg, ei;
+    eg.reserve(npw);
+    ei.reserve(npw);
+    for (int c = 0; c < m.ncol; ++c) {
+        ptr[c + 1] = ptr[c] + (int)ents[c].size();
+        for (int g : ents[c]) {
+            eg.push_back(g);
+            ei.push_back(((mill3[3 * g + 2] % s.n3) + s.n3) % s.n3);
+        }
+    }
+    m.col_ptr = dev_upload(s, ptr.data(), ptr.size());
+    m.ent_g = dev_upload(s, eg.data(), eg.size());
+    m.ent_i3 = dev_upload(s, ei.data(), ei.size());
+    m.col_pos = dev_upload(s, colpos.data(), colpos.size());
+    m.h_col_pos = colpos;
+}
+
+std::vector<int> shifted(const std::vector<int>& mill, int npw, const int* g) {
+    std::vector<int> out(3 * (size_t)npw);
+    for (int i = 0; i < npw; ++i)
+        for (int c = 0; c < 3; ++c) out[3 * i + c] = mill[3 * i + c] - (g ? g[c] : 0);
+    return out;
+}
+
+template <typename T>
+T** upload_table(System& s, const std::vector<T*>& v) {
+    return dev_upload(s, const_cast<T**>(v.data()), v.size());
+}
+
+void transpose_to_planes(const System& s, const double* src, std::vector<double>& dst, int ncomp) {
+    // C order [n1][n2][n3] -> plane-major [i3][i1][i2]
+    dst.resize((size_t)ncomp * s.N);
+    for (int c = 0; c < ncomp; ++c)
+        for (int i1 = 0; i1 < s.n1; ++i1)
+            for (int i2 = 0; i2 < s.n2; ++i2)
+                for (int i3 = 0; i3 < s.n3; ++i3)
+                    dst[(size_t)c * s.N + ((size_t)i3 * s.n1 + i1) * s.n2 + i2] =
+                        src[(size_t)c * s.N + ((size_t)i1 * s.n2 + i2) * s.n3 + i3];
+}
+
+void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
+    const int nk = d->nk;
+    q.nk = nk;
+    for (int c = 0; c < 3; ++c) q.xq[c] = d->xq[3 * iq + c];
+    q.kb.resize(nk);
+    int npw_max = 0;
+    for (int ik = 0; ik < nk; ++ik) {
+        const int* r = d->roles + ((size_t)iq * nk + ik) * 4;
+        for (int t = 0; t < 4; ++t) TM_CHECK(r[t] >= 0 && r[t] < d->npts, TM_EINVAL, "role index out of range");
+        npw_max = std::max(npw_max, d->npw[r[2]]);
+    }
+    q.npw_pad = (npw_max + 15) / 16 * 16;
+    const int P = q.npw_pad, nb = s.nbnd;
+    hipStream_t st = nullptr;
+    q.ncol_max = 0;
+    q.ncol_u_max = 0;
+    q.lam = 0.0;
+    std::vector<int*> t_colptr_kq(2 * nk), t_entg_kq(2 * nk), t_enti3_kq(2 * nk), t_colpos_kq(2 * nk);
+    std::vector<int*> t_colptr_u(2 * nk), t_entg_u(2 * nk), t_enti3_u(2 * nk), t_colpos_u(2 * nk);
+    std::vector<int> t_ncol_kq(2 * nk), t_npw_kq(2 * nk), t_ncol_u(2 * nk), t_npw_u(2 * nk);
+    std::vector<const double2*> t_ucoef(2 * nk);
+    std::vector<double*> t_kin(2 * nk), t_eps(2 * nk);
+    std::vector<double2*> t_occ(2 * nk), t_vkb(2 * nk);
+    std::vector<int*> t_maps(2 * nk);
+    for (int ik = 0; ik < nk; ++ik) {
+        KBlock& kb = q.kb[ik];
+        const int* r = d->roles + ((size_t)iq * nk + ik) * 4;
+        const int* sh = d->shifts ? d->shifts + ((size_t)iq * nk + ik) * 12 : nullptr;
+        const int pk = r[0], pmk = r[1], pkq = r[2], pmkq = r[3];
+        const int npw = d->npw[pkq];
+        kb.npw = npw;
+        std::vector<int> m_kq = shifted(s.mill[pkq], npw, sh ? sh + 6 : nullptr);
+        std::vector<int> m_k = shifted(s.mill[pk], d->npw[pk], sh ? sh + 0 : nullptr);
+        std::vector<int> m_mk = shifted(s.mill[pmk], d->npw[pmk], sh ? sh + 3 : nullptr);
+        std::vector<int> m_mkq = shifted(s.mill[pmkq], d->npw[pmkq], sh ? sh + 9 : nullptr);
+        for (int c = 0; c < 3; ++c) {
+            double g = 0;
+            for (int t = 0; t < 3; ++t) g += (sh ? sh[6 + t] : 0) * s.recip[3 * t + c];
+            kb.kq[c] = d->xk[3 * pkq + c] + g;
+        }
+        build_sphere_map(s, kb.sph_kq, m_kq, npw);
+        build_sphere_map(s, kb.sph_u[0], m_k, d->npw[pk]);
+        build_sphere_map(s, kb.sph_u[1], m_mk, d->npw[pmk]);
+        kb.u_coef[0] = s.evc[pk];
+        kb.u_coef[1] = s.evc[pmk];
+        kb.npw_u[0] = d->npw[pk];
+        kb.npw_u[1] = d->npw[pmk];
+        q.ncol_max = std::max(q.ncol_max, kb.sph_kq.ncol);
+        q.ncol_u_max = std::max({q.ncol_u_max, kb.sph_u[0].ncol, kb.sph_u[1].ncol});
+        // lookup tables
+        std::unordered_map<long long, int> lk, lmk, lmkq;
+        for (int g = 0; g < d->npw[pk]; ++g) lk[mkey(m_k[3 * g], m_k[3 * g + 1], m_k[3 * g + 2])] = g;
+        for (int g = 0; g < d->npw[pmk]; ++g) lmk[mkey(m_mk[3 * g], m_mk[3 * g + 1], m_mk[3 * g + 2])] = g;
+        for (int g = 0; g < d->npw[pmkq]; ++g)
+            lmkq[mkey(m_mkq[3 * g], m_mkq[3 * g + 1], m_mkq[3 * g + 2])] = g;
+        TM_CHECK(d->npw[pmkq] == npw, TM_EINVAL, "the -k-q sphere is not the negative of the k+q sphere");
+        std::vector<int> map_k(P, -1), map_mk(P, -1), map_mkq(npw, -1);
+        for (int g = 0; g < npw; ++g) {
+            int a = m_kq[3 * g], b = m_kq[3 * g + 1], c = m_kq[3 * g + 2];
+            auto i1 = lk.find(mkey(a, b, c));
+            if (i1 != lk.end()) map_k[g] = i1->second;
+            auto i2 = lmk.find(mkey(-a, -b, -c));
+            if (i2 != lmk.end()) map_mk[g] = i2->second;
+            auto i3 = lmkq.find(mkey(-a, -b, -c));
+            TM_CHECK(i3 != lmkq.end(), TM_EINVAL, "the -k-q sphere is not the negative of the k+q sphere");
+            map_mkq[g] = i3->second;
+        }
+        kb.map_k = dev_upload(s, map_k.data(), map_k.size());
+        kb.map_mk = dev_upload(s, map_mk.data(), map_mk.size());
+        int* d_map_mkq = dev_upload(s, map_mkq.data(), map_mkq.size());
+        // kinetic energies from the k+q point's own Miller indices
+        int* d_mill = dev_upload(s, s.mill[pkq].data(), s.mill[pkq].size());
+        kb.kin = dev_alloc<double>(s, P);
+        launch_kin(s, kb.kin, d_mill, npw, P, d->xk + 3 * pkq, st);
+        for (int g = 0; g < npw; ++g) {
+            double x[3];
+            for (int c = 0; c < 3; ++c) {
+                x[c] = d->xk[3 * pkq + c];
+                for (int t = 0; t < 3; ++t) x[c] += s.mill[pkq][3 * g + t] * s.recip[3 * t + c];
+            }
+            q.lam = std::max(q.lam, 0.5 * (x[0] * x[0] + x[1] * x[1] + x[2] * x[2]));
+        }
+        kb.eps[0] = dev_upload(s, s.et[pk].data(), nb);
+        kb.eps[1] = dev_upload(s, s.et[pmk].data(), nb);
+        kb.occ[0] = dev_alloc<double2>(s, (size_t)nb * 2 * P);
+        kb.occ[1] = dev_alloc<double2>(s, (size_t)nb * 2 * P);
+        dim3 gr((P + 127) / 128, nb);
+        hipLaunchKernelGGL(k_occ, gr, dim3(128), 0, st, s.evc[pkq], npw, (const int*)nullptr, npw, P, nb, 0, kb.occ[0]);
+        check_launch("k_occ");
+        hipLaunchKernelGGL(k_occ, gr, dim3(128), 0, st, s.evc[pmkq], npw, d_map_mkq, npw, P, nb, 1, kb.occ[1]);
+        check_launch("k_occ");
+        if (s.nproj > 0) {
+            double2* vk = dev_upload(s, s.h_vkb[pkq].data(), s.h_vkb[pkq].size());
+            kb.vkb = dev_alloc<double2>(s, (size_t)s.nproj * P);
+            hipLaunchKernelGGL(k_pad_copy, dim3((P + 127) / 128, s.nproj), dim3(128), 0, st, vk, npw, P, s.nproj,
+                               kb.vkb);
+            check_launch("k_pad_copy");
+        }
+        for (int side = 0; side < 2; ++side) {
+            int b = side * nk + ik;
+            t_colptr_kq[b] = kb.sph_kq.col_ptr;
+            t_entg_kq[b] = kb.sph_kq.ent_g;
+            t_enti3_kq[b] = kb.sph_kq.ent_i3;
+            t_colpos_kq[b] = kb.sph_kq.col_pos;
+            t_ncol_kq[b] = kb.sph_kq.ncol;
+            t_npw_kq[b] = npw;
+            t_colptr_u[b] = kb.sph_u[side].col_ptr;
+            t_entg_u[b] = kb.sph_u[side].ent_g;
+            t_enti3_u[b] = kb.sph_u[side].ent_i3;
+            t_colpos_u[b] = kb.sph_u[side].col_pos;
+            t_ncol_u[b] = kb.sph_u[side].ncol;
+            t_npw_u[b] = kb.npw_u[side];
+            t_ucoef[b] = kb.u_coef[side];
+            t_kin[b] = kb.kin;
+            t_eps[b] = kb.eps[side];
+            t_occ[b] = kb.occ[side];
+            t_vkb[b] = kb.vkb;
+            t_maps[b] = side == 0 ? kb.map_k : kb.map_mk;
+        }
+    }
+    q.d_colptr_kq = upload_table(s, t_colptr_kq);
+    q.d_entg_kq = upload_table(s, t_entg_kq);
+    q.d_enti3_kq = upload_table(s, t_enti3_kq);
+    q.d_colpos_kq = upload_table(s, t_colpos_kq);
+    q.d_ncol_kq = dev_upload(s, t_ncol_kq.data(), t_ncol_kq.size());
+    q.d_npw_kq = dev_upload(s, t_npw_kq.data(), t_npw_kq.size());
+    q.d_colptr_u = upload_table(s, t_colptr_u);
+    q.d_entg_u = upload_table(s, t_entg_u);
+    q.d_enti3_u = upload_table(s, t_enti3_u);
+    q.d_colpos_u = upload_table(s, t_colpos_u);
+    q.d_ncol_u = dev_upload(s, t_ncol_u.data(), t_ncol_u.size());
+    q.d_npw_u = dev_upload(s, t_npw_u.data(), t_npw_u.size());
+    q.d_ucoef = dev_upload(s, t_ucoef.data(), t_ucoef.size());
+    q.d_kin = upload_table(s, t_kin);
+    q.d_eps = upload_table(s, t_eps);
+    q.d_occ = upload_table(s, t_occ);
+    q.d_vkb = upload_table(s, t_vkb);
+    q.d_maps = upload_table(s, t_maps);
+    q.hq = dev_alloc<double>(s, s.N);
+    launch_coulomb_setup(s, q, st);
+}
+
+}  // namespace
+
+void ensure_workspace(System& s, const QSet& q) {
+    Workspace& w = s.ws;
+    const int nb = s.nbnd, nb2 = 2 * q.nk;
+    if (w.nchunk == 0) {
+        long long blocks_per_chunk = (long long)s.n3 * nb2;
+        int nchunk = (int)std::min<long long>(nb, std::max<long long>(1, (2048 + blocks_per_chunk - 1) / blocks_per_chunk));
+        w.nchunk = nchunk;
+    }
+    size_t need_x = (size_t)nb2 * 2 * nb * s.n3 * q.ncol_max;
+    if (need_x > w.cap_xcols) {
+        if (w.xcols) TM_HIP(hipFree(w.xcols));
+        TM_HIP(hipMalloc(&w.xcols, need_x * sizeof(double2)));
+        w.cap_xcols = need_x;
+    }
+    size_t need_rp = (size_t)nb2 * w.nchunk * 4 * s.N;
+    if (need_rp > w.cap_rho_part) {
+        if (w.rho_part) TM_HIP(hipFree(w.rho_part));
+        TM_HIP(hipMalloc(&w.rho_part, need_rp * sizeof(double2)));
+        w.cap_rho_part = need_rp;
+    }
+    if (!w.rho) {
+        TM_HIP(hipMalloc(&w.rho, 4 * s.N * sizeof(double2)));
+        TM_HIP(hipMalloc(&w.W, 4 * s.N * sizeof(double2)));
+        TM_HIP(hipMalloc(&w.work, s.N * sizeof(double2)));
+        TM_HIP(hipMalloc(&w.dots, 64 * sizeof(double2)));
+        TM_HIP(hipMalloc(&w.dotpart, 1024 * 8 * sizeof(double2)));
+    }
+    size_t need_gp = std::max(gemm_partial_elems(nb2, nb, nb, 2 * q.npw_pad),
+                              gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, q.npw_pad));
+    if (need_gp > w.cap_gpart) {
+        if (w.gpart) TM_HIP(hipFree(w.gpart));
+        TM_HIP(hipMalloc(&w.gpart, need_gp * sizeof(double2)));
+        w.cap_gpart = need_gp;
+    }
+    size_t need_gs = std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
+    if (need_gs > w.cap_gsmall) {
+        if (w.gsmall) TM_HIP(hipFree(w.gsmall));
+        TM_HIP(hipMalloc(&w.gsmall, need_gs * sizeof(double2)));
+        w.cap_gsmall = need_gs;
+    }
+}
+
+static void ensure_ucols(System& s, QSet& q, hipStream_t st) {
+    if (q.ucols_ready) return;
+    size_t need = (size_t)2 * q.nk * 2 * s.nbnd * s.n3 * q.ncol_u_max;
+    TM_HIP(hipMalloc(&q.ucols, need * sizeof(double2)));
+    s.allocs.push_back(q.ucols);
+    launch_zpass_inv(s, q, true, nullptr, 0, 2 * s.nbnd, 0, q.ucols, st);
+    q.ucols_ready = true;
+}
+
+void apply_fp64(System& s, int iq, const double2* in, double2* out, hipStream_t st) {
+    QSet& q = s.qs[iq];
+    ensure_workspace(s, q);
+    ensure_ucols(s, q, st);
+    const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
+    launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st);
+    launch_density(s, q, st);
+    launch_potential(s, q, st);
+    launch_apply_planes(s, q, st);
+    launch_zpass_fwd(s, q, s.ws.xcols, in, out, st);
+    launch_nonlocal(s, q, in, out, st);
+    launch_project(s, q, out, st);
+}
+
+void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st) {
+    QSet& q = s.qs[iq];
+    ensure_workspace(s, q);
+    dim3 gr((q.npw_pad + 127) / 128, s.nbnd, 2 * q.nk);
+    hipLaunchKernelGGL(k_start, gr, dim3(128), 0, st, q.d_ucoef, q.d_npw_u, (const int* const*)q.d_maps, q.nk,
+                       s.nbnd, q.npw_pad, dir, -1.0, u, v);
+    check_launch("k_start");
+    if (v) launch_project_signed(s, q, v, 1.0, 1.0, st);
+}
+
+static int run_chain(System& s, int iq, int dir, int flavour, int nsteps, tm_coeffs* out, hipStream_t st) {
+    QSet& q = s.qs[iq];
+    ensure_workspace(s, q);
+    const long long n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
+    const long long half = n / 2;
+    const double w = 1.0 / q.nk;
+    const int nvec = flavour == TM_PSEUDOHERMITIAN ? 5 : 9;
+    std::vector<double2*> vec(nvec + 3, nullptr);
+    struct Guard {
+        std::vector<void*> p;
+        ~Guard() {
+            for (void* x : p) (void)hipFree(x);
+        }
+    } guard;
+    auto galloc = [&](size_t bytes) {
+        void* p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) throw Error{TM_ENOMEM, "hipMalloc failed for Lanczos vectors"};
+        guard.p.push_back(p);
+        return p;
+    };
+    for (auto& p : vec) p = static_cast<double2*>(galloc(n * sizeof(double2)));
+    const int cap = nsteps;
+    Coeffs co;
+    co.cap = cap;
+    co.alpha = static_cast<double2*>(galloc(cap * sizeof(double2)));
+    co.beta = static_cast<double*>(galloc(cap * sizeof(double)));
+    co.gamma = static_cast<double2*>(galloc(cap * sizeof(double2)));
+    co.z = static_cast<double2*>(galloc(3 * cap * sizeof(double2)));
+    TM_HIP(hipMemsetAsync(co.alpha, 0, cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(co.beta, 0, cap * sizeof(double), st));
+    TM_HIP(hipMemsetAsync(co.gamma, 0, cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(co.z, 0, 3 * cap * sizeof(double2), st));
+    ChainState* cs = static_cast<ChainState*>(galloc(sizeof(ChainState)));
+    ChainState h{};
+    h.lam = q.lam;
+    TM_HIP(hipMemcpyAsync(cs, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    double2* u[3] = {vec[nvec], vec[nvec + 1], vec[nvec + 2]};
+    for (int l = 0; l < 3; ++l) start_vectors(s, iq, l, u[l], nullptr, st);
+    double2* d = s.ws.dots;
+    double2* part = s.ws.dotpart;
+    const double2* uc[3] = {u[0], u[1], u[2]};
+    if (flavour == TM_PSEUDOHERMITIAN) {
+        double2 *QP = vec[0], *Q = vec[1], *LQ = vec[2], *R = vec[3], *LR = vec[4];
+        TM_HIP(hipMemsetAsync(QP, 0, n * sizeof(double2), st));
+        start_vectors(s, iq, dir, nullptr, Q, st);
+        apply_fp64(s, iq, Q, LQ, st);
+        DotSet<6> ds0{{Q, Q, LQ, u[0], u[1], u[2]}, {LQ, Q, LQ, Q, Q, Q}, {1, 0, 1, 0, 0, 0}};
+        run_multidot<6>(ds0, n, half, w, part, d, st);
+        ctl_ph_start(cs, d, co, st);
+        for (int j = 0; j < nsteps; ++j) {
+            run_ph_update(cs, LQ, Q, QP, R, uc, n, w, part, d + 8, st);
+            apply_fp64(s, iq, R, LR, st);
+            DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}};
+            run_multidot<3>(ds, n, half, w, part, d, st);
+            ctl_ph_step(cs, d, d + 8, co, j, nsteps, st);
+            // rotate: q_prev <- q, q <- r, Lq <- Lr
+            double2 *oQP = QP, *oLQ = LQ;
+            QP = Q;
+            Q = R;
+            LQ = LR;
+            R = oQP;
+            LR = oLQ;
+            if ((j & 63) == 63) {
+                int br = 0;
+                TM_HIP(hipMemcpyAsync(&br, &cs->broken, sizeof(int), hipMemcpyDeviceToHost, st));
+                TM_HIP(hipStreamSynchronize(st));
+                if (br) break;
+            }
+        }
+    } else {
+        double2 *QP = vec[0], *Q = vec[1], *PP = vec[2], *Pv = vec[3], *LQ = vec[4], *LTP = vec[5], *TMP = vec[6],
+                *QH = vec[7], *PH = vec[8];
+        TM_HIP(hipMemsetAsync(QP, 0, n * sizeof(double2), st));
+        TM_HIP(hipMemsetAsync(PP, 0, n * sizeof(double2), st));
+        start_vectors(s, iq, dir, nullptr, Q, st);
+        TM_HIP(hipMemcpyAsync(Pv, Q, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        DotSet<4> ds0{{Q, u[0], u[1], u[2]}, {Q, Q, Q, Q}, {0, 0, 0, 0}};
+        run_multidot<4>(ds0, n, half, w, part, d, st);
+        ctl_nh_start(cs, d, co, st);
+        for (int j = 0; j < nsteps; ++j) {
+            apply_fp64(s, iq, Q, LQ, st);
+            run_jcopy(Pv, TMP, n, half, st);
+            apply_fp64(s, iq, TMP, LTP, st);
+            DotSet<1> da{{Pv}, {LQ}, {0}};
+            run_multidot<1>(da, n, half, w, part, d, st);
+            ctl_nh_alpha(cs, d, co, j, st);
+            run_nh_update(cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, w, part, d + 8, st);
+            ctl_nh_step(cs, d + 8, co, j, nsteps, st);
+            double2 *oQP = QP, *oPP = PP;
+            QP = Q;
+            Q = QH;
+            PP = Pv;
+            Pv = PH;
+            QH = oQP;
+            PH = oPP;
+            if ((j & 63) == 63) {
+                int br = 0;
+                TM_HIP(hipMemcpyAsync(&br, &cs->broken, sizeof(int), hipMemcpyDeviceToHost, st));
+                TM_HIP(hipStreamSynchronize(st));
+                if (br) break;
+            }
+        }
+    }
+    TM_HIP(hipMemcpyAsync(&h, cs, sizeof(h), hipMemcpyDeviceToHost, st));
+    TM_HIP(hipStreamSynchronize(st));
+    std::vector<double2> ha(cap), hg(cap), hz(3 * cap);
+    std::vector<double> hb(cap);
+    TM_HIP(hipMemcpy(ha.data(), co.alpha, cap * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hb.data(), co.beta, cap * sizeof(double), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hg.data(), co.gamma, cap * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hz.data(), co.z, 3 * cap * sizeof(double2), hipMemcpyDeviceToHost));
+    const int done = h.step;
+    out->steps_done = done;
+    out->n1 = h.n1;
+    for (int j = 0; j < nsteps; ++j) {
+        out->alpha[2 * j] = ha[j].x;
+        out->alpha[2 * j + 1] = ha[j].y;
+        out->beta[j] = hb[j];
+        out->gamma[2 * j] = hg[j].x;
+        out->gamma[2 * j + 1] = hg[j].y;
+        for (int l = 0; l < 3; ++l) {
+            out->z[2 * ((size_t)l * out->capacity + j)] = hz[l * cap + j].x;
+            out->z[2 * ((size_t)l * out->capacity + j) + 1] = hz[l * cap + j].y;
+        }
+    }
+    return h.broken ? TM_EBREAKDOWN : TM_OK;
+}
+
+}  // namespace tml
+
+using namespace tml;
+
+struct tm_system {
+    System s;
+};
+
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        set_error("");
+        return f();
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return TM_EINVAL;
+    }
+}
+
+extern "C" {
+
+const char* tm_last_error(void) { return g_err.c_str(); }
+
+int tm_system_create(const tm_system_desc* d, tm_system** out) {
+    return guarded([&]() -> int {
+        TM_CHECK(d && out, TM_EINVAL, "null argument");
+        *out = nullptr;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error{TM_EDEVICE, "no HIP device"};
+        TM_CHECK(d->nbnd > 0 && d->npts > 0 && d->nq >= 0 && d->nk > 0, TM_EINVAL, "bad sizes");
+        TM_CHECK(d->fft[0] > 0 && d->fft[1] > 0 && d->fft[2] > 0, TM_EINVAL, "bad FFT grid");
+        TM_CHECK(d->nproj >= 0, TM_EINVAL, "bad nproj");
+        std::unique_ptr<tm_system> ts(new tm_system());
+        System& s = ts->s;
+        TM_HIP(hipGetDevice(&s.device));
+        std::memcpy(s.cell, d->cell, sizeof(s.cell));
+        const double* a = d->cell;
+        double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                     a[2] * (a[3] * a[7] - a[4] * a[6]);
+        TM_CHECK(std::fabs(det) > 1e-12, TM_EINVAL, "singular cell");
+        s.omega = std::fabs(det);
+        // b_i = 2 pi (a_j x a_k) / det
+        auto cross = [](const double* u, const double* v, double* w) {
+            w[0] = u[1] * v[2] - u[2] * v[1];
+            w[1] = u[2] * v[0] - u[0] * v[2];
+            w[2] = u[0] * v[1] - u[1] * v[0];
+        };
+        cross(a + 3, a + 6, s.recip + 0);
+        cross(a + 6, a + 0, s.recip + 3);
+        cross(a + 0, a + 3, s.recip + 6);
+        for (int i = 0; i < 9; ++i) s.recip[i] *= 2 * M_PI / det;
+        s.n1 = d->fft[0];
+        s.n2 = d->fft[1];
+        s.n3 = d->fft[2];
+        s.N = (long long)s.n1 * s.n2 * s.n3;
+        s.nbnd = d->nbnd;
+        s.nproj = d->nproj;
+        const int ns[3] = {s.n1, s.n2, s.n3};
+        for (int i = 0; i < 3; ++i) {
+            TM_CHECK(make_radices(ns[i], s.plan[i]), TM_EUNSUPPORTED, "FFT length must factor into 2, 3, 5");
+            std::vector<double2> tw(ns[i]);
+            for (int j = 0; j < ns[i]; ++j) {
+                double ang = -2.0 * M_PI * (double)j / (double)ns[i];
+                tw[j] = cmk(std::cos(ang), std::sin(ang));
+            }
+            s.tw[i] = dev_upload(s, tw.data(), tw.size());
+            s.plan[i].tw = s.tw[i];
+        }
+        TM_CHECK(s.n1 * s.n2 <= 4 * 1024, TM_EUNSUPPORTED, "n1*n2 above 4096 is not supported by the plane kernels");
+        // ground-state points
+        s.evc.resize(d->npts);
+        s.npw.resize(d->npts);
+        s.mill.resize(d->npts);
+        s.et.resize(d->npts);
+        s.h_vkb.resize(d->npts);
+        for (int p = 0; p < d->npts; ++p) {
+            int npw = d->npw[p];
+            TM_CHECK(npw > 0 && d->mill[p] && d->evc[p] && d->et[p], TM_EINVAL, "bad ground-state point");
+            TM_CHECK(npw * 2 >= d->nbnd, TM_EINVAL, "sphere smaller than the number of bands");
+            s.npw[p] = npw;
+            s.mill[p].assign(d->mill[p], d->mill[p] + 3 * (size_t)npw);
+            s.et[p].assign(d->et[p], d->et[p] + d->nbnd);
+            s.evc[p] = dev_upload(s, reinterpret_cast<const double2*>(d->evc[p]), (size_t)d->nbnd * 2 * npw);
+            if (d->nproj > 0) {
+                TM_CHECK(d->vkb && d->vkb[p], TM_EINVAL, "missing projector table");
+                const double2* v = reinterpret_cast<const double2*>(d->vkb[p]);
+                s.h_vkb[p].assign(v, v + (size_t)d->nproj * npw);
+            }
+        }
+        if (d->nproj > 0) {
+            TM_CHECK(d->dvan != nullptr, TM_EINVAL, "missing D matrix");
+            s.dvan = dev_upload(s, reinterpret_cast<const double2*>(d->dvan), (size_t)d->nproj * d->nproj * 4);
+        }
+        // fields
+        TM_CHECK(d->vrs && d->rho, TM_EINVAL, "missing fields");
+        std::vector<double> tmp;
+        transpose_to_planes(s, d->vrs, tmp, 4);
+        s.vrs = dev_upload(s, tmp.data(), tmp.size());
+        transpose_to_planes(s, d->rho, tmp, 4);
+        double* rho_d = dev_upload(s, tmp.data(), tmp.size());
+        s.fxc = dev_alloc<double>(s, 10 * (size_t)s.N);
+        launch_fxc_setup(s, rho_d, nullptr);
+        // q-sets
+        s.qs.resize(d->nq);
+        for (int iq = 0; iq < d->nq; ++iq) build_qset(s, d, iq, s.qs[iq]);
+        TM_HIP(hipDeviceSynchronize());
+        *out = ts.release();
+        return TM_OK;
+    });
+}
+
+int tm_system_destroy(tm_system* sys) {
+    if (!sys) return TM_OK;
+    return guarded([&]() -> int {
+        System& s = sys->s;
+        (void)hipDeviceSynchronize();
+        for (void* p : s.allocs) (void)hipFree(p);
+        Workspace& w = s.ws;
+        void* wp[] = {w.xcols, w.rho_part, w.rho, w.W, w.work, w.gpart, w.gsmall, w.dots, w.dotpart};
+        for (void* p : wp)
+            if (p) (void)hipFree(p);
+        delete sys;
+        return TM_OK;
+    });
+}
+
+int tm_qset_info_get(const tm_system* sys, int iq, tm_qset_info* info) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && info, TM_EINVAL, "null argument");
+        const System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        const QSet& q = s.qs[iq];
+        info->nk = q.nk;
+        info->nbnd = s.nbnd;
+        info->npw_pad = q.npw_pad;
+        info->nelem = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
+        info->lam = q.lam;
+        return TM_OK;
+    });
+}
+
+int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,
+                         void* stream) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && xy_in && xy_out, TM_EINVAL, "null argument");
+        System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        TM_CHECK(prec == TM_FP64, TM_EUNSUPPORTED, "only TM_FP64 is implemented");
+        const QSet& q = s.qs[iq];
+        const size_t bytes = (size_t)2 * q.nk * s.nbnd * 2 * q.npw_pad * sizeof(double2);
+        const char* a = static_cast<const char*>(xy_in);
+        const char* b = static_cast<const char*>(xy_out);
+        TM_CHECK(a + bytes <= b || b + bytes <= a, TM_EINVAL, "xy_in and xy_out overlap");
+        apply_fp64(s, iq, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out),
+                   static_cast<hipStream_t>(stream));
+        return TM_OK;
+    });
+}
+
+int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void* stream) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys, TM_EINVAL, "null argument");
+        System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+        start_vectors(s, iq, (int)dir, static_cast<double2*>(u), static_cast<double2*>(v),
+                      static_cast<hipStream_t>(stream));
+        return TM_OK;
+    });
+}
+
+int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps, tm_precision prec,
+                   tm_coeffs* out) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && out, TM_EINVAL, "null argument");
+        System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+        TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
+        TM_CHECK(nsteps >= 1 && nsteps <= out->capacity, TM_EINVAL, "nsteps must be in [1, capacity]");
+        TM_CHECK(out->alpha && out->beta && out->gamma && out->z, TM_EINVAL, "null coefficient array");
+        TM_CHECK(prec == TM_FP64, TM_EUNSUPPORTED, "only TM_FP64 is implemented");
+        int rc = run_chain(s, iq, (int)dir, (int)f, nsteps, out, nullptr);
+        if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
+        return rc;
+    });
+}
+
+int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, double eta, double* chi) {
+    return guarded([&]() -> int {
+        TM_CHECK(c && omega && chi, TM_EINVAL, "null argument");
+        TM_CHECK(m_use >= 1 && m_use <= c->steps_done && m_use <= c->capacity, TM_EINVAL,
+                 "m_use must be in [1, steps_done]");
+        TM_CHECK(nomega >= 0, TM_EINVAL, "negative nomega");
+        if (nomega == 0) return TM_OK;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error{TM_EDEVICE, "no HIP device"};
+        const int M = m_use, cap = c->capacity;
+        std::vector<void*> mem;
+        struct G {
+            std::vector<void*>& m;
+            ~G() {
+                for (void* p : m) (void)hipFree(p);
+            }
+        } g{mem};
+        auto al = [&](size_t b) {
+            void* p = nullptr;
+            if (hipMalloc(&p, b) != hipSuccess) throw Error{TM_ENOMEM, "hipMalloc failed in tm_chi"};
+            mem.push_back(p);
+            return p;
+        };
+        double2* da = (double2*)al(M * sizeof(double2));
+        double* db = (double*)al(M * sizeof(double));
+        double2* dg = (double2*)al(M * sizeof(double2));
+        double2* dz = (double2*)al(3 * (size_t)M * sizeof(double2));
+        double* dw = (double*)al(nomega * sizeof(double));
+        double2* work = (double2*)al(4 * (size_t)M * nomega * sizeof(double2));
+        double2* dchi = (double2*)al(3 * (size_t)nomega * sizeof(double2));
+        int* dst = (int*)al(sizeof(int));
+        TM_HIP(hipMemcpy(da, c->alpha, M * sizeof(double2), hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(db, c->beta, M * sizeof(double), hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(dg, c->gamma, M * sizeof(double2), hipMemcpyHostToDevice));
+        for (int l = 0; l < 3; ++l)
+            TM_HIP(hipMemcpy(dz + (size_t)l * M, c->z + 2 * (size_t)l * cap, M * sizeof(double2),
+                             hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(dw, omega, nomega * sizeof(double), hipMemcpyHostToDevice));
+        TM_HIP(hipMemset(dst, 0, sizeof(int)));
+        launch_chi(da, db, dg, dz, M, M, c->n1, dw, nomega, eta, work, dchi, dst, nullptr);
+        int status = 0;
+        TM_HIP(hipMemcpy(&status, dst, sizeof(int), hipMemcpyDeviceToHost));
+        TM_HIP(hipMemcpy(chi, dchi, 3 * (size_t)nomega * sizeof(double2), hipMemcpyDeviceToHost));
+        TM_CHECK(status == 0, TM_EINVAL, "singular tridiagonal system (eta = 0 on a pole?)");
+        return TM_OK;
+    });
+}
+
+}  // extern "C"

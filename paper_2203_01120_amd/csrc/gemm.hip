@@ -1,0 +1,240 @@
+// Complex FP64 contractions on the matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Two shapes cover the nonlocal pseudopotential term and the projector onto
+// the empty manifold of every (side, k) block:
+//   k_gemm_cn:     C[m][n] = sum_k conj(A[m][k]) B[n][k]   (small C, long K;
+//                  split over K, partials summed by k_reduce_parts)
+//   k_gemm_update: Y[n][k] = os * (Y[n][k] + cs * sum_m C[m][n] A[m][k])
+//                  (long output rows, short inner dimension)
+// Nonlocal term (Eq. H0_k_plus_q, V_NL with the 2x2 spin D matrix):
+//   B = beta^dag x,  W_i = sum_j D_ij B_j,  phi += beta W.
+// Projector (Eqs. P_minus_q2 / P_plus_q2):
+//   S = O^dag phi,  phi <- sg (phi - O S), sg = -1 on the lower row of L.
+// Complex products use four real MFMAs (re*re, im*im, re*im, im*re).
+//
+// Lane layout of the 16x16x4 FP64 MFMA for wave lane l (measured on gfx950):
+// A[l%16][l/16], B[l/16][l%16], accumulator element v = D[4*v + l/16][l%16].
+#include "tm_internal.h"
+
+namespace tml {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct GemmCN {
+    const double2* const* A_tab;  // per batch (or null -> A_base + b*a_bstride)
+    const double2* A_base;
+    long long a_bstride;
+    int lda;
+    const double2* B_base;        // per batch B_base + b*b_bstride
+    long long b_bstride;
+    int ldb;
+    int M, Nn, K, kchunk, ksplit, nt;
+    double2* part;                // [b][ks][M][Nn]
+};
+
+__global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
+    const int b = blockIdx.z, ks = blockIdx.y;
+    const int tile = blockIdx.x;
+    const int m0 = (tile / g.nt) * 16, n0 = (tile % g.nt) * 16;
+    const int l = threadIdx.x, i = l & 15, kk = l >> 4;
+    const double2* A = g.A_tab ? g.A_tab[b] : g.A_base + (long long)b * g.a_bstride;
+    const double2* B = g.B_base + (long long)b * g.b_bstride;
+    const int kbeg = ks * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+    v4d cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const bool arow = (m0 + i) < g.M, brow = (n0 + i) < g.Nn;
+    const double2* Ap = A + (long long)(m0 + i) * g.lda;
+    const double2* Bp = B + (long long)(n0 + i) * g.ldb;
+    for (int k = kbeg; k < kend; k += 4) {
+        int kx = k + kk;
+        double2 a = (arow && kx < kend) ? Ap[kx] : cmk(0.0, 0.0);
+        double2 bv = (brow && kx < kend) ? Bp[kx] : cmk(0.0, 0.0);
+        cr = mfma(a.x, bv.x, cr);
+        cr = mfma(a.y, bv.y, cr);
+        ci = mfma(a.x, bv.y, ci);
+        ci = mfma(-a.y, bv.x, ci);
+    }
+    double2* out = g.part + ((long long)b * g.ksplit + ks) * g.M * g.Nn;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int m = m0 + 4 * v + kk, n = n0 + i;
+        if (m < g.M && n < g.Nn) out[(long long)m * g.Nn + n] = cmk(cr[v], ci[v]);
+    }
+}
+
+__global__ void k_reduce_parts(const double2* part, double2* out, int ksplit, long long mn, int nbatch) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= mn * nbatch) return;
+    long long b = idx / mn, e = idx - b * mn;
+    double2 s = cmk(0.0, 0.0);
+    for (int k = 0; k < ksplit; ++k) s = cadd(s, part[(b * ksplit + k) * mn + e]);
+    out[idx] = s;
+}
+
+struct GemmUpd {
+    double2* Y_base;
+    long long y_bstride;
+    int ldy;
+    const double2* C_base;        // per batch C_base + b*c_bstride, [Minner][Nout]
+    long long c_bstride;
+    int ldc;
+    const double2* const* A_tab;
+    int lda;
+    int Nout, K, Minner;
+    double cs;
+    double os_x, os_y;            // output sign of side 0 / side 1 batches
+    int nk;
+};
+
+__global__ void __launch_bounds__(64) k_gemm_update(GemmUpd g) {
+    const int b = blockIdx.z;
+    const int n0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
+    const int l = threadIdx.x, i = l & 15, kk = l >> 4;
+    const double2* A = g.A_tab[b];
+    const double2* C = g.C_base + (long long)b * g.c_bstride;
+    double2* Y = g.Y_base + (long long)b * g.y_bstride;
+    v4d dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    const bool ncol = (n0 + i) < g.Nout, kcol = (k0 + i) < g.K;
+    for (int m = 0; m < g.Minner; m += 4) {
+        int mm = m + kk;
+        double2 c = (mm < g.Minner && ncol) ? C[(long long)mm * g.ldc + n0 + i] : cmk(0.0, 0.0);
+        double2 a = (mm < g.Minner && kcol) ? A[(long long)mm * g.lda + k0 + i] : cmk(0.0, 0.0);
+        dr = mfma(c.x, a.x, dr);
+        dr = mfma(-c.y, a.y, dr);
+        di = mfma(c.x, a.y, di);
+        di = mfma(c.y, a.x, di);
+    }
+    const double os = b < g.nk ? g.os_x : g.os_y;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        int n = n0 + 4 * v + kk, k = k0 + i;
+        if (n < g.Nout && k < g.K) {
+            double2* y = Y + (long long)n * g.ldy + k;
+            double2 cur = *y;
+            *y = cmk(os * (cur.x + g.cs * dr[v]), os * (cur.y + g.cs * di[v]));
+        }
+    }
+}
+
+// W[b][i][(n,s)] = sum_j sum_t D[i][j][s][t] Bm[b][j][(n,t)]
+__global__ void k_dmat(const double2* Bm, const double2* D, double2* Wm, int nproj, int nb, int nbatch) {
+    long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long per = (long long)nproj * 2 * nb;
+    if (idx >= per * nbatch) return;
+    long long b = idx / per;
+    int r = (int)(idx - b * per);
+    int i = r / (2 * nb), ns = r % (2 * nb);
+    int n = ns >> 1, s = ns & 1;
+    const double2* Bb = Bm + b * per;
+    double2 acc = cmk(0.0, 0.0);
+    for (int j = 0; j < nproj; ++j)
+        for (int t = 0; t < 2; ++t)
+            acc = cadd(acc, cmul(D[((i * nproj + j) * 2 + s) * 2 + t], Bb[(long long)j * 2 * nb + 2 * n + t]));
+    Wm[idx] = acc;
+}
+
+int choose_kchunk(int K, long long tiles_times_batch) {
+    // enough waves to fill the chip, but chunks of at least 64
+    long long target = 8192;
+    int ks = (int)std::max<long long>(1, target / std::max<long long>(1, tiles_times_batch));
+    int kc = (K + ks - 1) / ks;
+    kc = std::max(64, (kc + 3) / 4 * 4);
+    return kc;
+}
+
+void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const double2* B_base, long long b_bstride,
+                 int ldb, int M, int Nn, int K, int nbatch, double2* out, hipStream_t st) {
+    GemmCN g;
+    g.A_tab = A_tab;
+    g.A_base = nullptr;
+    g.a_bstride = 0;
+    g.lda = lda;
+    g.B_base = B_base;
+    g.b_bstride = b_bstride;
+    g.ldb = ldb;
+    g.M = M;
+    g.Nn = Nn;
+    g.K = K;
+    int mt = (M + 15) / 16;
+    g.nt = (Nn + 15) / 16;
+    g.kchunk = choose_kchunk(K, (long long)mt * g.nt * nbatch);
+    g.ksplit = (K + g.kchunk - 1) / g.kchunk;
+    TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
+    g.part = s.ws.gpart;
+    dim3 grid(mt * g.nt, g.ksplit, nbatch);
+    hipLaunchKernelGGL(k_gemm_cn, grid, dim3(64), 0, st, g);
+    check_launch("k_gemm_cn");
+    long long mn = (long long)M * Nn;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((mn * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
+                       out, g.ksplit, mn, nbatch);
+    check_launch("k_reduce_parts");
+}
+
+void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C, long long c_bstride, int ldc,
+                     const double2* const* A_tab, int lda, int Nout, int K, int Minner, double cs, double osx,
+                     double osy, int nk, hipStream_t st) {
+    GemmUpd g;
+    g.Y_base = Y;
+    g.y_bstride = y_bstride;
+    g.ldy = ldy;
+    g.C_base = C;
+    g.c_bstride = c_bstride;
+    g.ldc = ldc;
+    g.A_tab = A_tab;
+    g.lda = lda;
+    g.Nout = Nout;
+    g.K = K;
+    g.Minner = Minner;
+    g.cs = cs;
+    g.os_x = osx;
+    g.os_y = osy;
+    g.nk = nk;
+    dim3 grid((Nout + 15) / 16, (K + 15) / 16, 2 * nk);
+    hipLaunchKernelGGL(k_gemm_update, grid, dim3(64), 0, st, g);
+    check_launch("k_gemm_update");
+}
+
+}  // namespace
+
+size_t gemm_partial_elems(int nbatch, int M, int Nn, int K) {
+    int mt = (M + 15) / 16, nt = (Nn + 15) / 16;
+    int kc = choose_kchunk(K, (long long)mt * nt * nbatch);
+    int ks = (K + kc - 1) / kc;
+    return (size_t)nbatch * ks * M * Nn;
+}
+
+void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st) {
+    if (s.nproj == 0) return;
+    const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
+    const long long bstride = (long long)nb * 2 * P;
+    double2* Bm = s.ws.gsmall;
+    double2* Wm = s.ws.gsmall + (size_t)nbatch * s.nproj * 2 * nb;
+    run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, Bm, st);
+    long long tot = (long long)nbatch * s.nproj * 2 * nb;
+    hipLaunchKernelGGL(k_dmat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Bm, s.dvan, Wm, s.nproj, nb,
+                       nbatch);
+    check_launch("k_dmat");
+    run_gemm_update(out, bstride, P, Wm, (long long)s.nproj * 2 * nb, 2 * nb, q.d_vkb, P, 2 * nb, P, s.nproj, 1.0,
+                    1.0, 1.0, q.nk, st);
+}
+
+void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st) {
+    const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
+    const long long bstride = (long long)nb * 2 * P;
+    double2* S = s.ws.gsmall;
+    run_gemm_cn(s, (const double2* const*)q.d_occ, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, S, st);
+    run_gemm_update(phi, bstride, 2 * P, S, (long long)nb * nb, nb, (const double2* const*)q.d_occ, 2 * P, nb,
+                    2 * P, nb, -1.0, osx, osy, q.nk, st);
+}
+
+void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st) {
+    launch_project_signed(s, q, out, 1.0, -1.0, st);
+}
+
+}  // namespace tml

@@ -1,0 +1,56 @@
+// Device-side state of one Lanczos chain and the launch helpers of lanczos.hip.
+#pragma once
+
+#include "tm_internal.h"
+
+namespace tml {
+
+// breakdown tolerance of the chains (see tm.h for the rule it enters)
+constexpr double kBreakdownTol = 1e-10;
+
+// true vector = scale * raw vector
+struct ChainState {
+    double2 sq, slq, sprev;     // q, Lq, q_prev (pH: real)
+    double2 sp, spprev;         // p, p_prev (nH)
+    double2 alpha;
+    double2 gamma_prev;
+    double beta_prev;
+    double qq, pp;              // (q_i, q_i), (p_i, p_i)
+    double lam;
+    double n1;
+    int step;
+    int broken;
+};
+
+struct Coeffs {
+    double2* alpha;   // [cap]
+    double* beta;     // [cap]
+    double2* gamma;   // [cap]
+    double2* z;       // [3][cap]
+    int cap;
+};
+
+template <int ND>
+struct DotSet {
+    const double2* a[ND];
+    const double2* b[ND];
+    int jsign[ND];
+};
+
+template <int ND>
+void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
+                  hipStream_t st);
+void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
+                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st);
+void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
+                   const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
+                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st);
+void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st);
+void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
+void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, int j, int nsteps,
+                 hipStream_t st);
+void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
+void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, int j, hipStream_t st);
+void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, int j, int nsteps, hipStream_t st);
+
+}  // namespace tml

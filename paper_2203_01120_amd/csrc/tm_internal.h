@@ -1,0 +1,204 @@
+// Internal declarations of libtm: device helpers, the system object and the
+// kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/tm.h"
+
+namespace tml {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+struct Error {
+    int code;
+    std::string msg;
+};
+#define TM_HIP(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess)                                                     \
+            throw ::tml::Error{TM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+#define TM_CHECK(cond, code, msg)                                                 \
+    do {                                                                          \
+        if (!(cond)) throw ::tml::Error{(code), (msg)};                           \
+    } while (0)
+void check_launch(const char* what);
+
+// ---------------------------------------------------------------- complex
+__host__ __device__ inline double2 cmk(double r, double i) { return make_double2(r, i); }
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return cmk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+    return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// conj(a) * b
+__host__ __device__ inline double2 cmulc(double2 a, double2 b) {
+    return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 cconj(double2 a) { return cmk(a.x, -a.y); }
+__host__ __device__ inline double2 cscale(double2 a, double s) { return cmk(a.x * s, a.y * s); }
+__host__ __device__ inline double2 cmuli(double2 a) { return cmk(-a.y, a.x); }  // i*a
+__host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------- FFT plans
+constexpr int kMaxRadices = 8;
+struct FFTPlan {
+    int n;
+    int nrad;
+    int rad[kMaxRadices];
+    const double2* tw;  // device table exp(-2 pi i j / n), j < n
+};
+// factor n into radices 4, 5, 3, 2 (returns false if another prime divides n)
+bool make_radices(int n, FFTPlan& p);
+
+// One plane-wave sphere as seen by the FFT: its (m1, m2) columns and, per
+// column, the G entries with their i3 grid index.
+struct SphereMap {
+    int npw = 0;
+    int ncol = 0;
+    int* col_ptr = nullptr;   // [ncol+1] CSR over entries sorted by column
+    int* ent_g = nullptr;     // [npw] sphere index of each entry
+    int* ent_i3 = nullptr;    // [npw] grid i3 of each entry
+    int* col_pos = nullptr;   // [ncol] plane position i1*n2 + i2 of each column
+    std::vector<int> h_col_pos;
+};
+
+// Per q-set, per mesh point k: everything the apply needs.
+struct KBlock {
+    double kq[3];
+    int npw;                      // sphere of k+q
+    SphereMap sph_kq;             // response sphere
+    SphereMap sph_u[2];           // spheres of U_k (side 0) and U_-k (side 1)
+    const double2* u_coef[2];     // device coefficients of U_k, U_-k [nb][2][npw_u]
+    int npw_u[2];
+    double* kin = nullptr;        // [npw_pad] |k+q+G|^2/2 (0 in padding)
+    double* eps[2];               // [nb] e_k, e_-k (device)
+    double2* occ[2];              // [nb][2][npw_pad]: U_{k+q}, T U_{-k-q} on the k+q sphere
+    double2* vkb = nullptr;       // [nproj][npw_pad] projectors at k+q
+    int* map_k = nullptr;         // [npw] index of G in the U_k sphere or -1
+    int* map_mk = nullptr;        // [npw] index of -G in the U_-k sphere or -1
+};
+
+struct QSet {
+    double xq[3];
+    int nk;
+    int npw_pad;
+    int ncol_max;                 // max columns over the k+q spheres
+    int ncol_u_max;               // max columns over the u spheres
+    double lam;
+    std::vector<KBlock> kb;
+    double* hq = nullptr;         // [N] 4 pi/|G+q|^2 / N, plane-major
+    // device pointer tables (one entry per batch b = side*nk + ik)
+    int** d_colptr_kq = nullptr;
+    int** d_entg_kq = nullptr;
+    int** d_enti3_kq = nullptr;
+    int** d_colpos_kq = nullptr;
+    int* d_ncol_kq = nullptr;
+    int* d_npw_kq = nullptr;
+    int** d_colptr_u = nullptr;
+    int** d_entg_u = nullptr;
+    int** d_enti3_u = nullptr;
+    int** d_colpos_u = nullptr;
+    int* d_ncol_u = nullptr;
+    const double2** d_ucoef = nullptr;
+    int* d_npw_u = nullptr;
+    double** d_kin = nullptr;
+    double** d_eps = nullptr;
+    double2** d_occ = nullptr;
+    double2** d_vkb = nullptr;
+    int** d_maps = nullptr;       // restriction maps for the start vectors (map_k, map_mk)
+    // lazily built caches
+    double2* ucols = nullptr;     // z-transformed ground-state columns [b][nb*2][n3][ncol_u_max]
+    bool ucols_ready = false;
+};
+
+struct Workspace {
+    size_t bytes = 0;
+    double2* xcols = nullptr;     // [2nk][nb*2][n3][ncol_max] (also reused for phi columns)
+    double2* rho_part = nullptr;  // [nslot][4][N]
+    double2* rho = nullptr;       // [4][N]
+    double2* work = nullptr;      // [N] Hartree scratch
+    double2* W = nullptr;         // [4][N]
+    double2* gpart = nullptr;     // GEMM split-K partials
+    double2* gsmall = nullptr;    // reduced small GEMM outputs
+    double2* dots = nullptr;      // reduced inner products [64]
+    double2* dotpart = nullptr;   // per-block partial inner products
+    int nchunk = 0;
+    int ksplit = 0;
+    size_t cap_xcols = 0, cap_rho_part = 0, cap_gpart = 0, cap_gsmall = 0;
+};
+
+struct System {
+    int device = 0;
+    double cell[9];
+    double recip[9];
+    double omega;
+    int n1, n2, n3;
+    long long N;
+    int nbnd;
+    int nproj;
+    FFTPlan plan[3];
+    double2* tw[3] = {nullptr, nullptr, nullptr};
+    // ground-state points (device)
+    std::vector<double2*> evc;    // [npts] [nb][2][npw]
+    std::vector<int> npw;
+    std::vector<std::vector<int>> mill;   // host copies
+    std::vector<std::vector<double>> et;
+    std::vector<std::vector<double2>> h_vkb;
+    std::vector<double2> dvan_h;
+    double2* dvan = nullptr;      // [nproj][nproj][2][2]
+    double* vrs = nullptr;        // [4][N] plane-major
+    double* fxc = nullptr;        // [10][N] unique kernel entries, plane-major
+    std::vector<QSet> qs;
+    Workspace ws;
+    std::vector<void*> allocs;
+};
+
+template <typename T>
+T* dev_alloc(System& s, size_t count) {
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess)
+        throw Error{TM_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                                   " bytes failed: " + hipGetErrorString(e)};
+    s.allocs.push_back(p);
+    return static_cast<T*>(p);
+}
+template <typename T>
+T* dev_upload(System& s, const T* h, size_t count) {
+    T* d = dev_alloc<T>(s, count);
+    if (count) TM_HIP(hipMemcpy(d, h, count * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+// ---------------------------------------------------------------- launchers
+// fft.hip
+void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2* coef, long long coef_bstride,
+                      int nitems, int item_stride, double2* cols, hipStream_t st);
+void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin,
+                      double2* out, hipStream_t st);
+void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st);
+// apply.hip
+void launch_density(const System& s, const QSet& q, hipStream_t st);
+void launch_potential(const System& s, const QSet& q, hipStream_t st);
+void launch_apply_planes(const System& s, const QSet& q, hipStream_t st);
+void launch_fxc_setup(System& s, const double* rho_plane, hipStream_t st);
+void launch_coulomb_setup(const System& s, QSet& q, hipStream_t st);
+// gemm.hip
+void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st);
+void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st);
+
+// api.hip
+void apply_fp64(System& s, int iq, const double2* in, double2* out, hipStream_t st);
+void ensure_workspace(System& s, const QSet& q);
+
+}  // namespace tml

@@ -1,0 +1,185 @@
+"""HIP path vs the CPU oracle, through the C ABI (needs an MI355X).
+
+Tolerances: FP64 throughout.  The apply and the start vectors agree to
+1e-12 relative (different summation orders only).  Lanczos coefficients of
+short chains agree to 1e-10 relative (the recursion amplifies rounding
+differences as Ritz values converge).  chi from identical coefficients agrees
+to 1e-12.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chi as ochi
+from oracle import lanczos as olanczos
+from oracle import liouvillian as lv
+
+from gpu_util import desc_from_problem, from_gpu, rel_err, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2203_01120_amd as tm
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    tm.load()
+    return tm
+
+
+class Sys:
+    def __init__(self, tm, prob):
+        self.tm, self.prob = tm, prob
+        self.h = tm.tm_system_create(desc_from_problem(prob))
+        self.info = tm.tm_qset_info_get(self.h, 0)
+        self.shape = (2, prob.nk, prob.nb, 2, self.info["npw_pad"])
+
+    def apply(self, x, kernel=True):
+        import torch
+        xin = to_gpu(x, self.info["npw_pad"])
+        out = torch.empty_like(xin)
+        self.tm.tm_liouvillian_apply(self.h, 0, xin, out)
+        torch.cuda.synchronize()
+        return from_gpu(out, self.shape, self.prob.npw_pad)
+
+    def close(self):
+        self.tm.tm_system_destroy(self.h)
+
+
+@pytest.fixture(scope="module")
+def tiny(lib, tiny_gs, tiny_q):
+    say("create tiny system")
+    s = Sys(lib, lv.build_problem(tiny_gs, tiny_q))
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def cfg1(lib, cfg1_gs, cfg1_q):
+    say("create cfg1 system")
+    s = Sys(lib, lv.build_problem(cfg1_gs, cfg1_q))
+    yield s
+    s.close()
+
+
+@pytest.mark.parametrize("which", ["tiny", "cfg1"])
+def test_apply_matches_oracle(which, request):
+    s = request.getfixturevalue(which)
+    for seed in (1, 2):
+        say(f"apply {which} seed {seed}")
+        x = s.prob.random_projected(seed)
+        got, raw = s.apply(x)
+        ref = s.prob.apply(x)
+        assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
+        # padding of the output is zero
+        npw = [kd.npw for kd in s.prob.k]
+        for ik, n in enumerate(npw):
+            assert np.all(raw[:, ik, :, :, n:] == 0)
+
+
+def test_apply_is_linear_and_orthogonal(cfg1):
+    say("apply linearity cfg1")
+    a = cfg1.prob.random_projected(3)
+    b = cfg1.prob.random_projected(4)
+    la, _ = cfg1.apply(a)
+    lb, _ = cfg1.apply(b)
+    lab, _ = cfg1.apply(a + (0.3 - 0.7j) * b)
+    assert rel_err(lab, la + (0.3 - 0.7j) * lb) <= 1e-12
+    assert cfg1.prob.occupied_overlap(la) <= 1e-12 * np.abs(la).max()
+
+
+@pytest.mark.parametrize("direction", ["x", "y", "z", "+", "-"])
+def test_start_vectors_match_oracle(cfg1, direction):
+    import torch
+    say(f"start vectors {direction}")
+    n = cfg1.info["nelem"]
+    u = torch.empty(n, dtype=torch.complex128, device="cuda")
+    v = torch.empty_like(u)
+    cfg1.tm.tm_start_vectors(cfg1.h, 0, direction, u, v)
+    torch.cuda.synchronize()
+    gu, _ = from_gpu(u, cfg1.shape, cfg1.prob.npw_pad)
+    gv, _ = from_gpu(v, cfg1.shape, cfg1.prob.npw_pad)
+    assert rel_err(gv, cfg1.prob.v_vector(direction)) <= 1e-12
+    if direction in "xyz":
+        assert rel_err(gu, cfg1.prob.u_vector(direction)) <= 1e-13
+
+
+@pytest.mark.parametrize("flavour,mu,nsteps", [("pH", "+", 60), ("nH", "+", 20), ("pH", "z", 20)])
+def test_lanczos_coefficients_match_oracle(cfg1, flavour, mu, nsteps):
+    say(f"lanczos cfg1 {flavour} {mu} {nsteps}")
+    got = cfg1.tm.tm_lanczos_run(cfg1.h, 0, mu, flavour, nsteps)
+    ref = olanczos.run(cfg1.prob, mu, flavour, nsteps)
+    assert got["steps_done"] == ref["steps_done"] == nsteps
+    assert not got["breakdown"]
+    assert abs(got["n1"] - ref["n1"]) <= 1e-12 * ref["n1"]
+    ascale = np.abs(ref["alpha"]).max()
+    assert np.abs(got["alpha"] - ref["alpha"]).max() <= 1e-10 * ascale
+    assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
+    assert np.abs(got["gamma"] - ref["gamma"]).max() <= 1e-10 * np.abs(ref["gamma"]).max()
+    zs = np.abs(ref["z"]).max()
+    assert np.abs(got["z"] - ref["z"]).max() <= 1e-10 * zs
+
+
+def test_chi_matches_oracle(cfg1):
+    say("chi cfg1")
+    coeffs = cfg1.tm.tm_lanczos_run(cfg1.h, 0, "+", "pH", 60)
+    omega = np.arange(400) * 5e-3 / 27.211386245988   # 0 .. 1.995 eV in Ha
+    eta = 5e-3 / 27.211386245988
+    got = cfg1.tm.tm_chi(coeffs, 60, omega, eta)
+    ref = ochi.chi_lanczos(coeffs, omega, eta, 60)
+    assert rel_err(got, ref) <= 1e-12
+    # and against the chain run entirely by the oracle
+    oref = olanczos.run(cfg1.prob, "+", "pH", 60)
+    cref = ochi.chi_lanczos(oref, omega, eta, 60)
+    assert rel_err(got, cref) <= 1e-9
+
+
+def test_nonhermitian_chi_solver_with_pivoting(lib, tiny):
+    """Complex alpha/gamma and near-singular leading entries exercise the row interchanges."""
+    say("chi solver pivoting")
+    rng = np.random.default_rng(7)
+    M = 40
+    co = dict(alpha=rng.standard_normal(M) * 1e-3 + 1j * rng.standard_normal(M) * 1e-4,
+              beta=np.abs(rng.standard_normal(M)) + 0.5,
+              gamma=rng.standard_normal(M) + 1j * rng.standard_normal(M),
+              z=rng.standard_normal((3, M)) + 1j * rng.standard_normal((3, M)),
+              n1=1.7, steps_done=M)
+    omega = np.linspace(-0.01, 0.01, 33)
+    got = lib.tm_chi(co, M, omega, 1e-6)
+    ref = ochi.chi_lanczos(co, omega, 1e-6, M)
+    assert rel_err(got, ref) <= 1e-10
+
+
+def test_goldstone_breakdown(lib, tiny_gs_nosoc):
+    say("goldstone breakdown")
+    prob = lv.build_problem(tiny_gs_nosoc, np.zeros(3))
+    s = Sys(lib, prob)
+    try:
+        r = lib.tm_lanczos_run(s.h, 0, "x", "nH", 5)
+        assert r["breakdown"] and r["steps_done"] == 1
+        r = lib.tm_lanczos_run(s.h, 0, "x", "pH", 5)
+        assert r["breakdown"] and r["steps_done"] == 0
+        ref = olanczos.run(prob, "x", "pH", 5)
+        assert ref["breakdown"] and ref["steps_done"] == 0
+    finally:
+        s.close()
+
+
+def test_invalid_arguments(lib, tiny):
+    import torch
+    say("invalid arguments")
+    n = tiny.info["nelem"]
+    x = torch.zeros(n, dtype=torch.complex128, device="cuda")
+    with pytest.raises(lib.TmError) as e:
+        lib.tm_liouvillian_apply(tiny.h, 0, x, x)
+    assert e.value.code == lib.TM_EINVAL
+    with pytest.raises(lib.TmError) as e:
+        lib.tm_liouvillian_apply(tiny.h, 3, x, torch.zeros_like(x))
+    assert e.value.code == lib.TM_EINVAL
+    with pytest.raises(lib.TmError) as e:
+        lib.tm_liouvillian_apply(tiny.h, 0, x, torch.zeros_like(x), prec=lib.TM_FP32)
+    co = dict(alpha=np.zeros(3, complex), beta=np.zeros(3), gamma=np.zeros(3, complex),
+              z=np.zeros((3, 3), complex), n1=1.0, steps_done=2)
+    with pytest.raises(lib.TmError):
+        lib.tm_chi(co, 3, np.zeros(4), 0.1)
