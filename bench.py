@@ -1,0 +1,255 @@
+#!/usr/bin/env python3
+"""Throughput of the Liouville-Lanczos hot path on one MI355X.
+
+Workload (default): the CrI3-monolayer-shaped system -- hexagonal a = 13 bohr,
+c = 31 bohr (25 bohr vacuum), 2 'Cr' + 6 'I' Gaussian sites with s/px/py
+Kleinman-Bylander projectors (SOC 0.02 Ha on 'I'), ~8000 plane waves per spinor
+component, FFT grid 48 x 48 x 180, 104 occupied spinor bands, 6x6x1 k-mesh
+(36 k, no symmetry), q = b1/6.  Inputs are seeded and synthetic: the occupied
+manifold is a smooth random orthonormal set (no SCF at this size).
+
+A step is one pseudo-Hermitian Lanczos step for the m_+ chain: one
+Liouvillian application (FFTs, response density, Hartree + ALSDA potential,
+local/nonlocal/SOC terms, empty-manifold projection) plus the FP64 recurrence.
+The timed region is one tm_lanczos_run of K steps (K + 1 applies, including
+the chain set-up), bracketed by device synchronisations.  `value` is
+Liouvillian applies per second; spectra/s is the rate of full 3000-step
+chains that implies.  The roofline object describes the kernel with the
+largest share of the timed region, from HIP events around its launches.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector and FP64 matrix (dense)
+HA_PER_MEV = 1.0 / 27211.386245988
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def build_inputs(workload: str, seed: int):
+    import synth
+    if workload == "cfg2":
+        sysd = synth.make_cfg2()
+        q = synth.cart_from_frac(sysd, [1.0 / 6.0, 0.0, 0.0])
+    elif workload == "cfg1":
+        sysd = synth.make_cfg1()
+        q = np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0
+    else:
+        raise SystemExit(f"unknown workload {workload}")
+    return synth.synthetic_inputs(sysd, q, seed=seed)
+
+
+def make_desc(inp):
+    import paper_2203_01120_amd as tm
+    qs = inp["qset"]
+    pts = [tm.Point(xk=p, mill=m, evc=e, et=et, vkb=v) for (p, m, e, et, v) in inp["points"]]
+    sysd = inp["sysd"]
+    return tm.SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=sysd.nbnd, points=pts, vrs=inp["vrs"],
+                         rho=inp["rho"], dvan=inp["dvan"], xq=qs.q[None], roles=qs.roles[None],
+                         shifts=qs.shifts[None])
+
+
+def kernel_models(inp, info):
+    """Algorithmic work per launch of the main kernels (flops, bytes)."""
+    sysd = inp["sysd"]
+    n1, n2, n3 = sysd.fft
+    NP = n1 * n2
+    nk = info["nk"]
+    nb = sysd.nbnd
+    P = info["npw_pad"]
+    nproj = sysd.nproj
+    fft2d = 5.0 * NP * math.log2(NP)
+    bands = 2 * nk * nb
+    npw_avg = np.mean([m.shape[0] for (_, m, _, _, _) in inp["points"]])
+    vec_bytes = 2 * nk * nb * 2 * npw_avg * 16
+    return {
+        # 4 inverse + 2 forward plane FFTs per band and plane, ~60 flops/point for V0 x + V' u
+        "k_apply_planes": dict(flops=bands * n3 * (6 * fft2d + 60.0 * NP), bound="alu"),
+        # 4 inverse plane FFTs per band and plane, ~40 flops/point for the 4 densities
+        "k_density": dict(flops=bands * n3 * (4 * fft2d + 40.0 * NP), bound="alu"),
+        # projector GEMMs: S = O^H phi and phi -= O S (8 real flops per complex MAC)
+        "k_gemm_cn": dict(flops=8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P), bound="mfma"),
+        "k_gemm_update": dict(flops=8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P), bound="mfma"),
+        "vector": dict(bytes=vec_bytes),
+    }
+
+
+def cpu_baseline(workload: str, seed: int, nk_full: int):
+    """The oracle's matrix-free apply on one mesh point of the same system (bounded sample)."""
+    import synth
+    from oracle import liouvillian as lv
+
+    class _GS:  # the oracle Problem only reads these fields here
+        pass
+
+    sysd = synth.make_cfg2() if workload == "cfg2" else synth.make_cfg1()
+    if workload == "cfg2":
+        q = synth.cart_from_frac(sysd, [1.0 / 6.0, 0.0, 0.0])
+        subset = [7] if len(sysd.kmesh) > 7 else [0]
+    else:
+        q = np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0
+        subset = [0]
+    inp = synth.synthetic_inputs(sysd, q, seed=seed, kmesh_subset=subset)
+    gs = _GS()
+    gs.sysd, gs.vrs, gs.rho = inp["sysd"], inp["vrs"], inp["rho"]
+    prob = lv.Problem(gs, inp["qset"], point_states=[(m, e, et) for (_, m, e, et, _) in inp["points"]])
+    x = prob.random_projected(1)
+    t0 = time.perf_counter()
+    prob.apply(x)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        blas = 1
+    per_apply = dt * nk_full / len(subset)
+    return {"value": 1.0 / per_apply, "unit": "applies/s", "cores": int(blas), "kind": "oracle",
+            "sample": f"one matrix-free oracle apply restricted to {len(subset)} of {nk_full} mesh points "
+                      f"(same grid, bands, spheres, projectors), {dt:.1f} s, scaled x{nk_full // len(subset)}; "
+                      f"numpy FFTs single-threaded, BLAS threads {blas}",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency-samples", type=int, default=20)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain device copy of known size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        raise SystemExit("bench.py supports --gpus 1 only: the hot path is built and measured on one GPU")
+
+    import torch
+    import paper_2203_01120_amd as tm
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    tm.load()
+
+    log(f"building {args.workload} inputs")
+    t0 = time.time()
+    inp = build_inputs(args.workload, args.seed)
+    log(f"inputs ready in {time.time() - t0:.1f} s ({len(inp['points'])} ground-state points)")
+    h = tm.tm_system_create(make_desc(inp))
+    info = tm.tm_qset_info_get(h, 0)
+    log(f"system created: nk={info['nk']} nbnd={info['nbnd']} npw_pad={info['npw_pad']} "
+        f"vector {info['nelem'] * 16 / 1e9:.2f} GB")
+
+    if args.calib_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log(f"warmup {args.warmup} steps")
+    tm.tm_lanczos_run(h, 0, "+", "pH", max(1, args.warmup))
+    torch.cuda.synchronize()
+
+    log(f"timed {args.steps} steps")
+    tm.tm_profile_reset()
+    tm.tm_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = tm.tm_lanczos_run(h, 0, "+", "pH", args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm.tm_profile_enable(False)
+    prof = tm.tm_profile_read()
+    applies = args.steps + 1
+    applies_per_s = applies / dt
+    log(f"{args.steps} steps in {dt:.3f} s -> {applies_per_s:.3f} applies/s; breakdown={res['breakdown']}")
+
+    # per-apply latency
+    lat = []
+    n = info["nelem"]
+    x = torch.empty(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    tm.tm_start_vectors(h, 0, "+", None, x)
+    for _ in range(args.latency_samples):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tm.tm_liouvillian_apply(h, 0, x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        lat.append(e0.elapsed_time(e1))
+    lat = np.array(lat)
+
+    models = kernel_models(inp, info)
+    total_ms = sum(v[0] for v in prof.values())
+    kernels = {k: {"ms_total": round(v[0], 3), "launches": v[1], "ms_avg": round(v[0] / max(v[1], 1), 4),
+                   "share": round(v[0] / total_ms, 4)} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    dom = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    avg_s = prof[dom][0] / prof[dom][1] / 1e3
+    roof = None
+    if dom in models and "flops" in models[dom]:
+        m = models[dom]
+        ach = m["flops"] / avg_s / 1e12
+        roof = {"kernel": dom, "bound": m["bound"], "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_ms": round(avg_s * 1e3, 4), "algorithmic_flops_per_launch": m["flops"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(args.workload, args.seed, info["nk"])
+        log(f"oracle: {cpu['seconds']:.1f} s for the sample")
+
+    sysd = inp["sysd"]
+    chain_m = 3000
+    out = {
+        "metric": "Liouvillian applies/s and chi(q,omega) spectra/s at stated error; p50/p99 latency",
+        "value": round(applies_per_s, 4),
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("CrI3-monolayer-shaped hexagonal slab, a=13 c=31 bohr, 2+6 Gaussian sites, "
+                         "48x48x180 grid, 104 bands, 6x6x1 mesh (36 k), q=b1/6, pH chain m_+"
+                         if args.workload == "cfg2" else
+                         "cubic a=10 bohr, 2 sites, 20^3 grid, 8 bands, Gamma, q=0.1 2pi/a, pH chain m_+"),
+            "fft": list(sysd.fft), "nbnd": sysd.nbnd, "nk": info["nk"], "npw_pad": info["npw_pad"],
+            "nproj": sysd.nproj, "precision": "fp64", "flavour": "pseudo_hermitian",
+        },
+        "spectra_per_s": round(applies_per_s / (chain_m + 1), 6),
+        "spectrum_steps": chain_m,
+        "apply_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                             "p99": round(float(np.percentile(lat, 99)), 3)},
+        "roofline": roof,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    tm.tm_system_destroy(h)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

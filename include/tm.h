@@ -191,6 +191,19 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
 int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, double eta,
            double* chi);
 
+/*
+ * Kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by two HIP events on the stream it runs on; tm_profile_count
+ * synchronises the device, folds the elapsed times per kernel name and
+ * returns the number of distinct kernels; tm_profile_get(i, ...) returns the
+ * name (truncated to name_cap-1 chars), total milliseconds and launch count of
+ * entry i (TM_EINVAL when i is out of range).  Process-wide; not thread-safe.
+ */
+int tm_profile_enable(int on);
+int tm_profile_reset(void);
+int tm_profile_count(void);
+int tm_profile_get(int i, char* name, int name_cap, double* total_ms, long long* launches);
+
 /* Message for the last error on the calling thread ("" if none). */
 const char* tm_last_error(void);
 

@@ -24,7 +24,8 @@ DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4}
 FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_liouvillian_apply",
-            "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_last_error"]
+            "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
+            "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
 
 class TmError(RuntimeError):
@@ -76,6 +77,10 @@ def load(path: str = LIB_PATH):
     lib.tm_lanczos_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_Coeffs)]
     lib.tm_chi.argtypes = [C.POINTER(_Coeffs), C.c_int, C.POINTER(C.c_double), C.c_int, C.c_double,
                            C.POINTER(C.c_double)]
+    lib.tm_profile_enable.argtypes = [C.c_int]
+    lib.tm_profile_reset.argtypes = []
+    lib.tm_profile_count.argtypes = []
+    lib.tm_profile_get.argtypes = [C.c_int, C.c_char_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_longlong)]
     lib.tm_last_error.restype = C.c_char_p
     for name in EXPORTED:
         getattr(lib, name).restype = C.c_int if name != "tm_last_error" else C.c_char_p
@@ -253,4 +258,27 @@ def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:
     out = np.zeros((3, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi(C.byref(co), int(m_use), _dptr(om), om.shape[0], float(eta),
                          out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def tm_profile_enable(on: bool = True):
+    _check(load().tm_profile_enable(1 if on else 0))
+
+
+def tm_profile_reset():
+    _check(load().tm_profile_reset())
+
+
+def tm_profile_read() -> dict:
+    """{kernel name: (total ms, launches)} of the launches recorded so far."""
+    lib = load()
+    n = lib.tm_profile_count()
+    if n < 0:
+        _check(n)
+    out = {}
+    buf = C.create_string_buffer(128)
+    for i in range(n):
+        ms, cnt = C.c_double(), C.c_longlong()
+        _check(lib.tm_profile_get(i, buf, 128, C.byref(ms), C.byref(cnt)))
+        out[buf.value.decode()] = (ms.value, cnt.value)
     return out

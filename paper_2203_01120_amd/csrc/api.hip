@@ -19,6 +19,66 @@ void launch_chi(const double2* alpha, const double* beta, const double2* gamma, 
 static thread_local std::string g_err;
 void set_error(const std::string& m) { g_err = m; }
 
+// ---- kernel timing ----------------------------------------------------------------
+namespace {
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+struct ProfAgg {
+    std::string name;
+    double ms = 0;
+    long long n = 0;
+};
+std::vector<ProfAgg> g_prof_agg;
+
+hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    TM_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void prof_fold() {
+    if (g_prof_pending.empty()) return;
+    TM_HIP(hipDeviceSynchronize());
+    for (auto& r : g_prof_pending) {
+        float ms = 0;
+        TM_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        auto it = std::find_if(g_prof_agg.begin(), g_prof_agg.end(), [&](const ProfAgg& x) { return x.name == r.name; });
+        if (it == g_prof_agg.end()) {
+            g_prof_agg.push_back(ProfAgg{r.name, 0, 0});
+            it = g_prof_agg.end() - 1;
+        }
+        it->ms += ms;
+        it->n += 1;
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof_pending.clear();
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t s) : slot(-1), st(s) {
+    if (!g_prof_on) return;
+    if (g_prof_pending.size() > 200000) prof_fold();
+    ProfRec r{name, prof_event(), prof_event()};
+    TM_HIP(hipEventRecord(r.a, st));
+    g_prof_pending.push_back(r);
+    slot = (int)g_prof_pending.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+    if (slot >= 0) (void)hipEventRecord(g_prof_pending[slot].b, st);
+}
+
 void check_launch(const char* what) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw Error{TM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e)};
@@ -270,16 +330,13 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
         kb.occ[0] = dev_alloc<double2>(s, (size_t)nb * 2 * P);
         kb.occ[1] = dev_alloc<double2>(s, (size_t)nb * 2 * P);
         dim3 gr((P + 127) / 128, nb);
-        hipLaunchKernelGGL(k_occ, gr, dim3(128), 0, st, s.evc[pkq], npw, (const int*)nullptr, npw, P, nb, 0, kb.occ[0]);
-        check_launch("k_occ");
-        hipLaunchKernelGGL(k_occ, gr, dim3(128), 0, st, s.evc[pmkq], npw, d_map_mkq, npw, P, nb, 1, kb.occ[1]);
-        check_launch("k_occ");
+        TM_LAUNCH(k_occ, gr, dim3(128), 0, st, s.evc[pkq], npw, (const int*)nullptr, npw, P, nb, 0, kb.occ[0]);
+        TM_LAUNCH(k_occ, gr, dim3(128), 0, st, s.evc[pmkq], npw, d_map_mkq, npw, P, nb, 1, kb.occ[1]);
         if (s.nproj > 0) {
             double2* vk = dev_upload(s, s.h_vkb[pkq].data(), s.h_vkb[pkq].size());
             kb.vkb = dev_alloc<double2>(s, (size_t)s.nproj * P);
-            hipLaunchKernelGGL(k_pad_copy, dim3((P + 127) / 128, s.nproj), dim3(128), 0, st, vk, npw, P, s.nproj,
+            TM_LAUNCH(k_pad_copy, dim3((P + 127) / 128, s.nproj), dim3(128), 0, st, vk, npw, P, s.nproj,
                                kb.vkb);
-            check_launch("k_pad_copy");
         }
         for (int side = 0; side < 2; ++side) {
             int b = side * nk + ik;
@@ -396,9 +453,8 @@ void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream
     QSet& q = s.qs[iq];
     ensure_workspace(s, q);
     dim3 gr((q.npw_pad + 127) / 128, s.nbnd, 2 * q.nk);
-    hipLaunchKernelGGL(k_start, gr, dim3(128), 0, st, q.d_ucoef, q.d_npw_u, (const int* const*)q.d_maps, q.nk,
+    TM_LAUNCH(k_start, gr, dim3(128), 0, st, q.d_ucoef, q.d_npw_u, (const int* const*)q.d_maps, q.nk,
                        s.nbnd, q.npw_pad, dir, -1.0, u, v);
-    check_launch("k_start");
     if (v) launch_project_signed(s, q, v, 1.0, 1.0, st);
 }
 
@@ -556,6 +612,43 @@ static int guarded(F&& f) {
 extern "C" {
 
 const char* tm_last_error(void) { return g_err.c_str(); }
+
+int tm_profile_enable(int on) {
+    return guarded([&]() -> int {
+        if (!on) prof_fold();
+        g_prof_on = on != 0;
+        return TM_OK;
+    });
+}
+
+int tm_profile_reset(void) {
+    return guarded([&]() -> int {
+        prof_fold();
+        g_prof_agg.clear();
+        return TM_OK;
+    });
+}
+
+int tm_profile_count(void) {
+    return guarded([&]() -> int {
+        prof_fold();
+        return (int)g_prof_agg.size();
+    });
+}
+
+int tm_profile_get(int i, char* name, int name_cap, double* total_ms, long long* launches) {
+    return guarded([&]() -> int {
+        TM_CHECK(i >= 0 && i < (int)g_prof_agg.size(), TM_EINVAL, "profile index out of range");
+        const ProfAgg& a = g_prof_agg[i];
+        if (name && name_cap > 0) {
+            std::strncpy(name, a.name.c_str(), name_cap - 1);
+            name[name_cap - 1] = 0;
+        }
+        if (total_ms) *total_ms = a.ms;
+        if (launches) *launches = a.n;
+        return TM_OK;
+    });
+}
 
 int tm_system_create(const tm_system_desc* d, tm_system** out) {
     return guarded([&]() -> int {

@@ -339,25 +339,20 @@ void launch_density(const System& s, const QSet& q, hipStream_t st) {
     int th = plane_threads(s);
     dim3 grid(s.n3, a.nchunk, 2 * q.nk);
     size_t shm = (size_t)a.NP * sizeof(double2);
-    hipLaunchKernelGGL(k_density, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
-    check_launch("k_density");
+    TM_LAUNCH(k_density, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
     long long n4 = 4 * s.N;
-    hipLaunchKernelGGL(k_density_reduce, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, s.ws.rho_part,
+    TM_LAUNCH(k_density_reduce, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, s.ws.rho_part,
                        s.ws.rho, s.N, q.nk, a.nchunk, 1.0 / (s.omega * q.nk));
-    check_launch("k_density_reduce");
 }
 
 void launch_potential(const System& s, const QSet& q, hipStream_t st) {
     long long N = s.N;
     unsigned nbk = (unsigned)((N + 255) / 256);
-    hipLaunchKernelGGL(k_copy_scale, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, N);
-    check_launch("k_copy_scale");
+    TM_LAUNCH(k_copy_scale, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, N);
     launch_fft3d_full(s, s.ws.work, -1, st);
-    hipLaunchKernelGGL(k_mul_real, dim3(nbk), dim3(256), 0, st, s.ws.work, q.hq, N);
-    check_launch("k_mul_real");
+    TM_LAUNCH(k_mul_real, dim3(nbk), dim3(256), 0, st, s.ws.work, q.hq, N);
     launch_fft3d_full(s, s.ws.work, +1, st);
-    hipLaunchKernelGGL(k_assemble_W, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, s.fxc, s.ws.W, N);
-    check_launch("k_assemble_W");
+    TM_LAUNCH(k_assemble_W, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, s.fxc, s.ws.W, N);
 }
 
 void launch_apply_planes(const System& s, const QSet& q, hipStream_t st) {
@@ -365,31 +360,27 @@ void launch_apply_planes(const System& s, const QSet& q, hipStream_t st) {
     int th = plane_threads(s);
     dim3 grid(s.n3, a.nchunk, 2 * q.nk);
     size_t shm = (size_t)a.NP * sizeof(double2);
-    hipLaunchKernelGGL(k_apply_planes, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
-    check_launch("k_apply_planes");
+    TM_LAUNCH(k_apply_planes, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
 }
 
 void launch_fxc_setup(System& s, const double* rho_plane, hipStream_t st) {
-    hipLaunchKernelGGL(k_fxc, dim3((unsigned)((s.N + 255) / 256)), dim3(256), 0, st, rho_plane, s.fxc, s.N);
-    check_launch("k_fxc");
+    TM_LAUNCH(k_fxc, dim3((unsigned)((s.N + 255) / 256)), dim3(256), 0, st, rho_plane, s.fxc, s.N);
 }
 
 void launch_coulomb_setup(const System& s, QSet& q, hipStream_t st) {
     const double* B = s.recip;
-    hipLaunchKernelGGL(k_coulomb, dim3((unsigned)((s.N + 255) / 256)), dim3(256), 0, st, q.hq, s.n1, s.n2, s.n3,
+    TM_LAUNCH(k_coulomb, dim3((unsigned)((s.N + 255) / 256)), dim3(256), 0, st, q.hq, s.n1, s.n2, s.n3,
                        make_double3(B[0], B[1], B[2]), make_double3(B[3], B[4], B[5]),
                        make_double3(B[6], B[7], B[8]), make_double3(q.xq[0], q.xq[1], q.xq[2]),
                        1.0 / (double)s.N);
-    check_launch("k_coulomb");
 }
 
 void launch_kin(const System& s, double* kin, const int* d_mill, int npw, int npw_pad, const double* p,
                 hipStream_t st) {
     const double* B = s.recip;
-    hipLaunchKernelGGL(k_kin, dim3((npw_pad + 255) / 256), dim3(256), 0, st, kin, d_mill, npw, npw_pad,
+    TM_LAUNCH(k_kin, dim3((npw_pad + 255) / 256), dim3(256), 0, st, kin, d_mill, npw, npw_pad,
                        make_double3(p[0], p[1], p[2]), make_double3(B[0], B[1], B[2]),
                        make_double3(B[3], B[4], B[5]), make_double3(B[6], B[7], B[8]));
-    check_launch("k_kin");
 }
 
 }  // namespace tml

@@ -89,9 +89,8 @@ void launch_chi(const double2* alpha, const double* beta, const double2* gamma, 
                 double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
                 hipStream_t st) {
     long long per = (long long)M * nw;
-    hipLaunchKernelGGL(k_chi, dim3((nw + 63) / 64), dim3(64), 0, st, alpha, beta, gamma, z, cap, M, n1, omega, nw,
+    TM_LAUNCH(k_chi, dim3((nw + 63) / 64), dim3(64), 0, st, alpha, beta, gamma, z, cap, M, n1, omega, nw,
                        eta, work, work + per, work + 2 * per, work + 3 * per, chi, status);
-    check_launch("k_chi");
 }
 
 }  // namespace tml

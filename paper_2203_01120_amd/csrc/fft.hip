@@ -226,8 +226,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
     int ncolmax = ucols ? q.ncol_u_max : q.ncol_max;
     dim3 grid((ncolmax + a.ct - 1) / a.ct, (nitems + it - 1) / it, nb2);
     size_t shm = (size_t)L * n3 * sizeof(double2);
-    hipLaunchKernelGGL(k_zpass_inv, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
-    check_launch("k_zpass_inv");
+    TM_LAUNCH(k_zpass_inv, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
 }
 
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin, double2* out,
@@ -254,8 +253,7 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
     int it = L / a.ct;
     dim3 grid((q.ncol_max + a.ct - 1) / a.ct, (a.nitems + it - 1) / it, 2 * q.nk);
     size_t shm = (size_t)L * n3 * sizeof(double2);
-    hipLaunchKernelGGL(k_zpass_fwd, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
-    check_launch("k_zpass_fwd");
+    TM_LAUNCH(k_zpass_fwd, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
 }
 
 // data: plane-major [i3][i1][i2]
@@ -279,9 +277,8 @@ void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st)
         }
         dim3 grid((nlines + L - 1) / L);
         size_t shm = (size_t)L * p.n * sizeof(double2);
-        hipLaunchKernelGGL(k_fft_lines, grid, dim3(kZThreads), shm, st, data, nlines, inner, outer_stride,
+        TM_LAUNCH(k_fft_lines, grid, dim3(kZThreads), shm, st, data, nlines, inner, outer_stride,
                            inner_stride, estride, L, *pl, sign);
-        check_launch("k_fft_lines");
     }
 }
 

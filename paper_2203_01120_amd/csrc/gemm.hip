@@ -168,12 +168,10 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
     TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
     g.part = s.ws.gpart;
     dim3 grid(mt * g.nt, g.ksplit, nbatch);
-    hipLaunchKernelGGL(k_gemm_cn, grid, dim3(64), 0, st, g);
-    check_launch("k_gemm_cn");
+    TM_LAUNCH(k_gemm_cn, grid, dim3(64), 0, st, g);
     long long mn = (long long)M * Nn;
-    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((mn * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
+    TM_LAUNCH(k_reduce_parts, dim3((unsigned)((mn * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
                        out, g.ksplit, mn, nbatch);
-    check_launch("k_reduce_parts");
 }
 
 void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C, long long c_bstride, int ldc,
@@ -196,8 +194,7 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
     g.os_y = osy;
     g.nk = nk;
     dim3 grid((Nout + 15) / 16, (K + 15) / 16, 2 * nk);
-    hipLaunchKernelGGL(k_gemm_update, grid, dim3(64), 0, st, g);
-    check_launch("k_gemm_update");
+    TM_LAUNCH(k_gemm_update, grid, dim3(64), 0, st, g);
 }
 
 }  // namespace
@@ -217,9 +214,8 @@ void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* 
     double2* Wm = s.ws.gsmall + (size_t)nbatch * s.nproj * 2 * nb;
     run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, Bm, st);
     long long tot = (long long)nbatch * s.nproj * 2 * nb;
-    hipLaunchKernelGGL(k_dmat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Bm, s.dvan, Wm, s.nproj, nb,
+    TM_LAUNCH(k_dmat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Bm, s.dvan, Wm, s.nproj, nb,
                        nbatch);
-    check_launch("k_dmat");
     run_gemm_update(out, bstride, P, Wm, (long long)s.nproj * 2 * nb, 2 * nb, q.d_vkb, P, 2 * nb, P, s.nproj, 1.0,
                     1.0, 1.0, q.nk, st);
 }

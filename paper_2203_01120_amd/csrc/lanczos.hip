@@ -274,10 +274,8 @@ template <int ND>
 void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
                   hipStream_t st) {
     int nblk = (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
-    hipLaunchKernelGGL(k_multidot<ND>, dim3(nblk), dim3(kRedThreads), 0, st, ds, n, half, part);
-    check_launch("k_multidot");
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, ND, w, out);
-    check_launch("k_dot_final");
+    TM_LAUNCH(k_multidot<ND>, dim3(nblk), dim3(kRedThreads), 0, st, ds, n, half, part);
+    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, ND, w, out);
 }
 template void run_multidot<1>(const DotSet<1>&, long long, long long, double, double2*, double2*, hipStream_t);
 template void run_multidot<3>(const DotSet<3>&, long long, long long, double, double2*, double2*, hipStream_t);
@@ -291,48 +289,38 @@ static int red_blocks(long long n) {
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
                    const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st) {
     int nblk = red_blocks(n);
-    hipLaunchKernelGGL(k_ph_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], n, part);
-    check_launch("k_ph_update");
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 3, w, out);
-    check_launch("k_dot_final");
+    TM_LAUNCH(k_ph_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], n, part);
+    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 3, w, out);
 }
 
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
                    long long n, long long half, double w, double2* part, double2* out, hipStream_t st) {
     int nblk = red_blocks(n);
-    hipLaunchKernelGGL(k_nh_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0], u[1],
+    TM_LAUNCH(k_nh_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0], u[1],
                        u[2], n, half, part);
-    check_launch("k_nh_update");
-    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 6, w, out);
-    check_launch("k_dot_final");
+    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 6, w, out);
 }
 
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st) {
-    hipLaunchKernelGGL(k_jcopy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n, half);
-    check_launch("k_jcopy");
+    TM_LAUNCH(k_jcopy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n, half);
 }
 
 void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
-    hipLaunchKernelGGL(k_ph_start, dim3(1), dim3(1), 0, st, cs, d, co);
-    check_launch("k_ph_start");
+    TM_LAUNCH(k_ph_start, dim3(1), dim3(1), 0, st, cs, d, co);
 }
 void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, int j, int nsteps,
                  hipStream_t st) {
-    hipLaunchKernelGGL(k_ph_step, dim3(1), dim3(1), 0, st, cs, d, zu, co, j, nsteps);
-    check_launch("k_ph_step");
+    TM_LAUNCH(k_ph_step, dim3(1), dim3(1), 0, st, cs, d, zu, co, j, nsteps);
 }
 void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
-    hipLaunchKernelGGL(k_nh_start, dim3(1), dim3(1), 0, st, cs, d, co);
-    check_launch("k_nh_start");
+    TM_LAUNCH(k_nh_start, dim3(1), dim3(1), 0, st, cs, d, co);
 }
 void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, int j, hipStream_t st) {
-    hipLaunchKernelGGL(k_nh_alpha, dim3(1), dim3(1), 0, st, cs, d, co, j);
-    check_launch("k_nh_alpha");
+    TM_LAUNCH(k_nh_alpha, dim3(1), dim3(1), 0, st, cs, d, co, j);
 }
 void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, int j, int nsteps, hipStream_t st) {
-    hipLaunchKernelGGL(k_nh_step, dim3(1), dim3(1), 0, st, cs, d, co, j, nsteps);
-    check_launch("k_nh_step");
+    TM_LAUNCH(k_nh_step, dim3(1), dim3(1), 0, st, cs, d, co, j, nsteps);
 }
 
 }  // namespace tml

@@ -32,6 +32,21 @@ struct Error {
     } while (0)
 void check_launch(const char* what);
 
+// Kernel timing with HIP events (enabled by tm_profile_enable); a scope
+// records an event before and after the launches it encloses.
+struct ProfScope {
+    ProfScope(const char* name, hipStream_t st);
+    ~ProfScope();
+    int slot;
+    hipStream_t st;
+};
+#define TM_LAUNCH(kern, grid, block, shm, st, ...)                          \
+    do {                                                                    \
+        ::tml::ProfScope ps_(#kern, (st));                                  \
+        hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);       \
+        ::tml::check_launch(#kern);                                         \
+    } while (0)
+
 // ---------------------------------------------------------------- complex
 __host__ __device__ inline double2 cmk(double r, double i) { return make_double2(r, i); }
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }

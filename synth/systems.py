@@ -30,7 +30,7 @@ __all__ = [
     "Atom", "SystemDef", "recip", "volume", "sphere", "grid_points",
     "vloc_grid", "projector_table", "dmatrix", "make_cfg1", "make_tiny",
     "make_cfg2", "kmesh_cart", "QSetDef", "qset_exact", "qset_folded",
-    "random_br", "synthetic_ground_state", "synthetic_fields",
+    "random_br", "synthetic_ground_state", "synthetic_fields", "synthetic_inputs",
     "cart_from_frac",
 ]
 
@@ -306,15 +306,20 @@ class QSetDef:
     shifts: np.ndarray
 
 
-def qset_exact(sysd: SystemDef, qcart) -> QSetDef:
-    """Every role vector kept as its own point (no folding)."""
+def qset_exact(sysd: SystemDef, qcart, bitwise: bool = False) -> QSetDef:
+    """Every role vector kept as its own point (no folding).
+
+    With bitwise=True two role vectors share a point only if they are equal
+    bit for bit, so -k-q is always the exact negation of k+q and the two
+    spheres are exact negatives of each other.
+    """
     q = np.asarray(qcart, dtype=float)
     km = kmesh_cart(sysd)
     pts: list = []
 
     def idx(v):
         for i, p in enumerate(pts):
-            if np.allclose(p, v, atol=1e-12):
+            if (np.array_equal(p, v) if bitwise else np.allclose(p, v, atol=1e-12)):
                 return i
         pts.append(np.array(v, dtype=float))
         return len(pts) - 1
@@ -380,6 +385,36 @@ def synthetic_ground_state(sysd: SystemDef, kcart, mill, seed: int, sigma2: floa
     vmin = -max(at.depth for at in sysd.atoms)
     et = np.sort(vmin - 1.5 + 0.5 * rng.random(nb))
     return evc, et
+
+
+def synthetic_inputs(sysd: SystemDef, qcart, seed: int = 0, kmesh_subset=None):
+    """Everything a Liouvillian needs for a benchmark-shaped system, without an SCF.
+
+    Returns dict(qset, points=[(xk, mill, evc, et, vkb)], vrs, rho, dvan):
+    spheres per distinct role vector, smooth random orthonormal occupied
+    spinors (``synthetic_ground_state``), Gaussian projector tables, the
+    time-reversal-invariant D matrix and smooth fields.  kmesh_subset keeps
+    only those mesh points (used for bounded CPU samples).
+    """
+    if kmesh_subset is not None:
+        sysd = SystemDef(name=sysd.name, cell=sysd.cell, atoms=sysd.atoms, ecut=sysd.ecut, fft=sysd.fft,
+                         nbnd=sysd.nbnd, kmesh=np.asarray(sysd.kmesh)[list(kmesh_subset)], seed=sysd.seed,
+                         notes=sysd.notes)
+    qs = qset_exact(sysd, qcart, bitwise=True)
+    points = []
+    cache = {}
+    for i, p in enumerate(qs.points):
+        neg = tuple((-p).tolist())
+        if neg in cache:  # the negated point: negate its sphere exactly
+            mill = -cache[neg]
+        else:
+            mill = sphere(sysd, p)
+        cache[tuple(p.tolist())] = mill
+        evc, et = synthetic_ground_state(sysd, p, mill, seed=seed * 100003 + i)
+        vkb = projector_table(sysd, p, mill)
+        points.append((p, mill, evc, et, vkb))
+    vrs, rho = synthetic_fields(sysd, seed)
+    return dict(sysd=sysd, qset=qs, points=points, vrs=vrs, rho=rho, dvan=dmatrix(sysd))
 
 
 def synthetic_fields(sysd: SystemDef, seed: int, bmag: float = 0.1):
