@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libtm.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["fft.hip", "apply.hip", "gemm.hip", "lanczos.hip", "chi.hip", "api.hip"]
+SOURCES = ["fft.hip", "apply.hip", "plane.hip", "gemm.hip", "lanczos.hip", "chi.hip", "api.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Wno-unused-result",
          # packed-FP32 instructions are disabled for every HIP translation unit

@@ -6,6 +6,7 @@
 #include <unordered_map>
 
 #include "lanczos_dev.h"
+#include "plane.h"
 
 namespace tml {
 
@@ -203,21 +204,33 @@ void build_sphere_map(System& s, SphereMap& m, const std::vector<int>& mill3, in
         ents[c].push_back(g);
     }
     m.ncol = (int)colpos.size();
-    std::vector<int> ptr(m.ncol + 1, 0), eg, ei;
+    // columns in plane order (row-major in (i1, i2)) so each plane row is one contiguous run
+    std::vector<int> order(m.ncol);
+    for (int c = 0; c < m.ncol; ++c) order[c] = c;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return colpos[x] < colpos[y]; });
+    std::vector<int> ptr(m.ncol + 1, 0), eg, ei, cpos(m.ncol), rows;
     eg.reserve(npw);
     ei.reserve(npw);
+    m.rmask = 0;
     for (int c = 0; c < m.ncol; ++c) {
-        ptr[c + 1] = ptr[c] + (int)ents[c].size();
-        for (int g : ents[c]) {
+        const int oc = order[c];
+        cpos[c] = colpos[oc];
+        ptr[c + 1] = ptr[c] + (int)ents[oc].size();
+        for (int g : ents[oc]) {
             eg.push_back(g);
             ei.push_back(((mill3[3 * g + 2] % s.n3) + s.n3) % s.n3);
         }
+        const int i1 = cpos[c] / s.n2;
+        if (rows.empty() || rows.back() != i1) rows.push_back(i1);
+        if (i1 < 64) m.rmask |= 1ULL << i1;
     }
     m.col_ptr = dev_upload(s, ptr.data(), ptr.size());
     m.ent_g = dev_upload(s, eg.data(), eg.size());
     m.ent_i3 = dev_upload(s, ei.data(), ei.size());
-    m.col_pos = dev_upload(s, colpos.data(), colpos.size());
-    m.h_col_pos = colpos;
+    m.col_pos = dev_upload(s, cpos.data(), cpos.size());
+    m.h_col_pos = cpos;
+    m.nrows = (int)rows.size();
+    m.rows = dev_upload(s, rows.data(), rows.size());
 }
 
 std::vector<int> shifted(const std::vector<int>& mill, int npw, const int* g) {
@@ -267,6 +280,9 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
     std::vector<double*> t_kin(2 * nk), t_eps(2 * nk);
     std::vector<double2*> t_occ(2 * nk), t_vkb(2 * nk);
     std::vector<int*> t_maps(2 * nk);
+    std::vector<int*> t_rows_kq(2 * nk), t_rows_u(2 * nk);
+    std::vector<int> t_nrows_kq(2 * nk), t_nrows_u(2 * nk);
+    std::vector<unsigned long long> t_rmask_kq(2 * nk), t_rmask_u(2 * nk);
     for (int ik = 0; ik < nk; ++ik) {
         KBlock& kb = q.kb[ik];
         const int* r = d->roles + ((size_t)iq * nk + ik) * 4;
@@ -358,8 +374,20 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
             t_occ[b] = kb.occ[side];
             t_vkb[b] = kb.vkb;
             t_maps[b] = side == 0 ? kb.map_k : kb.map_mk;
+            t_rows_kq[b] = kb.sph_kq.rows;
+            t_nrows_kq[b] = kb.sph_kq.nrows;
+            t_rmask_kq[b] = kb.sph_kq.rmask;
+            t_rows_u[b] = kb.sph_u[side].rows;
+            t_nrows_u[b] = kb.sph_u[side].nrows;
+            t_rmask_u[b] = kb.sph_u[side].rmask;
         }
     }
+    q.d_rows_kq = upload_table(s, t_rows_kq);
+    q.d_rows_u = upload_table(s, t_rows_u);
+    q.d_nrows_kq = dev_upload(s, t_nrows_kq.data(), t_nrows_kq.size());
+    q.d_nrows_u = dev_upload(s, t_nrows_u.data(), t_nrows_u.size());
+    q.d_rmask_kq = dev_upload(s, t_rmask_kq.data(), t_rmask_kq.size());
+    q.d_rmask_u = dev_upload(s, t_rmask_u.data(), t_rmask_u.size());
     q.d_colptr_kq = upload_table(s, t_colptr_kq);
     q.d_entg_kq = upload_table(s, t_entg_kq);
     q.d_enti3_kq = upload_table(s, t_enti3_kq);
@@ -694,6 +722,8 @@ int tm_system_create(const tm_system_desc* d, tm_system** out) {
             }
             s.tw[i] = dev_upload(s, tw.data(), tw.size());
             s.plan[i].tw = s.tw[i];
+            std::vector<int> pr = digit_reversal(ns[i]);
+            s.perm[i] = dev_upload(s, pr.data(), pr.size());
         }
         TM_CHECK(s.n1 * s.n2 <= 4 * 1024, TM_EUNSUPPORTED, "n1*n2 above 4096 is not supported by the plane kernels");
         // ground-state points

@@ -19,28 +19,13 @@
 // (sg = -1 on the Y side: H+ and V'+ flip the magnetic parts, Sec. 2.2), and
 // transform phi forward back to the columns of the k+q sphere.
 #include "fft_lds.h"
+#include "plane.h"
 
 namespace tml {
 
 namespace {
 
 constexpr int kPts = 4;  // grid points per thread in the plane kernels
-
-struct PlaneArgs {
-    int n1, n2, n3, NP;
-    int nk, nb, nitems, bpc, nchunk;
-    double2* xcols;
-    int ncol_max;
-    const double2* ucols;
-    int ncol_u_max;
-    const int* const* colpos_kq;
-    const int* ncol_kq;
-    const int* const* colpos_u;
-    const int* ncol_u;
-    double2* rho_part;
-    const double* vrs;
-    const double2* W;
-};
 
 // scatter one column set into the zeroed plane and inverse-transform it
 __device__ inline void plane_inverse(double2* plane, const double2* cols, const int* colpos, int ncol,
@@ -334,12 +319,31 @@ int plane_threads_for(int n1, int n2) {
     return t < 64 ? 64 : t;
 }
 
+static PlaneTabs plane_tabs(const System& s, const QSet& q) {
+    PlaneTabs t;
+    t.nrows_kq = q.d_nrows_kq;
+    t.nrows_u = q.d_nrows_u;
+    t.rmask_kq = q.d_rmask_kq;
+    t.rmask_u = q.d_rmask_u;
+    t.rows_kq = q.d_rows_kq;
+    t.rows_u = q.d_rows_u;
+    t.tw1 = s.plan[0].tw;
+    t.tw2 = s.plan[1].tw;
+    t.perm1 = s.perm[0];
+    t.perm2 = s.perm[1];
+    return t;
+}
+
 void launch_density(const System& s, const QSet& q, hipStream_t st) {
     PlaneArgs a = plane_args(s, q);
-    int th = plane_threads(s);
     dim3 grid(s.n3, a.nchunk, 2 * q.nk);
-    size_t shm = (size_t)a.NP * sizeof(double2);
-    TM_LAUNCH(k_density, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
+    if (plane_fixed_supported(s.n1, s.n2)) {
+        launch_plane_fixed(true, a, plane_tabs(s, q), grid, s.n1, s.n2, st);
+    } else {
+        int th = plane_threads(s);
+        size_t shm = (size_t)a.NP * sizeof(double2);
+        TM_LAUNCH(k_density, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
+    }
     long long n4 = 4 * s.N;
     TM_LAUNCH(k_density_reduce, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, s.ws.rho_part,
                        s.ws.rho, s.N, q.nk, a.nchunk, 1.0 / (s.omega * q.nk));
@@ -357,8 +361,12 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st) {
 
 void launch_apply_planes(const System& s, const QSet& q, hipStream_t st) {
     PlaneArgs a = plane_args(s, q);
-    int th = plane_threads(s);
     dim3 grid(s.n3, a.nchunk, 2 * q.nk);
+    if (plane_fixed_supported(s.n1, s.n2)) {
+        launch_plane_fixed(false, a, plane_tabs(s, q), grid, s.n1, s.n2, st);
+        return;
+    }
+    int th = plane_threads(s);
     size_t shm = (size_t)a.NP * sizeof(double2);
     TM_LAUNCH(k_apply_planes, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
 }

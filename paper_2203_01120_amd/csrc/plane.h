@@ -1,0 +1,46 @@
+// Arguments of the plane kernels (generic ones in apply.hip, fixed-size ones in plane.hip).
+#pragma once
+
+#include "tm_internal.h"
+
+namespace tml {
+
+struct PlaneArgs {
+    int n1, n2, n3, NP;
+    int nk, nb, nitems, bpc, nchunk;
+    double2* xcols;
+    int ncol_max;
+    const double2* ucols;
+    int ncol_u_max;
+    const int* const* colpos_kq;
+    const int* ncol_kq;
+    const int* const* colpos_u;
+    const int* ncol_u;
+    double2* rho_part;
+    const double* vrs;
+    const double2* W;
+};
+
+// rows of the (i1, i2) plane occupied by each sphere, per batch b
+struct PlaneTabs {
+    const int* nrows_kq;
+    const int* nrows_u;
+    const unsigned long long* rmask_kq;
+    const unsigned long long* rmask_u;
+    const int* const* rows_kq;
+    const int* const* rows_u;
+    const double2* tw1;  // exp(-2 pi i j / n1)
+    const double2* tw2;  // exp(-2 pi i j / n2)
+    const int* perm1;    // mixed-radix digit reversal of the in-place transforms along i1
+    const int* perm2;    // and along i2
+};
+
+// position p of an in-place decimation-in-frequency transform of length n holds
+// output index perm[p] (radices 4, 5, 3, 2 in that order)
+std::vector<int> digit_reversal(int n);
+
+bool plane_fixed_supported(int n1, int n2);
+void launch_plane_fixed(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
+                        hipStream_t st);
+
+}  // namespace tml

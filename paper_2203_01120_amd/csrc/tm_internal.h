@@ -82,8 +82,11 @@ struct SphereMap {
     int* col_ptr = nullptr;   // [ncol+1] CSR over entries sorted by column
     int* ent_g = nullptr;     // [npw] sphere index of each entry
     int* ent_i3 = nullptr;    // [npw] grid i3 of each entry
-    int* col_pos = nullptr;   // [ncol] plane position i1*n2 + i2 of each column
+    int* col_pos = nullptr;   // [ncol] plane position i1*n2 + i2 of each column (sorted)
     std::vector<int> h_col_pos;
+    int nrows = 0;            // plane rows i1 holding at least one column
+    int* rows = nullptr;      // [nrows] their i1
+    unsigned long long rmask = 0;  // bit i1 set for every such row (n1 <= 64)
 };
 
 // Per q-set, per mesh point k: everything the apply needs.
@@ -130,6 +133,12 @@ struct QSet {
     double2** d_occ = nullptr;
     double2** d_vkb = nullptr;
     int** d_maps = nullptr;       // restriction maps for the start vectors (map_k, map_mk)
+    int* d_nrows_kq = nullptr;    // occupied plane rows of each batch's spheres
+    int* d_nrows_u = nullptr;
+    unsigned long long* d_rmask_kq = nullptr;
+    unsigned long long* d_rmask_u = nullptr;
+    int** d_rows_kq = nullptr;
+    int** d_rows_u = nullptr;
     // lazily built caches
     double2* ucols = nullptr;     // z-transformed ground-state columns [b][nb*2][n3][ncol_u_max]
     bool ucols_ready = false;
@@ -162,6 +171,7 @@ struct System {
     int nproj;
     FFTPlan plan[3];
     double2* tw[3] = {nullptr, nullptr, nullptr};
+    int* perm[3] = {nullptr, nullptr, nullptr};  // digit reversal of the in-place plane transforms
     // ground-state points (device)
     std::vector<double2*> evc;    // [npts] [nb][2][npw]
     std::vector<int> npw;

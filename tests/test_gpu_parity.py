@@ -78,6 +78,44 @@ def test_apply_matches_oracle(which, request):
             assert np.all(raw[:, ik, :, :, n:] == 0)
 
 
+def test_apply_generic_plane_path(lib):
+    """A 10^3 grid has no fixed-size plane kernel: the generic kernels run."""
+    import synth
+    from oracle import scf
+    say("apply tiny 10^3 (generic plane kernels)")
+    gs = scf.scf(synth.make_tiny(fft=(10, 10, 10), seed=3), tol=1e-12, beta=0.5)
+    s = Sys(lib, lv.build_problem(gs, np.array([0.05, 0.1, 0.0]) * 2 * np.pi / 6.0))
+    try:
+        x = s.prob.random_projected(9)
+        got, _ = s.apply(x)
+        assert rel_err(got, s.prob.apply(x)) <= 1e-12
+    finally:
+        s.close()
+
+
+def test_apply_two_kpoints_folded(lib):
+    """Two-point mesh, q on the mesh: sister points folded with Miller shifts."""
+    import synth
+    from oracle import scf
+    say("apply tiny 2-k mesh, folded roles")
+    sd = synth.make_tiny(kmesh=((0.0, 0.0, 0.0), (0.5, 0.0, 0.0)), nbnd=3, seed=11)
+    gs = scf.scf(sd, tol=1e-12, beta=0.5)
+    qs = synth.qset_folded(sd, (0.5, 0.0, 0.0))
+    assert np.any(qs.shifts != 0)
+    prob = lv.Problem(gs, qs)
+    s = Sys(lib, prob)
+    try:
+        for seed in (1, 2):
+            x = prob.random_projected(seed)
+            got, _ = s.apply(x)
+            assert rel_err(got, prob.apply(x)) <= 1e-12
+        got = lib.tm_lanczos_run(s.h, 0, "z", "nH", 8)
+        ref = olanczos.run(prob, "z", "nH", 8)
+        assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
+    finally:
+        s.close()
+
+
 def test_apply_is_linear_and_orthogonal(cfg1):
     say("apply linearity cfg1")
     a = cfg1.prob.random_projected(3)
