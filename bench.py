@@ -77,11 +77,15 @@ def kernel_models(inp, info):
     bands = 2 * nk * nb
     npw_avg = np.mean([m.shape[0] for (_, m, _, _, _) in inp["points"]])
     vec_bytes = 2 * nk * nb * 2 * npw_avg * 16
+    apply_flops = bands * n3 * (6 * fft2d + 60.0 * NP)
+    dens_flops = bands * n3 * (4 * fft2d + 40.0 * NP)
     return {
         # 4 inverse + 2 forward plane FFTs per band and plane, ~60 flops/point for V0 x + V' u
-        "k_apply_planes": dict(flops=bands * n3 * (6 * fft2d + 60.0 * NP), bound="alu"),
+        "k_apply_planes": dict(flops=apply_flops, bound="alu"),
+        "k_apply_t": dict(flops=apply_flops, bound="alu"),
         # 4 inverse plane FFTs per band and plane, ~40 flops/point for the 4 densities
-        "k_density": dict(flops=bands * n3 * (4 * fft2d + 40.0 * NP), bound="alu"),
+        "k_density": dict(flops=dens_flops, bound="alu"),
+        "k_density_t": dict(flops=dens_flops, bound="alu"),
         # projector GEMMs: S = O^H phi and phi -= O S (8 real flops per complex MAC)
         "k_gemm_cn": dict(flops=8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P), bound="mfma"),
         "k_gemm_update": dict(flops=8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P), bound="mfma"),
@@ -176,7 +180,11 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     tm.tm_profile_enable(False)
-    prof = tm.tm_profile_read()
+    prof = {}
+    for k, (ms, cnt) in tm.tm_profile_read().items():
+        name = k.strip("()").split("<")[0]
+        old = prof.get(name, (0.0, 0))
+        prof[name] = (old[0] + ms, old[1] + cnt)
     applies = args.steps + 1
     applies_per_s = applies / dt
     log(f"{args.steps} steps in {dt:.3f} s -> {applies_per_s:.3f} applies/s; breakdown={res['breakdown']}")
@@ -194,7 +202,7 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1))
-    lat = np.array(lat)
+    lat = np.array(lat) if lat else np.array([dt / applies * 1e3])
 
     models = kernel_models(inp, info)
     total_ms = sum(v[0] for v in prof.values())

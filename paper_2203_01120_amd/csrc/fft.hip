@@ -7,6 +7,7 @@
 // buffers are laid out [batch][item][i3][column] so a plane kernel reads all
 // columns of one plane contiguously.
 #include "fft_lds.h"
+#include "plane.h"
 
 namespace tml {
 
@@ -219,11 +220,30 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
     }
     a.cols = cols;
     const int n3 = s.n3;
+    int ncolmax = ucols ? q.ncol_u_max : q.ncol_max;
+    if (zpass_fixed_supported(n3)) {
+        ZPassArgs z{};
+        z.coef_table = a.coef_table;
+        z.coef_base = a.coef_base;
+        z.coef_bstride = a.coef_bstride;
+        z.istride = a.coef_item_stride;
+        z.istride_tab = a.coef_item_stride_tab;
+        z.colptr = a.colptr;
+        z.entg = a.entg;
+        z.enti3 = a.enti3;
+        z.ncol = a.ncol;
+        z.cols = cols;
+        z.ncol_stride = a.ncol_stride;
+        z.nitems = nitems;
+        z.tw = s.plan[2].tw;
+        z.perm = s.perm[2];
+        launch_zpass_fixed(true, z, ncolmax, nb2, n3, st);
+        return;
+    }
     int L = lines_for(n3, 64, kZThreads);
     a.ct = L >= 16 ? 16 : L;
     a.lines_per_block = L;
     int it = L / a.ct;
-    int ncolmax = ucols ? q.ncol_u_max : q.ncol_max;
     dim3 grid((ncolmax + a.ct - 1) / a.ct, (nitems + it - 1) / it, nb2);
     size_t shm = (size_t)L * n3 * sizeof(double2);
     TM_LAUNCH(k_zpass_inv, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
@@ -246,6 +266,27 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
     a.npw_pad = q.npw_pad;
     a.nitems = 2 * s.nbnd;
     const int n3 = s.n3;
+    if (zpass_fixed_supported(n3)) {
+        ZPassArgs z{};
+        z.colptr = a.colptr;
+        z.entg = a.entg;
+        z.enti3 = a.enti3;
+        z.ncol = a.ncol;
+        z.cols = const_cast<double2*>(cols);
+        z.ncol_stride = q.ncol_max;
+        z.nitems = a.nitems;
+        z.tw = s.plan[2].tw;
+        z.perm = s.perm[2];
+        z.npw = a.npw;
+        z.kin = a.kin;
+        z.eps = a.eps;
+        z.xin = xin;
+        z.out = out;
+        z.npw_pad = q.npw_pad;
+        z.inv_n = 1.0 / (double)s.N;
+        launch_zpass_fixed(false, z, q.ncol_max, 2 * q.nk, n3, st);
+        return;
+    }
     int L = lines_for(n3, 64, kZThreads);
     a.ct = L >= 16 ? 16 : L;
     a.lines_per_block = L;

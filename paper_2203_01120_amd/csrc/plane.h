@@ -39,6 +39,35 @@ struct PlaneTabs {
 // output index perm[p] (radices 4, 5, 3, 2 in that order)
 std::vector<int> digit_reversal(int n);
 
+// arguments of the fixed-size z passes (sphere <-> columns along i3)
+struct ZPassArgs {
+    const double2* const* coef_table;  // inverse: per-batch coefficient base, or null
+    const double2* coef_base;          //          else coef_base + b * coef_bstride
+    long long coef_bstride;
+    long long istride;                 // complex elements between items
+    const int* istride_tab;            // per-batch item stride (overrides when non-null)
+    const int* const* colptr;
+    const int* const* entg;
+    const int* const* enti3;
+    const int* ncol;
+    double2* cols;                     // [b][item][n3][ncol_stride]
+    int ncol_stride;
+    int nitems;
+    const double2* tw;                 // exp(-2 pi i j / n3)
+    const int* perm;                   // digit reversal along i3
+    // forward only
+    const int* npw;
+    const double* const* kin;
+    const double* const* eps;
+    const double2* xin;
+    double2* out;
+    int npw_pad;
+    double inv_n;
+};
+
+bool zpass_fixed_supported(int n3);
+void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st);
+
 bool plane_fixed_supported(int n1, int n2);
 void launch_plane_fixed(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
                         hipStream_t st);

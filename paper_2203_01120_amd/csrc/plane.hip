@@ -413,6 +413,153 @@ void launch_t(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, h
 
 }  // namespace
 
+// ---------------------------------------------------------------- z passes
+// Sphere <-> column transforms along i3 with a compile-time length.  Lines of
+// L = CT x IT (column, item) pairs sit in LDS with a padded stride; the
+// in-place stages leave the inverse output digit-reversed, so the write-out
+// puts LDS position p at grid index perm3[p], and the forward load does the
+// converse before the DIT stages restore natural order.
+namespace {
+
+template <int LS>
+struct ZLines {
+    static constexpr int ES = 1;
+    __device__ int base(int l) const { return l * LS; }
+    __device__ bool valid(int, int) const { return true; }
+};
+
+template <int N3, int NT, int CT, int IT>
+__global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
+    constexpr int L = CT * IT;
+    constexpr int LS = N3 + 1;
+    extern __shared__ double2 lds[];
+    double2* tw = lds + L * LS;
+    int* perm = reinterpret_cast<int*>(tw + N3);
+    const int b = blockIdx.z;
+    const int ncol = a.ncol[b];
+    const int col0 = blockIdx.x * CT;
+    if (col0 >= ncol) return;
+    const int item0 = blockIdx.y * IT;
+    for (int i = threadIdx.x; i < N3; i += NT) {
+        tw[i] = a.tw[i];
+        perm[i] = a.perm[i];
+    }
+    for (int i = threadIdx.x; i < L * LS; i += NT) lds[i] = cmk(0.0, 0.0);
+    __syncthreads();
+    const int* cp = a.colptr[b];
+    const int* eg = a.entg[b];
+    const int* ei = a.enti3[b];
+    const double2* coef = a.coef_table ? a.coef_table[b] : a.coef_base + (long long)b * a.coef_bstride;
+    const long long istr = a.istride_tab ? a.istride_tab[b] : a.istride;
+    constexpr int PER = NT / L > 0 ? NT / L : 1;
+    for (int l = threadIdx.x / PER; l < L; l += NT / PER) {
+        const int c = col0 + l % CT, item = item0 + l / CT;
+        if (c < ncol && item < a.nitems) {
+            const double2* src = coef + (long long)item * istr;
+            for (int e = cp[c] + threadIdx.x % PER; e < cp[c + 1]; e += PER) lds[l * LS + ei[e]] = src[eg[e]];
+        }
+    }
+    __syncthreads();
+    fft_dif<N3, +1, NT, false>(lds, L, ZLines<LS>{}, tw);
+    double2* out = a.cols + (long long)b * a.nitems * N3 * a.ncol_stride;
+    for (int i = threadIdx.x; i < L * N3; i += NT) {
+        const int cl = i % CT, rest = i / CT;
+        const int p = rest % N3, il = rest / N3;
+        const int c = col0 + cl, item = item0 + il;
+        if (c < ncol && item < a.nitems)
+            out[((long long)item * N3 + perm[p]) * a.ncol_stride + c] = lds[(il * CT + cl) * LS + p];
+    }
+}
+
+template <int N3, int NT, int CT, int IT>
+__global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
+    constexpr int L = CT * IT;
+    constexpr int LS = N3 + 1;
+    extern __shared__ double2 lds[];
+    double2* tw = lds + L * LS;
+    int* perm = reinterpret_cast<int*>(tw + N3);
+    const int b = blockIdx.z;
+    const int ncol = a.ncol[b];
+    const int col0 = blockIdx.x * CT;
+    const int item0 = blockIdx.y * IT;
+    const long long bbase = (long long)b * a.nitems * a.npw_pad;
+    if (blockIdx.x == 0) {  // the first column tile clears the padding of its items
+        const int npw = a.npw[b], padn = a.npw_pad - npw;
+        for (int i = threadIdx.x; i < IT * padn; i += NT) {
+            const int item = item0 + i / padn;
+            if (item < a.nitems) a.out[bbase + (long long)item * a.npw_pad + npw + i % padn] = cmk(0.0, 0.0);
+        }
+    }
+    if (col0 >= ncol) return;
+    for (int i = threadIdx.x; i < N3; i += NT) {
+        tw[i] = a.tw[i];
+        perm[i] = a.perm[i];
+    }
+    __syncthreads();
+    const double2* cin = a.cols + (long long)b * a.nitems * N3 * a.ncol_stride;
+    for (int i = threadIdx.x; i < L * N3; i += NT) {
+        const int cl = i % CT, rest = i / CT;
+        const int p = rest % N3, il = rest / N3;
+        const int c = col0 + cl, item = item0 + il;
+        double2 v = cmk(0.0, 0.0);
+        if (c < ncol && item < a.nitems) v = cin[((long long)item * N3 + perm[p]) * a.ncol_stride + c];
+        lds[(il * CT + cl) * LS + p] = v;
+    }
+    __syncthreads();
+    fft_dit_all<N3, -1, NT>(lds, L, ZLines<LS>{}, tw);
+    const int* cp = a.colptr[b];
+    const int* eg = a.entg[b];
+    const int* ei = a.enti3[b];
+    const double* kin = a.kin[b];
+    const double* eps = a.eps[b];
+    constexpr int PER = NT / L > 0 ? NT / L : 1;
+    for (int l = threadIdx.x / PER; l < L; l += NT / PER) {
+        const int c = col0 + l % CT, item = item0 + l / CT;
+        if (c < ncol && item < a.nitems) {
+            const double e = eps[item >> 1];
+            const long long off = bbase + (long long)item * a.npw_pad;
+            for (int en = cp[c] + threadIdx.x % PER; en < cp[c + 1]; en += PER) {
+                const int g = eg[en];
+                const double2 f = cscale(lds[l * LS + ei[en]], a.inv_n);
+                const double2 x = a.xin[off + g];
+                const double s = kin[g] - e;
+                a.out[off + g] = cmk(f.x + s * x.x, f.y + s * x.y);
+            }
+        }
+    }
+}
+
+template <int N3, int NT, int CT, int IT>
+void launch_z(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStream_t st) {
+    constexpr int L = CT * IT;
+    const size_t shm = (size_t)L * (N3 + 1) * sizeof(double2) + N3 * sizeof(double2) + N3 * sizeof(int);
+    dim3 grid((ncolmax + CT - 1) / CT, (a.nitems + IT - 1) / IT, nbatch);
+    if (inverse) {
+        TM_LAUNCH((k_zinv_t<N3, NT, CT, IT>), grid, dim3(NT), shm, st, a);
+    } else {
+        TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT>), grid, dim3(NT), shm, st, a);
+    }
+}
+
+}  // namespace
+
+bool zpass_fixed_supported(int n3) {
+    return n3 == 8 || n3 == 20 || n3 == 24 || n3 == 32 || n3 == 48 || n3 == 96 || n3 == 180;
+}
+
+void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st) {
+    switch (n3) {
+        case 8: launch_z<8, 256, 16, 4>(inverse, a, ncolmax, nbatch, st); break;
+        case 20: launch_z<20, 256, 16, 4>(inverse, a, ncolmax, nbatch, st); break;
+        case 24: launch_z<24, 256, 16, 4>(inverse, a, ncolmax, nbatch, st); break;
+        case 32: launch_z<32, 256, 16, 2>(inverse, a, ncolmax, nbatch, st); break;
+        case 48: launch_z<48, 256, 16, 2>(inverse, a, ncolmax, nbatch, st); break;
+        case 96: launch_z<96, 256, 16, 1>(inverse, a, ncolmax, nbatch, st); break;
+        case 180: launch_z<180, 256, 16, 1>(inverse, a, ncolmax, nbatch, st); break;
+        default: throw Error{TM_EUNSUPPORTED, "no fixed-size z pass for this grid"};
+    }
+}
+
 std::vector<int> digit_reversal(int n) {
     FFTPlan p;
     std::vector<int> perm(n, 0);
