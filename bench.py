@@ -64,8 +64,17 @@ def make_desc(inp):
                          shifts=qs.shifts[None])
 
 
-def kernel_models(inp, info):
-    """Algorithmic work per launch of the main kernels (flops, bytes)."""
+def kernel_models(inp, info, resident: bool):
+    """Algorithmic work per launch of the main kernels: flops and HBM bytes.
+
+    Plane kernels, per band, spin pair and plane i3: a 2D FFT of n1 x n2
+    points costs 5 NP log2 NP flops.  With the resident real-space ground
+    state the apply transforms x (2 inverse) and its product (2 forward) and
+    reads u from HBM; the density transforms x (2 inverse) and reads u.  On the
+    column path the kernels also finish the inverse transforms of u (2 more).
+    Bytes: x columns in (and out for the apply), u planes or u columns in, the
+    fields once per block (apply), the 4 density partial planes once per block.
+    """
     sysd = inp["sysd"]
     n1, n2, n3 = sysd.fft
     NP = n1 * n2
@@ -75,20 +84,26 @@ def kernel_models(inp, info):
     nproj = sysd.nproj
     fft2d = 5.0 * NP * math.log2(NP)
     bands = 2 * nk * nb
-    npw_avg = np.mean([m.shape[0] for (_, m, _, _, _) in inp["points"]])
+    mills = [m for (_, m, _, _, _) in inp["points"]]
+    npw_avg = np.mean([m.shape[0] for m in mills])
+    ncol_avg = np.mean([len({(int(a), int(b)) for a, b, _ in m}) for m in mills])
     vec_bytes = 2 * nk * nb * 2 * npw_avg * 16
-    apply_flops = bands * n3 * (6 * fft2d + 60.0 * NP)
-    dens_flops = bands * n3 * (4 * fft2d + 40.0 * NP)
+    u_bytes = 2 * NP * 16 if resident else 2 * ncol_avg * 16
+    n_inv = 2 if resident else 4
+    blocks = 2 * nk * n3
+    apply_flops = bands * n3 * ((n_inv + 2) * fft2d + 60.0 * NP)
+    apply_bytes = bands * n3 * (4 * ncol_avg * 16 + u_bytes) + blocks * NP * 96
+    dens_flops = bands * n3 * (n_inv * fft2d + 40.0 * NP)
+    dens_bytes = bands * n3 * (2 * ncol_avg * 16 + u_bytes) + blocks * 4 * NP * 16
+    gemm_flops = 8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P)
     return {
-        # 4 inverse + 2 forward plane FFTs per band and plane, ~60 flops/point for V0 x + V' u
-        "k_apply_planes": dict(flops=apply_flops, bound="alu"),
-        "k_apply_t": dict(flops=apply_flops, bound="alu"),
-        # 4 inverse plane FFTs per band and plane, ~40 flops/point for the 4 densities
-        "k_density": dict(flops=dens_flops, bound="alu"),
-        "k_density_t": dict(flops=dens_flops, bound="alu"),
+        "k_apply_planes": dict(flops=apply_flops, bytes=apply_bytes),
+        "k_apply_t": dict(flops=apply_flops, bytes=apply_bytes),
+        "k_density": dict(flops=dens_flops, bytes=dens_bytes),
+        "k_density_t": dict(flops=dens_flops, bytes=dens_bytes),
         # projector GEMMs: S = O^H phi and phi -= O S (8 real flops per complex MAC)
-        "k_gemm_cn": dict(flops=8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P), bound="mfma"),
-        "k_gemm_update": dict(flops=8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P), bound="mfma"),
+        "k_gemm_cn": dict(flops=gemm_flops, bytes=vec_bytes, mfma=True),
+        "k_gemm_update": dict(flops=gemm_flops, bytes=2 * vec_bytes, mfma=True),
         "vector": dict(bytes=vec_bytes),
     }
 
@@ -159,6 +174,8 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=20)
+    ap.add_argument("--no-resident", action="store_true",
+                    help="keep the ground state as z-transformed columns instead of resident real-space planes")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
@@ -188,9 +205,13 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    if args.no_resident:
+        tm.tm_system_set_resident_limit(h, 0)
     log(f"warmup {args.warmup} steps")
     tm.tm_lanczos_run(h, 0, "+", "pH", max(1, args.warmup))
     torch.cuda.synchronize()
+    resident = tm.tm_system_resident_bytes(h)
+    log(f"resident real-space ground state: {resident / 1e9:.2f} GB")
 
     log(f"timed {args.steps} steps")
     tm.tm_profile_reset()
@@ -225,7 +246,7 @@ def main():
         lat.append(e0.elapsed_time(e1))
     lat = np.array(lat) if lat else np.array([dt / applies * 1e3])
 
-    models = kernel_models(inp, info)
+    models = kernel_models(inp, info, resident > 0)
     total_ms = sum(v[0] for v in prof.values())
     kernels = {k: {"ms_total": round(v[0], 3), "launches": v[1], "ms_avg": round(v[0] / max(v[1], 1), 4),
                    "share": round(v[0] / total_ms, 4)} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
@@ -234,11 +255,21 @@ def main():
     roof = None
     if dom in models and "flops" in models[dom]:
         m = models[dom]
-        ach = m["flops"] / avg_s / 1e12
-        roof = {"kernel": dom, "bound": m["bound"], "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP64_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dom) if args.workload == "cfg2" else None,
-                "avg_ms": round(avg_s * 1e3, 4), "algorithmic_flops_per_launch": m["flops"]}
+        tflops = m["flops"] / avg_s / 1e12
+        gbs = m["bytes"] / avg_s / 1e9
+        f_alu = tflops / FP64_PEAK_TFLOPS
+        f_hbm = gbs / HBM_PEAK_GBS
+        # the bound is whichever ceiling the kernel sits closer to
+        if f_hbm > f_alu:
+            roof = {"kernel": dom, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(f_hbm, 4)}
+        else:
+            roof = {"kernel": dom, "bound": "mfma" if m.get("mfma") else "alu", "achieved": round(tflops, 3),
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(f_alu, 4)}
+        roof.update({"traffic": measured_traffic(dom) if args.workload == "cfg2" else None,
+                     "avg_ms": round(avg_s * 1e3, 4), "algorithmic_flops_per_launch": m["flops"],
+                     "algorithmic_bytes_per_launch": round(m["bytes"]),
+                     "other": {"alu_frac": round(f_alu, 4), "hbm_frac": round(f_hbm, 4)}})
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -273,6 +304,7 @@ def main():
         "spectrum_steps": chain_m,
         "apply_latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                              "p99": round(float(np.percentile(lat, 99)), 3)},
+        "resident_ground_bytes": resident,
         "roofline": roof,
         "kernels": kernels,
         "cpu_baseline": cpu,

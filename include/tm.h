@@ -126,6 +126,26 @@ int tm_system_destroy(tm_system* sys);
 int tm_qset_info_get(const tm_system* sys, int iq, tm_qset_info* info);
 
 /*
+ * Resident ground state (a memory/time trade, not part of the method).  Every
+ * apply of L (Eq. liouvillian_blocks) needs each ground-state band U_k, and
+ * T U_-k on the Y side, in real space.  When the (n1, n2) plane has a
+ * fixed-size kernel and the real-space copy fits in `bytes`, the first apply
+ * transforms each band once and keeps it in device memory (complex FP64,
+ * [distinct (point, G shift, side)][band][i3][spin][n1 n2]); otherwise every
+ * apply repeats the in-plane inverse transforms from the bands' z-transformed
+ * columns.  Both paths give the same result up to rounding order.
+ * bytes < 0 (the default) allows up to 80% of the device memory free at the
+ * first apply; 0 disables the copy.  Setting a limit frees an existing copy and
+ * the next apply decides again.  Must not be called while work of this system
+ * is in flight.  The first apply of a q set after creation or after this call
+ * builds these caches and synchronises its stream.
+ */
+int tm_system_set_resident_limit(tm_system* sys, long long bytes);
+
+/* Bytes of device memory held by the resident real-space ground state (0 if none). */
+int tm_system_resident_bytes(const tm_system* sys, long long* bytes);
+
+/*
  * tm_liouvillian_apply: xy_out = L_q xy_in (Eqs. Liouvillian_BR_q and
  * liouvillian_blocks; one projector P, P+ applied to the sum of the D and K
  * parts, lower row multiplied by -1).

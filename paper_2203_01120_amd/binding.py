@@ -23,7 +23,8 @@ TM_FP64, TM_FP32 = 0, 1
 DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4}
 FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
-EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_liouvillian_apply",
+EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
+            "tm_system_resident_bytes", "tm_liouvillian_apply",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -72,6 +73,8 @@ def load(path: str = LIB_PATH):
     lib.tm_system_create.argtypes = [C.POINTER(_Desc), C.POINTER(C.c_void_p)]
     lib.tm_system_destroy.argtypes = [C.c_void_p]
     lib.tm_qset_info_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(_QInfo)]
+    lib.tm_system_set_resident_limit.argtypes = [C.c_void_p, C.c_longlong]
+    lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.tm_lanczos_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_Coeffs)]
@@ -195,6 +198,17 @@ def tm_qset_info_get(h, iq: int = 0) -> dict:
     info = _QInfo()
     _check(load().tm_qset_info_get(C.c_void_p(h), iq, C.byref(info)))
     return dict(nk=info.nk, nbnd=info.nbnd, npw_pad=info.npw_pad, nelem=info.nelem, lam=info.lam)
+
+
+def tm_system_set_resident_limit(h, nbytes: int) -> None:
+    """Limit (bytes) on the resident real-space ground state; -1 = default, 0 = off."""
+    _check(load().tm_system_set_resident_limit(C.c_void_p(h), int(nbytes)))
+
+
+def tm_system_resident_bytes(h) -> int:
+    out = C.c_longlong(0)
+    _check(load().tm_system_resident_bytes(C.c_void_p(h), C.byref(out)))
+    return int(out.value)
 
 
 def _stream(stream):

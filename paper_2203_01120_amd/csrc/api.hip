@@ -283,6 +283,8 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
     std::vector<int*> t_rows_kq(2 * nk), t_rows_u(2 * nk);
     std::vector<int> t_nrows_kq(2 * nk), t_nrows_u(2 * nk);
     std::vector<unsigned long long> t_rmask_kq(2 * nk), t_rmask_u(2 * nk);
+    std::vector<int> t_uslot(2 * nk);
+    std::vector<short*> t_colidx(2 * nk);
     for (int ik = 0; ik < nk; ++ik) {
         KBlock& kb = q.kb[ik];
         const int* r = d->roles + ((size_t)iq * nk + ik) * 4;
@@ -354,8 +356,13 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
             TM_LAUNCH(k_pad_copy, dim3((P + 127) / 128, s.nproj), dim3(128), 0, st, vk, npw, P, s.nproj,
                                kb.vkb);
         }
+        // plane position -> column of the k+q sphere (wave-local plane kernels)
+        std::vector<short> ci((size_t)s.n1 * s.n2, (short)-1);
+        for (int c = 0; c < kb.sph_kq.ncol; ++c) ci[kb.sph_kq.h_col_pos[c]] = (short)c;
+        short* d_ci = dev_upload(s, ci.data(), ci.size());
         for (int side = 0; side < 2; ++side) {
             int b = side * nk + ik;
+            t_colidx[b] = d_ci;
             t_colptr_kq[b] = kb.sph_kq.col_ptr;
             t_entg_kq[b] = kb.sph_kq.ent_g;
             t_enti3_kq[b] = kb.sph_kq.ent_i3;
@@ -380,8 +387,17 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
             t_rows_u[b] = kb.sph_u[side].rows;
             t_nrows_u[b] = kb.sph_u[side].nrows;
             t_rmask_u[b] = kb.sph_u[side].rmask;
+            // the real-space ground state of a batch depends only on its point,
+            // its G shift and the side (time reversal on the y side)
+            const int* gs = sh ? sh + 3 * side : nullptr;
+            std::array<int, 5> key{side == 0 ? pk : pmk, gs ? gs[0] : 0, gs ? gs[1] : 0, gs ? gs[2] : 0, side};
+            auto it = s.uslot_of.find(key);
+            if (it == s.uslot_of.end()) it = s.uslot_of.emplace(key, (int)s.uslot_of.size()).first;
+            t_uslot[b] = it->second;
         }
     }
+    q.d_uslot = dev_upload(s, t_uslot.data(), t_uslot.size());
+    q.d_colidx_kq = upload_table(s, t_colidx);
     q.d_rows_kq = upload_table(s, t_rows_kq);
     q.d_rows_u = upload_table(s, t_rows_u);
     q.d_nrows_kq = dev_upload(s, t_nrows_kq.data(), t_nrows_kq.size());
@@ -438,6 +454,7 @@ void ensure_workspace(System& s, const QSet& q) {
         TM_HIP(hipMalloc(&w.work, s.N * sizeof(double2)));
         TM_HIP(hipMalloc(&w.dots, 64 * sizeof(double2)));
         TM_HIP(hipMalloc(&w.dotpart, 1024 * 8 * sizeof(double2)));
+        if (plane_fixed_supported(s.n1, s.n2)) TM_HIP(hipMalloc(&w.fields, 6 * s.N * sizeof(double2)));
     }
     size_t need_gp = std::max(gemm_partial_elems(nb2, nb, nb, 2 * q.npw_pad),
                               gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, q.npw_pad));
@@ -454,19 +471,68 @@ void ensure_workspace(System& s, const QSet& q) {
     }
 }
 
-static void ensure_ucols(System& s, QSet& q, hipStream_t st) {
-    if (q.ucols_ready) return;
-    size_t need = (size_t)2 * q.nk * 2 * s.nbnd * s.n3 * q.ncol_u_max;
-    TM_HIP(hipMalloc(&q.ucols, need * sizeof(double2)));
-    s.allocs.push_back(q.ucols);
-    launch_zpass_inv(s, q, true, nullptr, 0, 2 * s.nbnd, 0, q.ucols, st);
-    q.ucols_ready = true;
+// Ground-state planes for the plane kernels.  With fixed-size plane kernels
+// and enough device memory the bands are kept in real space (one inverse
+// transform per band for the lifetime of the system instead of one per
+// apply); otherwise their z-transformed columns are kept and the plane
+// kernels finish the inverse transform on every apply.
+static void ensure_ground(System& s, QSet& q, hipStream_t st) {
+    if (q.ground_ready) return;
+    const size_t NP = (size_t)s.n1 * s.n2;
+    if (s.ureal_mode == 0) {
+        const size_t need = s.uslot_of.size() * (size_t)s.nbnd * s.n3 * 2 * NP * sizeof(double2);
+        size_t limit = 0;
+        if (s.resident_limit < 0) {
+            size_t fr = 0, tot = 0;
+            TM_HIP(hipMemGetInfo(&fr, &tot));
+            // leave room for the column caches built on the way and for chains
+            const size_t ucol = (size_t)2 * q.nk * 2 * s.nbnd * s.n3 * q.ncol_u_max * sizeof(double2);
+            limit = fr > ucol ? (size_t)(0.8 * (double)(fr - ucol)) : 0;
+        } else {
+            limit = (size_t)s.resident_limit;
+        }
+        const bool res = plane_fixed_supported(s.n1, s.n2) && need > 0 && need <= limit;
+        if (res) {
+            void* p = nullptr;
+            if (hipMalloc(&p, need) == hipSuccess) {
+                s.ureal = static_cast<double2*>(p);
+                s.ureal_bytes = need;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        s.ureal_mode = s.ureal ? 1 : 2;
+    }
+    if (!q.ucols) {
+        const size_t need = (size_t)2 * q.nk * 2 * s.nbnd * s.n3 * q.ncol_u_max;
+        TM_HIP(hipMalloc(&q.ucols, need * sizeof(double2)));
+        launch_zpass_inv(s, q, true, nullptr, 0, 2 * s.nbnd, 0, q.ucols, st);
+    }
+    if (s.ureal_mode == 1) {
+        launch_ureal(s, q, st);
+        TM_HIP(hipStreamSynchronize(st));
+        TM_HIP(hipFree(q.ucols));
+        q.ucols = nullptr;
+    }
+    q.ground_ready = true;
+}
+
+// drops the resident real-space ground state (the next apply decides again)
+static void reset_ground(System& s) {
+    if (s.ureal) {
+        TM_HIP(hipDeviceSynchronize());
+        TM_HIP(hipFree(s.ureal));
+    }
+    s.ureal = nullptr;
+    s.ureal_bytes = 0;
+    s.ureal_mode = 0;
+    for (QSet& q : s.qs) q.ground_ready = false;
 }
 
 void apply_fp64(System& s, int iq, const double2* in, double2* out, hipStream_t st) {
     QSet& q = s.qs[iq];
     ensure_workspace(s, q);
-    ensure_ucols(s, q, st);
+    ensure_ground(s, q, st);
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
     launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st);
     launch_density(s, q, st);
@@ -774,8 +840,11 @@ int tm_system_destroy(tm_system* sys) {
         System& s = sys->s;
         (void)hipDeviceSynchronize();
         for (void* p : s.allocs) (void)hipFree(p);
+        for (QSet& q : s.qs)
+            if (q.ucols) (void)hipFree(q.ucols);
+        if (s.ureal) (void)hipFree(s.ureal);
         Workspace& w = s.ws;
-        void* wp[] = {w.xcols, w.rho_part, w.rho, w.W, w.work, w.gpart, w.gsmall, w.dots, w.dotpart};
+        void* wp[] = {w.xcols, w.rho_part, w.rho, w.W, w.work, w.gpart, w.gsmall, w.dots, w.dotpart, w.fields};
         for (void* p : wp)
             if (p) (void)hipFree(p);
         delete sys;
@@ -794,6 +863,23 @@ int tm_qset_info_get(const tm_system* sys, int iq, tm_qset_info* info) {
         info->npw_pad = q.npw_pad;
         info->nelem = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
         info->lam = q.lam;
+        return TM_OK;
+    });
+}
+
+int tm_system_set_resident_limit(tm_system* sys, long long bytes) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys, TM_EINVAL, "null system");
+        reset_ground(sys->s);
+        sys->s.resident_limit = bytes < 0 ? -1 : bytes;
+        return TM_OK;
+    });
+}
+
+int tm_system_resident_bytes(const tm_system* sys, long long* bytes) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && bytes, TM_EINVAL, "null argument");
+        *bytes = (long long)sys->s.ureal_bytes;
         return TM_OK;
     });
 }

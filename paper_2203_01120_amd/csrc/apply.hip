@@ -302,6 +302,9 @@ PlaneArgs plane_args(const System& s, const QSet& q) {
     a.rho_part = s.ws.rho_part;
     a.vrs = s.vrs;
     a.W = s.ws.W;
+    a.ureal = s.ureal_mode == 1 ? s.ureal : nullptr;
+    a.uslot = q.d_uslot;
+    a.fields = s.ws.fields;
     return a;
 }
 
@@ -331,6 +334,7 @@ static PlaneTabs plane_tabs(const System& s, const QSet& q) {
     t.tw2 = s.plan[1].tw;
     t.perm1 = s.perm[0];
     t.perm2 = s.perm[1];
+    t.colidx_kq = q.d_colidx_kq;
     return t;
 }
 
@@ -369,6 +373,13 @@ void launch_apply_planes(const System& s, const QSet& q, hipStream_t st) {
     int th = plane_threads(s);
     size_t shm = (size_t)a.NP * sizeof(double2);
     TM_LAUNCH(k_apply_planes, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
+}
+
+void launch_ureal(const System& s, const QSet& q, hipStream_t st) {
+    PlaneArgs a = plane_args(s, q);
+    a.ureal = s.ureal;
+    dim3 grid(s.n3, a.nchunk, 2 * q.nk);
+    launch_ureal_fixed(a, plane_tabs(s, q), grid, s.n1, s.n2, st);
 }
 
 void launch_fxc_setup(System& s, const double* rho_plane, hipStream_t st) {

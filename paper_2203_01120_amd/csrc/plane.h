@@ -19,6 +19,13 @@ struct PlaneArgs {
     double2* rho_part;
     const double* vrs;
     const double2* W;
+    // resident real-space ground state (fixed-size kernels only; null = use
+    // ucols): [slot][nb][n3][2][n1*n2], plane points column-major over the
+    // digit-reversed positions of the in-place transforms, time reversal
+    // applied on the y side
+    double2* ureal;
+    const int* uslot;  // [2nk] slot of each batch
+    double2* fields;   // [n3][n1*n2][6] local fields in the order of the resident planes
 };
 
 // rows of the (i1, i2) plane occupied by each sphere, per batch b
@@ -33,6 +40,7 @@ struct PlaneTabs {
     const double2* tw2;  // exp(-2 pi i j / n2)
     const int* perm1;    // mixed-radix digit reversal of the in-place transforms along i1
     const int* perm2;    // and along i2
+    const short* const* colidx_kq;  // [n1*n2] column of the k+q sphere at each plane position, or -1
 };
 
 // position p of an in-place decimation-in-frequency transform of length n holds
@@ -71,5 +79,7 @@ void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatc
 bool plane_fixed_supported(int n1, int n2);
 void launch_plane_fixed(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
                         hipStream_t st);
+// fills a.ureal for the batches of the grid from a.ucols
+void launch_ureal_fixed(const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2, hipStream_t st);
 
 }  // namespace tml

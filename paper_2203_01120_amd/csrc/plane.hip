@@ -153,12 +153,19 @@ __device__ __forceinline__ void fft_dit_all(double2* pl, int nlines, const Lines
     fft_dit<N, SIGN, NT, cp.nrad - 1>(pl, nlines, L, tw);
 }
 
-template <int N1, int N2, int NT>
+// Which planes a block-synchronous kernel keeps in LDS.
+//   kXU: x_up, x_dn, u_up, u_dn; the ground-state band is transformed in the
+//        kernel from its z-transformed columns (column path);
+//   kU:  u_up, u_dn; builds the resident real-space copy.
+enum PlaneSet { kXU = 0, kU = 2 };
+
+template <int N1, int N2, int NT, int SET>
 struct PlaneKernel {
     using G = Geom<N1, N2>;
+    static constexpr int NPL = SET == kXU ? 4 : 2;
     static constexpr int PTS = cdiv(G::NP, NT);
 
-    // LDS carve-up: 4 planes, twiddles, row line table, digit-reversal tables
+    // LDS carve-up: planes, twiddles, row line table, digit-reversal tables
     struct Smem {
         double2* pl;
         double2* tw1;
@@ -170,25 +177,40 @@ struct PlaneKernel {
     __device__ static Smem carve(double2* lds) {
         Smem m;
         m.pl = lds;
-        m.tw1 = lds + 4 * G::PS;
+        m.tw1 = lds + NPL * G::PS;
         m.tw2 = m.tw1 + N1;
         m.rowbase = reinterpret_cast<int*>(m.tw2 + N2);
-        m.perm1 = m.rowbase + 4 * N1;
+        m.perm1 = m.rowbase + NPL * N1;
         m.perm2 = m.perm1 + N1;
         return m;
     }
     static constexpr size_t bytes() {
-        return (size_t)4 * G::PS * sizeof(double2) + (N1 + N2) * sizeof(double2) + (4 * N1 + N1 + N2) * sizeof(int);
+        return (size_t)NPL * G::PS * sizeof(double2) + (N1 + N2) * sizeof(double2) +
+               (NPL * N1 + N1 + N2) * sizeof(int);
     }
 
-    __device__ static void setup(const PlaneTabs& t, int b, const Smem& m, int& nrx, int& nru,
-                                 unsigned long long& mx, unsigned long long& mu) {
-        nrx = t.nrows_kq[b];
-        nru = t.nrows_u[b];
-        mx = t.rmask_kq[b];
-        mu = t.rmask_u[b];
+    // occupied rows of the block's planes
+    struct Rows {
+        int nrl;                  // row lines in the row table
+        int nrx;                  // occupied rows of the k+q sphere
+        unsigned long long m01;   // row mask of planes 0, 1
+        unsigned long long m23;   // row mask of planes 2, 3
+    };
+
+    __device__ static Rows setup(const PlaneTabs& t, int b, const Smem& m) {
+        Rows R;
+        const int nrx = t.nrows_kq[b], nru = t.nrows_u[b];
         const int* rx = t.rows_kq[b];
         const int* ru = t.rows_u[b];
+        R.nrx = nrx;
+        if (SET == kU) {
+            R.m01 = R.m23 = t.rmask_u[b];
+            R.nrl = 2 * nru;
+        } else {
+            R.m01 = t.rmask_kq[b];
+            R.m23 = t.rmask_u[b];
+            R.nrl = 2 * nrx + 2 * nru;
+        }
         for (int i = threadIdx.x; i < N1; i += NT) {
             m.tw1[i] = t.tw1[i];
             m.perm1[i] = t.perm1[i];
@@ -197,73 +219,80 @@ struct PlaneKernel {
             m.tw2[i] = t.tw2[i];
             m.perm2[i] = t.perm2[i];
         }
-        for (int i = threadIdx.x; i < 2 * nrx + 2 * nru; i += NT) {
+        const int nr0 = SET == kU ? nru : nrx;
+        const int* r0 = SET == kU ? ru : rx;
+        for (int i = threadIdx.x; i < R.nrl; i += NT) {
             int plane, row;
-            if (i < 2 * nrx) {
-                plane = i / nrx;
-                row = rx[i - plane * nrx];
+            if (i < 2 * nr0) {
+                plane = i / nr0;
+                row = r0[i - plane * nr0];
             } else {
-                int j = i - 2 * nrx;
+                const int j = i - 2 * nr0;
                 plane = 2 + j / nru;
                 row = ru[j - (plane - 2) * nru];
             }
             m.rowbase[i] = plane * G::PS + row * G::N2P;
         }
         __syncthreads();
+        return R;
     }
 
-    // x_up, x_dn, u_up, u_dn of band n at plane i3 -> real space in the 4 LDS
-    // planes, stored at digit-reversed positions along both axes
-    __device__ static void inverse4(const Smem& m, const PlaneArgs& a, int b, int n, int i3, int nrx, int nru,
-                                    unsigned long long mx, unsigned long long mu) {
+    // scatter the z-transformed columns of item pair (2n, 2n+1) of one sphere
+    // into planes p0, p0+1
+    __device__ static void scatter(double2* pl, int p0, const double2* cols, long long cstride, int ncol,
+                                   const int* colpos) {
+        for (int i = threadIdx.x; i < 2 * ncol; i += NT) {
+            const int s = i >= ncol, c = i - s * ncol;
+            const int pos = colpos[c];
+            const int i1 = pos / N2, i2 = pos - i1 * N2;
+            pl[(p0 + s) * G::PS + i1 * G::N2P + i2] = cols[s * cstride + c];
+        }
+    }
+
+    // band n at plane i3 -> real space in the LDS planes, stored at
+    // digit-reversed positions along both axes
+    __device__ static void inverse(const Smem& m, const PlaneArgs& a, int b, int n, int i3, const Rows& R) {
         double2* pl = m.pl;
-        const int nrl = 2 * nrx + 2 * nru;
-        for (int i = threadIdx.x; i < nrl * N2; i += NT) {  // clear the occupied rows
-            int l = i / N2;
+        for (int i = threadIdx.x; i < R.nrl * N2; i += NT) {  // clear the occupied rows
+            const int l = i / N2;
             pl[m.rowbase[l] + (i - l * N2)] = cmk(0.0, 0.0);
         }
         __syncthreads();
-        const int ncx = a.ncol_kq[b], ncu = a.ncol_u[b];
-        const int* cpx = a.colpos_kq[b];
-        const int* cpu = a.colpos_u[b];
-        const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-        const long long xs = (long long)a.n3 * a.ncol_max;
+        if (SET == kXU) {
+            const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+            scatter(pl, 0, cx, (long long)a.n3 * a.ncol_max, a.ncol_kq[b], a.colpos_kq[b]);
+        }
         const double2* cu = a.ucols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_u_max;
-        const long long us = (long long)a.n3 * a.ncol_u_max;
-        for (int i = threadIdx.x; i < 2 * ncx; i += NT) {
-            int s = i >= ncx, c = i - s * ncx;
-            int pos = cpx[c];
-            int i1 = pos / N2, i2 = pos - i1 * N2;
-            pl[s * G::PS + i1 * G::N2P + i2] = cx[s * xs + c];
-        }
-        for (int i = threadIdx.x; i < 2 * ncu; i += NT) {
-            int s = i >= ncu, c = i - s * ncu;
-            int pos = cpu[c];
-            int i1 = pos / N2, i2 = pos - i1 * N2;
-            pl[(2 + s) * G::PS + i1 * G::N2P + i2] = cu[s * us + c];
-        }
+        scatter(pl, SET == kXU ? 2 : 0, cu, (long long)a.n3 * a.ncol_u_max, a.ncol_u[b], a.colpos_u[b]);
         __syncthreads();
         RowLines rl{m.rowbase};
-        fft_dif<N2, +1, NT, false>(pl, nrl, rl, m.tw2);
+        fft_dif<N2, +1, NT, false>(pl, R.nrl, rl, m.tw2);
         ColLines<N1, N2> cl;
-        cl.mx = mx;
-        cl.mu = mu;
-        fft_dif<N1, +1, NT, true>(pl, 4 * N2, cl, m.tw1);
+        cl.mx = R.m01;
+        cl.mu = R.m23;
+        fft_dif<N1, +1, NT, true>(pl, NPL * N2, cl, m.tw1);
     }
 };
 
+// time reversal of the spinor (u_up, u_dn) -> (conj u_dn, -conj u_up)
+__device__ __forceinline__ void time_reverse(double2& uu, double2& ud) {
+    const double2 t0 = uu;
+    uu = cconj(ud);
+    ud = cmk(-t0.x, t0.y);
+}
+
+// Column path, block-synchronous: every radix stage of a plane transform is
+// one workgroup-wide pass over all lines of the four planes.
 template <int N1, int N2, int NT>
 __global__ void __launch_bounds__(NT) k_density_t(PlaneArgs a, PlaneTabs t) {
-    using K = PlaneKernel<N1, N2, NT>;
+    using K = PlaneKernel<N1, N2, NT, kXU>;
     using G = typename K::G;
     constexpr int PTS = K::PTS;
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     double2* pl = m.pl;
     const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
-    int nrx, nru;
-    unsigned long long mx, mu;
-    K::setup(t, b, m, nrx, nru, mx, mu);
+    const typename K::Rows R = K::setup(t, b, m);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const bool yside = b >= a.nk;
@@ -273,18 +302,14 @@ __global__ void __launch_bounds__(NT) k_density_t(PlaneArgs a, PlaneTabs t) {
 #pragma unroll
         for (int j = 0; j < PTS; ++j) acc[c][j] = cmk(0.0, 0.0);
     for (int n = n0; n < n1e; ++n) {
-        K::inverse4(m, a, b, n, i3, nrx, nru, mx, mu);
+        K::inverse(m, a, b, n, i3, R);
 #pragma unroll
         for (int j = 0; j < PTS; ++j) {
             const int pt = threadIdx.x + j * NT;
             if (pt < G::NP) {
                 const int p1 = pt / N2, o = p1 * G::N2P + (pt - p1 * N2);
                 double2 xu = pl[o], xd = pl[G::PS + o], uu = pl[2 * G::PS + o], ud = pl[3 * G::PS + o];
-                if (yside) {  // u' = T U_-k: (a, b) -> (conj b, -conj a)
-                    double2 t0 = uu;
-                    uu = cconj(ud);
-                    ud = cmk(-t0.x, t0.y);
-                }
+                if (yside) time_reverse(uu, ud);  // u' = T U_-k
                 double2 uu_xu = cmulc(uu, xu), ud_xd = cmulc(ud, xd);
                 double2 uu_xd = cmulc(uu, xd), ud_xu = cmulc(ud, xu);
                 acc[0][j] = cadd(acc[0][j], cadd(uu_xu, ud_xd));
@@ -311,16 +336,14 @@ __global__ void __launch_bounds__(NT) k_density_t(PlaneArgs a, PlaneTabs t) {
 
 template <int N1, int N2, int NT>
 __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
-    using K = PlaneKernel<N1, N2, NT>;
+    using K = PlaneKernel<N1, N2, NT, kXU>;
     using G = typename K::G;
     constexpr int PTS = K::PTS;
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     double2* pl = m.pl;
     const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
-    int nrx, nru;
-    unsigned long long mx, mu;
-    K::setup(t, b, m, nrx, nru, mx, mu);
+    const typename K::Rows R = K::setup(t, b, m);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const double sg = b < a.nk ? 1.0 : -1.0;
@@ -353,18 +376,14 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
     const int ncx = a.ncol_kq[b];
     const int* cpx = a.colpos_kq[b];
     for (int n = n0; n < n1e; ++n) {
-        K::inverse4(m, a, b, n, i3, nrx, nru, mx, mu);
+        K::inverse(m, a, b, n, i3, R);
 #pragma unroll
         for (int j = 0; j < PTS; ++j) {
             const int pt = threadIdx.x + j * NT;
             if (pt < G::NP) {
                 const int p1 = pt / N2, o = p1 * G::N2P + (pt - p1 * N2);
                 double2 xu = pl[o], xd = pl[G::PS + o], uu = pl[2 * G::PS + o], ud = pl[3 * G::PS + o];
-                if (yside) {
-                    double2 t0 = uu;
-                    uu = cconj(ud);
-                    ud = cmk(-t0.x, t0.y);
-                }
+                if (yside) time_reverse(uu, ud);
                 double2 bm = cmk(bx[j], -by[j]), bp = cmk(bx[j], by[j]);
                 double2 pu = cadd(cscale(xu, vv[j] + bz[j]), cmul(bm, xd));
                 double2 pd = cadd(cscale(xd, vv[j] - bz[j]), cmul(bp, xu));
@@ -377,12 +396,12 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
         }
         __syncthreads();
         // forward, digit-reversed -> natural: columns of planes 0, 1, then the
-        // occupied rows of the k+q sphere
+        // occupied rows of the k+q sphere (the first 2 nrx row lines)
         ColLines<N1, N2> cl;
         cl.mx = cl.mu = ~0ULL;
         fft_dit_all<N1, -1, NT>(pl, 2 * N2, cl, m.tw1);
         RowLines rl{m.rowbase};
-        fft_dit_all<N2, -1, NT>(pl, 2 * nrx, rl, m.tw2);
+        fft_dit_all<N2, -1, NT>(pl, 2 * R.nrx, rl, m.tw2);
         double2* co = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const long long cs = (long long)a.n3 * a.ncol_max;
         for (int i = threadIdx.x; i < 2 * ncx; i += NT) {
@@ -395,19 +414,493 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
     }
 }
 
+// Resident real-space ground state: [slot][band][i3][spin][plane point], the
+// plane points in column-major order of the LDS positions (p1 fastest,
+// p1 and p2 digit-reversed), time reversal applied on the y side.
+__device__ __forceinline__ const double2* ureal_plane(const PlaneArgs& a, int b, int n, int i3) {
+    return a.ureal + (((long long)a.uslot[b] * a.nb + n) * a.n3 + i3) * 2 * a.NP;
+}
+
 template <int N1, int N2, int NT>
-void launch_t(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st) {
-    size_t shm = PlaneKernel<N1, N2, NT>::bytes();
-    if (density) {
-        TM_CHECK(hipFuncSetAttribute((const void*)k_density_t<N1, N2, NT>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess,
-                 TM_EDEVICE, "cannot raise the LDS limit of k_density_t");
-        TM_LAUNCH((k_density_t<N1, N2, NT>), grid, dim3(NT), shm, st, a, t);
+__global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
+    using K = PlaneKernel<N1, N2, NT, kU>;
+    using G = typename K::G;
+    extern __shared__ double2 lds[];
+    const typename K::Smem m = K::carve(lds);
+    double2* pl = m.pl;
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
+    const typename K::Rows R = K::setup(t, b, m);
+    const int n0 = chunk * a.bpc;
+    const int n1e = min(a.nb, n0 + a.bpc);
+    const bool yside = b >= a.nk;
+    for (int n = n0; n < n1e; ++n) {
+        K::inverse(m, a, b, n, i3, R);
+        double2* out = a.ureal + (((long long)a.uslot[b] * a.nb + n) * a.n3 + i3) * 2 * G::NP;
+        for (int idx = threadIdx.x; idx < G::NP; idx += NT) {
+            const int p2 = idx / N1, p1 = idx - p2 * N1;
+            const int o = p1 * G::N2P + p2;
+            double2 uu = pl[o], ud = pl[G::PS + o];
+            if (yside) time_reverse(uu, ud);
+            out[idx] = uu;
+            out[G::NP + idx] = ud;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- wave-local kernels
+// Resident ground state.  Each wave owns whole lines: in the row phase a
+// subset of the occupied rows, in the column phase the columns
+// p2 in [w CPW, (w+1) CPW) of both x planes.  The radix stages of a line then
+// need no workgroup barrier: LDS instructions of one wave complete in issue
+// order, and a wave-scope fence keeps the compiler from reordering them.  The
+// point-wise products run inside the column phase on the wave's own columns,
+// and two LDS buffers alternate between bands, so a band costs one workgroup
+// barrier in the density and two in the apply.
+constexpr int kCPW = 4;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// one in-place stage (see ipass) over the nl lines of one wave.
+//  * A line's butterflies sit on consecutive lanes; a line of 12 butterflies
+//    takes a whole 16-lane group, so the 16 lanes that LDS serves together
+//    address distinct banks (row pitch n2+1 puts element e of column c at bank
+//    group (e + c) mod 16; offsets within a line are distinct mod 16 for every
+//    stage of 48 = 4 x 4 x 3).
+//  * Twiddles come from the table in device memory (vector L1), not from LDS.
+//  * The lane's butterflies go in groups of BT whose loads are all issued
+//    before their stores (BT trades registers for memory-level parallelism).
+template <int N, int R, int LB, int SIGN, bool DIF, bool MASKED, int MAXL, int BT, class WL>
+__device__ __forceinline__ void wpass(double2* pl, const WL& L, int nl, const double2* __restrict__ tw, int lane) {
+    constexpr int M = LB / R;
+    constexpr int BPL = N / R;
+    constexpr int SPL = (BPL > 8 && BPL < 16) ? 16 : BPL;  // lane slots per line
+    constexpr int TWS = N / LB;
+    constexpr int ES = WL::ES;
+    constexpr int IT = cdiv(MAXL * SPL, 64);
+    constexpr int B = BT < IT ? BT : IT;
+    const int ns = nl * SPL;
+#pragma unroll
+    for (int g0 = 0; g0 < IT; g0 += B) {
+        double2 u[B][R];
+        int base[B], jv[B];
+#pragma unroll
+        for (int it = 0; it < B; ++it) {
+            const int sl = lane + (g0 + it) * 64;
+            const int li = sl / SPL;
+            const int r0 = sl - li * SPL;
+            base[it] = -1;
+            jv[it] = 0;
+            if (g0 + it < IT && sl < ns && r0 < BPL) {
+                const int blk = r0 / M;
+                const int j = r0 - blk * M;
+                const int e0 = blk * LB + j;
+                const int bs = L.base(li) + e0 * ES;
+                base[it] = bs;
+                jv[it] = j;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    double2 x = cmk(0.0, 0.0);
+                    if (!MASKED || L.valid(e0 + t * M)) x = pl[bs + t * M * ES];
+                    if (!DIF && t > 0 && j > 0) {
+                        double2 w = tw[t * j * TWS];
+                        if (SIGN > 0) w.y = -w.y;
+                        x = cmul(x, w);
+                    }
+                    u[it][t] = x;
+                }
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < B; ++it) {
+            if (base[it] >= 0) {
+                dft_small<R>(u[it], SIGN);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    double2 y = u[it][r];
+                    if (DIF && r > 0 && jv[it] > 0) {
+                        double2 w = tw[r * jv[it] * TWS];
+                        if (SIGN > 0) w.y = -w.y;
+                        y = cmul(y, w);
+                    }
+                    pl[base[it] + r * M * ES] = y;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+template <int N, int SIGN, bool MASKED, int MAXL, int BT, int STAGE = 0, int LB = N, class WL>
+__device__ __forceinline__ void wfft_dif(double2* pl, const WL& L, int nl, const double2* tw, int lane) {
+    constexpr CPlan cp = cplan(N);
+    if constexpr (STAGE < cp.nrad) {
+        constexpr int R = cp.rad[STAGE];
+        wpass<N, R, LB, SIGN, true, MASKED && STAGE == 0, MAXL, BT>(pl, L, nl, tw, lane);
+        wfft_dif<N, SIGN, MASKED, MAXL, BT, STAGE + 1, LB / R>(pl, L, nl, tw, lane);
+    }
+}
+
+template <int N, int SIGN, int MAXL, int BT, int STAGE, class WL>
+__device__ __forceinline__ void wfft_dit(double2* pl, const WL& L, int nl, const double2* tw, int lane) {
+    constexpr CPlan cp = cplan(N);
+    if constexpr (STAGE >= 0) {
+        constexpr int R = cp.rad[STAGE];
+        constexpr int LB = N / cp.pre[STAGE];
+        wpass<N, R, LB, SIGN, false, false, MAXL, BT>(pl, L, nl, tw, lane);
+        wfft_dit<N, SIGN, MAXL, BT, STAGE - 1>(pl, L, nl, tw, lane);
+    }
+}
+
+// row lines w, w + NW, ... of the block's row table
+template <int NW>
+struct WRows {
+    static constexpr int ES = 1;
+    const int* rowbase;
+    int w, boff;
+    __device__ int base(int li) const { return boff + rowbase[w + li * NW]; }
+    __device__ bool valid(int) const { return true; }
+};
+
+// columns c0 .. c0 + kCPW - 1 of x planes 0 and 1; rows outside `mask` are
+// read as zero by a masked first stage
+template <int N1, int N2>
+struct WCols {
+    static constexpr int ES = Geom<N1, N2>::N2P;
+    int c0, boff;
+    unsigned long long mask;
+    __device__ int base(int li) const {
+        const int s = li / kCPW;
+        return boff + s * Geom<N1, N2>::PS + c0 + (li - s * kCPW);
+    }
+    __device__ bool valid(int row) const { return (mask >> row) & 1ULL; }
+};
+
+template <int N1, int N2, int BT_>
+struct WaveKernel {
+    using G = Geom<N1, N2>;
+    static constexpr int NW = N2 / kCPW;            // waves
+    static constexpr int NT = 64 * NW;
+    static constexpr int WPTS = kCPW * N1;          // points of a wave (per plane)
+    static constexpr int PPL = cdiv(WPTS, 64);      // points per lane
+    static constexpr int MAXR = cdiv(2 * N1, NW);   // row lines of a wave, at most
+    static constexpr int BUF = 2 * G::PS;           // one buffer: planes x_up, x_dn
+    static constexpr int BT = BT_;                  // butterflies per load group
+    static_assert(N2 % kCPW == 0 && NW <= 16, "plane shape");
+
+    struct Smem {
+        double2* pl;       // 2 buffers
+        double2* tw1;
+        double2* tw2;
+        int* rowbase;      // [2 N1] plane * PS + row * N2P of the occupied rows of planes 0, 1
+        int* rowinfo;      // [2 N1] plane * N1 + row
+        int* perm1;
+        int* perm2;
+        short* colidx;     // [N1 N2] column of the k+q sphere at natural plane position, or -1
+    };
+    __device__ static Smem carve(double2* lds) {
+        Smem m;
+        m.pl = lds;
+        m.tw1 = lds + 2 * BUF;
+        m.tw2 = m.tw1 + N1;
+        m.rowbase = reinterpret_cast<int*>(m.tw2 + N2);
+        m.rowinfo = m.rowbase + 2 * N1;
+        m.perm1 = m.rowinfo + 2 * N1;
+        m.perm2 = m.perm1 + N1;
+        m.colidx = reinterpret_cast<short*>(m.perm2 + N2);
+        return m;
+    }
+    static constexpr size_t bytes() {
+        return (size_t)2 * BUF * sizeof(double2) + (N1 + N2) * sizeof(double2) +
+               (4 * N1 + N1 + N2) * sizeof(int) + (size_t)N1 * N2 * sizeof(short);
+    }
+
+    __device__ static int setup(const PlaneTabs& t, int b, const Smem& m) {
+        const int nrx = t.nrows_kq[b];
+        const int* rx = t.rows_kq[b];
+        const short* ci = t.colidx_kq[b];
+        for (int i = threadIdx.x; i < N1; i += NT) {
+            m.tw1[i] = t.tw1[i];
+            m.perm1[i] = t.perm1[i];
+        }
+        for (int i = threadIdx.x; i < N2; i += NT) {
+            m.tw2[i] = t.tw2[i];
+            m.perm2[i] = t.perm2[i];
+        }
+        for (int i = threadIdx.x; i < 2 * nrx; i += NT) {
+            const int s = i >= nrx;
+            const int row = rx[i - s * nrx];
+            m.rowbase[i] = s * G::PS + row * G::N2P;
+            m.rowinfo[i] = s * N1 + row;
+        }
+        for (int i = threadIdx.x; i < N1 * N2; i += NT) m.colidx[i] = ci[i];
+        __syncthreads();
+        return nrx;
+    }
+
+    // row lines of wave w among nrl
+    __device__ static int wave_rows(int nrl, int w) { return w < nrl ? (nrl - 1 - w) / NW + 1 : 0; }
+
+    // fill the wave's occupied rows of buffer boff from the z-transformed
+    // columns of item pair (2n, 2n+1), then the inverse transforms along i2
+    __device__ static void rows_inverse(const Smem& m, const double2* cx, long long cs, int nlw, int w, int boff,
+                                        int lane, const double2* __restrict__ gtw2) {
+        for (int k = lane; k < nlw * N2; k += 64) {
+            const int li = k / N2, p2 = k - li * N2;
+            const int l = w + li * NW;
+            const int info = m.rowinfo[l];
+            const int s = info / N1, row = info - s * N1;
+            const int c = m.colidx[row * N2 + p2];
+            m.pl[boff + m.rowbase[l] + p2] = c >= 0 ? cx[s * cs + c] : cmk(0.0, 0.0);
+        }
+        wave_sync();
+        WRows<NW> rl{m.rowbase, w, boff};
+        wfft_dif<N2, +1, false, MAXR, BT>(m.pl, rl, nlw, gtw2, lane);
+    }
+};
+
+// the lane's points of wave w: LDS offset (within a buffer's plane 0), and
+// natural grid index in the plane
+template <int N1, int N2>
+__device__ __forceinline__ void wave_point(int w, int q, const int* perm1, const int* perm2, int& o, int& g) {
+    const int cc = q / N1, p1 = q - cc * N1;
+    const int p2 = w * kCPW + cc;
+    o = p1 * Geom<N1, N2>::N2P + p2;
+    g = perm1[p1] * N2 + perm2[p2];
+}
+
+template <int N1, int N2, int BT>
+__global__ void __launch_bounds__(64 * (N2 / kCPW)) k_density_w(PlaneArgs a, PlaneTabs t) {
+    using K = WaveKernel<N1, N2, BT>;
+    using G = typename K::G;
+    constexpr int PPL = K::PPL;
+    extern __shared__ double2 lds[];
+    const typename K::Smem m = K::carve(lds);
+    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nrx = K::setup(t, b, m);
+    const unsigned long long mask = t.rmask_kq[b];
+    const int nlw = K::wave_rows(2 * nrx, w);
+    const int n0 = chunk * a.bpc;
+    const int n1e = min(a.nb, n0 + a.bpc);
+    const long long cs = (long long)a.n3 * a.ncol_max;
+    int o[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        int g;
+        wave_point<N1, N2>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
+    }
+    double2 acc[4][PPL];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) acc[c][j] = cmk(0.0, 0.0);
+    for (int n = n0; n < n1e; ++n) {
+        const int boff = (n & 1) * K::BUF;
+        const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        const double2* ur = ureal_plane(a, b, n, i3) + w * K::WPTS;
+        double2 uu[PPL], ud[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            const int q = lane + 64 * j;
+            if (q < K::WPTS) {
+                uu[j] = ur[q];
+                ud[j] = ur[G::NP + q];
+            }
+        }
+        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, t.tw2);
+        __syncthreads();
+        WCols<N1, N2> cl{w * kCPW, boff, mask};
+        wfft_dif<N1, +1, true, 2 * kCPW, K::BT>(m.pl, cl, 2 * kCPW, t.tw1, lane);
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            if (lane + 64 * j < K::WPTS) {
+                const double2 xu = m.pl[boff + o[j]], xd = m.pl[boff + G::PS + o[j]];
+                const double2 uu_xu = cmulc(uu[j], xu), ud_xd = cmulc(ud[j], xd);
+                const double2 uu_xd = cmulc(uu[j], xd), ud_xu = cmulc(ud[j], xu);
+                acc[0][j] = cadd(acc[0][j], cadd(uu_xu, ud_xd));
+                acc[1][j] = cadd(acc[1][j], cadd(uu_xd, ud_xu));
+                acc[2][j] = cadd(acc[2][j], cmuli(csub(ud_xu, uu_xd)));
+                acc[3][j] = cadd(acc[3][j], csub(uu_xu, ud_xd));
+            }
+        }
+    }
+    const long long N = (long long)G::NP * a.n3;
+    double2* out = a.rho_part + ((long long)b * a.nchunk + chunk) * 4 * N + (long long)i3 * G::NP;
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        const int q = lane + 64 * j;
+        if (q < K::WPTS) {
+            int oo, g;
+            wave_point<N1, N2>(w, q, m.perm1, m.perm2, oo, g);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) out[c * N + g] = acc[c][j];
+        }
+    }
+}
+
+// Local fields in the wave kernels' point order, per plane i3 and point
+// idx = p2 n1 + p1 (LDS position, digit-reversed), 6 complex per point:
+//   (v + Bz, v - Bz), (Bx, By), W0 + Wz, W0 - Wz, Wx - i Wy, Wx + i Wy
+// (x side; the y side flips the sign of B and of the vector part of W).
+template <int N1, int N2>
+__global__ void k_fields_w(const double* __restrict__ vrs, const double2* __restrict__ W, const int* perm1,
+                           const int* perm2, double2* __restrict__ F, int n3) {
+    constexpr int NP = N1 * N2;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i3 = blockIdx.y;
+    if (idx >= NP) return;
+    const int p2 = idx / N1, p1 = idx - p2 * N1;
+    const long long N = (long long)NP * n3;
+    const long long g = (long long)i3 * NP + perm1[p1] * N2 + perm2[p2];
+    const double v = vrs[g], bx = vrs[N + g], by = vrs[2 * N + g], bz = vrs[3 * N + g];
+    const double2 w0 = W[g], wx = W[N + g], wy = W[2 * N + g], wz = W[3 * N + g];
+    double2* f = F + ((long long)i3 * NP + idx) * 6;
+    f[0] = cmk(v + bz, v - bz);
+    f[1] = cmk(bx, by);
+    f[2] = cadd(w0, wz);
+    f[3] = csub(w0, wz);
+    f[4] = csub(wx, cmuli(wy));
+    f[5] = cadd(wx, cmuli(wy));
+}
+
+// grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
+// planes and their field tables stay in L2
+template <int N1, int N2, int BT>
+__global__ void __launch_bounds__(64 * (N2 / kCPW)) k_apply_w(PlaneArgs a, PlaneTabs t) {
+    using K = WaveKernel<N1, N2, BT>;
+    using G = typename K::G;
+    constexpr int PPL = K::PPL;
+    extern __shared__ double2 lds[];
+    const typename K::Smem m = K::carve(lds);
+    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nrx = K::setup(t, b, m);
+    const unsigned long long mask = t.rmask_kq[b];
+    const int nlw = K::wave_rows(2 * nrx, w);
+    const int n0 = chunk * a.bpc;
+    const int n1e = min(a.nb, n0 + a.bpc);
+    const long long cs = (long long)a.n3 * a.ncol_max;
+    const bool yside = b >= a.nk;
+    int o[PPL];
+#pragma unroll
+    for (int j = 0; j < PPL; ++j) {
+        int g;
+        wave_point<N1, N2>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
+    }
+    const double2* fw = a.fields + ((long long)i3 * G::NP + w * K::WPTS) * 6;
+    for (int n = n0; n < n1e; ++n) {
+        const int boff = (n & 1) * K::BUF;
+        const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        const double2* ur = ureal_plane(a, b, n, i3) + w * K::WPTS;
+        double2 uu[PPL], ud[PPL];
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            const int q = lane + 64 * j;
+            if (q < K::WPTS) {
+                uu[j] = ur[q];
+                ud[j] = ur[G::NP + q];
+            }
+        }
+        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, t.tw2);
+        __syncthreads();
+        // columns: inverse along i1, point-wise products, forward along i1
+        WCols<N1, N2> cl{w * kCPW, boff, mask};
+        wfft_dif<N1, +1, true, 2 * kCPW, K::BT>(m.pl, cl, 2 * kCPW, t.tw1, lane);
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            const int q = lane + 64 * j;
+            if (q < K::WPTS) {
+                const double2* f = fw + q * 6;
+                double2 f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4], f5 = f[5];
+                if (yside) {  // B -> -B, W -> (W0, -W)
+                    f0 = cmk(f0.y, f0.x);
+                    f1 = cmk(-f1.x, -f1.y);
+                    const double2 t2 = f2;
+                    f2 = f3;
+                    f3 = t2;
+                    f4 = cmk(-f4.x, -f4.y);
+                    f5 = cmk(-f5.x, -f5.y);
+                }
+                double2* px = m.pl + boff + o[j];
+                const double2 xu = px[0], xd = px[G::PS];
+                const double2 bm = cmk(f1.x, -f1.y), bp = f1;
+                double2 pu = cadd(cscale(xu, f0.x), cmul(bm, xd));
+                double2 pd = cadd(cscale(xd, f0.y), cmul(bp, xu));
+                pu = cadd(pu, cadd(cmul(f2, uu[j]), cmul(f4, ud[j])));
+                pd = cadd(pd, cadd(cmul(f3, ud[j]), cmul(f5, uu[j])));
+                px[0] = pu;
+                px[G::PS] = pd;
+            }
+        }
+        wave_sync();
+        constexpr CPlan c1 = cplan(N1);
+        wfft_dit<N1, -1, 2 * kCPW, K::BT, c1.nrad - 1>(m.pl, cl, 2 * kCPW, t.tw1, lane);
+        __syncthreads();
+        // rows: forward along i2 on the occupied rows of the k+q sphere, then
+        // the output columns
+        constexpr CPlan c2 = cplan(N2);
+        WRows<K::NW> rl{m.rowbase, w, boff};
+        wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rl, nlw, t.tw2, lane);
+        double2* co = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        for (int k = lane; k < nlw * N2; k += 64) {
+            const int li = k / N2, p2 = k - li * N2;
+            const int l = w + li * K::NW;
+            const int info = m.rowinfo[l];
+            const int s = info / N1, row = info - s * N1;
+            const int c = m.colidx[row * N2 + p2];
+            if (c >= 0) co[s * cs + c] = m.pl[boff + m.rowbase[l] + p2];
+        }
+        // the next band works in the other buffer: no barrier here
+    }
+}
+
+enum PlaneOp { kOpDensity = 0, kOpApply = 1, kOpUreal = 2 };
+
+template <class F>
+void launch_with_lds(F kernel, const char* name, size_t shm, dim3 grid, int nt, hipStream_t st, PlaneArgs a,
+                     PlaneTabs t) {
+    TM_CHECK(hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) ==
+                 hipSuccess,
+             TM_EDEVICE, std::string("cannot raise the LDS limit of ") + name);
+    ProfScope ps(name, st);
+    void* args[] = {&a, &t};
+    TM_CHECK(hipLaunchKernel((const void*)kernel, grid, dim3(nt), args, shm, st) == hipSuccess, TM_EDEVICE,
+             std::string("launch of ") + name + " failed");
+    check_launch(name);
+}
+
+// NT: threads of the block-synchronous kernels (column path, builder)
+template <int N1, int N2, int NT>
+void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st) {
+    // butterflies per load group: the 48 x 48 apply holds 3 points of fields
+    // per lane and has registers for one butterfly at a time
+    constexpr int BTD = 2, BTA = 2;
+    using WD = WaveKernel<N1, N2, BTD>;
+    using WA = WaveKernel<N1, N2, BTA>;
+    if (op == kOpUreal) {
+        launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
+    } else if (a.ureal) {
+        TM_CHECK(t.colidx_kq != nullptr, TM_EINVAL, "missing column index tables");
+        const dim3 wgrid(grid.z, grid.y, grid.x);  // (b, chunk, i3)
+        if (op == kOpDensity) {
+            launch_with_lds(k_density_w<N1, N2, BTD>, "k_density_w", WD::bytes(), wgrid, WD::NT, st, a, t);
+        } else {
+            TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
+            TM_LAUNCH((k_fields_w<N1, N2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs, a.W, t.perm1,
+                      t.perm2, a.fields, a.n3);
+            launch_with_lds(k_apply_w<N1, N2, BTA>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
+        }
+    } else if (op == kOpDensity) {
+        launch_with_lds(k_density_t<N1, N2, NT>, "k_density_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT, st,
+                        a, t);
     } else {
-        TM_CHECK(hipFuncSetAttribute((const void*)k_apply_t<N1, N2, NT>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess,
-                 TM_EDEVICE, "cannot raise the LDS limit of k_apply_t");
-        TM_LAUNCH((k_apply_t<N1, N2, NT>), grid, dim3(NT), shm, st, a, t);
+        launch_with_lds(k_apply_t<N1, N2, NT>, "k_apply_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT, st, a,
+                        t);
     }
 }
 
@@ -583,14 +1076,24 @@ bool plane_fixed_supported(int n1, int n2) {
            (n1 == 48 && n2 == 48);
 }
 
+static void launch_plane_op(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
+                            hipStream_t st) {
+    if (n1 == 8 && n2 == 8) launch_t<8, 8, 64>(op, a, t, grid, st);
+    else if (n1 == 20 && n2 == 20) launch_t<20, 20, 256>(op, a, t, grid, st);
+    else if (n1 == 24 && n2 == 24) launch_t<24, 24, 256>(op, a, t, grid, st);
+    else if (n1 == 32 && n2 == 32) launch_t<32, 32, 512>(op, a, t, grid, st);
+    else if (n1 == 48 && n2 == 48) launch_t<48, 48, 1024>(op, a, t, grid, st);
+    else throw Error{TM_EUNSUPPORTED, "no fixed-size plane kernel for this grid"};
+}
+
 void launch_plane_fixed(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
                         hipStream_t st) {
-    if (n1 == 8 && n2 == 8) launch_t<8, 8, 64>(density, a, t, grid, st);
-    else if (n1 == 20 && n2 == 20) launch_t<20, 20, 256>(density, a, t, grid, st);
-    else if (n1 == 24 && n2 == 24) launch_t<24, 24, 256>(density, a, t, grid, st);
-    else if (n1 == 32 && n2 == 32) launch_t<32, 32, 512>(density, a, t, grid, st);
-    else if (n1 == 48 && n2 == 48) launch_t<48, 48, 1024>(density, a, t, grid, st);
-    else throw Error{TM_EUNSUPPORTED, "no fixed-size plane kernel for this grid"};
+    launch_plane_op(density ? kOpDensity : kOpApply, a, t, grid, n1, n2, st);
+}
+
+void launch_ureal_fixed(const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2, hipStream_t st) {
+    TM_CHECK(a.ureal != nullptr && a.uslot != nullptr, TM_EINVAL, "no resident ground-state buffer");
+    launch_plane_op(kOpUreal, a, t, grid, n1, n2, st);
 }
 
 }  // namespace tml

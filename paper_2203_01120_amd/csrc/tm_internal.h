@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <memory>
 #include <string>
+#include <array>
+#include <map>
 #include <vector>
 
 #include "../../include/tm.h"
@@ -139,9 +141,11 @@ struct QSet {
     unsigned long long* d_rmask_u = nullptr;
     int** d_rows_kq = nullptr;
     int** d_rows_u = nullptr;
+    int* d_uslot = nullptr;       // [2nk] slot of each batch in the resident real-space ground state
+    short** d_colidx_kq = nullptr;  // [2nk] plane position -> column of the k+q sphere, or -1
     // lazily built caches
     double2* ucols = nullptr;     // z-transformed ground-state columns [b][nb*2][n3][ncol_u_max]
-    bool ucols_ready = false;
+    bool ground_ready = false;    // ucols or the resident real-space slots of this set are built
 };
 
 struct Workspace {
@@ -151,6 +155,7 @@ struct Workspace {
     double2* rho = nullptr;       // [4][N]
     double2* work = nullptr;      // [N] Hartree scratch
     double2* W = nullptr;         // [4][N]
+    double2* fields = nullptr;    // [N][6] fields in the order of the resident real-space planes
     double2* gpart = nullptr;     // GEMM split-K partials
     double2* gsmall = nullptr;    // reduced small GEMM outputs
     double2* dots = nullptr;      // reduced inner products [64]
@@ -183,6 +188,13 @@ struct System {
     double* vrs = nullptr;        // [4][N] plane-major
     double* fxc = nullptr;        // [10][N] unique kernel entries, plane-major
     std::vector<QSet> qs;
+    // resident real-space ground state: one slot per distinct (point, G shift,
+    // side) over all q sets, [slot][nb][n3][2][n1*n2]
+    std::map<std::array<int, 5>, int> uslot_of;
+    long long resident_limit = -1;  // bytes; -1 = a share of the free device memory
+    int ureal_mode = 0;             // 0 undecided, 1 resident, 2 columns
+    double2* ureal = nullptr;
+    size_t ureal_bytes = 0;
     Workspace ws;
     std::vector<void*> allocs;
 };
@@ -216,6 +228,7 @@ void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st)
 void launch_density(const System& s, const QSet& q, hipStream_t st);
 void launch_potential(const System& s, const QSet& q, hipStream_t st);
 void launch_apply_planes(const System& s, const QSet& q, hipStream_t st);
+void launch_ureal(const System& s, const QSet& q, hipStream_t st);
 void launch_fxc_setup(System& s, const double* rho_plane, hipStream_t st);
 void launch_coulomb_setup(const System& s, QSet& q, hipStream_t st);
 // gemm.hip

@@ -43,6 +43,13 @@ class Sys:
         torch.cuda.synchronize()
         return from_gpu(out, self.shape, self.prob.npw_pad)
 
+    def resident(self, on):
+        """Switch between the resident real-space ground state and the column path."""
+        self.tm.tm_system_set_resident_limit(self.h, -1 if on else 0)
+
+    def resident_bytes(self):
+        return self.tm.tm_system_resident_bytes(self.h)
+
     def close(self):
         self.tm.tm_system_destroy(self.h)
 
@@ -63,19 +70,29 @@ def cfg1(lib, cfg1_gs, cfg1_q):
     s.close()
 
 
+@pytest.mark.parametrize("resident", [True, False], ids=["resident", "columns"])
 @pytest.mark.parametrize("which", ["tiny", "cfg1"])
-def test_apply_matches_oracle(which, request):
+def test_apply_matches_oracle(which, resident, request):
     s = request.getfixturevalue(which)
-    for seed in (1, 2):
-        say(f"apply {which} seed {seed}")
-        x = s.prob.random_projected(seed)
-        got, raw = s.apply(x)
-        ref = s.prob.apply(x)
-        assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
-        # padding of the output is zero
-        npw = [kd.npw for kd in s.prob.k]
-        for ik, n in enumerate(npw):
-            assert np.all(raw[:, ik, :, :, n:] == 0)
+    s.resident(resident)
+    try:
+        for seed in (1, 2):
+            say(f"apply {which} resident={resident} seed {seed}")
+            x = s.prob.random_projected(seed)
+            got, raw = s.apply(x)
+            ref = s.prob.apply(x)
+            assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
+            # padding of the output is zero
+            npw = [kd.npw for kd in s.prob.k]
+            for ik, n in enumerate(npw):
+                assert np.all(raw[:, ik, :, :, n:] == 0)
+        # which path ran: one slot per distinct (point, side), all bands and planes
+        nslot = 2 * s.prob.nk
+        n1, n2, n3 = s.prob.gs.sysd.fft
+        expect = nslot * s.prob.nb * n3 * 2 * n1 * n2 * 16 if resident else 0
+        assert s.resident_bytes() == expect
+    finally:
+        s.resident(True)
 
 
 def test_apply_generic_plane_path(lib):
@@ -105,10 +122,14 @@ def test_apply_two_kpoints_folded(lib):
     prob = lv.Problem(gs, qs)
     s = Sys(lib, prob)
     try:
-        for seed in (1, 2):
-            x = prob.random_projected(seed)
-            got, _ = s.apply(x)
-            assert rel_err(got, prob.apply(x)) <= 1e-12
+        for resident in (True, False):
+            s.resident(resident)
+            for seed in (1, 2):
+                x = prob.random_projected(seed)
+                got, _ = s.apply(x)
+                assert rel_err(got, prob.apply(x)) <= 1e-12
+            assert (s.resident_bytes() > 0) == resident
+        s.resident(True)
         got = lib.tm_lanczos_run(s.h, 0, "z", "nH", 8)
         ref = olanczos.run(prob, "z", "nH", 8)
         assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
