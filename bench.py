@@ -43,11 +43,11 @@ def log(msg):
 
 def build_inputs(workload: str, seed: int):
     import synth
-    if workload == "cfg2":
-        sysd = synth.make_cfg2()
+    if workload == "hexslab":
+        sysd = synth.make_hexslab()
         q = synth.cart_from_frac(sysd, [1.0 / 6.0, 0.0, 0.0])
-    elif workload == "cfg1":
-        sysd = synth.make_cfg1()
+    elif workload == "cubic20":
+        sysd = synth.make_cubic20()
         q = np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0
     else:
         raise SystemExit(f"unknown workload {workload}")
@@ -113,7 +113,7 @@ def measured_traffic(kernel: str):
     runs (calibrated against a plain copy), or None when the kernel source has
     changed since those counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "cfg2_hbm_counters.json")
+    path = os.path.join(ROOT, "profiles", "hexslab_48x48x180_hbm_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -132,13 +132,13 @@ def cpu_baseline(workload: str, seed: int, nk_full: int):
     class _GS:  # the oracle Problem only reads these fields here
         pass
 
-    if workload == "cfg2":
-        full_nb = synth.make_cfg2().nbnd
-        sysd = synth.make_cfg2(nbnd=full_nb // 2)   # half the bands keeps the sample near 30 s
+    if workload == "hexslab":
+        full_nb = synth.make_hexslab().nbnd
+        sysd = synth.make_hexslab(nbnd=full_nb // 2)   # half the bands keeps the sample near 30 s
         q = synth.cart_from_frac(sysd, [1.0 / 6.0, 0.0, 0.0])
         subset = [7]
     else:
-        sysd = synth.make_cfg1()
+        sysd = synth.make_cubic20()
         full_nb = sysd.nbnd
         q = np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0
         subset = [0]
@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg1"])
+    ap.add_argument("--workload", default="hexslab", choices=["hexslab", "cubic20"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=20)
@@ -266,7 +266,7 @@ def main():
         else:
             roof = {"kernel": dom, "bound": "mfma" if m.get("mfma") else "alu", "achieved": round(tflops, 3),
                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(f_alu, 4)}
-        roof.update({"traffic": measured_traffic(dom) if args.workload == "cfg2" else None,
+        roof.update({"traffic": measured_traffic(dom) if args.workload == "hexslab" else None,
                      "avg_ms": round(avg_s * 1e3, 4), "algorithmic_flops_per_launch": m["flops"],
                      "algorithmic_bytes_per_launch": round(m["bytes"]),
                      "other": {"alu_frac": round(f_alu, 4), "hbm_frac": round(f_hbm, 4)}})
@@ -295,7 +295,7 @@ def main():
         "config": {
             "workload": ("CrI3-monolayer-shaped hexagonal slab, a=13 c=31 bohr, 2+6 Gaussian sites, "
                          "48x48x180 grid, 104 bands, 6x6x1 mesh (36 k), q=b1/6, pH chain m_+"
-                         if args.workload == "cfg2" else
+                         if args.workload == "hexslab" else
                          "cubic a=10 bohr, 2 sites, 20^3 grid, 8 bands, Gamma, q=0.1 2pi/a, pH chain m_+"),
             "fft": list(sysd.fft), "nbnd": sysd.nbnd, "nk": info["nk"], "npw_pad": info["npw_pad"],
             "nproj": sysd.nproj, "precision": "fp64", "flavour": "pseudo_hermitian",

@@ -457,7 +457,6 @@ __global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
 // point-wise products run inside the column phase on the wave's own columns,
 // and two LDS buffers alternate between bands, so a band costs one workgroup
 // barrier in the density and two in the apply.
-constexpr int kCPW = 4;
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -566,36 +565,35 @@ struct WRows {
     __device__ bool valid(int) const { return true; }
 };
 
-// columns c0 .. c0 + kCPW - 1 of x planes 0 and 1; rows outside `mask` are
+// columns c0 .. c0 + CPW - 1 of x planes 0 and 1; rows outside `mask` are
 // read as zero by a masked first stage
-template <int N1, int N2>
+template <int N1, int N2, int CPW>
 struct WCols {
     static constexpr int ES = Geom<N1, N2>::N2P;
     int c0, boff;
     unsigned long long mask;
     __device__ int base(int li) const {
-        const int s = li / kCPW;
-        return boff + s * Geom<N1, N2>::PS + c0 + (li - s * kCPW);
+        const int s = li / CPW;
+        return boff + s * Geom<N1, N2>::PS + c0 + (li - s * CPW);
     }
     __device__ bool valid(int row) const { return (mask >> row) & 1ULL; }
 };
 
-template <int N1, int N2, int BT_>
+template <int N1, int N2, int BT_, int CPW_>
 struct WaveKernel {
     using G = Geom<N1, N2>;
-    static constexpr int NW = N2 / kCPW;            // waves
+    static constexpr int CPW = CPW_;                // columns per wave
+    static constexpr int NW = N2 / CPW;             // waves
     static constexpr int NT = 64 * NW;
-    static constexpr int WPTS = kCPW * N1;          // points of a wave (per plane)
+    static constexpr int WPTS = CPW * N1;           // points of a wave (per plane)
     static constexpr int PPL = cdiv(WPTS, 64);      // points per lane
     static constexpr int MAXR = cdiv(2 * N1, NW);   // row lines of a wave, at most
     static constexpr int BUF = 2 * G::PS;           // one buffer: planes x_up, x_dn
     static constexpr int BT = BT_;                  // butterflies per load group
-    static_assert(N2 % kCPW == 0 && NW <= 16, "plane shape");
+    static_assert(N2 % CPW == 0 && NW <= 16, "plane shape");
 
     struct Smem {
         double2* pl;       // 2 buffers
-        double2* tw1;
-        double2* tw2;
         int* rowbase;      // [2 N1] plane * PS + row * N2P of the occupied rows of planes 0, 1
         int* rowinfo;      // [2 N1] plane * N1 + row
         int* perm1;
@@ -605,9 +603,7 @@ struct WaveKernel {
     __device__ static Smem carve(double2* lds) {
         Smem m;
         m.pl = lds;
-        m.tw1 = lds + 2 * BUF;
-        m.tw2 = m.tw1 + N1;
-        m.rowbase = reinterpret_cast<int*>(m.tw2 + N2);
+        m.rowbase = reinterpret_cast<int*>(lds + 2 * BUF);
         m.rowinfo = m.rowbase + 2 * N1;
         m.perm1 = m.rowinfo + 2 * N1;
         m.perm2 = m.perm1 + N1;
@@ -615,22 +611,16 @@ struct WaveKernel {
         return m;
     }
     static constexpr size_t bytes() {
-        return (size_t)2 * BUF * sizeof(double2) + (N1 + N2) * sizeof(double2) +
-               (4 * N1 + N1 + N2) * sizeof(int) + (size_t)N1 * N2 * sizeof(short);
+        return (size_t)2 * BUF * sizeof(double2) + (4 * N1 + N1 + N2) * sizeof(int) +
+               (size_t)N1 * N2 * sizeof(short);
     }
 
     __device__ static int setup(const PlaneTabs& t, int b, const Smem& m) {
         const int nrx = t.nrows_kq[b];
         const int* rx = t.rows_kq[b];
         const short* ci = t.colidx_kq[b];
-        for (int i = threadIdx.x; i < N1; i += NT) {
-            m.tw1[i] = t.tw1[i];
-            m.perm1[i] = t.perm1[i];
-        }
-        for (int i = threadIdx.x; i < N2; i += NT) {
-            m.tw2[i] = t.tw2[i];
-            m.perm2[i] = t.perm2[i];
-        }
+        for (int i = threadIdx.x; i < N1; i += NT) m.perm1[i] = t.perm1[i];
+        for (int i = threadIdx.x; i < N2; i += NT) m.perm2[i] = t.perm2[i];
         for (int i = threadIdx.x; i < 2 * nrx; i += NT) {
             const int s = i >= nrx;
             const int row = rx[i - s * nrx];
@@ -665,17 +655,17 @@ struct WaveKernel {
 
 // the lane's points of wave w: LDS offset (within a buffer's plane 0), and
 // natural grid index in the plane
-template <int N1, int N2>
+template <int N1, int N2, int CPW>
 __device__ __forceinline__ void wave_point(int w, int q, const int* perm1, const int* perm2, int& o, int& g) {
     const int cc = q / N1, p1 = q - cc * N1;
-    const int p2 = w * kCPW + cc;
+    const int p2 = w * CPW + cc;
     o = p1 * Geom<N1, N2>::N2P + p2;
     g = perm1[p1] * N2 + perm2[p2];
 }
 
-template <int N1, int N2, int BT>
-__global__ void __launch_bounds__(64 * (N2 / kCPW)) k_density_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT>;
+template <int N1, int N2, int BT, int CPW>
+__global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, PlaneTabs t) {
+    using K = WaveKernel<N1, N2, BT, CPW>;
     using G = typename K::G;
     constexpr int PPL = K::PPL;
     extern __shared__ double2 lds[];
@@ -692,7 +682,7 @@ __global__ void __launch_bounds__(64 * (N2 / kCPW)) k_density_w(PlaneArgs a, Pla
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         int g;
-        wave_point<N1, N2>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
+        wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
     }
     double2 acc[4][PPL];
 #pragma unroll
@@ -714,8 +704,8 @@ __global__ void __launch_bounds__(64 * (N2 / kCPW)) k_density_w(PlaneArgs a, Pla
         }
         K::rows_inverse(m, cx, cs, nlw, w, boff, lane, t.tw2);
         __syncthreads();
-        WCols<N1, N2> cl{w * kCPW, boff, mask};
-        wfft_dif<N1, +1, true, 2 * kCPW, K::BT>(m.pl, cl, 2 * kCPW, t.tw1, lane);
+        WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
+        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, t.tw1, lane);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if (lane + 64 * j < K::WPTS) {
@@ -736,7 +726,7 @@ __global__ void __launch_bounds__(64 * (N2 / kCPW)) k_density_w(PlaneArgs a, Pla
         const int q = lane + 64 * j;
         if (q < K::WPTS) {
             int oo, g;
-            wave_point<N1, N2>(w, q, m.perm1, m.perm2, oo, g);
+            wave_point<N1, N2, CPW>(w, q, m.perm1, m.perm2, oo, g);
 #pragma unroll
             for (int c = 0; c < 4; ++c) out[c * N + g] = acc[c][j];
         }
@@ -770,9 +760,9 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-template <int N1, int N2, int BT>
-__global__ void __launch_bounds__(64 * (N2 / kCPW)) k_apply_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT>;
+template <int N1, int N2, int BT, int CPW>
+__global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneTabs t) {
+    using K = WaveKernel<N1, N2, BT, CPW>;
     using G = typename K::G;
     constexpr int PPL = K::PPL;
     extern __shared__ double2 lds[];
@@ -790,7 +780,7 @@ __global__ void __launch_bounds__(64 * (N2 / kCPW)) k_apply_w(PlaneArgs a, Plane
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         int g;
-        wave_point<N1, N2>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
+        wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
     }
     const double2* fw = a.fields + ((long long)i3 * G::NP + w * K::WPTS) * 6;
     for (int n = n0; n < n1e; ++n) {
@@ -809,8 +799,8 @@ __global__ void __launch_bounds__(64 * (N2 / kCPW)) k_apply_w(PlaneArgs a, Plane
         K::rows_inverse(m, cx, cs, nlw, w, boff, lane, t.tw2);
         __syncthreads();
         // columns: inverse along i1, point-wise products, forward along i1
-        WCols<N1, N2> cl{w * kCPW, boff, mask};
-        wfft_dif<N1, +1, true, 2 * kCPW, K::BT>(m.pl, cl, 2 * kCPW, t.tw1, lane);
+        WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
+        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, t.tw1, lane);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             const int q = lane + 64 * j;
@@ -839,7 +829,7 @@ __global__ void __launch_bounds__(64 * (N2 / kCPW)) k_apply_w(PlaneArgs a, Plane
         }
         wave_sync();
         constexpr CPlan c1 = cplan(N1);
-        wfft_dit<N1, -1, 2 * kCPW, K::BT, c1.nrad - 1>(m.pl, cl, 2 * kCPW, t.tw1, lane);
+        wfft_dit<N1, -1, 2 * CPW, K::BT, c1.nrad - 1>(m.pl, cl, 2 * CPW, t.tw1, lane);
         __syncthreads();
         // rows: forward along i2 on the occupied rows of the k+q sphere, then
         // the output columns
@@ -879,21 +869,24 @@ template <int N1, int N2, int NT>
 void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st) {
     // butterflies per load group: the 48 x 48 apply holds 3 points of fields
     // per lane and has registers for one butterfly at a time
+    // 4 columns per wave (12 waves for 48 x 48; 3 columns and 16 waves measured
+    // slower: idle lanes in the column stages and register spills at 128 VGPRs)
+    constexpr int CPW = 4;
     constexpr int BTD = 2, BTA = 2;
-    using WD = WaveKernel<N1, N2, BTD>;
-    using WA = WaveKernel<N1, N2, BTA>;
+    using WD = WaveKernel<N1, N2, BTD, CPW>;
+    using WA = WaveKernel<N1, N2, BTA, CPW>;
     if (op == kOpUreal) {
         launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
     } else if (a.ureal) {
         TM_CHECK(t.colidx_kq != nullptr, TM_EINVAL, "missing column index tables");
         const dim3 wgrid(grid.z, grid.y, grid.x);  // (b, chunk, i3)
         if (op == kOpDensity) {
-            launch_with_lds(k_density_w<N1, N2, BTD>, "k_density_w", WD::bytes(), wgrid, WD::NT, st, a, t);
+            launch_with_lds(k_density_w<N1, N2, BTD, CPW>, "k_density_w", WD::bytes(), wgrid, WD::NT, st, a, t);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs, a.W, t.perm1,
                       t.perm2, a.fields, a.n3);
-            launch_with_lds(k_apply_w<N1, N2, BTA>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
+            launch_with_lds(k_apply_w<N1, N2, BTA, CPW>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
         }
     } else if (op == kOpDensity) {
         launch_with_lds(k_density_t<N1, N2, NT>, "k_density_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT, st,

@@ -28,8 +28,8 @@ import numpy as np
 
 __all__ = [
     "Atom", "SystemDef", "recip", "volume", "sphere", "grid_points",
-    "vloc_grid", "projector_table", "dmatrix", "make_cfg1", "make_tiny",
-    "make_cfg2", "kmesh_cart", "QSetDef", "qset_exact", "qset_folded",
+    "vloc_grid", "projector_table", "dmatrix", "make_cubic20", "make_tiny",
+    "make_hexslab", "kmesh_cart", "QSetDef", "qset_exact", "qset_folded",
     "random_br", "synthetic_ground_state", "synthetic_fields", "synthetic_inputs",
     "cart_from_frac",
 ]
@@ -211,7 +211,7 @@ def _random_positions(rng, cell, nat, min_sep):
             return frac @ cell
 
 
-def make_cfg1(seed: int = 2205, soc: float = 0.01, nbnd: int = 8) -> SystemDef:
+def make_cubic20(seed: int = 2205, soc: float = 0.01, nbnd: int = 8) -> SystemDef:
     """Oracle-sized cubic system: a = 10 bohr, 2 atoms, ~500 PW, 20^3 grid, Gamma.
 
     Seed 2205 is the first seed from 2203 upward whose SCF ground state has a
@@ -229,7 +229,7 @@ def make_cfg1(seed: int = 2205, soc: float = 0.01, nbnd: int = 8) -> SystemDef:
         atoms.append(Atom(pos=p, depth=depth, width=width, kinds=("px", "py"),
                           dscal=(d, d), soc=soc))
     ecut = 4.79
-    return SystemDef(name="cfg1", cell=cell, atoms=atoms, ecut=ecut, fft=(20, 20, 20),
+    return SystemDef(name="cubic20", cell=cell, atoms=atoms, ecut=ecut, fft=(20, 20, 20),
                      nbnd=nbnd, kmesh=np.zeros((1, 3)), seed=seed)
 
 
@@ -267,7 +267,7 @@ _CRI3_SITES = [
 ]
 
 
-def make_cfg2(seed: int = 2022, a: float = 13.0, c: float = 31.0, ecut: float = 11.09,
+def make_hexslab(seed: int = 2022, a: float = 13.0, c: float = 31.0, ecut: float = 11.09,
               fft=(48, 48, 180), nbnd: int = 104, nk: int = 6, soc: float = 0.02) -> SystemDef:
     """CrI3-monolayer-shaped hexagonal slab: 2 'Cr' + 6 'I', 6x6x1 Gamma-centred mesh."""
     rng = np.random.default_rng(seed)
@@ -286,7 +286,7 @@ def make_cfg2(seed: int = 2022, a: float = 13.0, c: float = 31.0, ecut: float = 
         atoms.append(Atom(pos=p, depth=depth, width=width, kinds=("s", "px", "py"),
                           dscal=tuple(d), soc=lam))
     km = np.array([[i / nk, j / nk, 0.0] for i in range(nk) for j in range(nk)])
-    return SystemDef(name="cfg2", cell=cell, atoms=atoms, ecut=ecut, fft=tuple(fft),
+    return SystemDef(name="hexslab", cell=cell, atoms=atoms, ecut=ecut, fft=tuple(fft),
                      nbnd=nbnd, kmesh=km, seed=seed, notes={"c": c, "vacuum": c - 6.0})
 
 

@@ -29,10 +29,10 @@ def tiny_gs_nosoc():
 
 
 @pytest.fixture(scope="session")
-def cfg1_gs():
+def cubic_gs():
     import synth
     from oracle import scf
-    return scf.scf(synth.make_cfg1(), tol=1e-10, beta=0.5)
+    return scf.scf(synth.make_cubic20(), tol=1e-10, beta=0.5)
 
 
 @pytest.fixture(scope="session")
@@ -41,5 +41,5 @@ def tiny_q():
 
 
 @pytest.fixture(scope="session")
-def cfg1_q():
+def cubic_q():
     return np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0

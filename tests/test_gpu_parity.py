@@ -63,15 +63,15 @@ def tiny(lib, tiny_gs, tiny_q):
 
 
 @pytest.fixture(scope="module")
-def cfg1(lib, cfg1_gs, cfg1_q):
-    say("create cfg1 system")
-    s = Sys(lib, lv.build_problem(cfg1_gs, cfg1_q))
+def cubic20(lib, cubic_gs, cubic_q):
+    say("create cubic20 system")
+    s = Sys(lib, lv.build_problem(cubic_gs, cubic_q))
     yield s
     s.close()
 
 
 @pytest.mark.parametrize("resident", [True, False], ids=["resident", "columns"])
-@pytest.mark.parametrize("which", ["tiny", "cfg1"])
+@pytest.mark.parametrize("which", ["tiny", "cubic20"])
 def test_apply_matches_oracle(which, resident, request):
     s = request.getfixturevalue(which)
     s.resident(resident)
@@ -137,38 +137,38 @@ def test_apply_two_kpoints_folded(lib):
         s.close()
 
 
-def test_apply_is_linear_and_orthogonal(cfg1):
-    say("apply linearity cfg1")
-    a = cfg1.prob.random_projected(3)
-    b = cfg1.prob.random_projected(4)
-    la, _ = cfg1.apply(a)
-    lb, _ = cfg1.apply(b)
-    lab, _ = cfg1.apply(a + (0.3 - 0.7j) * b)
+def test_apply_is_linear_and_orthogonal(cubic20):
+    say("apply linearity cubic20")
+    a = cubic20.prob.random_projected(3)
+    b = cubic20.prob.random_projected(4)
+    la, _ = cubic20.apply(a)
+    lb, _ = cubic20.apply(b)
+    lab, _ = cubic20.apply(a + (0.3 - 0.7j) * b)
     assert rel_err(lab, la + (0.3 - 0.7j) * lb) <= 1e-12
-    assert cfg1.prob.occupied_overlap(la) <= 1e-12 * np.abs(la).max()
+    assert cubic20.prob.occupied_overlap(la) <= 1e-12 * np.abs(la).max()
 
 
 @pytest.mark.parametrize("direction", ["x", "y", "z", "+", "-"])
-def test_start_vectors_match_oracle(cfg1, direction):
+def test_start_vectors_match_oracle(cubic20, direction):
     import torch
     say(f"start vectors {direction}")
-    n = cfg1.info["nelem"]
+    n = cubic20.info["nelem"]
     u = torch.empty(n, dtype=torch.complex128, device="cuda")
     v = torch.empty_like(u)
-    cfg1.tm.tm_start_vectors(cfg1.h, 0, direction, u, v)
+    cubic20.tm.tm_start_vectors(cubic20.h, 0, direction, u, v)
     torch.cuda.synchronize()
-    gu, _ = from_gpu(u, cfg1.shape, cfg1.prob.npw_pad)
-    gv, _ = from_gpu(v, cfg1.shape, cfg1.prob.npw_pad)
-    assert rel_err(gv, cfg1.prob.v_vector(direction)) <= 1e-12
+    gu, _ = from_gpu(u, cubic20.shape, cubic20.prob.npw_pad)
+    gv, _ = from_gpu(v, cubic20.shape, cubic20.prob.npw_pad)
+    assert rel_err(gv, cubic20.prob.v_vector(direction)) <= 1e-12
     if direction in "xyz":
-        assert rel_err(gu, cfg1.prob.u_vector(direction)) <= 1e-13
+        assert rel_err(gu, cubic20.prob.u_vector(direction)) <= 1e-13
 
 
 @pytest.mark.parametrize("flavour,mu,nsteps", [("pH", "+", 60), ("nH", "+", 20), ("pH", "z", 20)])
-def test_lanczos_coefficients_match_oracle(cfg1, flavour, mu, nsteps):
-    say(f"lanczos cfg1 {flavour} {mu} {nsteps}")
-    got = cfg1.tm.tm_lanczos_run(cfg1.h, 0, mu, flavour, nsteps)
-    ref = olanczos.run(cfg1.prob, mu, flavour, nsteps)
+def test_lanczos_coefficients_match_oracle(cubic20, flavour, mu, nsteps):
+    say(f"lanczos cubic20 {flavour} {mu} {nsteps}")
+    got = cubic20.tm.tm_lanczos_run(cubic20.h, 0, mu, flavour, nsteps)
+    ref = olanczos.run(cubic20.prob, mu, flavour, nsteps)
     assert got["steps_done"] == ref["steps_done"] == nsteps
     assert not got["breakdown"]
     assert abs(got["n1"] - ref["n1"]) <= 1e-12 * ref["n1"]
@@ -180,16 +180,16 @@ def test_lanczos_coefficients_match_oracle(cfg1, flavour, mu, nsteps):
     assert np.abs(got["z"] - ref["z"]).max() <= 1e-10 * zs
 
 
-def test_chi_matches_oracle(cfg1):
-    say("chi cfg1")
-    coeffs = cfg1.tm.tm_lanczos_run(cfg1.h, 0, "+", "pH", 60)
+def test_chi_matches_oracle(cubic20):
+    say("chi cubic20")
+    coeffs = cubic20.tm.tm_lanczos_run(cubic20.h, 0, "+", "pH", 60)
     omega = np.arange(400) * 5e-3 / 27.211386245988   # 0 .. 1.995 eV in Ha
     eta = 5e-3 / 27.211386245988
-    got = cfg1.tm.tm_chi(coeffs, 60, omega, eta)
+    got = cubic20.tm.tm_chi(coeffs, 60, omega, eta)
     ref = ochi.chi_lanczos(coeffs, omega, eta, 60)
     assert rel_err(got, ref) <= 1e-12
     # and against the chain run entirely by the oracle
-    oref = olanczos.run(cfg1.prob, "+", "pH", 60)
+    oref = olanczos.run(cubic20.prob, "+", "pH", 60)
     cref = ochi.chi_lanczos(oref, omega, eta, 60)
     assert rel_err(got, cref) <= 1e-9
 

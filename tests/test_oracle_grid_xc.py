@@ -37,7 +37,7 @@ def test_to_grid_is_direct_dft():
 
 
 def test_sphere_count_matches_volume_estimate():
-    sd = synth.make_cfg1()
+    sd = synth.make_cubic20()
     n = len(synth.sphere(sd, np.zeros(3)))
     est = sd.omega * (2 * sd.ecut) ** 1.5 / (6 * np.pi ** 2)
     assert abs(n - est) / est < 0.05

@@ -22,11 +22,11 @@ def tiny_ts(tiny_prob):
     return dense.TransitionSpace(tiny_prob)
 
 
-def test_scf_converged(tiny_gs, cfg1_gs):
+def test_scf_converged(tiny_gs, cubic_gs):
     assert tiny_gs.residual < 1e-12
-    assert cfg1_gs.residual < 1e-10
-    assert cfg1_gs.gaps[0] >= 0.02
-    assert np.linalg.norm(cfg1_gs.magnetization) >= 0.5
+    assert cubic_gs.residual < 1e-10
+    assert cubic_gs.gaps[0] >= 0.02
+    assert np.linalg.norm(cubic_gs.magnetization) >= 0.5
 
 
 def test_matrix_free_equals_transition_space(tiny_ts):
@@ -202,9 +202,9 @@ def test_chi_solvers_agree(tiny_prob):
     assert np.abs(c3[0] - res["n1"] * res["z"][0, 0] * cf).max() <= 1e-12 * np.abs(c3[0]).max()
 
 
-def test_cfg1_pseudo_hermitian_probe_and_chain(cfg1_gs, cfg1_q):
-    """cfg1: JL symmetric on random probes; a short pH chain runs without breakdown."""
-    prob = lv.build_problem(cfg1_gs, cfg1_q)
+def test_cubic20_pseudo_hermitian_probe_and_chain(cubic_gs, cubic_q):
+    """cubic20: JL symmetric on random probes; a short pH chain runs without breakdown."""
+    prob = lv.build_problem(cubic_gs, cubic_q)
     a, b = prob.random_projected(11), prob.random_projected(12)
     lhs = prob.dot(a, prob.J(prob.apply(b)))
     rhs = np.conj(prob.dot(b, prob.J(prob.apply(a))))
