@@ -201,6 +201,34 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
                    tm_precision prec, tm_coeffs* out);
 
 /*
+ * Chain-level interface (serving).  One chain = one recursion of Sec. 2.5 for
+ * (q set, direction, flavour), resident on the device; tm_lanczos_run is
+ * begin + steps + coeffs + end.
+ * tm_chain_begin: allocates the chain's vectors (pseudo-Hermitian: 5 BR
+ *   vectors, non-Hermitian: 9, plus the three u^lambda) and coefficient
+ *   storage for `capacity` steps, builds v^mu (as tm_start_vectors) and
+ *   starts the recursion (pseudo-Hermitian: one apply), asynchronously on
+ *   `stream` (a hipStream_t, NULL = default stream).  TM_ENOMEM when the
+ *   vectors do not fit.
+ * tm_chains_step: advances each of the n chains by up to k_steps steps (never
+ *   past its capacity), one step per chain in turn, all on `stream`;
+ *   asynchronous.  Chains may belong to different systems, but all work of
+ *   one system must be issued on one stream at a time (its chains share the
+ *   system's apply workspace).  The step index and the breakdown flag live on
+ *   the device: after a breakdown the chain's coefficients stop changing.
+ * tm_chain_coeffs: waits for the chain's last stream, copies the first
+ *   min(capacity, out->capacity) coefficients, steps_done and n1 into `out`
+ *   (layout of tm_coeffs); TM_EBREAKDOWN when the chain has broken down.
+ * tm_chain_end: waits for the chain's last stream and frees it (NULL allowed).
+ */
+typedef struct tm_chain tm_chain;
+int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity,
+                   void* stream, tm_chain** out);
+int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream);
+int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out);
+int tm_chain_end(tm_chain* chain);
+
+/*
  * tm_chi: chi_l(omega_j) = n1 sum_i z[l][i] eta_i with
  *   ((omega_j + i eta) I - T) eta = e_1            (Eq. post_processing)
  * over the first m_use steps (m_use <= c->steps_done), l = x, y, z.

@@ -24,7 +24,8 @@ DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4}
 FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
-            "tm_system_resident_bytes", "tm_liouvillian_apply",
+            "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step",
+            "tm_chain_coeffs", "tm_chain_end",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -74,6 +75,11 @@ def load(path: str = LIB_PATH):
     lib.tm_system_destroy.argtypes = [C.c_void_p]
     lib.tm_qset_info_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(_QInfo)]
     lib.tm_system_set_resident_limit.argtypes = [C.c_void_p, C.c_longlong]
+    lib.tm_chain_begin.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                                   C.POINTER(C.c_void_p)]
+    lib.tm_chains_step.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p]
+    lib.tm_chain_coeffs.argtypes = [C.c_void_p, C.POINTER(_Coeffs)]
+    lib.tm_chain_end.argtypes = [C.c_void_p]
     lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -256,6 +262,42 @@ def tm_lanczos_run(h, iq: int, direction: str, flavour: str, nsteps: int, prec: 
                                       C.byref(co)), allow=(TM_EBREAKDOWN,))
     return dict(alpha=alpha, beta=beta, gamma=gamma, z=z, n1=co.n1, steps_done=co.steps_done,
                 breakdown=rc == TM_EBREAKDOWN)
+
+
+def _coeff_arrays(cap: int):
+    alpha = np.zeros(cap, dtype=np.complex128)
+    beta = np.zeros(cap)
+    gamma = np.zeros(cap, dtype=np.complex128)
+    z = np.zeros((3, cap), dtype=np.complex128)
+    co = _Coeffs(cap, 0, 0.0, alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
+                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
+    return co, dict(alpha=alpha, beta=beta, gamma=gamma, z=z)
+
+
+def tm_chain_begin(h, iq: int, direction: str, flavour: str, capacity: int, prec: int = TM_FP64,
+                   stream=None) -> int:
+    """Start a device-resident chain; returns its handle (asynchronous on `stream`)."""
+    out = C.c_void_p()
+    _check(load().tm_chain_begin(C.c_void_p(h), iq, DIRS[direction], FLAVOURS[flavour], prec, int(capacity),
+                                 _stream(stream), C.byref(out)))
+    return out.value
+
+
+def tm_chains_step(chains, k_steps: int, stream=None) -> None:
+    """Advance every chain by up to k_steps steps, one step per chain in turn."""
+    arr = (C.c_void_p * max(len(chains), 1))(*chains)
+    _check(load().tm_chains_step(arr, len(chains), int(k_steps), _stream(stream)))
+
+
+def tm_chain_coeffs(chain, capacity: int) -> dict:
+    """Coefficients of a chain so far (waits for its stream)."""
+    co, arrs = _coeff_arrays(int(capacity))
+    rc = _check(load().tm_chain_coeffs(C.c_void_p(chain), C.byref(co)), allow=(TM_EBREAKDOWN,))
+    return dict(arrs, n1=co.n1, steps_done=co.steps_done, breakdown=rc == TM_EBREAKDOWN)
+
+
+def tm_chain_end(chain) -> None:
+    _check(load().tm_chain_end(C.c_void_p(chain)))
 
 
 def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:

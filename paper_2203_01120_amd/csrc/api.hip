@@ -552,133 +552,191 @@ void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream
     if (v) launch_project_signed(s, q, v, 1.0, 1.0, st);
 }
 
-static int run_chain(System& s, int iq, int dir, int flavour, int nsteps, tm_coeffs* out, hipStream_t st) {
-    QSet& q = s.qs[iq];
-    ensure_workspace(s, q);
-    const long long n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
-    const long long half = n / 2;
-    const double w = 1.0 / q.nk;
-    const int nvec = flavour == TM_PSEUDOHERMITIAN ? 5 : 9;
-    std::vector<double2*> vec(nvec + 3, nullptr);
-    struct Guard {
-        std::vector<void*> p;
-        ~Guard() {
-            for (void* x : p) (void)hipFree(x);
-        }
-    } guard;
-    auto galloc = [&](size_t bytes) {
+// One Lanczos chain (Sec. 2.5) resident on the device: its vectors, the
+// three u^lambda, the coefficient arrays and the scale/step state.  Steps are
+// issued asynchronously; the step index and the breakdown flag live on the
+// device, so a chain never returns to the host until its coefficients are read.
+struct Chain {
+    System* s = nullptr;
+    int iq = 0, dir = 0, flavour = 0, cap = 0;
+    long long n = 0, half = 0;
+    double w = 1.0;
+    std::vector<double2*> vec;  // work vectors (5 pH, 9 nH)
+    int ix[9] = {0, 1, 2, 3, 4, 5, 6, 7, 8};  // current role -> vector
+    double2* u[3] = {nullptr, nullptr, nullptr};
+    Coeffs co{};
+    ChainState* cs = nullptr;
+    double2* dots = nullptr;   // [16] reduced inner products
+    double2* part = nullptr;   // per-block partial sums
+    int issued = 0;            // steps issued so far
+    int broken_seen = 0;       // breakdown observed on the host
+    hipStream_t last = nullptr;
+    std::vector<void*> mem;
+
+    void* alloc(size_t bytes) {
         void* p = nullptr;
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) throw Error{TM_ENOMEM, "hipMalloc failed for Lanczos vectors"};
-        guard.p.push_back(p);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{TM_ENOMEM, "hipMalloc failed for a Lanczos chain"};
+        }
+        mem.push_back(p);
         return p;
-    };
-    for (auto& p : vec) p = static_cast<double2*>(galloc(n * sizeof(double2)));
-    const int cap = nsteps;
-    Coeffs co;
-    co.cap = cap;
-    co.alpha = static_cast<double2*>(galloc(cap * sizeof(double2)));
-    co.beta = static_cast<double*>(galloc(cap * sizeof(double)));
-    co.gamma = static_cast<double2*>(galloc(cap * sizeof(double2)));
-    co.z = static_cast<double2*>(galloc(3 * cap * sizeof(double2)));
-    TM_HIP(hipMemsetAsync(co.alpha, 0, cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(co.beta, 0, cap * sizeof(double), st));
-    TM_HIP(hipMemsetAsync(co.gamma, 0, cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(co.z, 0, 3 * cap * sizeof(double2), st));
-    ChainState* cs = static_cast<ChainState*>(galloc(sizeof(ChainState)));
+    }
+    ~Chain() {
+        if (!mem.empty()) (void)hipStreamSynchronize(last);
+        for (void* p : mem) (void)hipFree(p);
+    }
+    double2* V(int role) const { return vec[ix[role]]; }
+};
+
+static void chain_begin(Chain& c, hipStream_t st) {
+    System& s = *c.s;
+    QSet& q = s.qs[c.iq];
+    ensure_workspace(s, q);
+    c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
+    c.half = c.n / 2;
+    c.w = 1.0 / q.nk;
+    const int nvec = c.flavour == TM_PSEUDOHERMITIAN ? 5 : 9;
+    for (int i = 0; i < nvec; ++i) c.vec.push_back(static_cast<double2*>(c.alloc(c.n * sizeof(double2))));
+    for (int l = 0; l < 3; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
+    const int cap = c.cap;
+    c.co.cap = cap;
+    c.co.alpha = static_cast<double2*>(c.alloc(cap * sizeof(double2)));
+    c.co.beta = static_cast<double*>(c.alloc(cap * sizeof(double)));
+    c.co.gamma = static_cast<double2*>(c.alloc(cap * sizeof(double2)));
+    c.co.z = static_cast<double2*>(c.alloc(3 * cap * sizeof(double2)));
+    c.cs = static_cast<ChainState*>(c.alloc(sizeof(ChainState)));
+    c.dots = static_cast<double2*>(c.alloc(16 * sizeof(double2)));
+    c.part = static_cast<double2*>(c.alloc(1024 * 8 * sizeof(double2)));
+    c.last = st;
+    TM_HIP(hipMemsetAsync(c.co.alpha, 0, cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.beta, 0, cap * sizeof(double), st));
+    TM_HIP(hipMemsetAsync(c.co.gamma, 0, cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.z, 0, 3 * cap * sizeof(double2), st));
     ChainState h{};
     h.lam = q.lam;
-    TM_HIP(hipMemcpyAsync(cs, &h, sizeof(h), hipMemcpyHostToDevice, st));
-    double2* u[3] = {vec[nvec], vec[nvec + 1], vec[nvec + 2]};
-    for (int l = 0; l < 3; ++l) start_vectors(s, iq, l, u[l], nullptr, st);
-    double2* d = s.ws.dots;
-    double2* part = s.ws.dotpart;
-    const double2* uc[3] = {u[0], u[1], u[2]};
-    if (flavour == TM_PSEUDOHERMITIAN) {
-        double2 *QP = vec[0], *Q = vec[1], *LQ = vec[2], *R = vec[3], *LR = vec[4];
-        TM_HIP(hipMemsetAsync(QP, 0, n * sizeof(double2), st));
-        start_vectors(s, iq, dir, nullptr, Q, st);
-        apply_fp64(s, iq, Q, LQ, st);
-        DotSet<6> ds0{{Q, Q, LQ, u[0], u[1], u[2]}, {LQ, Q, LQ, Q, Q, Q}, {1, 0, 1, 0, 0, 0}};
-        run_multidot<6>(ds0, n, half, w, part, d, st);
-        ctl_ph_start(cs, d, co, st);
-        for (int j = 0; j < nsteps; ++j) {
-            run_ph_update(cs, LQ, Q, QP, R, uc, n, w, part, d + 8, st);
-            apply_fp64(s, iq, R, LR, st);
-            DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}};
-            run_multidot<3>(ds, n, half, w, part, d, st);
-            ctl_ph_step(cs, d, d + 8, co, j, nsteps, st);
-            // rotate: q_prev <- q, q <- r, Lq <- Lr
-            double2 *oQP = QP, *oLQ = LQ;
-            QP = Q;
-            Q = R;
-            LQ = LR;
-            R = oQP;
-            LR = oLQ;
-            if ((j & 63) == 63) {
-                int br = 0;
-                TM_HIP(hipMemcpyAsync(&br, &cs->broken, sizeof(int), hipMemcpyDeviceToHost, st));
-                TM_HIP(hipStreamSynchronize(st));
-                if (br) break;
-            }
-        }
+    TM_HIP(hipMemcpyAsync(c.cs, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    for (int l = 0; l < 3; ++l) start_vectors(s, c.iq, l, c.u[l], nullptr, st);
+    const long long n = c.n, half = c.half;
+    double2* d = c.dots;
+    if (c.flavour == TM_PSEUDOHERMITIAN) {
+        // roles: 0 q_prev, 1 q, 2 Lq, 3 r, 4 Lr
+        TM_HIP(hipMemsetAsync(c.V(0), 0, n * sizeof(double2), st));
+        start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
+        apply_fp64(s, c.iq, c.V(1), c.V(2), st);
+        DotSet<6> ds0{{c.V(1), c.V(1), c.V(2), c.u[0], c.u[1], c.u[2]},
+                      {c.V(2), c.V(1), c.V(2), c.V(1), c.V(1), c.V(1)},
+                      {1, 0, 1, 0, 0, 0}};
+        run_multidot<6>(ds0, n, half, c.w, c.part, d, st);
+        ctl_ph_start(c.cs, d, c.co, st);
     } else {
-        double2 *QP = vec[0], *Q = vec[1], *PP = vec[2], *Pv = vec[3], *LQ = vec[4], *LTP = vec[5], *TMP = vec[6],
-                *QH = vec[7], *PH = vec[8];
-        TM_HIP(hipMemsetAsync(QP, 0, n * sizeof(double2), st));
-        TM_HIP(hipMemsetAsync(PP, 0, n * sizeof(double2), st));
-        start_vectors(s, iq, dir, nullptr, Q, st);
-        TM_HIP(hipMemcpyAsync(Pv, Q, n * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        DotSet<4> ds0{{Q, u[0], u[1], u[2]}, {Q, Q, Q, Q}, {0, 0, 0, 0}};
-        run_multidot<4>(ds0, n, half, w, part, d, st);
-        ctl_nh_start(cs, d, co, st);
-        for (int j = 0; j < nsteps; ++j) {
-            apply_fp64(s, iq, Q, LQ, st);
-            run_jcopy(Pv, TMP, n, half, st);
-            apply_fp64(s, iq, TMP, LTP, st);
-            DotSet<1> da{{Pv}, {LQ}, {0}};
-            run_multidot<1>(da, n, half, w, part, d, st);
-            ctl_nh_alpha(cs, d, co, j, st);
-            run_nh_update(cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, w, part, d + 8, st);
-            ctl_nh_step(cs, d + 8, co, j, nsteps, st);
-            double2 *oQP = QP, *oPP = PP;
-            QP = Q;
-            Q = QH;
-            PP = Pv;
-            Pv = PH;
-            QH = oQP;
-            PH = oPP;
-            if ((j & 63) == 63) {
-                int br = 0;
-                TM_HIP(hipMemcpyAsync(&br, &cs->broken, sizeof(int), hipMemcpyDeviceToHost, st));
-                TM_HIP(hipStreamSynchronize(st));
-                if (br) break;
-            }
-        }
+        // roles: 0 q_prev, 1 q, 2 p_prev, 3 p, 4 Lq, 5 L^dag p, 6 J p, 7 q^, 8 p^
+        TM_HIP(hipMemsetAsync(c.V(0), 0, n * sizeof(double2), st));
+        TM_HIP(hipMemsetAsync(c.V(2), 0, n * sizeof(double2), st));
+        start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
+        TM_HIP(hipMemcpyAsync(c.V(3), c.V(1), n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        DotSet<4> ds0{{c.V(1), c.u[0], c.u[1], c.u[2]}, {c.V(1), c.V(1), c.V(1), c.V(1)}, {0, 0, 0, 0}};
+        run_multidot<4>(ds0, n, half, c.w, c.part, d, st);
+        ctl_nh_start(c.cs, d, c.co, st);
     }
-    TM_HIP(hipMemcpyAsync(&h, cs, sizeof(h), hipMemcpyDeviceToHost, st));
-    TM_HIP(hipStreamSynchronize(st));
-    std::vector<double2> ha(cap), hg(cap), hz(3 * cap);
+}
+
+// one step of the chain on stream st
+static void chain_step(Chain& c, hipStream_t st) {
+    System& s = *c.s;
+    const long long n = c.n, half = c.half;
+    double2* d = c.dots;
+    const double2* uc[3] = {c.u[0], c.u[1], c.u[2]};
+    if (c.flavour == TM_PSEUDOHERMITIAN) {
+        double2 *QP = c.V(0), *Q = c.V(1), *LQ = c.V(2), *R = c.V(3), *LR = c.V(4);
+        run_ph_update(c.cs, LQ, Q, QP, R, uc, n, c.w, c.part, d + 8, st);
+        apply_fp64(s, c.iq, R, LR, st);
+        DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}};
+        run_multidot<3>(ds, n, half, c.w, c.part, d, st);
+        ctl_ph_step(c.cs, d, d + 8, c.co, st);
+        // q_prev <- q, q <- r, Lq <- Lr; the old q_prev and Lq become scratch
+        const int oqp = c.ix[0], olq = c.ix[2];
+        c.ix[0] = c.ix[1];
+        c.ix[1] = c.ix[3];
+        c.ix[2] = c.ix[4];
+        c.ix[3] = oqp;
+        c.ix[4] = olq;
+    } else {
+        double2 *QP = c.V(0), *Q = c.V(1), *PP = c.V(2), *Pv = c.V(3), *LQ = c.V(4), *LTP = c.V(5),
+                *TMP = c.V(6), *QH = c.V(7), *PH = c.V(8);
+        apply_fp64(s, c.iq, Q, LQ, st);
+        run_jcopy(Pv, TMP, n, half, st);
+        apply_fp64(s, c.iq, TMP, LTP, st);
+        DotSet<1> da{{Pv}, {LQ}, {0}};
+        run_multidot<1>(da, n, half, c.w, c.part, d, st);
+        ctl_nh_alpha(c.cs, d, c.co, st);
+        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, c.w, c.part, d + 8, st);
+        ctl_nh_step(c.cs, d + 8, c.co, st);
+        // q_prev <- q, q <- q^, p_prev <- p, p <- p^
+        const int oqp = c.ix[0], opp = c.ix[2];
+        c.ix[0] = c.ix[1];
+        c.ix[1] = c.ix[7];
+        c.ix[2] = c.ix[3];
+        c.ix[3] = c.ix[8];
+        c.ix[7] = oqp;
+        c.ix[8] = opp;
+    }
+    ++c.issued;
+    c.last = st;
+}
+
+// reads the device state; returns 1 if the chain has broken down
+static int chain_poll(Chain& c) {
+    ChainState h{};
+    TM_HIP(hipMemcpyAsync(&h, c.cs, sizeof(h), hipMemcpyDeviceToHost, c.last));
+    TM_HIP(hipStreamSynchronize(c.last));
+    c.broken_seen = h.broken;
+    return h.broken;
+}
+
+static int chain_coeffs(Chain& c, tm_coeffs* out) {
+    ChainState h{};
+    TM_HIP(hipMemcpyAsync(&h, c.cs, sizeof(h), hipMemcpyDeviceToHost, c.last));
+    TM_HIP(hipStreamSynchronize(c.last));
+    c.broken_seen = h.broken;
+    const int cap = c.cap;
+    std::vector<double2> ha(cap), hg(cap), hz(3 * (size_t)cap);
     std::vector<double> hb(cap);
-    TM_HIP(hipMemcpy(ha.data(), co.alpha, cap * sizeof(double2), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hb.data(), co.beta, cap * sizeof(double), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hg.data(), co.gamma, cap * sizeof(double2), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hz.data(), co.z, 3 * cap * sizeof(double2), hipMemcpyDeviceToHost));
-    const int done = h.step;
-    out->steps_done = done;
+    TM_HIP(hipMemcpy(ha.data(), c.co.alpha, cap * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hb.data(), c.co.beta, cap * sizeof(double), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hg.data(), c.co.gamma, cap * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hz.data(), c.co.z, 3 * cap * sizeof(double2), hipMemcpyDeviceToHost));
+    out->steps_done = h.step;
     out->n1 = h.n1;
-    for (int j = 0; j < nsteps; ++j) {
+    const int m = std::min(cap, out->capacity);
+    for (int j = 0; j < m; ++j) {
         out->alpha[2 * j] = ha[j].x;
         out->alpha[2 * j + 1] = ha[j].y;
         out->beta[j] = hb[j];
         out->gamma[2 * j] = hg[j].x;
         out->gamma[2 * j + 1] = hg[j].y;
         for (int l = 0; l < 3; ++l) {
-            out->z[2 * ((size_t)l * out->capacity + j)] = hz[l * cap + j].x;
-            out->z[2 * ((size_t)l * out->capacity + j) + 1] = hz[l * cap + j].y;
+            out->z[2 * ((size_t)l * out->capacity + j)] = hz[l * (size_t)cap + j].x;
+            out->z[2 * ((size_t)l * out->capacity + j) + 1] = hz[l * (size_t)cap + j].y;
         }
     }
     return h.broken ? TM_EBREAKDOWN : TM_OK;
+}
+
+static int run_chain(System& s, int iq, int dir, int flavour, int nsteps, tm_coeffs* out, hipStream_t st) {
+    Chain c;
+    c.s = &s;
+    c.iq = iq;
+    c.dir = dir;
+    c.flavour = flavour;
+    c.cap = nsteps;
+    chain_begin(c, st);
+    while (c.issued < nsteps) {
+        const int k = std::min(64, nsteps - c.issued);
+        for (int i = 0; i < k; ++i) chain_step(c, st);
+        if (c.issued < nsteps && chain_poll(c)) break;
+    }
+    return chain_coeffs(c, out);
 }
 
 }  // namespace tml
@@ -687,6 +745,10 @@ using namespace tml;
 
 struct tm_system {
     System s;
+};
+
+struct tm_chain {
+    Chain c;
 };
 
 template <typename F>
@@ -928,6 +990,69 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
         int rc = run_chain(s, iq, (int)dir, (int)f, nsteps, out, nullptr);
         if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
         return rc;
+    });
+}
+
+int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity, void* stream,
+                   tm_chain** out) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && out, TM_EINVAL, "null argument");
+        *out = nullptr;
+        System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+        TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
+        TM_CHECK(capacity >= 1, TM_EINVAL, "capacity must be >= 1");
+        TM_CHECK(prec == TM_FP64, TM_EUNSUPPORTED, "only TM_FP64 is implemented");
+        std::unique_ptr<tm_chain> h(new tm_chain());
+        Chain& c = h->c;
+        c.s = &s;
+        c.iq = iq;
+        c.dir = (int)dir;
+        c.flavour = (int)f;
+        c.cap = capacity;
+        chain_begin(c, static_cast<hipStream_t>(stream));
+        *out = h.release();
+        return TM_OK;
+    });
+}
+
+int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream) {
+    return guarded([&]() -> int {
+        TM_CHECK(n >= 0 && k_steps >= 0, TM_EINVAL, "negative count");
+        TM_CHECK(n == 0 || chains, TM_EINVAL, "null chain array");
+        for (int i = 0; i < n; ++i) TM_CHECK(chains[i] != nullptr, TM_EINVAL, "null chain");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (int k = 0; k < k_steps; ++k) {
+            bool any = false;
+            for (int i = 0; i < n; ++i) {
+                Chain& c = chains[i]->c;
+                if (c.issued >= c.cap || c.broken_seen) continue;
+                chain_step(c, st);
+                any = true;
+            }
+            if (!any) break;
+        }
+        return TM_OK;
+    });
+}
+
+int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out) {
+    return guarded([&]() -> int {
+        TM_CHECK(chain && out, TM_EINVAL, "null argument");
+        TM_CHECK(out->capacity >= 1 && out->alpha && out->beta && out->gamma && out->z, TM_EINVAL,
+                 "bad coefficient arrays");
+        int rc = chain_coeffs(chain->c, out);
+        if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
+        return rc;
+    });
+}
+
+int tm_chain_end(tm_chain* chain) {
+    if (!chain) return TM_OK;
+    return guarded([&]() -> int {
+        delete chain;
+        return TM_OK;
     });
 }
 

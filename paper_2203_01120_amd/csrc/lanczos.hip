@@ -186,8 +186,9 @@ __global__ void k_ph_start(ChainState* cs, const double2* d, Coeffs co) {
 }
 
 // pH after the apply; d: (r, J Lr), (r, r), (Lr, J Lr); zu: (u_l, r)
-__global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, Coeffs co, int j, int nsteps) {
-    if (cs->broken) return;
+__global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, Coeffs co) {
+    const int j = cs->step;
+    if (cs->broken || j >= co.cap) return;
     const double b2 = d[0].x, rr = d[1].x, ll = d[2].x;
     const double lam = cs->lam, eps = kBreakdownTol;
     cs->step = j + 1;
@@ -203,7 +204,7 @@ __global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, C
     cs->beta_prev = b;
     cs->alpha = cmk(ll / b2, 0.0);
     cs->qq = rr / b2;
-    if (j + 1 < nsteps) {
+    if (j + 1 < co.cap) {
         co.alpha[j + 1] = cs->alpha;
         for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cscale(zu[l], 1.0 / b);
     }
@@ -230,15 +231,17 @@ __global__ void k_nh_start(ChainState* cs, const double2* d, Coeffs co) {
 }
 
 // nH alpha from (P_raw, LQ_raw)
-__global__ void k_nh_alpha(ChainState* cs, const double2* d, Coeffs co, int j) {
-    if (cs->broken) return;
+__global__ void k_nh_alpha(ChainState* cs, const double2* d, Coeffs co) {
+    const int j = cs->step;
+    if (cs->broken || j >= co.cap) return;
     cs->alpha = cmul(cmul(cconj(cs->sp), cs->sq), d[0]);
     co.alpha[j] = cs->alpha;
 }
 
 // nH after the update; d: (ph, qh), (qh, qh), (ph, ph), (u_l, qh)
-__global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co, int j, int nsteps) {
-    if (cs->broken) return;
+__global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
+    const int j = cs->step;
+    if (cs->broken || j >= co.cap) return;
     const double2 s = d[0];
     const double qq = d[1].x, pp = d[2].x;
     const double lam = cs->lam, eps = kBreakdownTol;
@@ -262,7 +265,7 @@ __global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co, int j, in
     cs->pp = pp / gg;
     cs->beta_prev = b;
     cs->gamma_prev = g;
-    if (j + 1 < nsteps)
+    if (j + 1 < co.cap)
         for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cscale(d[3 + l], 1.0 / b);
 }
 
@@ -309,18 +312,17 @@ void run_jcopy(const double2* src, double2* dst, long long n, long long half, hi
 void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
     TM_LAUNCH(k_ph_start, dim3(1), dim3(1), 0, st, cs, d, co);
 }
-void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, int j, int nsteps,
-                 hipStream_t st) {
-    TM_LAUNCH(k_ph_step, dim3(1), dim3(1), 0, st, cs, d, zu, co, j, nsteps);
+void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st) {
+    TM_LAUNCH(k_ph_step, dim3(1), dim3(1), 0, st, cs, d, zu, co);
 }
 void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
     TM_LAUNCH(k_nh_start, dim3(1), dim3(1), 0, st, cs, d, co);
 }
-void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, int j, hipStream_t st) {
-    TM_LAUNCH(k_nh_alpha, dim3(1), dim3(1), 0, st, cs, d, co, j);
+void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
+    TM_LAUNCH(k_nh_alpha, dim3(1), dim3(1), 0, st, cs, d, co);
 }
-void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, int j, int nsteps, hipStream_t st) {
-    TM_LAUNCH(k_nh_step, dim3(1), dim3(1), 0, st, cs, d, co, j, nsteps);
+void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
+    TM_LAUNCH(k_nh_step, dim3(1), dim3(1), 0, st, cs, d, co);
 }
 
 }  // namespace tml

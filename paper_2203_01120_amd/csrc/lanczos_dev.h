@@ -47,10 +47,11 @@ void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, co
                    long long n, long long half, double w, double2* part, double2* out, hipStream_t st);
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st);
 void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
-void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, int j, int nsteps,
-                 hipStream_t st);
+// the step index comes from cs->step (device side), so step sequences can be
+// replayed from a graph; steps past co.cap are ignored
+void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st);
 void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
-void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, int j, hipStream_t st);
-void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, int j, int nsteps, hipStream_t st);
+void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
+void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
 
 }  // namespace tml

@@ -1,0 +1,110 @@
+"""Chain-level interface (tm_chain_*) through the C ABI (needs an MI355X).
+
+A chain stepped in pieces, or interleaved with other chains on one stream,
+runs the same kernels on the same data as tm_lanczos_run, so its
+coefficients agree bit for bit; against the oracle the tolerance is the one
+of the Lanczos parity tests (1e-10 relative).
+"""
+import numpy as np
+import pytest
+
+from oracle import lanczos as olanczos
+from oracle import liouvillian as lv
+
+from gpu_util import desc_from_problem, say
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("alpha", "beta", "gamma", "z")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    import paper_2203_01120_amd as tm
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    tm.load()
+    return tm
+
+
+@pytest.fixture(scope="module")
+def systems(lib, tiny_gs, tiny_q, cubic_gs, cubic_q):
+    say("create tiny and cubic20 systems")
+    out = {}
+    for name, gs, q in (("tiny", tiny_gs, tiny_q), ("cubic20", cubic_gs, cubic_q)):
+        prob = lv.build_problem(gs, q)
+        out[name] = (prob, lib.tm_system_create(desc_from_problem(prob)))
+    yield out
+    for _, h in out.values():
+        lib.tm_system_destroy(h)
+
+
+def same(a, b):
+    for k in KEYS:
+        assert np.array_equal(a[k], b[k]), k
+    assert a["steps_done"] == b["steps_done"] and a["n1"] == b["n1"]
+
+
+def test_chain_in_pieces_equals_lanczos_run(lib, systems):
+    prob, h = systems["cubic20"]
+    for flavour, mu, pieces in (("pH", "+", (7, 13, 40)), ("nH", "z", (1, 5, 14))):
+        say(f"chain in pieces cubic20 {flavour} {mu} {pieces}")
+        m = sum(pieces)
+        ref = lib.tm_lanczos_run(h, 0, mu, flavour, m)
+        c = lib.tm_chain_begin(h, 0, mu, flavour, m)
+        try:
+            for k in pieces:
+                lib.tm_chains_step([c], k)
+            got = lib.tm_chain_coeffs(c, m)
+        finally:
+            lib.tm_chain_end(c)
+        same(got, ref)
+        oref = olanczos.run(prob, mu, flavour, m)
+        assert np.abs(got["beta"] - oref["beta"]).max() <= 1e-10 * oref["beta"].max()
+
+
+def test_interleaved_chains_match_alone(lib, systems):
+    """Chains of two systems and two chains of one system, stepped in turn."""
+    pt, ht = systems["tiny"]
+    pc, hc = systems["cubic20"]
+    specs = [(ht, "z", "pH", 20), (hc, "+", "pH", 30), (hc, "-", "nH", 12), (ht, "x", "nH", 9)]
+    alone = [lib.tm_lanczos_run(h, 0, mu, f, m) for h, mu, f, m in specs]
+    say("interleaved chains")
+    chains = [lib.tm_chain_begin(h, 0, mu, f, m) for h, mu, f, m in specs]
+    try:
+        lib.tm_chains_step(chains, 4)
+        lib.tm_chains_step(chains[1:], 3)
+        lib.tm_chains_step(chains, 100)   # capped at each chain's capacity
+        got = [lib.tm_chain_coeffs(c, m) for c, (_, _, _, m) in zip(chains, specs)]
+    finally:
+        for c in chains:
+            lib.tm_chain_end(c)
+    for g, a, (_, _, _, m) in zip(got, alone, specs):
+        assert g["steps_done"] == m
+        same(g, a)
+
+
+def test_chain_breakdown(lib, tiny_gs_nosoc):
+    prob = lv.build_problem(tiny_gs_nosoc, np.zeros(3))
+    h = lib.tm_system_create(desc_from_problem(prob))
+    try:
+        say("chain breakdown (Goldstone mode)")
+        c = lib.tm_chain_begin(h, 0, "x", "nH", 6)
+        try:
+            lib.tm_chains_step([c], 6)
+            r = lib.tm_chain_coeffs(c, 6)
+        finally:
+            lib.tm_chain_end(c)
+        assert r["breakdown"] and r["steps_done"] == 1
+    finally:
+        lib.tm_system_destroy(h)
+
+
+def test_chain_invalid_arguments(lib, systems):
+    _, h = systems["tiny"]
+    with pytest.raises(lib.TmError):
+        lib.tm_chain_begin(h, 0, "x", "pH", 0)
+    with pytest.raises(lib.TmError):
+        lib.tm_chain_begin(h, 3, "x", "pH", 5)
+    with pytest.raises(lib.TmError):
+        lib.tm_chain_begin(h, 0, "x", "pH", 5, prec=lib.TM_FP32)
