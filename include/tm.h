@@ -222,6 +222,11 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
  * tm_chain_end: waits for the chain's last stream and frees it (NULL allowed).
  */
 typedef struct tm_chain tm_chain;
+/* Steps are replayed from a captured HIP graph of one period of steps (6
+ * pseudo-Hermitian, 3 non-Hermitian) when possible; tm_chains_use_graphs(0)
+ * issues every kernel directly (process-wide switch, default on; the kernel
+ * profiler also issues directly).  Both give identical coefficients. */
+int tm_chains_use_graphs(int on);
 int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity,
                    void* stream, tm_chain** out);
 int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream);

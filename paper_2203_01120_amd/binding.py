@@ -24,7 +24,7 @@ DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4}
 FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
-            "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step",
+            "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
@@ -80,6 +80,7 @@ def load(path: str = LIB_PATH):
     lib.tm_chains_step.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p]
     lib.tm_chain_coeffs.argtypes = [C.c_void_p, C.POINTER(_Coeffs)]
     lib.tm_chain_end.argtypes = [C.c_void_p]
+    lib.tm_chains_use_graphs.argtypes = [C.c_int]
     lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -294,6 +295,11 @@ def tm_chain_coeffs(chain, capacity: int) -> dict:
     co, arrs = _coeff_arrays(int(capacity))
     rc = _check(load().tm_chain_coeffs(C.c_void_p(chain), C.byref(co)), allow=(TM_EBREAKDOWN,))
     return dict(arrs, n1=co.n1, steps_done=co.steps_done, breakdown=rc == TM_EBREAKDOWN)
+
+
+def tm_chains_use_graphs(on: bool) -> None:
+    """Process-wide: replay chain steps from captured HIP graphs (default) or issue them directly."""
+    _check(load().tm_chains_use_graphs(1 if on else 0))
 
 
 def tm_chain_end(chain) -> None:

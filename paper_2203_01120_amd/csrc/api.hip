@@ -571,6 +571,7 @@ struct Chain {
     int issued = 0;            // steps issued so far
     int broken_seen = 0;       // breakdown observed on the host
     hipStream_t last = nullptr;
+    hipGraphExec_t gexec = nullptr;  // one period of steps, captured
     std::vector<void*> mem;
 
     void* alloc(size_t bytes) {
@@ -584,8 +585,11 @@ struct Chain {
     }
     ~Chain() {
         if (!mem.empty()) (void)hipStreamSynchronize(last);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
         for (void* p : mem) (void)hipFree(p);
     }
+    // steps after which the vector roles return to their initial assignment
+    int period() const { return flavour == TM_PSEUDOHERMITIAN ? 6 : 3; }
     double2* V(int role) const { return vec[ix[role]]; }
 };
 
@@ -593,6 +597,7 @@ static void chain_begin(Chain& c, hipStream_t st) {
     System& s = *c.s;
     QSet& q = s.qs[c.iq];
     ensure_workspace(s, q);
+    ensure_ground(s, q, st);  // before any step, so steps never allocate or synchronise
     c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
     c.half = c.n / 2;
     c.w = 1.0 / q.nk;
@@ -681,7 +686,57 @@ static void chain_step(Chain& c, hipStream_t st) {
         c.ix[7] = oqp;
         c.ix[8] = opp;
     }
-    ++c.issued;
+}
+
+// Graph replay of a period of steps.  Small systems spend most of a step in
+// launch gaps (about 25 kernels per step); a captured period replays with the
+// gaps of a graph.  The step index and the breakdown flag are device state, so
+// the replayed kernels need no new arguments; the capture stream is private to
+// the system and the replay goes to the caller's stream.
+bool g_use_graphs = true;
+
+static void chain_capture(Chain& c) {
+    System& s = *c.s;
+    if (!s.cap_stream) TM_HIP(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
+    int saved[9];
+    std::copy(c.ix, c.ix + 9, saved);
+    hipGraph_t g = nullptr;
+    TM_HIP(hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeRelaxed));
+    try {
+        for (int i = 0; i < c.period(); ++i) chain_step(c, s.cap_stream);
+    } catch (...) {
+        (void)hipStreamEndCapture(s.cap_stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        std::copy(saved, saved + 9, c.ix);
+        throw;
+    }
+    TM_HIP(hipStreamEndCapture(s.cap_stream, &g));
+    TM_CHECK(std::equal(saved, saved + 9, c.ix), TM_EDEVICE, "vector roles did not return after a period");
+    hipError_t e = hipGraphInstantiate(&c.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        c.gexec = nullptr;
+        throw Error{TM_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e)};
+    }
+}
+
+// up to k steps of one chain (never past its capacity)
+static void chain_steps(Chain& c, int k, hipStream_t st) {
+    k = std::min(k, c.cap - c.issued);
+    const int P = c.period();
+    while (k > 0) {
+        if (g_use_graphs && !g_prof_on && c.issued % P == 0 && k >= P) {
+            if (!c.gexec) chain_capture(c);
+            const int r = k / P;
+            for (int i = 0; i < r; ++i) TM_HIP(hipGraphLaunch(c.gexec, st));
+            c.issued += r * P;
+            k -= r * P;
+        } else {
+            chain_step(c, st);
+            ++c.issued;
+            --k;
+        }
+    }
     c.last = st;
 }
 
@@ -732,8 +787,7 @@ static int run_chain(System& s, int iq, int dir, int flavour, int nsteps, tm_coe
     c.cap = nsteps;
     chain_begin(c, st);
     while (c.issued < nsteps) {
-        const int k = std::min(64, nsteps - c.issued);
-        for (int i = 0; i < k; ++i) chain_step(c, st);
+        chain_steps(c, 66, st);
         if (c.issued < nsteps && chain_poll(c)) break;
     }
     return chain_coeffs(c, out);
@@ -904,6 +958,7 @@ int tm_system_destroy(tm_system* sys) {
         for (void* p : s.allocs) (void)hipFree(p);
         for (QSet& q : s.qs)
             if (q.ucols) (void)hipFree(q.ucols);
+        if (s.cap_stream) (void)hipStreamDestroy(s.cap_stream);
         if (s.ureal) (void)hipFree(s.ureal);
         Workspace& w = s.ws;
         void* wp[] = {w.xcols, w.rho_part, w.rho, w.W, w.work, w.gpart, w.gsmall, w.dots, w.dotpart, w.fields};
@@ -1023,18 +1078,26 @@ int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream) {
         TM_CHECK(n == 0 || chains, TM_EINVAL, "null chain array");
         for (int i = 0; i < n; ++i) TM_CHECK(chains[i] != nullptr, TM_EINVAL, "null chain");
         hipStream_t st = static_cast<hipStream_t>(stream);
-        for (int k = 0; k < k_steps; ++k) {
-            bool any = false;
+        // round robin, one period of steps per chain and turn
+        std::vector<int> left(n, k_steps);
+        for (bool any = true; any;) {
+            any = false;
             for (int i = 0; i < n; ++i) {
                 Chain& c = chains[i]->c;
-                if (c.issued >= c.cap || c.broken_seen) continue;
-                chain_step(c, st);
+                if (left[i] <= 0 || c.issued >= c.cap || c.broken_seen) continue;
+                const int before = c.issued;
+                chain_steps(c, std::min(left[i], c.period()), st);
+                left[i] -= c.issued - before;
                 any = true;
             }
-            if (!any) break;
         }
         return TM_OK;
     });
+}
+
+int tm_chains_use_graphs(int on) {
+    g_use_graphs = on != 0;
+    return TM_OK;
 }
 
 int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out) {

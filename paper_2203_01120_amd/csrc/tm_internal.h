@@ -195,6 +195,7 @@ struct System {
     int ureal_mode = 0;             // 0 undecided, 1 resident, 2 columns
     double2* ureal = nullptr;
     size_t ureal_bytes = 0;
+    hipStream_t cap_stream = nullptr;  // private stream for graph capture of chain steps
     Workspace ws;
     std::vector<void*> allocs;
 };

@@ -84,6 +84,42 @@ def test_interleaved_chains_match_alone(lib, systems):
         same(g, a)
 
 
+def test_graph_replay_matches_direct_issue(lib, systems):
+    """Captured periods replayed many times, with eager work of the same system
+    (a direct apply) and host synchronisations between the replays."""
+    import torch
+    prob, h = systems["cubic20"]
+    info = lib.tm_qset_info_get(h, 0)
+    for flavour, mu, m in (("pH", "+", 60), ("nH", "z", 21)):
+        say(f"graph vs direct cubic20 {flavour} {mu} {m}")
+        lib.tm_chains_use_graphs(False)
+        try:
+            direct = lib.tm_lanczos_run(h, 0, mu, flavour, m)
+        finally:
+            lib.tm_chains_use_graphs(True)
+        x = torch.zeros(info["nelem"], dtype=torch.complex128, device="cuda")
+        y = torch.empty_like(x)
+        lib.tm_start_vectors(h, 0, "x", None, x)
+        c = lib.tm_chain_begin(h, 0, mu, flavour, m)
+        try:
+            done = 0
+            while done < m:
+                k = min(12, m - done)
+                lib.tm_chains_step([c], k)
+                lib.tm_liouvillian_apply(h, 0, x, y)
+                torch.cuda.synchronize()
+                part = lib.tm_chain_coeffs(c, m)
+                done += k
+                assert part["steps_done"] == done
+                # every replay so far agrees with the directly issued chain
+                for key in ("beta", "alpha"):
+                    assert np.array_equal(part[key][:done], direct[key][:done]), key
+            got = lib.tm_chain_coeffs(c, m)
+        finally:
+            lib.tm_chain_end(c)
+        same(got, direct)
+
+
 def test_chain_breakdown(lib, tiny_gs_nosoc):
     prob = lv.build_problem(tiny_gs_nosoc, np.zeros(3))
     h = lib.tm_system_create(desc_from_problem(prob))
