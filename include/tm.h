@@ -119,7 +119,8 @@ typedef struct {
  */
 int tm_system_create(const tm_system_desc* desc, tm_system** out);
 
-/* Free everything tm_system_create allocated.  NULL is allowed. */
+/* Free everything tm_system_create allocated.  NULL is allowed.  TM_EINVAL
+ * (nothing freed) while chains of the system exist (tm_chain_end them first). */
 int tm_system_destroy(tm_system* sys);
 
 /* Shape of the BR vectors of q-set iq. */
@@ -137,8 +138,9 @@ int tm_qset_info_get(const tm_system* sys, int iq, tm_qset_info* info);
  * bytes < 0 (the default) allows up to 80% of the device memory free at the
  * first apply; 0 disables the copy.  Setting a limit frees an existing copy and
  * the next apply decides again.  Must not be called while work of this system
- * is in flight.  The first apply of a q set after creation or after this call
- * builds these caches and synchronises its stream.
+ * is in flight; TM_EINVAL while chains of the system exist (their captured
+ * steps hold the copy's address).  The first apply of a q set after creation
+ * or after this call builds these caches and synchronises its stream.
  */
 int tm_system_set_resident_limit(tm_system* sys, long long bytes);
 

@@ -41,12 +41,26 @@ scale of L and eps = BREAKDOWN_TOL:
     pH step:   r^dag J L r <= eps Lam (r, r)   or   (r, r) <= eps^2 Lam^2 (q_i, q_i)
 The chain then stops; ``steps_done`` counts the steps whose alpha and z were
 recorded (the step that broke down included).
+
+Re-projection (the project's reading of how the recursion stays in the space
+L acts on).  The Liouvillian is defined on the empty manifold (the P_c, P_c^+
+projectors of Sec. 2.4, Eqs. P_minus_q2 and P_plus_q2); every vector of the
+recursion lies in it in exact arithmetic.  In floating point, rounding-level
+occupied components creep in; they carry no weight in the metric S = JL (its
+null space), so dividing by ever smaller beta amplifies them until
+r^dag J L r reaches zero and the pseudo-Hermitian chain breaks down after a
+few hundred steps.  The residual r (pH) and the pair q_i, p_i (nH) are
+therefore projected again before every application -- the identity in exact
+arithmetic.  (A projection only every sixth step was tried and still let
+some chains of the 24-q path break down.)
 """
 from __future__ import annotations
 
 import numpy as np
 
 BREAKDOWN_TOL = 1e-10
+REPROJECT_PH = 1    # steps between re-projections (pH)
+REPROJECT_NH = 1    # (nH)
 
 
 def _result(M, nlam):
@@ -56,7 +70,7 @@ def _result(M, nlam):
                 breakdown=False)
 
 
-def pseudo_hermitian(apply, v, us, nsteps, dot, J, lam):
+def pseudo_hermitian(apply, v, us, nsteps, dot, J, lam, proj=None):
     eps = BREAKDOWN_TOL
     res = _result(nsteps, len(us))
     w = apply(v)
@@ -76,6 +90,8 @@ def pseudo_hermitian(apply, v, us, nsteps, dot, J, lam):
         a = dot(Lq, J(Lq)).real
         res["alpha"][j] = a
         r = Lq - a * q - b_prev * q_prev
+        if proj is not None and j % REPROJECT_PH == 0:
+            r = proj(r)
         Lr = apply(r)
         b2 = dot(r, J(Lr)).real
         rr = dot(r, r).real
@@ -90,7 +106,7 @@ def pseudo_hermitian(apply, v, us, nsteps, dot, J, lam):
     return res
 
 
-def non_hermitian(apply, apply_dag, v, us, nsteps, dot, lam):
+def non_hermitian(apply, apply_dag, v, us, nsteps, dot, lam, proj=None):
     eps = BREAKDOWN_TOL
     res = _result(nsteps, len(us))
     n1 = np.sqrt(dot(v, v).real)
@@ -104,6 +120,8 @@ def non_hermitian(apply, apply_dag, v, us, nsteps, dot, lam):
     p_prev = np.zeros_like(v)
     b_prev, g_prev = 0.0, 0.0
     for j in range(nsteps):
+        if proj is not None and j % REPROJECT_NH == 0:
+            q, p = proj(q), proj(p)
         for l, u in enumerate(us):
             res["z"][l, j] = dot(u, q)
         Lq = apply(q)
@@ -129,16 +147,17 @@ def non_hermitian(apply, apply_dag, v, us, nsteps, dot, lam):
     return res
 
 
-def run(problem, mu, flavour, nsteps, measure=("x", "y", "z"), **kw):
+def run(problem, mu, flavour, nsteps, measure=("x", "y", "z"), reproject=True, **kw):
     """One chain for direction mu on an oracle Problem."""
     v = problem.v_vector(mu)
     us = [problem.u_vector(l) for l in measure]
     apply = lambda x: problem.apply(x, **kw)
     lam = operator_scale(problem)
+    proj = problem.project_all if reproject else None
     if flavour in ("pH", "pseudo_hermitian"):
-        return pseudo_hermitian(apply, v, us, nsteps, problem.dot, problem.J, lam)
+        return pseudo_hermitian(apply, v, us, nsteps, problem.dot, problem.J, lam, proj)
     apply_dag = lambda x: problem.apply_dagger(x, **kw)
-    return non_hermitian(apply, apply_dag, v, us, nsteps, problem.dot, lam)
+    return non_hermitian(apply, apply_dag, v, us, nsteps, problem.dot, lam, proj)
 
 
 def operator_scale(problem):

@@ -428,47 +428,41 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
 
 }  // namespace
 
-void ensure_workspace(System& s, const QSet& q) {
+// Workspace of the apply, sized once for every q set of the system: captured
+// chain graphs keep its pointers, so it is never reallocated afterwards.
+void ensure_workspace(System& s, const QSet&) {
     Workspace& w = s.ws;
-    const int nb = s.nbnd, nb2 = 2 * q.nk;
-    if (w.nchunk == 0) {
-        long long blocks_per_chunk = (long long)s.n3 * nb2;
-        int nchunk = (int)std::min<long long>(nb, std::max<long long>(1, (2048 + blocks_per_chunk - 1) / blocks_per_chunk));
-        w.nchunk = nchunk;
+    if (w.rho) return;
+    const int nb = s.nbnd;
+    int nb2 = 0, ncol_max = 0, npw_pad = 0;
+    for (const QSet& q : s.qs) {
+        nb2 = std::max(nb2, 2 * q.nk);
+        ncol_max = std::max(ncol_max, q.ncol_max);
+        npw_pad = std::max(npw_pad, q.npw_pad);
     }
-    size_t need_x = (size_t)nb2 * 2 * nb * s.n3 * q.ncol_max;
-    if (need_x > w.cap_xcols) {
-        if (w.xcols) TM_HIP(hipFree(w.xcols));
-        TM_HIP(hipMalloc(&w.xcols, need_x * sizeof(double2)));
-        w.cap_xcols = need_x;
-    }
-    size_t need_rp = (size_t)nb2 * w.nchunk * 4 * s.N;
-    if (need_rp > w.cap_rho_part) {
-        if (w.rho_part) TM_HIP(hipFree(w.rho_part));
-        TM_HIP(hipMalloc(&w.rho_part, need_rp * sizeof(double2)));
-        w.cap_rho_part = need_rp;
-    }
-    if (!w.rho) {
-        TM_HIP(hipMalloc(&w.rho, 4 * s.N * sizeof(double2)));
-        TM_HIP(hipMalloc(&w.W, 4 * s.N * sizeof(double2)));
-        TM_HIP(hipMalloc(&w.work, s.N * sizeof(double2)));
-        TM_HIP(hipMalloc(&w.dots, 64 * sizeof(double2)));
-        TM_HIP(hipMalloc(&w.dotpart, 1024 * 8 * sizeof(double2)));
-        if (plane_fixed_supported(s.n1, s.n2)) TM_HIP(hipMalloc(&w.fields, 6 * s.N * sizeof(double2)));
-    }
-    size_t need_gp = std::max(gemm_partial_elems(nb2, nb, nb, 2 * q.npw_pad),
-                              gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, q.npw_pad));
-    if (need_gp > w.cap_gpart) {
-        if (w.gpart) TM_HIP(hipFree(w.gpart));
-        TM_HIP(hipMalloc(&w.gpart, need_gp * sizeof(double2)));
-        w.cap_gpart = need_gp;
-    }
-    size_t need_gs = std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
-    if (need_gs > w.cap_gsmall) {
-        if (w.gsmall) TM_HIP(hipFree(w.gsmall));
-        TM_HIP(hipMalloc(&w.gsmall, need_gs * sizeof(double2)));
-        w.cap_gsmall = need_gs;
-    }
+    long long blocks_per_chunk = (long long)s.n3 * nb2;
+    w.nchunk = (int)std::min<long long>(nb, std::max<long long>(1, (2048 + blocks_per_chunk - 1) / blocks_per_chunk));
+    w.cap_xcols = (size_t)nb2 * 2 * nb * s.n3 * ncol_max;
+    w.cap_rho_part = (size_t)nb2 * w.nchunk * 4 * s.N;
+    w.cap_gpart = std::max(gemm_partial_elems(nb2, nb, nb, 2 * npw_pad),
+                           gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, npw_pad));
+    w.cap_gsmall = std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
+    auto grab = [&](void** p, size_t bytes) {
+        if (hipMalloc(p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{TM_ENOMEM, "hipMalloc of the apply workspace failed"};
+        }
+    };
+    grab((void**)&w.xcols, w.cap_xcols * sizeof(double2));
+    grab((void**)&w.rho_part, w.cap_rho_part * sizeof(double2));
+    grab((void**)&w.gpart, w.cap_gpart * sizeof(double2));
+    grab((void**)&w.gsmall, w.cap_gsmall * sizeof(double2));
+    grab((void**)&w.W, 4 * s.N * sizeof(double2));
+    grab((void**)&w.work, s.N * sizeof(double2));
+    grab((void**)&w.dots, 64 * sizeof(double2));
+    grab((void**)&w.dotpart, 1024 * 8 * sizeof(double2));
+    if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, 6 * s.N * sizeof(double2));
+    grab((void**)&w.rho, 4 * s.N * sizeof(double2));  // last: marks the workspace complete
 }
 
 // Ground-state planes for the plane kernels.  With fixed-size plane kernels
@@ -552,6 +546,10 @@ void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream
     if (v) launch_project_signed(s, q, v, 1.0, 1.0, st);
 }
 
+// Steps after which the vector roles of a chain return to their initial
+// assignment (pH: q_prev, q, r rotate in 3, Lq, Lr in 2; nH: two 3-cycles).
+constexpr int kPeriodPH = 6, kPeriodNH = 3;
+
 // One Lanczos chain (Sec. 2.5) resident on the device: its vectors, the
 // three u^lambda, the coefficient arrays and the scale/step state.  Steps are
 // issued asynchronously; the step index and the breakdown flag live on the
@@ -589,7 +587,7 @@ struct Chain {
         for (void* p : mem) (void)hipFree(p);
     }
     // steps after which the vector roles return to their initial assignment
-    int period() const { return flavour == TM_PSEUDOHERMITIAN ? 6 : 3; }
+    int period() const { return flavour == TM_PSEUDOHERMITIAN ? kPeriodPH : kPeriodNH; }
     double2* V(int role) const { return vec[ix[role]]; }
 };
 
@@ -655,6 +653,9 @@ static void chain_step(Chain& c, hipStream_t st) {
     if (c.flavour == TM_PSEUDOHERMITIAN) {
         double2 *QP = c.V(0), *Q = c.V(1), *LQ = c.V(2), *R = c.V(3), *LR = c.V(4);
         run_ph_update(c.cs, LQ, Q, QP, R, uc, n, c.w, c.part, d + 8, st);
+        // back onto the empty manifold: removes rounding-level occupied parts
+        // that the metric JL cannot see (identity in exact arithmetic)
+        launch_project_signed(s, s.qs[c.iq], R, 1.0, 1.0, st);
         apply_fp64(s, c.iq, R, LR, st);
         DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}};
         run_multidot<3>(ds, n, half, c.w, c.part, d, st);
@@ -669,6 +670,9 @@ static void chain_step(Chain& c, hipStream_t st) {
     } else {
         double2 *QP = c.V(0), *Q = c.V(1), *PP = c.V(2), *Pv = c.V(3), *LQ = c.V(4), *LTP = c.V(5),
                 *TMP = c.V(6), *QH = c.V(7), *PH = c.V(8);
+        // q_i, p_i back onto the empty manifold (see the pH step)
+        launch_project_signed(s, s.qs[c.iq], Q, 1.0, 1.0, st);
+        launch_project_signed(s, s.qs[c.iq], Pv, 1.0, 1.0, st);
         apply_fp64(s, c.iq, Q, LQ, st);
         run_jcopy(Pv, TMP, n, half, st);
         apply_fp64(s, c.iq, TMP, LTP, st);
@@ -954,6 +958,7 @@ int tm_system_destroy(tm_system* sys) {
     if (!sys) return TM_OK;
     return guarded([&]() -> int {
         System& s = sys->s;
+        TM_CHECK(s.nchains == 0, TM_EINVAL, "end the system's chains before destroying it");
         (void)hipDeviceSynchronize();
         for (void* p : s.allocs) (void)hipFree(p);
         for (QSet& q : s.qs)
@@ -987,6 +992,7 @@ int tm_qset_info_get(const tm_system* sys, int iq, tm_qset_info* info) {
 int tm_system_set_resident_limit(tm_system* sys, long long bytes) {
     return guarded([&]() -> int {
         TM_CHECK(sys, TM_EINVAL, "null system");
+        TM_CHECK(sys->s.nchains == 0, TM_EINVAL, "the residency limit cannot change while chains exist");
         reset_ground(sys->s);
         sys->s.resident_limit = bytes < 0 ? -1 : bytes;
         return TM_OK;
@@ -1067,6 +1073,7 @@ int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precisio
         c.flavour = (int)f;
         c.cap = capacity;
         chain_begin(c, static_cast<hipStream_t>(stream));
+        ++s.nchains;
         *out = h.release();
         return TM_OK;
     });
@@ -1114,7 +1121,9 @@ int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out) {
 int tm_chain_end(tm_chain* chain) {
     if (!chain) return TM_OK;
     return guarded([&]() -> int {
+        System* s = chain->c.s;
         delete chain;
+        if (s && s->nchains > 0) --s->nchains;
         return TM_OK;
     });
 }

@@ -196,6 +196,7 @@ struct System {
     double2* ureal = nullptr;
     size_t ureal_bytes = 0;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture of chain steps
+    int nchains = 0;                   // chains alive (tm_chain_begin .. tm_chain_end)
     Workspace ws;
     std::vector<void*> allocs;
 };

@@ -31,7 +31,7 @@ __all__ = [
     "vloc_grid", "projector_table", "dmatrix", "make_cubic20", "make_tiny",
     "make_hexslab", "kmesh_cart", "QSetDef", "qset_exact", "qset_folded",
     "random_br", "synthetic_ground_state", "synthetic_fields", "synthetic_inputs",
-    "cart_from_frac",
+    "cart_from_frac", "q_path", "synthetic_inputs_multi",
 ]
 
 
@@ -415,6 +415,60 @@ def synthetic_inputs(sysd: SystemDef, qcart, seed: int = 0, kmesh_subset=None):
         points.append((p, mill, evc, et, vkb))
     vrs, rho = synthetic_fields(sysd, seed)
     return dict(sysd=sysd, qset=qs, points=points, vrs=vrs, rho=rho, dvan=dmatrix(sysd))
+
+
+def q_path(n: int = 24, q_min: float = 0.02, verts=((0.0, 0.0, 0.0), (0.5, 0.0, 0.0),
+                                                     (1.0 / 3.0, 1.0 / 3.0, 0.0), (0.0, 0.0, 0.0))):
+    """n fractional q points along the polyline verts (default Gamma -> M(1/2,0,0)
+    -> K(1/3,1/3,0) -> Gamma), equally spaced by path length in fractional
+    units, the first and last q_min away from the start and end."""
+    v = np.asarray(verts, dtype=float)
+    seg = np.linalg.norm(np.diff(v, axis=0), axis=1)
+    ends = np.cumsum(seg)
+    total = ends[-1]
+    out = []
+    for t in q_min + (total - 2 * q_min) * np.arange(n) / max(n - 1, 1):
+        i = int(min(np.searchsorted(ends, t), len(seg) - 1))
+        t0 = ends[i] - seg[i]
+        out.append(v[i] + (v[i + 1] - v[i]) * (t - t0) / seg[i])
+    return np.array(out)
+
+
+def synthetic_inputs_multi(sysd: SystemDef, qcarts, seed: int = 0):
+    """synthetic_inputs for several q sets sharing one point list.
+
+    Returns dict(sysd, xq[nq][3], roles[nq][nk][4], shifts[nq][nk][4][3],
+    points=[(xk, mill, evc, et, vkb)], vrs, rho, dvan); every distinct role
+    vector (compared bit for bit) is one point, a negated point gets the
+    negated sphere of its partner.
+    """
+    km = kmesh_cart(sysd)
+    qcarts = np.asarray(qcarts, dtype=float)
+    pts: list = []
+    index: dict = {}
+
+    def idx(v):
+        key = tuple(np.asarray(v, dtype=float).tolist())
+        if key not in index:
+            index[key] = len(pts)
+            pts.append(np.asarray(v, dtype=float))
+        return index[key]
+
+    roles = np.zeros((len(qcarts), len(km), 4), dtype=np.int32)
+    for iq, q in enumerate(qcarts):
+        for ik, k in enumerate(km):
+            roles[iq, ik] = [idx(k), idx(-k), idx(k + q), idx(-k - q)]
+    points = []
+    cache: dict = {}
+    for i, p in enumerate(pts):
+        neg = tuple((-p).tolist())
+        mill = -cache[neg] if neg in cache else sphere(sysd, p)
+        cache[tuple(p.tolist())] = mill
+        evc, et = synthetic_ground_state(sysd, p, mill, seed=seed * 100003 + i)
+        points.append((p, mill, evc, et, projector_table(sysd, p, mill)))
+    vrs, rho = synthetic_fields(sysd, seed)
+    return dict(sysd=sysd, xq=qcarts, roles=roles, shifts=np.zeros(roles.shape + (3,), dtype=np.int32),
+                points=points, vrs=vrs, rho=rho, dvan=dmatrix(sysd))
 
 
 def synthetic_fields(sysd: SystemDef, seed: int, bmag: float = 0.1):

@@ -25,6 +25,25 @@ def desc_from_problem(prob):
                       roles=np.asarray(prob.qset.roles)[None], shifts=np.asarray(prob.qset.shifts)[None])
 
 
+def desc_from_problems(probs):
+    """One system holding the q sets of several oracle Problems of one ground state."""
+    from paper_2203_01120_amd import Point, SystemDesc
+    p0 = probs[0]
+    sysd, nb = p0.sysd, p0.nb
+    pts, roles, shifts = [], [], []
+    for prob in probs:
+        off = len(pts)
+        for i, p in enumerate(prob.qset.points):
+            mill, evc, et = prob.point_states[i]
+            pts.append(Point(xk=np.asarray(p, float), mill=mill, evc=evc[:nb], et=np.asarray(et[:nb]),
+                             vkb=synth.projector_table(sysd, p, mill)))
+        roles.append(np.asarray(prob.qset.roles) + off)
+        shifts.append(np.asarray(prob.qset.shifts))
+    return SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=nb, points=pts, vrs=p0.vrs, rho=p0.gs.rho,
+                      dvan=synth.dmatrix(sysd), xq=np.array([np.asarray(pr.qset.q) for pr in probs]),
+                      roles=np.array(roles), shifts=np.array(shifts))
+
+
 def to_gpu(x, npw_pad):
     import torch
     out = np.zeros(x.shape[:-1] + (npw_pad,), dtype=np.complex128)

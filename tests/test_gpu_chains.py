@@ -11,7 +11,7 @@ import pytest
 from oracle import lanczos as olanczos
 from oracle import liouvillian as lv
 
-from gpu_util import desc_from_problem, say
+from gpu_util import desc_from_problem, desc_from_problems, from_gpu, rel_err, say, to_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -118,6 +118,43 @@ def test_graph_replay_matches_direct_issue(lib, systems):
         finally:
             lib.tm_chain_end(c)
         same(got, direct)
+
+
+def test_several_q_sets_in_one_system(lib, tiny_gs):
+    """Chains on different q sets of one system, stepped together (workspace
+    sized for all sets, graphs of one set unaffected by the others)."""
+    qs = [np.array(v) * 2 * np.pi / 6.0 for v in ((0.1, 0.05, 0.0), (0.0, 0.2, 0.1), (0.25, 0.0, 0.0))]
+    probs = [lv.build_problem(tiny_gs, q) for q in qs]
+    h = lib.tm_system_create(desc_from_problems(probs))
+    try:
+        # (the tiny system's JL is indefinite at q != 0: pseudo-Hermitian chains along m_z only)
+        specs = [(0, "z", "pH", 20), (1, "z", "pH", 18), (2, "-", "nH", 9), (1, "x", "nH", 6)]
+        say("chains on three q sets")
+        chains = [lib.tm_chain_begin(h, iq, mu, f, m) for iq, mu, f, m in specs]
+        try:
+            lib.tm_chains_step(chains, 25)
+            got = [lib.tm_chain_coeffs(c, m) for c, (_, _, _, m) in zip(chains, specs)]
+        finally:
+            for c in chains:
+                lib.tm_chain_end(c)
+        for g, (iq, mu, f, m) in zip(got, specs):
+            ref = olanczos.run(probs[iq], mu, f, m)
+            assert g["steps_done"] == ref["steps_done"] == m
+            assert np.abs(g["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
+            assert np.abs(g["alpha"] - ref["alpha"]).max() <= 1e-10 * np.abs(ref["alpha"]).max()
+        # a direct apply on the middle set
+        import torch
+        prob = probs[1]
+        info = lib.tm_qset_info_get(h, 1)
+        x = prob.random_projected(5)
+        xin = to_gpu(x, info["npw_pad"])
+        out = torch.empty_like(xin)
+        lib.tm_liouvillian_apply(h, 1, xin, out)
+        torch.cuda.synchronize()
+        gotx, _ = from_gpu(out, (2, prob.nk, prob.nb, 2, info["npw_pad"]), prob.npw_pad)
+        assert rel_err(gotx, prob.apply(x)) <= 1e-12
+    finally:
+        lib.tm_system_destroy(h)
 
 
 def test_chain_breakdown(lib, tiny_gs_nosoc):
