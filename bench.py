@@ -230,13 +230,97 @@ def run_qpath(args, tm, torch):
     print(json.dumps(out))
 
 
+def run_serving(args, tm, torch):
+    """Poisson arrivals of chi requests on a pool of systems (cubic a = 10 bohr cell:
+    20^3 / 8 bands / Gamma, 24^3 / 16 bands / 2x2x1 k, 32^3 / 32 bands / 3x3x1 k;
+    two q sets each), drawn 4:2:1 toward the small ones; direction uniform over
+    x, y, z, +, -; flavour uniform over pH, nH; 500..3000 steps.  The
+    continuous-batching server is compared with the plain one-at-a-time path
+    (FIFO, tm_lanczos_run with directly issued kernels) on the same requests."""
+    import synth
+    from paper_2203_01120_amd import serving as sv
+    pool = {"cubic20": synth.make_cubic20(), "cubic24": synth.make_cubic(24, 16, 2),
+            "cubic32": synth.make_cubic(32, 32, 3)}
+    weights = np.array([4.0, 2.0, 1.0]) / 7.0
+    slots = {}
+    for name, sysd in pool.items():
+        qs = np.array([[0.1, 0.0, 0.0], [0.0, 0.15, 0.05]]) * 2 * np.pi / 10.0
+        inp = synth.synthetic_inputs_multi(sysd, qs, seed=args.seed)
+        pts = [tm.Point(xk=p, mill=m, evc=e, et=et, vkb=v) for (p, m, e, et, v) in inp["points"]]
+        desc = tm.SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=sysd.nbnd, points=pts, vrs=inp["vrs"],
+                             rho=inp["rho"], dvan=inp["dvan"], xq=inp["xq"], roles=inp["roles"],
+                             shifts=inp["shifts"])
+        h = tm.tm_system_create(desc)
+        nelem = {iq: tm.tm_qset_info_get(h, iq)["nelem"] for iq in range(len(qs))}
+        for iq in range(len(qs)):   # builds the per-q caches outside the timed runs
+            tm.tm_lanczos_run(h, iq, "z", "nH", 3)
+        slots[name] = sv.SystemSlot(handle=h, nelem=nelem)
+        log(f"system {name}: fft {sysd.fft}, {sysd.nbnd} bands, {len(sysd.kmesh)} k")
+    torch.cuda.synchronize()
+    omega = np.arange(400) * 5e-3 / EV
+    eta = 5e-3 / EV
+    names = list(pool)
+    results = []
+    maxdiff = 0.0
+    for rate in [float(r) for r in args.rates.split(",")]:
+        rng = np.random.default_rng(5000 + int(round(rate * 10)))
+        t = np.cumsum(rng.exponential(1.0 / rate, args.requests))
+
+        def make():
+            out = []
+            for i in range(args.requests):
+                r2 = np.random.default_rng(7000 + 1000 * int(round(rate * 10)) + i)
+                out.append(sv.Request(rid=i, system=names[r2.choice(3, p=weights)], iq=int(r2.integers(2)),
+                                      direction=str(r2.choice(["x", "y", "z", "+", "-"])),
+                                      flavour=str(r2.choice(["pH", "nH"])), nsteps=int(r2.integers(500, 3001)),
+                                      omega=omega, eta=eta, arrival=float(t[i])))
+            return out
+        log(f"rate {rate}/s: {args.requests} requests, batched server")
+        server = sv.Server(slots, budget_bytes=32 << 30)
+        batched = server.run(make())
+        log(f"rate {rate}/s: one at a time")
+        plain = sv.run_one_at_a_time(slots, make())
+        by_id = {r.rid: r for r in plain}
+        for r in batched:
+            ref = by_id[r.rid].chi
+            maxdiff = max(maxdiff, float(np.abs(r.chi - ref).max() / max(np.abs(ref).max(), 1e-300)))
+        sb, sp = sv.summary(batched), sv.summary(plain)
+        log(f"rate {rate}: batched {sb}  plain {sp}")
+        results.append({"rate_per_s": rate, "batched": sb, "one_at_a_time": sp})
+    for s in slots.values():
+        tm.tm_system_destroy(s.handle)
+    best = max(results, key=lambda r: r["batched"]["spectra_per_s"])
+    out = {
+        "metric": "chi(q,omega) spectra/s and p50/p99 latency under Poisson load",
+        "value": best["batched"]["spectra_per_s"],
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": None,
+        "warmup": 3,
+        "ms_per_step": None,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "serving: pool 20^3/8/1k, 24^3/16/4k, 32^3/32/9k (cubic a=10 bohr), 4:2:1, "
+                               "500..3000 steps, pH|nH, x|y|z|+|-, chi on 400 omega",
+                   "rates_per_s": [r["rate_per_s"] for r in results], "requests_per_rate": args.requests},
+        "per_rate": results,
+        "chi_max_rel_diff_batched_vs_alone": maxdiff,
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="hexslab", choices=["hexslab", "cubic20", "qpath"])
+    ap.add_argument("--workload", default="hexslab", choices=["hexslab", "cubic20", "qpath", "serving"])
     ap.add_argument("--chain-steps", type=int, default=2000, help="qpath: steps per chain")
+    ap.add_argument("--rates", default="0.5,1,2", help="serving: Poisson arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=20)
@@ -256,6 +340,8 @@ def main():
     tm.load()
     if args.workload == "qpath":
         return run_qpath(args, tm, torch)
+    if args.workload == "serving":
+        return run_serving(args, tm, torch)
 
     log(f"building {args.workload} inputs")
     t0 = time.time()

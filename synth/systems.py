@@ -31,7 +31,7 @@ __all__ = [
     "vloc_grid", "projector_table", "dmatrix", "make_cubic20", "make_tiny",
     "make_hexslab", "kmesh_cart", "QSetDef", "qset_exact", "qset_folded",
     "random_br", "synthetic_ground_state", "synthetic_fields", "synthetic_inputs",
-    "cart_from_frac", "q_path", "synthetic_inputs_multi",
+    "cart_from_frac", "q_path", "synthetic_inputs_multi", "make_cubic",
 ]
 
 
@@ -231,6 +231,16 @@ def make_cubic20(seed: int = 2205, soc: float = 0.01, nbnd: int = 8) -> SystemDe
     ecut = 4.79
     return SystemDef(name="cubic20", cell=cell, atoms=atoms, ecut=ecut, fft=(20, 20, 20),
                      nbnd=nbnd, kmesh=np.zeros((1, 3)), seed=seed)
+
+
+def make_cubic(n: int, nbnd: int, mesh: int, seed: int = 2205, soc: float = 0.01) -> SystemDef:
+    """cubic20's cell and atoms on an n^3 grid: E_cut scaled with n^2 (so the
+    sphere fills the grid as at 20^3), nbnd bands, Gamma-centred mesh x mesh x 1."""
+    base = make_cubic20(seed=seed, soc=soc, nbnd=nbnd)
+    f = np.arange(mesh) / mesh
+    kmesh = np.array([[a, b, 0.0] for a in f for b in f])
+    return SystemDef(name=f"cubic{n}", cell=base.cell, atoms=base.atoms, ecut=base.ecut * (n / 20.0) ** 2,
+                     fft=(n, n, n), nbnd=nbnd, kmesh=kmesh, seed=seed)
 
 
 def make_tiny(seed: int = 7, nat: int = 2, a: float = 6.0, ecut: float = 2.0,
