@@ -101,8 +101,10 @@ def kernel_models(inp, info, resident: bool):
     return {
         "k_apply_planes": dict(flops=apply_flops, bytes=apply_bytes),
         "k_apply_t": dict(flops=apply_flops, bytes=apply_bytes),
+        "k_apply_w": dict(flops=apply_flops, bytes=apply_bytes),
         "k_density": dict(flops=dens_flops, bytes=dens_bytes),
         "k_density_t": dict(flops=dens_flops, bytes=dens_bytes),
+        "k_density_w": dict(flops=dens_flops, bytes=dens_bytes),
         # projector GEMMs: S = O^H phi and phi -= O S (8 real flops per complex MAC)
         "k_gemm_cn": dict(flops=gemm_flops, bytes=vec_bytes, mfma=True),
         "k_gemm_update": dict(flops=gemm_flops, bytes=2 * vec_bytes, mfma=True),
