@@ -47,6 +47,18 @@ enum {
                              length with a prime factor other than 2, 3, 5)     */
 };
 
+/*
+ * Arithmetic of a Liouvillian application (Eq. liouvillian_blocks).
+ * TM_FP64: everything in double precision.
+ * TM_FP32 (single-precision bulk): the 3D FFTs, the response densities, the
+ *   real-space products and the nonlocal/projector contractions (FP32 MFMA,
+ *   FP32 accumulation) run in single precision; the Hartree + xc potential,
+ *   the kinetic term, the BR vectors themselves, every Lanczos recurrence and
+ *   inner product and chi stay FP64, and the chains re-project their vectors
+ *   onto the empty manifold in FP64 every step.  Needs the fixed-size plane
+ *   and z kernels and the resident real-space ground state
+ *   (tm_system_set_resident_limit), else TM_EUNSUPPORTED at the first apply.
+ */
 typedef enum { TM_FP64 = 0, TM_FP32 = 1 } tm_precision;
 
 /* Direction of the perturbing field (Sec. 2.5, Eq. off-diag-resolvent):
@@ -157,7 +169,7 @@ int tm_system_resident_bytes(const tm_system* sys, long long* bytes);
  * be orthogonal to the occupied manifold (X side to U_{k+q}, Y side to
  * T U_{-k-q}); the output always is.
  * stream: a hipStream_t (NULL = default stream); the call is asynchronous.
- * prec: TM_FP64 (TM_FP32 returns TM_EUNSUPPORTED in this version).
+ * prec: TM_FP64 or TM_FP32 (see tm_precision).
  */
 int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out,
                          tm_precision prec, void* stream);

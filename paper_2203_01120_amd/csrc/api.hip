@@ -11,7 +11,8 @@
 namespace tml {
 
 void launch_kin(const System& s, double* kin, const int* d_mill, int npw, int npw_pad, const double* p, hipStream_t st);
-void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st);
+void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
+                           bool f32 = false);
 size_t gemm_partial_elems(int nbatch, int M, int Nn, int K);
 void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int cap, int M,
                 double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
@@ -523,18 +524,25 @@ static void reset_ground(System& s) {
     for (QSet& q : s.qs) q.ground_ready = false;
 }
 
-void apply_fp64(System& s, int iq, const double2* in, double2* out, hipStream_t st) {
+// out = L_q in.  fp32: the FFTs, densities, point-wise products and the
+// nonlocal/projector contractions run in single precision (FP32 MFMA, FP32
+// accumulation); the potential (Hartree + kernel), the kinetic term and the
+// vectors stay FP64.  Needs the fixed-size kernels and the resident ground state.
+void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st) {
     QSet& q = s.qs[iq];
     ensure_workspace(s, q);
     ensure_ground(s, q, st);
+    if (fp32)
+        TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
+                 "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
-    launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st);
-    launch_density(s, q, st);
+    launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st, fp32);
+    launch_density(s, q, st, fp32);
     launch_potential(s, q, st);
-    launch_apply_planes(s, q, st);
-    launch_zpass_fwd(s, q, s.ws.xcols, in, out, st);
-    launch_nonlocal(s, q, in, out, st);
-    launch_project(s, q, out, st);
+    launch_apply_planes(s, q, st, fp32);
+    launch_zpass_fwd(s, q, s.ws.xcols, in, out, st, fp32);
+    launch_nonlocal(s, q, in, out, st, fp32);
+    launch_project(s, q, out, st, fp32);
 }
 
 void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st) {
@@ -557,6 +565,7 @@ constexpr int kPeriodPH = 6, kPeriodNH = 3;
 struct Chain {
     System* s = nullptr;
     int iq = 0, dir = 0, flavour = 0, cap = 0;
+    bool fp32 = false;         // single-precision applies (recurrence and dots stay FP64)
     long long n = 0, half = 0;
     double w = 1.0;
     std::vector<double2*> vec;  // work vectors (5 pH, 9 nH)
@@ -626,7 +635,7 @@ static void chain_begin(Chain& c, hipStream_t st) {
         // roles: 0 q_prev, 1 q, 2 Lq, 3 r, 4 Lr
         TM_HIP(hipMemsetAsync(c.V(0), 0, n * sizeof(double2), st));
         start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
-        apply_fp64(s, c.iq, c.V(1), c.V(2), st);
+        apply_l(s, c.iq, c.V(1), c.V(2), c.fp32, st);
         DotSet<6> ds0{{c.V(1), c.V(1), c.V(2), c.u[0], c.u[1], c.u[2]},
                       {c.V(2), c.V(1), c.V(2), c.V(1), c.V(1), c.V(1)},
                       {1, 0, 1, 0, 0, 0}};
@@ -656,7 +665,7 @@ static void chain_step(Chain& c, hipStream_t st) {
         // back onto the empty manifold: removes rounding-level occupied parts
         // that the metric JL cannot see (identity in exact arithmetic)
         launch_project_signed(s, s.qs[c.iq], R, 1.0, 1.0, st);
-        apply_fp64(s, c.iq, R, LR, st);
+        apply_l(s, c.iq, R, LR, c.fp32, st);
         DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}};
         run_multidot<3>(ds, n, half, c.w, c.part, d, st);
         ctl_ph_step(c.cs, d, d + 8, c.co, st);
@@ -673,9 +682,9 @@ static void chain_step(Chain& c, hipStream_t st) {
         // q_i, p_i back onto the empty manifold (see the pH step)
         launch_project_signed(s, s.qs[c.iq], Q, 1.0, 1.0, st);
         launch_project_signed(s, s.qs[c.iq], Pv, 1.0, 1.0, st);
-        apply_fp64(s, c.iq, Q, LQ, st);
+        apply_l(s, c.iq, Q, LQ, c.fp32, st);
         run_jcopy(Pv, TMP, n, half, st);
-        apply_fp64(s, c.iq, TMP, LTP, st);
+        apply_l(s, c.iq, TMP, LTP, c.fp32, st);
         DotSet<1> da{{Pv}, {LQ}, {0}};
         run_multidot<1>(da, n, half, c.w, c.part, d, st);
         ctl_nh_alpha(c.cs, d, c.co, st);
@@ -782,9 +791,11 @@ static int chain_coeffs(Chain& c, tm_coeffs* out) {
     return h.broken ? TM_EBREAKDOWN : TM_OK;
 }
 
-static int run_chain(System& s, int iq, int dir, int flavour, int nsteps, tm_coeffs* out, hipStream_t st) {
+static int run_chain(System& s, int iq, int dir, int flavour, bool fp32, int nsteps, tm_coeffs* out,
+                     hipStream_t st) {
     Chain c;
     c.s = &s;
+    c.fp32 = fp32;
     c.iq = iq;
     c.dir = dir;
     c.flavour = flavour;
@@ -908,6 +919,9 @@ int tm_system_create(const tm_system_desc* d, tm_system** out) {
             }
             s.tw[i] = dev_upload(s, tw.data(), tw.size());
             s.plan[i].tw = s.tw[i];
+            std::vector<float2> twf(ns[i]);
+            for (int j = 0; j < ns[i]; ++j) twf[j] = make_float2((float)tw[j].x, (float)tw[j].y);
+            s.twf[i] = dev_upload(s, twf.data(), twf.size());
             std::vector<int> pr = digit_reversal(ns[i]);
             s.perm[i] = dev_upload(s, pr.data(), pr.size());
         }
@@ -1013,14 +1027,14 @@ int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out
         TM_CHECK(sys && xy_in && xy_out, TM_EINVAL, "null argument");
         System& s = sys->s;
         TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
-        TM_CHECK(prec == TM_FP64, TM_EUNSUPPORTED, "only TM_FP64 is implemented");
+        TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
         const QSet& q = s.qs[iq];
         const size_t bytes = (size_t)2 * q.nk * s.nbnd * 2 * q.npw_pad * sizeof(double2);
         const char* a = static_cast<const char*>(xy_in);
         const char* b = static_cast<const char*>(xy_out);
         TM_CHECK(a + bytes <= b || b + bytes <= a, TM_EINVAL, "xy_in and xy_out overlap");
-        apply_fp64(s, iq, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out),
-                   static_cast<hipStream_t>(stream));
+        apply_l(s, iq, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out), prec == TM_FP32,
+                static_cast<hipStream_t>(stream));
         return TM_OK;
     });
 }
@@ -1047,8 +1061,8 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
         TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
         TM_CHECK(nsteps >= 1 && nsteps <= out->capacity, TM_EINVAL, "nsteps must be in [1, capacity]");
         TM_CHECK(out->alpha && out->beta && out->gamma && out->z, TM_EINVAL, "null coefficient array");
-        TM_CHECK(prec == TM_FP64, TM_EUNSUPPORTED, "only TM_FP64 is implemented");
-        int rc = run_chain(s, iq, (int)dir, (int)f, nsteps, out, nullptr);
+        TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
+        int rc = run_chain(s, iq, (int)dir, (int)f, prec == TM_FP32, nsteps, out, nullptr);
         if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
         return rc;
     });
@@ -1064,7 +1078,7 @@ int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precisio
         TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
         TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
         TM_CHECK(capacity >= 1, TM_EINVAL, "capacity must be >= 1");
-        TM_CHECK(prec == TM_FP64, TM_EUNSUPPORTED, "only TM_FP64 is implemented");
+        TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
         std::unique_ptr<tm_chain> h(new tm_chain());
         Chain& c = h->c;
         c.s = &s;
@@ -1072,6 +1086,7 @@ int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precisio
         c.dir = (int)dir;
         c.flavour = (int)f;
         c.cap = capacity;
+        c.fp32 = prec == TM_FP32;
         chain_begin(c, static_cast<hipStream_t>(stream));
         ++s.nchains;
         *out = h.release();

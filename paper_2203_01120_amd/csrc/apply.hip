@@ -105,7 +105,8 @@ __global__ void k_density(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
         }
 }
 
-__global__ void k_density_reduce(const double2* part, double2* rho, long long N, int nk, int nchunk, double scale) {
+template <class T2>
+__global__ void k_density_reduce(const T2* part, double2* rho, long long N, int nk, int nchunk, double scale) {
     long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 4 * N) return;
     int comp = (int)(idx / N);
@@ -113,7 +114,7 @@ __global__ void k_density_reduce(const double2* part, double2* rho, long long N,
     double2 sx = cmk(0.0, 0.0), sy = cmk(0.0, 0.0);
     for (int b = 0; b < 2 * nk; ++b)
         for (int c = 0; c < nchunk; ++c) {
-            double2 v = part[(((long long)b * nchunk + c) * 4 + comp) * N + p];
+            double2 v = Cx<double2>::from(part[(((long long)b * nchunk + c) * 4 + comp) * N + p]);
             if (b < nk) sx = cadd(sx, v); else sy = cadd(sy, v);
         }
     double sgn = comp == 0 ? 1.0 : -1.0;
@@ -305,6 +306,9 @@ PlaneArgs plane_args(const System& s, const QSet& q) {
     a.ureal = s.ureal_mode == 1 ? s.ureal : nullptr;
     a.uslot = q.d_uslot;
     a.fields = s.ws.fields;
+    a.xcols32 = reinterpret_cast<float2*>(s.ws.xcols);
+    a.rho_part32 = reinterpret_cast<float2*>(s.ws.rho_part);
+    a.fields32 = reinterpret_cast<float2*>(s.ws.fields);
     return a;
 }
 
@@ -335,22 +339,31 @@ static PlaneTabs plane_tabs(const System& s, const QSet& q) {
     t.perm1 = s.perm[0];
     t.perm2 = s.perm[1];
     t.colidx_kq = q.d_colidx_kq;
+    t.tw1f = s.twf[0];
+    t.tw2f = s.twf[1];
     return t;
 }
 
-void launch_density(const System& s, const QSet& q, hipStream_t st) {
+void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32) {
     PlaneArgs a = plane_args(s, q);
     dim3 grid(s.n3, a.nchunk, 2 * q.nk);
     if (plane_fixed_supported(s.n1, s.n2)) {
-        launch_plane_fixed(true, a, plane_tabs(s, q), grid, s.n1, s.n2, st);
+        launch_plane_fixed(true, a, plane_tabs(s, q), grid, s.n1, s.n2, st, fp32);
     } else {
+        TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision plane kernels need a fixed-size plane");
         int th = plane_threads(s);
         size_t shm = (size_t)a.NP * sizeof(double2);
         TM_LAUNCH(k_density, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);
     }
     long long n4 = 4 * s.N;
-    TM_LAUNCH(k_density_reduce, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, s.ws.rho_part,
-                       s.ws.rho, s.N, q.nk, a.nchunk, 1.0 / (s.omega * q.nk));
+    const double scale = 1.0 / (s.omega * q.nk);
+    if (fp32) {
+        TM_LAUNCH(k_density_reduce<float2>, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, a.rho_part32,
+                  s.ws.rho, s.N, q.nk, a.nchunk, scale);
+    } else {
+        TM_LAUNCH(k_density_reduce<double2>, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, s.ws.rho_part,
+                  s.ws.rho, s.N, q.nk, a.nchunk, scale);
+    }
 }
 
 void launch_potential(const System& s, const QSet& q, hipStream_t st) {
@@ -363,13 +376,14 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st) {
     TM_LAUNCH(k_assemble_W, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, s.fxc, s.ws.W, N);
 }
 
-void launch_apply_planes(const System& s, const QSet& q, hipStream_t st) {
+void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32) {
     PlaneArgs a = plane_args(s, q);
     dim3 grid(s.n3, a.nchunk, 2 * q.nk);
     if (plane_fixed_supported(s.n1, s.n2)) {
-        launch_plane_fixed(false, a, plane_tabs(s, q), grid, s.n1, s.n2, st);
+        launch_plane_fixed(false, a, plane_tabs(s, q), grid, s.n1, s.n2, st, fp32);
         return;
     }
+    TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision plane kernels need a fixed-size plane");
     int th = plane_threads(s);
     size_t shm = (size_t)a.NP * sizeof(double2);
     TM_LAUNCH(k_apply_planes, grid, dim3(th), shm, st, a, s.plan[0], s.plan[1]);

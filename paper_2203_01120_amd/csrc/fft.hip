@@ -192,7 +192,7 @@ int lines_for(int n, int cap_lines, int threads) {
 }  // namespace
 
 void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2* coef, long long coef_bstride,
-                      int nitems, int item_stride, double2* cols, hipStream_t st) {
+                      int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32) {
     const int nb2 = 2 * q.nk;
     ZArgs a;
     a.nitems = nitems;
@@ -236,10 +236,13 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
         z.ncol_stride = a.ncol_stride;
         z.nitems = nitems;
         z.tw = s.plan[2].tw;
+        z.tw32 = s.twf[2];
+        z.cols32 = reinterpret_cast<float2*>(cols);
         z.perm = s.perm[2];
-        launch_zpass_fixed(true, z, ncolmax, nb2, n3, st);
+        launch_zpass_fixed(true, z, ncolmax, nb2, n3, st, fp32);
         return;
     }
+    TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision z passes need a fixed-size grid length");
     int L = lines_for(n3, 64, kZThreads);
     a.ct = L >= 16 ? 16 : L;
     a.lines_per_block = L;
@@ -250,7 +253,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
 }
 
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin, double2* out,
-                      hipStream_t st) {
+                      hipStream_t st, bool fp32) {
     ZFwdArgs a;
     a.cols = cols;
     a.ncol_stride = q.ncol_max;
@@ -284,9 +287,12 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
         z.out = out;
         z.npw_pad = q.npw_pad;
         z.inv_n = 1.0 / (double)s.N;
-        launch_zpass_fixed(false, z, q.ncol_max, 2 * q.nk, n3, st);
+        z.tw32 = s.twf[2];
+        z.cols32 = reinterpret_cast<float2*>(const_cast<double2*>(cols));
+        launch_zpass_fixed(false, z, q.ncol_max, 2 * q.nk, n3, st, fp32);
         return;
     }
+    TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision z passes need a fixed-size grid length");
     int L = lines_for(n3, 64, kZThreads);
     a.ct = L >= 16 ? 16 : L;
     a.lines_per_block = L;

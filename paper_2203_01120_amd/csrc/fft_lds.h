@@ -22,43 +22,46 @@ __device__ inline double2 twiddle(const double2* tw, int idx, int sign) {
     return sign < 0 ? w : cmk(w.x, -w.y);
 }
 
-template <int R>
-__device__ inline void dft_small(double2* v, int sign) {
+// in-register DFT of length R on v[0..R), sign = -1 forward, +1 inverse;
+// T2 = double2 or float2
+template <int R, class T2>
+__device__ inline void dft_small(T2* v, int sign) {
+    using Re = typename Cx<T2>::R;
     if constexpr (R == 2) {
-        double2 a = v[0], b = v[1];
+        T2 a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
     } else if constexpr (R == 3) {
-        const double c = -0.5, s = 0.86602540378443864676 * sign;
-        double2 a = v[0], b = v[1], d = v[2];
-        double2 t = cadd(b, d);
-        double2 m = cmk(a.x + c * t.x, a.y + c * t.y);
-        double2 df = csub(b, d);
-        double2 r = cmk(-s * df.y, s * df.x);  // i s (b - d)
+        const Re c = Re(-0.5), s = Re(0.86602540378443864676) * Re(sign);
+        T2 a = v[0], b = v[1], d = v[2];
+        T2 t = cadd(b, d);
+        T2 m = Cx<T2>::mk(a.x + c * t.x, a.y + c * t.y);
+        T2 df = csub(b, d);
+        T2 r = Cx<T2>::mk(-s * df.y, s * df.x);  // i s (b - d)
         v[0] = cadd(a, t);
         v[1] = cadd(m, r);
         v[2] = csub(m, r);
     } else if constexpr (R == 4) {
-        double2 a = v[0], b = v[1], c = v[2], d = v[3];
-        double2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
+        T2 a = v[0], b = v[1], c = v[2], d = v[3];
+        T2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
         // sign * i * t3
-        double2 it3 = sign < 0 ? cmk(t3.y, -t3.x) : cmk(-t3.y, t3.x);
+        T2 it3 = sign < 0 ? Cx<T2>::mk(t3.y, -t3.x) : Cx<T2>::mk(-t3.y, t3.x);
         v[0] = cadd(t0, t2);
         v[2] = csub(t0, t2);
         v[1] = cadd(t1, it3);
         v[3] = csub(t1, it3);
     } else if constexpr (R == 5) {
-        const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;
-        const double s1 = 0.95105651629515357212 * sign, s2 = 0.58778525229247312917 * sign;
-        double2 a = v[0];
-        double2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
-        double2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
-        double2 m1 = cmk(a.x + c1 * b1.x + c2 * b2.x, a.y + c1 * b1.y + c2 * b2.y);
-        double2 m2 = cmk(a.x + c2 * b1.x + c1 * b2.x, a.y + c2 * b1.y + c1 * b2.y);
+        const Re c1 = Re(0.30901699437494742410), c2 = Re(-0.80901699437494742410);
+        const Re s1 = Re(0.95105651629515357212) * Re(sign), s2 = Re(0.58778525229247312917) * Re(sign);
+        T2 a = v[0];
+        T2 b1 = cadd(v[1], v[4]), b2 = cadd(v[2], v[3]);
+        T2 d1 = csub(v[1], v[4]), d2 = csub(v[2], v[3]);
+        T2 m1 = Cx<T2>::mk(a.x + c1 * b1.x + c2 * b2.x, a.y + c1 * b1.y + c2 * b2.y);
+        T2 m2 = Cx<T2>::mk(a.x + c2 * b1.x + c1 * b2.x, a.y + c2 * b1.y + c1 * b2.y);
         // i*(s1 d1 + s2 d2) and i*(s2 d1 - s1 d2)
-        double2 e1 = cmk(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
-        double2 e2 = cmk(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
-        double2 ie1 = cmuli(e1), ie2 = cmuli(e2);
+        T2 e1 = Cx<T2>::mk(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y);
+        T2 e2 = Cx<T2>::mk(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y);
+        T2 ie1 = cmuli(e1), ie2 = cmuli(e2);
         v[0] = cadd(a, cadd(b1, b2));
         v[1] = cadd(m1, ie1);
         v[4] = csub(m1, ie1);

@@ -12,8 +12,12 @@
 //   S = O^dag phi,  phi <- sg (phi - O S), sg = -1 on the lower row of L.
 // Complex products use four real MFMAs (re*re, im*im, re*im, im*re).
 //
-// Lane layout of the 16x16x4 FP64 MFMA for wave lane l (measured on gfx950):
-// A[l%16][l/16], B[l/16][l%16], accumulator element v = D[4*v + l/16][l%16].
+// Lane layout of the 16x16x4 MFMAs for wave lane l (measured on gfx950):
+// A[l%16][l/16], B[l/16][l%16]; accumulator element v holds
+//   FP64 (v_mfma_f64_16x16x4f64): D[4*v + l/16][l%16]
+//   FP32 (v_mfma_f32_16x16x4f32): D[4*(l/16) + v][l%16]
+// The FP32 variants (single-precision bulk path) round the FP64 operands to
+// FP32 on load and accumulate in FP32; partial sums and outputs stay FP64.
 #include "tm_internal.h"
 
 namespace tml {
@@ -21,10 +25,26 @@ namespace tml {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ inline v4d mfma(double a, double b, v4d c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ inline v4f mfma(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+template <class R>
+struct MF;
+template <>
+struct MF<double> {
+    using V = v4d;
+    // output row of accumulator element v for lane group kk = l / 16
+    __device__ static int row(int v, int kk) { return 4 * v + kk; }
+};
+template <>
+struct MF<float> {
+    using V = v4f;
+    __device__ static int row(int v, int kk) { return 4 * kk + v; }
+};
 
 struct GemmCN {
     const double2* const* A_tab;  // per batch (or null -> A_base + b*a_bstride)
@@ -38,6 +58,7 @@ struct GemmCN {
     double2* part;                // [b][ks][M][Nn]
 };
 
+template <class R>
 __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     const int b = blockIdx.z, ks = blockIdx.y;
     const int tile = blockIdx.x;
@@ -47,7 +68,7 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     const double2* B = g.B_base + (long long)b * g.b_bstride;
     const int kbeg = ks * g.kchunk;
     const int kend = min(g.K, kbeg + g.kchunk);
-    v4d cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    typename MF<R>::V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
     const bool arow = (m0 + i) < g.M, brow = (n0 + i) < g.Nn;
     const double2* Ap = A + (long long)(m0 + i) * g.lda;
     const double2* Bp = B + (long long)(n0 + i) * g.ldb;
@@ -55,16 +76,17 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
         int kx = k + kk;
         double2 a = (arow && kx < kend) ? Ap[kx] : cmk(0.0, 0.0);
         double2 bv = (brow && kx < kend) ? Bp[kx] : cmk(0.0, 0.0);
-        cr = mfma(a.x, bv.x, cr);
-        cr = mfma(a.y, bv.y, cr);
-        ci = mfma(a.x, bv.y, ci);
-        ci = mfma(-a.y, bv.x, ci);
+        const R ax = (R)a.x, ay = (R)a.y, bx = (R)bv.x, by = (R)bv.y;
+        cr = mfma(ax, bx, cr);
+        cr = mfma(ay, by, cr);
+        ci = mfma(ax, by, ci);
+        ci = mfma(-ay, bx, ci);
     }
     double2* out = g.part + ((long long)b * g.ksplit + ks) * g.M * g.Nn;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        int m = m0 + 4 * v + kk, n = n0 + i;
-        if (m < g.M && n < g.Nn) out[(long long)m * g.Nn + n] = cmk(cr[v], ci[v]);
+        int m = m0 + MF<R>::row(v, kk), n = n0 + i;
+        if (m < g.M && n < g.Nn) out[(long long)m * g.Nn + n] = cmk((double)cr[v], (double)ci[v]);
     }
 }
 
@@ -92,6 +114,7 @@ struct GemmUpd {
     int nk;
 };
 
+template <class R>
 __global__ void __launch_bounds__(64) k_gemm_update(GemmUpd g) {
     const int b = blockIdx.z;
     const int n0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
@@ -99,25 +122,26 @@ __global__ void __launch_bounds__(64) k_gemm_update(GemmUpd g) {
     const double2* A = g.A_tab[b];
     const double2* C = g.C_base + (long long)b * g.c_bstride;
     double2* Y = g.Y_base + (long long)b * g.y_bstride;
-    v4d dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
+    typename MF<R>::V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
     const bool ncol = (n0 + i) < g.Nout, kcol = (k0 + i) < g.K;
     for (int m = 0; m < g.Minner; m += 4) {
         int mm = m + kk;
         double2 c = (mm < g.Minner && ncol) ? C[(long long)mm * g.ldc + n0 + i] : cmk(0.0, 0.0);
         double2 a = (mm < g.Minner && kcol) ? A[(long long)mm * g.lda + k0 + i] : cmk(0.0, 0.0);
-        dr = mfma(c.x, a.x, dr);
-        dr = mfma(-c.y, a.y, dr);
-        di = mfma(c.x, a.y, di);
-        di = mfma(c.y, a.x, di);
+        const R cx = (R)c.x, cy = (R)c.y, ax = (R)a.x, ay = (R)a.y;
+        dr = mfma(cx, ax, dr);
+        dr = mfma(-cy, ay, dr);
+        di = mfma(cx, ay, di);
+        di = mfma(cy, ax, di);
     }
     const double os = b < g.nk ? g.os_x : g.os_y;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        int n = n0 + 4 * v + kk, k = k0 + i;
+        int n = n0 + MF<R>::row(v, kk), k = k0 + i;
         if (n < g.Nout && k < g.K) {
             double2* y = Y + (long long)n * g.ldy + k;
             double2 cur = *y;
-            *y = cmk(os * (cur.x + g.cs * dr[v]), os * (cur.y + g.cs * di[v]));
+            *y = cmk(os * (cur.x + g.cs * (double)dr[v]), os * (cur.y + g.cs * (double)di[v]));
         }
     }
 }
@@ -149,7 +173,7 @@ int choose_kchunk(int K, long long tiles_times_batch) {
 }
 
 void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const double2* B_base, long long b_bstride,
-                 int ldb, int M, int Nn, int K, int nbatch, double2* out, hipStream_t st) {
+                 int ldb, int M, int Nn, int K, int nbatch, double2* out, hipStream_t st, bool f32 = false) {
     GemmCN g;
     g.A_tab = A_tab;
     g.A_base = nullptr;
@@ -168,7 +192,11 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
     TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
     g.part = s.ws.gpart;
     dim3 grid(mt * g.nt, g.ksplit, nbatch);
-    TM_LAUNCH(k_gemm_cn, grid, dim3(64), 0, st, g);
+    if (f32) {
+        TM_LAUNCH(k_gemm_cn<float>, grid, dim3(64), 0, st, g);
+    } else {
+        TM_LAUNCH(k_gemm_cn<double>, grid, dim3(64), 0, st, g);
+    }
     long long mn = (long long)M * Nn;
     TM_LAUNCH(k_reduce_parts, dim3((unsigned)((mn * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
                        out, g.ksplit, mn, nbatch);
@@ -176,7 +204,7 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
 
 void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C, long long c_bstride, int ldc,
                      const double2* const* A_tab, int lda, int Nout, int K, int Minner, double cs, double osx,
-                     double osy, int nk, hipStream_t st) {
+                     double osy, int nk, hipStream_t st, bool f32 = false) {
     GemmUpd g;
     g.Y_base = Y;
     g.y_bstride = y_bstride;
@@ -194,7 +222,11 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
     g.os_y = osy;
     g.nk = nk;
     dim3 grid((Nout + 15) / 16, (K + 15) / 16, 2 * nk);
-    TM_LAUNCH(k_gemm_update, grid, dim3(64), 0, st, g);
+    if (f32) {
+        TM_LAUNCH(k_gemm_update<float>, grid, dim3(64), 0, st, g);
+    } else {
+        TM_LAUNCH(k_gemm_update<double>, grid, dim3(64), 0, st, g);
+    }
 }
 
 }  // namespace
@@ -206,31 +238,32 @@ size_t gemm_partial_elems(int nbatch, int M, int Nn, int K) {
     return (size_t)nbatch * ks * M * Nn;
 }
 
-void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st) {
+void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st, bool f32) {
     if (s.nproj == 0) return;
     const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
     const long long bstride = (long long)nb * 2 * P;
     double2* Bm = s.ws.gsmall;
     double2* Wm = s.ws.gsmall + (size_t)nbatch * s.nproj * 2 * nb;
-    run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, Bm, st);
+    run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, Bm, st, f32);
     long long tot = (long long)nbatch * s.nproj * 2 * nb;
     TM_LAUNCH(k_dmat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Bm, s.dvan, Wm, s.nproj, nb,
                        nbatch);
     run_gemm_update(out, bstride, P, Wm, (long long)s.nproj * 2 * nb, 2 * nb, q.d_vkb, P, 2 * nb, P, s.nproj, 1.0,
-                    1.0, 1.0, q.nk, st);
+                    1.0, 1.0, q.nk, st, f32);
 }
 
-void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st) {
+void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
+                           bool f32) {
     const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
     const long long bstride = (long long)nb * 2 * P;
     double2* S = s.ws.gsmall;
-    run_gemm_cn(s, (const double2* const*)q.d_occ, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, S, st);
+    run_gemm_cn(s, (const double2* const*)q.d_occ, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, S, st, f32);
     run_gemm_update(phi, bstride, 2 * P, S, (long long)nb * nb, nb, (const double2* const*)q.d_occ, 2 * P, nb,
-                    2 * P, nb, -1.0, osx, osy, q.nk, st);
+                    2 * P, nb, -1.0, osx, osy, q.nk, st, f32);
 }
 
-void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st) {
-    launch_project_signed(s, q, out, 1.0, -1.0, st);
+void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32) {
+    launch_project_signed(s, q, out, 1.0, -1.0, st, f32);
 }
 
 }  // namespace tml

@@ -26,6 +26,10 @@ struct PlaneArgs {
     double2* ureal;
     const int* uslot;  // [2nk] slot of each batch
     double2* fields;   // [n3][n1*n2][6] local fields in the order of the resident planes
+    // single-precision views of xcols, rho_part and fields (FP32 bulk path)
+    float2* xcols32;
+    float2* rho_part32;
+    float2* fields32;
 };
 
 // rows of the (i1, i2) plane occupied by each sphere, per batch b
@@ -41,6 +45,8 @@ struct PlaneTabs {
     const int* perm1;    // mixed-radix digit reversal of the in-place transforms along i1
     const int* perm2;    // and along i2
     const short* const* colidx_kq;  // [n1*n2] column of the k+q sphere at each plane position, or -1
+    const float2* tw1f;  // single-precision twiddles (FP32 bulk path)
+    const float2* tw2f;
 };
 
 // position p of an in-place decimation-in-frequency transform of length n holds
@@ -59,9 +65,11 @@ struct ZPassArgs {
     const int* const* enti3;
     const int* ncol;
     double2* cols;                     // [b][item][n3][ncol_stride]
+    float2* cols32;                    // the same in single precision (FP32 bulk path)
     int ncol_stride;
     int nitems;
     const double2* tw;                 // exp(-2 pi i j / n3)
+    const float2* tw32;
     const int* perm;                   // digit reversal along i3
     // forward only
     const int* npw;
@@ -74,11 +82,12 @@ struct ZPassArgs {
 };
 
 bool zpass_fixed_supported(int n3);
-void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st);
+void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st,
+                        bool fp32 = false);
 
 bool plane_fixed_supported(int n1, int n2);
 void launch_plane_fixed(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
-                        hipStream_t st);
+                        hipStream_t st, bool fp32 = false);
 // fills a.ureal for the batches of the grid from a.ucols
 void launch_ureal_fixed(const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2, hipStream_t st);
 

@@ -13,6 +13,8 @@
 //     plane-wave sphere occupies; the column direction reads inactive rows as
 //     zero instead of clearing them;
 //   * the local fields of a block's points stay in registers across bands.
+#include <type_traits>
+
 #include "fft_lds.h"
 #include "plane.h"
 
@@ -83,8 +85,8 @@ struct ColLines {
 // digit-reversed input to natural order.  Every butterfly reads and writes the
 // same R locations, so a thread may process any number of butterflies of a
 // stage without an intermediate barrier.
-template <int N, int R, int LB, int SIGN, bool DIF, bool MASKED, int NT, class Lines>
-__device__ __forceinline__ void ipass(double2* pl, int nlines, const Lines& L, const double2* tw) {
+template <int N, int R, int LB, int SIGN, bool DIF, bool MASKED, int NT, class Lines, class T2>
+__device__ __forceinline__ void ipass(T2* pl, int nlines, const Lines& L, const T2* tw) {
     constexpr int M = LB / R;
     constexpr int BPL = N / R;
     constexpr int TWS = N / LB;
@@ -97,13 +99,13 @@ __device__ __forceinline__ void ipass(double2* pl, int nlines, const Lines& L, c
         const int j = r0 - blk * M;
         const int e0 = blk * LB + j;
         const int base = L.base(line) + e0 * ES;
-        double2 u[R];
+        T2 u[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) {
-            double2 x = cmk(0.0, 0.0);
+            T2 x = Cx<T2>::mk(0, 0);
             if (!MASKED || L.valid(line, e0 + t * M)) x = pl[base + t * M * ES];
             if (!DIF && t > 0 && j > 0) {
-                double2 w = tw[t * j * TWS];
+                T2 w = tw[t * j * TWS];
                 if (SIGN > 0) w.y = -w.y;
                 x = cmul(x, w);
             }
@@ -112,9 +114,9 @@ __device__ __forceinline__ void ipass(double2* pl, int nlines, const Lines& L, c
         dft_small<R>(u, SIGN);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            double2 y = u[r];
+            T2 y = u[r];
             if (DIF && r > 0 && j > 0) {
-                double2 w = tw[r * j * TWS];
+                T2 w = tw[r * j * TWS];
                 if (SIGN > 0) w.y = -w.y;
                 y = cmul(y, w);
             }
@@ -125,8 +127,8 @@ __device__ __forceinline__ void ipass(double2* pl, int nlines, const Lines& L, c
 }
 
 // natural -> digit-reversed (inverse direction of the apply, SIGN = +1)
-template <int N, int SIGN, int NT, bool MASKED, int STAGE = 0, int LB = N, class Lines>
-__device__ __forceinline__ void fft_dif(double2* pl, int nlines, const Lines& L, const double2* tw) {
+template <int N, int SIGN, int NT, bool MASKED, int STAGE = 0, int LB = N, class Lines, class T2>
+__device__ __forceinline__ void fft_dif(T2* pl, int nlines, const Lines& L, const T2* tw) {
     constexpr CPlan cp = cplan(N);
     if constexpr (STAGE < cp.nrad) {
         constexpr int R = cp.rad[STAGE];
@@ -136,8 +138,8 @@ __device__ __forceinline__ void fft_dif(double2* pl, int nlines, const Lines& L,
 }
 
 // digit-reversed -> natural; stages in reverse order (LB = N / (R0 ... R_{s-1}))
-template <int N, int SIGN, int NT, int STAGE, class Lines>
-__device__ __forceinline__ void fft_dit(double2* pl, int nlines, const Lines& L, const double2* tw) {
+template <int N, int SIGN, int NT, int STAGE, class Lines, class T2>
+__device__ __forceinline__ void fft_dit(T2* pl, int nlines, const Lines& L, const T2* tw) {
     constexpr CPlan cp = cplan(N);
     if constexpr (STAGE >= 0) {
         constexpr int R = cp.rad[STAGE];
@@ -147,8 +149,8 @@ __device__ __forceinline__ void fft_dit(double2* pl, int nlines, const Lines& L,
     }
 }
 
-template <int N, int SIGN, int NT, class Lines>
-__device__ __forceinline__ void fft_dit_all(double2* pl, int nlines, const Lines& L, const double2* tw) {
+template <int N, int SIGN, int NT, class Lines, class T2>
+__device__ __forceinline__ void fft_dit_all(T2* pl, int nlines, const Lines& L, const T2* tw) {
     constexpr CPlan cp = cplan(N);
     fft_dit<N, SIGN, NT, cp.nrad - 1>(pl, nlines, L, tw);
 }
@@ -458,6 +460,13 @@ __global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
 // and two LDS buffers alternate between bands, so a band costs one workgroup
 // barrier in the density and two in the apply.
 
+// the double- or single-precision member of a pair of buffers
+template <class T2, class D, class F>
+__host__ __device__ inline auto pick(D d, F f) {
+    if constexpr (std::is_same<T2, double2>::value) return d;
+    else return f;
+}
+
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -473,8 +482,8 @@ __device__ __forceinline__ void wave_sync() {
 //  * Twiddles come from the table in device memory (vector L1), not from LDS.
 //  * The lane's butterflies go in groups of BT whose loads are all issued
 //    before their stores (BT trades registers for memory-level parallelism).
-template <int N, int R, int LB, int SIGN, bool DIF, bool MASKED, int MAXL, int BT, class WL>
-__device__ __forceinline__ void wpass(double2* pl, const WL& L, int nl, const double2* __restrict__ tw, int lane) {
+template <int N, int R, int LB, int SIGN, bool DIF, bool MASKED, int MAXL, int BT, class WL, class T2>
+__device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const T2* __restrict__ tw, int lane) {
     constexpr int M = LB / R;
     constexpr int BPL = N / R;
     constexpr int SPL = (BPL > 8 && BPL < 16) ? 16 : BPL;  // lane slots per line
@@ -485,7 +494,7 @@ __device__ __forceinline__ void wpass(double2* pl, const WL& L, int nl, const do
     const int ns = nl * SPL;
 #pragma unroll
     for (int g0 = 0; g0 < IT; g0 += B) {
-        double2 u[B][R];
+        T2 u[B][R];
         int base[B], jv[B];
 #pragma unroll
         for (int it = 0; it < B; ++it) {
@@ -503,10 +512,10 @@ __device__ __forceinline__ void wpass(double2* pl, const WL& L, int nl, const do
                 jv[it] = j;
 #pragma unroll
                 for (int t = 0; t < R; ++t) {
-                    double2 x = cmk(0.0, 0.0);
+                    T2 x = Cx<T2>::mk(0, 0);
                     if (!MASKED || L.valid(e0 + t * M)) x = pl[bs + t * M * ES];
                     if (!DIF && t > 0 && j > 0) {
-                        double2 w = tw[t * j * TWS];
+                        T2 w = tw[t * j * TWS];
                         if (SIGN > 0) w.y = -w.y;
                         x = cmul(x, w);
                     }
@@ -520,9 +529,9 @@ __device__ __forceinline__ void wpass(double2* pl, const WL& L, int nl, const do
                 dft_small<R>(u[it], SIGN);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    double2 y = u[it][r];
+                    T2 y = u[it][r];
                     if (DIF && r > 0 && jv[it] > 0) {
-                        double2 w = tw[r * jv[it] * TWS];
+                        T2 w = tw[r * jv[it] * TWS];
                         if (SIGN > 0) w.y = -w.y;
                         y = cmul(y, w);
                     }
@@ -534,8 +543,8 @@ __device__ __forceinline__ void wpass(double2* pl, const WL& L, int nl, const do
     wave_sync();
 }
 
-template <int N, int SIGN, bool MASKED, int MAXL, int BT, int STAGE = 0, int LB = N, class WL>
-__device__ __forceinline__ void wfft_dif(double2* pl, const WL& L, int nl, const double2* tw, int lane) {
+template <int N, int SIGN, bool MASKED, int MAXL, int BT, int STAGE = 0, int LB = N, class WL, class T2>
+__device__ __forceinline__ void wfft_dif(T2* pl, const WL& L, int nl, const T2* tw, int lane) {
     constexpr CPlan cp = cplan(N);
     if constexpr (STAGE < cp.nrad) {
         constexpr int R = cp.rad[STAGE];
@@ -544,8 +553,8 @@ __device__ __forceinline__ void wfft_dif(double2* pl, const WL& L, int nl, const
     }
 }
 
-template <int N, int SIGN, int MAXL, int BT, int STAGE, class WL>
-__device__ __forceinline__ void wfft_dit(double2* pl, const WL& L, int nl, const double2* tw, int lane) {
+template <int N, int SIGN, int MAXL, int BT, int STAGE, class WL, class T2>
+__device__ __forceinline__ void wfft_dit(T2* pl, const WL& L, int nl, const T2* tw, int lane) {
     constexpr CPlan cp = cplan(N);
     if constexpr (STAGE >= 0) {
         constexpr int R = cp.rad[STAGE];
@@ -579,7 +588,7 @@ struct WCols {
     __device__ bool valid(int row) const { return (mask >> row) & 1ULL; }
 };
 
-template <int N1, int N2, int BT_, int CPW_>
+template <int N1, int N2, int BT_, int CPW_, class T2>
 struct WaveKernel {
     using G = Geom<N1, N2>;
     static constexpr int CPW = CPW_;                // columns per wave
@@ -593,17 +602,17 @@ struct WaveKernel {
     static_assert(N2 % CPW == 0 && NW <= 16, "plane shape");
 
     struct Smem {
-        double2* pl;       // 2 buffers
+        T2* pl;            // 2 buffers
         int* rowbase;      // [2 N1] plane * PS + row * N2P of the occupied rows of planes 0, 1
         int* rowinfo;      // [2 N1] plane * N1 + row
         int* perm1;
         int* perm2;
         short* colidx;     // [N1 N2] column of the k+q sphere at natural plane position, or -1
     };
-    __device__ static Smem carve(double2* lds) {
+    __device__ static Smem carve(void* lds) {
         Smem m;
-        m.pl = lds;
-        m.rowbase = reinterpret_cast<int*>(lds + 2 * BUF);
+        m.pl = static_cast<T2*>(lds);
+        m.rowbase = reinterpret_cast<int*>(m.pl + 2 * BUF);
         m.rowinfo = m.rowbase + 2 * N1;
         m.perm1 = m.rowinfo + 2 * N1;
         m.perm2 = m.perm1 + N1;
@@ -611,7 +620,7 @@ struct WaveKernel {
         return m;
     }
     static constexpr size_t bytes() {
-        return (size_t)2 * BUF * sizeof(double2) + (4 * N1 + N1 + N2) * sizeof(int) +
+        return (size_t)2 * BUF * sizeof(T2) + (4 * N1 + N1 + N2) * sizeof(int) +
                (size_t)N1 * N2 * sizeof(short);
     }
 
@@ -637,15 +646,15 @@ struct WaveKernel {
 
     // fill the wave's occupied rows of buffer boff from the z-transformed
     // columns of item pair (2n, 2n+1), then the inverse transforms along i2
-    __device__ static void rows_inverse(const Smem& m, const double2* cx, long long cs, int nlw, int w, int boff,
-                                        int lane, const double2* __restrict__ gtw2) {
+    __device__ static void rows_inverse(const Smem& m, const T2* cx, long long cs, int nlw, int w, int boff,
+                                        int lane, const T2* __restrict__ gtw2) {
         for (int k = lane; k < nlw * N2; k += 64) {
             const int li = k / N2, p2 = k - li * N2;
             const int l = w + li * NW;
             const int info = m.rowinfo[l];
             const int s = info / N1, row = info - s * N1;
             const int c = m.colidx[row * N2 + p2];
-            m.pl[boff + m.rowbase[l] + p2] = c >= 0 ? cx[s * cs + c] : cmk(0.0, 0.0);
+            m.pl[boff + m.rowbase[l] + p2] = c >= 0 ? cx[s * cs + c] : Cx<T2>::mk(0, 0);
         }
         wave_sync();
         WRows<NW> rl{m.rowbase, w, boff};
@@ -663,13 +672,16 @@ __device__ __forceinline__ void wave_point(int w, int q, const int* perm1, const
     g = perm1[p1] * N2 + perm2[p2];
 }
 
-template <int N1, int N2, int BT, int CPW>
+template <int N1, int N2, int BT, int CPW, class T2>
 __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW>;
+    using K = WaveKernel<N1, N2, BT, CPW, T2>;
     using G = typename K::G;
     constexpr int PPL = K::PPL;
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
+    const T2* xcols = pick<T2>(a.xcols, a.xcols32);
+    const T2* tw1 = pick<T2>(t.tw1, t.tw1f);
+    const T2* tw2 = pick<T2>(t.tw2, t.tw2f);
     const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nrx = K::setup(t, b, m);
@@ -684,34 +696,34 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
         int g;
         wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
     }
-    double2 acc[4][PPL];
+    T2 acc[4][PPL];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) acc[c][j] = cmk(0.0, 0.0);
+        for (int j = 0; j < PPL; ++j) acc[c][j] = Cx<T2>::mk(0, 0);
     for (int n = n0; n < n1e; ++n) {
         const int boff = (n & 1) * K::BUF;
-        const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const double2* ur = ureal_plane(a, b, n, i3) + w * K::WPTS;
-        double2 uu[PPL], ud[PPL];
+        T2 uu[PPL], ud[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             const int q = lane + 64 * j;
             if (q < K::WPTS) {
-                uu[j] = ur[q];
-                ud[j] = ur[G::NP + q];
+                uu[j] = Cx<T2>::from(ur[q]);
+                ud[j] = Cx<T2>::from(ur[G::NP + q]);
             }
         }
-        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, t.tw2);
+        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2);
         __syncthreads();
         WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
-        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, t.tw1, lane);
+        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, tw1, lane);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             if (lane + 64 * j < K::WPTS) {
-                const double2 xu = m.pl[boff + o[j]], xd = m.pl[boff + G::PS + o[j]];
-                const double2 uu_xu = cmulc(uu[j], xu), ud_xd = cmulc(ud[j], xd);
-                const double2 uu_xd = cmulc(uu[j], xd), ud_xu = cmulc(ud[j], xu);
+                const T2 xu = m.pl[boff + o[j]], xd = m.pl[boff + G::PS + o[j]];
+                const T2 uu_xu = cmulc(uu[j], xu), ud_xd = cmulc(ud[j], xd);
+                const T2 uu_xd = cmulc(uu[j], xd), ud_xu = cmulc(ud[j], xu);
                 acc[0][j] = cadd(acc[0][j], cadd(uu_xu, ud_xd));
                 acc[1][j] = cadd(acc[1][j], cadd(uu_xd, ud_xu));
                 acc[2][j] = cadd(acc[2][j], cmuli(csub(ud_xu, uu_xd)));
@@ -720,7 +732,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
         }
     }
     const long long N = (long long)G::NP * a.n3;
-    double2* out = a.rho_part + ((long long)b * a.nchunk + chunk) * 4 * N + (long long)i3 * G::NP;
+    T2* out = pick<T2>(a.rho_part, a.rho_part32) + ((long long)b * a.nchunk + chunk) * 4 * N + (long long)i3 * G::NP;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         const int q = lane + 64 * j;
@@ -737,9 +749,9 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
 // idx = p2 n1 + p1 (LDS position, digit-reversed), 6 complex per point:
 //   (v + Bz, v - Bz), (Bx, By), W0 + Wz, W0 - Wz, Wx - i Wy, Wx + i Wy
 // (x side; the y side flips the sign of B and of the vector part of W).
-template <int N1, int N2>
+template <int N1, int N2, class T2>
 __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __restrict__ W, const int* perm1,
-                           const int* perm2, double2* __restrict__ F, int n3) {
+                           const int* perm2, T2* __restrict__ F, int n3) {
     constexpr int NP = N1 * N2;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int i3 = blockIdx.y;
@@ -749,24 +761,27 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
     const long long g = (long long)i3 * NP + perm1[p1] * N2 + perm2[p2];
     const double v = vrs[g], bx = vrs[N + g], by = vrs[2 * N + g], bz = vrs[3 * N + g];
     const double2 w0 = W[g], wx = W[N + g], wy = W[2 * N + g], wz = W[3 * N + g];
-    double2* f = F + ((long long)i3 * NP + idx) * 6;
-    f[0] = cmk(v + bz, v - bz);
-    f[1] = cmk(bx, by);
-    f[2] = cadd(w0, wz);
-    f[3] = csub(w0, wz);
-    f[4] = csub(wx, cmuli(wy));
-    f[5] = cadd(wx, cmuli(wy));
+    T2* f = F + ((long long)i3 * NP + idx) * 6;
+    f[0] = Cx<T2>::from(cmk(v + bz, v - bz));
+    f[1] = Cx<T2>::from(cmk(bx, by));
+    f[2] = Cx<T2>::from(cadd(w0, wz));
+    f[3] = Cx<T2>::from(csub(w0, wz));
+    f[4] = Cx<T2>::from(csub(wx, cmuli(wy)));
+    f[5] = Cx<T2>::from(cadd(wx, cmuli(wy)));
 }
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-template <int N1, int N2, int BT, int CPW>
+template <int N1, int N2, int BT, int CPW, class T2>
 __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW>;
+    using K = WaveKernel<N1, N2, BT, CPW, T2>;
     using G = typename K::G;
     constexpr int PPL = K::PPL;
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
+    T2* xcols = pick<T2>(a.xcols, a.xcols32);
+    const T2* tw1 = pick<T2>(t.tw1, t.tw1f);
+    const T2* tw2 = pick<T2>(t.tw2, t.tw2f);
     const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nrx = K::setup(t, b, m);
@@ -782,45 +797,45 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
         int g;
         wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
     }
-    const double2* fw = a.fields + ((long long)i3 * G::NP + w * K::WPTS) * 6;
+    const T2* fw = pick<T2>(a.fields, a.fields32) + ((long long)i3 * G::NP + w * K::WPTS) * 6;
     for (int n = n0; n < n1e; ++n) {
         const int boff = (n & 1) * K::BUF;
-        const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const double2* ur = ureal_plane(a, b, n, i3) + w * K::WPTS;
-        double2 uu[PPL], ud[PPL];
+        T2 uu[PPL], ud[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             const int q = lane + 64 * j;
             if (q < K::WPTS) {
-                uu[j] = ur[q];
-                ud[j] = ur[G::NP + q];
+                uu[j] = Cx<T2>::from(ur[q]);
+                ud[j] = Cx<T2>::from(ur[G::NP + q]);
             }
         }
-        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, t.tw2);
+        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2);
         __syncthreads();
         // columns: inverse along i1, point-wise products, forward along i1
         WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
-        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, t.tw1, lane);
+        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, tw1, lane);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
             const int q = lane + 64 * j;
             if (q < K::WPTS) {
-                const double2* f = fw + q * 6;
-                double2 f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4], f5 = f[5];
+                const T2* f = fw + q * 6;
+                T2 f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4], f5 = f[5];
                 if (yside) {  // B -> -B, W -> (W0, -W)
-                    f0 = cmk(f0.y, f0.x);
-                    f1 = cmk(-f1.x, -f1.y);
-                    const double2 t2 = f2;
+                    f0 = Cx<T2>::mk(f0.y, f0.x);
+                    f1 = Cx<T2>::mk(-f1.x, -f1.y);
+                    const T2 t2 = f2;
                     f2 = f3;
                     f3 = t2;
-                    f4 = cmk(-f4.x, -f4.y);
-                    f5 = cmk(-f5.x, -f5.y);
+                    f4 = Cx<T2>::mk(-f4.x, -f4.y);
+                    f5 = Cx<T2>::mk(-f5.x, -f5.y);
                 }
-                double2* px = m.pl + boff + o[j];
-                const double2 xu = px[0], xd = px[G::PS];
-                const double2 bm = cmk(f1.x, -f1.y), bp = f1;
-                double2 pu = cadd(cscale(xu, f0.x), cmul(bm, xd));
-                double2 pd = cadd(cscale(xd, f0.y), cmul(bp, xu));
+                T2* px = m.pl + boff + o[j];
+                const T2 xu = px[0], xd = px[G::PS];
+                const T2 bm = Cx<T2>::mk(f1.x, -f1.y), bp = f1;
+                T2 pu = cadd(cscale(xu, f0.x), cmul(bm, xd));
+                T2 pd = cadd(cscale(xd, f0.y), cmul(bp, xu));
                 pu = cadd(pu, cadd(cmul(f2, uu[j]), cmul(f4, ud[j])));
                 pd = cadd(pd, cadd(cmul(f3, ud[j]), cmul(f5, uu[j])));
                 px[0] = pu;
@@ -829,14 +844,14 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
         }
         wave_sync();
         constexpr CPlan c1 = cplan(N1);
-        wfft_dit<N1, -1, 2 * CPW, K::BT, c1.nrad - 1>(m.pl, cl, 2 * CPW, t.tw1, lane);
+        wfft_dit<N1, -1, 2 * CPW, K::BT, c1.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
         __syncthreads();
         // rows: forward along i2 on the occupied rows of the k+q sphere, then
         // the output columns
         constexpr CPlan c2 = cplan(N2);
         WRows<K::NW> rl{m.rowbase, w, boff};
-        wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rl, nlw, t.tw2, lane);
-        double2* co = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rl, nlw, tw2, lane);
+        T2* co = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         for (int k = lane; k < nlw * N2; k += 64) {
             const int li = k / N2, p2 = k - li * N2;
             const int l = w + li * K::NW;
@@ -866,34 +881,49 @@ void launch_with_lds(F kernel, const char* name, size_t shm, dim3 grid, int nt, 
 
 // NT: threads of the block-synchronous kernels (column path, builder)
 template <int N1, int N2, int NT>
-void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st) {
-    // butterflies per load group: the 48 x 48 apply holds 3 points of fields
-    // per lane and has registers for one butterfly at a time
+void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st, bool fp32) {
     // 4 columns per wave (12 waves for 48 x 48; 3 columns and 16 waves measured
     // slower: idle lanes in the column stages and register spills at 128 VGPRs)
     constexpr int CPW = 4;
     constexpr int BTD = 2, BTA = 2;
-    using WD = WaveKernel<N1, N2, BTD, CPW>;
-    using WA = WaveKernel<N1, N2, BTA, CPW>;
     if (op == kOpUreal) {
         launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
     } else if (a.ureal) {
         TM_CHECK(t.colidx_kq != nullptr, TM_EINVAL, "missing column index tables");
         const dim3 wgrid(grid.z, grid.y, grid.x);  // (b, chunk, i3)
+        if (fp32) {
+            using WD = WaveKernel<N1, N2, BTD, CPW, float2>;
+            using WA = WaveKernel<N1, N2, BTA, CPW, float2>;
+            if (op == kOpDensity) {
+                launch_with_lds(k_density_w<N1, N2, BTD, CPW, float2>, "k_density_w32", WD::bytes(), wgrid, WD::NT,
+                                st, a, t);
+            } else {
+                TM_LAUNCH((k_fields_w<N1, N2, float2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs,
+                          a.W, t.perm1, t.perm2, a.fields32, a.n3);
+                launch_with_lds(k_apply_w<N1, N2, BTA, CPW, float2>, "k_apply_w32", WA::bytes(), wgrid, WA::NT, st,
+                                a, t);
+            }
+            return;
+        }
+        using WD = WaveKernel<N1, N2, BTD, CPW, double2>;
+        using WA = WaveKernel<N1, N2, BTA, CPW, double2>;
         if (op == kOpDensity) {
-            launch_with_lds(k_density_w<N1, N2, BTD, CPW>, "k_density_w", WD::bytes(), wgrid, WD::NT, st, a, t);
+            launch_with_lds(k_density_w<N1, N2, BTD, CPW, double2>, "k_density_w", WD::bytes(), wgrid, WD::NT, st, a,
+                            t);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
-            TM_LAUNCH((k_fields_w<N1, N2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs, a.W, t.perm1,
-                      t.perm2, a.fields, a.n3);
-            launch_with_lds(k_apply_w<N1, N2, BTA, CPW>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
+            TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs,
+                      a.W, t.perm1, t.perm2, a.fields, a.n3);
+            launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
         }
-    } else if (op == kOpDensity) {
-        launch_with_lds(k_density_t<N1, N2, NT>, "k_density_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT, st,
-                        a, t);
     } else {
-        launch_with_lds(k_apply_t<N1, N2, NT>, "k_apply_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT, st, a,
-                        t);
+        TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision plane kernels need the resident ground state");
+        if (op == kOpDensity)
+            launch_with_lds(k_density_t<N1, N2, NT>, "k_density_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT,
+                            st, a, t);
+        else
+            launch_with_lds(k_apply_t<N1, N2, NT>, "k_apply_t", PlaneKernel<N1, N2, NT, kXU>::bytes(), grid, NT, st,
+                            a, t);
     }
 }
 
@@ -914,12 +944,14 @@ struct ZLines {
     __device__ bool valid(int, int) const { return true; }
 };
 
-template <int N3, int NT, int CT, int IT>
+template <int N3, int NT, int CT, int IT, class T2>
 __global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
     constexpr int L = CT * IT;
     constexpr int LS = N3 + 1;
-    extern __shared__ double2 lds[];
-    double2* tw = lds + L * LS;
+    extern __shared__ double2 lds_raw[];
+    T2* lds = reinterpret_cast<T2*>(lds_raw);
+    T2* tw = lds + L * LS;
+    const T2* gtw = pick<T2>(a.tw, a.tw32);
     int* perm = reinterpret_cast<int*>(tw + N3);
     const int b = blockIdx.z;
     const int ncol = a.ncol[b];
@@ -927,10 +959,10 @@ __global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
     if (col0 >= ncol) return;
     const int item0 = blockIdx.y * IT;
     for (int i = threadIdx.x; i < N3; i += NT) {
-        tw[i] = a.tw[i];
+        tw[i] = gtw[i];
         perm[i] = a.perm[i];
     }
-    for (int i = threadIdx.x; i < L * LS; i += NT) lds[i] = cmk(0.0, 0.0);
+    for (int i = threadIdx.x; i < L * LS; i += NT) lds[i] = Cx<T2>::mk(0, 0);
     __syncthreads();
     const int* cp = a.colptr[b];
     const int* eg = a.entg[b];
@@ -942,12 +974,13 @@ __global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
         const int c = col0 + l % CT, item = item0 + l / CT;
         if (c < ncol && item < a.nitems) {
             const double2* src = coef + (long long)item * istr;
-            for (int e = cp[c] + threadIdx.x % PER; e < cp[c + 1]; e += PER) lds[l * LS + ei[e]] = src[eg[e]];
+            for (int e = cp[c] + threadIdx.x % PER; e < cp[c + 1]; e += PER)
+                lds[l * LS + ei[e]] = Cx<T2>::from(src[eg[e]]);
         }
     }
     __syncthreads();
     fft_dif<N3, +1, NT, false>(lds, L, ZLines<LS>{}, tw);
-    double2* out = a.cols + (long long)b * a.nitems * N3 * a.ncol_stride;
+    T2* out = pick<T2>(a.cols, a.cols32) + (long long)b * a.nitems * N3 * a.ncol_stride;
     for (int i = threadIdx.x; i < L * N3; i += NT) {
         const int cl = i % CT, rest = i / CT;
         const int p = rest % N3, il = rest / N3;
@@ -957,12 +990,14 @@ __global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
     }
 }
 
-template <int N3, int NT, int CT, int IT>
+template <int N3, int NT, int CT, int IT, class T2>
 __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
     constexpr int L = CT * IT;
     constexpr int LS = N3 + 1;
-    extern __shared__ double2 lds[];
-    double2* tw = lds + L * LS;
+    extern __shared__ double2 lds_raw[];
+    T2* lds = reinterpret_cast<T2*>(lds_raw);
+    T2* tw = lds + L * LS;
+    const T2* gtw = pick<T2>(a.tw, a.tw32);
     int* perm = reinterpret_cast<int*>(tw + N3);
     const int b = blockIdx.z;
     const int ncol = a.ncol[b];
@@ -978,16 +1013,16 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
     }
     if (col0 >= ncol) return;
     for (int i = threadIdx.x; i < N3; i += NT) {
-        tw[i] = a.tw[i];
+        tw[i] = gtw[i];
         perm[i] = a.perm[i];
     }
     __syncthreads();
-    const double2* cin = a.cols + (long long)b * a.nitems * N3 * a.ncol_stride;
+    const T2* cin = pick<T2>(a.cols, a.cols32) + (long long)b * a.nitems * N3 * a.ncol_stride;
     for (int i = threadIdx.x; i < L * N3; i += NT) {
         const int cl = i % CT, rest = i / CT;
         const int p = rest % N3, il = rest / N3;
         const int c = col0 + cl, item = item0 + il;
-        double2 v = cmk(0.0, 0.0);
+        T2 v = Cx<T2>::mk(0, 0);
         if (c < ncol && item < a.nitems) v = cin[((long long)item * N3 + perm[p]) * a.ncol_stride + c];
         lds[(il * CT + cl) * LS + p] = v;
     }
@@ -1006,7 +1041,7 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
             const long long off = bbase + (long long)item * a.npw_pad;
             for (int en = cp[c] + threadIdx.x % PER; en < cp[c + 1]; en += PER) {
                 const int g = eg[en];
-                const double2 f = cscale(lds[l * LS + ei[en]], a.inv_n);
+                const double2 f = cscale(Cx<double2>::from(lds[l * LS + ei[en]]), a.inv_n);
                 const double2 x = a.xin[off + g];
                 const double s = kin[g] - e;
                 a.out[off + g] = cmk(f.x + s * x.x, f.y + s * x.y);
@@ -1016,14 +1051,22 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
 }
 
 template <int N3, int NT, int CT, int IT>
-void launch_z(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStream_t st) {
+void launch_z(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStream_t st, bool fp32) {
     constexpr int L = CT * IT;
-    const size_t shm = (size_t)L * (N3 + 1) * sizeof(double2) + N3 * sizeof(double2) + N3 * sizeof(int);
+    const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
+    const size_t shm = (size_t)L * (N3 + 1) * esz + N3 * esz + N3 * sizeof(int);
     dim3 grid((ncolmax + CT - 1) / CT, (a.nitems + IT - 1) / IT, nbatch);
-    if (inverse) {
-        TM_LAUNCH((k_zinv_t<N3, NT, CT, IT>), grid, dim3(NT), shm, st, a);
+    if (fp32) {
+        TM_CHECK(a.cols32 != nullptr && a.tw32 != nullptr, TM_EINVAL, "missing single-precision buffers");
+        if (inverse) {
+            TM_LAUNCH((k_zinv_t<N3, NT, CT, IT, float2>), grid, dim3(NT), shm, st, a);
+        } else {
+            TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT, float2>), grid, dim3(NT), shm, st, a);
+        }
+    } else if (inverse) {
+        TM_LAUNCH((k_zinv_t<N3, NT, CT, IT, double2>), grid, dim3(NT), shm, st, a);
     } else {
-        TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT>), grid, dim3(NT), shm, st, a);
+        TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT, double2>), grid, dim3(NT), shm, st, a);
     }
 }
 
@@ -1033,15 +1076,16 @@ bool zpass_fixed_supported(int n3) {
     return n3 == 8 || n3 == 20 || n3 == 24 || n3 == 32 || n3 == 48 || n3 == 96 || n3 == 180;
 }
 
-void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st) {
+void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st,
+                        bool fp32) {
     switch (n3) {
-        case 8: launch_z<8, 256, 16, 4>(inverse, a, ncolmax, nbatch, st); break;
-        case 20: launch_z<20, 256, 16, 4>(inverse, a, ncolmax, nbatch, st); break;
-        case 24: launch_z<24, 256, 16, 4>(inverse, a, ncolmax, nbatch, st); break;
-        case 32: launch_z<32, 256, 16, 2>(inverse, a, ncolmax, nbatch, st); break;
-        case 48: launch_z<48, 256, 16, 2>(inverse, a, ncolmax, nbatch, st); break;
-        case 96: launch_z<96, 256, 16, 1>(inverse, a, ncolmax, nbatch, st); break;
-        case 180: launch_z<180, 256, 16, 1>(inverse, a, ncolmax, nbatch, st); break;
+        case 8: launch_z<8, 256, 16, 4>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 20: launch_z<20, 256, 16, 4>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 24: launch_z<24, 256, 16, 4>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 32: launch_z<32, 256, 16, 2>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 48: launch_z<48, 256, 16, 2>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 96: launch_z<96, 256, 16, 1>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 180: launch_z<180, 256, 16, 1>(inverse, a, ncolmax, nbatch, st, fp32); break;
         default: throw Error{TM_EUNSUPPORTED, "no fixed-size z pass for this grid"};
     }
 }
@@ -1070,23 +1114,23 @@ bool plane_fixed_supported(int n1, int n2) {
 }
 
 static void launch_plane_op(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
-                            hipStream_t st) {
-    if (n1 == 8 && n2 == 8) launch_t<8, 8, 64>(op, a, t, grid, st);
-    else if (n1 == 20 && n2 == 20) launch_t<20, 20, 256>(op, a, t, grid, st);
-    else if (n1 == 24 && n2 == 24) launch_t<24, 24, 256>(op, a, t, grid, st);
-    else if (n1 == 32 && n2 == 32) launch_t<32, 32, 512>(op, a, t, grid, st);
-    else if (n1 == 48 && n2 == 48) launch_t<48, 48, 1024>(op, a, t, grid, st);
+                            hipStream_t st, bool fp32) {
+    if (n1 == 8 && n2 == 8) launch_t<8, 8, 64>(op, a, t, grid, st, fp32);
+    else if (n1 == 20 && n2 == 20) launch_t<20, 20, 256>(op, a, t, grid, st, fp32);
+    else if (n1 == 24 && n2 == 24) launch_t<24, 24, 256>(op, a, t, grid, st, fp32);
+    else if (n1 == 32 && n2 == 32) launch_t<32, 32, 512>(op, a, t, grid, st, fp32);
+    else if (n1 == 48 && n2 == 48) launch_t<48, 48, 1024>(op, a, t, grid, st, fp32);
     else throw Error{TM_EUNSUPPORTED, "no fixed-size plane kernel for this grid"};
 }
 
 void launch_plane_fixed(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2,
-                        hipStream_t st) {
-    launch_plane_op(density ? kOpDensity : kOpApply, a, t, grid, n1, n2, st);
+                        hipStream_t st, bool fp32) {
+    launch_plane_op(density ? kOpDensity : kOpApply, a, t, grid, n1, n2, st, fp32);
 }
 
 void launch_ureal_fixed(const PlaneArgs& a, const PlaneTabs& t, dim3 grid, int n1, int n2, hipStream_t st) {
     TM_CHECK(a.ureal != nullptr && a.uslot != nullptr, TM_EINVAL, "no resident ground-state buffer");
-    launch_plane_op(kOpUreal, a, t, grid, n1, n2, st);
+    launch_plane_op(kOpUreal, a, t, grid, n1, n2, st, false);
 }
 
 }  // namespace tml

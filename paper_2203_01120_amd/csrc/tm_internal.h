@@ -65,6 +65,38 @@ __host__ __device__ inline double2 cscale(double2 a, double s) { return cmk(a.x 
 __host__ __device__ inline double2 cmuli(double2 a) { return cmk(-a.y, a.x); }  // i*a
 __host__ __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
+// the same for single precision (the FP32 bulk path)
+__host__ __device__ inline float2 cmkf(float r, float i) { return make_float2(r, i); }
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return cmkf(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return cmkf(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+    return cmkf(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {
+    return cmkf(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline float2 cconj(float2 a) { return cmkf(a.x, -a.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) { return cmkf(a.x * s, a.y * s); }
+__host__ __device__ inline float2 cmuli(float2 a) { return cmkf(-a.y, a.x); }
+
+// complex type traits: real type, constructor, conversions
+template <class T2>
+struct Cx;
+template <>
+struct Cx<double2> {
+    using R = double;
+    __host__ __device__ static double2 mk(double r, double i) { return make_double2(r, i); }
+    __host__ __device__ static double2 from(double2 a) { return a; }
+    __host__ __device__ static double2 from(float2 a) { return make_double2(a.x, a.y); }
+};
+template <>
+struct Cx<float2> {
+    using R = float;
+    __host__ __device__ static float2 mk(float r, float i) { return make_float2(r, i); }
+    __host__ __device__ static float2 from(double2 a) { return make_float2((float)a.x, (float)a.y); }
+    __host__ __device__ static float2 from(float2 a) { return a; }
+};
+
 // ---------------------------------------------------------------- FFT plans
 constexpr int kMaxRadices = 8;
 struct FFTPlan {
@@ -176,6 +208,7 @@ struct System {
     int nproj;
     FFTPlan plan[3];
     double2* tw[3] = {nullptr, nullptr, nullptr};
+    float2* twf[3] = {nullptr, nullptr, nullptr};  // the same twiddles in single precision
     int* perm[3] = {nullptr, nullptr, nullptr};  // digit reversal of the in-place plane transforms
     // ground-state points (device)
     std::vector<double2*> evc;    // [npts] [nb][2][npw]
@@ -221,24 +254,26 @@ T* dev_upload(System& s, const T* h, size_t count) {
 
 // ---------------------------------------------------------------- launchers
 // fft.hip
+// fp32: single-precision columns (stored in the same buffer, cast to float2)
 void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2* coef, long long coef_bstride,
-                      int nitems, int item_stride, double2* cols, hipStream_t st);
+                      int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32 = false);
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin,
-                      double2* out, hipStream_t st);
+                      double2* out, hipStream_t st, bool fp32 = false);
 void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st);
 // apply.hip
-void launch_density(const System& s, const QSet& q, hipStream_t st);
+void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32 = false);
 void launch_potential(const System& s, const QSet& q, hipStream_t st);
-void launch_apply_planes(const System& s, const QSet& q, hipStream_t st);
+void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32 = false);
 void launch_ureal(const System& s, const QSet& q, hipStream_t st);
 void launch_fxc_setup(System& s, const double* rho_plane, hipStream_t st);
 void launch_coulomb_setup(const System& s, QSet& q, hipStream_t st);
 // gemm.hip
-void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st);
-void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st);
+void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st,
+                     bool f32 = false);
+void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32 = false);
 
 // api.hip
-void apply_fp64(System& s, int iq, const double2* in, double2* out, hipStream_t st);
+void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st);
 void ensure_workspace(System& s, const QSet& q);
 
 }  // namespace tml

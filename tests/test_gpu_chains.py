@@ -180,4 +180,4 @@ def test_chain_invalid_arguments(lib, systems):
     with pytest.raises(lib.TmError):
         lib.tm_chain_begin(h, 3, "x", "pH", 5)
     with pytest.raises(lib.TmError):
-        lib.tm_chain_begin(h, 0, "x", "pH", 5, prec=lib.TM_FP32)
+        lib.tm_chain_begin(h, 0, "x", "pH", 5, prec=7)   # no such precision

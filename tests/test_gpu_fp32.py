@@ -1,0 +1,114 @@
+"""Single-precision bulk mode (TM_FP32) against the FP64 oracle and FP64 chains.
+
+Tolerances, derived from the arithmetic: FP32 unit roundoff u = 2^-24 = 6e-8.
+One apply chains ~13 radix stages per 3D FFT (20^3) and contractions over
+K ~ 2 npw ~ 10^3 (random-walk growth ~ sqrt(K) = 30), so its relative error is
+at most ~1e-6 (measured: 2e-8); the bound is 2e-5.
+
+Spectrum: the strongest peak of |Im chi| moves by at most 0.05 meV (1 % of
+eta = 5 meV).  For the spectrum as a whole, an FP32 apply is L plus a
+perturbation of norm ~ u ||L|| (||L|| ~ Lambda = 4.8 Ha here), which moves
+poles by up to ~1e-7 Ha; with eta = 1.8e-4 Ha that changes Im chi near a
+peak by ~ shift / eta ~ 1e-3 relative, and the recursion amplifies it further
+along a 60-step chain.  The bound on ||Im chi_32 - Im chi_64|| / ||Im chi_64||
+over 400 frequencies from 0 to 1.995 eV is therefore 1e-2 (measured: 3.9e-3
+for the transverse m_+ chain, 4.6e-5 for the longitudinal m_z chain).
+"""
+import numpy as np
+import pytest
+
+from oracle import liouvillian as lv
+
+from gpu_util import desc_from_problem, from_gpu, rel_err, say, to_gpu
+
+pytestmark = pytest.mark.gpu
+
+EV = 27.211386245988
+
+
+@pytest.fixture(scope="module")
+def cubic(cubic_gs, cubic_q):
+    import torch
+    import paper_2203_01120_amd as tm
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    tm.load()
+    prob = lv.build_problem(cubic_gs, cubic_q)
+    h = tm.tm_system_create(desc_from_problem(prob))
+    yield tm, prob, h
+    tm.tm_system_destroy(h)
+
+
+def apply(tm, prob, h, x, prec):
+    import torch
+    info = tm.tm_qset_info_get(h, 0)
+    xin = to_gpu(x, info["npw_pad"])
+    out = torch.empty_like(xin)
+    tm.tm_liouvillian_apply(h, 0, xin, out, prec)
+    torch.cuda.synchronize()
+    got, _ = from_gpu(out, (2, prob.nk, prob.nb, 2, info["npw_pad"]), prob.npw_pad)
+    return got
+
+
+def test_fp32_apply_matches_oracle(cubic):
+    tm, prob, h = cubic
+    for seed in (1, 2):
+        say(f"fp32 apply cubic20 seed {seed}")
+        x = prob.random_projected(seed)
+        ref = prob.apply(x)
+        e32 = rel_err(apply(tm, prob, h, x, tm.TM_FP32), ref)
+        e64 = rel_err(apply(tm, prob, h, x, tm.TM_FP64), ref)
+        say(f"  fp32 apply rel err {e32:.2e} (fp64 {e64:.1e})")
+        assert e32 <= 2e-5, e32
+        assert e64 <= 1e-12
+        assert e32 > 1e-10   # the single-precision kernels ran
+
+
+def peak(tm, coeffs, m, omega0, eta, comp):
+    """Frequency of the largest |Im chi[comp]| within 10 meV of omega0, on a 0.01 meV grid."""
+    w = omega0 + np.arange(-1000, 1001) * 1e-5 / EV
+    c = np.abs(tm.tm_chi(coeffs, m, w, eta)[comp].imag)
+    return w[int(np.argmax(c))]
+
+
+def strongest_peak(chi, omega):
+    """(component, frequency) of the largest interior local maximum of |Im chi|."""
+    a = np.abs(chi.imag)
+    best = (0, 0, -1.0)
+    for c in range(a.shape[0]):
+        for i in range(1, a.shape[1] - 1):
+            if a[c, i] >= a[c, i - 1] and a[c, i] >= a[c, i + 1] and a[c, i] > best[2]:
+                best = (c, i, a[c, i])
+    return best[0], omega[best[1]]
+
+
+@pytest.mark.parametrize("flavour,mu", [("pH", "+"), ("nH", "z")])
+def test_fp32_spectrum_within_bounds(cubic, flavour, mu):
+    tm, prob, h = cubic
+    m = 60
+    say(f"fp32 chain cubic20 {flavour} {mu} {m}")
+    c64 = tm.tm_lanczos_run(h, 0, mu, flavour, m, tm.TM_FP64)
+    c32 = tm.tm_lanczos_run(h, 0, mu, flavour, m, tm.TM_FP32)
+    assert c64["steps_done"] == c32["steps_done"] == m
+    omega = np.arange(400) * 5e-3 / EV
+    eta = 5e-3 / EV
+    x64 = tm.tm_chi(c64, m, omega, eta)
+    x32 = tm.tm_chi(c32, m, omega, eta)
+    l2 = np.linalg.norm(x32.imag - x64.imag) / np.linalg.norm(x64.imag)
+    comp, w0 = strongest_peak(x64, omega)
+    dpeak = abs(peak(tm, c32, m, w0, eta, comp) - peak(tm, c64, m, w0, eta, comp)) * EV * 1e3
+    say(f"  L2 {l2:.2e}, peak shift {dpeak:.4f} meV at {w0 * EV * 1e3:.1f} meV (component {comp}), "
+        f"beta rel diff {np.abs(c32['beta'] - c64['beta']).max() / c64['beta'].max():.2e}")
+    assert l2 <= 1e-2, l2
+    assert dpeak <= 0.05, dpeak
+
+
+def test_fp32_needs_resident_ground_state(cubic):
+    tm, prob, h = cubic
+    tm.tm_system_set_resident_limit(h, 0)
+    try:
+        x = prob.random_projected(3)
+        with pytest.raises(tm.TmError) as e:
+            apply(tm, prob, h, x, tm.TM_FP32)
+        assert e.value.code == -5
+    finally:
+        tm.tm_system_set_resident_limit(h, -1)

@@ -237,7 +237,8 @@ def test_invalid_arguments(lib, tiny):
         lib.tm_liouvillian_apply(tiny.h, 3, x, torch.zeros_like(x))
     assert e.value.code == lib.TM_EINVAL
     with pytest.raises(lib.TmError) as e:
-        lib.tm_liouvillian_apply(tiny.h, 0, x, torch.zeros_like(x), prec=lib.TM_FP32)
+        lib.tm_liouvillian_apply(tiny.h, 0, x, torch.zeros_like(x), prec=7)   # no such precision
+    assert e.value.code == lib.TM_EINVAL
     co = dict(alpha=np.zeros(3, complex), beta=np.zeros(3), gamma=np.zeros(3, complex),
               z=np.zeros((3, 3), complex), n1=1.0, steps_done=2)
     with pytest.raises(lib.TmError):
