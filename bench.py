@@ -194,13 +194,14 @@ def run_qpath(args, tm, torch):
     omega = np.arange(400) * 5e-3 / EV
     eta = 5e-3 / EV
     specs = [(iq, mu) for iq in range(len(qs)) for mu in ("+", "-", "z")]
+    prec = tm.TM_FP32 if args.precision == "fp32" else tm.TM_FP64
     # warm-up: one short chain per q set builds the per-q caches outside the timed region
     for iq in range(len(qs)):
-        tm.tm_lanczos_run(h, iq, "+", "pH", 6)
+        tm.tm_lanczos_run(h, iq, "+", "pH", 6, prec)
     torch.cuda.synchronize()
-    log(f"timed: {len(specs)} chains x {m} steps + chi")
+    log(f"timed: {len(specs)} chains x {m} steps + chi ({args.precision})")
     t0 = time.perf_counter()
-    chains = [tm.tm_chain_begin(h, iq, mu, "pH", m) for iq, mu in specs]
+    chains = [tm.tm_chain_begin(h, iq, mu, "pH", m, prec) for iq, mu in specs]
     tm.tm_chains_step(chains, m)
     coeffs = [tm.tm_chain_coeffs(c, m) for c in chains]
     spectra = [tm.tm_chi(co, co["steps_done"], omega, eta) for co in coeffs]
@@ -225,11 +226,11 @@ def run_qpath(args, tm, torch):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32" if prec == tm.TM_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": "cubic a=10 bohr, 2 sites, 20^3 grid, 8 bands, Gamma; 24 q on Gamma-M-K-Gamma "
                                "x (m_+, m_-, m_z) = 72 pseudo-Hermitian chains, chi on 400 omega each",
-                   "chains": len(specs), "chain_steps": m, "precision": "fp64"},
+                   "chains": len(specs), "chain_steps": m, "precision": args.precision},
         "applies_per_s": round((steps + len(specs)) / dt, 1),
         "breakdowns": nbroken,
     }

@@ -90,6 +90,86 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     }
 }
 
+// The same contraction with both operands of a K-chunk staged in LDS: one
+// block per (batch, K split) computes every 16x16 output tile from LDS (waves
+// take tiles in turn), so each operand element is read from memory once
+// instead of once per output tile.  Needs M, Nn <= 16 * kMaxTiles1D.
+constexpr int kCnThreads = 512;
+constexpr int kCnChunk = 16;          // K values per LDS chunk
+constexpr int kMaxTiles1D = 14;       // M, Nn up to 224
+constexpr int kCnTilesPerWave = 7;    // (mt * nt) / 8 waves, at most
+
+template <class R>
+struct LdsC {
+    R re, im;
+};
+
+template <class R>
+__global__ void __launch_bounds__(kCnThreads) k_gemm_cn_lds(GemmCN g, int mt) {
+    extern __shared__ double lds_raw[];
+    constexpr int LS = kCnChunk + 1;  // padded row
+    const int Mp = mt * 16, Np = g.nt * 16;
+    LdsC<R>* As = reinterpret_cast<LdsC<R>*>(lds_raw);
+    LdsC<R>* Bs = As + Mp * LS;
+    const int b = blockIdx.y, ks = blockIdx.x;
+    const double2* A = g.A_tab ? g.A_tab[b] : g.A_base + (long long)b * g.a_bstride;
+    const double2* B = g.B_base + (long long)b * g.b_bstride;
+    const int kbeg = ks * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+    const int l = threadIdx.x & 63, w = threadIdx.x >> 6, i = l & 15, kk = l >> 4;
+    const int ntiles = mt * g.nt;
+    typename MF<R>::V cr[kCnTilesPerWave], ci[kCnTilesPerWave];
+#pragma unroll
+    for (int t = 0; t < kCnTilesPerWave; ++t) {
+        cr[t] = typename MF<R>::V{0, 0, 0, 0};
+        ci[t] = typename MF<R>::V{0, 0, 0, 0};
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += kCnChunk) {
+        // stage A[0..Mp)[k0..k0+16) and B[0..Np)[k0..k0+16); rows past M / Nn and k past K read as zero
+        for (int e = threadIdx.x; e < (Mp + Np) * kCnChunk; e += kCnThreads) {
+            const int row = e / kCnChunk, kx = k0 + (e - row * kCnChunk);
+            const bool isA = row < Mp;
+            const int r = isA ? row : row - Mp;
+            double2 v = cmk(0.0, 0.0);
+            if (kx < kend && (isA ? r < g.M : r < g.Nn))
+                v = isA ? A[(long long)r * g.lda + kx] : B[(long long)r * g.ldb + kx];
+            LdsC<R>* dst = isA ? As : Bs;
+            dst[r * LS + (e - row * kCnChunk)] = LdsC<R>{(R)v.x, (R)v.y};
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < kCnTilesPerWave; ++t) {
+            const int tile = w + 8 * t;
+            if (tile < ntiles) {
+                const int m0 = (tile / g.nt) * 16, n0 = (tile % g.nt) * 16;
+#pragma unroll
+                for (int k4 = 0; k4 < kCnChunk; k4 += 4) {
+                    const LdsC<R> a = As[(m0 + i) * LS + k4 + kk];
+                    const LdsC<R> bv = Bs[(n0 + i) * LS + k4 + kk];
+                    cr[t] = mfma(a.re, bv.re, cr[t]);
+                    cr[t] = mfma(a.im, bv.im, cr[t]);
+                    ci[t] = mfma(a.re, bv.im, ci[t]);
+                    ci[t] = mfma(-a.im, bv.re, ci[t]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    double2* out = g.part + ((long long)b * g.ksplit + ks) * g.M * g.Nn;
+#pragma unroll
+    for (int t = 0; t < kCnTilesPerWave; ++t) {
+        const int tile = w + 8 * t;
+        if (tile < ntiles) {
+            const int m0 = (tile / g.nt) * 16, n0 = (tile % g.nt) * 16;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + MF<R>::row(v, kk), n = n0 + i;
+                if (m < g.M && n < g.Nn) out[(long long)m * g.Nn + n] = cmk((double)cr[t][v], (double)ci[t][v]);
+            }
+        }
+    }
+}
+
 __global__ void k_reduce_parts(const double2* part, double2* out, int ksplit, long long mn, int nbatch) {
     long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= mn * nbatch) return;
@@ -163,6 +243,21 @@ __global__ void k_dmat(const double2* Bm, const double2* D, double2* Wm, int npr
     Wm[idx] = acc;
 }
 
+// the LDS-staged kernel needs its tiles to fit the waves, and enough tiles to
+// keep its 8 waves busy (single-tile products stay on k_gemm_cn)
+bool cn_lds_fits(int M, int Nn) {
+    const int mt = (M + 15) / 16, nt = (Nn + 15) / 16;
+    return mt <= kMaxTiles1D && nt <= kMaxTiles1D && mt * nt <= 8 * kCnTilesPerWave && mt * nt >= 8;
+}
+
+// K range per block: about 4 blocks per CU over all batches, a multiple of the LDS chunk
+int cn_lds_kchunk(int K, int nbatch) {
+    const int ks = std::max(1, 1024 / std::max(1, nbatch));
+    int kc = (K + ks - 1) / ks;
+    kc = std::max(kCnChunk * 4, (kc + kCnChunk - 1) / kCnChunk * kCnChunk);
+    return kc;
+}
+
 int choose_kchunk(int K, long long tiles_times_batch) {
     // enough waves to fill the chip, but chunks of at least 64
     long long target = 8192;
@@ -187,15 +282,31 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
     g.K = K;
     int mt = (M + 15) / 16;
     g.nt = (Nn + 15) / 16;
-    g.kchunk = choose_kchunk(K, (long long)mt * g.nt * nbatch);
-    g.ksplit = (K + g.kchunk - 1) / g.kchunk;
-    TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
     g.part = s.ws.gpart;
-    dim3 grid(mt * g.nt, g.ksplit, nbatch);
-    if (f32) {
-        TM_LAUNCH(k_gemm_cn<float>, grid, dim3(64), 0, st, g);
+    if (cn_lds_fits(M, Nn)) {
+        g.kchunk = cn_lds_kchunk(K, nbatch);
+        g.ksplit = (K + g.kchunk - 1) / g.kchunk;
+        TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
+        const size_t shm = (size_t)(mt + g.nt) * 16 * (kCnChunk + 1) * (f32 ? 8 : 16);
+        dim3 grid(g.ksplit, nbatch);
+        const void* fn = f32 ? (const void*)k_gemm_cn_lds<float> : (const void*)k_gemm_cn_lds<double>;
+        TM_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess,
+                 TM_EDEVICE, "cannot raise the LDS limit of k_gemm_cn_lds");
+        if (f32) {
+            TM_LAUNCH(k_gemm_cn_lds<float>, grid, dim3(kCnThreads), shm, st, g, mt);
+        } else {
+            TM_LAUNCH(k_gemm_cn_lds<double>, grid, dim3(kCnThreads), shm, st, g, mt);
+        }
     } else {
-        TM_LAUNCH(k_gemm_cn<double>, grid, dim3(64), 0, st, g);
+        g.kchunk = choose_kchunk(K, (long long)mt * g.nt * nbatch);
+        g.ksplit = (K + g.kchunk - 1) / g.kchunk;
+        TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
+        dim3 grid(mt * g.nt, g.ksplit, nbatch);
+        if (f32) {
+            TM_LAUNCH(k_gemm_cn<float>, grid, dim3(64), 0, st, g);
+        } else {
+            TM_LAUNCH(k_gemm_cn<double>, grid, dim3(64), 0, st, g);
+        }
     }
     long long mn = (long long)M * Nn;
     TM_LAUNCH(k_reduce_parts, dim3((unsigned)((mn * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
@@ -233,7 +344,7 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
 
 size_t gemm_partial_elems(int nbatch, int M, int Nn, int K) {
     int mt = (M + 15) / 16, nt = (Nn + 15) / 16;
-    int kc = choose_kchunk(K, (long long)mt * nt * nbatch);
+    int kc = cn_lds_fits(M, Nn) ? cn_lds_kchunk(K, nbatch) : choose_kchunk(K, (long long)mt * nt * nbatch);
     int ks = (K + kc - 1) / kc;
     return (size_t)nbatch * ks * M * Nn;
 }
