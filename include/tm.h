@@ -259,6 +259,34 @@ int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, doubl
            double* chi);
 
 /*
+ * tm_chi_extrapolated: tm_chi on a tridiagonal matrix extended from m_use
+ * computed steps to m_total (Sec. 2.5, last paragraph on the Lanczos
+ * algorithm; the turbo_spectrum inputs itermax0 = m_use, itermax = m_total,
+ * extrapolation = 'constant' | 'osc' of Sec. 4 and Table 2).  The paper names
+ * the schemes without formulas; this library's reading: past m_use, alpha,
+ * beta and gamma take their mean over the second half of the computed
+ * coefficients (indices m_use/2 .. m_use-1) -- one mean (TM_EXTRAP_CONSTANT)
+ * or one per parity of the index (TM_EXTRAP_OSC, bi-constant) -- and z is
+ * zero (no overlaps were measured there).  TM_EXTRAP_NONE requires
+ * m_total == m_use and equals tm_chi.  m_use >= 4 when extrapolating.
+ * Work memory on the device: 64 * m_total * nomega bytes.  Synchronous.
+ */
+typedef enum { TM_EXTRAP_NONE = 0, TM_EXTRAP_CONSTANT = 1, TM_EXTRAP_OSC = 2 } tm_extrap;
+int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega,
+                        int nomega, double eta, double* chi);
+
+/*
+ * tm_structure_factor: S(q, omega) = -Im Tr[P_perp(q) chi(q, q; omega)]
+ * (Eq. S_def), P_perp_ab = delta_ab - q_a q_b / q^2.
+ * q: host [3] Cartesian (bohr^-1), nonzero (TM_EINVAL for q = 0).
+ * chi: host complex chi_{lambda mu}(omega) at index (lambda * 3 + mu) * nomega
+ *   + omega (interleaved re, im); column mu is what tm_chi returns for the
+ *   chain with field direction mu (x, y, z).
+ * s: host [nomega].  Host arithmetic only; synchronous.
+ */
+int tm_structure_factor(const double* q, const double* chi, int nomega, double* s);
+
+/*
  * Kernel timing.  While enabled, every kernel launch of the library is
  * bracketed by two HIP events on the stream it runs on; tm_profile_count
  * synchronises the device, folds the elapsed times per kernel name and

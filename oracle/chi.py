@@ -68,6 +68,45 @@ def chi_pole_residue(coeffs, omega, eta, m_use=None):
     return coeffs["n1"] * np.einsum("lj,j,jw->lw", zR, left, 1.0 / (wc - lam[:, None]))
 
 
+def extrapolate(coeffs, m_use, m_total, mode):
+    """Coefficients extended from m_use computed steps to m_total.
+
+    The paper names two schemes ('constant' and the bi-constant 'osc'; Sec. 2.5,
+    last paragraph, and the turbo_spectrum inputs of Sec. 4) without formulas.
+    Reading: past m_use, alpha, beta and gamma take their mean over the second
+    half of the computed coefficients -- one mean ('constant') or one for each
+    parity of the index ('osc') -- and z is zero there (nothing was measured).
+    """
+    out = {k: coeffs[k] for k in ("n1",)}
+    a = np.zeros(m_total, dtype=np.complex128)
+    b = np.zeros(m_total)
+    g = np.zeros(m_total, dtype=np.complex128)
+    z = np.zeros((coeffs["z"].shape[0], m_total), dtype=np.complex128)
+    a[:m_use] = coeffs["alpha"][:m_use]
+    b[:m_use] = coeffs["beta"][:m_use]
+    g[:m_use] = coeffs["gamma"][:m_use]
+    z[:, :m_use] = coeffs["z"][:, :m_use]
+    if m_total > m_use:
+        period = {"constant": 1, "osc": 2}[mode]
+        window = np.arange(m_use // 2, m_use)
+        for p in range(period):
+            sel = window[window % period == p]
+            tail = np.arange(m_use, m_total)
+            tail = tail[tail % period == p]
+            a[tail] = a[sel].mean()
+            b[tail] = b[sel].mean()
+            g[tail] = g[sel].mean()
+    out.update(alpha=a, beta=b, gamma=g, z=z, steps_done=m_total)
+    return out
+
+
+def structure_factor(q, chi):
+    """S(q, w) = -Im Tr[P_perp(q) chi(w)] (Eq. S_def), chi[lambda][mu][w]."""
+    q = np.asarray(q, dtype=float)
+    P = np.eye(3) - np.outer(q, q) / q.dot(q)
+    return -np.einsum("ab,baw->w", P, chi).imag
+
+
 def kubo_k0(gs, prob, lam, mu, omega, eta):
     """Textbook K = 0 (independent-particle) transverse susceptibility.
 

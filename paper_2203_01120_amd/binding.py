@@ -25,7 +25,7 @@ FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
             "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
-            "tm_chain_coeffs", "tm_chain_end",
+            "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -81,6 +81,10 @@ def load(path: str = LIB_PATH):
     lib.tm_chain_coeffs.argtypes = [C.c_void_p, C.POINTER(_Coeffs)]
     lib.tm_chain_end.argtypes = [C.c_void_p]
     lib.tm_chains_use_graphs.argtypes = [C.c_int]
+    lib.tm_chi_extrapolated.argtypes = [C.POINTER(_Coeffs), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                        C.c_int, C.c_double, C.POINTER(C.c_double)]
+    lib.tm_structure_factor.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
+                                        C.POINTER(C.c_double)]
     lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -320,6 +324,37 @@ def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:
     out = np.zeros((3, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi(C.byref(co), int(m_use), _dptr(om), om.shape[0], float(eta),
                          out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+EXTRAP = {"no": 0, "constant": 1, "osc": 2}
+
+
+def tm_chi_extrapolated(coeffs: dict, m_use: int, m_total: int, mode: str, omega, eta: float) -> np.ndarray:
+    """chi[l][w] with the tridiagonal matrix extended to m_total ('no', 'constant', 'osc')."""
+    alpha = np.ascontiguousarray(coeffs["alpha"], dtype=np.complex128)
+    beta = np.ascontiguousarray(coeffs["beta"], dtype=np.float64)
+    gamma = np.ascontiguousarray(coeffs["gamma"], dtype=np.complex128)
+    z = np.ascontiguousarray(coeffs["z"], dtype=np.complex128)
+    cap = alpha.shape[0]
+    co = _Coeffs(cap, int(coeffs["steps_done"]), float(coeffs["n1"]),
+                 alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
+                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros((3, om.shape[0]), dtype=np.complex128)
+    _check(load().tm_chi_extrapolated(C.byref(co), int(m_use), int(m_total), EXTRAP[mode], _dptr(om),
+                                      om.shape[0], float(eta), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def tm_structure_factor(q, chi) -> np.ndarray:
+    """S(q, w) = -Im Tr[P_perp(q) chi(w)] from chi[lambda][mu][w] (complex 3 x 3 x nomega)."""
+    qv = np.ascontiguousarray(q, dtype=np.float64)
+    ch = np.ascontiguousarray(chi, dtype=np.complex128)
+    assert ch.shape[:2] == (3, 3)
+    out = np.zeros(ch.shape[2])
+    _check(load().tm_structure_factor(_dptr(qv), ch.ctypes.data_as(C.POINTER(C.c_double)), ch.shape[2],
+                                      _dptr(out)))
     return out
 
 

@@ -1144,15 +1144,62 @@ int tm_chain_end(tm_chain* chain) {
 }
 
 int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, double eta, double* chi) {
+    return tm_chi_extrapolated(c, m_use, m_use, TM_EXTRAP_NONE, omega, nomega, eta, chi);
+}
+
+int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega,
+                        int nomega, double eta, double* chi) {
     return guarded([&]() -> int {
         TM_CHECK(c && omega && chi, TM_EINVAL, "null argument");
         TM_CHECK(m_use >= 1 && m_use <= c->steps_done && m_use <= c->capacity, TM_EINVAL,
                  "m_use must be in [1, steps_done]");
+        TM_CHECK(mode == TM_EXTRAP_NONE || mode == TM_EXTRAP_CONSTANT || mode == TM_EXTRAP_OSC, TM_EINVAL,
+                 "bad extrapolation mode");
+        TM_CHECK(mode == TM_EXTRAP_NONE ? m_total == m_use : m_total >= m_use, TM_EINVAL,
+                 "m_total must equal m_use without extrapolation and be >= m_use with it");
+        TM_CHECK(mode == TM_EXTRAP_NONE || m_use >= 4, TM_EINVAL, "extrapolation needs at least 4 steps");
         TM_CHECK(nomega >= 0, TM_EINVAL, "negative nomega");
         if (nomega == 0) return TM_OK;
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error{TM_EDEVICE, "no HIP device"};
-        const int M = m_use, cap = c->capacity;
+        const int M0 = m_use, M = m_total, cap = c->capacity;
+        // host coefficients, extended past M0: alpha, beta, gamma by their mean over
+        // the second half of the computed ones (one mean: constant; one per parity
+        // of the index: osc), z = 0 beyond M0 (no measured overlaps there)
+        std::vector<double2> ha(M), hg(M), hz(3 * (size_t)M, cmk(0.0, 0.0));
+        std::vector<double> hb(M);
+        for (int j = 0; j < M0; ++j) {
+            ha[j] = cmk(c->alpha[2 * j], c->alpha[2 * j + 1]);
+            hb[j] = c->beta[j];
+            hg[j] = cmk(c->gamma[2 * j], c->gamma[2 * j + 1]);
+            for (int l = 0; l < 3; ++l)
+                hz[(size_t)l * M + j] = cmk(c->z[2 * ((size_t)l * cap + j)], c->z[2 * ((size_t)l * cap + j) + 1]);
+        }
+        if (M > M0) {
+            const int np = mode == TM_EXTRAP_OSC ? 2 : 1;
+            double2 ma[2] = {cmk(0, 0), cmk(0, 0)}, mg[2] = {cmk(0, 0), cmk(0, 0)};
+            double mb[2] = {0, 0};
+            int cnt[2] = {0, 0};
+            for (int j = M0 / 2; j < M0; ++j) {
+                const int p = j % np;
+                ma[p] = cadd(ma[p], ha[j]);
+                mg[p] = cadd(mg[p], hg[j]);
+                mb[p] += hb[j];
+                ++cnt[p];
+            }
+            for (int p = 0; p < np; ++p) {
+                TM_CHECK(cnt[p] > 0, TM_EINVAL, "too few steps to extrapolate");
+                ma[p] = cscale(ma[p], 1.0 / cnt[p]);
+                mg[p] = cscale(mg[p], 1.0 / cnt[p]);
+                mb[p] /= cnt[p];
+            }
+            for (int j = M0; j < M; ++j) {
+                const int p = j % np;
+                ha[j] = ma[p];
+                hb[j] = mb[p];
+                hg[j] = mg[p];
+            }
+        }
         std::vector<void*> mem;
         struct G {
             std::vector<void*>& m;
@@ -1174,12 +1221,10 @@ int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, doubl
         double2* work = (double2*)al(4 * (size_t)M * nomega * sizeof(double2));
         double2* dchi = (double2*)al(3 * (size_t)nomega * sizeof(double2));
         int* dst = (int*)al(sizeof(int));
-        TM_HIP(hipMemcpy(da, c->alpha, M * sizeof(double2), hipMemcpyHostToDevice));
-        TM_HIP(hipMemcpy(db, c->beta, M * sizeof(double), hipMemcpyHostToDevice));
-        TM_HIP(hipMemcpy(dg, c->gamma, M * sizeof(double2), hipMemcpyHostToDevice));
-        for (int l = 0; l < 3; ++l)
-            TM_HIP(hipMemcpy(dz + (size_t)l * M, c->z + 2 * (size_t)l * cap, M * sizeof(double2),
-                             hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(da, ha.data(), M * sizeof(double2), hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(db, hb.data(), M * sizeof(double), hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(dg, hg.data(), M * sizeof(double2), hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(dz, hz.data(), 3 * (size_t)M * sizeof(double2), hipMemcpyHostToDevice));
         TM_HIP(hipMemcpy(dw, omega, nomega * sizeof(double), hipMemcpyHostToDevice));
         TM_HIP(hipMemset(dst, 0, sizeof(int)));
         launch_chi(da, db, dg, dz, M, M, c->n1, dw, nomega, eta, work, dchi, dst, nullptr);
@@ -1187,6 +1232,25 @@ int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, doubl
         TM_HIP(hipMemcpy(&status, dst, sizeof(int), hipMemcpyDeviceToHost));
         TM_HIP(hipMemcpy(chi, dchi, 3 * (size_t)nomega * sizeof(double2), hipMemcpyDeviceToHost));
         TM_CHECK(status == 0, TM_EINVAL, "singular tridiagonal system (eta = 0 on a pole?)");
+        return TM_OK;
+    });
+}
+
+int tm_structure_factor(const double* q, const double* chi, int nomega, double* s) {
+    return guarded([&]() -> int {
+        TM_CHECK(q && chi && s && nomega >= 0, TM_EINVAL, "bad argument");
+        const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        TM_CHECK(q2 > 0.0, TM_EINVAL, "q = 0 has no transverse projector");
+        // P_ab = delta_ab - q_a q_b / q^2;  S = -Im sum_ab P_ab chi_ba
+        for (int w = 0; w < nomega; ++w) {
+            double acc = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    const double p = (a == b ? 1.0 : 0.0) - q[a] * q[b] / q2;
+                    acc += p * chi[2 * (((size_t)b * 3 + a) * nomega + w) + 1];
+                }
+            s[w] = -acc;
+        }
         return TM_OK;
     });
 }

@@ -250,3 +250,71 @@ def test_reprojection_removes_occupied_leakage():
     assert np.abs(a["beta"][:k] - b["beta"][:k]).max() <= 1e-8 * b["beta"][:k].max()
     assert lanczos.run(prob, "+", "pH", 1)["n1"] > 0
     assert prob.occupied_overlap(prob.random_projected(3)) < 1e-12
+
+
+def _chain(alpha, beta, gamma):
+    m = len(alpha)
+    z = np.zeros((3, m), dtype=np.complex128)
+    z[0, 0] = 1.0
+    return dict(alpha=np.asarray(alpha, dtype=np.complex128), beta=np.asarray(beta, dtype=float),
+                gamma=np.asarray(gamma, dtype=np.complex128), z=z, n1=1.0, steps_done=m)
+
+
+def test_constant_extrapolation_reaches_the_infinite_chain():
+    """A chain with constant a, b continued by 'constant' extrapolation tends to
+    the closed-form Green's function of the infinite chain,
+    G = (w' - a - sqrt((w' - a)^2 - 4 b^2)) / (2 b^2), Im G < 0."""
+    a, b, eta = 0.3, 0.5, 0.05
+    co = _chain([a] * 8, [b] * 8, [b] * 8)
+    omega = np.linspace(-1.5, 2.0, 71)
+    ext = chi.extrapolate(co, 8, 3000, "constant")
+    got = chi.chi_lanczos(ext, omega, eta, 3000)[0]
+    wc = omega + 1j * eta
+    r = np.sqrt((wc - a) ** 2 - 4 * b * b)
+    G = np.where(((wc - a - r) / (2 * b * b)).imag < 0, (wc - a - r) / (2 * b * b), (wc - a + r) / (2 * b * b))
+    assert np.abs(got - G).max() <= 1e-8 * np.abs(G).max()
+    # without extrapolation the 8-step chain is visibly different (finite poles)
+    assert np.abs(chi.chi_lanczos(co, omega, eta, 8)[0] - G).max() > 1e-2 * np.abs(G).max()
+
+
+def test_osc_extrapolation_reaches_the_two_periodic_chain():
+    """Alternating couplings b1, b2 (alpha = 0) continued by the bi-constant scheme
+    tend to the closed form of the 2-periodic infinite chain:
+    w b2^2 G^2 - (w^2 - b1^2 + b2^2) G + w = 0 (the root with Im G < 0)."""
+    b1, b2, eta = 0.6, 0.25, 0.04
+    co = _chain([0.0] * 8, [b1, b2] * 4, [b1, b2] * 4)
+    omega = np.linspace(0.05, 1.2, 47)
+    ext = chi.extrapolate(co, 8, 4000, "osc")
+    got = chi.chi_lanczos(ext, omega, eta, 4000)[0]
+    w = omega + 1j * eta
+    A, B, Cc = w * b2 ** 2, -(w ** 2 - b1 ** 2 + b2 ** 2), w
+    disc = np.sqrt(B * B - 4 * A * Cc)
+    r1, r2 = (-B + disc) / (2 * A), (-B - disc) / (2 * A)
+    G = np.where(r1.imag < 0, r1, r2)
+    assert np.all(G.imag < 0)
+    assert np.abs(got - G).max() <= 1e-8 * np.abs(G).max()
+    # the constant scheme averages b1 and b2 and misses the gap structure
+    cst = chi.chi_lanczos(chi.extrapolate(co, 8, 4000, "constant"), omega, eta, 4000)[0]
+    assert np.abs(cst - G).max() > 1e-2 * np.abs(G).max()
+
+
+def test_no_extrapolation_is_the_plain_chain(tiny_prob):
+    c = lanczos.run(tiny_prob, "z", "pH", 12)
+    omega = np.linspace(0.0, 0.1, 9)
+    ext = chi.extrapolate(c, 12, 12, "constant")
+    assert np.array_equal(chi.chi_lanczos(ext, omega, 1e-3, 12), chi.chi_lanczos(c, omega, 1e-3, 12))
+
+
+def test_structure_factor_transverse_projector():
+    """q along z keeps -Im(chi_xx + chi_yy); S is invariant under a common rotation of q and chi."""
+    rng = np.random.default_rng(4)
+    c3 = rng.standard_normal((3, 3, 5)) + 1j * rng.standard_normal((3, 3, 5))
+    s = chi.structure_factor([0, 0, 0.7], c3)
+    assert np.allclose(s, -(c3[0, 0] + c3[1, 1]).imag, atol=1e-14)
+    th = 0.83
+    Rz = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1]])
+    Rx = np.array([[1, 0, 0], [0, np.cos(0.4), -np.sin(0.4)], [0, np.sin(0.4), np.cos(0.4)]])
+    R = Rx @ Rz
+    q = np.array([0.2, -0.1, 0.5])
+    rot = np.einsum("ab,bcw,dc->adw", R, c3, R)
+    assert np.allclose(chi.structure_factor(R @ q, rot), chi.structure_factor(q, c3), atol=1e-13)
