@@ -126,7 +126,9 @@ typedef struct {
  * Sec. 2.2), the ALSDA kernel fields (Eqs. v_XC_q, b_XC_q) and the Coulomb
  * multipliers 4 pi / |G+q|^2 (Eq. v_H_q).
  * Returns TM_EINVAL for inconsistent input (e.g. the sphere of -k-q is not the
- * negative of the sphere of k+q), TM_EUNSUPPORTED for unsupported grid sizes,
+ * negative of the sphere of k+q) and for a NaN or Inf in any floating-point
+ * input (checked on the host before the device is touched), TM_EUNSUPPORTED
+ * for unsupported grid sizes,
  * TM_ENOMEM / TM_EDEVICE for device failures.  *out owns all device memory.
  */
 int tm_system_create(const tm_system_desc* desc, tm_system** out);
@@ -248,6 +250,29 @@ int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out);
 int tm_chain_end(tm_chain* chain);
 
 /*
+ * Chain checkpoint and restart (the restart / restart_step inputs of
+ * turbo_magnon, Sec. 3.2 and Table 1): the chain's complete state -- its BR
+ * vectors, the three u^lambda, the coefficients and the device scale/step
+ * state -- as one host blob.
+ * tm_chain_state_size: bytes of the blob (pseudo-Hermitian: 8 BR vectors,
+ *   non-Hermitian: 12, plus 88 bytes per step of capacity and a header).
+ * tm_chain_save: waits for the chain's last stream and copies its state into
+ *   `host` (caller-owned, at least tm_chain_state_size bytes); the chain stays
+ *   usable.
+ * tm_chain_restore: a new chain of system `sys` from a blob saved from a chain
+ *   of the same system (same q set shapes; TM_EINVAL otherwise), with
+ *   capacity max(capacity, saved capacity) -- a restart may run more steps
+ *   than the original chain was sized for.  Stepping it continues the
+ *   recursion exactly where the saved chain stood: the coefficients equal
+ *   those of an uninterrupted chain bit for bit.  Synchronises `stream`; the
+ *   blob may be released when the call returns.
+ */
+int tm_chain_state_size(const tm_chain* chain, size_t* bytes);
+int tm_chain_save(tm_chain* chain, void* host, size_t bytes);
+int tm_chain_restore(tm_system* sys, const void* host, size_t bytes, int capacity, void* stream,
+                     tm_chain** out);
+
+/*
  * tm_chi: chi_l(omega_j) = n1 sum_i z[l][i] eta_i with
  *   ((omega_j + i eta) I - T) eta = e_1            (Eq. post_processing)
  * over the first m_use steps (m_use <= c->steps_done), l = x, y, z.
@@ -262,7 +287,7 @@ int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, doubl
  * tm_chi_extrapolated: tm_chi on a tridiagonal matrix extended from m_use
  * computed steps to m_total (Sec. 2.5, last paragraph on the Lanczos
  * algorithm; the turbo_spectrum inputs itermax0 = m_use, itermax = m_total,
- * extrapolation = 'constant' | 'osc' of Sec. 4 and Table 2).  The paper names
+ * extrapolation = 'constant' | 'osc' of Sec. 3.3 and Table 2).  The paper names
  * the schemes without formulas; this library's reading: past m_use, alpha,
  * beta and gamma take their mean over the second half of the computed
  * coefficients (indices m_use/2 .. m_use-1) -- one mean (TM_EXTRAP_CONSTANT)

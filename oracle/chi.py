@@ -72,7 +72,7 @@ def extrapolate(coeffs, m_use, m_total, mode):
     """Coefficients extended from m_use computed steps to m_total.
 
     The paper names two schemes ('constant' and the bi-constant 'osc'; Sec. 2.5,
-    last paragraph, and the turbo_spectrum inputs of Sec. 4) without formulas.
+    last paragraph, and the turbo_spectrum inputs of Sec. 3.3) without formulas.
     Reading: past m_use, alpha, beta and gamma take their mean over the second
     half of the computed coefficients -- one mean ('constant') or one for each
     parity of the index ('osc') -- and z is zero there (nothing was measured).

@@ -26,6 +26,7 @@ FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
             "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
+            "tm_chain_state_size", "tm_chain_save", "tm_chain_restore",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -81,6 +82,10 @@ def load(path: str = LIB_PATH):
     lib.tm_chain_coeffs.argtypes = [C.c_void_p, C.POINTER(_Coeffs)]
     lib.tm_chain_end.argtypes = [C.c_void_p]
     lib.tm_chains_use_graphs.argtypes = [C.c_int]
+    lib.tm_chain_state_size.argtypes = [C.c_void_p, C.POINTER(C.c_size_t)]
+    lib.tm_chain_save.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    lib.tm_chain_restore.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]
     lib.tm_chi_extrapolated.argtypes = [C.POINTER(_Coeffs), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.c_int, C.c_double, C.POINTER(C.c_double)]
     lib.tm_structure_factor.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
@@ -304,6 +309,24 @@ def tm_chain_coeffs(chain, capacity: int) -> dict:
 def tm_chains_use_graphs(on: bool) -> None:
     """Process-wide: replay chain steps from captured HIP graphs (default) or issue them directly."""
     _check(load().tm_chains_use_graphs(1 if on else 0))
+
+
+def tm_chain_save(chain) -> np.ndarray:
+    """The chain's complete state as a host byte array (waits for its stream)."""
+    n = C.c_size_t(0)
+    _check(load().tm_chain_state_size(C.c_void_p(chain), C.byref(n)))
+    buf = np.empty(n.value, dtype=np.uint8)
+    _check(load().tm_chain_save(C.c_void_p(chain), C.c_void_p(buf.ctypes.data), n.value))
+    return buf
+
+
+def tm_chain_restore(h, blob: np.ndarray, capacity: int = 0, stream=None) -> int:
+    """A new chain continuing a saved one (capacity may grow)."""
+    blob = np.ascontiguousarray(blob, dtype=np.uint8)
+    out = C.c_void_p()
+    _check(load().tm_chain_restore(C.c_void_p(h), C.c_void_p(blob.ctypes.data), blob.nbytes, int(capacity),
+                                   _stream(stream), C.byref(out)))
+    return out.value
 
 
 def tm_chain_end(chain) -> None:

@@ -791,6 +791,146 @@ static int chain_coeffs(Chain& c, tm_coeffs* out) {
     return h.broken ? TM_EBREAKDOWN : TM_OK;
 }
 
+// ---- checkpoint: header, device state struct, coefficients, vectors
+struct ChainBlobHeader {
+    char magic[8];       // "TMCHAIN1"
+    int iq, dir, flavour, fp32, cap, issued, nvec;
+    int ix[9];
+    long long n;
+};
+
+static size_t chain_blob_bytes(const Chain& c) {
+    return sizeof(ChainBlobHeader) + sizeof(ChainState) + (size_t)c.cap * (3 * sizeof(double2) + sizeof(double)) +
+           3 * (size_t)c.cap * sizeof(double2) + (c.vec.size() + 3) * (size_t)c.n * sizeof(double2);
+}
+
+static void chain_save(Chain& c, char* out) {
+    TM_HIP(hipStreamSynchronize(c.last));
+    ChainBlobHeader h{};
+    std::memcpy(h.magic, "TMCHAIN1", 8);
+    h.iq = c.iq;
+    h.dir = c.dir;
+    h.flavour = c.flavour;
+    h.fp32 = c.fp32 ? 1 : 0;
+    h.cap = c.cap;
+    h.issued = c.issued;
+    h.nvec = (int)c.vec.size();
+    std::copy(c.ix, c.ix + 9, h.ix);
+    h.n = c.n;
+    char* p = out;
+    std::memcpy(p, &h, sizeof(h));
+    p += sizeof(h);
+    TM_HIP(hipMemcpy(p, c.cs, sizeof(ChainState), hipMemcpyDeviceToHost));
+    p += sizeof(ChainState);
+    TM_HIP(hipMemcpy(p, c.co.alpha, c.cap * sizeof(double2), hipMemcpyDeviceToHost));
+    p += c.cap * sizeof(double2);
+    TM_HIP(hipMemcpy(p, c.co.beta, c.cap * sizeof(double), hipMemcpyDeviceToHost));
+    p += c.cap * sizeof(double);
+    TM_HIP(hipMemcpy(p, c.co.gamma, c.cap * sizeof(double2), hipMemcpyDeviceToHost));
+    p += c.cap * sizeof(double2);
+    TM_HIP(hipMemcpy(p, c.co.z, 3 * (size_t)c.cap * sizeof(double2), hipMemcpyDeviceToHost));
+    p += 3 * (size_t)c.cap * sizeof(double2);
+    for (double2* v : c.vec) {
+        TM_HIP(hipMemcpy(p, v, c.n * sizeof(double2), hipMemcpyDeviceToHost));
+        p += c.n * sizeof(double2);
+    }
+    for (int l = 0; l < 3; ++l) {
+        TM_HIP(hipMemcpy(p, c.u[l], c.n * sizeof(double2), hipMemcpyDeviceToHost));
+        p += c.n * sizeof(double2);
+    }
+}
+
+// rebuilds a chain from a checkpoint of a chain of the same system; capacity
+// may grow (more steps than the original run was sized for)
+static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, hipStream_t st) {
+    ChainBlobHeader h{};
+    TM_CHECK(bytes >= sizeof(h), TM_EINVAL, "checkpoint too short");
+    std::memcpy(&h, in, sizeof(h));
+    TM_CHECK(std::memcmp(h.magic, "TMCHAIN1", 8) == 0, TM_EINVAL, "not a chain checkpoint");
+    System& s = *c.s;
+    TM_CHECK(h.iq >= 0 && h.iq < (int)s.qs.size(), TM_EINVAL, "checkpoint q set not in this system");
+    const QSet& q = s.qs[h.iq];
+    TM_CHECK(h.n == 2LL * q.nk * s.nbnd * 2 * q.npw_pad, TM_EINVAL, "checkpoint vectors do not fit this system");
+    TM_CHECK(h.flavour == TM_PSEUDOHERMITIAN || h.flavour == TM_NONHERMITIAN, TM_EINVAL, "bad flavour");
+    TM_CHECK(h.nvec == (h.flavour == TM_PSEUDOHERMITIAN ? 5 : 9), TM_EINVAL, "bad vector count");
+    TM_CHECK(h.dir >= TM_DIR_X && h.dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+    TM_CHECK(h.cap >= 1 && capacity >= 0, TM_EINVAL, "bad capacity");
+    {
+        int seen = 0;
+        for (int i = 0; i < h.nvec; ++i) {
+            TM_CHECK(h.ix[i] >= 0 && h.ix[i] < h.nvec && !(seen >> h.ix[i] & 1), TM_EINVAL, "bad vector roles");
+            seen |= 1 << h.ix[i];
+        }
+    }
+    c.iq = h.iq;
+    c.dir = h.dir;
+    c.flavour = h.flavour;
+    c.fp32 = h.fp32 != 0;
+    c.cap = std::max(capacity, h.cap);
+    TM_CHECK(h.issued >= 0 && h.issued <= h.cap, TM_EINVAL, "bad step count");
+    c.n = h.n;
+    const size_t need = sizeof(h) + sizeof(ChainState) + (size_t)h.cap * (3 * sizeof(double2) + sizeof(double)) +
+                        3 * (size_t)h.cap * sizeof(double2) + (h.nvec + 3) * (size_t)h.n * sizeof(double2);
+    TM_CHECK(bytes >= need, TM_EINVAL, "checkpoint truncated");
+    QSet& qm = s.qs[c.iq];
+    ensure_workspace(s, qm);
+    ensure_ground(s, qm, st);
+    c.half = c.n / 2;
+    c.w = 1.0 / qm.nk;
+    for (int i = 0; i < h.nvec; ++i) c.vec.push_back(static_cast<double2*>(c.alloc(c.n * sizeof(double2))));
+    for (int l = 0; l < 3; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
+    c.co.cap = c.cap;
+    c.co.alpha = static_cast<double2*>(c.alloc(c.cap * sizeof(double2)));
+    c.co.beta = static_cast<double*>(c.alloc(c.cap * sizeof(double)));
+    c.co.gamma = static_cast<double2*>(c.alloc(c.cap * sizeof(double2)));
+    c.co.z = static_cast<double2*>(c.alloc(3 * (size_t)c.cap * sizeof(double2)));
+    c.cs = static_cast<ChainState*>(c.alloc(sizeof(ChainState)));
+    c.dots = static_cast<double2*>(c.alloc(16 * sizeof(double2)));
+    c.part = static_cast<double2*>(c.alloc(1024 * 8 * sizeof(double2)));
+    c.last = st;
+    std::copy(h.ix, h.ix + 9, c.ix);
+    c.issued = h.issued;
+    TM_HIP(hipMemsetAsync(c.co.alpha, 0, c.cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.beta, 0, c.cap * sizeof(double), st));
+    TM_HIP(hipMemsetAsync(c.co.gamma, 0, c.cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.z, 0, 3 * (size_t)c.cap * sizeof(double2), st));
+    const char* p = in + sizeof(h);
+    TM_HIP(hipMemcpyAsync(c.cs, p, sizeof(ChainState), hipMemcpyHostToDevice, st));
+    p += sizeof(ChainState);
+    TM_HIP(hipMemcpyAsync(c.co.alpha, p, h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
+    p += h.cap * sizeof(double2);
+    TM_HIP(hipMemcpyAsync(c.co.beta, p, h.cap * sizeof(double), hipMemcpyHostToDevice, st));
+    p += h.cap * sizeof(double);
+    TM_HIP(hipMemcpyAsync(c.co.gamma, p, h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
+    p += h.cap * sizeof(double2);
+    // z is [3][cap]: rows move to the new stride
+    for (int l = 0; l < 3; ++l)
+        TM_HIP(hipMemcpyAsync(c.co.z + (size_t)l * c.cap, p + (size_t)l * h.cap * sizeof(double2),
+                              h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
+    p += 3 * (size_t)h.cap * sizeof(double2);
+    for (double2* v : c.vec) {
+        TM_HIP(hipMemcpyAsync(v, p, c.n * sizeof(double2), hipMemcpyHostToDevice, st));
+        p += c.n * sizeof(double2);
+    }
+    for (int l = 0; l < 3; ++l) {
+        TM_HIP(hipMemcpyAsync(c.u[l], p, c.n * sizeof(double2), hipMemcpyHostToDevice, st));
+        p += c.n * sizeof(double2);
+    }
+    // a chain saved at its capacity holds the coefficients of its next index
+    // only in the state struct (alpha for pH; z for both): grown capacity gets them
+    ChainState hs{};
+    std::memcpy(&hs, in + sizeof(h), sizeof(hs));
+    if (c.cap > h.cap && h.issued == h.cap && hs.step == h.cap && !hs.broken) {
+        if (c.flavour == TM_PSEUDOHERMITIAN)
+            TM_HIP(hipMemcpyAsync(c.co.alpha + h.cap, &hs.alpha, sizeof(double2), hipMemcpyHostToDevice, st));
+        for (int l = 0; l < 3; ++l)
+            TM_HIP(hipMemcpyAsync(c.co.z + (size_t)l * c.cap + h.cap, &hs.znext[l], sizeof(double2),
+                                  hipMemcpyHostToDevice, st));
+    }
+    // the host blob (and hs) may be released as soon as the call returns
+    TM_HIP(hipStreamSynchronize(st));
+}
+
 static int run_chain(System& s, int iq, int dir, int flavour, bool fp32, int nsteps, tm_coeffs* out,
                      hipStream_t st) {
     Chain c;
@@ -875,15 +1015,44 @@ int tm_profile_get(int i, char* name, int name_cap, double* total_ms, long long*
     });
 }
 
+static bool all_finite(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// every floating-point input of the description is finite (NaN or Inf -> TM_EINVAL)
+static void check_finite(const tm_system_desc* d) {
+    const size_t N = (size_t)d->fft[0] * d->fft[1] * d->fft[2];
+    TM_CHECK(all_finite(d->cell, 9), TM_EINVAL, "non-finite cell");
+    TM_CHECK(d->xk && all_finite(d->xk, 3 * (size_t)d->npts), TM_EINVAL, "non-finite point vectors");
+    for (int p = 0; p < d->npts; ++p) {
+        const size_t npw = (size_t)std::max(d->npw[p], 0);
+        TM_CHECK(!d->evc[p] || all_finite(d->evc[p], 4 * (size_t)d->nbnd * npw), TM_EINVAL,
+                 "non-finite ground-state spinors");
+        TM_CHECK(!d->et[p] || all_finite(d->et[p], d->nbnd), TM_EINVAL, "non-finite eigenvalues");
+        if (d->nproj > 0 && d->vkb && d->vkb[p])
+            TM_CHECK(all_finite(d->vkb[p], 2 * (size_t)d->nproj * npw), TM_EINVAL, "non-finite projectors");
+    }
+    if (d->nproj > 0 && d->dvan)
+        TM_CHECK(all_finite(d->dvan, 8 * (size_t)d->nproj * d->nproj), TM_EINVAL, "non-finite D matrix");
+    if (d->vrs) TM_CHECK(all_finite(d->vrs, 4 * N), TM_EINVAL, "non-finite potential");
+    if (d->rho) TM_CHECK(all_finite(d->rho, 4 * N), TM_EINVAL, "non-finite ground-state density");
+    if (d->nq > 0) TM_CHECK(d->xq && all_finite(d->xq, 3 * (size_t)d->nq), TM_EINVAL, "non-finite q");
+}
+
 int tm_system_create(const tm_system_desc* d, tm_system** out) {
     return guarded([&]() -> int {
         TM_CHECK(d && out, TM_EINVAL, "null argument");
         *out = nullptr;
-        int ndev = 0;
-        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error{TM_EDEVICE, "no HIP device"};
+        // host-side validation first: it needs no device
         TM_CHECK(d->nbnd > 0 && d->npts > 0 && d->nq >= 0 && d->nk > 0, TM_EINVAL, "bad sizes");
         TM_CHECK(d->fft[0] > 0 && d->fft[1] > 0 && d->fft[2] > 0, TM_EINVAL, "bad FFT grid");
         TM_CHECK(d->nproj >= 0, TM_EINVAL, "bad nproj");
+        TM_CHECK(d->npw && d->mill && d->evc && d->et, TM_EINVAL, "missing ground-state points");
+        check_finite(d);
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error{TM_EDEVICE, "no HIP device"};
         std::unique_ptr<tm_system> ts(new tm_system());
         System& s = ts->s;
         TM_HIP(hipGetDevice(&s.device));
@@ -1130,6 +1299,36 @@ int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out) {
         int rc = chain_coeffs(chain->c, out);
         if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
         return rc;
+    });
+}
+
+int tm_chain_state_size(const tm_chain* chain, size_t* bytes) {
+    return guarded([&]() -> int {
+        TM_CHECK(chain && bytes, TM_EINVAL, "null argument");
+        *bytes = chain_blob_bytes(chain->c);
+        return TM_OK;
+    });
+}
+
+int tm_chain_save(tm_chain* chain, void* host, size_t bytes) {
+    return guarded([&]() -> int {
+        TM_CHECK(chain && host, TM_EINVAL, "null argument");
+        TM_CHECK(bytes >= chain_blob_bytes(chain->c), TM_EINVAL, "buffer smaller than tm_chain_state_size");
+        chain_save(chain->c, static_cast<char*>(host));
+        return TM_OK;
+    });
+}
+
+int tm_chain_restore(tm_system* sys, const void* host, size_t bytes, int capacity, void* stream, tm_chain** out) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && host && out, TM_EINVAL, "null argument");
+        *out = nullptr;
+        std::unique_ptr<tm_chain> h(new tm_chain());
+        h->c.s = &sys->s;
+        chain_restore(h->c, static_cast<const char*>(host), bytes, capacity, static_cast<hipStream_t>(stream));
+        ++sys->s.nchains;
+        *out = h.release();
+        return TM_OK;
     });
 }
 

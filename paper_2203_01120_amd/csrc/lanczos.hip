@@ -204,9 +204,10 @@ __global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, C
     cs->beta_prev = b;
     cs->alpha = cmk(ll / b2, 0.0);
     cs->qq = rr / b2;
+    for (int l = 0; l < 3; ++l) cs->znext[l] = cscale(zu[l], 1.0 / b);
     if (j + 1 < co.cap) {
         co.alpha[j + 1] = cs->alpha;
-        for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cscale(zu[l], 1.0 / b);
+        for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
     }
 }
 
@@ -265,8 +266,9 @@ __global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
     cs->pp = pp / gg;
     cs->beta_prev = b;
     cs->gamma_prev = g;
+    for (int l = 0; l < 3; ++l) cs->znext[l] = cscale(d[3 + l], 1.0 / b);
     if (j + 1 < co.cap)
-        for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cscale(d[3 + l], 1.0 / b);
+        for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
 }
 
 }  // namespace

@@ -18,6 +18,7 @@ struct ChainState {
     double qq, pp;              // (q_i, q_i), (p_i, p_i)
     double lam;
     double n1;
+    double2 znext[3];           // z of the next index, kept when it falls past the capacity
     int step;
     int broken;
 };

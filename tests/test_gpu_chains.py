@@ -157,6 +157,35 @@ def test_several_q_sets_in_one_system(lib, tiny_gs):
         lib.tm_system_destroy(h)
 
 
+@pytest.mark.parametrize("flavour,mu,k,m", [("pH", "+", 30, 60), ("nH", "z", 7, 20)])
+def test_checkpoint_restart_continues_exactly(lib, systems, flavour, mu, k, m):
+    """Stop at step k, save, end; restore with a larger capacity and run on:
+    the coefficients equal an uninterrupted chain bit for bit."""
+    prob, h = systems["cubic20"]
+    say(f"checkpoint {flavour} {mu}: {k} + {m - k} steps")
+    ref = lib.tm_lanczos_run(h, 0, mu, flavour, m)
+    c = lib.tm_chain_begin(h, 0, mu, flavour, k)
+    try:
+        lib.tm_chains_step([c], k)
+        blob = lib.tm_chain_save(c)
+        first = lib.tm_chain_coeffs(c, k)
+    finally:
+        lib.tm_chain_end(c)
+    c2 = lib.tm_chain_restore(h, blob, capacity=m)
+    try:
+        mid = lib.tm_chain_coeffs(c2, m)
+        assert mid["steps_done"] == k
+        for key in KEYS:
+            assert np.array_equal(mid[key][..., :k], first[key][..., :k]), key
+        lib.tm_chains_step([c2], m)
+        got = lib.tm_chain_coeffs(c2, m)
+    finally:
+        lib.tm_chain_end(c2)
+    same(got, ref)
+    with pytest.raises(lib.TmError):
+        lib.tm_chain_restore(h, blob[:100])
+
+
 def test_chain_breakdown(lib, tiny_gs_nosoc):
     prob = lv.build_problem(tiny_gs_nosoc, np.zeros(3))
     h = lib.tm_system_create(desc_from_problem(prob))
