@@ -473,6 +473,55 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// lane slots per line of a stage with bpl butterflies per line
+constexpr int wslots(int bpl) { return (bpl > 8 && bpl < 16) ? 16 : bpl; }
+
+// true when every stage's slots per line divide the wave: a lane then sits at
+// the same butterfly position of its line in every iteration, line and band
+constexpr bool lane_fixed(int n) {
+    const CPlan p = cplan(n);
+    for (int s = 0; s < p.nrad; ++s)
+        if (64 % wslots(n / p.rad[s]) != 0) return false;
+    return true;
+}
+
+// Twiddles of a wave's stages.  With lane_fixed(N) a lane's twiddles are the
+// same for the whole kernel: they are read from the table once, into
+// registers, and the radix stages issue no global loads (whose in-order
+// completion counter would also make them wait for the band's ground-state
+// and column loads).  Otherwise they come from the table through the vector L1.
+template <int N, class T2>
+struct WTw {
+    static constexpr CPlan cp = cplan(N);
+    static constexpr bool kReg = lane_fixed(N);
+    const T2* __restrict__ tab;
+    T2 w[cp.nrad][4];
+
+    template <int S = 0>
+    __device__ __forceinline__ void init(int lane) {
+        if constexpr (kReg && S < cp.nrad) {
+            constexpr int R = cp.rad[S];
+            constexpr int LB = N / cp.pre[S];
+            constexpr int M = LB / R;
+            constexpr int BPL = N / R;
+            constexpr int TWS = N / LB;
+            if constexpr (M > 1) {
+                const int r0 = lane % wslots(BPL);
+                const int j = r0 < BPL ? r0 % M : 0;
+#pragma unroll
+                for (int t = 1; t < R; ++t) w[S][t - 1] = tab[t * j * TWS];
+            }
+            init<S + 1>(lane);
+        }
+    }
+    // twiddle t of butterfly j at stage S (LB = N / pre[S])
+    template <int S, int LB>
+    __device__ __forceinline__ T2 get(int t, int j) const {
+        if constexpr (kReg) return w[S][t - 1];
+        else return tab[t * j * (N / LB)];
+    }
+};
+
 // one in-place stage (see ipass) over the nl lines of one wave.
 //  * A line's butterflies sit on consecutive lanes; a line of 12 butterflies
 //    takes a whole 16-lane group, so the 16 lanes that LDS serves together
@@ -482,12 +531,11 @@ __device__ __forceinline__ void wave_sync() {
 //  * Twiddles come from the table in device memory (vector L1), not from LDS.
 //  * The lane's butterflies go in groups of BT whose loads are all issued
 //    before their stores (BT trades registers for memory-level parallelism).
-template <int N, int R, int LB, int SIGN, bool DIF, bool MASKED, int MAXL, int BT, class WL, class T2>
-__device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const T2* __restrict__ tw, int lane) {
+template <int N, int S, int R, int LB, int SIGN, bool DIF, bool MASKED, int MAXL, int BT, class WL, class T2>
+__device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const WTw<N, T2>& tw, int lane) {
     constexpr int M = LB / R;
     constexpr int BPL = N / R;
-    constexpr int SPL = (BPL > 8 && BPL < 16) ? 16 : BPL;  // lane slots per line
-    constexpr int TWS = N / LB;
+    constexpr int SPL = wslots(BPL);  // lane slots per line
     constexpr int ES = WL::ES;
     constexpr int IT = cdiv(MAXL * SPL, 64);
     constexpr int B = BT < IT ? BT : IT;
@@ -515,7 +563,7 @@ __device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const T2* __r
                     T2 x = Cx<T2>::mk(0, 0);
                     if (!MASKED || L.valid(e0 + t * M)) x = pl[bs + t * M * ES];
                     if (!DIF && t > 0 && j > 0) {
-                        T2 w = tw[t * j * TWS];
+                        T2 w = tw.template get<S, LB>(t, j);
                         if (SIGN > 0) w.y = -w.y;
                         x = cmul(x, w);
                     }
@@ -531,7 +579,7 @@ __device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const T2* __r
                 for (int r = 0; r < R; ++r) {
                     T2 y = u[it][r];
                     if (DIF && r > 0 && jv[it] > 0) {
-                        T2 w = tw[r * jv[it] * TWS];
+                        T2 w = tw.template get<S, LB>(r, jv[it]);
                         if (SIGN > 0) w.y = -w.y;
                         y = cmul(y, w);
                     }
@@ -544,22 +592,22 @@ __device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const T2* __r
 }
 
 template <int N, int SIGN, bool MASKED, int MAXL, int BT, int STAGE = 0, int LB = N, class WL, class T2>
-__device__ __forceinline__ void wfft_dif(T2* pl, const WL& L, int nl, const T2* tw, int lane) {
+__device__ __forceinline__ void wfft_dif(T2* pl, const WL& L, int nl, const WTw<N, T2>& tw, int lane) {
     constexpr CPlan cp = cplan(N);
     if constexpr (STAGE < cp.nrad) {
         constexpr int R = cp.rad[STAGE];
-        wpass<N, R, LB, SIGN, true, MASKED && STAGE == 0, MAXL, BT>(pl, L, nl, tw, lane);
+        wpass<N, STAGE, R, LB, SIGN, true, MASKED && STAGE == 0, MAXL, BT>(pl, L, nl, tw, lane);
         wfft_dif<N, SIGN, MASKED, MAXL, BT, STAGE + 1, LB / R>(pl, L, nl, tw, lane);
     }
 }
 
 template <int N, int SIGN, int MAXL, int BT, int STAGE, class WL, class T2>
-__device__ __forceinline__ void wfft_dit(T2* pl, const WL& L, int nl, const T2* tw, int lane) {
+__device__ __forceinline__ void wfft_dit(T2* pl, const WL& L, int nl, const WTw<N, T2>& tw, int lane) {
     constexpr CPlan cp = cplan(N);
     if constexpr (STAGE >= 0) {
         constexpr int R = cp.rad[STAGE];
         constexpr int LB = N / cp.pre[STAGE];
-        wpass<N, R, LB, SIGN, false, false, MAXL, BT>(pl, L, nl, tw, lane);
+        wpass<N, STAGE, R, LB, SIGN, false, false, MAXL, BT>(pl, L, nl, tw, lane);
         wfft_dit<N, SIGN, MAXL, BT, STAGE - 1>(pl, L, nl, tw, lane);
     }
 }
@@ -647,7 +695,7 @@ struct WaveKernel {
     // fill the wave's occupied rows of buffer boff from the z-transformed
     // columns of item pair (2n, 2n+1), then the inverse transforms along i2
     __device__ static void rows_inverse(const Smem& m, const T2* cx, long long cs, int nlw, int w, int boff,
-                                        int lane, const T2* __restrict__ gtw2) {
+                                        int lane, const WTw<N2, T2>& gtw2) {
         for (int k = lane; k < nlw * N2; k += 64) {
             const int li = k / N2, p2 = k - li * N2;
             const int l = w + li * NW;
@@ -680,10 +728,13 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     const T2* xcols = pick<T2>(a.xcols, a.xcols32);
-    const T2* tw1 = pick<T2>(t.tw1, t.tw1f);
-    const T2* tw2 = pick<T2>(t.tw2, t.tw2f);
     const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    WTw<N1, T2> tw1{pick<T2>(t.tw1, t.tw1f)};
+    // equal lengths share one table, so the two register sets are one
+    WTw<N2, T2> tw2{N1 == N2 ? pick<T2>(t.tw1, t.tw1f) : pick<T2>(t.tw2, t.tw2f)};
+    tw1.init(lane);
+    tw2.init(lane);
     const int nrx = K::setup(t, b, m);
     const unsigned long long mask = t.rmask_kq[b];
     const int nlw = K::wave_rows(2 * nrx, w);
@@ -780,10 +831,13 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     T2* xcols = pick<T2>(a.xcols, a.xcols32);
-    const T2* tw1 = pick<T2>(t.tw1, t.tw1f);
-    const T2* tw2 = pick<T2>(t.tw2, t.tw2f);
     const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    WTw<N1, T2> tw1{pick<T2>(t.tw1, t.tw1f)};
+    // equal lengths share one table, so the two register sets are one
+    WTw<N2, T2> tw2{N1 == N2 ? pick<T2>(t.tw1, t.tw1f) : pick<T2>(t.tw2, t.tw2f)};
+    tw1.init(lane);
+    tw2.init(lane);
     const int nrx = K::setup(t, b, m);
     const unsigned long long mask = t.rmask_kq[b];
     const int nlw = K::wave_rows(2 * nrx, w);
