@@ -741,6 +741,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const long long cs = (long long)a.n3 * a.ncol_max;
+    // the side's resident slot, read once (the loop's stores could alias it)
+    const double2* ub = a.ureal + (long long)a.uslot[b] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
     int o[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
@@ -755,7 +757,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
     for (int n = n0; n < n1e; ++n) {
         const int boff = (n & 1) * K::BUF;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-        const double2* ur = ureal_plane(a, b, n, i3) + w * K::WPTS;
+        const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
         T2 uu[PPL], ud[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
@@ -844,6 +846,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const long long cs = (long long)a.n3 * a.ncol_max;
+    // the side's resident slot, read once (the loop's stores could alias it)
+    const double2* ub = a.ureal + (long long)a.uslot[b] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
     const bool yside = b >= a.nk;
     int o[PPL];
 #pragma unroll
@@ -855,7 +859,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
     for (int n = n0; n < n1e; ++n) {
         const int boff = (n & 1) * K::BUF;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-        const double2* ur = ureal_plane(a, b, n, i3) + w * K::WPTS;
+        const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
         T2 uu[PPL], ud[PPL];
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
