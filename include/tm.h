@@ -62,8 +62,14 @@ enum {
 typedef enum { TM_FP64 = 0, TM_FP32 = 1 } tm_precision;
 
 /* Direction of the perturbing field (Sec. 2.5, Eq. off-diag-resolvent):
- * sigma^mu = sigma_x, sigma_y, sigma_z, sigma_x + i sigma_y, sigma_x - i sigma_y. */
-typedef enum { TM_DIR_X = 0, TM_DIR_Y = 1, TM_DIR_Z = 2, TM_DIR_PLUS = 3, TM_DIR_MINUS = 4 } tm_dir;
+ * sigma^mu = sigma_x, sigma_y, sigma_z, sigma_x + i sigma_y, sigma_x - i sigma_y,
+ * and TM_DIR_N = sigma_0, the charge channel of the generalized 4 x 4
+ * (charge + spin) susceptibility (Sec. 2.3).  sigma_0 is even under time
+ * reversal where the spin matrices are odd, so its vectors carry the opposite
+ * sign on the lower (y) side: u^n = (U~, +T U~), v^n = (P U~, -P+ T U~). */
+typedef enum {
+    TM_DIR_X = 0, TM_DIR_Y = 1, TM_DIR_Z = 2, TM_DIR_PLUS = 3, TM_DIR_MINUS = 4, TM_DIR_N = 5
+} tm_dir;
 
 /* Lanczos flavour (Sec. 2.5): non-Hermitian biorthogonalisation (two
  * applications of L per step) or pseudo-Hermitian (one per step). */
@@ -189,9 +195,10 @@ int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void*
  * Lanczos coefficients (Sec. 2.5).  All arrays are host memory owned by the
  * caller with room for `capacity` steps.  For 0-based step j:
  *   alpha[j] = T[j][j], beta[j] = T[j+1][j], gamma[j] = T[j][j+1],
- *   z[l][j] = (u^l, q_j) for l = x, y, z;
+ *   z[l][j] = (u^l, q_j) for l = x, y, z;  zn[j] = (u^n, q_j) (charge);
  * the last beta/gamma is the residual coupling beyond the M x M matrix.
  * For the pseudo-Hermitian flavour beta = gamma (real) and alpha is real.
+ * zn may be NULL (then the charge overlaps are not returned).
  */
 typedef struct {
     int capacity;               /* in: room for this many steps                          */
@@ -201,6 +208,7 @@ typedef struct {
     double* beta;               /* real    [capacity]                                    */
     double* gamma;              /* complex [capacity]                                    */
     double* z;                  /* complex [3][capacity]                                 */
+    double* zn;                 /* complex [capacity] or NULL                             */
 } tm_coeffs;
 
 /*
@@ -221,7 +229,7 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
  * (q set, direction, flavour), resident on the device; tm_lanczos_run is
  * begin + steps + coeffs + end.
  * tm_chain_begin: allocates the chain's vectors (pseudo-Hermitian: 5 BR
- *   vectors, non-Hermitian: 9, plus the three u^lambda) and coefficient
+ *   vectors, non-Hermitian: 9, plus the four u^lambda, lambda = x, y, z, n) and coefficient
  *   storage for `capacity` steps, builds v^mu (as tm_start_vectors) and
  *   starts the recursion (pseudo-Hermitian: one apply), asynchronously on
  *   `stream` (a hipStream_t, NULL = default stream).  TM_ENOMEM when the
@@ -254,8 +262,8 @@ int tm_chain_end(tm_chain* chain);
  * turbo_magnon, Sec. 3.2 and Table 1): the chain's complete state -- its BR
  * vectors, the three u^lambda, the coefficients and the device scale/step
  * state -- as one host blob.
- * tm_chain_state_size: bytes of the blob (pseudo-Hermitian: 8 BR vectors,
- *   non-Hermitian: 12, plus 88 bytes per step of capacity and a header).
+ * tm_chain_state_size: bytes of the blob (pseudo-Hermitian: 9 BR vectors,
+ *   non-Hermitian: 13, plus 104 bytes per step of capacity and a header).
  * tm_chain_save: waits for the chain's last stream and copies its state into
  *   `host` (caller-owned, at least tm_chain_state_size bytes); the chain stays
  *   usable.
@@ -299,6 +307,15 @@ int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, doubl
 typedef enum { TM_EXTRAP_NONE = 0, TM_EXTRAP_CONSTANT = 1, TM_EXTRAP_OSC = 2 } tm_extrap;
 int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega,
                         int nomega, double eta, double* chi);
+
+/*
+ * tm_chi_tensor: one column (field direction mu of the chain) of the
+ * generalized 4 x 4 susceptibility, rows lambda = n, x, y, z:
+ *   chi[0] from zn, chi[1..3] from z, otherwise as tm_chi_extrapolated.
+ * c->zn must be set.  chi: host complex [4][nomega].  Synchronous.
+ */
+int tm_chi_tensor(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega,
+                  int nomega, double eta, double* chi);
 
 /*
  * tm_structure_factor: S(q, omega) = -Im Tr[P_perp(q) chi(q, q; omega)]

@@ -23,7 +23,13 @@ and V' = W_0 sigma_0 + W . sigma with W_a = delta_a0 v'_H + sum_b f_ab rho'_b
 Start and measure vectors (Sec. 2.5, Eq. off-diag-resolvent and below):
     u^l = ( sigma^l U~_{n,k}, -sigma^l T U~_{n,-k} ),
     v^m = ( P sigma^m U~_{n,k}, P+ sigma^m T U~_{n,-k} ),
-with U~ the coefficients restricted to the sphere of k+q.  Inner product
+with U~ the coefficients restricted to the sphere of k+q.  The charge
+channel (l or m = n, sigma^n = sigma_0, the generalized 4x4 susceptibility
+of Sec. 2.3) follows the same derivation with the time-reversal parity of
+sigma_0, which is +1 where the spin matrices have -1 (T sigma T^-1 = -sigma):
+the lower component of u is s_l sigma^l T U~ and that of v is
+-s_m P+ sigma^m T U~, s = +1 for n and -1 for the spin directions; for the
+spin directions these are the printed vectors.  Inner product
 (a, b) = (1/Nk) sum a^dag b, conjugate-linear in a.
 """
 from __future__ import annotations
@@ -37,6 +43,7 @@ from . import grid, xc
 from .scf import PAULI
 
 DIRECTIONS = {
+    "n": PAULI[0],
     "x": PAULI[1],
     "y": PAULI[2],
     "z": PAULI[3],
@@ -44,6 +51,8 @@ DIRECTIONS = {
     "-": PAULI[1] - 1j * PAULI[2],
 }
 SIDE_SIGNS = (np.array([1.0, 1.0, 1.0, 1.0]), np.array([1.0, -1.0, -1.0, -1.0]))
+# time-reversal parity s of each direction's matrix: T sigma T^-1 = s sigma
+TR_PARITY = {"n": 1.0, "x": -1.0, "y": -1.0, "z": -1.0, "+": -1.0, "-": -1.0}
 
 
 @dataclass
@@ -198,7 +207,7 @@ class Problem:
         for ik, kd in enumerate(self.k):
             for s in range(2):
                 su = np.einsum("st,ntg->nsg", sig, kd.u_sph[s])
-                u[s, ik, :, :, :kd.npw] = su if s == 0 else -su
+                u[s, ik, :, :, :kd.npw] = su if s == 0 else TR_PARITY[lam] * su
         return u
 
     def v_vector(self, mu):
@@ -207,6 +216,8 @@ class Problem:
         for ik, kd in enumerate(self.k):
             for s in range(2):
                 su = np.einsum("st,ntg->nsg", sig, kd.u_sph[s])
+                if s == 1:
+                    su = -TR_PARITY[mu] * su
                 v[s, ik, :, :, :kd.npw] = self.project(s, ik, su)
         return v
 

@@ -20,13 +20,13 @@ LIB_PATH = os.path.join(_HERE, "libtm.so")
 
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_EDEVICE, TM_EBREAKDOWN, TM_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 TM_FP64, TM_FP32 = 0, 1
-DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4}
+DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4, "n": 5}
 FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
             "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
-            "tm_chain_state_size", "tm_chain_save", "tm_chain_restore",
+            "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -58,7 +58,8 @@ class _QInfo(C.Structure):
 class _Coeffs(C.Structure):
     _fields_ = [("capacity", C.c_int), ("steps_done", C.c_int), ("n1", C.c_double),
                 ("alpha", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double)),
-                ("gamma", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double))]
+                ("gamma", C.POINTER(C.c_double)), ("z", C.POINTER(C.c_double)),
+                ("zn", C.POINTER(C.c_double))]
 
 
 _lib = None
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
                                      C.POINTER(C.c_void_p)]
     lib.tm_chi_extrapolated.argtypes = [C.POINTER(_Coeffs), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                         C.c_int, C.c_double, C.POINTER(C.c_double)]
+    lib.tm_chi_tensor.argtypes = [C.POINTER(_Coeffs), C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                  C.c_int, C.c_double, C.POINTER(C.c_double)]
     lib.tm_structure_factor.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
                                         C.POINTER(C.c_double)]
     lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
@@ -259,29 +262,39 @@ def tm_start_vectors(h, iq: int, direction: str, u=None, v=None, stream=None):
                                    C.c_void_p(v.data_ptr() if v is not None else 0), _stream(stream)))
 
 
-def tm_lanczos_run(h, iq: int, direction: str, flavour: str, nsteps: int, prec: int = TM_FP64) -> dict:
-    """Run one chain; returns dict(alpha, beta, gamma, z[3], n1, steps_done, breakdown)."""
-    cap = int(nsteps)
-    alpha = np.zeros(cap, dtype=np.complex128)
-    beta = np.zeros(cap)
-    gamma = np.zeros(cap, dtype=np.complex128)
-    z = np.zeros((3, cap), dtype=np.complex128)
-    co = _Coeffs(cap, 0, 0.0, alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
-                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
-    rc = _check(load().tm_lanczos_run(C.c_void_p(h), iq, DIRS[direction], FLAVOURS[flavour], cap, prec,
-                                      C.byref(co)), allow=(TM_EBREAKDOWN,))
-    return dict(alpha=alpha, beta=beta, gamma=gamma, z=z, n1=co.n1, steps_done=co.steps_done,
-                breakdown=rc == TM_EBREAKDOWN)
+def _cptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
 def _coeff_arrays(cap: int):
-    alpha = np.zeros(cap, dtype=np.complex128)
-    beta = np.zeros(cap)
-    gamma = np.zeros(cap, dtype=np.complex128)
-    z = np.zeros((3, cap), dtype=np.complex128)
-    co = _Coeffs(cap, 0, 0.0, alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
-                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
-    return co, dict(alpha=alpha, beta=beta, gamma=gamma, z=z)
+    """Output arrays for `cap` steps: alpha, beta, gamma, z[3] (x, y, z) and zn (charge)."""
+    arrs = dict(alpha=np.zeros(cap, dtype=np.complex128), beta=np.zeros(cap),
+                gamma=np.zeros(cap, dtype=np.complex128), z=np.zeros((3, cap), dtype=np.complex128),
+                zn=np.zeros(cap, dtype=np.complex128))
+    co = _Coeffs(cap, 0, 0.0, _cptr(arrs["alpha"]), _cptr(arrs["beta"]), _cptr(arrs["gamma"]), _cptr(arrs["z"]),
+                 _cptr(arrs["zn"]))
+    return co, arrs
+
+
+def _coeffs_in(coeffs: dict):
+    """A tm_coeffs view of a coefficient dict (arrays kept alive in the returned tuple)."""
+    keep = {k: np.ascontiguousarray(coeffs[k], dtype=np.float64 if k == "beta" else np.complex128)
+            for k in ("alpha", "beta", "gamma", "z")}
+    zn = coeffs.get("zn")
+    if zn is not None:
+        keep["zn"] = np.ascontiguousarray(zn, dtype=np.complex128)
+    co = _Coeffs(keep["alpha"].shape[0], int(coeffs["steps_done"]), float(coeffs["n1"]), _cptr(keep["alpha"]),
+                 _cptr(keep["beta"]), _cptr(keep["gamma"]), _cptr(keep["z"]),
+                 _cptr(keep["zn"]) if "zn" in keep else None)
+    return co, keep
+
+
+def tm_lanczos_run(h, iq: int, direction: str, flavour: str, nsteps: int, prec: int = TM_FP64) -> dict:
+    """Run one chain; returns dict(alpha, beta, gamma, z[3], zn, n1, steps_done, breakdown)."""
+    co, arrs = _coeff_arrays(int(nsteps))
+    rc = _check(load().tm_lanczos_run(C.c_void_p(h), iq, DIRS[direction], FLAVOURS[flavour], int(nsteps), prec,
+                                      C.byref(co)), allow=(TM_EBREAKDOWN,))
+    return dict(arrs, n1=co.n1, steps_done=co.steps_done, breakdown=rc == TM_EBREAKDOWN)
 
 
 def tm_chain_begin(h, iq: int, direction: str, flavour: str, capacity: int, prec: int = TM_FP64,
@@ -335,14 +348,7 @@ def tm_chain_end(chain) -> None:
 
 def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:
     """chi[l][w] for l = x, y, z from the Lanczos coefficients (runs on the GPU)."""
-    alpha = np.ascontiguousarray(coeffs["alpha"], dtype=np.complex128)
-    beta = np.ascontiguousarray(coeffs["beta"], dtype=np.float64)
-    gamma = np.ascontiguousarray(coeffs["gamma"], dtype=np.complex128)
-    z = np.ascontiguousarray(coeffs["z"], dtype=np.complex128)
-    cap = alpha.shape[0]
-    co = _Coeffs(cap, int(coeffs["steps_done"]), float(coeffs["n1"]),
-                 alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
-                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
+    co, _keep = _coeffs_in(coeffs)
     om = np.ascontiguousarray(omega, dtype=np.float64)
     out = np.zeros((3, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi(C.byref(co), int(m_use), _dptr(om), om.shape[0], float(eta),
@@ -355,18 +361,21 @@ EXTRAP = {"no": 0, "constant": 1, "osc": 2}
 
 def tm_chi_extrapolated(coeffs: dict, m_use: int, m_total: int, mode: str, omega, eta: float) -> np.ndarray:
     """chi[l][w] with the tridiagonal matrix extended to m_total ('no', 'constant', 'osc')."""
-    alpha = np.ascontiguousarray(coeffs["alpha"], dtype=np.complex128)
-    beta = np.ascontiguousarray(coeffs["beta"], dtype=np.float64)
-    gamma = np.ascontiguousarray(coeffs["gamma"], dtype=np.complex128)
-    z = np.ascontiguousarray(coeffs["z"], dtype=np.complex128)
-    cap = alpha.shape[0]
-    co = _Coeffs(cap, int(coeffs["steps_done"]), float(coeffs["n1"]),
-                 alpha.ctypes.data_as(C.POINTER(C.c_double)), _dptr(beta),
-                 gamma.ctypes.data_as(C.POINTER(C.c_double)), z.ctypes.data_as(C.POINTER(C.c_double)))
+    co, _keep = _coeffs_in(coeffs)
     om = np.ascontiguousarray(omega, dtype=np.float64)
     out = np.zeros((3, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi_extrapolated(C.byref(co), int(m_use), int(m_total), EXTRAP[mode], _dptr(om),
                                       om.shape[0], float(eta), out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out
+
+
+def tm_chi_tensor(coeffs: dict, m_use: int, omega, eta: float, m_total: int = 0, mode: str = "no") -> np.ndarray:
+    """One column of the 4 x 4 susceptibility: chi[l][w], rows l = n, x, y, z."""
+    co, _keep = _coeffs_in(coeffs)
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    out = np.zeros((4, om.shape[0]), dtype=np.complex128)
+    _check(load().tm_chi_tensor(C.byref(co), int(m_use), int(m_total or m_use), EXTRAP[mode], _dptr(om),
+                                om.shape[0], float(eta), out.ctypes.data_as(C.POINTER(C.c_double))))
     return out
 
 

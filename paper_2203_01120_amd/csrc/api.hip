@@ -14,8 +14,8 @@ void launch_kin(const System& s, double* kin, const int* d_mill, int npw, int np
 void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
                            bool f32 = false);
 size_t gemm_partial_elems(int nbatch, int M, int Nn, int K);
-void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int cap, int M,
-                double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
+void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int nz, int cap,
+                int M, double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
                 hipStream_t st);
 
 static thread_local std::string g_err;
@@ -109,7 +109,7 @@ inline long long mkey(int a, int b, int c) {
 
 // start vectors: su = sigma^dir (U~_k) on side 0, sigma^dir (T U~_-k) on side 1
 __global__ void k_start(const double2* const* ucoef, const int* npw_u, const int* const* maps, int nk, int nb,
-                        int npw_pad, int dir, double usign_y, double2* u, double2* v) {
+                        int npw_pad, int dir, double usign_y, double vsign_y, double2* u, double2* v) {
     const int b = blockIdx.z;
     const int n = blockIdx.y;
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -136,12 +136,14 @@ __global__ void k_start(const double2* const* ucoef, const int* npw_u, const int
         case TM_DIR_Y: ra = cmk(c.y, -c.x); rc = cmk(-a.y, a.x); break;  // (-i c, i a)
         case TM_DIR_Z: ra = a; rc = cmk(-c.x, -c.y); break;
         case TM_DIR_PLUS: ra = cscale(c, 2.0); rc = cmk(0, 0); break;
-        default: ra = cmk(0, 0); rc = cscale(a, 2.0); break;
+        case TM_DIR_MINUS: ra = cmk(0, 0); rc = cscale(a, 2.0); break;
+        default: ra = a; rc = c; break;  // TM_DIR_N: sigma_0
     }
     long long off = (((long long)b * nb + n) * 2) * npw_pad + g;
     if (v) {
-        v[off] = ra;
-        v[off + npw_pad] = rc;
+        double sg = side ? vsign_y : 1.0;
+        v[off] = cscale(ra, sg);
+        v[off + npw_pad] = cscale(rc, sg);
     }
     if (u) {
         double sg = side ? usign_y : 1.0;
@@ -549,8 +551,11 @@ void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream
     QSet& q = s.qs[iq];
     ensure_workspace(s, q);
     dim3 gr((q.npw_pad + 127) / 128, s.nbnd, 2 * q.nk);
+    // lower-side signs: u^l = (s U, t_l s T U), v^m = (P s U, -t_m P+ s T U) with the
+    // time-reversal parity t = -1 of the spin matrices and +1 of sigma_0
+    const double t = dir == TM_DIR_N ? 1.0 : -1.0;
     TM_LAUNCH(k_start, gr, dim3(128), 0, st, q.d_ucoef, q.d_npw_u, (const int* const*)q.d_maps, q.nk,
-                       s.nbnd, q.npw_pad, dir, -1.0, u, v);
+                       s.nbnd, q.npw_pad, dir, t, -t, u, v);
     if (v) launch_project_signed(s, q, v, 1.0, 1.0, st);
 }
 
@@ -570,7 +575,7 @@ struct Chain {
     double w = 1.0;
     std::vector<double2*> vec;  // work vectors (5 pH, 9 nH)
     int ix[9] = {0, 1, 2, 3, 4, 5, 6, 7, 8};  // current role -> vector
-    double2* u[3] = {nullptr, nullptr, nullptr};
+    double2* u[kNMeasure] = {};  // measure vectors u^l, l = x, y, z, n
     Coeffs co{};
     ChainState* cs = nullptr;
     double2* dots = nullptr;   // [16] reduced inner products
@@ -610,13 +615,13 @@ static void chain_begin(Chain& c, hipStream_t st) {
     c.w = 1.0 / q.nk;
     const int nvec = c.flavour == TM_PSEUDOHERMITIAN ? 5 : 9;
     for (int i = 0; i < nvec; ++i) c.vec.push_back(static_cast<double2*>(c.alloc(c.n * sizeof(double2))));
-    for (int l = 0; l < 3; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
+    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
     const int cap = c.cap;
     c.co.cap = cap;
     c.co.alpha = static_cast<double2*>(c.alloc(cap * sizeof(double2)));
     c.co.beta = static_cast<double*>(c.alloc(cap * sizeof(double)));
     c.co.gamma = static_cast<double2*>(c.alloc(cap * sizeof(double2)));
-    c.co.z = static_cast<double2*>(c.alloc(3 * cap * sizeof(double2)));
+    c.co.z = static_cast<double2*>(c.alloc(kNMeasure * (size_t)cap * sizeof(double2)));
     c.cs = static_cast<ChainState*>(c.alloc(sizeof(ChainState)));
     c.dots = static_cast<double2*>(c.alloc(16 * sizeof(double2)));
     c.part = static_cast<double2*>(c.alloc(1024 * 8 * sizeof(double2)));
@@ -624,11 +629,12 @@ static void chain_begin(Chain& c, hipStream_t st) {
     TM_HIP(hipMemsetAsync(c.co.alpha, 0, cap * sizeof(double2), st));
     TM_HIP(hipMemsetAsync(c.co.beta, 0, cap * sizeof(double), st));
     TM_HIP(hipMemsetAsync(c.co.gamma, 0, cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(c.co.z, 0, 3 * cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.z, 0, kNMeasure * (size_t)cap * sizeof(double2), st));
     ChainState h{};
     h.lam = q.lam;
     TM_HIP(hipMemcpyAsync(c.cs, &h, sizeof(h), hipMemcpyHostToDevice, st));
-    for (int l = 0; l < 3; ++l) start_vectors(s, c.iq, l, c.u[l], nullptr, st);
+    const int mdir[kNMeasure] = {TM_DIR_X, TM_DIR_Y, TM_DIR_Z, TM_DIR_N};
+    for (int l = 0; l < kNMeasure; ++l) start_vectors(s, c.iq, mdir[l], c.u[l], nullptr, st);
     const long long n = c.n, half = c.half;
     double2* d = c.dots;
     if (c.flavour == TM_PSEUDOHERMITIAN) {
@@ -636,10 +642,10 @@ static void chain_begin(Chain& c, hipStream_t st) {
         TM_HIP(hipMemsetAsync(c.V(0), 0, n * sizeof(double2), st));
         start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
         apply_l(s, c.iq, c.V(1), c.V(2), c.fp32, st);
-        DotSet<6> ds0{{c.V(1), c.V(1), c.V(2), c.u[0], c.u[1], c.u[2]},
-                      {c.V(2), c.V(1), c.V(2), c.V(1), c.V(1), c.V(1)},
-                      {1, 0, 1, 0, 0, 0}};
-        run_multidot<6>(ds0, n, half, c.w, c.part, d, st);
+        DotSet<7> ds0{{c.V(1), c.V(1), c.V(2), c.u[0], c.u[1], c.u[2], c.u[3]},
+                      {c.V(2), c.V(1), c.V(2), c.V(1), c.V(1), c.V(1), c.V(1)},
+                      {1, 0, 1, 0, 0, 0, 0}};
+        run_multidot<7>(ds0, n, half, c.w, c.part, d, st);
         ctl_ph_start(c.cs, d, c.co, st);
     } else {
         // roles: 0 q_prev, 1 q, 2 p_prev, 3 p, 4 Lq, 5 L^dag p, 6 J p, 7 q^, 8 p^
@@ -647,8 +653,10 @@ static void chain_begin(Chain& c, hipStream_t st) {
         TM_HIP(hipMemsetAsync(c.V(2), 0, n * sizeof(double2), st));
         start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
         TM_HIP(hipMemcpyAsync(c.V(3), c.V(1), n * sizeof(double2), hipMemcpyDeviceToDevice, st));
-        DotSet<4> ds0{{c.V(1), c.u[0], c.u[1], c.u[2]}, {c.V(1), c.V(1), c.V(1), c.V(1)}, {0, 0, 0, 0}};
-        run_multidot<4>(ds0, n, half, c.w, c.part, d, st);
+        DotSet<5> ds0{{c.V(1), c.u[0], c.u[1], c.u[2], c.u[3]},
+                      {c.V(1), c.V(1), c.V(1), c.V(1), c.V(1)},
+                      {0, 0, 0, 0, 0}};
+        run_multidot<5>(ds0, n, half, c.w, c.part, d, st);
         ctl_nh_start(c.cs, d, c.co, st);
     }
 }
@@ -658,7 +666,7 @@ static void chain_step(Chain& c, hipStream_t st) {
     System& s = *c.s;
     const long long n = c.n, half = c.half;
     double2* d = c.dots;
-    const double2* uc[3] = {c.u[0], c.u[1], c.u[2]};
+    const double2* uc[kNMeasure] = {c.u[0], c.u[1], c.u[2], c.u[3]};
     if (c.flavour == TM_PSEUDOHERMITIAN) {
         double2 *QP = c.V(0), *Q = c.V(1), *LQ = c.V(2), *R = c.V(3), *LR = c.V(4);
         run_ph_update(c.cs, LQ, Q, QP, R, uc, n, c.w, c.part, d + 8, st);
@@ -768,12 +776,12 @@ static int chain_coeffs(Chain& c, tm_coeffs* out) {
     TM_HIP(hipStreamSynchronize(c.last));
     c.broken_seen = h.broken;
     const int cap = c.cap;
-    std::vector<double2> ha(cap), hg(cap), hz(3 * (size_t)cap);
+    std::vector<double2> ha(cap), hg(cap), hz(kNMeasure * (size_t)cap);
     std::vector<double> hb(cap);
     TM_HIP(hipMemcpy(ha.data(), c.co.alpha, cap * sizeof(double2), hipMemcpyDeviceToHost));
     TM_HIP(hipMemcpy(hb.data(), c.co.beta, cap * sizeof(double), hipMemcpyDeviceToHost));
     TM_HIP(hipMemcpy(hg.data(), c.co.gamma, cap * sizeof(double2), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hz.data(), c.co.z, 3 * cap * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hz.data(), c.co.z, kNMeasure * (size_t)cap * sizeof(double2), hipMemcpyDeviceToHost));
     out->steps_done = h.step;
     out->n1 = h.n1;
     const int m = std::min(cap, out->capacity);
@@ -787,13 +795,17 @@ static int chain_coeffs(Chain& c, tm_coeffs* out) {
             out->z[2 * ((size_t)l * out->capacity + j)] = hz[l * (size_t)cap + j].x;
             out->z[2 * ((size_t)l * out->capacity + j) + 1] = hz[l * (size_t)cap + j].y;
         }
+        if (out->zn) {
+            out->zn[2 * j] = hz[3 * (size_t)cap + j].x;
+            out->zn[2 * j + 1] = hz[3 * (size_t)cap + j].y;
+        }
     }
     return h.broken ? TM_EBREAKDOWN : TM_OK;
 }
 
 // ---- checkpoint: header, device state struct, coefficients, vectors
 struct ChainBlobHeader {
-    char magic[8];       // "TMCHAIN1"
+    char magic[8];       // "TMCHAIN2"
     int iq, dir, flavour, fp32, cap, issued, nvec;
     int ix[9];
     long long n;
@@ -801,13 +813,13 @@ struct ChainBlobHeader {
 
 static size_t chain_blob_bytes(const Chain& c) {
     return sizeof(ChainBlobHeader) + sizeof(ChainState) + (size_t)c.cap * (3 * sizeof(double2) + sizeof(double)) +
-           3 * (size_t)c.cap * sizeof(double2) + (c.vec.size() + 3) * (size_t)c.n * sizeof(double2);
+           kNMeasure * (size_t)c.cap * sizeof(double2) + (c.vec.size() + kNMeasure) * (size_t)c.n * sizeof(double2);
 }
 
 static void chain_save(Chain& c, char* out) {
     TM_HIP(hipStreamSynchronize(c.last));
     ChainBlobHeader h{};
-    std::memcpy(h.magic, "TMCHAIN1", 8);
+    std::memcpy(h.magic, "TMCHAIN2", 8);
     h.iq = c.iq;
     h.dir = c.dir;
     h.flavour = c.flavour;
@@ -828,13 +840,13 @@ static void chain_save(Chain& c, char* out) {
     p += c.cap * sizeof(double);
     TM_HIP(hipMemcpy(p, c.co.gamma, c.cap * sizeof(double2), hipMemcpyDeviceToHost));
     p += c.cap * sizeof(double2);
-    TM_HIP(hipMemcpy(p, c.co.z, 3 * (size_t)c.cap * sizeof(double2), hipMemcpyDeviceToHost));
-    p += 3 * (size_t)c.cap * sizeof(double2);
+    TM_HIP(hipMemcpy(p, c.co.z, kNMeasure * (size_t)c.cap * sizeof(double2), hipMemcpyDeviceToHost));
+    p += kNMeasure * (size_t)c.cap * sizeof(double2);
     for (double2* v : c.vec) {
         TM_HIP(hipMemcpy(p, v, c.n * sizeof(double2), hipMemcpyDeviceToHost));
         p += c.n * sizeof(double2);
     }
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < kNMeasure; ++l) {
         TM_HIP(hipMemcpy(p, c.u[l], c.n * sizeof(double2), hipMemcpyDeviceToHost));
         p += c.n * sizeof(double2);
     }
@@ -846,14 +858,14 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     ChainBlobHeader h{};
     TM_CHECK(bytes >= sizeof(h), TM_EINVAL, "checkpoint too short");
     std::memcpy(&h, in, sizeof(h));
-    TM_CHECK(std::memcmp(h.magic, "TMCHAIN1", 8) == 0, TM_EINVAL, "not a chain checkpoint");
+    TM_CHECK(std::memcmp(h.magic, "TMCHAIN2", 8) == 0, TM_EINVAL, "not a chain checkpoint");
     System& s = *c.s;
     TM_CHECK(h.iq >= 0 && h.iq < (int)s.qs.size(), TM_EINVAL, "checkpoint q set not in this system");
     const QSet& q = s.qs[h.iq];
     TM_CHECK(h.n == 2LL * q.nk * s.nbnd * 2 * q.npw_pad, TM_EINVAL, "checkpoint vectors do not fit this system");
     TM_CHECK(h.flavour == TM_PSEUDOHERMITIAN || h.flavour == TM_NONHERMITIAN, TM_EINVAL, "bad flavour");
     TM_CHECK(h.nvec == (h.flavour == TM_PSEUDOHERMITIAN ? 5 : 9), TM_EINVAL, "bad vector count");
-    TM_CHECK(h.dir >= TM_DIR_X && h.dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+    TM_CHECK(h.dir >= TM_DIR_X && h.dir <= TM_DIR_N, TM_EINVAL, "bad direction");
     TM_CHECK(h.cap >= 1 && capacity >= 0, TM_EINVAL, "bad capacity");
     {
         int seen = 0;
@@ -870,7 +882,7 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     TM_CHECK(h.issued >= 0 && h.issued <= h.cap, TM_EINVAL, "bad step count");
     c.n = h.n;
     const size_t need = sizeof(h) + sizeof(ChainState) + (size_t)h.cap * (3 * sizeof(double2) + sizeof(double)) +
-                        3 * (size_t)h.cap * sizeof(double2) + (h.nvec + 3) * (size_t)h.n * sizeof(double2);
+                        kNMeasure * (size_t)h.cap * sizeof(double2) + (h.nvec + kNMeasure) * (size_t)h.n * sizeof(double2);
     TM_CHECK(bytes >= need, TM_EINVAL, "checkpoint truncated");
     QSet& qm = s.qs[c.iq];
     ensure_workspace(s, qm);
@@ -878,12 +890,12 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     c.half = c.n / 2;
     c.w = 1.0 / qm.nk;
     for (int i = 0; i < h.nvec; ++i) c.vec.push_back(static_cast<double2*>(c.alloc(c.n * sizeof(double2))));
-    for (int l = 0; l < 3; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
+    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
     c.co.cap = c.cap;
     c.co.alpha = static_cast<double2*>(c.alloc(c.cap * sizeof(double2)));
     c.co.beta = static_cast<double*>(c.alloc(c.cap * sizeof(double)));
     c.co.gamma = static_cast<double2*>(c.alloc(c.cap * sizeof(double2)));
-    c.co.z = static_cast<double2*>(c.alloc(3 * (size_t)c.cap * sizeof(double2)));
+    c.co.z = static_cast<double2*>(c.alloc(kNMeasure * (size_t)c.cap * sizeof(double2)));
     c.cs = static_cast<ChainState*>(c.alloc(sizeof(ChainState)));
     c.dots = static_cast<double2*>(c.alloc(16 * sizeof(double2)));
     c.part = static_cast<double2*>(c.alloc(1024 * 8 * sizeof(double2)));
@@ -893,7 +905,7 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     TM_HIP(hipMemsetAsync(c.co.alpha, 0, c.cap * sizeof(double2), st));
     TM_HIP(hipMemsetAsync(c.co.beta, 0, c.cap * sizeof(double), st));
     TM_HIP(hipMemsetAsync(c.co.gamma, 0, c.cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(c.co.z, 0, 3 * (size_t)c.cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.z, 0, kNMeasure * (size_t)c.cap * sizeof(double2), st));
     const char* p = in + sizeof(h);
     TM_HIP(hipMemcpyAsync(c.cs, p, sizeof(ChainState), hipMemcpyHostToDevice, st));
     p += sizeof(ChainState);
@@ -904,15 +916,15 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     TM_HIP(hipMemcpyAsync(c.co.gamma, p, h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
     p += h.cap * sizeof(double2);
     // z is [3][cap]: rows move to the new stride
-    for (int l = 0; l < 3; ++l)
+    for (int l = 0; l < kNMeasure; ++l)
         TM_HIP(hipMemcpyAsync(c.co.z + (size_t)l * c.cap, p + (size_t)l * h.cap * sizeof(double2),
                               h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
-    p += 3 * (size_t)h.cap * sizeof(double2);
+    p += kNMeasure * (size_t)h.cap * sizeof(double2);
     for (double2* v : c.vec) {
         TM_HIP(hipMemcpyAsync(v, p, c.n * sizeof(double2), hipMemcpyHostToDevice, st));
         p += c.n * sizeof(double2);
     }
-    for (int l = 0; l < 3; ++l) {
+    for (int l = 0; l < kNMeasure; ++l) {
         TM_HIP(hipMemcpyAsync(c.u[l], p, c.n * sizeof(double2), hipMemcpyHostToDevice, st));
         p += c.n * sizeof(double2);
     }
@@ -923,7 +935,7 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     if (c.cap > h.cap && h.issued == h.cap && hs.step == h.cap && !hs.broken) {
         if (c.flavour == TM_PSEUDOHERMITIAN)
             TM_HIP(hipMemcpyAsync(c.co.alpha + h.cap, &hs.alpha, sizeof(double2), hipMemcpyHostToDevice, st));
-        for (int l = 0; l < 3; ++l)
+        for (int l = 0; l < kNMeasure; ++l)
             TM_HIP(hipMemcpyAsync(c.co.z + (size_t)l * c.cap + h.cap, &hs.znext[l], sizeof(double2),
                                   hipMemcpyHostToDevice, st));
     }
@@ -1213,7 +1225,7 @@ int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void*
         TM_CHECK(sys, TM_EINVAL, "null argument");
         System& s = sys->s;
         TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
-        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_N, TM_EINVAL, "bad direction");
         start_vectors(s, iq, (int)dir, static_cast<double2*>(u), static_cast<double2*>(v),
                       static_cast<hipStream_t>(stream));
         return TM_OK;
@@ -1226,7 +1238,7 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
         TM_CHECK(sys && out, TM_EINVAL, "null argument");
         System& s = sys->s;
         TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
-        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_N, TM_EINVAL, "bad direction");
         TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
         TM_CHECK(nsteps >= 1 && nsteps <= out->capacity, TM_EINVAL, "nsteps must be in [1, capacity]");
         TM_CHECK(out->alpha && out->beta && out->gamma && out->z, TM_EINVAL, "null coefficient array");
@@ -1244,7 +1256,7 @@ int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precisio
         *out = nullptr;
         System& s = sys->s;
         TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
-        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_MINUS, TM_EINVAL, "bad direction");
+        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_N, TM_EINVAL, "bad direction");
         TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
         TM_CHECK(capacity >= 1, TM_EINVAL, "capacity must be >= 1");
         TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
@@ -1346,10 +1358,13 @@ int tm_chi(const tm_coeffs* c, int m_use, const double* omega, int nomega, doubl
     return tm_chi_extrapolated(c, m_use, m_use, TM_EXTRAP_NONE, omega, nomega, eta, chi);
 }
 
-int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega,
-                        int nomega, double eta, double* chi) {
+// chi rows from the measure overlaps: the three spin rows (z), or with
+// `tensor` the charge row (zn) first and then the spin rows
+static int chi_rows(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega, int nomega,
+                    double eta, double* chi, bool tensor) {
     return guarded([&]() -> int {
         TM_CHECK(c && omega && chi, TM_EINVAL, "null argument");
+        TM_CHECK(!tensor || c->zn, TM_EINVAL, "the 4 x 4 tensor needs the charge overlaps zn");
         TM_CHECK(m_use >= 1 && m_use <= c->steps_done && m_use <= c->capacity, TM_EINVAL,
                  "m_use must be in [1, steps_done]");
         TM_CHECK(mode == TM_EXTRAP_NONE || mode == TM_EXTRAP_CONSTANT || mode == TM_EXTRAP_OSC, TM_EINVAL,
@@ -1362,17 +1377,21 @@ int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mo
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) throw Error{TM_EDEVICE, "no HIP device"};
         const int M0 = m_use, M = m_total, cap = c->capacity;
+        const int nz = tensor ? 4 : 3;
+        auto zsrc = [&](int l, int j) -> double2 {
+            const double* zr = tensor ? (l == 0 ? c->zn : c->z + 2 * (size_t)(l - 1) * cap) : c->z + 2 * (size_t)l * cap;
+            return cmk(zr[2 * j], zr[2 * j + 1]);
+        };
         // host coefficients, extended past M0: alpha, beta, gamma by their mean over
         // the second half of the computed ones (one mean: constant; one per parity
         // of the index: osc), z = 0 beyond M0 (no measured overlaps there)
-        std::vector<double2> ha(M), hg(M), hz(3 * (size_t)M, cmk(0.0, 0.0));
+        std::vector<double2> ha(M), hg(M), hz(nz * (size_t)M, cmk(0.0, 0.0));
         std::vector<double> hb(M);
         for (int j = 0; j < M0; ++j) {
             ha[j] = cmk(c->alpha[2 * j], c->alpha[2 * j + 1]);
             hb[j] = c->beta[j];
             hg[j] = cmk(c->gamma[2 * j], c->gamma[2 * j + 1]);
-            for (int l = 0; l < 3; ++l)
-                hz[(size_t)l * M + j] = cmk(c->z[2 * ((size_t)l * cap + j)], c->z[2 * ((size_t)l * cap + j) + 1]);
+            for (int l = 0; l < nz; ++l) hz[(size_t)l * M + j] = zsrc(l, j);
         }
         if (M > M0) {
             const int np = mode == TM_EXTRAP_OSC ? 2 : 1;
@@ -1415,24 +1434,34 @@ int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mo
         double2* da = (double2*)al(M * sizeof(double2));
         double* db = (double*)al(M * sizeof(double));
         double2* dg = (double2*)al(M * sizeof(double2));
-        double2* dz = (double2*)al(3 * (size_t)M * sizeof(double2));
+        double2* dz = (double2*)al(nz * (size_t)M * sizeof(double2));
         double* dw = (double*)al(nomega * sizeof(double));
         double2* work = (double2*)al(4 * (size_t)M * nomega * sizeof(double2));
-        double2* dchi = (double2*)al(3 * (size_t)nomega * sizeof(double2));
+        double2* dchi = (double2*)al(nz * (size_t)nomega * sizeof(double2));
         int* dst = (int*)al(sizeof(int));
         TM_HIP(hipMemcpy(da, ha.data(), M * sizeof(double2), hipMemcpyHostToDevice));
         TM_HIP(hipMemcpy(db, hb.data(), M * sizeof(double), hipMemcpyHostToDevice));
         TM_HIP(hipMemcpy(dg, hg.data(), M * sizeof(double2), hipMemcpyHostToDevice));
-        TM_HIP(hipMemcpy(dz, hz.data(), 3 * (size_t)M * sizeof(double2), hipMemcpyHostToDevice));
+        TM_HIP(hipMemcpy(dz, hz.data(), nz * (size_t)M * sizeof(double2), hipMemcpyHostToDevice));
         TM_HIP(hipMemcpy(dw, omega, nomega * sizeof(double), hipMemcpyHostToDevice));
         TM_HIP(hipMemset(dst, 0, sizeof(int)));
-        launch_chi(da, db, dg, dz, M, M, c->n1, dw, nomega, eta, work, dchi, dst, nullptr);
+        launch_chi(da, db, dg, dz, nz, M, M, c->n1, dw, nomega, eta, work, dchi, dst, nullptr);
         int status = 0;
         TM_HIP(hipMemcpy(&status, dst, sizeof(int), hipMemcpyDeviceToHost));
-        TM_HIP(hipMemcpy(chi, dchi, 3 * (size_t)nomega * sizeof(double2), hipMemcpyDeviceToHost));
+        TM_HIP(hipMemcpy(chi, dchi, nz * (size_t)nomega * sizeof(double2), hipMemcpyDeviceToHost));
         TM_CHECK(status == 0, TM_EINVAL, "singular tridiagonal system (eta = 0 on a pole?)");
         return TM_OK;
     });
+}
+
+int tm_chi_extrapolated(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega,
+                        int nomega, double eta, double* chi) {
+    return chi_rows(c, m_use, m_total, mode, omega, nomega, eta, chi, false);
+}
+
+int tm_chi_tensor(const tm_coeffs* c, int m_use, int m_total, tm_extrap mode, const double* omega, int nomega,
+                  double eta, double* chi) {
+    return chi_rows(c, m_use, m_total, mode, omega, nomega, eta, chi, true);
 }
 
 int tm_structure_factor(const double* q, const double* chi, int nomega, double* s) {

@@ -24,8 +24,8 @@ __device__ inline double2 cdiv(double2 a, double2 b) {
 
 __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 
-__global__ void k_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int cap,
-                      int M, double n1, const double* omega, int nw, double eta, double2* wd, double2* wdu,
+__global__ void k_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int nz,
+                      int cap, int M, double n1, const double* omega, int nw, double eta, double2* wd, double2* wdu,
                       double2* wdu2, double2* wb, double2* chi, int* status) {
     int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nw) return;
@@ -65,7 +65,7 @@ __global__ void k_chi(const double2* alpha, const double* beta, const double2* g
         }
     }
     if (!bad && cabs1(D(M - 1)) == 0.0) bad = 1;
-    double2 acc[3] = {cmk(0, 0), cmk(0, 0), cmk(0, 0)};
+    double2 acc[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};
     if (!bad) {
         double2 x1 = cmk(0, 0), x2 = cmk(0, 0);  // x[i+1], x[i+2]
         for (int i = M - 1; i >= 0; --i) {
@@ -73,23 +73,25 @@ __global__ void k_chi(const double2* alpha, const double* beta, const double2* g
             if (i + 1 < M) r = csub(r, cmul(DU(i), x1));
             if (i + 2 < M) r = csub(r, cmul(DU2(i), x2));
             double2 xi = cdiv(r, D(i));
-            for (int l = 0; l < 3; ++l) acc[l] = cadd(acc[l], cmul(z[(long long)l * cap + i], xi));
+            for (int l = 0; l < 4; ++l)
+                if (l < nz) acc[l] = cadd(acc[l], cmul(z[(long long)l * cap + i], xi));
             x2 = x1;
             x1 = xi;
         }
     } else {
         atomicOr(status, 1);
     }
-    for (int l = 0; l < 3; ++l) chi[(long long)l * nw + w] = cscale(acc[l], n1);
+    for (int l = 0; l < nz; ++l) chi[(long long)l * nw + w] = cscale(acc[l], n1);
 }
 
 }  // namespace
 
-void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int cap, int M,
-                double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
+void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int nz, int cap,
+                int M, double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
                 hipStream_t st) {
+    TM_CHECK(nz >= 1 && nz <= 4, TM_EINVAL, "1 to 4 measure rows");
     long long per = (long long)M * nw;
-    TM_LAUNCH(k_chi, dim3((nw + 63) / 64), dim3(64), 0, st, alpha, beta, gamma, z, cap, M, n1, omega, nw,
+    TM_LAUNCH(k_chi, dim3((nw + 63) / 64), dim3(64), 0, st, alpha, beta, gamma, z, nz, cap, M, n1, omega, nw,
                        eta, work, work + per, work + 2 * per, work + 3 * per, chi, status);
 }
 

@@ -90,14 +90,15 @@ __global__ void k_dot_final(const double2* part, int nblk, int nd, double w, dou
 }
 
 // pH residual: r = slq Lq - alpha sq q - beta sprev qprev; partials of (u_l, r)
+// for the measure vectors l = x, y, z, n
 __global__ void __launch_bounds__(kRedThreads) k_ph_update(const ChainState* cs, const double2* Lq, const double2* q,
                                                             const double2* qp, double2* r, const double2* u0,
-                                                            const double2* u1, const double2* u2, long long n,
-                                                            double2* part) {
+                                                            const double2* u1, const double2* u2,
+                                                            const double2* u3, long long n, double2* part) {
     const double slq = cs->slq.x, sq = cs->sq.x, sp = cs->sprev.x;
     const double a = cs->alpha.x, bp = cs->beta_prev;
     const bool live = !cs->broken;
-    double2 acc[3] = {cmk(0, 0), cmk(0, 0), cmk(0, 0)};
+    double2 acc[4] = {cmk(0, 0), cmk(0, 0), cmk(0, 0), cmk(0, 0)};
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         double2 v = cmk(0.0, 0.0);
         if (live) {
@@ -109,20 +110,22 @@ __global__ void __launch_bounds__(kRedThreads) k_ph_update(const ChainState* cs,
         acc[0] = cadd(acc[0], cmulc(u0[i], v));
         acc[1] = cadd(acc[1], cmulc(u1[i], v));
         acc[2] = cadd(acc[2], cmulc(u2[i], v));
+        acc[3] = cadd(acc[3], cmulc(u3[i], v));
     }
-    block_sum<3>(acc);
+    block_sum<4>(acc);
     if (threadIdx.x == 0)
-        for (int d = 0; d < 3; ++d) part[(long long)blockIdx.x * 3 + d] = acc[d];
+        for (int d = 0; d < 4; ++d) part[(long long)blockIdx.x * 4 + d] = acc[d];
 }
 
 // nH residuals: qh = sq Lq - alpha sq q - gamma_p sqp qp,
 //               ph = sp J Ltp - conj(alpha) sp p - conj(beta_p) spp pp;
-// partials of (ph, qh), (qh, qh), (ph, ph), (u_l, qh)
+// partials of (ph, qh), (qh, qh), (ph, ph), (u_l, qh) for l = x, y, z, n
 __global__ void __launch_bounds__(kRedThreads) k_nh_update(const ChainState* cs, const double2* Lq, const double2* q,
                                                             const double2* qp, const double2* Ltp, const double2* p,
                                                             const double2* pp, double2* qh, double2* ph,
                                                             const double2* u0, const double2* u1, const double2* u2,
-                                                            long long n, long long half, double2* part) {
+                                                            const double2* u3, long long n, long long half,
+                                                            double2* part) {
     const double2 sq = cs->sq, sqp = cs->sprev, sp = cs->sp, spp = cs->spprev;
     const double2 a = cs->alpha;
     const double2 g = cs->gamma_prev;
@@ -130,9 +133,9 @@ __global__ void __launch_bounds__(kRedThreads) k_nh_update(const ChainState* cs,
     const bool live = !cs->broken;
     const double2 c_q = cmul(a, sq), c_qp = cmul(g, sqp);
     const double2 c_p = cmul(cconj(a), sp), c_pp = cscale(spp, bpv);  // conj(beta) = beta (real)
-    double2 acc[6];
+    double2 acc[7];
 #pragma unroll
-    for (int d = 0; d < 6; ++d) acc[d] = cmk(0.0, 0.0);
+    for (int d = 0; d < 7; ++d) acc[d] = cmk(0.0, 0.0);
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         double2 vq = cmk(0.0, 0.0), vp = cmk(0.0, 0.0);
         if (live) {
@@ -149,10 +152,11 @@ __global__ void __launch_bounds__(kRedThreads) k_nh_update(const ChainState* cs,
         acc[3] = cadd(acc[3], cmulc(u0[i], vq));
         acc[4] = cadd(acc[4], cmulc(u1[i], vq));
         acc[5] = cadd(acc[5], cmulc(u2[i], vq));
+        acc[6] = cadd(acc[6], cmulc(u3[i], vq));
     }
-    block_sum<6>(acc);
+    block_sum<7>(acc);
     if (threadIdx.x == 0)
-        for (int d = 0; d < 6; ++d) part[(long long)blockIdx.x * 6 + d] = acc[d];
+        for (int d = 0; d < 7; ++d) part[(long long)blockIdx.x * 7 + d] = acc[d];
 }
 
 __global__ void k_jcopy(const double2* src, double2* dst, long long n, long long half) {
@@ -164,7 +168,7 @@ __global__ void k_jcopy(const double2* src, double2* dst, long long n, long long
 
 // ---- control kernels (one thread) -------------------------------------------------
 
-// pH start; dots: (v, J Lv), (v, v), (Lv, J Lv), (u_l, v) l = 0..2
+// pH start; dots: (v, J Lv), (v, v), (Lv, J Lv), (u_l, v) l = 0..3
 __global__ void k_ph_start(ChainState* cs, const double2* d, Coeffs co) {
     const double n1sq = d[0].x, vv = d[1].x;
     cs->broken = 0;
@@ -182,7 +186,7 @@ __global__ void k_ph_start(ChainState* cs, const double2* d, Coeffs co) {
     cs->alpha = cmk(d[2].x / n1sq, 0.0);
     cs->qq = vv / n1sq;
     co.alpha[0] = cs->alpha;
-    for (int l = 0; l < 3; ++l) co.z[l * co.cap] = cscale(d[3 + l], 1.0 / n1);
+    for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap] = cscale(d[3 + l], 1.0 / n1);
 }
 
 // pH after the apply; d: (r, J Lr), (r, r), (Lr, J Lr); zu: (u_l, r)
@@ -204,10 +208,10 @@ __global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, C
     cs->beta_prev = b;
     cs->alpha = cmk(ll / b2, 0.0);
     cs->qq = rr / b2;
-    for (int l = 0; l < 3; ++l) cs->znext[l] = cscale(zu[l], 1.0 / b);
+    for (int l = 0; l < kNMeasure; ++l) cs->znext[l] = cscale(zu[l], 1.0 / b);
     if (j + 1 < co.cap) {
         co.alpha[j + 1] = cs->alpha;
-        for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
+        for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
     }
 }
 
@@ -228,7 +232,7 @@ __global__ void k_nh_start(ChainState* cs, const double2* d, Coeffs co) {
     cs->beta_prev = 0.0;
     cs->gamma_prev = cmk(0.0, 0.0);
     cs->qq = cs->pp = 1.0;
-    for (int l = 0; l < 3; ++l) co.z[l * co.cap] = cscale(d[1 + l], 1.0 / n1);
+    for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap] = cscale(d[1 + l], 1.0 / n1);
 }
 
 // nH alpha from (P_raw, LQ_raw)
@@ -266,9 +270,9 @@ __global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
     cs->pp = pp / gg;
     cs->beta_prev = b;
     cs->gamma_prev = g;
-    for (int l = 0; l < 3; ++l) cs->znext[l] = cscale(d[3 + l], 1.0 / b);
+    for (int l = 0; l < kNMeasure; ++l) cs->znext[l] = cscale(d[3 + l], 1.0 / b);
     if (j + 1 < co.cap)
-        for (int l = 0; l < 3; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
+        for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
 }
 
 }  // namespace
@@ -284,8 +288,8 @@ void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, d
 }
 template void run_multidot<1>(const DotSet<1>&, long long, long long, double, double2*, double2*, hipStream_t);
 template void run_multidot<3>(const DotSet<3>&, long long, long long, double, double2*, double2*, hipStream_t);
-template void run_multidot<4>(const DotSet<4>&, long long, long long, double, double2*, double2*, hipStream_t);
-template void run_multidot<6>(const DotSet<6>&, long long, long long, double, double2*, double2*, hipStream_t);
+template void run_multidot<5>(const DotSet<5>&, long long, long long, double, double2*, double2*, hipStream_t);
+template void run_multidot<7>(const DotSet<7>&, long long, long long, double, double2*, double2*, hipStream_t);
 
 static int red_blocks(long long n) {
     return (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
@@ -294,8 +298,8 @@ static int red_blocks(long long n) {
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
                    const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st) {
     int nblk = red_blocks(n);
-    TM_LAUNCH(k_ph_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], n, part);
-    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 3, w, out);
+    TM_LAUNCH(k_ph_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3], n, part);
+    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, kNMeasure, w, out);
 }
 
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
@@ -303,8 +307,8 @@ void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, co
                    long long n, long long half, double w, double2* part, double2* out, hipStream_t st) {
     int nblk = red_blocks(n);
     TM_LAUNCH(k_nh_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0], u[1],
-                       u[2], n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 6, w, out);
+                       u[2], u[3], n, half, part);
+    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 3 + kNMeasure, w, out);
 }
 
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st) {

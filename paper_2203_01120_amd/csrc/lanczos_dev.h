@@ -9,6 +9,9 @@ namespace tml {
 constexpr double kBreakdownTol = 1e-10;
 
 // true vector = scale * raw vector
+// measure vectors u^l of a chain: l = x, y, z (spin) and n (charge)
+constexpr int kNMeasure = 4;
+
 struct ChainState {
     double2 sq, slq, sprev;     // q, Lq, q_prev (pH: real)
     double2 sp, spprev;         // p, p_prev (nH)
@@ -18,7 +21,7 @@ struct ChainState {
     double qq, pp;              // (q_i, q_i), (p_i, p_i)
     double lam;
     double n1;
-    double2 znext[3];           // z of the next index, kept when it falls past the capacity
+    double2 znext[kNMeasure];   // z of the next index, kept when it falls past the capacity
     int step;
     int broken;
 };
@@ -27,7 +30,7 @@ struct Coeffs {
     double2* alpha;   // [cap]
     double* beta;     // [cap]
     double2* gamma;   // [cap]
-    double2* z;       // [3][cap]
+    double2* z;       // [kNMeasure][cap]
     int cap;
 };
 

@@ -59,9 +59,9 @@ class SystemSlot:
 
 
 def chain_bytes(nelem: int, flavour: str, nsteps: int) -> int:
-    """Device bytes of one chain: its BR vectors (pH 5 + 3 u, nH 9 + 3 u) and coefficients."""
-    nvec = (5 if flavour == "pH" else 9) + 3
-    return nvec * nelem * 16 + nsteps * 88
+    """Device bytes of one chain: its BR vectors (pH 5 + 4 u, nH 9 + 4 u) and coefficients."""
+    nvec = (5 if flavour == "pH" else 9) + 4
+    return nvec * nelem * 16 + nsteps * 104
 
 
 class Server:

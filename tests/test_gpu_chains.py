@@ -15,7 +15,7 @@ from gpu_util import desc_from_problem, desc_from_problems, from_gpu, rel_err, s
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("alpha", "beta", "gamma", "z")
+KEYS = ("alpha", "beta", "gamma", "z", "zn")
 
 
 @pytest.fixture(scope="module")

@@ -148,7 +148,7 @@ def test_apply_is_linear_and_orthogonal(cubic20):
     assert cubic20.prob.occupied_overlap(la) <= 1e-12 * np.abs(la).max()
 
 
-@pytest.mark.parametrize("direction", ["x", "y", "z", "+", "-"])
+@pytest.mark.parametrize("direction", ["x", "y", "z", "+", "-", "n"])
 def test_start_vectors_match_oracle(cubic20, direction):
     import torch
     say(f"start vectors {direction}")
@@ -160,15 +160,17 @@ def test_start_vectors_match_oracle(cubic20, direction):
     gu, _ = from_gpu(u, cubic20.shape, cubic20.prob.npw_pad)
     gv, _ = from_gpu(v, cubic20.shape, cubic20.prob.npw_pad)
     assert rel_err(gv, cubic20.prob.v_vector(direction)) <= 1e-12
-    if direction in "xyz":
+    if direction in "xyzn":
         assert rel_err(gu, cubic20.prob.u_vector(direction)) <= 1e-13
 
 
-@pytest.mark.parametrize("flavour,mu,nsteps", [("pH", "+", 60), ("nH", "+", 20), ("pH", "z", 20)])
+@pytest.mark.parametrize("flavour,mu,nsteps", [("pH", "+", 60), ("nH", "+", 20), ("pH", "z", 20), ("pH", "n", 30),
+                                               ("nH", "n", 16)])
 def test_lanczos_coefficients_match_oracle(cubic20, flavour, mu, nsteps):
+    """Coefficients and the overlaps with all four measure vectors (x, y, z and the charge n)."""
     say(f"lanczos cubic20 {flavour} {mu} {nsteps}")
     got = cubic20.tm.tm_lanczos_run(cubic20.h, 0, mu, flavour, nsteps)
-    ref = olanczos.run(cubic20.prob, mu, flavour, nsteps)
+    ref = olanczos.run(cubic20.prob, mu, flavour, nsteps, measure=("x", "y", "z", "n"))
     assert got["steps_done"] == ref["steps_done"] == nsteps
     assert not got["breakdown"]
     assert abs(got["n1"] - ref["n1"]) <= 1e-12 * ref["n1"]
@@ -177,7 +179,24 @@ def test_lanczos_coefficients_match_oracle(cubic20, flavour, mu, nsteps):
     assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
     assert np.abs(got["gamma"] - ref["gamma"]).max() <= 1e-10 * np.abs(ref["gamma"]).max()
     zs = np.abs(ref["z"]).max()
-    assert np.abs(got["z"] - ref["z"]).max() <= 1e-10 * zs
+    assert np.abs(got["z"] - ref["z"][:3]).max() <= 1e-10 * zs
+    assert np.abs(got["zn"] - ref["z"][3]).max() <= 1e-10 * zs
+
+
+def test_chi_tensor_matches_oracle(cubic20):
+    """A column of the 4 x 4 (charge + spin) susceptibility for a charge and a spin field."""
+    omega = np.arange(200) * 1e-2 / 27.211386245988
+    eta = 1e-2 / 27.211386245988
+    for mu, flavour in (("n", "pH"), ("z", "nH")):
+        say(f"chi tensor column {mu} {flavour}")
+        coeffs = cubic20.tm.tm_lanczos_run(cubic20.h, 0, mu, flavour, 24)
+        got = cubic20.tm.tm_chi_tensor(coeffs, 24, omega, eta)
+        four = dict(coeffs, z=np.vstack([coeffs["zn"][None], coeffs["z"]]))
+        ref = ochi.chi_lanczos(four, omega, eta, 24)
+        assert rel_err(got, ref) <= 1e-12
+        assert np.array_equal(got[1:], cubic20.tm.tm_chi(coeffs, 24, omega, eta))
+        oref = olanczos.run(cubic20.prob, mu, flavour, 24, measure=("n", "x", "y", "z"))
+        assert rel_err(got, ochi.chi_lanczos(oref, omega, eta, 24)) <= 1e-9
 
 
 def test_chi_matches_oracle(cubic20):

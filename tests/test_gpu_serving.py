@@ -59,7 +59,7 @@ def test_server_chi_identical_to_alone(pool, stagger):
     for r in done:
         alone = tm.tm_lanczos_run(slots[r.system].handle, 0, r.direction, r.flavour, r.nsteps)
         assert r.coeffs["steps_done"] == alone["steps_done"]
-        for key in ("alpha", "beta", "gamma", "z"):
+        for key in ("alpha", "beta", "gamma", "z", "zn"):
             assert np.array_equal(r.coeffs[key], alone[key]), (r.rid, key)
         ref = tm.tm_chi(alone, max(1, alone["steps_done"]), omega, eta)
         assert np.array_equal(r.chi, ref)

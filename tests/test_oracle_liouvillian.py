@@ -55,9 +55,11 @@ def test_output_orthogonal_to_occupied(tiny_prob):
     assert tiny_prob.occupied_overlap(y) < 1e-12 * np.abs(y).max()
 
 
-@pytest.mark.parametrize("lam,mu", [("x", "x"), ("x", "y"), ("y", "x"), ("z", "z"), ("x", "z")])
+@pytest.mark.parametrize("lam,mu", [("x", "x"), ("x", "y"), ("y", "x"), ("z", "z"), ("x", "z"),
+                                    ("n", "n"), ("n", "z"), ("z", "n"), ("x", "n")])
 def test_k0_matches_kubo_sum(tiny_gs, tiny_prob, tiny_ts, lam, mu):
-    """P2: with the kernel off, (u, (w - L)^{-1} v) is the textbook Kubo sum."""
+    """P2: with the kernel off, (u, (w - L)^{-1} v) is the textbook Kubo sum
+    (n: the charge channel, sigma_0; pins its time-reversal signs)."""
     om = np.linspace(-2.0, 2.0, 41)
     L0 = tiny_ts.liouvillian(kernel=False)
     cd = tiny_ts.chi_dense(L0, tiny_prob.u_vector(lam), tiny_prob.v_vector(mu), om, 0.05)
@@ -89,6 +91,22 @@ def test_sum_rule_identity_at_q0(tiny_gs):
         for j, m in enumerate("xyz"):
             val = prob.dot(prob.u_vector(l), prob.v_vector(m))
             assert abs(val - 2j * eps[i, j] @ M) < 1e-12
+
+
+def test_charge_channel_commutes_at_q0(tiny_gs):
+    """P6 for the charge row and column: sigma_0 commutes with every sigma, so
+    (u^n, v^m) = 0 at q = 0 while both vectors are nonzero; and a uniform
+    potential moves no charge, so v^n itself vanishes at q = 0 (the occupied
+    states are projected out of themselves) but not at finite q."""
+    prob = lv.build_problem(tiny_gs, np.zeros(3))
+    un = prob.u_vector("n")
+    assert np.linalg.norm(un) > 0.1
+    for m in "xy+":   # (v^z may vanish too: the tiny system keeps S_z)
+        vm = prob.v_vector(m)
+        assert np.linalg.norm(vm) > 1e-3
+        assert abs(prob.dot(un, vm)) < 1e-12
+    assert np.abs(prob.v_vector("n")).max() < 1e-13
+    assert np.linalg.norm(lv.build_problem(tiny_gs, synth.cart_from_frac(tiny_gs.sysd, (0.1, 0.05, 0))).v_vector("n")) > 1e-2
 
 
 def test_sum_rule_frequency_integral(tiny_prob):
