@@ -67,7 +67,7 @@ def make_desc(inp):
                          shifts=qs.shifts[None])
 
 
-def kernel_models(inp, info, resident: bool):
+def kernel_models(inp, info, resident: bool, lanes: int = 1):
     """Algorithmic work per launch of the main kernels: flops and HBM bytes.
 
     Plane kernels, per band, spin pair and plane i3: a 2D FFT of n1 x n2
@@ -77,6 +77,8 @@ def kernel_models(inp, info, resident: bool):
     column path the kernels also finish the inverse transforms of u (2 more).
     Bytes: x columns in (and out for the apply), u planes or u columns in, the
     fields once per block (apply), the 4 density partial planes once per block.
+    With `lanes` right-hand sides per launch, everything per right-hand side
+    scales with it; the ground state is needed once.
     """
     sysd = inp["sysd"]
     n1, n2, n3 = sysd.fft
@@ -94,11 +96,13 @@ def kernel_models(inp, info, resident: bool):
     u_bytes = 2 * NP * 16 if resident else 2 * ncol_avg * 16
     n_inv = 2 if resident else 4
     blocks = 2 * nk * n3
-    apply_flops = bands * n3 * ((n_inv + 2) * fft2d + 60.0 * NP)
-    apply_bytes = bands * n3 * (4 * ncol_avg * 16 + u_bytes) + blocks * NP * 96
-    dens_flops = bands * n3 * (n_inv * fft2d + 40.0 * NP)
-    dens_bytes = bands * n3 * (2 * ncol_avg * 16 + u_bytes) + blocks * 4 * NP * 16
-    gemm_flops = 8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P)
+    L = lanes
+    apply_flops = L * bands * n3 * ((n_inv + 2) * fft2d + 60.0 * NP)
+    apply_bytes = bands * n3 * (L * 4 * ncol_avg * 16 + u_bytes) + L * blocks * NP * 96
+    dens_flops = L * bands * n3 * (n_inv * fft2d + 40.0 * NP)
+    dens_bytes = bands * n3 * (L * 2 * ncol_avg * 16 + u_bytes) + L * blocks * 4 * NP * 16
+    gemm_flops = L * 8.0 * 2 * nk * (nb * nb * 2 * P + nproj * 2 * nb * P)
+    vec_bytes = L * vec_bytes
     return {
         "k_apply_planes": dict(flops=apply_flops, bytes=apply_bytes),
         "k_apply_t": dict(flops=apply_flops, bytes=apply_bytes),
@@ -107,8 +111,8 @@ def kernel_models(inp, info, resident: bool):
         "k_density_t": dict(flops=dens_flops, bytes=dens_bytes),
         "k_density_w": dict(flops=dens_flops, bytes=dens_bytes),
         # single-precision bulk: x columns FP32, u planes still read in FP64
-        "k_apply_w32": dict(flops=apply_flops, bytes=apply_bytes - bands * n3 * 2 * ncol_avg * 16, fp32=True),
-        "k_density_w32": dict(flops=dens_flops, bytes=dens_bytes - bands * n3 * ncol_avg * 16, fp32=True),
+        "k_apply_w32": dict(flops=apply_flops, bytes=apply_bytes - L * bands * n3 * 2 * ncol_avg * 16, fp32=True),
+        "k_density_w32": dict(flops=dens_flops, bytes=dens_bytes - L * bands * n3 * ncol_avg * 16, fp32=True),
         # projector GEMMs: S = O^H phi and phi -= O S (8 real flops per complex MAC)
         "k_gemm_cn": dict(flops=gemm_flops, bytes=vec_bytes, mfma=True),
         "k_gemm_update": dict(flops=gemm_flops, bytes=2 * vec_bytes, mfma=True),
@@ -329,6 +333,9 @@ def main():
     ap.add_argument("--rates", default="0.5,1,2", help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--tensor", default="",
+                    help="hexslab/cubic20: field directions run together as lanes of one chain "
+                         "(e.g. xyz: the 3 x 3 spin tensor in one pass); default: the m_+ chain alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-samples", type=int, default=20)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
@@ -371,8 +378,17 @@ def main():
     if args.no_resident:
         tm.tm_system_set_resident_limit(h, 0)
     prec = tm.TM_FP32 if args.precision == "fp32" else tm.TM_FP64
-    log(f"warmup {args.warmup} steps ({args.precision})")
-    tm.tm_lanczos_run(h, 0, "+", "pH", max(1, args.warmup), prec)
+    dirs = list(args.tensor) if args.tensor else ["+"]
+    lanes = len(dirs)
+
+    def run(nsteps, p=prec):
+        """the timed unit: one chain (or one tensor chain of `lanes` directions) of nsteps steps"""
+        if args.tensor:
+            return tm.tm_tensor_run(h, 0, dirs, "pH", nsteps, p)[0]
+        return tm.tm_lanczos_run(h, 0, "+", "pH", nsteps, p)
+
+    log(f"warmup {args.warmup} steps ({args.precision}, directions {''.join(dirs)})")
+    run(max(1, args.warmup))
     torch.cuda.synchronize()
     resident = tm.tm_system_resident_bytes(h)
     log(f"resident real-space ground state: {resident / 1e9:.2f} GB")
@@ -380,20 +396,20 @@ def main():
     log(f"timed {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = tm.tm_lanczos_run(h, 0, "+", "pH", args.steps, prec)
+    res = run(args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     log(f"profiled run of {args.steps} steps")
     tm.tm_profile_reset()
     tm.tm_profile_enable(True)
     t1 = time.perf_counter()
-    tm.tm_lanczos_run(h, 0, "+", "pH", args.steps, prec)
+    run(args.steps)
     torch.cuda.synchronize()
     dt_prof = time.perf_counter() - t1
     tm.tm_profile_enable(False)
     accuracy = None
     if prec == tm.TM_FP32:   # the same chain in FP64 (untimed): spectrum error of the FP32 bulk path
-        ref = tm.tm_lanczos_run(h, 0, "+", "pH", args.steps, tm.TM_FP64)
+        ref = run(args.steps, tm.TM_FP64)
         om = np.arange(400) * 5e-3 / EV
         eta = 5e-3 / EV
         m = min(res["steps_done"], ref["steps_done"])
@@ -417,7 +433,7 @@ def main():
         name = k.strip("()").split("<")[0]
         old = prof.get(name, (0.0, 0))
         prof[name] = (old[0] + ms, old[1] + cnt)
-    applies = args.steps + 1
+    applies = lanes * (args.steps + 1)
     applies_per_s = applies / dt
     log(f"{args.steps} steps in {dt:.3f} s -> {applies_per_s:.3f} applies/s (profiled run {dt_prof:.3f} s); "
         f"breakdown={res['breakdown']}")
@@ -425,19 +441,20 @@ def main():
     # per-apply latency
     lat = []
     n = info["nelem"]
-    x = torch.empty(n, dtype=torch.complex128, device="cuda")
+    x = torch.empty(lanes * n, dtype=torch.complex128, device="cuda")
     y = torch.empty_like(x)
-    tm.tm_start_vectors(h, 0, "+", None, x)
+    for r, d in enumerate(dirs):
+        tm.tm_start_vectors(h, 0, d, None, x[r * n:(r + 1) * n])
     for _ in range(args.latency_samples):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        tm.tm_liouvillian_apply(h, 0, x, y)
+        tm.tm_liouvillian_apply_multi(h, 0, lanes, x, y, prec)
         e1.record()
         torch.cuda.synchronize()
         lat.append(e0.elapsed_time(e1))
     lat = np.array(lat) if lat else np.array([dt / applies * 1e3])
 
-    models = kernel_models(inp, info, resident > 0)
+    models = kernel_models(inp, info, resident > 0, lanes)
     total_ms = sum(v[0] for v in prof.values())
     kernels = {k: {"ms_total": round(v[0], 3), "launches": v[1], "ms_avg": round(v[0] / max(v[1], 1), 4),
                    "share": round(v[0] / total_ms, 4)} for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
@@ -486,9 +503,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": ("CrI3-monolayer-shaped hexagonal slab, a=13 c=31 bohr, 2+6 Gaussian sites, "
-                         "48x48x180 grid, 104 bands, 6x6x1 mesh (36 k), q=b1/6, pH chain m_+"
+                         "48x48x180 grid, 104 bands, 6x6x1 mesh (36 k), q=b1/6, "
                          if args.workload == "hexslab" else
-                         "cubic a=10 bohr, 2 sites, 20^3 grid, 8 bands, Gamma, q=0.1 2pi/a, pH chain m_+"),
+                         "cubic a=10 bohr, 2 sites, 20^3 grid, 8 bands, Gamma, q=0.1 2pi/a, ") +
+                        (f"pH chains of directions {args.tensor} in one pass" if args.tensor else "pH chain m_+"),
+            "directions": "".join(dirs),
             "fft": list(sysd.fft), "nbnd": sysd.nbnd, "nk": info["nk"], "npw_pad": info["npw_pad"],
             "nproj": sysd.nproj, "precision": args.precision, "flavour": "pseudo_hermitian",
         },

@@ -183,6 +183,17 @@ int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out
                          tm_precision prec, void* stream);
 
 /*
+ * tm_liouvillian_apply_multi: nrhs (1..4) applications in one pass.  xy_in and
+ * xy_out hold nrhs BR vectors back to back (vector r at + r * nelem complex
+ * elements); the kernels take the right-hand sides as extra batches, reading
+ * the ground state and the projector and occupied-state tables once for all.
+ * Each output equals tm_liouvillian_apply of its input bit for bit.  Grows the
+ * system's workspace to nrhs right-hand sides (see tm_chain_begin_multi).
+ */
+int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_in, void* xy_out,
+                               tm_precision prec, void* stream);
+
+/*
  * tm_start_vectors: the BR vectors of Sec. 2.5 (below Eq. off-diag-resolvent):
  *   u^dir = ( sigma U~_{n,k}, -sigma T U~_{n,-k} ),
  *   v^dir = ( P sigma U~_{n,k}, P+ sigma T U~_{n,-k} ),
@@ -225,6 +236,16 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
                    tm_precision prec, tm_coeffs* out);
 
 /*
+ * tm_tensor_run: tm_lanczos_run for ndir directions at once (1..4, e.g. x, y,
+ * z for the 3 x 3 spin tensor or n, x, y, z for the 4 x 4 one), stepped
+ * together as the lanes of one chain (see tm_chain_begin_multi); out: ndir
+ * tm_coeffs, each as tm_lanczos_run fills it.  TM_EBREAKDOWN if any lane
+ * broke down (the others ran all nsteps).  Synchronous.
+ */
+int tm_tensor_run(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, int nsteps,
+                  tm_precision prec, tm_coeffs* out);
+
+/*
  * Chain-level interface (serving).  One chain = one recursion of Sec. 2.5 for
  * (q set, direction, flavour), resident on the device; tm_lanczos_run is
  * begin + steps + coeffs + end.
@@ -242,8 +263,23 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
  *   the device: after a breakdown the chain's coefficients stop changing.
  * tm_chain_coeffs: waits for the chain's last stream, copies the first
  *   min(capacity, out->capacity) coefficients, steps_done and n1 into `out`
- *   (layout of tm_coeffs); TM_EBREAKDOWN when the chain has broken down.
+ *   (layout of tm_coeffs; one struct per lane, see below); TM_EBREAKDOWN
+ *   when a lane has broken down.
  * tm_chain_end: waits for the chain's last stream and frees it (NULL allowed).
+ *
+ * Several field directions in one pass (the full tensor; ipol = 4 of
+ * turbo_magnon, Table 1): tm_chain_begin_multi starts one chain with ndir
+ * lanes (1 <= ndir <= 4), one independent recursion per direction dirs[r].
+ * The lanes step together: every application of L, every projection and
+ * every inner product runs once for all lanes, with the lanes as extra
+ * batches of the same kernels (the ground state and the projector and
+ * occupied-state tables are read once per step for all of them).  Each lane's
+ * coefficients equal those of a single-direction chain bit for bit; a lane
+ * that breaks down idles while the others go on.  tm_chain_lanes returns the
+ * lane count; tm_chain_coeffs then takes an array of that many tm_coeffs.
+ * The system's apply workspace grows to ndir right-hand sides (its
+ * reallocation makes other chains of the system re-capture their graphs).
+ * tm_chain_begin is tm_chain_begin_multi with one direction.
  */
 typedef struct tm_chain tm_chain;
 /* Steps are replayed from a captured HIP graph of one period of steps (6
@@ -253,6 +289,9 @@ typedef struct tm_chain tm_chain;
 int tm_chains_use_graphs(int on);
 int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity,
                    void* stream, tm_chain** out);
+int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, tm_precision prec,
+                         int capacity, void* stream, tm_chain** out);
+int tm_chain_lanes(const tm_chain* chain, int* lanes);
 int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream);
 int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out);
 int tm_chain_end(tm_chain* chain);
@@ -262,8 +301,9 @@ int tm_chain_end(tm_chain* chain);
  * turbo_magnon, Sec. 3.2 and Table 1): the chain's complete state -- its BR
  * vectors, the three u^lambda, the coefficients and the device scale/step
  * state -- as one host blob.
- * tm_chain_state_size: bytes of the blob (pseudo-Hermitian: 9 BR vectors,
- *   non-Hermitian: 13, plus 104 bytes per step of capacity and a header).
+ * tm_chain_state_size: bytes of the blob (per lane 5 BR vectors pseudo-Hermitian
+ *   or 9 non-Hermitian and 104 bytes per step of capacity, plus the 4 shared
+ *   measure vectors and a header).
  * tm_chain_save: waits for the chain's last stream and copies its state into
  *   `host` (caller-owned, at least tm_chain_state_size bytes); the chain stays
  *   usable.

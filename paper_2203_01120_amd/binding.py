@@ -27,6 +27,7 @@ EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_sys
             "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
+            "tm_chain_begin_multi", "tm_chain_lanes", "tm_tensor_run", "tm_liouvillian_apply_multi",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -95,8 +96,15 @@ def load(path: str = LIB_PATH):
                                         C.POINTER(C.c_double)]
     lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    lib.tm_liouvillian_apply_multi.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
+                                               C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
     lib.tm_lanczos_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_Coeffs)]
+    lib.tm_tensor_run.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int,
+                                  C.POINTER(_Coeffs)]
+    lib.tm_chain_begin_multi.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int,
+                                         C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.tm_chain_lanes.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
     lib.tm_chi.argtypes = [C.POINTER(_Coeffs), C.c_int, C.POINTER(C.c_double), C.c_int, C.c_double,
                            C.POINTER(C.c_double)]
     lib.tm_profile_enable.argtypes = [C.c_int]
@@ -252,6 +260,15 @@ def tm_liouvillian_apply(h, iq: int, xy_in, xy_out, prec: int = TM_FP64, stream=
                                        C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
 
 
+def tm_liouvillian_apply_multi(h, iq: int, nrhs: int, xy_in, xy_out, prec: int = TM_FP64, stream=None):
+    """nrhs applications in one pass; xy_in / xy_out hold nrhs BR vectors back to back."""
+    nelem = tm_qset_info_get(h, iq)["nelem"]
+    _check_tensor(xy_in, nrhs * nelem)
+    _check_tensor(xy_out, nrhs * nelem)
+    _check(load().tm_liouvillian_apply_multi(C.c_void_p(h), iq, int(nrhs), C.c_void_p(xy_in.data_ptr()),
+                                             C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
+
+
 def tm_start_vectors(h, iq: int, direction: str, u=None, v=None, stream=None):
     nelem = tm_qset_info_get(h, iq)["nelem"]
     for t in (u, v):
@@ -312,11 +329,54 @@ def tm_chains_step(chains, k_steps: int, stream=None) -> None:
     _check(load().tm_chains_step(arr, len(chains), int(k_steps), _stream(stream)))
 
 
+def tm_chain_lanes(chain) -> int:
+    n = C.c_int(0)
+    _check(load().tm_chain_lanes(C.c_void_p(chain), C.byref(n)))
+    return n.value
+
+
+def _lane_coeffs(capacity: int, lanes: int):
+    pairs = [_coeff_arrays(int(capacity)) for _ in range(lanes)]
+    return (_Coeffs * max(lanes, 1))(*[p[0] for p in pairs]), [p[1] for p in pairs]
+
+
+def _lane_dicts(carr, arrs, rc):
+    return [dict(a, n1=co.n1, steps_done=co.steps_done, breakdown=co.steps_done < co.capacity and rc == TM_EBREAKDOWN)
+            for co, a in zip(carr, arrs)]
+
+
+def tm_chain_coeffs_lanes(chain, capacity: int) -> list:
+    """Coefficients of every lane of a chain so far (waits for its stream)."""
+    carr, arrs = _lane_coeffs(capacity, tm_chain_lanes(chain))
+    rc = _check(load().tm_chain_coeffs(C.c_void_p(chain), carr), allow=(TM_EBREAKDOWN,))
+    return _lane_dicts(carr, arrs, rc)
+
+
 def tm_chain_coeffs(chain, capacity: int) -> dict:
-    """Coefficients of a chain so far (waits for its stream)."""
+    """Coefficients of a single-direction chain so far (waits for its stream)."""
     co, arrs = _coeff_arrays(int(capacity))
+    assert tm_chain_lanes(chain) == 1, "use tm_chain_coeffs_lanes for a chain of several directions"
     rc = _check(load().tm_chain_coeffs(C.c_void_p(chain), C.byref(co)), allow=(TM_EBREAKDOWN,))
     return dict(arrs, n1=co.n1, steps_done=co.steps_done, breakdown=rc == TM_EBREAKDOWN)
+
+
+def tm_chain_begin_multi(h, iq: int, directions, flavour: str, capacity: int, prec: int = TM_FP64,
+                         stream=None) -> int:
+    """One chain whose lanes run several field directions together."""
+    d = (C.c_int * len(directions))(*[DIRS[x] for x in directions])
+    out = C.c_void_p()
+    _check(load().tm_chain_begin_multi(C.c_void_p(h), iq, len(directions), d, FLAVOURS[flavour], prec,
+                                       int(capacity), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def tm_tensor_run(h, iq: int, directions, flavour: str, nsteps: int, prec: int = TM_FP64) -> list:
+    """tm_lanczos_run for several directions in one pass; one coefficient dict per direction."""
+    d = (C.c_int * len(directions))(*[DIRS[x] for x in directions])
+    carr, arrs = _lane_coeffs(nsteps, len(directions))
+    rc = _check(load().tm_tensor_run(C.c_void_p(h), iq, len(directions), d, FLAVOURS[flavour], int(nsteps), prec,
+                                     carr), allow=(TM_EBREAKDOWN,))
+    return _lane_dicts(carr, arrs, rc)
 
 
 def tm_chains_use_graphs(on: bool) -> None:

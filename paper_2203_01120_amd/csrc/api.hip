@@ -11,8 +11,6 @@
 namespace tml {
 
 void launch_kin(const System& s, double* kin, const int* d_mill, int npw, int npw_pad, const double* p, hipStream_t st);
-void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
-                           bool f32 = false);
 size_t gemm_partial_elems(int nbatch, int M, int Nn, int K);
 void launch_chi(const double2* alpha, const double* beta, const double2* gamma, const double2* z, int nz, int cap,
                 int M, double n1, const double* omega, int nw, double eta, double2* work, double2* chi, int* status,
@@ -433,9 +431,25 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
 
 // Workspace of the apply, sized once for every q set of the system: captured
 // chain graphs keep its pointers, so it is never reallocated afterwards.
-void ensure_workspace(System& s, const QSet&) {
+static void free_workspace(Workspace& w) {
+    void* wp[] = {w.xcols, w.rho_part, w.rho, w.W, w.work, w.gpart, w.gsmall, w.dots, w.dotpart, w.fields};
+    for (void* p : wp)
+        if (p) (void)hipFree(p);
+    w = Workspace{};
+}
+
+// Sized for nrhs right-hand sides over all q sets.  Growing it frees the old
+// buffers (after the device is idle) and bumps the epoch, so chains re-capture
+// their step graphs, which hold its pointers.
+void ensure_workspace(System& s, const QSet&, int nrhs) {
     Workspace& w = s.ws;
-    if (w.rho) return;
+    if (w.rho && w.width >= nrhs) return;
+    if (w.rho) {
+        TM_HIP(hipDeviceSynchronize());
+        free_workspace(w);
+        ++s.ws_epoch;
+    }
+    w.width = nrhs;
     const int nb = s.nbnd;
     int nb2 = 0, ncol_max = 0, npw_pad = 0;
     for (const QSet& q : s.qs) {
@@ -445,11 +459,12 @@ void ensure_workspace(System& s, const QSet&) {
     }
     long long blocks_per_chunk = (long long)s.n3 * nb2;
     w.nchunk = (int)std::min<long long>(nb, std::max<long long>(1, (2048 + blocks_per_chunk - 1) / blocks_per_chunk));
-    w.cap_xcols = (size_t)nb2 * 2 * nb * s.n3 * ncol_max;
-    w.cap_rho_part = (size_t)nb2 * w.nchunk * 4 * s.N;
-    w.cap_gpart = std::max(gemm_partial_elems(nb2, nb, nb, 2 * npw_pad),
-                           gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, npw_pad));
-    w.cap_gsmall = std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
+    const size_t R = (size_t)nrhs;
+    w.cap_xcols = R * nb2 * 2 * nb * s.n3 * ncol_max;
+    w.cap_rho_part = R * nb2 * w.nchunk * 4 * s.N;
+    w.cap_gpart = R * std::max(gemm_partial_elems(nb2, nb, nb, 2 * npw_pad),
+                               gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, npw_pad));
+    w.cap_gsmall = R * std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
     auto grab = [&](void** p, size_t bytes) {
         if (hipMalloc(p, bytes) != hipSuccess) {
             (void)hipGetLastError();
@@ -460,12 +475,12 @@ void ensure_workspace(System& s, const QSet&) {
     grab((void**)&w.rho_part, w.cap_rho_part * sizeof(double2));
     grab((void**)&w.gpart, w.cap_gpart * sizeof(double2));
     grab((void**)&w.gsmall, w.cap_gsmall * sizeof(double2));
-    grab((void**)&w.W, 4 * s.N * sizeof(double2));
+    grab((void**)&w.W, R * 4 * s.N * sizeof(double2));
     grab((void**)&w.work, s.N * sizeof(double2));
     grab((void**)&w.dots, 64 * sizeof(double2));
     grab((void**)&w.dotpart, 1024 * 8 * sizeof(double2));
-    if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, 6 * s.N * sizeof(double2));
-    grab((void**)&w.rho, 4 * s.N * sizeof(double2));  // last: marks the workspace complete
+    if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, R * 6 * s.N * sizeof(double2));
+    grab((void**)&w.rho, R * 4 * s.N * sizeof(double2));  // last: marks the workspace complete
 }
 
 // Ground-state planes for the plane kernels.  With fixed-size plane kernels
@@ -530,21 +545,21 @@ static void reset_ground(System& s) {
 // nonlocal/projector contractions run in single precision (FP32 MFMA, FP32
 // accumulation); the potential (Hartree + kernel), the kinetic term and the
 // vectors stay FP64.  Needs the fixed-size kernels and the resident ground state.
-void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st) {
+void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st, int nrhs) {
     QSet& q = s.qs[iq];
-    ensure_workspace(s, q);
+    ensure_workspace(s, q, nrhs);
     ensure_ground(s, q, st);
     if (fp32)
         TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
                  "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
-    launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st, fp32);
-    launch_density(s, q, st, fp32);
-    launch_potential(s, q, st);
-    launch_apply_planes(s, q, st, fp32);
-    launch_zpass_fwd(s, q, s.ws.xcols, in, out, st, fp32);
-    launch_nonlocal(s, q, in, out, st, fp32);
-    launch_project(s, q, out, st, fp32);
+    launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st, fp32, nrhs);
+    launch_density(s, q, st, fp32, nrhs);
+    launch_potential(s, q, st, nrhs);
+    launch_apply_planes(s, q, st, fp32, nrhs);
+    launch_zpass_fwd(s, q, s.ws.xcols, in, out, st, fp32, nrhs);
+    launch_nonlocal(s, q, in, out, st, fp32, nrhs);
+    launch_project(s, q, out, st, fp32, nrhs);
 }
 
 void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st) {
@@ -563,27 +578,36 @@ void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream
 // assignment (pH: q_prev, q, r rotate in 3, Lq, Lr in 2; nH: two 3-cycles).
 constexpr int kPeriodPH = 6, kPeriodNH = 3;
 
-// One Lanczos chain (Sec. 2.5) resident on the device: its vectors, the
-// three u^lambda, the coefficient arrays and the scale/step state.  Steps are
-// issued asynchronously; the step index and the breakdown flag live on the
-// device, so a chain never returns to the host until its coefficients are read.
+// One Lanczos chain (Sec. 2.5) resident on the device: its vectors, the four
+// measure vectors u^lambda, the coefficient arrays and the scale/step state.
+// A chain may carry several lanes: independent recursions for several field
+// directions (the columns of the susceptibility tensor) that step together,
+// so that every application of L runs on all of them at once (the plane,
+// z-pass and contraction kernels take the lanes as extra batches and read the
+// ground state and the projectors once for all).  Work vector i of lane r
+// sits at vec[i] + r n.  Steps are issued asynchronously; step indices and
+// breakdown flags live on the device, so a chain never returns to the host
+// until its coefficients are read.
 struct Chain {
     System* s = nullptr;
-    int iq = 0, dir = 0, flavour = 0, cap = 0;
+    int iq = 0, flavour = 0, cap = 0;
+    int lanes = 1;
+    int dir[kMaxLanes] = {};
     bool fp32 = false;         // single-precision applies (recurrence and dots stay FP64)
     long long n = 0, half = 0;
     double w = 1.0;
-    std::vector<double2*> vec;  // work vectors (5 pH, 9 nH)
+    std::vector<double2*> vec;  // work vectors (5 pH, 9 nH), each [lanes][n]
     int ix[9] = {0, 1, 2, 3, 4, 5, 6, 7, 8};  // current role -> vector
-    double2* u[kNMeasure] = {};  // measure vectors u^l, l = x, y, z, n
-    Coeffs co{};
-    ChainState* cs = nullptr;
-    double2* dots = nullptr;   // [16] reduced inner products
-    double2* part = nullptr;   // per-block partial sums
+    double2* u[kNMeasure] = {};  // measure vectors u^l, l = x, y, z, n (shared by the lanes)
+    Coeffs co{};               // [lanes] coefficient arrays
+    ChainState* cs = nullptr;  // [lanes]
+    double2* dots = nullptr;   // [lanes][kDotStride] reduced inner products
+    double2* part = nullptr;   // [lanes][blocks x values] partial sums
     int issued = 0;            // steps issued so far
     int broken_seen = 0;       // breakdown observed on the host
     hipStream_t last = nullptr;
     hipGraphExec_t gexec = nullptr;  // one period of steps, captured
+    int gepoch = -1;                 // workspace epoch the graph was captured against
     std::vector<void*> mem;
 
     void* alloc(size_t bytes) {
@@ -602,81 +626,98 @@ struct Chain {
     }
     // steps after which the vector roles return to their initial assignment
     int period() const { return flavour == TM_PSEUDOHERMITIAN ? kPeriodPH : kPeriodNH; }
+    int nvec() const { return flavour == TM_PSEUDOHERMITIAN ? 5 : 9; }
     double2* V(int role) const { return vec[ix[role]]; }
 };
+
+// device memory of a chain: vectors, coefficients and state
+static void chain_alloc(Chain& c) {
+    const size_t L = (size_t)c.lanes, cap = (size_t)c.cap;
+    for (int i = 0; i < c.nvec(); ++i) c.vec.push_back(static_cast<double2*>(c.alloc(L * c.n * sizeof(double2))));
+    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
+    c.co.cap = c.cap;
+    c.co.alpha = static_cast<double2*>(c.alloc(L * cap * sizeof(double2)));
+    c.co.beta = static_cast<double*>(c.alloc(L * cap * sizeof(double)));
+    c.co.gamma = static_cast<double2*>(c.alloc(L * cap * sizeof(double2)));
+    c.co.z = static_cast<double2*>(c.alloc(L * kNMeasure * cap * sizeof(double2)));
+    c.cs = static_cast<ChainState*>(c.alloc(L * sizeof(ChainState)));
+    c.dots = static_cast<double2*>(c.alloc(L * kDotStride * sizeof(double2)));
+    c.part = static_cast<double2*>(c.alloc(L * 1024 * 8 * sizeof(double2)));
+}
+
+static void chain_clear_coeffs(Chain& c, hipStream_t st) {
+    const size_t L = (size_t)c.lanes, cap = (size_t)c.cap;
+    TM_HIP(hipMemsetAsync(c.co.alpha, 0, L * cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.beta, 0, L * cap * sizeof(double), st));
+    TM_HIP(hipMemsetAsync(c.co.gamma, 0, L * cap * sizeof(double2), st));
+    TM_HIP(hipMemsetAsync(c.co.z, 0, L * kNMeasure * cap * sizeof(double2), st));
+}
 
 static void chain_begin(Chain& c, hipStream_t st) {
     System& s = *c.s;
     QSet& q = s.qs[c.iq];
-    ensure_workspace(s, q);
+    TM_CHECK(c.lanes >= 1 && c.lanes <= kMaxLanes, TM_EINVAL, "1 to 4 lanes per chain");
+    ensure_workspace(s, q, c.lanes);
     ensure_ground(s, q, st);  // before any step, so steps never allocate or synchronise
     c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
     c.half = c.n / 2;
     c.w = 1.0 / q.nk;
-    const int nvec = c.flavour == TM_PSEUDOHERMITIAN ? 5 : 9;
-    for (int i = 0; i < nvec; ++i) c.vec.push_back(static_cast<double2*>(c.alloc(c.n * sizeof(double2))));
-    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
-    const int cap = c.cap;
-    c.co.cap = cap;
-    c.co.alpha = static_cast<double2*>(c.alloc(cap * sizeof(double2)));
-    c.co.beta = static_cast<double*>(c.alloc(cap * sizeof(double)));
-    c.co.gamma = static_cast<double2*>(c.alloc(cap * sizeof(double2)));
-    c.co.z = static_cast<double2*>(c.alloc(kNMeasure * (size_t)cap * sizeof(double2)));
-    c.cs = static_cast<ChainState*>(c.alloc(sizeof(ChainState)));
-    c.dots = static_cast<double2*>(c.alloc(16 * sizeof(double2)));
-    c.part = static_cast<double2*>(c.alloc(1024 * 8 * sizeof(double2)));
+    chain_alloc(c);
     c.last = st;
-    TM_HIP(hipMemsetAsync(c.co.alpha, 0, cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(c.co.beta, 0, cap * sizeof(double), st));
-    TM_HIP(hipMemsetAsync(c.co.gamma, 0, cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(c.co.z, 0, kNMeasure * (size_t)cap * sizeof(double2), st));
-    ChainState h{};
-    h.lam = q.lam;
-    TM_HIP(hipMemcpyAsync(c.cs, &h, sizeof(h), hipMemcpyHostToDevice, st));
+    chain_clear_coeffs(c, st);
+    std::vector<ChainState> h(c.lanes);
+    for (ChainState& x : h) x.lam = q.lam;
+    TM_HIP(hipMemcpyAsync(c.cs, h.data(), h.size() * sizeof(ChainState), hipMemcpyHostToDevice, st));
+    TM_HIP(hipStreamSynchronize(st));  // h is released on return
     const int mdir[kNMeasure] = {TM_DIR_X, TM_DIR_Y, TM_DIR_Z, TM_DIR_N};
     for (int l = 0; l < kNMeasure; ++l) start_vectors(s, c.iq, mdir[l], c.u[l], nullptr, st);
-    const long long n = c.n, half = c.half;
+    const long long n = c.n, half = c.half, L = c.lanes;
     double2* d = c.dots;
     if (c.flavour == TM_PSEUDOHERMITIAN) {
         // roles: 0 q_prev, 1 q, 2 Lq, 3 r, 4 Lr
-        TM_HIP(hipMemsetAsync(c.V(0), 0, n * sizeof(double2), st));
-        start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
-        apply_l(s, c.iq, c.V(1), c.V(2), c.fp32, st);
+        TM_HIP(hipMemsetAsync(c.V(0), 0, L * n * sizeof(double2), st));
+        for (int r = 0; r < c.lanes; ++r) start_vectors(s, c.iq, c.dir[r], nullptr, c.V(1) + r * n, st);
+        apply_l(s, c.iq, c.V(1), c.V(2), c.fp32, st, c.lanes);
         DotSet<7> ds0{{c.V(1), c.V(1), c.V(2), c.u[0], c.u[1], c.u[2], c.u[3]},
                       {c.V(2), c.V(1), c.V(2), c.V(1), c.V(1), c.V(1), c.V(1)},
-                      {1, 0, 1, 0, 0, 0, 0}};
-        run_multidot<7>(ds0, n, half, c.w, c.part, d, st);
-        ctl_ph_start(c.cs, d, c.co, st);
+                      {1, 0, 1, 0, 0, 0, 0},
+                      {n, n, n, 0, 0, 0, 0},
+                      {n, n, n, n, n, n, n}};
+        run_multidot<7>(ds0, n, half, c.w, c.part, d, st, c.lanes);
+        ctl_ph_start(c.cs, d, c.co, st, c.lanes);
     } else {
         // roles: 0 q_prev, 1 q, 2 p_prev, 3 p, 4 Lq, 5 L^dag p, 6 J p, 7 q^, 8 p^
-        TM_HIP(hipMemsetAsync(c.V(0), 0, n * sizeof(double2), st));
-        TM_HIP(hipMemsetAsync(c.V(2), 0, n * sizeof(double2), st));
-        start_vectors(s, c.iq, c.dir, nullptr, c.V(1), st);
-        TM_HIP(hipMemcpyAsync(c.V(3), c.V(1), n * sizeof(double2), hipMemcpyDeviceToDevice, st));
+        TM_HIP(hipMemsetAsync(c.V(0), 0, L * n * sizeof(double2), st));
+        TM_HIP(hipMemsetAsync(c.V(2), 0, L * n * sizeof(double2), st));
+        for (int r = 0; r < c.lanes; ++r) start_vectors(s, c.iq, c.dir[r], nullptr, c.V(1) + r * n, st);
+        TM_HIP(hipMemcpyAsync(c.V(3), c.V(1), L * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
         DotSet<5> ds0{{c.V(1), c.u[0], c.u[1], c.u[2], c.u[3]},
                       {c.V(1), c.V(1), c.V(1), c.V(1), c.V(1)},
-                      {0, 0, 0, 0, 0}};
-        run_multidot<5>(ds0, n, half, c.w, c.part, d, st);
-        ctl_nh_start(c.cs, d, c.co, st);
+                      {0, 0, 0, 0, 0},
+                      {n, 0, 0, 0, 0},
+                      {n, n, n, n, n}};
+        run_multidot<5>(ds0, n, half, c.w, c.part, d, st, c.lanes);
+        ctl_nh_start(c.cs, d, c.co, st, c.lanes);
     }
 }
 
-// one step of the chain on stream st
+// one step of the chain (all lanes) on stream st
 static void chain_step(Chain& c, hipStream_t st) {
     System& s = *c.s;
     const long long n = c.n, half = c.half;
+    const int L = c.lanes;
     double2* d = c.dots;
     const double2* uc[kNMeasure] = {c.u[0], c.u[1], c.u[2], c.u[3]};
     if (c.flavour == TM_PSEUDOHERMITIAN) {
         double2 *QP = c.V(0), *Q = c.V(1), *LQ = c.V(2), *R = c.V(3), *LR = c.V(4);
-        run_ph_update(c.cs, LQ, Q, QP, R, uc, n, c.w, c.part, d + 8, st);
+        run_ph_update(c.cs, LQ, Q, QP, R, uc, n, c.w, c.part, d + 8, st, L);
         // back onto the empty manifold: removes rounding-level occupied parts
         // that the metric JL cannot see (identity in exact arithmetic)
-        launch_project_signed(s, s.qs[c.iq], R, 1.0, 1.0, st);
-        apply_l(s, c.iq, R, LR, c.fp32, st);
-        DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}};
-        run_multidot<3>(ds, n, half, c.w, c.part, d, st);
-        ctl_ph_step(c.cs, d, d + 8, c.co, st);
+        launch_project_signed(s, s.qs[c.iq], R, 1.0, 1.0, st, false, L);
+        apply_l(s, c.iq, R, LR, c.fp32, st, L);
+        DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}, {n, n, n}, {n, n, n}};
+        run_multidot<3>(ds, n, half, c.w, c.part, d, st, L);
+        ctl_ph_step(c.cs, d, d + 8, c.co, st, L);
         // q_prev <- q, q <- r, Lq <- Lr; the old q_prev and Lq become scratch
         const int oqp = c.ix[0], olq = c.ix[2];
         c.ix[0] = c.ix[1];
@@ -688,16 +729,16 @@ static void chain_step(Chain& c, hipStream_t st) {
         double2 *QP = c.V(0), *Q = c.V(1), *PP = c.V(2), *Pv = c.V(3), *LQ = c.V(4), *LTP = c.V(5),
                 *TMP = c.V(6), *QH = c.V(7), *PH = c.V(8);
         // q_i, p_i back onto the empty manifold (see the pH step)
-        launch_project_signed(s, s.qs[c.iq], Q, 1.0, 1.0, st);
-        launch_project_signed(s, s.qs[c.iq], Pv, 1.0, 1.0, st);
-        apply_l(s, c.iq, Q, LQ, c.fp32, st);
-        run_jcopy(Pv, TMP, n, half, st);
-        apply_l(s, c.iq, TMP, LTP, c.fp32, st);
-        DotSet<1> da{{Pv}, {LQ}, {0}};
-        run_multidot<1>(da, n, half, c.w, c.part, d, st);
-        ctl_nh_alpha(c.cs, d, c.co, st);
-        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, c.w, c.part, d + 8, st);
-        ctl_nh_step(c.cs, d + 8, c.co, st);
+        launch_project_signed(s, s.qs[c.iq], Q, 1.0, 1.0, st, false, L);
+        launch_project_signed(s, s.qs[c.iq], Pv, 1.0, 1.0, st, false, L);
+        apply_l(s, c.iq, Q, LQ, c.fp32, st, L);
+        run_jcopy(Pv, TMP, n, half, st, L);
+        apply_l(s, c.iq, TMP, LTP, c.fp32, st, L);
+        DotSet<1> da{{Pv}, {LQ}, {0}, {n}, {n}};
+        run_multidot<1>(da, n, half, c.w, c.part, d, st, L);
+        ctl_nh_alpha(c.cs, d, c.co, st, L);
+        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, c.w, c.part, d + 8, st, L);
+        ctl_nh_step(c.cs, d + 8, c.co, st, L);
         // q_prev <- q, q <- q^, p_prev <- p, p <- p^
         const int oqp = c.ix[0], opp = c.ix[2];
         c.ix[0] = c.ix[1];
@@ -739,6 +780,7 @@ static void chain_capture(Chain& c) {
         c.gexec = nullptr;
         throw Error{TM_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e)};
     }
+    c.gepoch = s.ws_epoch;
 }
 
 // up to k steps of one chain (never past its capacity)
@@ -747,6 +789,10 @@ static void chain_steps(Chain& c, int k, hipStream_t st) {
     const int P = c.period();
     while (k > 0) {
         if (g_use_graphs && !g_prof_on && c.issued % P == 0 && k >= P) {
+            if (c.gexec && c.gepoch != c.s->ws_epoch) {  // the workspace moved since the capture
+                (void)hipGraphExecDestroy(c.gexec);
+                c.gexec = nullptr;
+            }
             if (!c.gexec) chain_capture(c);
             const int r = k / P;
             for (int i = 0; i < r; ++i) TM_HIP(hipGraphLaunch(c.gexec, st));
@@ -761,95 +807,113 @@ static void chain_steps(Chain& c, int k, hipStream_t st) {
     c.last = st;
 }
 
-// reads the device state; returns 1 if the chain has broken down
-static int chain_poll(Chain& c) {
-    ChainState h{};
-    TM_HIP(hipMemcpyAsync(&h, c.cs, sizeof(h), hipMemcpyDeviceToHost, c.last));
+static std::vector<ChainState> chain_states(Chain& c) {
+    std::vector<ChainState> h(c.lanes);
+    TM_HIP(hipMemcpyAsync(h.data(), c.cs, h.size() * sizeof(ChainState), hipMemcpyDeviceToHost, c.last));
     TM_HIP(hipStreamSynchronize(c.last));
-    c.broken_seen = h.broken;
-    return h.broken;
+    return h;
 }
 
+// reads the device state; returns 1 once every lane has broken down (a
+// broken lane idles: its kernels skip it while the others go on)
+static int chain_poll(Chain& c) {
+    int all = 1;
+    for (const ChainState& h : chain_states(c)) all &= h.broken != 0;
+    c.broken_seen = all;
+    return all;
+}
+
+// out: one tm_coeffs per lane
 static int chain_coeffs(Chain& c, tm_coeffs* out) {
-    ChainState h{};
-    TM_HIP(hipMemcpyAsync(&h, c.cs, sizeof(h), hipMemcpyDeviceToHost, c.last));
-    TM_HIP(hipStreamSynchronize(c.last));
-    c.broken_seen = h.broken;
+    const std::vector<ChainState> hs = chain_states(c);
     const int cap = c.cap;
-    std::vector<double2> ha(cap), hg(cap), hz(kNMeasure * (size_t)cap);
-    std::vector<double> hb(cap);
-    TM_HIP(hipMemcpy(ha.data(), c.co.alpha, cap * sizeof(double2), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hb.data(), c.co.beta, cap * sizeof(double), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hg.data(), c.co.gamma, cap * sizeof(double2), hipMemcpyDeviceToHost));
-    TM_HIP(hipMemcpy(hz.data(), c.co.z, kNMeasure * (size_t)cap * sizeof(double2), hipMemcpyDeviceToHost));
-    out->steps_done = h.step;
-    out->n1 = h.n1;
-    const int m = std::min(cap, out->capacity);
-    for (int j = 0; j < m; ++j) {
-        out->alpha[2 * j] = ha[j].x;
-        out->alpha[2 * j + 1] = ha[j].y;
-        out->beta[j] = hb[j];
-        out->gamma[2 * j] = hg[j].x;
-        out->gamma[2 * j + 1] = hg[j].y;
-        for (int l = 0; l < 3; ++l) {
-            out->z[2 * ((size_t)l * out->capacity + j)] = hz[l * (size_t)cap + j].x;
-            out->z[2 * ((size_t)l * out->capacity + j) + 1] = hz[l * (size_t)cap + j].y;
-        }
-        if (out->zn) {
-            out->zn[2 * j] = hz[3 * (size_t)cap + j].x;
-            out->zn[2 * j + 1] = hz[3 * (size_t)cap + j].y;
+    const size_t L = (size_t)c.lanes;
+    std::vector<double2> ha(L * cap), hg(L * cap), hz(L * kNMeasure * (size_t)cap);
+    std::vector<double> hb(L * cap);
+    TM_HIP(hipMemcpy(ha.data(), c.co.alpha, ha.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hb.data(), c.co.beta, hb.size() * sizeof(double), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hg.data(), c.co.gamma, hg.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    TM_HIP(hipMemcpy(hz.data(), c.co.z, hz.size() * sizeof(double2), hipMemcpyDeviceToHost));
+    int broken = 0, all = 1;
+    for (size_t r = 0; r < L; ++r) {
+        tm_coeffs* o = out + r;
+        const ChainState& h = hs[r];
+        broken |= h.broken;
+        all &= h.broken != 0;
+        o->steps_done = h.step;
+        o->n1 = h.n1;
+        const int m = std::min(cap, o->capacity);
+        const double2* a = ha.data() + r * cap;
+        const double* b = hb.data() + r * cap;
+        const double2* g = hg.data() + r * cap;
+        const double2* z = hz.data() + r * kNMeasure * cap;
+        for (int j = 0; j < m; ++j) {
+            o->alpha[2 * j] = a[j].x;
+            o->alpha[2 * j + 1] = a[j].y;
+            o->beta[j] = b[j];
+            o->gamma[2 * j] = g[j].x;
+            o->gamma[2 * j + 1] = g[j].y;
+            for (int l = 0; l < 3; ++l) {
+                o->z[2 * ((size_t)l * o->capacity + j)] = z[l * (size_t)cap + j].x;
+                o->z[2 * ((size_t)l * o->capacity + j) + 1] = z[l * (size_t)cap + j].y;
+            }
+            if (o->zn) {
+                o->zn[2 * j] = z[3 * (size_t)cap + j].x;
+                o->zn[2 * j + 1] = z[3 * (size_t)cap + j].y;
+            }
         }
     }
-    return h.broken ? TM_EBREAKDOWN : TM_OK;
+    c.broken_seen = all;
+    return broken ? TM_EBREAKDOWN : TM_OK;
 }
 
-// ---- checkpoint: header, device state struct, coefficients, vectors
+// ---- checkpoint: header, per-lane device state, coefficients, vectors
 struct ChainBlobHeader {
-    char magic[8];       // "TMCHAIN2"
-    int iq, dir, flavour, fp32, cap, issued, nvec;
+    char magic[8];       // "TMCHAIN3"
+    int iq, flavour, fp32, cap, issued, nvec, lanes;
+    int dir[kMaxLanes];
     int ix[9];
     long long n;
 };
 
-static size_t chain_blob_bytes(const Chain& c) {
-    return sizeof(ChainBlobHeader) + sizeof(ChainState) + (size_t)c.cap * (3 * sizeof(double2) + sizeof(double)) +
-           kNMeasure * (size_t)c.cap * sizeof(double2) + (c.vec.size() + kNMeasure) * (size_t)c.n * sizeof(double2);
+static size_t blob_bytes(int lanes, int cap, int nvec, long long n) {
+    const size_t L = (size_t)lanes;
+    return sizeof(ChainBlobHeader) + L * sizeof(ChainState) +
+           L * (size_t)cap * (3 * sizeof(double2) + sizeof(double) + kNMeasure * sizeof(double2)) +
+           (L * nvec + kNMeasure) * (size_t)n * sizeof(double2);
 }
+
+static size_t chain_blob_bytes(const Chain& c) { return blob_bytes(c.lanes, c.cap, c.nvec(), c.n); }
 
 static void chain_save(Chain& c, char* out) {
     TM_HIP(hipStreamSynchronize(c.last));
     ChainBlobHeader h{};
-    std::memcpy(h.magic, "TMCHAIN2", 8);
+    std::memcpy(h.magic, "TMCHAIN3", 8);
     h.iq = c.iq;
-    h.dir = c.dir;
     h.flavour = c.flavour;
     h.fp32 = c.fp32 ? 1 : 0;
     h.cap = c.cap;
     h.issued = c.issued;
-    h.nvec = (int)c.vec.size();
+    h.nvec = c.nvec();
+    h.lanes = c.lanes;
+    std::copy(c.dir, c.dir + kMaxLanes, h.dir);
     std::copy(c.ix, c.ix + 9, h.ix);
     h.n = c.n;
+    const size_t L = (size_t)c.lanes, cap = (size_t)c.cap;
     char* p = out;
+    auto put = [&](const void* dev, size_t bytes) {
+        TM_HIP(hipMemcpy(p, dev, bytes, hipMemcpyDeviceToHost));
+        p += bytes;
+    };
     std::memcpy(p, &h, sizeof(h));
     p += sizeof(h);
-    TM_HIP(hipMemcpy(p, c.cs, sizeof(ChainState), hipMemcpyDeviceToHost));
-    p += sizeof(ChainState);
-    TM_HIP(hipMemcpy(p, c.co.alpha, c.cap * sizeof(double2), hipMemcpyDeviceToHost));
-    p += c.cap * sizeof(double2);
-    TM_HIP(hipMemcpy(p, c.co.beta, c.cap * sizeof(double), hipMemcpyDeviceToHost));
-    p += c.cap * sizeof(double);
-    TM_HIP(hipMemcpy(p, c.co.gamma, c.cap * sizeof(double2), hipMemcpyDeviceToHost));
-    p += c.cap * sizeof(double2);
-    TM_HIP(hipMemcpy(p, c.co.z, kNMeasure * (size_t)c.cap * sizeof(double2), hipMemcpyDeviceToHost));
-    p += kNMeasure * (size_t)c.cap * sizeof(double2);
-    for (double2* v : c.vec) {
-        TM_HIP(hipMemcpy(p, v, c.n * sizeof(double2), hipMemcpyDeviceToHost));
-        p += c.n * sizeof(double2);
-    }
-    for (int l = 0; l < kNMeasure; ++l) {
-        TM_HIP(hipMemcpy(p, c.u[l], c.n * sizeof(double2), hipMemcpyDeviceToHost));
-        p += c.n * sizeof(double2);
-    }
+    put(c.cs, L * sizeof(ChainState));
+    put(c.co.alpha, L * cap * sizeof(double2));
+    put(c.co.beta, L * cap * sizeof(double));
+    put(c.co.gamma, L * cap * sizeof(double2));
+    put(c.co.z, L * kNMeasure * cap * sizeof(double2));
+    for (double2* v : c.vec) put(v, L * c.n * sizeof(double2));
+    for (int l = 0; l < kNMeasure; ++l) put(c.u[l], c.n * sizeof(double2));
 }
 
 // rebuilds a chain from a checkpoint of a chain of the same system; capacity
@@ -858,15 +922,18 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     ChainBlobHeader h{};
     TM_CHECK(bytes >= sizeof(h), TM_EINVAL, "checkpoint too short");
     std::memcpy(&h, in, sizeof(h));
-    TM_CHECK(std::memcmp(h.magic, "TMCHAIN2", 8) == 0, TM_EINVAL, "not a chain checkpoint");
+    TM_CHECK(std::memcmp(h.magic, "TMCHAIN3", 8) == 0, TM_EINVAL, "not a chain checkpoint");
     System& s = *c.s;
     TM_CHECK(h.iq >= 0 && h.iq < (int)s.qs.size(), TM_EINVAL, "checkpoint q set not in this system");
     const QSet& q = s.qs[h.iq];
     TM_CHECK(h.n == 2LL * q.nk * s.nbnd * 2 * q.npw_pad, TM_EINVAL, "checkpoint vectors do not fit this system");
     TM_CHECK(h.flavour == TM_PSEUDOHERMITIAN || h.flavour == TM_NONHERMITIAN, TM_EINVAL, "bad flavour");
     TM_CHECK(h.nvec == (h.flavour == TM_PSEUDOHERMITIAN ? 5 : 9), TM_EINVAL, "bad vector count");
-    TM_CHECK(h.dir >= TM_DIR_X && h.dir <= TM_DIR_N, TM_EINVAL, "bad direction");
+    TM_CHECK(h.lanes >= 1 && h.lanes <= kMaxLanes, TM_EINVAL, "bad lane count");
+    for (int r = 0; r < h.lanes; ++r)
+        TM_CHECK(h.dir[r] >= TM_DIR_X && h.dir[r] <= TM_DIR_N, TM_EINVAL, "bad direction");
     TM_CHECK(h.cap >= 1 && capacity >= 0, TM_EINVAL, "bad capacity");
+    TM_CHECK(h.issued >= 0 && h.issued <= h.cap, TM_EINVAL, "bad step count");
     {
         int seen = 0;
         for (int i = 0; i < h.nvec; ++i) {
@@ -874,82 +941,67 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
             seen |= 1 << h.ix[i];
         }
     }
+    TM_CHECK(bytes >= blob_bytes(h.lanes, h.cap, h.nvec, h.n), TM_EINVAL, "checkpoint truncated");
     c.iq = h.iq;
-    c.dir = h.dir;
     c.flavour = h.flavour;
     c.fp32 = h.fp32 != 0;
+    c.lanes = h.lanes;
+    std::copy(h.dir, h.dir + kMaxLanes, c.dir);
     c.cap = std::max(capacity, h.cap);
-    TM_CHECK(h.issued >= 0 && h.issued <= h.cap, TM_EINVAL, "bad step count");
     c.n = h.n;
-    const size_t need = sizeof(h) + sizeof(ChainState) + (size_t)h.cap * (3 * sizeof(double2) + sizeof(double)) +
-                        kNMeasure * (size_t)h.cap * sizeof(double2) + (h.nvec + kNMeasure) * (size_t)h.n * sizeof(double2);
-    TM_CHECK(bytes >= need, TM_EINVAL, "checkpoint truncated");
     QSet& qm = s.qs[c.iq];
-    ensure_workspace(s, qm);
+    ensure_workspace(s, qm, c.lanes);
     ensure_ground(s, qm, st);
     c.half = c.n / 2;
     c.w = 1.0 / qm.nk;
-    for (int i = 0; i < h.nvec; ++i) c.vec.push_back(static_cast<double2*>(c.alloc(c.n * sizeof(double2))));
-    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
-    c.co.cap = c.cap;
-    c.co.alpha = static_cast<double2*>(c.alloc(c.cap * sizeof(double2)));
-    c.co.beta = static_cast<double*>(c.alloc(c.cap * sizeof(double)));
-    c.co.gamma = static_cast<double2*>(c.alloc(c.cap * sizeof(double2)));
-    c.co.z = static_cast<double2*>(c.alloc(kNMeasure * (size_t)c.cap * sizeof(double2)));
-    c.cs = static_cast<ChainState*>(c.alloc(sizeof(ChainState)));
-    c.dots = static_cast<double2*>(c.alloc(16 * sizeof(double2)));
-    c.part = static_cast<double2*>(c.alloc(1024 * 8 * sizeof(double2)));
+    chain_alloc(c);
     c.last = st;
     std::copy(h.ix, h.ix + 9, c.ix);
     c.issued = h.issued;
-    TM_HIP(hipMemsetAsync(c.co.alpha, 0, c.cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(c.co.beta, 0, c.cap * sizeof(double), st));
-    TM_HIP(hipMemsetAsync(c.co.gamma, 0, c.cap * sizeof(double2), st));
-    TM_HIP(hipMemsetAsync(c.co.z, 0, kNMeasure * (size_t)c.cap * sizeof(double2), st));
+    chain_clear_coeffs(c, st);
+    const size_t L = (size_t)c.lanes, hcap = (size_t)h.cap, ccap = (size_t)c.cap;
     const char* p = in + sizeof(h);
-    TM_HIP(hipMemcpyAsync(c.cs, p, sizeof(ChainState), hipMemcpyHostToDevice, st));
-    p += sizeof(ChainState);
-    TM_HIP(hipMemcpyAsync(c.co.alpha, p, h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
-    p += h.cap * sizeof(double2);
-    TM_HIP(hipMemcpyAsync(c.co.beta, p, h.cap * sizeof(double), hipMemcpyHostToDevice, st));
-    p += h.cap * sizeof(double);
-    TM_HIP(hipMemcpyAsync(c.co.gamma, p, h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
-    p += h.cap * sizeof(double2);
-    // z is [3][cap]: rows move to the new stride
-    for (int l = 0; l < kNMeasure; ++l)
-        TM_HIP(hipMemcpyAsync(c.co.z + (size_t)l * c.cap, p + (size_t)l * h.cap * sizeof(double2),
-                              h.cap * sizeof(double2), hipMemcpyHostToDevice, st));
-    p += kNMeasure * (size_t)h.cap * sizeof(double2);
-    for (double2* v : c.vec) {
-        TM_HIP(hipMemcpyAsync(v, p, c.n * sizeof(double2), hipMemcpyHostToDevice, st));
-        p += c.n * sizeof(double2);
-    }
-    for (int l = 0; l < kNMeasure; ++l) {
-        TM_HIP(hipMemcpyAsync(c.u[l], p, c.n * sizeof(double2), hipMemcpyHostToDevice, st));
-        p += c.n * sizeof(double2);
-    }
-    // a chain saved at its capacity holds the coefficients of its next index
+    std::vector<ChainState> hs(L);
+    std::memcpy(hs.data(), p, L * sizeof(ChainState));
+    auto get = [&](void* dev, size_t nbytes) {
+        TM_HIP(hipMemcpyAsync(dev, p, nbytes, hipMemcpyHostToDevice, st));
+        p += nbytes;
+    };
+    get(c.cs, L * sizeof(ChainState));
+    // coefficient rows move to the (possibly larger) new capacity
+    for (size_t r = 0; r < L; ++r) get(c.co.alpha + r * ccap, hcap * sizeof(double2));
+    for (size_t r = 0; r < L; ++r) get(c.co.beta + r * ccap, hcap * sizeof(double));
+    for (size_t r = 0; r < L; ++r) get(c.co.gamma + r * ccap, hcap * sizeof(double2));
+    for (size_t r = 0; r < L; ++r)
+        for (int l = 0; l < kNMeasure; ++l) get(c.co.z + (r * kNMeasure + l) * ccap, hcap * sizeof(double2));
+    for (double2* v : c.vec) get(v, L * c.n * sizeof(double2));
+    for (int l = 0; l < kNMeasure; ++l) get(c.u[l], c.n * sizeof(double2));
+    // a lane saved at its capacity holds the coefficients of its next index
     // only in the state struct (alpha for pH; z for both): grown capacity gets them
-    ChainState hs{};
-    std::memcpy(&hs, in + sizeof(h), sizeof(hs));
-    if (c.cap > h.cap && h.issued == h.cap && hs.step == h.cap && !hs.broken) {
-        if (c.flavour == TM_PSEUDOHERMITIAN)
-            TM_HIP(hipMemcpyAsync(c.co.alpha + h.cap, &hs.alpha, sizeof(double2), hipMemcpyHostToDevice, st));
-        for (int l = 0; l < kNMeasure; ++l)
-            TM_HIP(hipMemcpyAsync(c.co.z + (size_t)l * c.cap + h.cap, &hs.znext[l], sizeof(double2),
-                                  hipMemcpyHostToDevice, st));
+    if (ccap > hcap && h.issued == h.cap) {
+        for (size_t r = 0; r < L; ++r) {
+            const ChainState& x = hs[r];
+            if (x.step != h.cap || x.broken) continue;
+            if (c.flavour == TM_PSEUDOHERMITIAN)
+                TM_HIP(hipMemcpyAsync(c.co.alpha + r * ccap + hcap, &x.alpha, sizeof(double2), hipMemcpyHostToDevice,
+                                      st));
+            for (int l = 0; l < kNMeasure; ++l)
+                TM_HIP(hipMemcpyAsync(c.co.z + (r * kNMeasure + l) * ccap + hcap, &x.znext[l], sizeof(double2),
+                                      hipMemcpyHostToDevice, st));
+        }
     }
     // the host blob (and hs) may be released as soon as the call returns
     TM_HIP(hipStreamSynchronize(st));
 }
 
-static int run_chain(System& s, int iq, int dir, int flavour, bool fp32, int nsteps, tm_coeffs* out,
-                     hipStream_t st) {
+static int run_chain(System& s, int iq, int lanes, const int* dirs, int flavour, bool fp32, int nsteps,
+                     tm_coeffs* out, hipStream_t st) {
     Chain c;
     c.s = &s;
     c.fp32 = fp32;
     c.iq = iq;
-    c.dir = dir;
+    c.lanes = lanes;
+    std::copy(dirs, dirs + lanes, c.dir);
     c.flavour = flavour;
     c.cap = nsteps;
     chain_begin(c, st);
@@ -1160,10 +1212,7 @@ int tm_system_destroy(tm_system* sys) {
             if (q.ucols) (void)hipFree(q.ucols);
         if (s.cap_stream) (void)hipStreamDestroy(s.cap_stream);
         if (s.ureal) (void)hipFree(s.ureal);
-        Workspace& w = s.ws;
-        void* wp[] = {w.xcols, w.rho_part, w.rho, w.W, w.work, w.gpart, w.gsmall, w.dots, w.dotpart, w.fields};
-        for (void* p : wp)
-            if (p) (void)hipFree(p);
+        free_workspace(s.ws);
         delete sys;
         return TM_OK;
     });
@@ -1202,22 +1251,28 @@ int tm_system_resident_bytes(const tm_system* sys, long long* bytes) {
     });
 }
 
-int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,
-                         void* stream) {
+int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_in, void* xy_out,
+                               tm_precision prec, void* stream) {
     return guarded([&]() -> int {
         TM_CHECK(sys && xy_in && xy_out, TM_EINVAL, "null argument");
         System& s = sys->s;
         TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
         TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
+        TM_CHECK(nrhs >= 1 && nrhs <= kMaxLanes, TM_EINVAL, "1 to 4 right-hand sides");
         const QSet& q = s.qs[iq];
-        const size_t bytes = (size_t)2 * q.nk * s.nbnd * 2 * q.npw_pad * sizeof(double2);
+        const size_t bytes = (size_t)nrhs * 2 * q.nk * s.nbnd * 2 * q.npw_pad * sizeof(double2);
         const char* a = static_cast<const char*>(xy_in);
         const char* b = static_cast<const char*>(xy_out);
         TM_CHECK(a + bytes <= b || b + bytes <= a, TM_EINVAL, "xy_in and xy_out overlap");
         apply_l(s, iq, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out), prec == TM_FP32,
-                static_cast<hipStream_t>(stream));
+                static_cast<hipStream_t>(stream), nrhs);
         return TM_OK;
     });
+}
+
+int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,
+                         void* stream) {
+    return tm_liouvillian_apply_multi(sys, iq, 1, xy_in, xy_out, prec, stream);
 }
 
 int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void* stream) {
@@ -1243,20 +1298,46 @@ int tm_lanczos_run(tm_system* sys, int iq, tm_dir dir, tm_flavour f, int nsteps,
         TM_CHECK(nsteps >= 1 && nsteps <= out->capacity, TM_EINVAL, "nsteps must be in [1, capacity]");
         TM_CHECK(out->alpha && out->beta && out->gamma && out->z, TM_EINVAL, "null coefficient array");
         TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
-        int rc = run_chain(s, iq, (int)dir, (int)f, prec == TM_FP32, nsteps, out, nullptr);
+        const int d = (int)dir;
+        int rc = run_chain(s, iq, 1, &d, (int)f, prec == TM_FP32, nsteps, out, nullptr);
         if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
         return rc;
     });
 }
 
-int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity, void* stream,
-                   tm_chain** out) {
+int tm_tensor_run(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, int nsteps,
+                  tm_precision prec, tm_coeffs* out) {
     return guarded([&]() -> int {
-        TM_CHECK(sys && out, TM_EINVAL, "null argument");
+        TM_CHECK(sys && dirs && out, TM_EINVAL, "null argument");
+        System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        TM_CHECK(ndir >= 1 && ndir <= kMaxLanes, TM_EINVAL, "1 to 4 directions");
+        int d[kMaxLanes];
+        for (int r = 0; r < ndir; ++r) {
+            TM_CHECK(dirs[r] >= TM_DIR_X && dirs[r] <= TM_DIR_N, TM_EINVAL, "bad direction");
+            TM_CHECK(nsteps >= 1 && nsteps <= out[r].capacity, TM_EINVAL, "nsteps must be in [1, capacity]");
+            TM_CHECK(out[r].alpha && out[r].beta && out[r].gamma && out[r].z, TM_EINVAL,
+                     "null coefficient array");
+            d[r] = (int)dirs[r];
+        }
+        TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
+        TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
+        int rc = run_chain(s, iq, ndir, d, (int)f, prec == TM_FP32, nsteps, out, nullptr);
+        if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
+        return rc;
+    });
+}
+
+int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, tm_precision prec,
+                         int capacity, void* stream, tm_chain** out) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && out && dirs, TM_EINVAL, "null argument");
         *out = nullptr;
         System& s = sys->s;
         TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
-        TM_CHECK(dir >= TM_DIR_X && dir <= TM_DIR_N, TM_EINVAL, "bad direction");
+        TM_CHECK(ndir >= 1 && ndir <= kMaxLanes, TM_EINVAL, "1 to 4 directions");
+        for (int r = 0; r < ndir; ++r)
+            TM_CHECK(dirs[r] >= TM_DIR_X && dirs[r] <= TM_DIR_N, TM_EINVAL, "bad direction");
         TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
         TM_CHECK(capacity >= 1, TM_EINVAL, "capacity must be >= 1");
         TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
@@ -1264,13 +1345,27 @@ int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precisio
         Chain& c = h->c;
         c.s = &s;
         c.iq = iq;
-        c.dir = (int)dir;
+        c.lanes = ndir;
+        for (int r = 0; r < ndir; ++r) c.dir[r] = (int)dirs[r];
         c.flavour = (int)f;
         c.cap = capacity;
         c.fp32 = prec == TM_FP32;
         chain_begin(c, static_cast<hipStream_t>(stream));
         ++s.nchains;
         *out = h.release();
+        return TM_OK;
+    });
+}
+
+int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity, void* stream,
+                   tm_chain** out) {
+    return tm_chain_begin_multi(sys, iq, 1, &dir, f, prec, capacity, stream, out);
+}
+
+int tm_chain_lanes(const tm_chain* chain, int* lanes) {
+    return guarded([&]() -> int {
+        TM_CHECK(chain && lanes, TM_EINVAL, "null argument");
+        *lanes = chain->c.lanes;
         return TM_OK;
     });
 }
@@ -1306,8 +1401,9 @@ int tm_chains_use_graphs(int on) {
 int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out) {
     return guarded([&]() -> int {
         TM_CHECK(chain && out, TM_EINVAL, "null argument");
-        TM_CHECK(out->capacity >= 1 && out->alpha && out->beta && out->gamma && out->z, TM_EINVAL,
-                 "bad coefficient arrays");
+        for (int r = 0; r < chain->c.lanes; ++r)
+            TM_CHECK(out[r].capacity >= 1 && out[r].alpha && out[r].beta && out[r].gamma && out[r].z, TM_EINVAL,
+                     "bad coefficient arrays");
         int rc = chain_coeffs(chain->c, out);
         if (rc == TM_EBREAKDOWN) set_error("Lanczos breakdown");
         return rc;

@@ -38,19 +38,20 @@ __device__ inline void plane_inverse(double2* plane, const double2* cols, const 
     lds_fft(plane, a.n2, 1, a.n2, p1, +1);  // along i1 for every i2
 }
 
-__device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, int b, int n, int i3,
+// b: batch (columns of x); bt = b % nb2: side and k point (sphere tables, u)
+__device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, int b, int bt, int n, int i3,
                                        const PlaneArgs& a, const FFTPlan& p1, const FFTPlan& p2) {
-    const int* cpos_x = a.colpos_kq[b];
-    const int ncx = a.ncol_kq[b];
-    const int* cpos_u = a.colpos_u[b];
-    const int ncu = a.ncol_u[b];
+    const int* cpos_x = a.colpos_kq[bt];
+    const int ncx = a.ncol_kq[bt];
+    const int* cpos_u = a.colpos_u[bt];
+    const int ncu = a.ncol_u[bt];
 #pragma unroll
     for (int comp = 0; comp < 4; ++comp) {
         const double2* cols;
         if (comp < 2)
             cols = a.xcols + (((long long)b * a.nitems + 2 * n + comp) * a.n3 + i3) * a.ncol_max;
         else
-            cols = a.ucols + (((long long)b * a.nitems + 2 * n + comp - 2) * a.n3 + i3) * a.ncol_u_max;
+            cols = a.ucols + (((long long)bt * a.nitems + 2 * n + comp - 2) * a.n3 + i3) * a.ncol_u_max;
         plane_inverse(plane, cols, comp < 2 ? cpos_x : cpos_u, comp < 2 ? ncx : ncu, a, p1, p2);
 #pragma unroll
         for (int j = 0; j < kPts; ++j) {
@@ -59,7 +60,7 @@ __device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, 
         }
         __syncthreads();
     }
-    if (b >= a.nk) {  // Y side: u' = T U_{-k} = i sigma_y K U: (a, b) -> (conj b, -conj a)
+    if (bt >= a.nk) {  // Y side: u' = T U_{-k} = i sigma_y K U: (a, b) -> (conj b, -conj a)
 #pragma unroll
         for (int j = 0; j < kPts; ++j) {
             double2 up = val[2][j], dn = val[3][j];
@@ -71,7 +72,7 @@ __device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, 
 
 __global__ void k_density(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
     extern __shared__ double2 plane[];
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     double2 acc[4][kPts];
@@ -81,7 +82,7 @@ __global__ void k_density(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
         for (int j = 0; j < kPts; ++j) acc[c][j] = cmk(0.0, 0.0);
     for (int n = n0; n < n1e; ++n) {
         double2 val[4][kPts];
-        load_components(val, plane, b, n, i3, a, p1, p2);
+        load_components(val, plane, b, bt, n, i3, a, p1, p2);
 #pragma unroll
         for (int j = 0; j < kPts; ++j) {
             double2 xu = val[0][j], xd = val[1][j], uu = val[2][j], ud = val[3][j];
@@ -105,10 +106,13 @@ __global__ void k_density(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
         }
 }
 
+// right-hand side blockIdx.y: its 2 nk batches of partials -> its rho [4][N]
 template <class T2>
 __global__ void k_density_reduce(const T2* part, double2* rho, long long N, int nk, int nchunk, double scale) {
     long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 4 * N) return;
+    part += (long long)blockIdx.y * 2 * nk * nchunk * 4 * N;
+    rho += (long long)blockIdx.y * 4 * N;
     int comp = (int)(idx / N);
     long long p = idx - comp * N;
     double2 sx = cmk(0.0, 0.0), sy = cmk(0.0, 0.0);
@@ -150,12 +154,13 @@ __global__ void k_assemble_W(const double2* rho, const double2* vH, const double
 
 __global__ void k_apply_planes(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
     extern __shared__ double2 plane[];
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
-    const double sg = b < a.nk ? 1.0 : -1.0;
+    const double sg = bt < a.nk ? 1.0 : -1.0;
     const long long N = (long long)a.NP * a.n3;
     const long long off = (long long)i3 * a.NP;
+    const double2* Wr = a.W + (long long)(b / a.nb2) * a.wstride;
     // local fields of my points
     double v[kPts], Bx[kPts], By[kPts], Bz[kPts];
     double2 W0[kPts], Wx[kPts], Wy[kPts], Wz[kPts];
@@ -168,20 +173,20 @@ __global__ void k_apply_planes(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
             Bx[j] = sg * a.vrs[N + g];
             By[j] = sg * a.vrs[2 * N + g];
             Bz[j] = sg * a.vrs[3 * N + g];
-            W0[j] = a.W[g];
-            Wx[j] = cscale(a.W[N + g], sg);
-            Wy[j] = cscale(a.W[2 * N + g], sg);
-            Wz[j] = cscale(a.W[3 * N + g], sg);
+            W0[j] = Wr[g];
+            Wx[j] = cscale(Wr[N + g], sg);
+            Wy[j] = cscale(Wr[2 * N + g], sg);
+            Wz[j] = cscale(Wr[3 * N + g], sg);
         } else {
             v[j] = Bx[j] = By[j] = Bz[j] = 0.0;
             W0[j] = Wx[j] = Wy[j] = Wz[j] = cmk(0.0, 0.0);
         }
     }
-    const int* cpos = a.colpos_kq[b];
-    const int ncx = a.ncol_kq[b];
+    const int* cpos = a.colpos_kq[bt];
+    const int ncx = a.ncol_kq[bt];
     for (int n = n0; n < n1e; ++n) {
         double2 val[4][kPts];
-        load_components(val, plane, b, n, i3, a, p1, p2);
+        load_components(val, plane, b, bt, n, i3, a, p1, p2);
         double2 phi[2][kPts];
 #pragma unroll
         for (int j = 0; j < kPts; ++j) {
@@ -290,6 +295,9 @@ PlaneArgs plane_args(const System& s, const QSet& q) {
     PlaneArgs a;
     a.n1 = s.n1; a.n2 = s.n2; a.n3 = s.n3; a.NP = s.n1 * s.n2;
     a.nk = q.nk; a.nb = s.nbnd; a.nitems = 2 * s.nbnd;
+    a.nb2 = 2 * q.nk;
+    a.wstride = 4 * s.N;
+    a.fstride = 6 * s.N;
     a.nchunk = s.ws.nchunk;
     a.bpc = (s.nbnd + a.nchunk - 1) / a.nchunk;
     a.xcols = s.ws.xcols;
@@ -344,9 +352,9 @@ static PlaneTabs plane_tabs(const System& s, const QSet& q) {
     return t;
 }
 
-void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32) {
+void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32, int nrhs) {
     PlaneArgs a = plane_args(s, q);
-    dim3 grid(s.n3, a.nchunk, 2 * q.nk);
+    dim3 grid(s.n3, a.nchunk, 2 * q.nk * nrhs);
     if (plane_fixed_supported(s.n1, s.n2)) {
         launch_plane_fixed(true, a, plane_tabs(s, q), grid, s.n1, s.n2, st, fp32);
     } else {
@@ -357,28 +365,34 @@ void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32) {
     }
     long long n4 = 4 * s.N;
     const double scale = 1.0 / (s.omega * q.nk);
+    const dim3 rgrid((unsigned)((n4 + 255) / 256), nrhs);
     if (fp32) {
-        TM_LAUNCH(k_density_reduce<float2>, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, a.rho_part32,
-                  s.ws.rho, s.N, q.nk, a.nchunk, scale);
+        TM_LAUNCH(k_density_reduce<float2>, rgrid, dim3(256), 0, st, a.rho_part32, s.ws.rho, s.N, q.nk, a.nchunk,
+                  scale);
     } else {
-        TM_LAUNCH(k_density_reduce<double2>, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st, s.ws.rho_part,
-                  s.ws.rho, s.N, q.nk, a.nchunk, scale);
+        TM_LAUNCH(k_density_reduce<double2>, rgrid, dim3(256), 0, st, s.ws.rho_part, s.ws.rho, s.N, q.nk, a.nchunk,
+                  scale);
     }
 }
 
-void launch_potential(const System& s, const QSet& q, hipStream_t st) {
+// one Hartree solve per right-hand side (the scratch grid is reused in turn)
+void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) {
     long long N = s.N;
     unsigned nbk = (unsigned)((N + 255) / 256);
-    TM_LAUNCH(k_copy_scale, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, N);
-    launch_fft3d_full(s, s.ws.work, -1, st);
-    TM_LAUNCH(k_mul_real, dim3(nbk), dim3(256), 0, st, s.ws.work, q.hq, N);
-    launch_fft3d_full(s, s.ws.work, +1, st);
-    TM_LAUNCH(k_assemble_W, dim3(nbk), dim3(256), 0, st, s.ws.rho, s.ws.work, s.fxc, s.ws.W, N);
+    for (int r = 0; r < nrhs; ++r) {
+        const double2* rho = s.ws.rho + (size_t)r * 4 * N;
+        double2* W = s.ws.W + (size_t)r * 4 * N;
+        TM_LAUNCH(k_copy_scale, dim3(nbk), dim3(256), 0, st, rho, s.ws.work, N);
+        launch_fft3d_full(s, s.ws.work, -1, st);
+        TM_LAUNCH(k_mul_real, dim3(nbk), dim3(256), 0, st, s.ws.work, q.hq, N);
+        launch_fft3d_full(s, s.ws.work, +1, st);
+        TM_LAUNCH(k_assemble_W, dim3(nbk), dim3(256), 0, st, rho, s.ws.work, s.fxc, W, N);
+    }
 }
 
-void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32) {
+void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32, int nrhs) {
     PlaneArgs a = plane_args(s, q);
-    dim3 grid(s.n3, a.nchunk, 2 * q.nk);
+    dim3 grid(s.n3, a.nchunk, 2 * q.nk * nrhs);
     if (plane_fixed_supported(s.n1, s.n2)) {
         launch_plane_fixed(false, a, plane_tabs(s, q), grid, s.n1, s.n2, st, fp32);
         return;

@@ -16,8 +16,10 @@ namespace {
 constexpr int kZThreads = 256;
 
 struct ZArgs {
-    // per batch b (side*nk + ik): coefficients of item 0 at coef_table[b] when
-    // the table is given, else at coef_base + b * coef_bstride
+    // per batch b (side*nk + ik, plus 2nk per further right-hand side):
+    // coefficients of item 0 at coef_table[b % nb2] when the table is given,
+    // else at coef_base + b * coef_bstride; sphere tables are per b % nb2
+    int nb2;
     const double2* const* coef_table;
     const double2* coef_base;
     long long coef_bstride;
@@ -37,8 +39,8 @@ struct ZArgs {
 __global__ void __launch_bounds__(kZThreads) k_zpass_inv(ZArgs a, FFTPlan pl) {
     extern __shared__ double2 lds[];
     const int n3 = pl.n;
-    const int b = blockIdx.z;
-    const int ncol = a.ncol[b];
+    const int b = blockIdx.z, bt = b % a.nb2;
+    const int ncol = a.ncol[bt];
     const int col0 = blockIdx.x * a.ct;
     if (col0 >= ncol) return;
     const int it = a.lines_per_block / a.ct;
@@ -46,17 +48,17 @@ __global__ void __launch_bounds__(kZThreads) k_zpass_inv(ZArgs a, FFTPlan pl) {
     const int L = a.lines_per_block;
     for (int i = threadIdx.x; i < L * n3; i += blockDim.x) lds[i] = cmk(0.0, 0.0);
     __syncthreads();
-    const int* cp = a.colptr[b];
-    const int* eg = a.entg[b];
-    const int* ei = a.enti3[b];
-    const double2* coef = a.coef_table ? a.coef_table[b] : a.coef_base + (long long)b * a.coef_bstride;
+    const int* cp = a.colptr[bt];
+    const int* eg = a.entg[bt];
+    const int* ei = a.enti3[bt];
+    const double2* coef = a.coef_table ? a.coef_table[bt] : a.coef_base + (long long)b * a.coef_bstride;
     // scatter: each (line, entry) pair by one thread
     const int per = (blockDim.x + L - 1) / L;
     for (int l = threadIdx.x / per; l < L; l += blockDim.x / per) {
         int c = col0 + (l % a.ct);
         int item = item0 + l / a.ct;
         if (c < ncol && item < a.nitems) {
-            const long long istr = a.coef_item_stride_tab ? a.coef_item_stride_tab[b] : a.coef_item_stride;
+            const long long istr = a.coef_item_stride_tab ? a.coef_item_stride_tab[bt] : a.coef_item_stride;
             const double2* src = coef + (long long)item * istr;
             for (int e = cp[c] + (threadIdx.x % per); e < cp[c + 1]; e += per)
                 lds[l * n3 + ei[e]] = src[eg[e]];
@@ -78,6 +80,7 @@ __global__ void __launch_bounds__(kZThreads) k_zpass_inv(ZArgs a, FFTPlan pl) {
 }
 
 struct ZFwdArgs {
+    int nb2;                      // sphere tables are per b % nb2 (see ZArgs)
     const double2* cols;          // [b][item][n3][ncol_stride]
     int ncol_stride;
     const int* const* colptr;
@@ -99,8 +102,8 @@ struct ZFwdArgs {
 __global__ void __launch_bounds__(kZThreads) k_zpass_fwd(ZFwdArgs a, FFTPlan pl) {
     extern __shared__ double2 lds[];
     const int n3 = pl.n;
-    const int b = blockIdx.z;
-    const int ncol = a.ncol[b];
+    const int b = blockIdx.z, bt = b % a.nb2;
+    const int ncol = a.ncol[bt];
     const int col0 = blockIdx.x * a.ct;
     const int it = a.lines_per_block / a.ct;
     const int item0 = blockIdx.y * it;
@@ -108,7 +111,7 @@ __global__ void __launch_bounds__(kZThreads) k_zpass_fwd(ZFwdArgs a, FFTPlan pl)
     const long long bbase = (long long)b * a.nitems * a.npw_pad;
     // the first column tile also clears the padding of its items
     if (blockIdx.x == 0) {
-        int npw = a.npw[b];
+        int npw = a.npw[bt];
         int padn = a.npw_pad - npw;
         for (int i = threadIdx.x; i < it * padn; i += blockDim.x) {
             int item = item0 + i / padn;
@@ -130,11 +133,11 @@ __global__ void __launch_bounds__(kZThreads) k_zpass_fwd(ZFwdArgs a, FFTPlan pl)
     }
     __syncthreads();
     lds_fft(lds, L, n3, 1, pl, -1);
-    const int* cp = a.colptr[b];
-    const int* eg = a.entg[b];
-    const int* ei = a.enti3[b];
-    const double* kin = a.kin[b];
-    const double* eps = a.eps[b];
+    const int* cp = a.colptr[bt];
+    const int* eg = a.entg[bt];
+    const int* ei = a.enti3[bt];
+    const double* kin = a.kin[bt];
+    const double* eps = a.eps[bt];
     const int per = (blockDim.x + L - 1) / L;
     for (int l = threadIdx.x / per; l < L; l += blockDim.x / per) {
         int c = col0 + (l % a.ct);
@@ -192,9 +195,11 @@ int lines_for(int n, int cap_lines, int threads) {
 }  // namespace
 
 void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2* coef, long long coef_bstride,
-                      int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32) {
+                      int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32, int nrhs) {
     const int nb2 = 2 * q.nk;
+    TM_CHECK(nrhs == 1 || !ucols, TM_EINVAL, "ground-state columns have one right-hand side");
     ZArgs a;
+    a.nb2 = nb2;
     a.nitems = nitems;
     a.coef_item_stride = item_stride;
     if (ucols) {
@@ -223,6 +228,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
     int ncolmax = ucols ? q.ncol_u_max : q.ncol_max;
     if (zpass_fixed_supported(n3)) {
         ZPassArgs z{};
+        z.nb2 = nb2;
         z.coef_table = a.coef_table;
         z.coef_base = a.coef_base;
         z.coef_bstride = a.coef_bstride;
@@ -239,7 +245,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
         z.tw32 = s.twf[2];
         z.cols32 = reinterpret_cast<float2*>(cols);
         z.perm = s.perm[2];
-        launch_zpass_fixed(true, z, ncolmax, nb2, n3, st, fp32);
+        launch_zpass_fixed(true, z, ncolmax, nb2 * nrhs, n3, st, fp32);
         return;
     }
     TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision z passes need a fixed-size grid length");
@@ -247,14 +253,15 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
     a.ct = L >= 16 ? 16 : L;
     a.lines_per_block = L;
     int it = L / a.ct;
-    dim3 grid((ncolmax + a.ct - 1) / a.ct, (nitems + it - 1) / it, nb2);
+    dim3 grid((ncolmax + a.ct - 1) / a.ct, (nitems + it - 1) / it, nb2 * nrhs);
     size_t shm = (size_t)L * n3 * sizeof(double2);
     TM_LAUNCH(k_zpass_inv, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
 }
 
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin, double2* out,
-                      hipStream_t st, bool fp32) {
+                      hipStream_t st, bool fp32, int nrhs) {
     ZFwdArgs a;
+    a.nb2 = 2 * q.nk;
     a.cols = cols;
     a.ncol_stride = q.ncol_max;
     a.colptr = q.d_colptr_kq;
@@ -271,6 +278,7 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
     const int n3 = s.n3;
     if (zpass_fixed_supported(n3)) {
         ZPassArgs z{};
+        z.nb2 = 2 * q.nk;
         z.colptr = a.colptr;
         z.entg = a.entg;
         z.enti3 = a.enti3;
@@ -289,7 +297,7 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
         z.inv_n = 1.0 / (double)s.N;
         z.tw32 = s.twf[2];
         z.cols32 = reinterpret_cast<float2*>(const_cast<double2*>(cols));
-        launch_zpass_fixed(false, z, q.ncol_max, 2 * q.nk, n3, st, fp32);
+        launch_zpass_fixed(false, z, q.ncol_max, 2 * q.nk * nrhs, n3, st, fp32);
         return;
     }
     TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision z passes need a fixed-size grid length");
@@ -298,7 +306,7 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
     a.lines_per_block = L;
     a.inv_n = 1.0 / (double)s.N;
     int it = L / a.ct;
-    dim3 grid((q.ncol_max + a.ct - 1) / a.ct, (a.nitems + it - 1) / it, 2 * q.nk);
+    dim3 grid((q.ncol_max + a.ct - 1) / a.ct, (a.nitems + it - 1) / it, 2 * q.nk * nrhs);
     size_t shm = (size_t)L * n3 * sizeof(double2);
     TM_LAUNCH(k_zpass_fwd, grid, dim3(kZThreads), shm, st, a, s.plan[2]);
 }

@@ -46,8 +46,11 @@ struct MF<float> {
     __device__ static int row(int v, int kk) { return 4 * kk + v; }
 };
 
+// Batches of several right-hand sides: batch b uses the A of b % amod (its
+// side and k point); B, C, Y and the partials are per b.
 struct GemmCN {
-    const double2* const* A_tab;  // per batch (or null -> A_base + b*a_bstride)
+    const double2* const* A_tab;  // per batch b % amod (or null -> A_base + b*a_bstride)
+    int amod;
     const double2* A_base;
     long long a_bstride;
     int lda;
@@ -64,7 +67,7 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     const int tile = blockIdx.x;
     const int m0 = (tile / g.nt) * 16, n0 = (tile % g.nt) * 16;
     const int l = threadIdx.x, i = l & 15, kk = l >> 4;
-    const double2* A = g.A_tab ? g.A_tab[b] : g.A_base + (long long)b * g.a_bstride;
+    const double2* A = g.A_tab ? g.A_tab[b % g.amod] : g.A_base + (long long)b * g.a_bstride;
     const double2* B = g.B_base + (long long)b * g.b_bstride;
     const int kbeg = ks * g.kchunk;
     const int kend = min(g.K, kbeg + g.kchunk);
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(kCnThreads) k_gemm_cn_lds(GemmCN g, int mt) {
     LdsC<R>* As = reinterpret_cast<LdsC<R>*>(lds_raw);
     LdsC<R>* Bs = As + Mp * LS;
     const int b = blockIdx.y, ks = blockIdx.x;
-    const double2* A = g.A_tab ? g.A_tab[b] : g.A_base + (long long)b * g.a_bstride;
+    const double2* A = g.A_tab ? g.A_tab[b % g.amod] : g.A_base + (long long)b * g.a_bstride;
     const double2* B = g.B_base + (long long)b * g.b_bstride;
     const int kbeg = ks * g.kchunk;
     const int kend = min(g.K, kbeg + g.kchunk);
@@ -186,7 +189,7 @@ struct GemmUpd {
     const double2* C_base;        // per batch C_base + b*c_bstride, [Minner][Nout]
     long long c_bstride;
     int ldc;
-    const double2* const* A_tab;
+    const double2* const* A_tab;  // per batch b % (2 nk)
     int lda;
     int Nout, K, Minner;
     double cs;
@@ -199,7 +202,8 @@ __global__ void __launch_bounds__(64) k_gemm_update(GemmUpd g) {
     const int b = blockIdx.z;
     const int n0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
     const int l = threadIdx.x, i = l & 15, kk = l >> 4;
-    const double2* A = g.A_tab[b];
+    const int bt = b % (2 * g.nk);
+    const double2* A = g.A_tab[bt];
     const double2* C = g.C_base + (long long)b * g.c_bstride;
     double2* Y = g.Y_base + (long long)b * g.y_bstride;
     typename MF<R>::V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
@@ -214,7 +218,7 @@ __global__ void __launch_bounds__(64) k_gemm_update(GemmUpd g) {
         di = mfma(cx, ay, di);
         di = mfma(cy, ax, di);
     }
-    const double os = b < g.nk ? g.os_x : g.os_y;
+    const double os = bt < g.nk ? g.os_x : g.os_y;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         int n = n0 + MF<R>::row(v, kk), k = k0 + i;
@@ -267,10 +271,14 @@ int choose_kchunk(int K, long long tiles_times_batch) {
     return kc;
 }
 
+// nbatch batches per right-hand side, nrhs right-hand sides (the K chunking
+// depends on nbatch only, so each right-hand side is summed as when alone)
 void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const double2* B_base, long long b_bstride,
-                 int ldb, int M, int Nn, int K, int nbatch, double2* out, hipStream_t st, bool f32 = false) {
+                 int ldb, int M, int Nn, int K, int nbatch, int nrhs, double2* out, hipStream_t st,
+                 bool f32 = false) {
     GemmCN g;
     g.A_tab = A_tab;
+    g.amod = nbatch;
     g.A_base = nullptr;
     g.a_bstride = 0;
     g.lda = lda;
@@ -286,9 +294,10 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
     if (cn_lds_fits(M, Nn)) {
         g.kchunk = cn_lds_kchunk(K, nbatch);
         g.ksplit = (K + g.kchunk - 1) / g.kchunk;
-        TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
+        TM_CHECK((size_t)nrhs * nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL,
+                 "GEMM partial buffer too small");
         const size_t shm = (size_t)(mt + g.nt) * 16 * (kCnChunk + 1) * (f32 ? 8 : 16);
-        dim3 grid(g.ksplit, nbatch);
+        dim3 grid(g.ksplit, nrhs * nbatch);
         const void* fn = f32 ? (const void*)k_gemm_cn_lds<float> : (const void*)k_gemm_cn_lds<double>;
         TM_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess,
                  TM_EDEVICE, "cannot raise the LDS limit of k_gemm_cn_lds");
@@ -300,8 +309,9 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
     } else {
         g.kchunk = choose_kchunk(K, (long long)mt * g.nt * nbatch);
         g.ksplit = (K + g.kchunk - 1) / g.kchunk;
-        TM_CHECK((size_t)nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL, "GEMM partial buffer too small");
-        dim3 grid(mt * g.nt, g.ksplit, nbatch);
+        TM_CHECK((size_t)nrhs * nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL,
+                 "GEMM partial buffer too small");
+        dim3 grid(mt * g.nt, g.ksplit, nrhs * nbatch);
         if (f32) {
             TM_LAUNCH(k_gemm_cn<float>, grid, dim3(64), 0, st, g);
         } else {
@@ -309,13 +319,13 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
         }
     }
     long long mn = (long long)M * Nn;
-    TM_LAUNCH(k_reduce_parts, dim3((unsigned)((mn * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
-                       out, g.ksplit, mn, nbatch);
+    TM_LAUNCH(k_reduce_parts, dim3((unsigned)((mn * nrhs * nbatch + 255) / 256)), dim3(256), 0, st, s.ws.gpart,
+                       out, g.ksplit, mn, nrhs * nbatch);
 }
 
 void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C, long long c_bstride, int ldc,
                      const double2* const* A_tab, int lda, int Nout, int K, int Minner, double cs, double osx,
-                     double osy, int nk, hipStream_t st, bool f32 = false) {
+                     double osy, int nk, int nrhs, hipStream_t st, bool f32 = false) {
     GemmUpd g;
     g.Y_base = Y;
     g.y_bstride = y_bstride;
@@ -332,7 +342,7 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
     g.os_x = osx;
     g.os_y = osy;
     g.nk = nk;
-    dim3 grid((Nout + 15) / 16, (K + 15) / 16, 2 * nk);
+    dim3 grid((Nout + 15) / 16, (K + 15) / 16, 2 * nk * nrhs);
     if (f32) {
         TM_LAUNCH(k_gemm_update<float>, grid, dim3(64), 0, st, g);
     } else {
@@ -349,32 +359,35 @@ size_t gemm_partial_elems(int nbatch, int M, int Nn, int K) {
     return (size_t)nbatch * ks * M * Nn;
 }
 
-void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st, bool f32) {
+// x and out hold nrhs BR vectors back to back
+void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st, bool f32,
+                     int nrhs) {
     if (s.nproj == 0) return;
     const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
     const long long bstride = (long long)nb * 2 * P;
     double2* Bm = s.ws.gsmall;
-    double2* Wm = s.ws.gsmall + (size_t)nbatch * s.nproj * 2 * nb;
-    run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, Bm, st, f32);
-    long long tot = (long long)nbatch * s.nproj * 2 * nb;
+    double2* Wm = s.ws.gsmall + (size_t)nrhs * nbatch * s.nproj * 2 * nb;
+    run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, nrhs, Bm, st, f32);
+    long long tot = (long long)nrhs * nbatch * s.nproj * 2 * nb;
     TM_LAUNCH(k_dmat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Bm, s.dvan, Wm, s.nproj, nb,
-                       nbatch);
+                       nrhs * nbatch);
     run_gemm_update(out, bstride, P, Wm, (long long)s.nproj * 2 * nb, 2 * nb, q.d_vkb, P, 2 * nb, P, s.nproj, 1.0,
-                    1.0, 1.0, q.nk, st, f32);
+                    1.0, 1.0, q.nk, nrhs, st, f32);
 }
 
 void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
-                           bool f32) {
+                           bool f32, int nrhs) {
     const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
     const long long bstride = (long long)nb * 2 * P;
     double2* S = s.ws.gsmall;
-    run_gemm_cn(s, (const double2* const*)q.d_occ, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, S, st, f32);
+    run_gemm_cn(s, (const double2* const*)q.d_occ, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, nrhs, S, st,
+                f32);
     run_gemm_update(phi, bstride, 2 * P, S, (long long)nb * nb, nb, (const double2* const*)q.d_occ, 2 * P, nb,
-                    2 * P, nb, -1.0, osx, osy, q.nk, st, f32);
+                    2 * P, nb, -1.0, osx, osy, q.nk, nrhs, st, f32);
 }
 
-void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32) {
-    launch_project_signed(s, q, out, 1.0, -1.0, st, f32);
+void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32, int nrhs) {
+    launch_project_signed(s, q, out, 1.0, -1.0, st, f32, nrhs);
 }
 
 }  // namespace tml

@@ -60,8 +60,18 @@ struct Dot {
     int jsign;  // 1: negate the contribution of the Y half
 };
 
+// lane blockIdx.y
 template <int ND>
 __global__ void __launch_bounds__(kRedThreads) k_multidot(DotSet<ND> ds, long long n, long long half, double2* part) {
+    const int lane = blockIdx.y;
+    const double2* A[ND];
+    const double2* B[ND];
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+        A[d] = ds.a[d] + lane * ds.sa[d];
+        B[d] = ds.b[d] + lane * ds.sb[d];
+    }
+    part += (long long)lane * gridDim.x * ND;
     double2 acc[ND];
 #pragma unroll
     for (int d = 0; d < ND; ++d) acc[d] = cmk(0.0, 0.0);
@@ -69,7 +79,7 @@ __global__ void __launch_bounds__(kRedThreads) k_multidot(DotSet<ND> ds, long lo
         const bool y = i >= half;
 #pragma unroll
         for (int d = 0; d < ND; ++d) {
-            double2 t = cmulc(ds.a[d][i], ds.b[d][i]);
+            double2 t = cmulc(A[d][i], B[d][i]);
             if (y && ds.jsign[d]) t = cmk(-t.x, -t.y);
             acc[d] = cadd(acc[d], t);
         }
@@ -80,10 +90,12 @@ __global__ void __launch_bounds__(kRedThreads) k_multidot(DotSet<ND> ds, long lo
         for (int d = 0; d < ND; ++d) part[(long long)blockIdx.x * ND + d] = acc[d];
 }
 
-// deterministic final sum of the block partials, times the 1/nk weight
+// deterministic final sum of the block partials, times the 1/nk weight (lane blockIdx.x)
 __global__ void k_dot_final(const double2* part, int nblk, int nd, double w, double2* out) {
     int d = threadIdx.x;
     if (d >= nd) return;
+    part += (long long)blockIdx.x * nblk * nd;
+    out += blockIdx.x * kDotStride;
     double2 s = cmk(0.0, 0.0);
     for (int b = 0; b < nblk; ++b) s = cadd(s, part[(long long)b * nd + d]);
     out[d] = cscale(s, w);
@@ -95,6 +107,13 @@ __global__ void __launch_bounds__(kRedThreads) k_ph_update(const ChainState* cs,
                                                             const double2* qp, double2* r, const double2* u0,
                                                             const double2* u1, const double2* u2,
                                                             const double2* u3, long long n, double2* part) {
+    const long long lo = (long long)blockIdx.y * n;  // lane blockIdx.y
+    cs += blockIdx.y;
+    Lq += lo;
+    q += lo;
+    qp += lo;
+    r += lo;
+    part += (long long)blockIdx.y * gridDim.x * 4;
     const double slq = cs->slq.x, sq = cs->sq.x, sp = cs->sprev.x;
     const double a = cs->alpha.x, bp = cs->beta_prev;
     const bool live = !cs->broken;
@@ -126,6 +145,17 @@ __global__ void __launch_bounds__(kRedThreads) k_nh_update(const ChainState* cs,
                                                             const double2* u0, const double2* u1, const double2* u2,
                                                             const double2* u3, long long n, long long half,
                                                             double2* part) {
+    const long long lo = (long long)blockIdx.y * n;  // lane blockIdx.y
+    cs += blockIdx.y;
+    Lq += lo;
+    q += lo;
+    qp += lo;
+    Ltp += lo;
+    p += lo;
+    pp += lo;
+    qh += lo;
+    ph += lo;
+    part += (long long)blockIdx.y * gridDim.x * 7;
     const double2 sq = cs->sq, sqp = cs->sprev, sp = cs->sp, spp = cs->spprev;
     const double2 a = cs->alpha;
     const double2 g = cs->gamma_prev;
@@ -162,14 +192,19 @@ __global__ void __launch_bounds__(kRedThreads) k_nh_update(const ChainState* cs,
 __global__ void k_jcopy(const double2* src, double2* dst, long long n, long long half) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    src += (long long)blockIdx.y * n;
+    dst += (long long)blockIdx.y * n;
     double2 v = src[i];
     dst[i] = i >= half ? cmk(-v.x, -v.y) : v;
 }
 
-// ---- control kernels (one thread) -------------------------------------------------
+// ---- control kernels (one thread per lane) ------------------------------------------
 
 // pH start; dots: (v, J Lv), (v, v), (Lv, J Lv), (u_l, v) l = 0..3
 __global__ void k_ph_start(ChainState* cs, const double2* d, Coeffs co) {
+    cs += threadIdx.x;
+    d += threadIdx.x * kDotStride;
+    co = co.lane(threadIdx.x);
     const double n1sq = d[0].x, vv = d[1].x;
     cs->broken = 0;
     cs->step = 0;
@@ -191,6 +226,10 @@ __global__ void k_ph_start(ChainState* cs, const double2* d, Coeffs co) {
 
 // pH after the apply; d: (r, J Lr), (r, r), (Lr, J Lr); zu: (u_l, r)
 __global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, Coeffs co) {
+    cs += threadIdx.x;
+    d += threadIdx.x * kDotStride;
+    zu += threadIdx.x * kDotStride;
+    co = co.lane(threadIdx.x);
     const int j = cs->step;
     if (cs->broken || j >= co.cap) return;
     const double b2 = d[0].x, rr = d[1].x, ll = d[2].x;
@@ -217,6 +256,9 @@ __global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, C
 
 // nH start; dots: (v, v), (u_l, v)
 __global__ void k_nh_start(ChainState* cs, const double2* d, Coeffs co) {
+    cs += threadIdx.x;
+    d += threadIdx.x * kDotStride;
+    co = co.lane(threadIdx.x);
     const double vv = d[0].x;
     cs->broken = 0;
     cs->step = 0;
@@ -237,6 +279,9 @@ __global__ void k_nh_start(ChainState* cs, const double2* d, Coeffs co) {
 
 // nH alpha from (P_raw, LQ_raw)
 __global__ void k_nh_alpha(ChainState* cs, const double2* d, Coeffs co) {
+    cs += threadIdx.x;
+    d += threadIdx.x * kDotStride;
+    co = co.lane(threadIdx.x);
     const int j = cs->step;
     if (cs->broken || j >= co.cap) return;
     cs->alpha = cmul(cmul(cconj(cs->sp), cs->sq), d[0]);
@@ -245,6 +290,9 @@ __global__ void k_nh_alpha(ChainState* cs, const double2* d, Coeffs co) {
 
 // nH after the update; d: (ph, qh), (qh, qh), (ph, ph), (u_l, qh)
 __global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
+    cs += threadIdx.x;
+    d += threadIdx.x * kDotStride;
+    co = co.lane(threadIdx.x);
     const int j = cs->step;
     if (cs->broken || j >= co.cap) return;
     const double2 s = d[0];
@@ -281,54 +329,62 @@ __global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
 
 template <int ND>
 void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
-                  hipStream_t st) {
+                  hipStream_t st, int lanes) {
     int nblk = (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
-    TM_LAUNCH(k_multidot<ND>, dim3(nblk), dim3(kRedThreads), 0, st, ds, n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, ND, w, out);
+    TM_LAUNCH(k_multidot<ND>, dim3(nblk, lanes), dim3(kRedThreads), 0, st, ds, n, half, part);
+    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64), 0, st, part, nblk, ND, w, out);
 }
-template void run_multidot<1>(const DotSet<1>&, long long, long long, double, double2*, double2*, hipStream_t);
-template void run_multidot<3>(const DotSet<3>&, long long, long long, double, double2*, double2*, hipStream_t);
-template void run_multidot<5>(const DotSet<5>&, long long, long long, double, double2*, double2*, hipStream_t);
-template void run_multidot<7>(const DotSet<7>&, long long, long long, double, double2*, double2*, hipStream_t);
+template void run_multidot<1>(const DotSet<1>&, long long, long long, double, double2*, double2*, hipStream_t,
+                                  int);
+template void run_multidot<3>(const DotSet<3>&, long long, long long, double, double2*, double2*, hipStream_t,
+                                  int);
+template void run_multidot<5>(const DotSet<5>&, long long, long long, double, double2*, double2*, hipStream_t,
+                                  int);
+template void run_multidot<7>(const DotSet<7>&, long long, long long, double, double2*, double2*, hipStream_t,
+                                  int);
 
 static int red_blocks(long long n) {
     return (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
 }
 
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
-                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st) {
+                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st,
+                   int lanes) {
     int nblk = red_blocks(n);
-    TM_LAUNCH(k_ph_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3], n, part);
-    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, kNMeasure, w, out);
+    TM_LAUNCH(k_ph_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3], n,
+              part);
+    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64), 0, st, part, nblk, kNMeasure, w, out);
 }
 
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
-                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st) {
+                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st,
+                   int lanes) {
     int nblk = red_blocks(n);
-    TM_LAUNCH(k_nh_update, dim3(nblk), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0], u[1],
-                       u[2], u[3], n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(1), dim3(64), 0, st, part, nblk, 3 + kNMeasure, w, out);
+    TM_LAUNCH(k_nh_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0],
+              u[1], u[2], u[3], n, half, part);
+    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64), 0, st, part, nblk, 3 + kNMeasure, w, out);
 }
 
-void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st) {
-    TM_LAUNCH(k_jcopy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, dst, n, half);
+void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes) {
+    TM_LAUNCH(k_jcopy, dim3((unsigned)((n + 255) / 256), lanes), dim3(256), 0, st, src, dst, n, half);
 }
 
-void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
-    TM_LAUNCH(k_ph_start, dim3(1), dim3(1), 0, st, cs, d, co);
+void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
+    TM_LAUNCH(k_ph_start, dim3(1), dim3(lanes), 0, st, cs, d, co);
 }
-void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st) {
-    TM_LAUNCH(k_ph_step, dim3(1), dim3(1), 0, st, cs, d, zu, co);
+void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st,
+                 int lanes) {
+    TM_LAUNCH(k_ph_step, dim3(1), dim3(lanes), 0, st, cs, d, zu, co);
 }
-void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
-    TM_LAUNCH(k_nh_start, dim3(1), dim3(1), 0, st, cs, d, co);
+void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
+    TM_LAUNCH(k_nh_start, dim3(1), dim3(lanes), 0, st, cs, d, co);
 }
-void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
-    TM_LAUNCH(k_nh_alpha, dim3(1), dim3(1), 0, st, cs, d, co);
+void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
+    TM_LAUNCH(k_nh_alpha, dim3(1), dim3(lanes), 0, st, cs, d, co);
 }
-void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st) {
-    TM_LAUNCH(k_nh_step, dim3(1), dim3(1), 0, st, cs, d, co);
+void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
+    TM_LAUNCH(k_nh_step, dim3(1), dim3(lanes), 0, st, cs, d, co);
 }
 
 }  // namespace tml

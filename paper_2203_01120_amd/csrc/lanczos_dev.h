@@ -8,10 +8,15 @@ namespace tml {
 // breakdown tolerance of the chains (see tm.h for the rule it enters)
 constexpr double kBreakdownTol = 1e-10;
 
-// true vector = scale * raw vector
 // measure vectors u^l of a chain: l = x, y, z (spin) and n (charge)
 constexpr int kNMeasure = 4;
+// field directions one chain can run together (lanes)
+constexpr int kMaxLanes = 4;
+// reduced inner products kept per lane (a lane is one recursion of a chain
+// that runs several field directions together)
+constexpr int kDotStride = 16;
 
+// one lane's scalars; true vector = scale * raw vector
 struct ChainState {
     double2 sq, slq, sprev;     // q, Lq, q_prev (pH: real)
     double2 sp, spprev;         // p, p_prev (nH)
@@ -26,36 +31,51 @@ struct ChainState {
     int broken;
 };
 
+// coefficient arrays of all lanes: lane r at alpha + r cap, ..., z + r kNMeasure cap
 struct Coeffs {
-    double2* alpha;   // [cap]
-    double* beta;     // [cap]
-    double2* gamma;   // [cap]
-    double2* z;       // [kNMeasure][cap]
+    double2* alpha;   // [lanes][cap]
+    double* beta;     // [lanes][cap]
+    double2* gamma;   // [lanes][cap]
+    double2* z;       // [lanes][kNMeasure][cap]
     int cap;
+    __host__ __device__ Coeffs lane(int r) const {
+        return Coeffs{alpha + (size_t)r * cap, beta + (size_t)r * cap, gamma + (size_t)r * cap,
+                      z + (size_t)r * kNMeasure * cap, cap};
+    }
 };
 
+// Inner products (a_d, b_d), d < ND, for each of `lanes` lanes: lane r reads
+// a_d + r sa_d and b_d + r sb_d (stride 0 for a vector the lanes share).
 template <int ND>
 struct DotSet {
     const double2* a[ND];
     const double2* b[ND];
     int jsign[ND];
+    long long sa[ND];
+    long long sb[ND];
 };
 
+// All helpers below work on `lanes` lanes at once: lane r's vectors at + r n,
+// its state at cs + r, its inner products at out + r kDotStride, its partial
+// sums at part + r (blocks x values); the measure vectors u are shared.
 template <int ND>
 void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
-                  hipStream_t st);
+                  hipStream_t st, int lanes = 1);
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
-                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st);
+                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st,
+                   int lanes = 1);
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
-                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st);
-void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st);
-void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
+                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st,
+                   int lanes = 1);
+void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes = 1);
+void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
 // the step index comes from cs->step (device side), so step sequences can be
 // replayed from a graph; steps past co.cap are ignored
-void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st);
-void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
-void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
-void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st);
+void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st,
+                 int lanes = 1);
+void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
+void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
+void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
 
 }  // namespace tml

@@ -5,9 +5,15 @@
 
 namespace tml {
 
+// Several right-hand sides run as one batch: batch b of the grid is side and
+// k point b % nb2 of right-hand side b / nb2.  Sphere tables are per b % nb2;
+// columns, densities, fields and W are per b (or per right-hand side).
 struct PlaneArgs {
     int n1, n2, n3, NP;
     int nk, nb, nitems, bpc, nchunk;
+    int nb2;            // 2 nk: batches of one right-hand side
+    long long wstride;  // elements between the W (and rho) of consecutive right-hand sides (4 N)
+    long long fstride;  // elements between the local field tables of consecutive right-hand sides (6 N)
     double2* xcols;
     int ncol_max;
     const double2* ucols;
@@ -55,6 +61,7 @@ std::vector<int> digit_reversal(int n);
 
 // arguments of the fixed-size z passes (sphere <-> columns along i3)
 struct ZPassArgs {
+    int nb2;                           // batches of one right-hand side (tables are per b % nb2)
     const double2* const* coef_table;  // inverse: per-batch coefficient base, or null
     const double2* coef_base;          //          else coef_base + b * coef_bstride
     long long coef_bstride;

@@ -253,7 +253,7 @@ struct PlaneKernel {
 
     // band n at plane i3 -> real space in the LDS planes, stored at
     // digit-reversed positions along both axes
-    __device__ static void inverse(const Smem& m, const PlaneArgs& a, int b, int n, int i3, const Rows& R) {
+    __device__ static void inverse(const Smem& m, const PlaneArgs& a, int b, int bt, int n, int i3, const Rows& R) {
         double2* pl = m.pl;
         for (int i = threadIdx.x; i < R.nrl * N2; i += NT) {  // clear the occupied rows
             const int l = i / N2;
@@ -262,10 +262,10 @@ struct PlaneKernel {
         __syncthreads();
         if (SET == kXU) {
             const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-            scatter(pl, 0, cx, (long long)a.n3 * a.ncol_max, a.ncol_kq[b], a.colpos_kq[b]);
+            scatter(pl, 0, cx, (long long)a.n3 * a.ncol_max, a.ncol_kq[bt], a.colpos_kq[bt]);
         }
-        const double2* cu = a.ucols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_u_max;
-        scatter(pl, SET == kXU ? 2 : 0, cu, (long long)a.n3 * a.ncol_u_max, a.ncol_u[b], a.colpos_u[b]);
+        const double2* cu = a.ucols + (((long long)bt * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_u_max;
+        scatter(pl, SET == kXU ? 2 : 0, cu, (long long)a.n3 * a.ncol_u_max, a.ncol_u[bt], a.colpos_u[bt]);
         __syncthreads();
         RowLines rl{m.rowbase};
         fft_dif<N2, +1, NT, false>(pl, R.nrl, rl, m.tw2);
@@ -293,18 +293,18 @@ __global__ void __launch_bounds__(NT) k_density_t(PlaneArgs a, PlaneTabs t) {
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     double2* pl = m.pl;
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
-    const typename K::Rows R = K::setup(t, b, m);
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
+    const typename K::Rows R = K::setup(t, bt, m);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
-    const bool yside = b >= a.nk;
+    const bool yside = bt >= a.nk;
     double2 acc[4][PTS];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int j = 0; j < PTS; ++j) acc[c][j] = cmk(0.0, 0.0);
     for (int n = n0; n < n1e; ++n) {
-        K::inverse(m, a, b, n, i3, R);
+        K::inverse(m, a, b, bt, n, i3, R);
 #pragma unroll
         for (int j = 0; j < PTS; ++j) {
             const int pt = threadIdx.x + j * NT;
@@ -344,12 +344,13 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     double2* pl = m.pl;
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z;
-    const typename K::Rows R = K::setup(t, b, m);
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
+    const typename K::Rows R = K::setup(t, bt, m);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
-    const double sg = b < a.nk ? 1.0 : -1.0;
-    const bool yside = b >= a.nk;
+    const double sg = bt < a.nk ? 1.0 : -1.0;
+    const bool yside = bt >= a.nk;
+    const double2* Wr = a.W + (long long)(b / a.nb2) * a.wstride;
     const long long N = (long long)G::NP * a.n3;
     const long long off = (long long)i3 * G::NP;
     // local fields of my points (at the digit-reversed positions the planes use):
@@ -366,19 +367,19 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
             bx[j] = sg * a.vrs[N + g];
             by[j] = sg * a.vrs[2 * N + g];
             bz[j] = sg * a.vrs[3 * N + g];
-            w0[j] = a.W[g];
-            wx[j] = cscale(a.W[N + g], sg);
-            wy[j] = cscale(a.W[2 * N + g], sg);
-            wz[j] = cscale(a.W[3 * N + g], sg);
+            w0[j] = Wr[g];
+            wx[j] = cscale(Wr[N + g], sg);
+            wy[j] = cscale(Wr[2 * N + g], sg);
+            wz[j] = cscale(Wr[3 * N + g], sg);
         } else {
             vv[j] = bx[j] = by[j] = bz[j] = 0.0;
             w0[j] = wx[j] = wy[j] = wz[j] = cmk(0.0, 0.0);
         }
     }
-    const int ncx = a.ncol_kq[b];
-    const int* cpx = a.colpos_kq[b];
+    const int ncx = a.ncol_kq[bt];
+    const int* cpx = a.colpos_kq[bt];
     for (int n = n0; n < n1e; ++n) {
-        K::inverse(m, a, b, n, i3, R);
+        K::inverse(m, a, b, bt, n, i3, R);
 #pragma unroll
         for (int j = 0; j < PTS; ++j) {
             const int pt = threadIdx.x + j * NT;
@@ -436,7 +437,7 @@ __global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
     const int n1e = min(a.nb, n0 + a.bpc);
     const bool yside = b >= a.nk;
     for (int n = n0; n < n1e; ++n) {
-        K::inverse(m, a, b, n, i3, R);
+        K::inverse(m, a, b, b, n, i3, R);
         double2* out = a.ureal + (((long long)a.uslot[b] * a.nb + n) * a.n3 + i3) * 2 * G::NP;
         for (int idx = threadIdx.x; idx < G::NP; idx += NT) {
             const int p2 = idx / N1, p1 = idx - p2 * N1;
@@ -728,21 +729,21 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     const T2* xcols = pick<T2>(a.xcols, a.xcols32);
-    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
+    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z, bt = b % a.nb2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     WTw<N1, T2> tw1{pick<T2>(t.tw1, t.tw1f)};
     // equal lengths share one table, so the two register sets are one
     WTw<N2, T2> tw2{N1 == N2 ? pick<T2>(t.tw1, t.tw1f) : pick<T2>(t.tw2, t.tw2f)};
     tw1.init(lane);
     tw2.init(lane);
-    const int nrx = K::setup(t, b, m);
-    const unsigned long long mask = t.rmask_kq[b];
+    const int nrx = K::setup(t, bt, m);
+    const unsigned long long mask = t.rmask_kq[bt];
     const int nlw = K::wave_rows(2 * nrx, w);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const long long cs = (long long)a.n3 * a.ncol_max;
     // the side's resident slot, read once (the loop's stores could alias it)
-    const double2* ub = a.ureal + (long long)a.uslot[b] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
+    const double2* ub = a.ureal + (long long)a.uslot[bt] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
     int o[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
@@ -802,13 +803,16 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
 // idx = p2 n1 + p1 (LDS position, digit-reversed), 6 complex per point:
 //   (v + Bz, v - Bz), (Bx, By), W0 + Wz, W0 - Wz, Wx - i Wy, Wx + i Wy
 // (x side; the y side flips the sign of B and of the vector part of W).
+// (right-hand side blockIdx.z: its W and its table, wstride / fstride apart)
 template <int N1, int N2, class T2>
 __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __restrict__ W, const int* perm1,
-                           const int* perm2, T2* __restrict__ F, int n3) {
+                           const int* perm2, T2* __restrict__ F, int n3, long long wstride, long long fstride) {
     constexpr int NP = N1 * N2;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int i3 = blockIdx.y;
     if (idx >= NP) return;
+    W += blockIdx.z * wstride;
+    F += blockIdx.z * fstride;
     const int p2 = idx / N1, p1 = idx - p2 * N1;
     const long long N = (long long)NP * n3;
     const long long g = (long long)i3 * NP + perm1[p1] * N2 + perm2[p2];
@@ -833,29 +837,30 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     T2* xcols = pick<T2>(a.xcols, a.xcols32);
-    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z;
+    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z, bt = b % a.nb2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     WTw<N1, T2> tw1{pick<T2>(t.tw1, t.tw1f)};
     // equal lengths share one table, so the two register sets are one
     WTw<N2, T2> tw2{N1 == N2 ? pick<T2>(t.tw1, t.tw1f) : pick<T2>(t.tw2, t.tw2f)};
     tw1.init(lane);
     tw2.init(lane);
-    const int nrx = K::setup(t, b, m);
-    const unsigned long long mask = t.rmask_kq[b];
+    const int nrx = K::setup(t, bt, m);
+    const unsigned long long mask = t.rmask_kq[bt];
     const int nlw = K::wave_rows(2 * nrx, w);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const long long cs = (long long)a.n3 * a.ncol_max;
     // the side's resident slot, read once (the loop's stores could alias it)
-    const double2* ub = a.ureal + (long long)a.uslot[b] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
-    const bool yside = b >= a.nk;
+    const double2* ub = a.ureal + (long long)a.uslot[bt] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
+    const bool yside = bt >= a.nk;
     int o[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
         int g;
         wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
     }
-    const T2* fw = pick<T2>(a.fields, a.fields32) + ((long long)i3 * G::NP + w * K::WPTS) * 6;
+    const T2* fw = pick<T2>(a.fields, a.fields32) + (long long)(b / a.nb2) * a.fstride +
+                   ((long long)i3 * G::NP + w * K::WPTS) * 6;
     for (int n = n0; n < n1e; ++n) {
         const int boff = (n & 1) * K::BUF;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
@@ -949,6 +954,7 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
     } else if (a.ureal) {
         TM_CHECK(t.colidx_kq != nullptr, TM_EINVAL, "missing column index tables");
         const dim3 wgrid(grid.z, grid.y, grid.x);  // (b, chunk, i3)
+        const int nrhs = (int)grid.z / a.nb2;
         if (fp32) {
             using WD = WaveKernel<N1, N2, BTD, CPW, float2>;
             using WA = WaveKernel<N1, N2, BTA, CPW, float2>;
@@ -956,8 +962,8 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
                 launch_with_lds(k_density_w<N1, N2, BTD, CPW, float2>, "k_density_w32", WD::bytes(), wgrid, WD::NT,
                                 st, a, t);
             } else {
-                TM_LAUNCH((k_fields_w<N1, N2, float2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs,
-                          a.W, t.perm1, t.perm2, a.fields32, a.n3);
+                TM_LAUNCH((k_fields_w<N1, N2, float2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
+                          a.vrs, a.W, t.perm1, t.perm2, a.fields32, a.n3, a.wstride, a.fstride);
                 launch_with_lds(k_apply_w<N1, N2, BTA, CPW, float2>, "k_apply_w32", WA::bytes(), wgrid, WA::NT, st,
                                 a, t);
             }
@@ -970,8 +976,8 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
                             t);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
-            TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3), dim3(256), 0, st, a.vrs,
-                      a.W, t.perm1, t.perm2, a.fields, a.n3);
+            TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
+                      a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
             launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
         }
     } else {
@@ -1011,8 +1017,8 @@ __global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
     T2* tw = lds + L * LS;
     const T2* gtw = pick<T2>(a.tw, a.tw32);
     int* perm = reinterpret_cast<int*>(tw + N3);
-    const int b = blockIdx.z;
-    const int ncol = a.ncol[b];
+    const int b = blockIdx.z, bt = b % a.nb2;
+    const int ncol = a.ncol[bt];
     const int col0 = blockIdx.x * CT;
     if (col0 >= ncol) return;
     const int item0 = blockIdx.y * IT;
@@ -1022,11 +1028,11 @@ __global__ void __launch_bounds__(NT) k_zinv_t(ZPassArgs a) {
     }
     for (int i = threadIdx.x; i < L * LS; i += NT) lds[i] = Cx<T2>::mk(0, 0);
     __syncthreads();
-    const int* cp = a.colptr[b];
-    const int* eg = a.entg[b];
-    const int* ei = a.enti3[b];
-    const double2* coef = a.coef_table ? a.coef_table[b] : a.coef_base + (long long)b * a.coef_bstride;
-    const long long istr = a.istride_tab ? a.istride_tab[b] : a.istride;
+    const int* cp = a.colptr[bt];
+    const int* eg = a.entg[bt];
+    const int* ei = a.enti3[bt];
+    const double2* coef = a.coef_table ? a.coef_table[bt] : a.coef_base + (long long)b * a.coef_bstride;
+    const long long istr = a.istride_tab ? a.istride_tab[bt] : a.istride;
     constexpr int PER = NT / L > 0 ? NT / L : 1;
     for (int l = threadIdx.x / PER; l < L; l += NT / PER) {
         const int c = col0 + l % CT, item = item0 + l / CT;
@@ -1057,13 +1063,13 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
     T2* tw = lds + L * LS;
     const T2* gtw = pick<T2>(a.tw, a.tw32);
     int* perm = reinterpret_cast<int*>(tw + N3);
-    const int b = blockIdx.z;
-    const int ncol = a.ncol[b];
+    const int b = blockIdx.z, bt = b % a.nb2;
+    const int ncol = a.ncol[bt];
     const int col0 = blockIdx.x * CT;
     const int item0 = blockIdx.y * IT;
     const long long bbase = (long long)b * a.nitems * a.npw_pad;
     if (blockIdx.x == 0) {  // the first column tile clears the padding of its items
-        const int npw = a.npw[b], padn = a.npw_pad - npw;
+        const int npw = a.npw[bt], padn = a.npw_pad - npw;
         for (int i = threadIdx.x; i < IT * padn; i += NT) {
             const int item = item0 + i / padn;
             if (item < a.nitems) a.out[bbase + (long long)item * a.npw_pad + npw + i % padn] = cmk(0.0, 0.0);
@@ -1086,11 +1092,11 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
     }
     __syncthreads();
     fft_dit_all<N3, -1, NT>(lds, L, ZLines<LS>{}, tw);
-    const int* cp = a.colptr[b];
-    const int* eg = a.entg[b];
-    const int* ei = a.enti3[b];
-    const double* kin = a.kin[b];
-    const double* eps = a.eps[b];
+    const int* cp = a.colptr[bt];
+    const int* eg = a.entg[bt];
+    const int* ei = a.enti3[bt];
+    const double* kin = a.kin[bt];
+    const double* eps = a.eps[bt];
     constexpr int PER = NT / L > 0 ? NT / L : 1;
     for (int l = threadIdx.x / PER; l < L; l += NT / PER) {
         const int c = col0 + l % CT, item = item0 + l / CT;

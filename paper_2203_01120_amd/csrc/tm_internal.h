@@ -194,6 +194,7 @@ struct Workspace {
     double2* dotpart = nullptr;   // per-block partial inner products
     int nchunk = 0;
     int ksplit = 0;
+    int width = 0;                // right-hand sides the buffers hold
     size_t cap_xcols = 0, cap_rho_part = 0, cap_gpart = 0, cap_gsmall = 0;
 };
 
@@ -226,6 +227,7 @@ struct System {
     std::map<std::array<int, 5>, int> uslot_of;
     long long resident_limit = -1;  // bytes; -1 = a share of the free device memory
     int ureal_mode = 0;             // 0 undecided, 1 resident, 2 columns
+    int ws_epoch = 0;               // bumped whenever the workspace is reallocated
     double2* ureal = nullptr;
     size_t ureal_bytes = 0;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture of chain steps
@@ -253,27 +255,33 @@ T* dev_upload(System& s, const T* h, size_t count) {
 }
 
 // ---------------------------------------------------------------- launchers
+// nrhs: right-hand sides applied together; their BR vectors sit back to back
+// (batch b of the kernels = side and k point b % 2nk of right-hand side b / 2nk)
 // fft.hip
 // fp32: single-precision columns (stored in the same buffer, cast to float2)
 void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2* coef, long long coef_bstride,
-                      int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32 = false);
+                      int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32 = false, int nrhs = 1);
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin,
-                      double2* out, hipStream_t st, bool fp32 = false);
+                      double2* out, hipStream_t st, bool fp32 = false, int nrhs = 1);
 void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st);
 // apply.hip
-void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32 = false);
-void launch_potential(const System& s, const QSet& q, hipStream_t st);
-void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32 = false);
+void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32 = false, int nrhs = 1);
+void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs = 1);
+void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32 = false, int nrhs = 1);
 void launch_ureal(const System& s, const QSet& q, hipStream_t st);
 void launch_fxc_setup(System& s, const double* rho_plane, hipStream_t st);
 void launch_coulomb_setup(const System& s, QSet& q, hipStream_t st);
 // gemm.hip
 void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* out, hipStream_t st,
-                     bool f32 = false);
-void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32 = false);
+                     bool f32 = false, int nrhs = 1);
+void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32 = false,
+                    int nrhs = 1);
+void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
+                           bool f32 = false, int nrhs = 1);
 
 // api.hip
-void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st);
-void ensure_workspace(System& s, const QSet& q);
+void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st, int nrhs = 1);
+// sizes the apply workspace for nrhs right-hand sides (grows it when needed)
+void ensure_workspace(System& s, const QSet& q, int nrhs = 1);
 
 }  // namespace tml
