@@ -183,7 +183,9 @@ EV = 27.211386245988  # eV per Hartree
 def run_qpath(args, tm, torch):
     """Batched chains: the cubic20 system with 24 q along Gamma-M-K-Gamma, three
     directions each (m_+, m_-, m_z), 72 pseudo-Hermitian chains stepped
-    together on one stream, then chi on 400 omega per chain."""
+    together on one stream, then chi on 400 omega per chain.  With
+    --qpath-lanes 3 the three directions of a q set run as the lanes of one
+    chain (one batched apply per step for all three)."""
     import synth
     sysd = synth.make_cubic20()
     qfrac = synth.q_path(24)
@@ -203,11 +205,17 @@ def run_qpath(args, tm, torch):
     for iq in range(len(qs)):
         tm.tm_lanczos_run(h, iq, "+", "pH", 6, prec)
     torch.cuda.synchronize()
-    log(f"timed: {len(specs)} chains x {m} steps + chi ({args.precision})")
+    lanes = args.qpath_lanes
+    log(f"timed: {len(specs)} chains x {m} steps + chi ({args.precision}, {lanes} lane(s) per chain object)")
     t0 = time.perf_counter()
-    chains = [tm.tm_chain_begin(h, iq, mu, "pH", m, prec) for iq, mu in specs]
-    tm.tm_chains_step(chains, m)
-    coeffs = [tm.tm_chain_coeffs(c, m) for c in chains]
+    if lanes == 3:
+        chains = [tm.tm_chain_begin_multi(h, iq, ["+", "-", "z"], "pH", m, prec) for iq in range(len(qs))]
+        tm.tm_chains_step(chains, m)
+        coeffs = [co for c in chains for co in tm.tm_chain_coeffs_lanes(c, m)]
+    else:
+        chains = [tm.tm_chain_begin(h, iq, mu, "pH", m, prec) for iq, mu in specs]
+        tm.tm_chains_step(chains, m)
+        coeffs = [tm.tm_chain_coeffs(c, m) for c in chains]
     spectra = [tm.tm_chi(co, co["steps_done"], omega, eta) for co in coeffs]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -234,7 +242,8 @@ def run_qpath(args, tm, torch):
         "data": "synthetic",
         "config": {"workload": "cubic a=10 bohr, 2 sites, 20^3 grid, 8 bands, Gamma; 24 q on Gamma-M-K-Gamma "
                                "x (m_+, m_-, m_z) = 72 pseudo-Hermitian chains, chi on 400 omega each",
-                   "chains": len(specs), "chain_steps": m, "precision": args.precision},
+                   "chains": len(specs), "chain_steps": m, "precision": args.precision,
+                   "lanes_per_chain": lanes},
         "applies_per_s": round((steps + len(specs)) / dt, 1),
         "breakdowns": nbroken,
     }
@@ -330,6 +339,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="hexslab", choices=["hexslab", "cubic20", "qpath", "serving"])
     ap.add_argument("--chain-steps", type=int, default=2000, help="qpath: steps per chain")
+    ap.add_argument("--qpath-lanes", type=int, default=3, choices=[1, 3],
+                    help="qpath: directions per chain object (3: one batched apply per q set and step)")
     ap.add_argument("--rates", default="0.5,1,2", help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
     ap.add_argument("--seed", type=int, default=1)
