@@ -2,13 +2,17 @@
 
 A request asks for chi(q, omega) of one system along one field direction:
 (system, q set, direction, flavour, steps, omega grid, eta).  The server
-admits requests as device-resident chains (tm_chain_begin) while their vectors
-fit a device-memory budget, advances every admitted chain in rounds (whole
-step periods, more of them per round for the faster systems; the chains of
-one system on that system's stream, different systems on different streams
-so that their kernels run concurrently), and finishes a chain -- coefficients, then chi on the
-request's frequencies (tm_chi) -- as soon as it has run its steps.  All
-arithmetic happens in the library; this module only schedules.
+admits requests as device-resident chains while their vectors fit a
+device-memory budget.  Pending requests of the same system, q set and
+flavour with similar step counts are admitted together as the lanes of one
+chain (tm_chain_begin_multi, up to `lanes` of them): each step then applies
+L to all of them in one pass.  The server advances every admitted chain in
+rounds (whole step periods, more of them per round for the faster systems;
+the chains of one system on that system's stream, different systems on
+different streams so that their kernels run concurrently), and finishes a
+request -- coefficients, then chi on its frequencies (tm_chi) -- as soon as
+its lane has run its steps.  All arithmetic happens in the library; this
+module only schedules.
 """
 from __future__ import annotations
 
@@ -42,10 +46,13 @@ class Request:
 
 @dataclass
 class _Active:
-    req: Request
+    reqs: List[Request]                   # one per lane
     chain: int
+    flavour: str
+    cap: int
     issued: int = 0
     nbytes: int = 0
+    done: List[bool] = field(default_factory=list)
 
 
 @dataclass
@@ -58,10 +65,11 @@ class SystemSlot:
     periods: int = 1                      # periods per round
 
 
-def chain_bytes(nelem: int, flavour: str, nsteps: int) -> int:
-    """Device bytes of one chain: its BR vectors (pH 5 + 4 u, nH 9 + 4 u) and coefficients."""
-    nvec = (5 if flavour == "pH" else 9) + 4
-    return nvec * nelem * 16 + nsteps * 104
+def chain_bytes(nelem: int, flavour: str, nsteps: int, lanes: int = 1) -> int:
+    """Device bytes of one chain: per lane its BR vectors (pH 5, nH 9) and
+    coefficients, plus the 4 shared measure vectors."""
+    nvec = lanes * (5 if flavour == "pH" else 9) + 4
+    return nvec * nelem * 16 + lanes * nsteps * 104
 
 
 class Server:
@@ -69,7 +77,8 @@ class Server:
 
     PERIOD = {"pH": 6, "nH": 3}
 
-    def __init__(self, systems: Dict[str, SystemSlot], budget_bytes: int, rounds_per_sync: int = 1):
+    def __init__(self, systems: Dict[str, SystemSlot], budget_bytes: int, rounds_per_sync: int = 1,
+                 lanes: int = 4, lane_slack: float = 1.25):
         import torch
         self.torch = torch
         self.systems = systems
@@ -81,6 +90,8 @@ class Server:
         self.pending: deque = deque()
         self.done: List[Request] = []
         self.rounds_per_sync = rounds_per_sync
+        self.lanes = max(1, min(4, int(lanes)))
+        self.lane_slack = lane_slack         # longest / shortest request of one chain, at most
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -92,29 +103,65 @@ class Server:
     def idle(self) -> bool:
         return not self.pending and all(not s.active for s in self.systems.values())
 
+    def _bytes(self, group: List[Request]) -> int:
+        head = group[0]
+        return chain_bytes(self.systems[head.system].nelem[head.iq], head.flavour, max(r.nsteps for r in group),
+                           len(group))
+
+    def _group(self, head: Request) -> List[Request]:
+        """The head request and up to lanes-1 pending partners for one chain
+        (same system, q set and flavour, similar step counts, within the budget)."""
+        group = [head]
+        for r in self.pending:
+            if len(group) == self.lanes:
+                break
+            if (r.system, r.iq, r.flavour) != (head.system, head.iq, head.flavour):
+                continue
+            steps = [q.nsteps for q in group] + [r.nsteps]
+            if max(steps) > self.lane_slack * min(steps):
+                continue
+            if self.used + self._bytes(group + [r]) > self.budget:
+                continue
+            group.append(r)
+        return group
+
     def _admit(self) -> None:
         while self.pending:
-            req = self.pending[0]
-            slot = self.systems[req.system]
-            nb = chain_bytes(slot.nelem[req.iq], req.flavour, req.nsteps)
+            head = self.pending.popleft()
+            group = self._group(head)
+            slot = self.systems[head.system]
+            cap = max(r.nsteps for r in group)
+            nb = self._bytes(group)
             if self.used + nb > self.budget and self.used > 0:
+                self.pending.appendleft(head)
                 return
-            self.pending.popleft()
-            h = tb.tm_chain_begin(slot.handle, req.iq, req.direction, req.flavour, req.nsteps,
-                                  stream=slot.stream.cuda_stream)
-            req.t_admit = self.now()
-            slot.active.append(_Active(req, h, 0, nb))
+            for r in group[1:]:
+                self.pending.remove(r)
+            h = tb.tm_chain_begin_multi(slot.handle, head.iq, [r.direction for r in group], head.flavour, cap,
+                                        stream=slot.stream.cuda_stream)
+            now = self.now()
+            for r in group:
+                r.t_admit = now
+            slot.active.append(_Active(group, h, head.flavour, cap, 0, nb, [False] * len(group)))
             self.used += nb
 
-    def _finish(self, slot: SystemSlot, a: _Active) -> None:
-        co = tb.tm_chain_coeffs(a.chain, a.req.nsteps)
-        tb.tm_chain_end(a.chain)
-        m = max(1, min(co["steps_done"], a.req.nsteps))
-        a.req.coeffs = co
-        a.req.chi = tb.tm_chi(co, m, a.req.omega, a.req.eta)
-        a.req.t_done = self.now()
-        self.used -= a.nbytes
-        self.done.append(a.req)
+    def _finish_lanes(self, a: _Active) -> None:
+        """Finishes every request whose lane has run its steps."""
+        lanes = None
+        for i, r in enumerate(a.reqs):
+            if a.done[i] or a.issued < r.nsteps:
+                continue
+            if lanes is None:
+                lanes = tb.tm_chain_coeffs_lanes(a.chain, a.cap)
+            co = lanes[i]
+            n = r.nsteps
+            mine = {k: co[k][..., :n].copy() for k in ("alpha", "beta", "gamma", "z", "zn")}
+            mine.update(n1=co["n1"], steps_done=min(co["steps_done"], n), breakdown=co["steps_done"] < n)
+            r.coeffs = mine
+            r.chi = tb.tm_chi(mine, max(1, mine["steps_done"]), r.omega, r.eta)
+            r.t_done = self.now()
+            a.done[i] = True
+            self.done.append(r)
 
     def round(self) -> None:
         """Admit what fits, advance the active chains, finish completed ones.
@@ -133,13 +180,13 @@ class Server:
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             ev0.record(slot.stream)
             for flav in ("pH", "nH"):
-                group = [a for a in slot.active if a.req.flavour == flav]
+                group = [a for a in slot.active if a.flavour == flav]
                 if not group:
                     continue
                 k = self.PERIOD[flav] * slot.periods * self.rounds_per_sync
                 tb.tm_chains_step([a.chain for a in group], k, stream=slot.stream.cuda_stream)
                 for a in group:
-                    a.issued = min(a.req.nsteps, a.issued + k)
+                    a.issued = min(a.cap, a.issued + k)
             ev1.record(slot.stream)
             marks.append((slot, ev0, ev1))
         for slot, ev0, ev1 in marks:
@@ -149,8 +196,10 @@ class Server:
         for slot in self.systems.values():
             keep = []
             for a in slot.active:
-                if a.issued >= a.req.nsteps:
-                    self._finish(slot, a)
+                self._finish_lanes(a)
+                if all(a.done):
+                    tb.tm_chain_end(a.chain)
+                    self.used -= a.nbytes
                 else:
                     keep.append(a)
             slot.active = keep

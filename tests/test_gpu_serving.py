@@ -1,8 +1,9 @@
 """Continuous-batching server (paper_2203_01120_amd.serving) on the GPU.
 
 Each request's chi must be identical whether its chain runs alone or
-interleaved with others on per-system streams under a memory budget: the
-same kernels run on the same data, so the comparison is exact.
+interleaved with others on per-system streams under a memory budget, or as
+one lane of a chain shared with other requests: the same per-request
+arithmetic runs on the same data, so the comparison is exact.
 """
 import numpy as np
 import pytest
@@ -37,25 +38,30 @@ def requests(sv, omega, eta, stagger):
                        arrival=stagger * i) for i, (s, d, f, m) in enumerate(spec)]
 
 
-@pytest.mark.parametrize("stagger", [0.0, 0.02])
-def test_server_chi_identical_to_alone(pool, stagger):
+@pytest.mark.parametrize("stagger,lanes,slack", [(0.0, 1, 1.0), (0.02, 1, 1.0), (0.0, 4, 2.0)])
+def test_server_chi_identical_to_alone(pool, stagger, lanes, slack):
     tm, sv, slots = pool
     omega = np.linspace(0.0, 0.07, 64)
     eta = 2e-4
     # a budget of about two cubic20 chains forces admissions to wait
     budget = 2 * sv.chain_bytes(slots["cubic20"].nelem[0], "nH", 30)
-    say(f"server run, stagger {stagger}, budget {budget} B")
-    server = sv.Server(slots, budget_bytes=budget)
+    say(f"server run, stagger {stagger}, lanes {lanes}, budget {budget} B")
+    server = sv.Server(slots, budget_bytes=budget, lanes=lanes, lane_slack=slack)
     peak = [0]
+    widest = [1]
     orig = server._admit
 
     def admit():
         orig()
         peak[0] = max(peak[0], server.used)
+        for s in slots.values():
+            for a in s.active:
+                widest[0] = max(widest[0], len(a.reqs))
     server._admit = admit
     done = server.run(requests(sv, omega, eta, stagger))
     assert len(done) == 6 and server.used == 0
     assert peak[0] <= budget
+    assert (widest[0] > 1) == (lanes > 1)    # the lane runs really shared chains
     for r in done:
         alone = tm.tm_lanczos_run(slots[r.system].handle, 0, r.direction, r.flavour, r.nsteps)
         assert r.coeffs["steps_done"] == alone["steps_done"]
