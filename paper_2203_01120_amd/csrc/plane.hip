@@ -637,9 +637,10 @@ struct WCols {
     __device__ bool valid(int row) const { return (mask >> row) & 1ULL; }
 };
 
-template <int N1, int N2, int BT_, int CPW_, class T2>
+template <int N1, int N2, int BT_, int CPW_, class T2, int NBUF_>
 struct WaveKernel {
     using G = Geom<N1, N2>;
+    static constexpr int NBUF = NBUF_;              // LDS buffers alternating between bands (1 or 2)
     static constexpr int CPW = CPW_;                // columns per wave
     static constexpr int NW = N2 / CPW;             // waves
     static constexpr int NT = 64 * NW;
@@ -651,7 +652,7 @@ struct WaveKernel {
     static_assert(N2 % CPW == 0 && NW <= 16, "plane shape");
 
     struct Smem {
-        T2* pl;            // 2 buffers
+        T2* pl;            // NBUF buffers
         int* rowbase;      // [2 N1] plane * PS + row * N2P of the occupied rows of planes 0, 1
         int* rowinfo;      // [2 N1] plane * N1 + row
         int* perm1;
@@ -661,7 +662,7 @@ struct WaveKernel {
     __device__ static Smem carve(void* lds) {
         Smem m;
         m.pl = static_cast<T2*>(lds);
-        m.rowbase = reinterpret_cast<int*>(m.pl + 2 * BUF);
+        m.rowbase = reinterpret_cast<int*>(m.pl + NBUF * BUF);
         m.rowinfo = m.rowbase + 2 * N1;
         m.perm1 = m.rowinfo + 2 * N1;
         m.perm2 = m.perm1 + N1;
@@ -669,7 +670,7 @@ struct WaveKernel {
         return m;
     }
     static constexpr size_t bytes() {
-        return (size_t)2 * BUF * sizeof(T2) + (4 * N1 + N1 + N2) * sizeof(int) +
+        return (size_t)NBUF * BUF * sizeof(T2) + (4 * N1 + N1 + N2) * sizeof(int) +
                (size_t)N1 * N2 * sizeof(short);
     }
 
@@ -721,9 +722,10 @@ __device__ __forceinline__ void wave_point(int w, int q, const int* perm1, const
     g = perm1[p1] * N2 + perm2[p2];
 }
 
-template <int N1, int N2, int BT, int CPW, class T2>
-__global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW, T2>;
+// MINW: waves per SIMD the register allocation must leave room for
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW>
+__global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a, PlaneTabs t) {
+    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF>;
     using G = typename K::G;
     constexpr int PPL = K::PPL;
     extern __shared__ double2 lds[];
@@ -756,7 +758,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
 #pragma unroll
         for (int j = 0; j < PPL; ++j) acc[c][j] = Cx<T2>::mk(0, 0);
     for (int n = n0; n < n1e; ++n) {
-        const int boff = (n & 1) * K::BUF;
+        const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
         T2 uu[PPL], ud[PPL];
@@ -784,6 +786,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_density_w(PlaneArgs a, Plan
                 acc[3][j] = cadd(acc[3][j], csub(uu_xu, ud_xd));
             }
         }
+        // one buffer: the next band's rows may not overwrite columns still being read
+        if (NBUF == 1) __syncthreads();
     }
     const long long N = (long long)G::NP * a.n3;
     T2* out = pick<T2>(a.rho_part, a.rho_part32) + ((long long)b * a.nchunk + chunk) * 4 * N + (long long)i3 * G::NP;
@@ -829,9 +833,9 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-template <int N1, int N2, int BT, int CPW, class T2>
-__global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW, T2>;
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW>
+__global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, PlaneTabs t) {
+    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF>;
     using G = typename K::G;
     constexpr int PPL = K::PPL;
     extern __shared__ double2 lds[];
@@ -862,7 +866,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
     const T2* fw = pick<T2>(a.fields, a.fields32) + (long long)(b / a.nb2) * a.fstride +
                    ((long long)i3 * G::NP + w * K::WPTS) * 6;
     for (int n = n0; n < n1e; ++n) {
-        const int boff = (n & 1) * K::BUF;
+        const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
         T2 uu[PPL], ud[PPL];
@@ -923,7 +927,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW)) k_apply_w(PlaneArgs a, PlaneT
             const int c = m.colidx[row * N2 + p2];
             if (c >= 0) co[s * cs + c] = m.pl[boff + m.rowbase[l] + p2];
         }
-        // the next band works in the other buffer: no barrier here
+        // no barrier here: with two buffers the next band works in the other
+        // one; with one, each wave rewrites only the rows it has just finished
     }
 }
 
@@ -947,8 +952,9 @@ template <int N1, int N2, int NT>
 void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st, bool fp32) {
     // 4 columns per wave (12 waves for 48 x 48; 3 columns and 16 waves measured
     // slower: idle lanes in the column stages and register spills at 128 VGPRs)
-    constexpr int CPW = 4;
+    constexpr int CPW = 4, CPW32 = 4;
     constexpr int BTD = 2, BTA = 2;
+    constexpr int NBUF = 2, MINW = 1, NBUF32 = 2, MINW32 = 1;
     if (op == kOpUreal) {
         launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
     } else if (a.ureal) {
@@ -956,29 +962,30 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
         const dim3 wgrid(grid.z, grid.y, grid.x);  // (b, chunk, i3)
         const int nrhs = (int)grid.z / a.nb2;
         if (fp32) {
-            using WD = WaveKernel<N1, N2, BTD, CPW, float2>;
-            using WA = WaveKernel<N1, N2, BTA, CPW, float2>;
+            using WD = WaveKernel<N1, N2, BTD, CPW32, float2, NBUF32>;
+            using WA = WaveKernel<N1, N2, BTA, CPW32, float2, NBUF32>;
             if (op == kOpDensity) {
-                launch_with_lds(k_density_w<N1, N2, BTD, CPW, float2>, "k_density_w32", WD::bytes(), wgrid, WD::NT,
-                                st, a, t);
+                launch_with_lds(k_density_w<N1, N2, BTD, CPW32, float2, NBUF32, MINW32>, "k_density_w32",
+                                WD::bytes(), wgrid, WD::NT, st, a, t);
             } else {
                 TM_LAUNCH((k_fields_w<N1, N2, float2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                           a.vrs, a.W, t.perm1, t.perm2, a.fields32, a.n3, a.wstride, a.fstride);
-                launch_with_lds(k_apply_w<N1, N2, BTA, CPW, float2>, "k_apply_w32", WA::bytes(), wgrid, WA::NT, st,
-                                a, t);
+                launch_with_lds(k_apply_w<N1, N2, BTA, CPW32, float2, NBUF32, MINW32>, "k_apply_w32", WA::bytes(),
+                                wgrid, WA::NT, st, a, t);
             }
             return;
         }
-        using WD = WaveKernel<N1, N2, BTD, CPW, double2>;
-        using WA = WaveKernel<N1, N2, BTA, CPW, double2>;
+        using WD = WaveKernel<N1, N2, BTD, CPW, double2, NBUF>;
+        using WA = WaveKernel<N1, N2, BTA, CPW, double2, NBUF>;
         if (op == kOpDensity) {
-            launch_with_lds(k_density_w<N1, N2, BTD, CPW, double2>, "k_density_w", WD::bytes(), wgrid, WD::NT, st, a,
-                            t);
+            launch_with_lds(k_density_w<N1, N2, BTD, CPW, double2, NBUF, MINW>, "k_density_w", WD::bytes(), wgrid,
+                            WD::NT, st, a, t);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                       a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
-            launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2>, "k_apply_w", WA::bytes(), wgrid, WA::NT, st, a, t);
+            launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2, NBUF, MINW>, "k_apply_w", WA::bytes(), wgrid,
+                            WA::NT, st, a, t);
         }
     } else {
         TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision plane kernels need the resident ground state");
