@@ -296,7 +296,7 @@ def run_serving(args, tm, torch):
                                       omega=omega, eta=eta, arrival=float(t[i])))
             return out
         log(f"rate {rate}/s: {args.requests} requests, batched server")
-        server = sv.Server(slots, budget_bytes=32 << 30, lanes=args.serving_lanes)
+        server = sv.Server(slots, budget_bytes=32 << 30, lanes=args.serving_lanes, max_chains=args.serving_max_chains)
         batched = server.run(make())
         log(f"rate {rate}/s: one at a time")
         plain = sv.run_one_at_a_time(slots, make())
@@ -326,7 +326,7 @@ def run_serving(args, tm, torch):
         "config": {"workload": "serving: pool 20^3/8/1k, 24^3/16/4k, 32^3/32/9k (cubic a=10 bohr), 4:2:1, "
                                "500..3000 steps, pH|nH, x|y|z|+|-, chi on 400 omega",
                    "rates_per_s": [r["rate_per_s"] for r in results], "requests_per_rate": args.requests,
-                   "lanes_per_chain_max": args.serving_lanes},
+                   "lanes_per_chain_max": args.serving_lanes, "chains_per_system_max": args.serving_max_chains},
         "per_rate": results,
         "chi_max_rel_diff_batched_vs_alone": maxdiff,
     }
@@ -346,6 +346,8 @@ def main():
     ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
     ap.add_argument("--serving-lanes", type=int, default=4, choices=[1, 2, 3, 4],
                     help="serving: pending requests of one system, q set and flavour share a chain (lanes)")
+    ap.add_argument("--serving-max-chains", type=int, default=4,
+                    help="serving: chains per system at a time (0: no limit); later requests wait and form lanes")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--tensor", default="",
                     help="hexslab/cubic20: field directions run together as lanes of one chain "

@@ -96,11 +96,15 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
 // The same contraction with both operands of a K-chunk staged in LDS: one
 // block per (batch, K split) computes every 16x16 output tile from LDS (waves
 // take tiles in turn), so each operand element is read from memory once
-// instead of once per output tile.  Needs M, Nn <= 16 * kMaxTiles1D.
+// instead of once per output tile.  The next chunk's loads are issued before
+// the current chunk's products, so memory latency hides behind the MFMAs.
+// Needs M, Nn <= 16 * kMaxTiles1D.
 constexpr int kCnThreads = 512;
 constexpr int kCnChunk = 16;          // K values per LDS chunk
 constexpr int kMaxTiles1D = 14;       // M, Nn up to 224
 constexpr int kCnTilesPerWave = 7;    // (mt * nt) / 8 waves, at most
+constexpr int kCnMaxTilesSum = 16;   // mt + nt, at most
+constexpr int kCnStage = kCnMaxTilesSum * 16 * kCnChunk / kCnThreads;  // staged elements per thread
 
 template <class R>
 struct LdsC {
@@ -127,19 +131,38 @@ __global__ void __launch_bounds__(kCnThreads) k_gemm_cn_lds(GemmCN g, int mt) {
         cr[t] = typename MF<R>::V{0, 0, 0, 0};
         ci[t] = typename MF<R>::V{0, 0, 0, 0};
     }
-    for (int k0 = kbeg; k0 < kend; k0 += kCnChunk) {
-        // stage A[0..Mp)[k0..k0+16) and B[0..Np)[k0..k0+16); rows past M / Nn and k past K read as zero
-        for (int e = threadIdx.x; e < (Mp + Np) * kCnChunk; e += kCnThreads) {
+    // A[0..Mp)[k0..k0+16) and B[0..Np)[k0..k0+16) of one chunk, kCnStage
+    // elements per thread; rows past M / Nn and k past the range read as zero
+    const int nst = (Mp + Np) * kCnChunk;
+    double2 stage[kCnStage];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int j = 0; j < kCnStage; ++j) {
+            const int e = threadIdx.x + j * kCnThreads;
             const int row = e / kCnChunk, kx = k0 + (e - row * kCnChunk);
             const bool isA = row < Mp;
             const int r = isA ? row : row - Mp;
             double2 v = cmk(0.0, 0.0);
-            if (kx < kend && (isA ? r < g.M : r < g.Nn))
+            if (e < nst && kx < kend && (isA ? r < g.M : r < g.Nn))
                 v = isA ? A[(long long)r * g.lda + kx] : B[(long long)r * g.ldb + kx];
-            LdsC<R>* dst = isA ? As : Bs;
-            dst[r * LS + (e - row * kCnChunk)] = LdsC<R>{(R)v.x, (R)v.y};
+            stage[j] = v;
+        }
+    };
+    fetch(kbeg);
+    for (int k0 = kbeg; k0 < kend; k0 += kCnChunk) {
+#pragma unroll
+        for (int j = 0; j < kCnStage; ++j) {
+            const int e = threadIdx.x + j * kCnThreads;
+            if (e < nst) {
+                const int row = e / kCnChunk;
+                const bool isA = row < Mp;
+                const int r = isA ? row : row - Mp;
+                LdsC<R>* dst = isA ? As : Bs;
+                dst[r * LS + (e - row * kCnChunk)] = LdsC<R>{(R)stage[j].x, (R)stage[j].y};
+            }
         }
         __syncthreads();
+        if (k0 + kCnChunk < kend) fetch(k0 + kCnChunk);  // in flight during the products below
 #pragma unroll
         for (int t = 0; t < kCnTilesPerWave; ++t) {
             const int tile = w + 8 * t;
@@ -197,11 +220,14 @@ struct GemmUpd {
     int nk;
 };
 
+// One block per 16 rows k of A and batch; its waves take the 16-wide tiles of
+// n, so that the A rows are fetched once (into one XCD's L2 and the CU's L1)
+// for all of them.
 template <class R>
-__global__ void __launch_bounds__(64) k_gemm_update(GemmUpd g) {
+__global__ void __launch_bounds__(1024) k_gemm_update(GemmUpd g) {
     const int b = blockIdx.z;
-    const int n0 = blockIdx.x * 16, k0 = blockIdx.y * 16;
-    const int l = threadIdx.x, i = l & 15, kk = l >> 4;
+    const int n0 = (threadIdx.x >> 6) * 16, k0 = blockIdx.y * 16;
+    const int l = threadIdx.x & 63, i = l & 15, kk = l >> 4;
     const int bt = b % (2 * g.nk);
     const double2* A = g.A_tab[bt];
     const double2* C = g.C_base + (long long)b * g.c_bstride;
@@ -251,7 +277,8 @@ __global__ void k_dmat(const double2* Bm, const double2* D, double2* Wm, int npr
 // keep its 8 waves busy (single-tile products stay on k_gemm_cn)
 bool cn_lds_fits(int M, int Nn) {
     const int mt = (M + 15) / 16, nt = (Nn + 15) / 16;
-    return mt <= kMaxTiles1D && nt <= kMaxTiles1D && mt * nt <= 8 * kCnTilesPerWave && mt * nt >= 8;
+    return mt <= kMaxTiles1D && nt <= kMaxTiles1D && mt + nt <= kCnMaxTilesSum && mt * nt <= 8 * kCnTilesPerWave &&
+           mt * nt >= 8;
 }
 
 // K range per block: about 4 blocks per CU over all batches, a multiple of the LDS chunk
@@ -342,11 +369,13 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
     g.os_x = osx;
     g.os_y = osy;
     g.nk = nk;
-    dim3 grid((Nout + 15) / 16, (K + 15) / 16, 2 * nk * nrhs);
+    const int ntile = (Nout + 15) / 16;
+    TM_CHECK(ntile <= 16, TM_EUNSUPPORTED, "more than 256 output columns per batch");
+    dim3 grid(1, (K + 15) / 16, 2 * nk * nrhs);
     if (f32) {
-        TM_LAUNCH(k_gemm_update<float>, grid, dim3(64), 0, st, g);
+        TM_LAUNCH(k_gemm_update<float>, grid, dim3(64 * ntile), 0, st, g);
     } else {
-        TM_LAUNCH(k_gemm_update<double>, grid, dim3(64), 0, st, g);
+        TM_LAUNCH(k_gemm_update<double>, grid, dim3(64 * ntile), 0, st, g);
     }
 }
 

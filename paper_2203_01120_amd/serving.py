@@ -78,7 +78,7 @@ class Server:
     PERIOD = {"pH": 6, "nH": 3}
 
     def __init__(self, systems: Dict[str, SystemSlot], budget_bytes: int, rounds_per_sync: int = 1,
-                 lanes: int = 4, lane_slack: float = 1.25):
+                 lanes: int = 4, lane_slack: float = 1.25, max_chains: int = 0):
         import torch
         self.torch = torch
         self.systems = systems
@@ -92,6 +92,9 @@ class Server:
         self.rounds_per_sync = rounds_per_sync
         self.lanes = max(1, min(4, int(lanes)))
         self.lane_slack = lane_slack         # longest / shortest request of one chain, at most
+        # chains per system at a time (0: no limit); requests beyond it wait and
+        # are admitted together as the lanes of a later chain
+        self.max_chains = int(max_chains)
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -126,14 +129,21 @@ class Server:
         return group
 
     def _admit(self) -> None:
-        while self.pending:
-            head = self.pending.popleft()
-            group = self._group(head)
+        """FIFO over the pending requests, skipping systems at their chain limit;
+        stops at the first chain that does not fit the memory budget."""
+        i = 0
+        while i < len(self.pending):
+            head = self.pending[i]
             slot = self.systems[head.system]
+            if self.max_chains and len(slot.active) >= self.max_chains:
+                i += 1
+                continue
+            del self.pending[i]
+            group = self._group(head)
             cap = max(r.nsteps for r in group)
             nb = self._bytes(group)
             if self.used + nb > self.budget and self.used > 0:
-                self.pending.appendleft(head)
+                self.pending.insert(i, head)
                 return
             for r in group[1:]:
                 self.pending.remove(r)

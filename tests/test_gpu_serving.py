@@ -38,15 +38,16 @@ def requests(sv, omega, eta, stagger):
                        arrival=stagger * i) for i, (s, d, f, m) in enumerate(spec)]
 
 
-@pytest.mark.parametrize("stagger,lanes,slack", [(0.0, 1, 1.0), (0.02, 1, 1.0), (0.0, 4, 2.0)])
-def test_server_chi_identical_to_alone(pool, stagger, lanes, slack):
+@pytest.mark.parametrize("stagger,lanes,slack,cap", [(0.0, 1, 1.0, 0), (0.02, 1, 1.0, 0), (0.0, 4, 2.0, 0),
+                                                     (0.0, 4, 4.0, 1)])
+def test_server_chi_identical_to_alone(pool, stagger, lanes, slack, cap):
     tm, sv, slots = pool
     omega = np.linspace(0.0, 0.07, 64)
     eta = 2e-4
     # a budget of about two cubic20 chains forces admissions to wait
     budget = 2 * sv.chain_bytes(slots["cubic20"].nelem[0], "nH", 30)
-    say(f"server run, stagger {stagger}, lanes {lanes}, budget {budget} B")
-    server = sv.Server(slots, budget_bytes=budget, lanes=lanes, lane_slack=slack)
+    say(f"server run, stagger {stagger}, lanes {lanes}, chains per system {cap}, budget {budget} B")
+    server = sv.Server(slots, budget_bytes=budget, lanes=lanes, lane_slack=slack, max_chains=cap)
     peak = [0]
     widest = [1]
     orig = server._admit
@@ -55,6 +56,7 @@ def test_server_chi_identical_to_alone(pool, stagger, lanes, slack):
         orig()
         peak[0] = max(peak[0], server.used)
         for s in slots.values():
+            assert not cap or len(s.active) <= cap
             for a in s.active:
                 widest[0] = max(widest[0], len(a.reqs))
     server._admit = admit
