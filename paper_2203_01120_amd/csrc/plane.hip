@@ -1130,16 +1130,25 @@ void launch_z(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStre
     const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
     const size_t shm = (size_t)L * (N3 + 1) * esz + N3 * esz + N3 * sizeof(int);
     dim3 grid((ncolmax + CT - 1) / CT, (a.nitems + IT - 1) / IT, nbatch);
+    auto lds = [&](const void* fn) {  // above 64 KB the limit must be raised first
+        if (shm > 65536)
+            TM_CHECK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) == hipSuccess,
+                     TM_EDEVICE, "cannot raise the LDS limit of a z pass");
+    };
     if (fp32) {
         TM_CHECK(a.cols32 != nullptr && a.tw32 != nullptr, TM_EINVAL, "missing single-precision buffers");
         if (inverse) {
+            lds((const void*)k_zinv_t<N3, NT, CT, IT, float2>);
             TM_LAUNCH((k_zinv_t<N3, NT, CT, IT, float2>), grid, dim3(NT), shm, st, a);
         } else {
+            lds((const void*)k_zfwd_t<N3, NT, CT, IT, float2>);
             TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT, float2>), grid, dim3(NT), shm, st, a);
         }
     } else if (inverse) {
+        lds((const void*)k_zinv_t<N3, NT, CT, IT, double2>);
         TM_LAUNCH((k_zinv_t<N3, NT, CT, IT, double2>), grid, dim3(NT), shm, st, a);
     } else {
+        lds((const void*)k_zfwd_t<N3, NT, CT, IT, double2>);
         TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT, double2>), grid, dim3(NT), shm, st, a);
     }
 }

@@ -53,6 +53,21 @@ def test_extrapolated_chi_matches_oracle(cubic, mode):
     assert np.abs(got - G).max() <= 1e-8 * np.abs(G).max()
 
 
+def test_chi_tensor_extrapolated_matches_oracle(cubic):
+    """The 4 x 4 column (rows n, x, y, z) with the bi-constant extrapolation."""
+    tm, prob, h = cubic
+    say("chi tensor column, extrapolated")
+    c = tm.tm_lanczos_run(h, 0, "n", "pH", 40)
+    omega = np.arange(300) * 5e-3 / EV
+    eta = 5e-3 / EV
+    got = tm.tm_chi_tensor(c, 40, omega, eta, m_total=1000, mode="osc")
+    four = dict(c, z=np.vstack([c["zn"][None], c["z"]]))
+    ref = ochi.chi_lanczos(ochi.extrapolate(four, 40, 1000, "osc"), omega, eta, 1000)
+    assert rel_err(got, ref) <= 1e-12
+    with pytest.raises(tm.TmError):
+        tm.tm_chi_tensor(dict(c, zn=None), 40, omega, eta)
+
+
 def test_structure_factor_matches_oracle(cubic):
     tm, prob, h = cubic
     say("structure factor from three chains")

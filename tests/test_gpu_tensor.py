@@ -111,6 +111,30 @@ def test_tensor_run_equals_single_chains(lib, cubic, flavour, dirs, m):
     assert np.abs(got["zn"] - ref["z"][3]).max() <= 1e-10 * np.abs(ref["z"]).max()
 
 
+def test_fp32_lanes_equal_single_fp32_chains_and_restart(lib, cubic):
+    """Single-precision bulk with lanes: each lane equals its FP32 single chain, and a
+    saved FP32 chain restores as FP32."""
+    prob, h = cubic
+    say("fp32 tensor run and restart")
+    lanes = lib.tm_tensor_run(h, 0, ["x", "z"], "nH", 9, lib.TM_FP32)
+    for d, got in zip("xz", lanes):
+        same(got, lib.tm_lanczos_run(h, 0, d, "nH", 9, lib.TM_FP32))
+    c = lib.tm_chain_begin_multi(h, 0, ["x", "z"], "nH", 3, lib.TM_FP32)
+    try:
+        lib.tm_chains_step([c], 3)
+        blob = lib.tm_chain_save(c)
+    finally:
+        lib.tm_chain_end(c)
+    c2 = lib.tm_chain_restore(h, blob, capacity=9)
+    try:
+        lib.tm_chains_step([c2], 9)
+        got = lib.tm_chain_coeffs_lanes(c2, 9)
+    finally:
+        lib.tm_chain_end(c2)
+    for a, b in zip(got, lanes):
+        same(a, b)
+
+
 def test_multi_chain_in_pieces_graphs_and_restart(lib, cubic):
     """A two-lane chain stepped in pieces (graph replay and direct steps), saved,
     restored with a larger capacity and run on equals one tensor run."""
