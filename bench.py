@@ -362,7 +362,7 @@ def main():
                     help="also run a plain device copy of known size (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}))
         raise SystemExit("bench.py supports --gpus 1 only: the hot path is built and measured on one GPU")
 
     import torch

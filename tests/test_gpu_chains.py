@@ -210,3 +210,29 @@ def test_chain_invalid_arguments(lib, systems):
         lib.tm_chain_begin(h, 3, "x", "pH", 5)
     with pytest.raises(lib.TmError):
         lib.tm_chain_begin(h, 0, "x", "pH", 5, prec=7)   # no such precision
+
+
+def test_degenerate_sizes(lib, systems):
+    """One-step chains, capacity 1 stepped past it, chi from one coefficient,
+    an empty frequency grid, a one-direction tensor run."""
+    prob, h = systems["cubic20"]
+    say("degenerate sizes")
+    for flavour in ("pH", "nH"):
+        one = lib.tm_lanczos_run(h, 0, "z", flavour, 1)
+        assert one["steps_done"] == 1
+        ref = olanczos.run(prob, "z", flavour, 1)
+        assert abs(one["alpha"][0] - ref["alpha"][0]) <= 1e-10 * abs(ref["alpha"][0])
+        c = lib.tm_chain_begin(h, 0, "z", flavour, 1)
+        try:
+            lib.tm_chains_step([c], 5)               # never past the capacity
+            got = lib.tm_chain_coeffs(c, 1)
+        finally:
+            lib.tm_chain_end(c)
+        same(got, one)
+        w = np.linspace(0.0, 0.1, 7)
+        chi1 = lib.tm_chi(one, 1, w, 1e-3)
+        # one coefficient: chi = n1 z_0 / (w + i eta - alpha_0)
+        expect = one["n1"] * one["z"][:, :1] / (w[None, :] + 1e-3j - one["alpha"][0])
+        assert np.abs(chi1 - expect).max() <= 1e-12 * np.abs(expect).max()
+        assert lib.tm_chi(one, 1, np.zeros(0), 1e-3).shape == (3, 0)
+        same(lib.tm_tensor_run(h, 0, ["z"], flavour, 1)[0], one)
