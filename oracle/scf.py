@@ -147,7 +147,10 @@ class GroundState:
 
 def initial_density(sysd, mfrac=(0.0, 0.0, 0.5)):
     g = synth.systems._image_sum(sysd, lambda r2, at: np.exp(-r2 / (2 * (1.5 * at.width) ** 2)))
-    n = 0.5 * g / (g.sum() * sysd.omega / sysd.ngrid) + 0.5 / sysd.omega
+    if g.sum() > 0:
+        n = 0.5 * g / (g.sum() * sysd.omega / sysd.ngrid) + 0.5 / sysd.omega
+    else:  # no atoms: start from the uniform density
+        n = np.full(g.shape, 1.0 / sysd.omega)
     n *= sysd.nbnd
     rho = np.zeros((4,) + n.shape)
     rho[0] = n

@@ -147,3 +147,25 @@ def test_kernel_isotropic_limit():
     f = xc.kernel(x)[:, :, 0]
     g = -(xc.CX / 3) * 0.1 ** (-2 / 3)
     assert np.allclose(f, np.diag([g / 2, g / 2, g / 2, g / 2]), rtol=1e-12)
+
+
+@pytest.mark.parametrize("nbnd,mfrac", [(1, (0.0, 0.0, 0.5)), (2, (0.0, 0.0, 0.0))])
+def test_scf_homogeneous_gas_limit(nbnd, mfrac):
+    """Without atoms the SCF ground state is the homogeneous electron gas: the
+    G = 0 plane wave(s), a uniform density N / Omega, and eigenvalue
+    v_sigma = -(6/pi)^(1/3) n_sigma^(1/3) (Slater exchange; Hartree vanishes for
+    a uniform density).  One electron ends fully polarised along the starting
+    moment; two unpolarised electrons fill both spins at the same energy."""
+    sd = synth.make_tiny(nat=0, nbnd=nbnd, fft=(8, 8, 8))
+    gs = scf.scf(sd, tol=1e-12, beta=0.5, mfrac=mfrac)
+    _, _, _, e = gs.mesh_states[0]
+    n_sigma = 1.0 / sd.omega                       # one electron per occupied spin channel
+    v = -(6.0 / np.pi) ** (1.0 / 3.0) * n_sigma ** (1.0 / 3.0)
+    assert np.allclose(gs.rho[0], nbnd / sd.omega, rtol=1e-12, atol=0)
+    assert np.allclose(e, v, rtol=1e-10, atol=0)
+    if nbnd == 1:
+        assert np.allclose(gs.rho[3], gs.rho[0], rtol=1e-12, atol=0)   # |m| = n along z
+        assert np.abs(gs.rho[1:3]).max() < 1e-14
+        assert abs(gs.gaps[0] + v) < 1e-5 * abs(v)     # the empty spin channel sits at v = 0
+    else:
+        assert np.abs(gs.rho[1:]).max() < 1e-14
