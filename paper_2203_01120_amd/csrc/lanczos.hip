@@ -90,15 +90,18 @@ __global__ void __launch_bounds__(kRedThreads) k_multidot(DotSet<ND> ds, long lo
         for (int d = 0; d < ND; ++d) part[(long long)blockIdx.x * ND + d] = acc[d];
 }
 
-// deterministic final sum of the block partials, times the 1/nk weight (lane blockIdx.x)
+// deterministic final sum of the block partials, times the 1/nk weight (lane
+// blockIdx.x): wave d sums value d, each of its lanes a fixed stride of blocks,
+// then the wave's lanes in a fixed tree
 __global__ void k_dot_final(const double2* part, int nblk, int nd, double w, double2* out) {
-    int d = threadIdx.x;
-    if (d >= nd) return;
+    const int d = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (d >= nd) return;  // whole waves
     part += (long long)blockIdx.x * nblk * nd;
     out += blockIdx.x * kDotStride;
     double2 s = cmk(0.0, 0.0);
-    for (int b = 0; b < nblk; ++b) s = cadd(s, part[(long long)b * nd + d]);
-    out[d] = cscale(s, w);
+    for (int b = l; b < nblk; b += 64) s = cadd(s, part[(long long)b * nd + d]);
+    s = wave_sum(s);
+    if (l == 0) out[d] = cscale(s, w);
 }
 
 // pH residual: r = slq Lq - alpha sq q - beta sprev qprev; partials of (u_l, r)
@@ -332,7 +335,7 @@ void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, d
                   hipStream_t st, int lanes) {
     int nblk = (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
     TM_LAUNCH(k_multidot<ND>, dim3(nblk, lanes), dim3(kRedThreads), 0, st, ds, n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64), 0, st, part, nblk, ND, w, out);
+    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * ND), 0, st, part, nblk, ND, w, out);
 }
 template void run_multidot<1>(const DotSet<1>&, long long, long long, double, double2*, double2*, hipStream_t,
                                   int);
@@ -353,7 +356,7 @@ void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, co
     int nblk = red_blocks(n);
     TM_LAUNCH(k_ph_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3], n,
               part);
-    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64), 0, st, part, nblk, kNMeasure, w, out);
+    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * kNMeasure), 0, st, part, nblk, kNMeasure, w, out);
 }
 
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
@@ -363,7 +366,7 @@ void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, co
     int nblk = red_blocks(n);
     TM_LAUNCH(k_nh_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0],
               u[1], u[2], u[3], n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64), 0, st, part, nblk, 3 + kNMeasure, w, out);
+    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * (3 + kNMeasure)), 0, st, part, nblk, 3 + kNMeasure, w, out);
 }
 
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes) {

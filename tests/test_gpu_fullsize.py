@@ -1,0 +1,111 @@
+"""The benchmark system at full size (48 x 48 x 180 grid, 104 bands, 36 k
+points), in the launch configuration the benchmark times (resident ground
+state, wave plane kernels, LDS-staged contractions).  The oracle cannot apply
+L at this size, so the checks are properties that hold at any size:
+
+* JL is Hermitian: (a, J L b) = conj((b, J L a)) for projected a, b; FP64
+  sums over 1.9e8 elements, so 1e-11 relative.
+* Linearity: L(a + 2 b) = L a + 2 L b to 1e-12 relative.
+* The chain start: the library's alpha_0 = (Lv, J Lv) / (v, J Lv) for the
+  start vector v equals the same ratio formed with torch (1e-10).
+* Several right-hand sides in one pass equal single applies bit for bit, and
+  lanes of a chain equal single chains bit for bit.
+* FP32 bulk stays within 2e-5 of the FP64 apply (the bound of the FP32 tests).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def slab():
+    import torch
+    import paper_2203_01120_amd as tm
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    tm.load()
+    sys.path.insert(0, ROOT)
+    import bench
+    say("full-size slab: building inputs")
+    inp = bench.build_inputs("hexslab", 1)
+    say("full-size slab: creating the system")
+    h = tm.tm_system_create(bench.make_desc(inp))
+    info = tm.tm_qset_info_get(h, 0)
+    yield tm, h, info
+    tm.tm_system_destroy(h)
+
+
+def jdot(a, b, half):
+    """(a, J b) with J = diag(1, -1) over the two sides (weights cancel in ratios)."""
+    import torch
+    return (torch.vdot(a[:half], b[:half]) - torch.vdot(a[half:], b[half:])).item()
+
+
+def test_fullsize_apply_properties(slab):
+    import torch
+    tm, h, info = slab
+    n = info["nelem"]
+    half = n // 2
+    g = torch.Generator(device="cuda").manual_seed(11)
+    say("full-size slab: projected random vectors")
+    raw = torch.randn(2 * n, dtype=torch.complex128, device="cuda", generator=g)
+    ab = torch.empty_like(raw)
+    tm.tm_liouvillian_apply_multi(h, 0, 2, raw, ab)        # outputs of L are projected
+    ab /= ab.abs().max()
+    a, b = ab[:n], ab[n:]
+    say("full-size slab: L a, L b (batched and single)")
+    lab = torch.empty_like(ab)
+    tm.tm_liouvillian_apply_multi(h, 0, 2, ab, lab)
+    la = torch.empty_like(a)
+    lb = torch.empty_like(b)
+    tm.tm_liouvillian_apply(h, 0, a, la)
+    tm.tm_liouvillian_apply(h, 0, b, lb)
+    torch.cuda.synchronize()
+    assert torch.equal(lab[:n], la) and torch.equal(lab[n:], lb)
+    say("full-size slab: JL Hermitian")
+    x, y = jdot(a, lb, half), np.conj(jdot(b, la, half))
+    assert abs(x - y) <= 1e-11 * max(abs(x), abs(y)), (x, y)
+    say("full-size slab: linearity")
+    c = a + 2.0 * b
+    lc = torch.empty_like(c)
+    tm.tm_liouvillian_apply(h, 0, c, lc)
+    torch.cuda.synchronize()
+    ref = la + 2.0 * lb
+    assert ((lc - ref).abs().max() / ref.abs().max()).item() <= 1e-12
+    say("full-size slab: FP32 bulk")
+    l32 = torch.empty_like(a)
+    tm.tm_liouvillian_apply(h, 0, a, l32, tm.TM_FP32)
+    torch.cuda.synchronize()
+    assert ((l32 - la).abs().max() / la.abs().max()).item() <= 2e-5
+
+
+def test_fullsize_chain_start_matches_torch(slab):
+    import torch
+    tm, h, info = slab
+    n = info["nelem"]
+    say("full-size slab: chain start")
+    v = torch.empty(n, dtype=torch.complex128, device="cuda")
+    tm.tm_start_vectors(h, 0, "+", None, v)           # v = P sigma^+ U
+    lv = torch.empty_like(v)
+    tm.tm_liouvillian_apply(h, 0, v, lv)
+    co = tm.tm_lanczos_run(h, 0, "+", "pH", 1)
+    torch.cuda.synchronize()
+    a0 = jdot(lv, lv, half=n // 2) / jdot(v, lv, half=n // 2)
+    assert abs(co["alpha"][0] - a0) <= 1e-10 * abs(a0)
+
+
+def test_fullsize_lanes_equal_single_chains(slab):
+    tm, h, info = slab
+    say("full-size slab: two-lane chain vs single chains (2 steps)")
+    lanes = tm.tm_tensor_run(h, 0, ["+", "z"], "pH", 2)
+    for d, got in zip("+z", lanes):
+        ref = tm.tm_lanczos_run(h, 0, d, "pH", 2)
+        for k in ("alpha", "beta", "gamma", "z", "zn"):
+            assert np.array_equal(got[k], ref[k]), (d, k)
