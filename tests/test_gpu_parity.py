@@ -110,6 +110,32 @@ def test_apply_generic_plane_path(lib):
         s.close()
 
 
+def test_apply_many_bands_staged_contractions(lib):
+    """48 bands: the projector contractions have 3 x 3 output tiles, enough for
+    the LDS-staged kernel the benchmark system runs; synthetic occupied
+    manifold (no SCF), 24^3 grid."""
+    say("apply cubic24, 48 bands (staged contractions)")
+    sd = synth.make_cubic(24, 48, 1)
+    inp = synth.synthetic_inputs(sd, np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0, seed=3)
+
+    class _GS:
+        pass
+    gs = _GS()
+    gs.sysd, gs.vrs, gs.rho = inp["sysd"], inp["vrs"], inp["rho"]
+    prob = lv.Problem(gs, inp["qset"], point_states=[(m, e, et) for (_, m, e, et, _) in inp["points"]])
+    s = Sys(lib, prob)
+    try:
+        for seed in (1, 2):
+            x = prob.random_projected(seed)
+            got, _ = s.apply(x)
+            assert rel_err(got, prob.apply(x)) <= 1e-12
+        got = lib.tm_lanczos_run(s.h, 0, "z", "pH", 12)
+        ref = olanczos.run(prob, "z", "pH", 12)
+        assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
+    finally:
+        s.close()
+
+
 def test_apply_two_kpoints_folded(lib):
     """Two-point mesh, q on the mesh: sister points folded with Miller shifts."""
     import synth
