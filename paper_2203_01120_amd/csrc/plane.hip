@@ -417,12 +417,22 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
     }
 }
 
-// Resident real-space ground state: [slot][band][i3][spin][plane point], the
-// plane points in column-major order of the LDS positions (p1 fastest,
-// p1 and p2 digit-reversed), time reversal applied on the y side.
-__device__ __forceinline__ const double2* ureal_plane(const PlaneArgs& a, int b, int n, int i3) {
-    return a.ureal + (((long long)a.uslot[b] * a.nb + n) * a.n3 + i3) * 2 * a.NP;
+// Point order of a plane in the resident ground state, the per-apply field
+// table and the wave kernels' point-wise phases: column-major over the LDS
+// positions (p1, p2 digit-reversed), and within a column the row p1 = R blk + t
+// (R the last radix of n1's plan) at r = t (n1 / R) + blk.  The last column
+// stage works on butterflies of R consecutive rows, one per lane, so the lanes
+// of a column read consecutive points of this order.
+template <int N1>
+__device__ __forceinline__ int wrow(int r) {
+    constexpr CPlan cp = cplan(N1);
+    constexpr int R = cp.rad[cp.nrad - 1], BPC = N1 / R;
+    const int t = r / BPC, blk = r - t * BPC;
+    return blk * R + t;
 }
+
+// Resident real-space ground state: [slot][band][i3][spin][plane point], the
+// points in the order above, time reversal applied on the y side.
 
 template <int N1, int N2, int NT>
 __global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
@@ -440,7 +450,7 @@ __global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
         K::inverse(m, a, b, b, n, i3, R);
         double2* out = a.ureal + (((long long)a.uslot[b] * a.nb + n) * a.n3 + i3) * 2 * G::NP;
         for (int idx = threadIdx.x; idx < G::NP; idx += NT) {
-            const int p2 = idx / N1, p1 = idx - p2 * N1;
+            const int p2 = idx / N1, p1 = wrow<N1>(idx - p2 * N1);
             const int o = p1 * G::N2P + p2;
             double2 uu = pl[o], ud = pl[G::PS + o];
             if (yside) time_reverse(uu, ud);
@@ -556,7 +566,7 @@ __device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const WTw<N, 
                 const int blk = r0 / M;
                 const int j = r0 - blk * M;
                 const int e0 = blk * LB + j;
-                const int bs = L.base(li) + e0 * ES;
+                const int bs = L.base(li, g0 + it) + e0 * ES;
                 base[it] = bs;
                 jv[it] = j;
 #pragma unroll
@@ -592,13 +602,15 @@ __device__ __forceinline__ void wpass(T2* pl, const WL& L, int nl, const WTw<N, 
     wave_sync();
 }
 
-template <int N, int SIGN, bool MASKED, int MAXL, int BT, int STAGE = 0, int LB = N, class WL, class T2>
+// stages 0 .. NST - 1 of the plan
+template <int N, int SIGN, bool MASKED, int MAXL, int BT, int NST = cplan(N).nrad, int STAGE = 0, int LB = N, class WL,
+          class T2>
 __device__ __forceinline__ void wfft_dif(T2* pl, const WL& L, int nl, const WTw<N, T2>& tw, int lane) {
     constexpr CPlan cp = cplan(N);
-    if constexpr (STAGE < cp.nrad) {
+    if constexpr (STAGE < NST) {
         constexpr int R = cp.rad[STAGE];
         wpass<N, STAGE, R, LB, SIGN, true, MASKED && STAGE == 0, MAXL, BT>(pl, L, nl, tw, lane);
-        wfft_dif<N, SIGN, MASKED, MAXL, BT, STAGE + 1, LB / R>(pl, L, nl, tw, lane);
+        wfft_dif<N, SIGN, MASKED, MAXL, BT, NST, STAGE + 1, LB / R>(pl, L, nl, tw, lane);
     }
 }
 
@@ -613,13 +625,44 @@ __device__ __forceinline__ void wfft_dit(T2* pl, const WL& L, int nl, const WTw<
     }
 }
 
-// row lines w, w + NW, ... of the block's row table
-template <int NW>
+// true when every stage of a length-n transform gives a line the same lane
+// slots, a divisor of 64: a lane then works on the same lines in every stage
+constexpr bool rows_fixed(int n) {
+    const CPlan p = cplan(n);
+    const int s0 = wslots(n / p.rad[0]);
+    if (64 % s0 != 0) return false;
+    for (int s = 1; s < p.nrad; ++s)
+        if (wslots(n / p.rad[s]) != s0) return false;
+    return true;
+}
+
+// row lines w, w + NW, ... of the block's row table (nl of them).  With
+// rows_fixed(N) the bases of the lane's lines are read from the table once,
+// into registers (the table does not change within a block), so that a
+// stage's loads do not wait on a dependent table read.
+template <int NW, int N, int MAXL, bool CACHE>
 struct WRows {
     static constexpr int ES = 1;
+    static constexpr bool kFix = CACHE && rows_fixed(N);
+    static constexpr int SPL = wslots(N / cplan(N).rad[0]);
+    static constexpr int IT = kFix ? cdiv(MAXL * SPL, 64) : 1;
     const int* rowbase;
     int w, boff;
-    __device__ int base(int li) const { return boff + rowbase[w + li * NW]; }
+    int lb[IT];
+    __device__ WRows(const int* rb, int w_, int nl, int lane) : rowbase(rb), w(w_), boff(0) {
+        if constexpr (kFix) {
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                const int li = (lane + 64 * it) / SPL;
+                lb[it] = li < nl ? rb[w + li * NW] : 0;
+            }
+        }
+    }
+    // line li, met in the lane's iteration it of a stage
+    __device__ int base(int li, int it) const {
+        if constexpr (kFix) return boff + lb[it];
+        else return boff + rowbase[w + li * NW];
+    }
     __device__ bool valid(int) const { return true; }
 };
 
@@ -630,14 +673,40 @@ struct WCols {
     static constexpr int ES = Geom<N1, N2>::N2P;
     int c0, boff;
     unsigned long long mask;
-    __device__ int base(int li) const {
+    __device__ int base(int li, int) const {
         const int s = li / CPW;
         return boff + s * Geom<N1, N2>::PS + c0 + (li - s * CPW);
     }
     __device__ bool valid(int row) const { return (mask >> row) & 1ULL; }
 };
 
-template <int N1, int N2, int BT_, int CPW_, class T2, int NBUF_>
+// The last column stage of the inverse transform (radix R, butterflies of R
+// consecutive rows, no twiddles) and the first of the forward one, fused with
+// the point-wise work in registers: slot sl of a wave's CPW n1 / R butterflies
+// holds rows R blk .. R blk + R - 1 of column cc in both spin planes.
+template <int N1, int N2, int CPW>
+struct WTail {
+    static constexpr CPlan cp = cplan(N1);
+    static constexpr int R = cp.rad[cp.nrad - 1];
+    static constexpr int BPC = N1 / R;        // butterflies per column
+    static constexpr int SLOTS = CPW * BPC;
+    static constexpr int IT = cdiv(SLOTS, 64);
+    static_assert(cp.nrad >= 2, "the first column stage reads the row mask");
+    int lo[IT];   // LDS offset (plane 0) of the slot's first row
+    int lq[IT];   // wave point of the slot's first row; row t at lq + t BPC
+    __device__ void init(int w, int lane) {
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int sl = min(lane + 64 * i, SLOTS - 1);
+            const int cc = sl / BPC, blk = sl - cc * BPC;
+            lo[i] = blk * R * Geom<N1, N2>::N2P + w * CPW + cc;
+            lq[i] = cc * N1 + blk;
+        }
+    }
+    __device__ static bool live(int lane, int i) { return lane + 64 * i < SLOTS; }
+};
+
+template <int N1, int N2, int BT_, int CPW_, class T2, int NBUF_, int FCH_ = 64>
 struct WaveKernel {
     using G = Geom<N1, N2>;
     static constexpr int NBUF = NBUF_;              // LDS buffers alternating between bands (1 or 2)
@@ -645,7 +714,6 @@ struct WaveKernel {
     static constexpr int NW = N2 / CPW;             // waves
     static constexpr int NT = 64 * NW;
     static constexpr int WPTS = CPW * N1;           // points of a wave (per plane)
-    static constexpr int PPL = cdiv(WPTS, 64);      // points per lane
     static constexpr int MAXR = cdiv(2 * N1, NW);   // row lines of a wave, at most
     static constexpr int BUF = 2 * G::PS;           // one buffer: planes x_up, x_dn
     static constexpr int BT = BT_;                  // butterflies per load group
@@ -694,40 +762,85 @@ struct WaveKernel {
     // row lines of wave w among nrl
     __device__ static int wave_rows(int nrl, int w) { return w < nrl ? (nrl - 1 - w) / NW + 1 : 0; }
 
+    static constexpr int FIT = cdiv(MAXR * N2, 64);  // row elements per lane, at most
+    static constexpr int FCH = FCH_ < FIT ? FCH_ : FIT;  // of them in flight together
+    using Rows = WRows<NW, N2, MAXR, (FCH > 1)>;        // line bases in registers with FCH > 1
+
+    // row element k = lane + 64 it of the wave: LDS offset within a buffer, and
+    // sphere column (spin plane s, column c; c < 0 outside the sphere)
+    __device__ static bool row_elem(const Smem& m, int nlw, int w, int lane, int it, int& dst, int& s, int& c) {
+        const int k = lane + 64 * it;
+        if (k >= nlw * N2) return false;
+        const int li = k / N2, p2 = k - li * N2;
+        const int l = w + li * NW;
+        const int info = m.rowinfo[l];
+        s = info / N1;
+        const int row = info - s * N1;
+        c = m.colidx[row * N2 + p2];
+        dst = m.rowbase[l] + p2;
+        return true;
+    }
+
     // fill the wave's occupied rows of buffer boff from the z-transformed
-    // columns of item pair (2n, 2n+1), then the inverse transforms along i2
+    // columns of item pair (2n, 2n+1), then the inverse transforms along i2.
+    // FCH > 1: the table reads and column loads of FCH elements are issued
+    // before their LDS stores, so that a lane's elements do not wait on each
+    // other (more registers); FCH = 1: one element at a time.
     __device__ static void rows_inverse(const Smem& m, const T2* cx, long long cs, int nlw, int w, int boff,
-                                        int lane, const WTw<N2, T2>& gtw2) {
+                                        int lane, const WTw<N2, T2>& gtw2, Rows rl) {
+        if constexpr (FCH == 1) {
+            for (int k = lane; k < nlw * N2; k += 64) {
+                const int li = k / N2, p2 = k - li * N2;
+                const int l = w + li * NW;
+                const int info = m.rowinfo[l];
+                const int s = info / N1, row = info - s * N1;
+                const int c = m.colidx[row * N2 + p2];
+                m.pl[boff + m.rowbase[l] + p2] = c >= 0 ? cx[s * cs + c] : Cx<T2>::mk(0, 0);
+            }
+        } else {
+#pragma unroll
+            for (int i0 = 0; i0 < FIT; i0 += FCH) {
+                T2 v[FCH];
+                int dst[FCH];
+#pragma unroll
+                for (int i = 0; i < FCH; ++i) {
+                    int s, c;
+                    v[i] = Cx<T2>::mk(0, 0);
+                    dst[i] = -1;
+                    if (i0 + i < FIT && row_elem(m, nlw, w, lane, i0 + i, dst[i], s, c) && c >= 0)
+                        v[i] = cx[s * cs + c];
+                }
+#pragma unroll
+                for (int i = 0; i < FCH; ++i)
+                    if (dst[i] >= 0) m.pl[boff + dst[i]] = v[i];
+            }
+        }
+        wave_sync();
+        rl.boff = boff;
+        wfft_dif<N2, +1, false, MAXR, BT>(m.pl, rl, nlw, gtw2, lane);
+    }
+
+    // the sphere columns of the wave's rows of buffer boff, to co
+    __device__ static void rows_out(const Smem& m, T2* co, long long cs, int nlw, int w, int boff, int lane) {
         for (int k = lane; k < nlw * N2; k += 64) {
             const int li = k / N2, p2 = k - li * N2;
             const int l = w + li * NW;
             const int info = m.rowinfo[l];
             const int s = info / N1, row = info - s * N1;
             const int c = m.colidx[row * N2 + p2];
-            m.pl[boff + m.rowbase[l] + p2] = c >= 0 ? cx[s * cs + c] : Cx<T2>::mk(0, 0);
+            if (c >= 0) co[s * cs + c] = m.pl[boff + m.rowbase[l] + p2];
         }
-        wave_sync();
-        WRows<NW> rl{m.rowbase, w, boff};
-        wfft_dif<N2, +1, false, MAXR, BT>(m.pl, rl, nlw, gtw2, lane);
     }
 };
 
-// the lane's points of wave w: LDS offset (within a buffer's plane 0), and
-// natural grid index in the plane
-template <int N1, int N2, int CPW>
-__device__ __forceinline__ void wave_point(int w, int q, const int* perm1, const int* perm2, int& o, int& g) {
-    const int cc = q / N1, p1 = q - cc * N1;
-    const int p2 = w * CPW + cc;
-    o = p1 * Geom<N1, N2>::N2P + p2;
-    g = perm1[p1] * N2 + perm2[p2];
-}
-
-// MINW: waves per SIMD the register allocation must leave room for
-template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW>
+// MINW: waves per SIMD the register allocation must leave room for; FCH: row
+// elements per lane whose loads are in flight together
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF>;
+    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH>;
     using G = typename K::G;
-    constexpr int PPL = K::PPL;
+    using TL = WTail<N1, N2, CPW>;
+    constexpr int R = TL::R, IT = TL::IT;
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     const T2* xcols = pick<T2>(a.xcols, a.xcols32);
@@ -746,44 +859,55 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a
     const long long cs = (long long)a.n3 * a.ncol_max;
     // the side's resident slot, read once (the loop's stores could alias it)
     const double2* ub = a.ureal + (long long)a.uslot[bt] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
-    int o[PPL];
-#pragma unroll
-    for (int j = 0; j < PPL; ++j) {
-        int g;
-        wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
-    }
-    T2 acc[4][PPL];
+    TL tl;
+    tl.init(w, lane);
+    const typename K::Rows rl(m.rowbase, w, nlw, lane);
+    T2 acc[4][IT][R];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) acc[c][j] = Cx<T2>::mk(0, 0);
+        for (int i = 0; i < IT; ++i)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[c][i][r] = Cx<T2>::mk(0, 0);
     for (int n = n0; n < n1e; ++n) {
         const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
-        T2 uu[PPL], ud[PPL];
-#pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            const int q = lane + 64 * j;
-            if (q < K::WPTS) {
-                uu[j] = Cx<T2>::from(ur[q]);
-                ud[j] = Cx<T2>::from(ur[G::NP + q]);
-            }
-        }
-        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2);
+        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
         __syncthreads();
-        WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
-        wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, tw1, lane);
+        // the band's ground state, in flight during the column stages
+        T2 uu[IT][R], ud[IT][R];
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            if (lane + 64 * j < K::WPTS) {
-                const T2 xu = m.pl[boff + o[j]], xd = m.pl[boff + G::PS + o[j]];
-                const T2 uu_xu = cmulc(uu[j], xu), ud_xd = cmulc(ud[j], xd);
-                const T2 uu_xd = cmulc(uu[j], xd), ud_xu = cmulc(ud[j], xu);
-                acc[0][j] = cadd(acc[0][j], cadd(uu_xu, ud_xd));
-                acc[1][j] = cadd(acc[1][j], cadd(uu_xd, ud_xu));
-                acc[2][j] = cadd(acc[2][j], cmuli(csub(ud_xu, uu_xd)));
-                acc[3][j] = cadd(acc[3][j], csub(uu_xu, ud_xd));
+        for (int i = 0; i < IT; ++i)
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                uu[i][r] = Cx<T2>::from(ur[tl.lq[i] + r * TL::BPC]);
+                ud[i][r] = Cx<T2>::from(ur[G::NP + tl.lq[i] + r * TL::BPC]);
+            }
+        WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
+        wfft_dif<N1, +1, true, 2 * CPW, K::BT, TL::cp.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
+        // last inverse stage in registers, then the four density components
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            if (TL::live(lane, i)) {
+                const T2* px = m.pl + boff + tl.lo[i];
+                T2 xu[R], xd[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    xu[r] = px[r * G::N2P];
+                    xd[r] = px[G::PS + r * G::N2P];
+                }
+                dft_small<R>(xu, +1);
+                dft_small<R>(xd, +1);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const T2 uu_xu = cmulc(uu[i][r], xu[r]), ud_xd = cmulc(ud[i][r], xd[r]);
+                    const T2 uu_xd = cmulc(uu[i][r], xd[r]), ud_xu = cmulc(ud[i][r], xu[r]);
+                    acc[0][i][r] = cadd(acc[0][i][r], cadd(uu_xu, ud_xd));
+                    acc[1][i][r] = cadd(acc[1][i][r], cadd(uu_xd, ud_xu));
+                    acc[2][i][r] = cadd(acc[2][i][r], cmuli(csub(ud_xu, uu_xd)));
+                    acc[3][i][r] = cadd(acc[3][i][r], csub(uu_xu, ud_xd));
+                }
             }
         }
         // one buffer: the next band's rows may not overwrite columns still being read
@@ -792,21 +916,28 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a
     const long long N = (long long)G::NP * a.n3;
     T2* out = pick<T2>(a.rho_part, a.rho_part32) + ((long long)b * a.nchunk + chunk) * 4 * N + (long long)i3 * G::NP;
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) {
-        const int q = lane + 64 * j;
-        if (q < K::WPTS) {
-            int oo, g;
-            wave_point<N1, N2, CPW>(w, q, m.perm1, m.perm2, oo, g);
+    for (int i = 0; i < IT; ++i) {
+        if (TL::live(lane, i)) {
+            const int sl = lane + 64 * i;
+            const int cc = sl / TL::BPC, blk = sl - cc * TL::BPC;
+            const int g2 = m.perm2[w * CPW + cc];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) out[c * N + g] = acc[c][j];
+            for (int r = 0; r < R; ++r) {
+                const int g = m.perm1[blk * R + r] * N2 + g2;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) out[c * N + g] = acc[c][i][r];
+            }
         }
     }
 }
 
-// Local fields in the wave kernels' point order, per plane i3 and point
-// idx = p2 n1 + p1 (LDS position, digit-reversed), 6 complex per point:
+// Local fields, six complex values per point:
 //   (v + Bz, v - Bz), (Bx, By), W0 + Wz, W0 - Wz, Wx - i Wy, Wx + i Wy
-// (x side; the y side flips the sign of B and of the vector part of W).
+// (x side; the y side flips the sign of B and of the vector part of W), laid
+// out per plane i3 and LDS column p2 as [t][value][blk] for the row
+// p1 = R blk + t, so that the lanes holding the butterflies blk of the last
+// column stage read 16-lane runs, and a lane's 6 R values sit at small
+// constant offsets from one address.
 // (right-hand side blockIdx.z: its W and its table, wstride / fstride apart)
 template <int N1, int N2, class T2>
 __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __restrict__ W, const int* perm1,
@@ -817,27 +948,33 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
     if (idx >= NP) return;
     W += blockIdx.z * wstride;
     F += blockIdx.z * fstride;
-    const int p2 = idx / N1, p1 = idx - p2 * N1;
+    using TL = WTail<N1, N2, 1>;
+    const int p2 = idx / N1, r = idx - p2 * N1;
+    const int tt = r / TL::BPC, blk = r - tt * TL::BPC;
+    const int p1 = blk * TL::R + tt;
     const long long N = (long long)NP * n3;
     const long long g = (long long)i3 * NP + perm1[p1] * N2 + perm2[p2];
     const double v = vrs[g], bx = vrs[N + g], by = vrs[2 * N + g], bz = vrs[3 * N + g];
     const double2 w0 = W[g], wx = W[N + g], wy = W[2 * N + g], wz = W[3 * N + g];
-    T2* f = F + ((long long)i3 * NP + idx) * 6;
+    constexpr int B = TL::BPC;
+    T2* f = F + ((long long)i3 * N2 + p2) * 6 * N1 + tt * 6 * B + blk;
     f[0] = Cx<T2>::from(cmk(v + bz, v - bz));
-    f[1] = Cx<T2>::from(cmk(bx, by));
-    f[2] = Cx<T2>::from(cadd(w0, wz));
-    f[3] = Cx<T2>::from(csub(w0, wz));
-    f[4] = Cx<T2>::from(csub(wx, cmuli(wy)));
-    f[5] = Cx<T2>::from(cadd(wx, cmuli(wy)));
+    f[B] = Cx<T2>::from(cmk(bx, by));
+    f[2 * B] = Cx<T2>::from(cadd(w0, wz));
+    f[3 * B] = Cx<T2>::from(csub(w0, wz));
+    f[4 * B] = Cx<T2>::from(csub(wx, cmuli(wy)));
+    f[5 * B] = Cx<T2>::from(cadd(wx, cmuli(wy)));
 }
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW>
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF>;
+    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH>;
     using G = typename K::G;
-    constexpr int PPL = K::PPL;
+    using TL = WTail<N1, N2, CPW>;
+    constexpr int PPL = cdiv(K::WPTS, 64);
+    constexpr int B = TL::BPC;
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     T2* xcols = pick<T2>(a.xcols, a.xcols32);
@@ -857,14 +994,20 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
     // the side's resident slot, read once (the loop's stores could alias it)
     const double2* ub = a.ureal + (long long)a.uslot[bt] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
     const bool yside = bt >= a.nk;
-    int o[PPL];
+    // the lane's points q = lane + 64 j of the wave (column cc, row position
+    // r = t B + blk in the point order): LDS offset, and field table offset
+    int o[PPL], fo[PPL];
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
-        int g;
-        wave_point<N1, N2, CPW>(w, min(lane + 64 * j, K::WPTS - 1), m.perm1, m.perm2, o[j], g);
+        const int q = min(lane + 64 * j, K::WPTS - 1);
+        const int cc = q / N1, r = q - cc * N1;
+        const int tt = r / B, blk = r - tt * B;
+        o[j] = (blk * TL::R + tt) * G::N2P + w * CPW + cc;
+        fo[j] = cc * 6 * N1 + tt * 6 * B + blk;
     }
     const T2* fw = pick<T2>(a.fields, a.fields32) + (long long)(b / a.nb2) * a.fstride +
-                   ((long long)i3 * G::NP + w * K::WPTS) * 6;
+                   ((long long)i3 * N2 + w * CPW) * 6 * N1;
+    const typename K::Rows rl(m.rowbase, w, nlw, lane);
     for (int n = n0; n < n1e; ++n) {
         const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
@@ -878,7 +1021,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
                 ud[j] = Cx<T2>::from(ur[G::NP + q]);
             }
         }
-        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2);
+        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
         __syncthreads();
         // columns: inverse along i1, point-wise products, forward along i1
         WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
@@ -887,8 +1030,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
         for (int j = 0; j < PPL; ++j) {
             const int q = lane + 64 * j;
             if (q < K::WPTS) {
-                const T2* f = fw + q * 6;
-                T2 f0 = f[0], f1 = f[1], f2 = f[2], f3 = f[3], f4 = f[4], f5 = f[5];
+                const T2* f = fw + fo[j];
+                T2 f0 = f[0], f1 = f[B], f2 = f[2 * B], f3 = f[3 * B], f4 = f[4 * B], f5 = f[5 * B];
                 if (yside) {  // B -> -B, W -> (W0, -W)
                     f0 = Cx<T2>::mk(f0.y, f0.x);
                     f1 = Cx<T2>::mk(-f1.x, -f1.y);
@@ -916,17 +1059,11 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
         // rows: forward along i2 on the occupied rows of the k+q sphere, then
         // the output columns
         constexpr CPlan c2 = cplan(N2);
-        WRows<K::NW> rl{m.rowbase, w, boff};
-        wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rl, nlw, tw2, lane);
-        T2* co = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-        for (int k = lane; k < nlw * N2; k += 64) {
-            const int li = k / N2, p2 = k - li * N2;
-            const int l = w + li * K::NW;
-            const int info = m.rowinfo[l];
-            const int s = info / N1, row = info - s * N1;
-            const int c = m.colidx[row * N2 + p2];
-            if (c >= 0) co[s * cs + c] = m.pl[boff + m.rowbase[l] + p2];
-        }
+        typename K::Rows rlb = rl;
+        rlb.boff = boff;
+        wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rlb, nlw, tw2, lane);
+        K::rows_out(m, xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max, cs, nlw, w, boff,
+                    lane);
         // no barrier here: with two buffers the next band works in the other
         // one; with one, each wave rewrites only the rows it has just finished
     }
@@ -958,6 +1095,11 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
     constexpr int CPW = 4, CPW32 = 4, CPWA32 = N2 == 48 ? 6 : 4;
     constexpr int BTD = 2, BTA = 2;
     constexpr int NBUF = 2, MINW = 1, NBUF32 = 2, MINW32 = 1, MINWA32 = N2 == 48 ? 4 : 1;
+    // Row fill with all of a lane's loads in flight together (FCH = 64) in the
+    // single-precision density (10 % faster at 48 x 48); element by element
+    // (FCH = 1) elsewhere: the FP64 density and the 6-column FP32 apply would
+    // spill, and the FP64 apply measured 2 % slower.
+    constexpr int FCHD = 1, FCHA = 1, FCHD32 = 64, FCHA32 = 1;
     if (op == kOpUreal) {
         launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
     } else if (a.ureal) {
@@ -968,12 +1110,12 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
             using WD = WaveKernel<N1, N2, BTD, CPW32, float2, NBUF32>;
             using WA = WaveKernel<N1, N2, BTA, CPWA32, float2, NBUF32>;
             if (op == kOpDensity) {
-                launch_with_lds(k_density_w<N1, N2, BTD, CPW32, float2, NBUF32, MINW32>, "k_density_w32",
+                launch_with_lds(k_density_w<N1, N2, BTD, CPW32, float2, NBUF32, MINW32, FCHD32>, "k_density_w32",
                                 WD::bytes(), wgrid, WD::NT, st, a, t);
             } else {
                 TM_LAUNCH((k_fields_w<N1, N2, float2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                           a.vrs, a.W, t.perm1, t.perm2, a.fields32, a.n3, a.wstride, a.fstride);
-                launch_with_lds(k_apply_w<N1, N2, BTA, CPWA32, float2, NBUF32, MINWA32>, "k_apply_w32",
+                launch_with_lds(k_apply_w<N1, N2, BTA, CPWA32, float2, NBUF32, MINWA32, FCHA32>, "k_apply_w32",
                                 WA::bytes(), wgrid, WA::NT, st, a, t);
             }
             return;
@@ -981,13 +1123,13 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
         using WD = WaveKernel<N1, N2, BTD, CPW, double2, NBUF>;
         using WA = WaveKernel<N1, N2, BTA, CPW, double2, NBUF>;
         if (op == kOpDensity) {
-            launch_with_lds(k_density_w<N1, N2, BTD, CPW, double2, NBUF, MINW>, "k_density_w", WD::bytes(), wgrid,
+            launch_with_lds(k_density_w<N1, N2, BTD, CPW, double2, NBUF, MINW, FCHD>, "k_density_w", WD::bytes(), wgrid,
                             WD::NT, st, a, t);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                       a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
-            launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2, NBUF, MINW>, "k_apply_w", WA::bytes(), wgrid,
+            launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2, NBUF, MINW, FCHA>, "k_apply_w", WA::bytes(), wgrid,
                             WA::NT, st, a, t);
         }
     } else {

@@ -115,14 +115,7 @@ def test_apply_many_bands_staged_contractions(lib):
     the LDS-staged kernel the benchmark system runs; synthetic occupied
     manifold (no SCF), 24^3 grid."""
     say("apply cubic24, 48 bands (staged contractions)")
-    sd = synth.make_cubic(24, 48, 1)
-    inp = synth.synthetic_inputs(sd, np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0, seed=3)
-
-    class _GS:
-        pass
-    gs = _GS()
-    gs.sysd, gs.vrs, gs.rho = inp["sysd"], inp["vrs"], inp["rho"]
-    prob = lv.Problem(gs, inp["qset"], point_states=[(m, e, et) for (_, m, e, et, _) in inp["points"]])
+    prob = _synthetic_problem(synth.make_cubic(24, 48, 1), np.array([0.1, 0.0, 0.0]) * 2 * np.pi / 10.0, 3)
     s = Sys(lib, prob)
     try:
         for seed in (1, 2):
@@ -132,6 +125,49 @@ def test_apply_many_bands_staged_contractions(lib):
         got = lib.tm_lanczos_run(s.h, 0, "z", "pH", 12)
         ref = olanczos.run(prob, "z", "pH", 12)
         assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
+    finally:
+        s.close()
+
+
+def _synthetic_problem(sd, qcart, seed):
+    inp = synth.synthetic_inputs(sd, qcart, seed=seed)
+
+    class _GS:
+        pass
+    gs = _GS()
+    gs.sysd, gs.vrs, gs.rho = inp["sysd"], inp["vrs"], inp["rho"]
+    return lv.Problem(gs, inp["qset"], point_states=[(m, e, et) for (_, m, e, et, _) in inp["points"]])
+
+
+@pytest.mark.parametrize("n", [32, 48])
+def test_apply_wave_plane_kernels_32_48(lib, n):
+    """The wave plane kernels at 32 x 32 and at the benchmark's 48 x 48 planes
+    (fused last column stage, field table, resident point order) against the
+    oracle: cubic cell with the sphere filling an n^3 grid, 4 bands, synthetic
+    occupied manifold.  FP64 to 1e-12, the single-precision bulk to 2e-5, two
+    right-hand sides in one pass equal to single applies bit for bit."""
+    import torch
+    say(f"apply cubic{n}, 4 bands (wave plane kernels)")
+    prob = _synthetic_problem(synth.make_cubic(n, 4, 1), np.array([0.1, 0.05, 0.0]) * 2 * np.pi / 10.0, 5)
+    s = Sys(lib, prob)
+    try:
+        xs = [prob.random_projected(seed) for seed in (1, 2)]
+        for x in xs:
+            got, _ = s.apply(x)
+            assert rel_err(got, prob.apply(x)) <= 1e-12, rel_err(got, prob.apply(x))
+        assert s.resident_bytes() > 0
+        npw_pad = s.info["npw_pad"]
+        xin = torch.cat([to_gpu(x, npw_pad) for x in xs])
+        n1 = xin.numel() // 2
+        for prec, tol in ((lib.TM_FP32, 2e-5), (lib.TM_FP64, 1e-12)):
+            out = torch.empty_like(xin)
+            lib.tm_liouvillian_apply_multi(s.h, 0, 2, xin, out, prec)
+            single = torch.empty_like(xin[:n1])
+            lib.tm_liouvillian_apply(s.h, 0, xin[n1:], single, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(out[n1:], single)
+            got, _ = from_gpu(out[:n1], s.shape, prob.npw_pad)
+            assert rel_err(got, prob.apply(xs[0])) <= tol
     finally:
         s.close()
 
