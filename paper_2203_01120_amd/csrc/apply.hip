@@ -376,8 +376,172 @@ void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32, i
 }
 
 // one Hartree solve per right-hand side (the scratch grid is reused in turn)
+// A grid of at most kPotLdsMax points: the response potential of right-hand
+// side blockIdx.y in one launch.  Block 0 holds the grid in LDS and takes the
+// same steps as the multi-kernel path below, in the same order: the charge
+// component to G space along i2, i1, i3, times the Coulomb multiplier
+// (Eq. v_H_q, normalisation included), back to real space, then
+// W_0 = v'_H + sum_b f_0b rho'_b.  Blocks 1 .. kPotParts form the other three
+// components W_a = sum_b f_ab rho'_b (Eqs. v_XC_q, b_XC_q), which do not wait
+// for v'_H, over a share of the points each.
+constexpr long long kPotLdsMax = 8192;  // 128 KB of LDS (and the twiddle tables)
+constexpr int kPotThreads = 512;
+constexpr int kPotParts = 8;
+
+// Transform of length N with the radices of the plan (4s, then 5s, 3s, 2s),
+// with N and the radices known at compile time: P = product of the earlier radices
+constexpr int next_radix(int m) { return m % 4 == 0 ? 4 : m % 5 == 0 ? 5 : m % 3 == 0 ? 3 : 2; }
+
+template <int N, int P = 1, class LN>
+__device__ __forceinline__ void ct_fft(double2* lds, int nlines, const LN& ln, int estride, const double2* tw,
+                                       int sign) {
+    if constexpr (P < N) {
+        constexpr int R = next_radix(N / P);
+        fft_pass<R>(lds, nlines, ln, estride, N, P, tw, sign);
+        ct_fft<N, P * R>(lds, nlines, ln, estride, tw, sign);
+    }
+}
+
+// 3D transform of the grid [i3][i1][i2] in LDS along i2, i1, i3; tw: the three
+// twiddle tables (lengths n1, n2, n3) one after the other.  N1 > 0: the sizes
+// are compile-time constants (the index arithmetic folds); else the plans'.
+template <int N1, int N2, int N3>
+__device__ void grid_fft(double2* g, int n1, int n2, int n3, const FFTPlan& p1, const FFTPlan& p2,
+                         const FFTPlan& p3, const double2* tw, int sign) {
+    if constexpr (N1 > 0) {
+        constexpr int NP = N1 * N2;
+        ct_fft<N2>(g, N3 * N1, StrideLines{N2}, 1, tw + N1, sign);          // along i2: lines (i3, i1)
+        ct_fft<N1>(g, N3 * N2, GridLines{N2, NP, 1}, N2, tw, sign);         // along i1: lines (i3, i2)
+        ct_fft<N3>(g, NP, StrideLines{1}, NP, tw + N1 + N2, sign);          // along i3: over the plane
+    } else {
+        const int NP = n1 * n2;
+        lds_fft_lines(g, n3 * n1, StrideLines{n2}, 1, p2, tw + n1, sign);
+        lds_fft_lines(g, n3 * n2, GridLines{n2, NP, 1}, n2, p1, tw, sign);
+        lds_fft_lines(g, NP, StrideLines{1}, NP, p3, tw + n1 + n2, sign);
+    }
+}
+
+template <int N1, int N2, int N3>
+__global__ void __launch_bounds__(kPotThreads) k_potential_lds(const double2* rho, const double* hq,
+                                                               const double* fxc, double2* W, int n1, int n2,
+                                                               int n3, FFTPlan p1, FFTPlan p2, FFTPlan p3) {
+    extern __shared__ double2 g[];
+    if constexpr (N1 > 0) {
+        n1 = N1;
+        n2 = N2;
+        n3 = N3;
+    }
+    const int N = n1 * n2 * n3;
+    rho += (size_t)blockIdx.y * 4 * N;
+    W += (size_t)blockIdx.y * 4 * N;
+    if (blockIdx.x > 0) {
+        const int per = (N + kPotParts - 1) / kPotParts;
+        const int i0 = (blockIdx.x - 1) * per, i1 = min(N, i0 + per);
+        for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+            double f[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) f[t] = fxc[(size_t)(t + 1) * N + i];
+            const double2 r0 = rho[i], r1 = rho[N + i], r2 = rho[2 * N + i], r3 = rho[3 * N + i];
+            auto comb = [&](double a0, double a1, double a2, double a3) {
+                return cmk(a0 * r0.x + a1 * r1.x + a2 * r2.x + a3 * r3.x,
+                           a0 * r0.y + a1 * r1.y + a2 * r2.y + a3 * r3.y);
+            };
+            W[N + i] = comb(f[0], f[3], f[4], f[5]);
+            W[2 * N + i] = comb(f[1], f[4], f[6], f[7]);
+            W[3 * N + i] = comb(f[2], f[5], f[7], f[8]);
+        }
+        return;
+    }
+    // the twiddle tables next to the grid, so that the passes read them from LDS
+    double2* tw = g + N;
+    for (int i = threadIdx.x; i < n1 + n2 + n3; i += blockDim.x)
+        tw[i] = i < n1 ? p1.tw[i] : i < n1 + n2 ? p2.tw[i - n1] : p3.tw[i - n1 - n2];
+    // element-wise loops in groups of U points a thread, loads first, so that a
+    // thread's global loads are in flight together
+    constexpr int U = 4;
+    const int step = U * blockDim.x;
+    for (int i0 = threadIdx.x; i0 < N; i0 += step) {
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            v[u] = i < N ? rho[i] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < N) g[i] = v[u];
+        }
+    }
+    __syncthreads();
+    grid_fft<N1, N2, N3>(g, n1, n2, n3, p1, p2, p3, tw, -1);
+    for (int i0 = threadIdx.x; i0 < N; i0 += step) {
+        double h[U];
+        double2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            h[u] = i < N ? hq[i] : 0.0;
+            v[u] = i < N ? g[i] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < N) g[i] = cscale(v[u], h[u]);
+        }
+    }
+    __syncthreads();
+    grid_fft<N1, N2, N3>(g, n1, n2, n3, p1, p2, p3, tw, +1);
+    for (int i0 = threadIdx.x; i0 < N; i0 += step) {
+        double2 r[U][4];
+        double f[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + u * (int)blockDim.x, N - 1);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                r[u][c] = rho[(size_t)c * N + i];
+                f[u][c] = fxc[(size_t)c * N + i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u * (int)blockDim.x;
+            if (i < N) {
+                W[i] = cadd(g[i], cmk(f[u][0] * r[u][0].x + f[u][1] * r[u][1].x + f[u][2] * r[u][2].x +
+                                          f[u][3] * r[u][3].x,
+                                      f[u][0] * r[u][0].y + f[u][1] * r[u][1].y + f[u][2] * r[u][2].y +
+                                          f[u][3] * r[u][3].y));
+            }
+        }
+    }
+}
+
+// smallest radix of a plan
+static int min_radix(const FFTPlan& p) {
+    int m = p.n;
+    for (int r = 0; r < p.nrad; ++r) m = std::min(m, p.rad[r]);
+    return m;
+}
+
 void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) {
     long long N = s.N;
+    // every radix pass of the in-LDS transform within kMaxBfly butterflies a thread
+    const int rmin = std::min(min_radix(s.plan[0]), std::min(min_radix(s.plan[1]), min_radix(s.plan[2])));
+    if (N <= kPotLdsMax && N / rmin <= (long long)kMaxBfly * kPotThreads) {
+        const size_t shm = (size_t)(N + s.n1 + s.n2 + s.n3) * sizeof(double2);
+        auto kern = s.n1 == 20 && s.n2 == 20 && s.n3 == 20 ? k_potential_lds<20, 20, 20>
+                    : s.n1 == 8 && s.n2 == 8 && s.n3 == 8  ? k_potential_lds<8, 8, 8>
+                                                            : k_potential_lds<0, 0, 0>;
+        TM_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) ==
+                     hipSuccess,
+                 TM_EDEVICE, "cannot raise the LDS limit of k_potential_lds");
+        ProfScope ps("k_potential_lds", st);
+        hipLaunchKernelGGL(kern, dim3(1 + kPotParts, nrhs), dim3(kPotThreads), shm, st, s.ws.rho, q.hq, s.fxc,
+                           s.ws.W, s.n1, s.n2, s.n3, s.plan[0], s.plan[1], s.plan[2]);
+        check_launch("k_potential_lds");
+        return;
+    }
     unsigned nbk = (unsigned)((N + 255) / 256);
     for (int r = 0; r < nrhs; ++r) {
         const double2* rho = s.ws.rho + (size_t)r * 4 * N;

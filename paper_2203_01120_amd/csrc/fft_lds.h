@@ -70,8 +70,23 @@ __device__ inline void dft_small(T2* v, int sign) {
     }
 }
 
-template <int R>
-__device__ inline void fft_pass(double2* lds, int nlines, int lstride, int estride, int n, int p,
+// line l at l * lstride
+struct StrideLines {
+    int lstride;
+    __device__ int base(int l) const { return l * lstride; }
+};
+
+// line l = (o, i), o = l / inner, at o * ostride + i * istride
+struct GridLines {
+    int inner, ostride, istride;
+    __device__ int base(int l) const {
+        const int o = l / inner;
+        return o * ostride + (l - o * inner) * istride;
+    }
+};
+
+template <int R, class LN>
+__device__ inline void fft_pass(double2* lds, int nlines, const LN& ln, int estride, int n, int p,
                                 const double2* tw, int sign) {
     const int T = n / R;
     const int nb = nlines * T;
@@ -86,13 +101,14 @@ __device__ inline void fft_pass(double2* lds, int nlines, int lstride, int estri
             int line = b / T;
             int i = b - line * T;
             int k = i % p;
-            double2* base = lds + line * lstride;
+            const int lb = ln.base(line);
+            double2* base = lds + lb;
 #pragma unroll
             for (int t = 0; t < R; ++t) {
                 double2 x = base[(i + t * T) * estride];
                 v[bi][t] = (t == 0 || k == 0) ? x : cmul(x, twiddle(tw, t * k * twstep, sign));
             }
-            pos[bi] = line * lstride + ((i - k) * R + k) * estride;
+            pos[bi] = lb + ((i - k) * R + k) * estride;
         }
     }
     __syncthreads();
@@ -107,21 +123,29 @@ __device__ inline void fft_pass(double2* lds, int nlines, int lstride, int estri
     __syncthreads();
 }
 
-// Full FFT of `nlines` lines: element t of line l is lds[l*lstride + t*estride].
+// Full FFT of `nlines` lines: element t of line l is lds[ln.base(l) + t*estride].
 // Unnormalised; sign = -1 forward, +1 inverse.  Ends with a barrier.
-__device__ inline void lds_fft(double2* lds, int nlines, int lstride, int estride, const FFTPlan& pl,
-                               int sign) {
+// (twiddles from tw, the plan's table or a copy of it)
+template <class LN>
+__device__ inline void lds_fft_lines(double2* lds, int nlines, const LN& ln, int estride, const FFTPlan& pl,
+                                     const double2* tw, int sign) {
     int p = 1;
     for (int r = 0; r < pl.nrad; ++r) {
         int R = pl.rad[r];
         switch (R) {
-            case 4: fft_pass<4>(lds, nlines, lstride, estride, pl.n, p, pl.tw, sign); break;
-            case 5: fft_pass<5>(lds, nlines, lstride, estride, pl.n, p, pl.tw, sign); break;
-            case 3: fft_pass<3>(lds, nlines, lstride, estride, pl.n, p, pl.tw, sign); break;
-            default: fft_pass<2>(lds, nlines, lstride, estride, pl.n, p, pl.tw, sign); break;
+            case 4: fft_pass<4>(lds, nlines, ln, estride, pl.n, p, tw, sign); break;
+            case 5: fft_pass<5>(lds, nlines, ln, estride, pl.n, p, tw, sign); break;
+            case 3: fft_pass<3>(lds, nlines, ln, estride, pl.n, p, tw, sign); break;
+            default: fft_pass<2>(lds, nlines, ln, estride, pl.n, p, tw, sign); break;
         }
         p *= R;
     }
+}
+
+// lines l * lstride
+__device__ inline void lds_fft(double2* lds, int nlines, int lstride, int estride, const FFTPlan& pl,
+                               int sign) {
+    lds_fft_lines(lds, nlines, StrideLines{lstride}, estride, pl, pl.tw, sign);
 }
 
 }  // namespace tml
