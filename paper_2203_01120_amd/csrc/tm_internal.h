@@ -187,7 +187,7 @@ struct Workspace {
     double2* rho = nullptr;       // [4][N]
     double2* work = nullptr;      // [N] Hartree scratch
     double2* W = nullptr;         // [4][N]
-    double2* fields = nullptr;    // [N][6] fields in the order of the resident real-space planes
+    double2* fields = nullptr;    // 6 fields per point, laid out for the wave plane kernels
     double2* gpart = nullptr;     // GEMM split-K partials
     double2* gsmall = nullptr;    // reduced small GEMM outputs
     double2* dots = nullptr;      // reduced inner products [64]
