@@ -476,7 +476,7 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
     grab((void**)&w.gpart, w.cap_gpart * sizeof(double2));
     grab((void**)&w.gsmall, w.cap_gsmall * sizeof(double2));
     grab((void**)&w.W, R * 4 * s.N * sizeof(double2));
-    grab((void**)&w.work, s.N * sizeof(double2));
+    grab((void**)&w.work, R * s.N * sizeof(double2));
     grab((void**)&w.dots, 64 * sizeof(double2));
     grab((void**)&w.dotpart, 1024 * 8 * sizeof(double2));
     if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, R * 6 * s.N * sizeof(double2));

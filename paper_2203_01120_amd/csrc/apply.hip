@@ -125,19 +125,27 @@ __global__ void k_density_reduce(const T2* part, double2* rho, long long N, int 
     rho[idx] = cscale(cmk(sx.x + sgn * sy.x, sx.y + sgn * sy.y), scale);
 }
 
-__global__ void k_copy_scale(const double2* src, double2* dst, long long n) {
+// Right-hand side blockIdx.y: its rho (4 N), its scratch grid (N) and its W (4 N).
+// the charge component of rho into the scratch grid
+__global__ void k_copy_scale(const double2* rho, double2* dst, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+    rho += blockIdx.y * 4 * n;
+    dst += blockIdx.y * n;
+    if (i < n) dst[i] = rho[i];
 }
 
 __global__ void k_mul_real(double2* data, const double* h, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    data += blockIdx.y * n;
     if (i < n) data[i] = cscale(data[i], h[i]);
 }
 
 // W_a = delta_a0 vH + sum_b f_ab rho_b with f stored as (00,01,02,03,11,12,13,22,23,33)
 __global__ void k_assemble_W(const double2* rho, const double2* vH, const double* fxc, double2* W, long long N) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    rho += blockIdx.y * 4 * N;
+    vH += blockIdx.y * N;
+    W += blockIdx.y * 4 * N;
     if (i >= N) return;
     double f[10];
 #pragma unroll
@@ -542,16 +550,13 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) 
         check_launch("k_potential_lds");
         return;
     }
-    unsigned nbk = (unsigned)((N + 255) / 256);
-    for (int r = 0; r < nrhs; ++r) {
-        const double2* rho = s.ws.rho + (size_t)r * 4 * N;
-        double2* W = s.ws.W + (size_t)r * 4 * N;
-        TM_LAUNCH(k_copy_scale, dim3(nbk), dim3(256), 0, st, rho, s.ws.work, N);
-        launch_fft3d_full(s, s.ws.work, -1, st);
-        TM_LAUNCH(k_mul_real, dim3(nbk), dim3(256), 0, st, s.ws.work, q.hq, N);
-        launch_fft3d_full(s, s.ws.work, +1, st);
-        TM_LAUNCH(k_assemble_W, dim3(nbk), dim3(256), 0, st, rho, s.ws.work, s.fxc, W, N);
-    }
+    // every right-hand side in each launch
+    const dim3 grid((unsigned)((N + 255) / 256), nrhs);
+    TM_LAUNCH(k_copy_scale, grid, dim3(256), 0, st, s.ws.rho, s.ws.work, N);
+    launch_fft3d_full(s, s.ws.work, -1, st, nrhs);
+    TM_LAUNCH(k_mul_real, grid, dim3(256), 0, st, s.ws.work, q.hq, N);
+    launch_fft3d_full(s, s.ws.work, +1, st, nrhs);
+    TM_LAUNCH(k_assemble_W, grid, dim3(256), 0, st, s.ws.rho, s.ws.work, s.fxc, s.ws.W, N);
 }
 
 void launch_apply_planes(const System& s, const QSet& q, hipStream_t st, bool fp32, int nrhs) {

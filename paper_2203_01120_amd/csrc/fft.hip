@@ -312,7 +312,8 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
 }
 
 // data: plane-major [i3][i1][i2]
-void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st) {
+// nrhs grids of N points back to back: the lines of every grid in one launch per axis
+void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st, int nrhs) {
     const int n1 = s.n1, n2 = s.n2, n3 = s.n3;
     const long long NP = (long long)n1 * n2;
     struct Pass {
@@ -323,12 +324,14 @@ void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st)
         int nlines, inner;
         long long outer_stride, inner_stride, estride;
         const FFTPlan* pl;
-        if (p.axis == 1) {  // along i2: lines (i3, i1)
-            nlines = n3 * n1; inner = n1; outer_stride = NP; inner_stride = n2; estride = 1; pl = &s.plan[1];
-        } else if (p.axis == 0) {  // along i1: lines (i3, i2)
-            nlines = n3 * n2; inner = n2; outer_stride = NP; inner_stride = 1; estride = n2; pl = &s.plan[0];
-        } else {  // along i3: lines p in plane
-            nlines = (int)NP; inner = (int)NP; outer_stride = 0; inner_stride = 1; estride = NP; pl = &s.plan[2];
+        // (the grid index counts as an outer index: planes follow planes)
+        if (p.axis == 1) {  // along i2: lines (grid, i3, i1)
+            nlines = nrhs * n3 * n1; inner = n1; outer_stride = NP; inner_stride = n2; estride = 1; pl = &s.plan[1];
+        } else if (p.axis == 0) {  // along i1: lines (grid, i3, i2)
+            nlines = nrhs * n3 * n2; inner = n2; outer_stride = NP; inner_stride = 1; estride = n2; pl = &s.plan[0];
+        } else {  // along i3: lines (grid, p) over the plane points
+            nlines = nrhs * (int)NP; inner = (int)NP; outer_stride = NP * n3; inner_stride = 1; estride = NP;
+            pl = &s.plan[2];
         }
         dim3 grid((nlines + L - 1) / L);
         size_t shm = (size_t)L * p.n * sizeof(double2);

@@ -185,7 +185,7 @@ struct Workspace {
     double2* xcols = nullptr;     // [2nk][nb*2][n3][ncol_max] (also reused for phi columns)
     double2* rho_part = nullptr;  // [nslot][4][N]
     double2* rho = nullptr;       // [4][N]
-    double2* work = nullptr;      // [N] Hartree scratch
+    double2* work = nullptr;      // [nrhs][N] Hartree scratch
     double2* W = nullptr;         // [4][N]
     double2* fields = nullptr;    // 6 fields per point, laid out for the wave plane kernels
     double2* gpart = nullptr;     // GEMM split-K partials
@@ -263,7 +263,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
                       int nitems, int item_stride, double2* cols, hipStream_t st, bool fp32 = false, int nrhs = 1);
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin,
                       double2* out, hipStream_t st, bool fp32 = false, int nrhs = 1);
-void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st);
+void launch_fft3d_full(const System& s, double2* data, int sign, hipStream_t st, int nrhs = 1);
 // apply.hip
 void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32 = false, int nrhs = 1);
 void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs = 1);
