@@ -383,7 +383,6 @@ void launch_density(const System& s, const QSet& q, hipStream_t st, bool fp32, i
     }
 }
 
-// one Hartree solve per right-hand side (the scratch grid is reused in turn)
 // A grid of at most kPotLdsMax points: the response potential of right-hand
 // side blockIdx.y in one launch.  Block 0 holds the grid in LDS and takes the
 // same steps as the multi-kernel path below, in the same order: the charge
