@@ -302,7 +302,8 @@ def run_serving(args, tm, torch):
                                       omega=omega, eta=eta, arrival=float(t[i])))
             return out
         log(f"rate {rate}/s: {args.requests} requests, batched server")
-        server = sv.Server(slots, budget_bytes=32 << 30, lanes=args.serving_lanes, max_chains=args.serving_max_chains)
+        server = sv.Server(slots, budget_bytes=32 << 30, lanes=args.serving_lanes, max_chains=args.serving_max_chains,
+                           chain_slots=args.serving_chain_slots)
         batched = server.run(make())
         log(f"rate {rate}/s: one at a time")
         plain = sv.run_one_at_a_time(slots, make())
@@ -352,6 +353,8 @@ def main():
     ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
     ap.add_argument("--serving-lanes", type=int, default=4, choices=[1, 2, 3, 4],
                     help="serving: pending requests of one system, q set and flavour share a chain (lanes)")
+    ap.add_argument("--serving-chain-slots", type=int, default=1,
+                    help="serving: concurrent workspace slots per system (1: its chains on its stream)")
     ap.add_argument("--serving-max-chains", type=int, default=4,
                     help="serving: chains per system at a time (0: no limit); later requests wait and form lanes")
     ap.add_argument("--seed", type=int, default=1)

@@ -256,11 +256,17 @@ int tm_tensor_run(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavo
  *   `stream` (a hipStream_t, NULL = default stream).  TM_ENOMEM when the
  *   vectors do not fit.
  * tm_chains_step: advances each of the n chains by up to k_steps steps (never
- *   past its capacity), one step per chain in turn, all on `stream`;
+ *   past its capacity), one step per chain in turn, ordered on `stream`;
  *   asynchronous.  Chains may belong to different systems, but all work of
  *   one system must be issued on one stream at a time (its chains share the
- *   system's apply workspace).  The step index and the breakdown flag live on
- *   the device: after a breakdown the chain's coefficients stop changing.
+ *   system's apply workspaces).  The chains of a system whose apply
+ *   workspace is small (at most 256 MB) are spread over up to 4 workspace
+ *   slots (see tm_system_set_chain_slots): slot 0 runs on `stream`, the other
+ *   slots on library streams that wait for the work issued on `stream` before
+ *   the call and that `stream` waits for before anything issued after it, so
+ *   the chains of different slots overlap on the device.  The step index and
+ *   the breakdown flag live on the device: after a breakdown the chain's
+ *   coefficients stop changing.
  * tm_chain_coeffs: waits for the chain's last stream, copies the first
  *   min(capacity, out->capacity) coefficients, steps_done and n1 into `out`
  *   (layout of tm_coeffs; one struct per lane, see below); TM_EBREAKDOWN
@@ -293,6 +299,12 @@ int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, t
                          int capacity, void* stream, tm_chain** out);
 int tm_chain_lanes(const tm_chain* chain, int* lanes);
 int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream);
+/* tm_system_set_chain_slots: at most nslots (1..16, default 4) workspace
+ * slots for the chains of sys begun afterwards; 1 runs all of them on the
+ * caller's stream (for a caller that overlaps systems on streams of its
+ * own).  Each slot holds its own apply workspace.  TM_EINVAL while chains of
+ * sys exist or for nslots outside 1..16. */
+int tm_system_set_chain_slots(tm_system* sys, int nslots);
 int tm_chain_coeffs(tm_chain* chain, tm_coeffs* out);
 int tm_chain_end(tm_chain* chain);
 

@@ -24,6 +24,7 @@ DIRS = {"x": 0, "y": 1, "z": 2, "+": 3, "-": 4, "n": 5}
 FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
+            "tm_system_set_chain_slots",
             "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
@@ -78,6 +79,7 @@ def load(path: str = LIB_PATH):
     lib.tm_system_destroy.argtypes = [C.c_void_p]
     lib.tm_qset_info_get.argtypes = [C.c_void_p, C.c_int, C.POINTER(_QInfo)]
     lib.tm_system_set_resident_limit.argtypes = [C.c_void_p, C.c_longlong]
+    lib.tm_system_set_chain_slots.argtypes = [C.c_void_p, C.c_int]
     lib.tm_chain_begin.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p,
                                    C.POINTER(C.c_void_p)]
     lib.tm_chains_step.argtypes = [C.POINTER(C.c_void_p), C.c_int, C.c_int, C.c_void_p]
@@ -230,6 +232,12 @@ def tm_qset_info_get(h, iq: int = 0) -> dict:
 def tm_system_set_resident_limit(h, nbytes: int) -> None:
     """Limit (bytes) on the resident real-space ground state; -1 = default, 0 = off."""
     _check(load().tm_system_set_resident_limit(C.c_void_p(h), int(nbytes)))
+
+
+def tm_system_set_chain_slots(h, nslots: int) -> None:
+    """At most nslots concurrent workspace slots for the system's chains begun
+    afterwards (1: every chain on the caller's stream)."""
+    _check(load().tm_system_set_chain_slots(C.c_void_p(h), int(nslots)))
 
 
 def tm_system_resident_bytes(h) -> int:

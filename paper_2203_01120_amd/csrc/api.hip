@@ -438,6 +438,15 @@ static void free_workspace(Workspace& w) {
     w = Workspace{};
 }
 
+// Makes slot j's workspace the one the launches use (see System::ws).
+static void select_slot(System& s, int j) {
+    if ((int)s.wslot.size() <= j) s.wslot.resize(j + 1);
+    if (j == s.wcur) return;
+    s.wslot[s.wcur] = s.ws;
+    s.ws = s.wslot[j];
+    s.wcur = j;
+}
+
 // Sized for nrhs right-hand sides over all q sets.  Growing it frees the old
 // buffers (after the device is idle) and bumps the epoch, so chains re-capture
 // their step graphs, which hold its pointers.
@@ -446,8 +455,9 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
     if (w.rho && w.width >= nrhs) return;
     if (w.rho) {
         TM_HIP(hipDeviceSynchronize());
+        const int epoch = w.epoch;
         free_workspace(w);
-        ++s.ws_epoch;
+        w.epoch = epoch + 1;
     }
     w.width = nrhs;
     const int nb = s.nbnd;
@@ -480,6 +490,7 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
     grab((void**)&w.dots, 64 * sizeof(double2));
     grab((void**)&w.dotpart, 1024 * 8 * sizeof(double2));
     if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, R * 6 * s.N * sizeof(double2));
+    w.bytes = (w.cap_xcols + w.cap_rho_part + w.cap_gpart + w.cap_gsmall + R * 9 * s.N) * sizeof(double2);
     grab((void**)&w.rho, R * 4 * s.N * sizeof(double2));  // last: marks the workspace complete
 }
 
@@ -608,6 +619,7 @@ struct Chain {
     hipStream_t last = nullptr;
     hipGraphExec_t gexec = nullptr;  // one period of steps, captured
     int gepoch = -1;                 // workspace epoch the graph was captured against
+    int slot = 0;                    // the system's workspace slot (and stream inside tm_chains_step)
     std::vector<void*> mem;
 
     void* alloc(size_t bytes) {
@@ -653,11 +665,28 @@ static void chain_clear_coeffs(Chain& c, hipStream_t st) {
     TM_HIP(hipMemsetAsync(c.co.z, 0, L * kNMeasure * cap * sizeof(double2), st));
 }
 
+// Chains of a system whose workspace is small are spread over up to
+// slot_cap workspace slots, which run concurrently inside tm_chains_step (a
+// small system's step leaves most of the device idle); others keep one.
+constexpr size_t kSlotBytes = 256u << 20;
+
+static void chain_bind_slot(Chain& c, const QSet& q) {
+    System& s = *c.s;
+    if (s.nslots == 0) {
+        select_slot(s, 0);
+        ensure_workspace(s, q, c.lanes);
+        s.nslots = s.ws.bytes <= kSlotBytes ? s.slot_cap : 1;
+    }
+    c.slot = s.next_slot++ % s.nslots;
+    select_slot(s, c.slot);
+    ensure_workspace(s, q, c.lanes);
+}
+
 static void chain_begin(Chain& c, hipStream_t st) {
     System& s = *c.s;
     QSet& q = s.qs[c.iq];
     TM_CHECK(c.lanes >= 1 && c.lanes <= kMaxLanes, TM_EINVAL, "1 to 4 lanes per chain");
-    ensure_workspace(s, q, c.lanes);
+    chain_bind_slot(c, q);
     ensure_ground(s, q, st);  // before any step, so steps never allocate or synchronise
     c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
     c.half = c.n / 2;
@@ -780,16 +809,17 @@ static void chain_capture(Chain& c) {
         c.gexec = nullptr;
         throw Error{TM_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(e)};
     }
-    c.gepoch = s.ws_epoch;
+    c.gepoch = s.ws.epoch;
 }
 
 // up to k steps of one chain (never past its capacity)
 static void chain_steps(Chain& c, int k, hipStream_t st) {
+    select_slot(*c.s, c.slot);
     k = std::min(k, c.cap - c.issued);
     const int P = c.period();
     while (k > 0) {
         if (g_use_graphs && !g_prof_on && c.issued % P == 0 && k >= P) {
-            if (c.gexec && c.gepoch != c.s->ws_epoch) {  // the workspace moved since the capture
+            if (c.gexec && c.gepoch != c.s->ws.epoch) {  // the workspace moved since the capture
                 (void)hipGraphExecDestroy(c.gexec);
                 c.gexec = nullptr;
             }
@@ -950,7 +980,7 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     c.cap = std::max(capacity, h.cap);
     c.n = h.n;
     QSet& qm = s.qs[c.iq];
-    ensure_workspace(s, qm, c.lanes);
+    chain_bind_slot(c, qm);
     ensure_ground(s, qm, st);
     c.half = c.n / 2;
     c.w = 1.0 / qm.nk;
@@ -1211,8 +1241,13 @@ int tm_system_destroy(tm_system* sys) {
         for (QSet& q : s.qs)
             if (q.ucols) (void)hipFree(q.ucols);
         if (s.cap_stream) (void)hipStreamDestroy(s.cap_stream);
+        for (hipStream_t x : s.slot_stream) (void)hipStreamDestroy(x);
+        for (hipEvent_t e : s.slot_event) (void)hipEventDestroy(e);
+        if (s.fork_event) (void)hipEventDestroy(s.fork_event);
         if (s.ureal) (void)hipFree(s.ureal);
-        free_workspace(s.ws);
+        if (s.wslot.empty()) s.wslot.push_back(s.ws);
+        else s.wslot[s.wcur] = s.ws;
+        for (Workspace& w : s.wslot) free_workspace(w);
         delete sys;
         return TM_OK;
     });
@@ -1239,6 +1274,19 @@ int tm_system_set_resident_limit(tm_system* sys, long long bytes) {
         TM_CHECK(sys->s.nchains == 0, TM_EINVAL, "the residency limit cannot change while chains exist");
         reset_ground(sys->s);
         sys->s.resident_limit = bytes < 0 ? -1 : bytes;
+        return TM_OK;
+    });
+}
+
+int tm_system_set_chain_slots(tm_system* sys, int nslots) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys, TM_EINVAL, "null system");
+        TM_CHECK(nslots >= 1 && nslots <= 16, TM_EINVAL, "1 to 16 chain slots");
+        System& s = sys->s;
+        TM_CHECK(s.nchains == 0, TM_EINVAL, "the chain slots cannot change while chains exist");
+        s.slot_cap = nslots;
+        s.nslots = 0;  // decided again at the next chain
+        s.next_slot = 0;
         return TM_OK;
     });
 }
@@ -1370,25 +1418,70 @@ int tm_chain_lanes(const tm_chain* chain, int* lanes) {
     });
 }
 
+// Slot 0 runs on st itself; slots 1 .. nslots-1 on streams of their own,
+// which wait for the work issued so far on st.
+static void fork_slots(System& s, hipStream_t st) {
+    if (!s.fork_event) TM_HIP(hipEventCreateWithFlags(&s.fork_event, hipEventDisableTiming));
+    while ((int)s.slot_stream.size() < s.nslots - 1) {
+        hipStream_t x = nullptr;
+        hipEvent_t e = nullptr;
+        TM_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        s.slot_stream.push_back(x);
+        TM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        s.slot_event.push_back(e);
+    }
+    TM_HIP(hipEventRecord(s.fork_event, st));
+    for (int j = 0; j + 1 < s.nslots; ++j) TM_HIP(hipStreamWaitEvent(s.slot_stream[j], s.fork_event, 0));
+}
+
+// st waits for everything issued on the slot streams
+static void join_slots(System& s, hipStream_t st) {
+    for (int j = 0; j + 1 < s.nslots; ++j) {
+        TM_HIP(hipEventRecord(s.slot_event[j], s.slot_stream[j]));
+        TM_HIP(hipStreamWaitEvent(st, s.slot_event[j], 0));
+    }
+}
+
+// the stream of chain c inside tm_chains_step
+static hipStream_t chain_stream(const Chain& c, hipStream_t st) {
+    return c.slot == 0 || c.s->nslots <= 1 ? st : c.s->slot_stream[c.slot - 1];
+}
+
 int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream) {
     return guarded([&]() -> int {
         TM_CHECK(n >= 0 && k_steps >= 0, TM_EINVAL, "negative count");
         TM_CHECK(n == 0 || chains, TM_EINVAL, "null chain array");
         for (int i = 0; i < n; ++i) TM_CHECK(chains[i] != nullptr, TM_EINVAL, "null chain");
         hipStream_t st = static_cast<hipStream_t>(stream);
-        // round robin, one period of steps per chain and turn
-        std::vector<int> left(n, k_steps);
-        for (bool any = true; any;) {
-            any = false;
-            for (int i = 0; i < n; ++i) {
-                Chain& c = chains[i]->c;
-                if (left[i] <= 0 || c.issued >= c.cap || c.broken_seen) continue;
-                const int before = c.issued;
-                chain_steps(c, std::min(left[i], c.period()), st);
-                left[i] -= c.issued - before;
-                any = true;
-            }
+        // Systems with several workspace slots: each slot's chains go to the
+        // slot's stream, forked from st and joined back into it, so that work
+        // issued on st afterwards comes after them.
+        std::vector<System*> forked;
+        for (int i = 0; i < n; ++i) {
+            System* s = chains[i]->c.s;
+            if (s->nslots > 1 && std::find(forked.begin(), forked.end(), s) == forked.end()) forked.push_back(s);
         }
+        for (System* s : forked) fork_slots(*s, st);
+        try {
+            // round robin, one period of steps per chain and turn
+            std::vector<int> left(n, k_steps);
+            for (bool any = true; any;) {
+                any = false;
+                for (int i = 0; i < n; ++i) {
+                    Chain& c = chains[i]->c;
+                    if (left[i] <= 0 || c.issued >= c.cap || c.broken_seen) continue;
+                    const int before = c.issued;
+                    chain_steps(c, std::min(left[i], c.period()), chain_stream(c, st));
+                    left[i] -= c.issued - before;
+                    any = true;
+                }
+            }
+        } catch (...) {
+            for (System* s : forked) join_slots(*s, st);
+            throw;
+        }
+        for (System* s : forked) join_slots(*s, st);
+        for (int i = 0; i < n; ++i) chains[i]->c.last = st;
         return TM_OK;
     });
 }

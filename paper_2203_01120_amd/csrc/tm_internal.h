@@ -182,6 +182,7 @@ struct QSet {
 
 struct Workspace {
     size_t bytes = 0;
+    int epoch = 0;                // bumped whenever the buffers are reallocated
     double2* xcols = nullptr;     // [2nk][nb*2][n3][ncol_max] (also reused for phi columns)
     double2* rho_part = nullptr;  // [nslot][4][N]
     double2* rho = nullptr;       // [4][N]
@@ -227,12 +228,23 @@ struct System {
     std::map<std::array<int, 5>, int> uslot_of;
     long long resident_limit = -1;  // bytes; -1 = a share of the free device memory
     int ureal_mode = 0;             // 0 undecided, 1 resident, 2 columns
-    int ws_epoch = 0;               // bumped whenever the workspace is reallocated
     double2* ureal = nullptr;
     size_t ureal_bytes = 0;
     hipStream_t cap_stream = nullptr;  // private stream for graph capture of chain steps
     int nchains = 0;                   // chains alive (tm_chain_begin .. tm_chain_end)
+    // Workspaces of the apply: one per chain slot.  Chains of a small system
+    // are spread over slots whose streams run concurrently inside
+    // tm_chains_step; `ws` is the selected slot's (its copy in wslot is stale
+    // while selected).
     Workspace ws;
+    std::vector<Workspace> wslot;
+    std::vector<hipStream_t> slot_stream;
+    std::vector<hipEvent_t> slot_event;
+    hipEvent_t fork_event = nullptr;
+    int wcur = 0;
+    int nslots = 0;                    // decided at the first chain
+    int slot_cap = 4;                  // at most this many (tm_system_set_chain_slots)
+    int next_slot = 0;
     std::vector<void*> allocs;
 };
 

@@ -78,13 +78,16 @@ class Server:
     PERIOD = {"pH": 6, "nH": 3}
 
     def __init__(self, systems: Dict[str, SystemSlot], budget_bytes: int, rounds_per_sync: int = 1,
-                 lanes: int = 4, lane_slack: float = 1.25, max_chains: int = 0):
+                 lanes: int = 4, lane_slack: float = 1.25, max_chains: int = 0, chain_slots: int = 1):
         import torch
         self.torch = torch
         self.systems = systems
         for s in systems.values():
             if s.stream is None:
                 s.stream = torch.cuda.Stream()   # default priority
+            # the systems already overlap on their own streams; chain_slots > 1
+            # also overlaps the chains of one system (library streams)
+            tb.tm_system_set_chain_slots(s.handle, chain_slots)
         self.budget = int(budget_bytes)
         self.used = 0
         self.pending: deque = deque()

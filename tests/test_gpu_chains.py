@@ -1,8 +1,8 @@
 """Chain-level interface (tm_chain_*) through the C ABI (needs an MI355X).
 
-A chain stepped in pieces, or interleaved with other chains on one stream,
-runs the same kernels on the same data as tm_lanczos_run, so its
-coefficients agree bit for bit; against the oracle the tolerance is the one
+A chain stepped in pieces, or interleaved with other chains (on one stream,
+or on the concurrent streams of the workspace slots), runs the same kernels
+on the same data as tm_lanczos_run, so its coefficients agree bit for bit; against the oracle the tolerance is the one
 of the Lanczos parity tests (1e-10 relative).
 """
 import numpy as np
@@ -82,6 +82,45 @@ def test_interleaved_chains_match_alone(lib, systems):
     for g, a, (_, _, _, m) in zip(got, alone, specs):
         assert g["steps_done"] == m
         same(g, a)
+
+
+def test_chain_slots_overlap_and_match(lib, systems):
+    """Chains of one small system spread over the workspace slots run on
+    concurrent streams inside tm_chains_step; each equals its chain run alone,
+    with the default slots and with one slot, and an apply issued between the
+    steps (on the caller's stream, in whichever slot is current) is unchanged."""
+    import torch
+    prob, h = systems["cubic20"]
+    specs = [("x", "pH", 18), ("y", "nH", 9), ("z", "pH", 24), ("+", "pH", 12), ("-", "nH", 6), ("n", "pH", 30)]
+    alone = [lib.tm_lanczos_run(h, 0, mu, f, m) for mu, f, m in specs]
+    info = lib.tm_qset_info_get(h, 0)
+    x = to_gpu(prob.random_projected(5), info["npw_pad"])
+    y0 = torch.empty_like(x)
+    lib.tm_liouvillian_apply(h, 0, x, y0)
+    for nslots in (4, 1, 4):
+        say(f"chains over {nslots} workspace slots")
+        lib.tm_system_set_chain_slots(h, nslots)
+        chains = [lib.tm_chain_begin(h, 0, mu, f, m) for mu, f, m in specs]
+        try:
+            with pytest.raises(lib.TmError):
+                lib.tm_system_set_chain_slots(h, 2)       # chains exist
+            lib.tm_chains_step(chains, 5)
+            y = torch.empty_like(x)
+            lib.tm_liouvillian_apply(h, 0, x, y)
+            lib.tm_chains_step(chains[::2], 7)
+            lib.tm_chains_step(chains, 100)
+            got = [lib.tm_chain_coeffs(c, m) for c, (_, _, m) in zip(chains, specs)]
+            torch.cuda.synchronize()
+        finally:
+            for c in chains:
+                lib.tm_chain_end(c)
+        assert torch.equal(y, y0)
+        for g, a, (_, _, m) in zip(got, alone, specs):
+            assert g["steps_done"] == m
+            same(g, a)
+    for bad in (0, 17):
+        with pytest.raises(lib.TmError):
+            lib.tm_system_set_chain_slots(h, bad)
 
 
 def test_graph_replay_matches_direct_issue(lib, systems):
