@@ -399,27 +399,28 @@ constexpr int kPotParts = 8;
 // with N and the radices known at compile time: P = product of the earlier radices
 constexpr int next_radix(int m) { return m % 4 == 0 ? 4 : m % 5 == 0 ? 5 : m % 3 == 0 ? 3 : 2; }
 
-template <int N, int P = 1, class LN>
-__device__ __forceinline__ void ct_fft(double2* lds, int nlines, const LN& ln, int estride, const double2* tw,
-                                       int sign) {
+// NL lines, NT threads: a thread takes at most ceil(NL N / R / NT) butterflies
+template <int N, int NL, int NT, int P = 1, class LN>
+__device__ __forceinline__ void ct_fft(double2* lds, const LN& ln, int estride, const double2* tw, int sign) {
     if constexpr (P < N) {
         constexpr int R = next_radix(N / P);
-        fft_pass<R>(lds, nlines, ln, estride, N, P, tw, sign);
-        ct_fft<N, P * R>(lds, nlines, ln, estride, tw, sign);
+        constexpr int BF = (NL * (N / R) + NT - 1) / NT;
+        fft_pass<R, BF>(lds, NL, ln, estride, N, P, tw, sign);
+        ct_fft<N, NL, NT, P * R>(lds, ln, estride, tw, sign);
     }
 }
 
 // 3D transform of the grid [i3][i1][i2] in LDS along i2, i1, i3; tw: the three
 // twiddle tables (lengths n1, n2, n3) one after the other.  N1 > 0: the sizes
 // are compile-time constants (the index arithmetic folds); else the plans'.
-template <int N1, int N2, int N3>
+template <int N1, int N2, int N3, int NT>
 __device__ void grid_fft(double2* g, int n1, int n2, int n3, const FFTPlan& p1, const FFTPlan& p2,
                          const FFTPlan& p3, const double2* tw, int sign) {
     if constexpr (N1 > 0) {
         constexpr int NP = N1 * N2;
-        ct_fft<N2>(g, N3 * N1, StrideLines{N2}, 1, tw + N1, sign);          // along i2: lines (i3, i1)
-        ct_fft<N1>(g, N3 * N2, GridLines{N2, NP, 1}, N2, tw, sign);         // along i1: lines (i3, i2)
-        ct_fft<N3>(g, NP, StrideLines{1}, NP, tw + N1 + N2, sign);          // along i3: over the plane
+        ct_fft<N2, N3 * N1, NT>(g, StrideLines{N2}, 1, tw + N1, sign);        // along i2: lines (i3, i1)
+        ct_fft<N1, N3 * N2, NT>(g, GridLines{N2, NP, 1}, N2, tw, sign);       // along i1: lines (i3, i2)
+        ct_fft<N3, NP, NT>(g, StrideLines{1}, NP, tw + N1 + N2, sign);        // along i3: over the plane
     } else {
         const int NP = n1 * n2;
         lds_fft_lines(g, n3 * n1, StrideLines{n2}, 1, p2, tw + n1, sign);
@@ -428,10 +429,16 @@ __device__ void grid_fft(double2* g, int n1, int n2, int n3, const FFTPlan& p1, 
     }
 }
 
+// threads of k_potential_lds: 1024 with compile-time sizes (few butterflies a
+// thread), kPotThreads for the generic kernel (kMaxBfly a thread)
+template <int N1>
+constexpr int pot_threads() { return N1 > 0 ? 1024 : kPotThreads; }
+
 template <int N1, int N2, int N3>
-__global__ void __launch_bounds__(kPotThreads) k_potential_lds(const double2* rho, const double* hq,
-                                                               const double* fxc, double2* W, int n1, int n2,
-                                                               int n3, FFTPlan p1, FFTPlan p2, FFTPlan p3) {
+__global__ void __launch_bounds__(pot_threads<N1>()) k_potential_lds(const double2* rho, const double* hq,
+                                                                     const double* fxc, double2* W, int n1, int n2,
+                                                                     int n3, FFTPlan p1, FFTPlan p2, FFTPlan p3) {
+    constexpr int NT = pot_threads<N1>();
     extern __shared__ double2 g[];
     if constexpr (N1 > 0) {
         n1 = N1;
@@ -465,7 +472,7 @@ __global__ void __launch_bounds__(kPotThreads) k_potential_lds(const double2* rh
         tw[i] = i < n1 ? p1.tw[i] : i < n1 + n2 ? p2.tw[i - n1] : p3.tw[i - n1 - n2];
     // element-wise loops in groups of U points a thread, loads first, so that a
     // thread's global loads are in flight together
-    constexpr int U = 4;
+    constexpr int U = NT >= 1024 ? 2 : 4;
     const int step = U * blockDim.x;
     for (int i0 = threadIdx.x; i0 < N; i0 += step) {
         double2 v[U];
@@ -481,7 +488,7 @@ __global__ void __launch_bounds__(kPotThreads) k_potential_lds(const double2* rh
         }
     }
     __syncthreads();
-    grid_fft<N1, N2, N3>(g, n1, n2, n3, p1, p2, p3, tw, -1);
+    grid_fft<N1, N2, N3, NT>(g, n1, n2, n3, p1, p2, p3, tw, -1);
     for (int i0 = threadIdx.x; i0 < N; i0 += step) {
         double h[U];
         double2 v[U];
@@ -498,7 +505,7 @@ __global__ void __launch_bounds__(kPotThreads) k_potential_lds(const double2* rh
         }
     }
     __syncthreads();
-    grid_fft<N1, N2, N3>(g, n1, n2, n3, p1, p2, p3, tw, +1);
+    grid_fft<N1, N2, N3, NT>(g, n1, n2, n3, p1, p2, p3, tw, +1);
     for (int i0 = threadIdx.x; i0 < N; i0 += step) {
         double2 r[U][4];
         double f[U][4];
@@ -537,14 +544,14 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) 
     const int rmin = std::min(min_radix(s.plan[0]), std::min(min_radix(s.plan[1]), min_radix(s.plan[2])));
     if (N <= kPotLdsMax && N / rmin <= (long long)kMaxBfly * kPotThreads) {
         const size_t shm = (size_t)(N + s.n1 + s.n2 + s.n3) * sizeof(double2);
-        auto kern = s.n1 == 20 && s.n2 == 20 && s.n3 == 20 ? k_potential_lds<20, 20, 20>
-                    : s.n1 == 8 && s.n2 == 8 && s.n3 == 8  ? k_potential_lds<8, 8, 8>
-                                                            : k_potential_lds<0, 0, 0>;
+        const bool c20 = s.n1 == 20 && s.n2 == 20 && s.n3 == 20, c8 = s.n1 == 8 && s.n2 == 8 && s.n3 == 8;
+        auto kern = c20 ? k_potential_lds<20, 20, 20> : c8 ? k_potential_lds<8, 8, 8> : k_potential_lds<0, 0, 0>;
+        const int nt = c20 || c8 ? pot_threads<20>() : pot_threads<0>();
         TM_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) ==
                      hipSuccess,
                  TM_EDEVICE, "cannot raise the LDS limit of k_potential_lds");
         ProfScope ps("k_potential_lds", st);
-        hipLaunchKernelGGL(kern, dim3(1 + kPotParts, nrhs), dim3(kPotThreads), shm, st, s.ws.rho, q.hq, s.fxc,
+        hipLaunchKernelGGL(kern, dim3(1 + kPotParts, nrhs), dim3(nt), shm, st, s.ws.rho, q.hq, s.fxc,
                            s.ws.W, s.n1, s.n2, s.n3, s.plan[0], s.plan[1], s.plan[2]);
         check_launch("k_potential_lds");
         return;

@@ -85,16 +85,17 @@ struct GridLines {
     }
 };
 
-template <int R, class LN>
+// BF: butterflies a thread takes, at most (nlines * n / R <= BF * blockDim.x)
+template <int R, int BF = kMaxBfly, class LN>
 __device__ inline void fft_pass(double2* lds, int nlines, const LN& ln, int estride, int n, int p,
                                 const double2* tw, int sign) {
     const int T = n / R;
     const int nb = nlines * T;
     const int twstep = n / (p * R);
-    double2 v[kMaxBfly][R];
-    int pos[kMaxBfly];
+    double2 v[BF][R];
+    int pos[BF];
 #pragma unroll
-    for (int bi = 0; bi < kMaxBfly; ++bi) {
+    for (int bi = 0; bi < BF; ++bi) {
         int b = threadIdx.x + bi * blockDim.x;
         pos[bi] = -1;
         if (b < nb) {
@@ -113,7 +114,7 @@ __device__ inline void fft_pass(double2* lds, int nlines, const LN& ln, int estr
     }
     __syncthreads();
 #pragma unroll
-    for (int bi = 0; bi < kMaxBfly; ++bi) {
+    for (int bi = 0; bi < BF; ++bi) {
         if (pos[bi] >= 0) {
             dft_small<R>(v[bi], sign);
 #pragma unroll
