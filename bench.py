@@ -202,6 +202,7 @@ def run_qpath(args, tm, torch):
     desc = tm.SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=sysd.nbnd, points=pts, vrs=inp["vrs"],
                          rho=inp["rho"], dvan=inp["dvan"], xq=inp["xq"], roles=inp["roles"], shifts=inp["shifts"])
     h = tm.tm_system_create(desc)
+    tm.tm_system_set_chain_slots(h, args.chain_slots)
     m = args.chain_steps
     omega = np.arange(400) * 5e-3 / EV
     eta = 5e-3 / EV
@@ -353,6 +354,8 @@ def main():
     ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
     ap.add_argument("--serving-lanes", type=int, default=4, choices=[1, 2, 3, 4],
                     help="serving: pending requests of one system, q set and flavour share a chain (lanes)")
+    ap.add_argument("--chain-slots", type=int, default=3,
+                    help="qpath: concurrent workspace slots for the system's chains")
     ap.add_argument("--serving-chain-slots", type=int, default=1,
                     help="serving: concurrent workspace slots per system (1: its chains on its stream)")
     ap.add_argument("--serving-max-chains", type=int, default=4,

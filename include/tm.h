@@ -260,7 +260,7 @@ int tm_tensor_run(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavo
  *   asynchronous.  Chains may belong to different systems, but all work of
  *   one system must be issued on one stream at a time (its chains share the
  *   system's apply workspaces).  The chains of a system whose apply
- *   workspace is small (at most 256 MB) are spread over up to 4 workspace
+ *   workspace is small (at most 256 MB) are spread over up to 3 workspace
  *   slots (see tm_system_set_chain_slots): slot 0 runs on `stream`, the other
  *   slots on library streams that wait for the work issued on `stream` before
  *   the call and that `stream` waits for before anything issued after it, so
@@ -299,7 +299,7 @@ int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, t
                          int capacity, void* stream, tm_chain** out);
 int tm_chain_lanes(const tm_chain* chain, int* lanes);
 int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream);
-/* tm_system_set_chain_slots: at most nslots (1..16, default 4) workspace
+/* tm_system_set_chain_slots: at most nslots (1..16, default 3) workspace
  * slots for the chains of sys begun afterwards; 1 runs all of them on the
  * caller's stream (for a caller that overlaps systems on streams of its
  * own).  Each slot holds its own apply workspace.  TM_EINVAL while chains of

@@ -243,7 +243,7 @@ struct System {
     hipEvent_t fork_event = nullptr;
     int wcur = 0;
     int nslots = 0;                    // decided at the first chain
-    int slot_cap = 4;                  // at most this many (tm_system_set_chain_slots)
+    int slot_cap = 3;                  // at most this many (tm_system_set_chain_slots)
     int next_slot = 0;
     std::vector<void*> allocs;
 };
