@@ -93,6 +93,56 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     }
 }
 
+// Small contractions (a few output tiles, K of at most kSmallK): one block
+// per (tile, batch); its waves take interleaved K slices of 4 and their
+// 16 x 16 accumulators are added in wave order through LDS, so the result
+// goes straight to `out` with no partial buffer and no second launch.
+constexpr int kSmallWaves = 8;
+constexpr int kSmallK = 4096;
+
+template <class R>
+__global__ void __launch_bounds__(64 * kSmallWaves) k_gemm_cn_small(GemmCN g, double2* out) {
+    __shared__ double2 red[kSmallWaves][256];
+    const int b = blockIdx.y, tile = blockIdx.x;
+    const int m0 = (tile / g.nt) * 16, n0 = (tile % g.nt) * 16;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, kk = l >> 4;
+    const double2* A = g.A_tab ? g.A_tab[b % g.amod] : g.A_base + (long long)b * g.a_bstride;
+    const double2* B = g.B_base + (long long)b * g.b_bstride;
+    typename MF<R>::V cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+    const bool arow = (m0 + i) < g.M, brow = (n0 + i) < g.Nn;
+    const double2* Ap = A + (long long)(m0 + i) * g.lda;
+    const double2* Bp = B + (long long)(n0 + i) * g.ldb;
+    // KU slices a wave's loads are in flight together
+    constexpr int KU = 4, KS = 4 * kSmallWaves;
+    for (int k0 = 4 * w; k0 < g.K; k0 += KU * KS) {
+        double2 a[KU], bv[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int kx = k0 + u * KS + kk;
+            a[u] = (arow && kx < g.K) ? Ap[kx] : cmk(0.0, 0.0);
+            bv[u] = (brow && kx < g.K) ? Bp[kx] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const R ax = (R)a[u].x, ay = (R)a[u].y, bx = (R)bv[u].x, by = (R)bv[u].y;
+            cr = mfma(ax, bx, cr);
+            cr = mfma(ay, by, cr);
+            ci = mfma(ax, by, ci);
+            ci = mfma(-ay, bx, ci);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[w][MF<R>::row(v, kk) * 16 + i] = cmk((double)cr[v], (double)ci[v]);
+    __syncthreads();
+    if (threadIdx.x < 256) {
+        const int m = m0 + threadIdx.x / 16, n = n0 + (threadIdx.x & 15);
+        double2 sum = red[0][threadIdx.x];
+#pragma unroll
+        for (int v = 1; v < kSmallWaves; ++v) sum = cadd(sum, red[v][threadIdx.x]);
+        if (m < g.M && n < g.Nn) out[((long long)b * g.M + m) * g.Nn + n] = sum;
+    }
+}
+
 // The same contraction with both operands of a K-chunk staged in LDS: one
 // block per (batch, K split) computes every 16x16 output tile from LDS (waves
 // take tiles in turn), so each operand element is read from memory once
@@ -318,6 +368,15 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
     int mt = (M + 15) / 16;
     g.nt = (Nn + 15) / 16;
     g.part = s.ws.gpart;
+    if (!cn_lds_fits(M, Nn) && K <= kSmallK) {
+        dim3 grid(mt * g.nt, nrhs * nbatch);
+        if (f32) {
+            TM_LAUNCH(k_gemm_cn_small<float>, grid, dim3(64 * kSmallWaves), 0, st, g, out);
+        } else {
+            TM_LAUNCH(k_gemm_cn_small<double>, grid, dim3(64 * kSmallWaves), 0, st, g, out);
+        }
+        return;
+    }
     if (cn_lds_fits(M, Nn)) {
         g.kchunk = cn_lds_kchunk(K, nbatch);
         g.ksplit = (K + g.kchunk - 1) / g.kchunk;
