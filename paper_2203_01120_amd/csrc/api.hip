@@ -654,7 +654,7 @@ static void chain_alloc(Chain& c) {
     c.co.z = static_cast<double2*>(c.alloc(L * kNMeasure * cap * sizeof(double2)));
     c.cs = static_cast<ChainState*>(c.alloc(L * sizeof(ChainState)));
     c.dots = static_cast<double2*>(c.alloc(L * kDotStride * sizeof(double2)));
-    c.part = static_cast<double2*>(c.alloc(L * 1024 * 8 * sizeof(double2)));
+    c.part = static_cast<double2*>(c.alloc(L * kPartBlocks * 8 * sizeof(double2)));
 }
 
 static void chain_clear_coeffs(Chain& c, hipStream_t st) {
@@ -739,14 +739,18 @@ static void chain_step(Chain& c, hipStream_t st) {
     const double2* uc[kNMeasure] = {c.u[0], c.u[1], c.u[2], c.u[3]};
     if (c.flavour == TM_PSEUDOHERMITIAN) {
         double2 *QP = c.V(0), *Q = c.V(1), *LQ = c.V(2), *R = c.V(3), *LR = c.V(4);
-        run_ph_update(c.cs, LQ, Q, QP, R, uc, n, c.w, c.part, d + 8, st, L);
+        // block partials of the update's (u_l, r) and, further on, of the
+        // multidot, side by side in c.part; both summed by the step control
+        double2* part_up = c.part;
+        double2* part_md = c.part + (size_t)L * kPartBlocks * kNMeasure;
+        run_ph_update(c.cs, LQ, Q, QP, R, uc, n, part_up, st, L);
         // back onto the empty manifold: removes rounding-level occupied parts
         // that the metric JL cannot see (identity in exact arithmetic)
         launch_project_signed(s, s.qs[c.iq], R, 1.0, 1.0, st, false, L);
         apply_l(s, c.iq, R, LR, c.fp32, st, L);
         DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}, {n, n, n}, {n, n, n}};
-        run_multidot<3>(ds, n, half, c.w, c.part, d, st, L);
-        ctl_ph_step(c.cs, d, d + 8, c.co, st, L);
+        run_multidot<3>(ds, n, half, c.w, part_md, d, st, L, false);
+        ctl_ph_step_sums(c.cs, part_md, part_up, n, c.w, d, d + 8, c.co, st, L);
         // q_prev <- q, q <- r, Lq <- Lr; the old q_prev and Lq become scratch
         const int oqp = c.ix[0], olq = c.ix[2];
         c.ix[0] = c.ix[1];
@@ -764,10 +768,10 @@ static void chain_step(Chain& c, hipStream_t st) {
         run_jcopy(Pv, TMP, n, half, st, L);
         apply_l(s, c.iq, TMP, LTP, c.fp32, st, L);
         DotSet<1> da{{Pv}, {LQ}, {0}, {n}, {n}};
-        run_multidot<1>(da, n, half, c.w, c.part, d, st, L);
-        ctl_nh_alpha(c.cs, d, c.co, st, L);
-        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, c.w, c.part, d + 8, st, L);
-        ctl_nh_step(c.cs, d + 8, c.co, st, L);
+        run_multidot<1>(da, n, half, c.w, c.part, d, st, L, false);
+        ctl_nh_alpha_sums(c.cs, c.part, n, c.w, d, c.co, st, L);
+        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, c.part, st, L);
+        ctl_nh_step_sums(c.cs, c.part, n, c.w, d + 8, c.co, st, L);
         // q_prev <- q, q <- q^, p_prev <- p, p <- p^
         const int oqp = c.ix[0], opp = c.ix[2];
         c.ix[0] = c.ix[1];

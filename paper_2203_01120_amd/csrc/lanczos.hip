@@ -23,7 +23,7 @@ namespace tml {
 namespace {
 
 constexpr int kRedThreads = 256;
-constexpr int kRedBlocks = 1024;
+constexpr int kRedBlocks = kPartBlocks;
 
 __device__ inline double2 wave_sum(double2 v) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -227,12 +227,8 @@ __global__ void k_ph_start(ChainState* cs, const double2* d, Coeffs co) {
     for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap] = cscale(d[3 + l], 1.0 / n1);
 }
 
-// pH after the apply; d: (r, J Lr), (r, r), (Lr, J Lr); zu: (u_l, r)
-__global__ void k_ph_step(ChainState* cs, const double2* d, const double2* zu, Coeffs co) {
-    cs += threadIdx.x;
-    d += threadIdx.x * kDotStride;
-    zu += threadIdx.x * kDotStride;
-    co = co.lane(threadIdx.x);
+// pH after the apply, one lane; d: (r, J Lr), (r, r), (Lr, J Lr); zu: (u_l, r)
+__device__ void ph_step_lane(ChainState* cs, const double2* d, const double2* zu, Coeffs co) {
     const int j = cs->step;
     if (cs->broken || j >= co.cap) return;
     const double b2 = d[0].x, rr = d[1].x, ll = d[2].x;
@@ -280,22 +276,16 @@ __global__ void k_nh_start(ChainState* cs, const double2* d, Coeffs co) {
     for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap] = cscale(d[1 + l], 1.0 / n1);
 }
 
-// nH alpha from (P_raw, LQ_raw)
-__global__ void k_nh_alpha(ChainState* cs, const double2* d, Coeffs co) {
-    cs += threadIdx.x;
-    d += threadIdx.x * kDotStride;
-    co = co.lane(threadIdx.x);
+// nH alpha from (P_raw, LQ_raw), one lane
+__device__ void nh_alpha_lane(ChainState* cs, const double2* d, Coeffs co) {
     const int j = cs->step;
     if (cs->broken || j >= co.cap) return;
     cs->alpha = cmul(cmul(cconj(cs->sp), cs->sq), d[0]);
     co.alpha[j] = cs->alpha;
 }
 
-// nH after the update; d: (ph, qh), (qh, qh), (ph, ph), (u_l, qh)
-__global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
-    cs += threadIdx.x;
-    d += threadIdx.x * kDotStride;
-    co = co.lane(threadIdx.x);
+// nH after the update, one lane; d: (ph, qh), (qh, qh), (ph, ph), (u_l, qh)
+__device__ void nh_step_lane(ChainState* cs, const double2* d, Coeffs co) {
     const int j = cs->step;
     if (cs->broken || j >= co.cap) return;
     const double2 s = d[0];
@@ -326,47 +316,89 @@ __global__ void k_nh_step(ChainState* cs, const double2* d, Coeffs co) {
         for (int l = 0; l < kNMeasure; ++l) co.z[l * co.cap + j + 1] = cs->znext[l];
 }
 
+// The final sums of the block partials (as k_dot_final) folded into the
+// control step that consumes them: block = lane blockIdx.x, wave v sums
+// value v; the sums also go to the inner-product array (out + lane kDotStride).
+__device__ inline void final_into(const double2* part, int nblk, int nd, int v, double w, double2* out,
+                                  double2* sh) {
+    const int l = threadIdx.x & 63, r = blockIdx.x;
+    part += (long long)r * nblk * nd;
+    double2 s = cmk(0.0, 0.0);
+    for (int b = l; b < nblk; b += 64) s = cadd(s, part[(long long)b * nd + v]);
+    s = wave_sum(s);
+    if (l == 0) {
+        s = cscale(s, w);
+        out[r * kDotStride + v] = s;
+        sh[v] = s;
+    }
+}
+
+// pH: waves 0-2 the multidot (r, J Lr), (r, r), (Lr, J Lr); waves 3-6 the
+// update's (u_l, r); then the step
+__global__ void __launch_bounds__(64 * (3 + kNMeasure)) k_ph_step_sums(ChainState* cs, const double2* part_md,
+                                                                        const double2* part_up, int nblk, double w,
+                                                                        double2* d, double2* zu, Coeffs co) {
+    __shared__ double2 sh[3 + kNMeasure];
+    const int v = threadIdx.x >> 6;
+    if (v < 3) final_into(part_md, nblk, 3, v, w, d, sh);
+    else final_into(part_up, nblk, kNMeasure, v - 3, w, zu, sh + 3);
+    __syncthreads();
+    if (threadIdx.x == 0) ph_step_lane(cs + blockIdx.x, sh, sh + 3, co.lane(blockIdx.x));
+}
+
+__global__ void __launch_bounds__(64) k_nh_alpha_sums(ChainState* cs, const double2* part, int nblk, double w,
+                                                      double2* d, Coeffs co) {
+    __shared__ double2 sh[1];
+    final_into(part, nblk, 1, 0, w, d, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) nh_alpha_lane(cs + blockIdx.x, sh, co.lane(blockIdx.x));
+}
+
+__global__ void __launch_bounds__(64 * (3 + kNMeasure)) k_nh_step_sums(ChainState* cs, const double2* part,
+                                                                        int nblk, double w, double2* d, Coeffs co) {
+    __shared__ double2 sh[3 + kNMeasure];
+    final_into(part, nblk, 3 + kNMeasure, threadIdx.x >> 6, w, d, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) nh_step_lane(cs + blockIdx.x, sh, co.lane(blockIdx.x));
+}
+
 }  // namespace
 
 // ---- host-side launch helpers ----------------------------------------------------
 
 template <int ND>
 void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
-                  hipStream_t st, int lanes) {
+                  hipStream_t st, int lanes, bool final) {
     int nblk = (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
     TM_LAUNCH(k_multidot<ND>, dim3(nblk, lanes), dim3(kRedThreads), 0, st, ds, n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * ND), 0, st, part, nblk, ND, w, out);
+    if (final) TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * ND), 0, st, part, nblk, ND, w, out);
 }
 template void run_multidot<1>(const DotSet<1>&, long long, long long, double, double2*, double2*, hipStream_t,
-                                  int);
+                                  int, bool);
 template void run_multidot<3>(const DotSet<3>&, long long, long long, double, double2*, double2*, hipStream_t,
-                                  int);
+                                  int, bool);
 template void run_multidot<5>(const DotSet<5>&, long long, long long, double, double2*, double2*, hipStream_t,
-                                  int);
+                                  int, bool);
 template void run_multidot<7>(const DotSet<7>&, long long, long long, double, double2*, double2*, hipStream_t,
-                                  int);
+                                  int, bool);
 
 static int red_blocks(long long n) {
     return (int)std::min<long long>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
 }
 
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
-                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st,
-                   int lanes) {
+                   const double2* const* u, long long n, double2* part, hipStream_t st, int lanes) {
     int nblk = red_blocks(n);
     TM_LAUNCH(k_ph_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3], n,
               part);
-    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * kNMeasure), 0, st, part, nblk, kNMeasure, w, out);
 }
 
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
-                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st,
-                   int lanes) {
+                   long long n, long long half, double2* part, hipStream_t st, int lanes) {
     int nblk = red_blocks(n);
     TM_LAUNCH(k_nh_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0],
               u[1], u[2], u[3], n, half, part);
-    TM_LAUNCH(k_dot_final, dim3(lanes), dim3(64 * (3 + kNMeasure)), 0, st, part, nblk, 3 + kNMeasure, w, out);
 }
 
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes) {
@@ -376,18 +408,21 @@ void run_jcopy(const double2* src, double2* dst, long long n, long long half, hi
 void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
     TM_LAUNCH(k_ph_start, dim3(1), dim3(lanes), 0, st, cs, d, co);
 }
-void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st,
-                 int lanes) {
-    TM_LAUNCH(k_ph_step, dim3(1), dim3(lanes), 0, st, cs, d, zu, co);
+void ctl_ph_step_sums(ChainState* cs, const double2* part_md, const double2* part_up, long long n, double w,
+                      double2* d, double2* zu, const Coeffs& co, hipStream_t st, int lanes) {
+    TM_LAUNCH(k_ph_step_sums, dim3(lanes), dim3(64 * (3 + kNMeasure)), 0, st, cs, part_md, part_up, red_blocks(n), w,
+              d, zu, co);
 }
 void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
     TM_LAUNCH(k_nh_start, dim3(1), dim3(lanes), 0, st, cs, d, co);
 }
-void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
-    TM_LAUNCH(k_nh_alpha, dim3(1), dim3(lanes), 0, st, cs, d, co);
+void ctl_nh_alpha_sums(ChainState* cs, const double2* part, long long n, double w, double2* d, const Coeffs& co,
+                       hipStream_t st, int lanes) {
+    TM_LAUNCH(k_nh_alpha_sums, dim3(lanes), dim3(64), 0, st, cs, part, red_blocks(n), w, d, co);
 }
-void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes) {
-    TM_LAUNCH(k_nh_step, dim3(1), dim3(lanes), 0, st, cs, d, co);
+void ctl_nh_step_sums(ChainState* cs, const double2* part, long long n, double w, double2* d, const Coeffs& co,
+                      hipStream_t st, int lanes) {
+    TM_LAUNCH(k_nh_step_sums, dim3(lanes), dim3(64 * (3 + kNMeasure)), 0, st, cs, part, red_blocks(n), w, d, co);
 }
 
 }  // namespace tml

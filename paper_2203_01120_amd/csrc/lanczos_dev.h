@@ -15,6 +15,8 @@ constexpr int kMaxLanes = 4;
 // reduced inner products kept per lane (a lane is one recursion of a chain
 // that runs several field directions together)
 constexpr int kDotStride = 16;
+// blocks of an inner-product kernel, at most (one partial per block and value)
+constexpr int kPartBlocks = 1024;
 
 // one lane's scalars; true vector = scale * raw vector
 struct ChainState {
@@ -58,24 +60,29 @@ struct DotSet {
 // All helpers below work on `lanes` lanes at once: lane r's vectors at + r n,
 // its state at cs + r, its inner products at out + r kDotStride, its partial
 // sums at part + r (blocks x values); the measure vectors u are shared.
+// final = false: only the block partials (a *_sums control step adds them)
 template <int ND>
 void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
-                  hipStream_t st, int lanes = 1);
+                  hipStream_t st, int lanes = 1, bool final = true);
+// the updates write the block partials of their inner products to part
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
-                   const double2* const* u, long long n, double w, double2* part, double2* out, hipStream_t st,
-                   int lanes = 1);
+                   const double2* const* u, long long n, double2* part, hipStream_t st, int lanes = 1);
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
-                   long long n, long long half, double w, double2* part, double2* out, hipStream_t st,
-                   int lanes = 1);
+                   long long n, long long half, double2* part, hipStream_t st, int lanes = 1);
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes = 1);
 void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
-// the step index comes from cs->step (device side), so step sequences can be
-// replayed from a graph; steps past co.cap are ignored
-void ctl_ph_step(ChainState* cs, const double2* d, const double2* zu, const Coeffs& co, hipStream_t st,
-                 int lanes = 1);
+// The step controls add the block partials of their inner products (over
+// vectors of n elements, weight w) in a fixed order, store the sums at
+// d (zu) + lane kDotStride, and update the state.  The step index comes from
+// cs->step (device side), so step sequences can be replayed from a graph;
+// steps past co.cap are ignored.
+void ctl_ph_step_sums(ChainState* cs, const double2* part_md, const double2* part_up, long long n, double w,
+                      double2* d, double2* zu, const Coeffs& co, hipStream_t st, int lanes = 1);
 void ctl_nh_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
-void ctl_nh_alpha(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
-void ctl_nh_step(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
+void ctl_nh_alpha_sums(ChainState* cs, const double2* part, long long n, double w, double2* d, const Coeffs& co,
+                       hipStream_t st, int lanes = 1);
+void ctl_nh_step_sums(ChainState* cs, const double2* part, long long n, double w, double2* d, const Coeffs& co,
+                      hipStream_t st, int lanes = 1);
 
 }  // namespace tml
