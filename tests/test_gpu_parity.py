@@ -110,6 +110,28 @@ def test_apply_generic_plane_path(lib):
         s.close()
 
 
+@pytest.mark.parametrize("fft", [(12, 10, 8), (24, 20, 18)], ids=["12x10x8", "24x20x18"])
+def test_apply_noncubic_grids(lib, fft):
+    """Grid sides that differ (n1 != n2 != n3): the generic plane kernels and z
+    passes, and the response potential on the in-LDS path (960 points) and on
+    the line-FFT path (8640 points), where a swapped axis would show."""
+    import synth
+    from oracle import scf
+    say(f"apply tiny {fft} (non-cubic grid)")
+    gs = scf.scf(synth.make_tiny(fft=fft, seed=3), tol=1e-12, beta=0.5)
+    s = Sys(lib, lv.build_problem(gs, np.array([0.05, 0.1, 0.0]) * 2 * np.pi / 6.0))
+    try:
+        for seed in (1, 2):
+            x = s.prob.random_projected(seed)
+            got, _ = s.apply(x)
+            assert rel_err(got, s.prob.apply(x)) <= 1e-12
+        got = lib.tm_lanczos_run(s.h, 0, "+", "pH", 10)
+        ref = olanczos.run(s.prob, "+", "pH", 10)
+        assert np.abs(got["beta"] - ref["beta"]).max() <= 1e-10 * ref["beta"].max()
+    finally:
+        s.close()
+
+
 def test_apply_many_bands_staged_contractions(lib):
     """48 bands: the projector contractions have 3 x 3 output tiles, enough for
     the LDS-staged kernel the benchmark system runs; synthetic occupied
