@@ -410,13 +410,50 @@ __device__ __forceinline__ void ct_fft(double2* lds, const LN& ln, int estride, 
     }
 }
 
+// Length-20 transform of whole lines in registers, one thread per line
+// (n = 5 n1 + n2, k = k1 + 4 k2: four-point transforms over n1, the twiddles
+// w20^(n2 k1), five-point transforms over n2), so an axis costs one LDS round
+// trip instead of two radix passes; natural order in and out.  tw: the table
+// exp(-2 pi i j / 20).  Ends with a barrier.
+template <int NL, class LN>
+__device__ __forceinline__ void line_dft20(double2* lds, const LN& ln, int estride, const double2* tw, int sign) {
+    for (int l = threadIdx.x; l < NL; l += blockDim.x) {
+        double2* base = lds + ln.base(l);
+        double2 z[5][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 5; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) z[n2][n1] = base[(5 * n1 + n2) * estride];
+            dft_small<4>(z[n2], sign);
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1)
+                if (n2 > 0) z[n2][k1] = cmul(z[n2][k1], twiddle(tw, n2 * k1, sign));
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            double2 v[5];
+#pragma unroll
+            for (int n2 = 0; n2 < 5; ++n2) v[n2] = z[n2][k1];
+            dft_small<5>(v, sign);
+#pragma unroll
+            for (int k2 = 0; k2 < 5; ++k2) base[(k1 + 4 * k2) * estride] = v[k2];
+        }
+    }
+    __syncthreads();
+}
+
 // 3D transform of the grid [i3][i1][i2] in LDS along i2, i1, i3; tw: the three
 // twiddle tables (lengths n1, n2, n3) one after the other.  N1 > 0: the sizes
 // are compile-time constants (the index arithmetic folds); else the plans'.
 template <int N1, int N2, int N3, int NT>
 __device__ void grid_fft(double2* g, int n1, int n2, int n3, const FFTPlan& p1, const FFTPlan& p2,
                          const FFTPlan& p3, const double2* tw, int sign) {
-    if constexpr (N1 > 0) {
+    if constexpr (N1 == 20 && N2 == 20 && N3 == 20) {
+        constexpr int NP = N1 * N2;
+        line_dft20<N3 * N1>(g, StrideLines{N2}, 1, tw + N1, sign);
+        line_dft20<N3 * N2>(g, GridLines{N2, NP, 1}, N2, tw, sign);
+        line_dft20<NP>(g, StrideLines{1}, NP, tw + N1 + N2, sign);
+    } else if constexpr (N1 > 0) {
         constexpr int NP = N1 * N2;
         ct_fft<N2, N3 * N1, NT>(g, StrideLines{N2}, 1, tw + N1, sign);        // along i2: lines (i3, i1)
         ct_fft<N1, N3 * N2, NT>(g, GridLines{N2, NP, 1}, N2, tw, sign);       // along i1: lines (i3, i2)
@@ -429,10 +466,11 @@ __device__ void grid_fft(double2* g, int n1, int n2, int n3, const FFTPlan& p1, 
     }
 }
 
-// threads of k_potential_lds: 1024 with compile-time sizes (few butterflies a
-// thread), kPotThreads for the generic kernel (kMaxBfly a thread)
+// threads of k_potential_lds: 512 for 20^3 (a line of 20 a thread, 400 lines
+// an axis), 1024 for other compile-time sizes (few butterflies a thread),
+// kPotThreads for the generic kernel (kMaxBfly a thread)
 template <int N1>
-constexpr int pot_threads() { return N1 > 0 ? 1024 : kPotThreads; }
+constexpr int pot_threads() { return N1 == 20 ? 512 : N1 > 0 ? 1024 : kPotThreads; }
 
 template <int N1, int N2, int N3>
 __global__ void __launch_bounds__(pot_threads<N1>()) k_potential_lds(const double2* rho, const double* hq,
@@ -546,7 +584,7 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) 
         const size_t shm = (size_t)(N + s.n1 + s.n2 + s.n3) * sizeof(double2);
         const bool c20 = s.n1 == 20 && s.n2 == 20 && s.n3 == 20, c8 = s.n1 == 8 && s.n2 == 8 && s.n3 == 8;
         auto kern = c20 ? k_potential_lds<20, 20, 20> : c8 ? k_potential_lds<8, 8, 8> : k_potential_lds<0, 0, 0>;
-        const int nt = c20 || c8 ? pot_threads<20>() : pot_threads<0>();
+        const int nt = c20 ? pot_threads<20>() : c8 ? pot_threads<8>() : pot_threads<0>();
         TM_CHECK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm) ==
                      hipSuccess,
                  TM_EDEVICE, "cannot raise the LDS limit of k_potential_lds");
