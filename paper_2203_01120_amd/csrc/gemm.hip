@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
 // per (tile, batch); its waves take interleaved K slices of 4 and their
 // 16 x 16 accumulators are added in wave order through LDS, so the result
 // goes straight to `out` with no partial buffer and no second launch.
-constexpr int kSmallWaves = 8;
+constexpr int kSmallWaves = 16;
 constexpr int kSmallK = 4096;
 
 template <class R>
