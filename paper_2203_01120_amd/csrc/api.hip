@@ -468,7 +468,12 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
         npw_pad = std::max(npw_pad, q.npw_pad);
     }
     long long blocks_per_chunk = (long long)s.n3 * nb2;
-    w.nchunk = (int)std::min<long long>(nb, std::max<long long>(1, (2048 + blocks_per_chunk - 1) / blocks_per_chunk));
+    // band chunks of the plane kernels: about 2048 blocks per right-hand side,
+    // but at least two bands per chunk (a block's set-up is then shared; on the
+    // 20^3 system 4 chunks of 2 bands: 7515 applies/s, 8 of 1: 7219); grids
+    // with many planes and sides get one chunk
+    w.nchunk = (int)std::min<long long>(std::max(1, nb / 2),
+                                        std::max<long long>(1, (2048 + blocks_per_chunk - 1) / blocks_per_chunk));
     const size_t R = (size_t)nrhs;
     w.cap_xcols = R * nb2 * 2 * nb * s.n3 * ncol_max;
     w.cap_rho_part = R * nb2 * w.nchunk * 4 * s.N;
