@@ -38,16 +38,18 @@ def requests(sv, omega, eta, stagger):
                        arrival=stagger * i) for i, (s, d, f, m) in enumerate(spec)]
 
 
-@pytest.mark.parametrize("stagger,lanes,slack,cap", [(0.0, 1, 1.0, 0), (0.02, 1, 1.0, 0), (0.0, 4, 2.0, 0),
-                                                     (0.0, 4, 4.0, 1)])
-def test_server_chi_identical_to_alone(pool, stagger, lanes, slack, cap):
+@pytest.mark.parametrize("stagger,lanes,slack,cap,cslots", [(0.0, 1, 1.0, 0, 1), (0.02, 1, 1.0, 0, 1),
+                                                            (0.0, 4, 2.0, 0, 1), (0.0, 4, 4.0, 1, 1),
+                                                            (0.0, 1, 1.0, 0, 3)])
+def test_server_chi_identical_to_alone(pool, stagger, lanes, slack, cap, cslots):
     tm, sv, slots = pool
     omega = np.linspace(0.0, 0.07, 64)
     eta = 2e-4
     # a budget of about two cubic20 chains forces admissions to wait
     budget = 2 * sv.chain_bytes(slots["cubic20"].nelem[0], "nH", 30)
-    say(f"server run, stagger {stagger}, lanes {lanes}, chains per system {cap}, budget {budget} B")
-    server = sv.Server(slots, budget_bytes=budget, lanes=lanes, lane_slack=slack, max_chains=cap)
+    say(f"server run, stagger {stagger}, lanes {lanes}, chains per system {cap}, slots {cslots}, budget {budget} B")
+    server = sv.Server(slots, budget_bytes=budget, lanes=lanes, lane_slack=slack, max_chains=cap,
+                       chain_slots=cslots)
     peak = [0]
     widest = [1]
     orig = server._admit
