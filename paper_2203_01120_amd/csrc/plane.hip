@@ -1092,7 +1092,9 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
     // one buffer with 6 or 8 columns, or 6 waves per SIMD, spill in FP64).  The
     // single-precision apply at 48 x 48 runs 6 columns per wave and 4 waves per
     // SIMD (2 blocks per CU in 2 x 81 KB of LDS, no spills): 7 % faster.
-    constexpr int CPW = 4, CPW32 = 4, CPWA32 = N2 == 48 ? 6 : 4;
+    // 20 x 20 planes: 5 columns per wave (4 waves), 1-2 % faster than 4 (5 waves) on
+    // the 20^3 system, 2 columns 7 % slower
+    constexpr int CPW = N2 == 20 ? 5 : 4, CPW32 = N2 == 20 ? 5 : 4, CPWA32 = N2 == 48 ? 6 : N2 == 20 ? 5 : 4;
     constexpr int BTD = 2, BTA = 2;
     constexpr int NBUF = 2, MINW = 1, NBUF32 = 2, MINW32 = 1, MINWA32 = N2 == 48 ? 4 : 1;
     // Row fill with all of a lane's loads in flight together (FCH = 64) in the
