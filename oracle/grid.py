@@ -7,10 +7,27 @@ Bloch spinors).  On the FFT grid the sum is a plain backward DFT, so
 ``from_grid`` is its inverse, c(G) = (1/N) sum_j f(r_j) exp(-iG.r_j).
 Products of grid functions are therefore circular convolutions in G, which
 is how the operator is defined at finite grid size.
+
+The transforms are scipy.fft's (the same discrete Fourier sums as numpy.fft,
+pinned against a direct DFT sum in the tests), run on every host thread the
+process may use.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import scipy.fft as sfft
+
+WORKERS = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+
+
+def _fftn(a, axes=None):
+    return sfft.fftn(a, axes=axes, workers=WORKERS)
+
+
+def _ifftn(a, axes=None):
+    return sfft.ifftn(a, axes=axes, workers=WORKERS)
 
 
 def grid_index(fft, mill):
@@ -26,19 +43,19 @@ def to_grid(fft, mill, coef):
     g = np.zeros(lead + tuple(fft), dtype=np.complex128)
     i1, i2, i3 = grid_index(fft, mill)
     g[..., i1, i2, i3] = coef
-    return np.fft.ifftn(g, axes=(-3, -2, -1)) * np.prod(fft)
+    return _ifftn(g, axes=(-3, -2, -1)) * np.prod(fft)
 
 
 def from_grid(fft, mill, f):
     """f [..., n1, n2, n3] -> c [..., npw] = (1/N) sum_j f(r_j) e^{-iG.r_j}."""
-    F = np.fft.fftn(f, axes=(-3, -2, -1)) / np.prod(fft)
+    F = _fftn(f, axes=(-3, -2, -1)) / np.prod(fft)
     i1, i2, i3 = grid_index(fft, mill)
     return F[..., i1, i2, i3]
 
 
 def field_fourier(f):
     """Fourier coefficients F[m mod n] = (1/N) sum_j f(r_j) e^{-iG.r_j} of a grid field."""
-    return np.fft.fftn(f, axes=(-3, -2, -1)) / f.shape[-1] / f.shape[-2] / f.shape[-3]
+    return _fftn(f, axes=(-3, -2, -1)) / f.shape[-1] / f.shape[-2] / f.shape[-3]
 
 
 def grid_gvectors(sysd):
@@ -71,7 +88,7 @@ def coulomb_multiplier(sysd, qcart):
 
 def apply_coulomb(h, f):
     """Grid function f -> inverse FFT of h(G) * FFT(f)."""
-    return np.fft.ifftn(h * np.fft.fftn(f))
+    return _ifftn(h * _fftn(f))
 
 
 def miller_lookup(mill):

@@ -11,7 +11,9 @@ def say(msg):
     sys.stdout.flush()
 
 
-def desc_from_problem(prob):
+def desc_from_problem(prob, rho=None):
+    """Library inputs for an oracle Problem; `rho` replaces the ground-state
+    density and magnetisation that the kernel fields are built from."""
     from paper_2203_01120_amd import Point, SystemDesc
     sysd = prob.sysd
     nb = prob.nb
@@ -20,7 +22,8 @@ def desc_from_problem(prob):
         mill, evc, et = prob.point_states[i]
         pts.append(Point(xk=np.asarray(p, float), mill=mill, evc=evc[:nb], et=np.asarray(et[:nb]),
                          vkb=synth.projector_table(sysd, p, mill)))
-    return SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=nb, points=pts, vrs=prob.vrs, rho=prob.gs.rho,
+    return SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=nb, points=pts, vrs=prob.vrs,
+                      rho=prob.gs.rho if rho is None else rho,
                       dvan=synth.dmatrix(sysd), xq=np.asarray(prob.qset.q)[None],
                       roles=np.asarray(prob.qset.roles)[None], shifts=np.asarray(prob.qset.shifts)[None])
 

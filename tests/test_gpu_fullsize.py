@@ -1,7 +1,22 @@
-"""The benchmark system at full size (48 x 48 x 180 grid, 104 bands, 36 k
-points), in the launch configuration the benchmark times (resident ground
-state, wave plane kernels, LDS-staged contractions).  The oracle cannot apply
-L at this size, so the checks are properties that hold at any size:
+"""The benchmark system at full size: 48 x 48 x 180 grid, 104 bands, in the
+launch configuration the benchmark times (resident real-space ground state,
+wave plane kernels, the 180-point z passes, LDS-staged contractions with
+7 x 7 output tiles of 16, the line-FFT potential on 414 720 points).
+
+Element-wise against the oracle, on the same system restricted to one mesh
+point (k index 7 of the 6 x 6 x 1 mesh; every per-k kernel then runs at its
+real shape, and one oracle apply is about 10 s of host time):
+
+* L applied to two projected random vectors, 1e-12 relative;
+* a 3-step pseudo-Hermitian m_+ chain and a 2-step non-Hermitian m_- chain:
+  alpha, beta, gamma, z and zn to 1e-10 relative.
+
+With one mesh point the contractions pick their K split from 2 batches
+instead of 72; that split and the number of batches are the only launch
+differences from the 36-point benchmark run.
+
+On the full 36-point system, where an oracle apply would take minutes, the
+checks are properties that hold at any size:
 
 * JL is Hermitian: (a, J L b) = conj((b, J L a)) for projected a, b; FP64
   sums over 1.9e8 elements, so 1e-11 relative.
@@ -23,6 +38,82 @@ from gpu_util import say
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE_TIMEOUT = 900      # seconds: about ten oracle applies at full grid size
+
+
+@pytest.fixture(scope="module")
+def slab1k():
+    """The benchmark system on mesh point 7 alone: library handle and oracle Problem."""
+    import torch
+    import paper_2203_01120_amd as tm
+    import synth
+    from oracle import liouvillian as lv
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    tm.load()
+    sys.path.insert(0, ROOT)
+    import bench
+    say("one-point slab: building inputs")
+    sysd = synth.make_hexslab()
+    inp = synth.synthetic_inputs(sysd, synth.cart_from_frac(sysd, [1.0 / 6.0, 0.0, 0.0]), seed=1,
+                                 kmesh_subset=[7])
+
+    class _GS:      # the oracle Problem reads only these ground-state fields
+        pass
+    gs = _GS()
+    gs.sysd, gs.vrs, gs.rho = inp["sysd"], inp["vrs"], inp["rho"]
+    prob = lv.Problem(gs, inp["qset"], point_states=[(m, e, et) for (_, m, e, et, _) in inp["points"]])
+    say("one-point slab: creating the system")
+    h = tm.tm_system_create(bench.make_desc(inp))
+    info = tm.tm_qset_info_get(h, 0)
+    assert info["nk"] == 1 and info["nbnd"] == 104
+    yield tm, h, info, prob
+    tm.tm_system_destroy(h)
+
+
+@pytest.mark.timeout(ORACLE_TIMEOUT)
+def test_fullsize_apply_matches_oracle(slab1k):
+    import torch
+    from gpu_util import from_gpu, rel_err, to_gpu
+    tm, h, info, prob = slab1k
+    shape = (2, 1, prob.nb, 2, info["npw_pad"])
+    for seed in (1, 2):
+        say(f"one-point slab: apply seed {seed} (GPU)")
+        x = prob.random_projected(seed)
+        xin = to_gpu(x, info["npw_pad"])
+        out = torch.empty_like(xin)
+        tm.tm_liouvillian_apply(h, 0, xin, out)
+        torch.cuda.synchronize()
+        got, raw = from_gpu(out, shape, prob.npw_pad)
+        say(f"one-point slab: apply seed {seed} (oracle)")
+        ref = prob.apply(x)
+        err = rel_err(got, ref)
+        say(f"one-point slab: apply seed {seed} rel err {err:.2e}")
+        assert err <= 1e-12, err
+        assert np.all(raw[:, 0, :, :, prob.k[0].npw:] == 0)
+    n1, n2, n3 = prob.sysd.fft
+    # the resident real-space ground state ran: one slot per side, all bands and planes
+    assert tm.tm_system_resident_bytes(h) == 2 * prob.nb * n3 * 2 * n1 * n2 * 16
+
+
+@pytest.mark.timeout(ORACLE_TIMEOUT)
+@pytest.mark.parametrize("flavour,mu,m", [("pH", "+", 3), ("nH", "-", 2)], ids=["pH+3", "nH-2"])
+def test_fullsize_chain_matches_oracle(slab1k, flavour, mu, m):
+    from oracle import lanczos as olanczos
+    tm, h, info, prob = slab1k
+    say(f"one-point slab: {flavour} {mu} {m} steps (GPU)")
+    co = tm.tm_lanczos_run(h, 0, mu, flavour, m)
+    say(f"one-point slab: {flavour} {mu} {m} steps (oracle)")
+    oc = olanczos.run(prob, mu, flavour, m, measure=("x", "y", "z", "n"))
+    assert co["steps_done"] == oc["steps_done"] == m
+    assert abs(co["n1"] - oc["n1"]) <= 1e-10 * oc["n1"]
+    for k in ("alpha", "beta", "gamma"):
+        err = np.abs(co[k] - oc[k]).max() / np.abs(oc[k]).max()
+        say(f"  {k} rel err {err:.2e}")
+        assert err <= 1e-10, (k, err)
+    zref = oc["z"]
+    zs = np.abs(zref).max()
+    assert np.abs(co["z"] - zref[:3]).max() <= 1e-10 * zs
+    assert np.abs(co["zn"] - zref[3]).max() <= 1e-10 * zs
 
 
 @pytest.fixture(scope="module")
