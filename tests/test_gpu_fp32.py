@@ -1,19 +1,22 @@
 """Single-precision bulk mode (TM_FP32) against the FP64 oracle and FP64 chains.
 
-Tolerances, derived from the arithmetic: FP32 unit roundoff u = 2^-24 = 6e-8.
-One apply chains ~13 radix stages per 3D FFT (20^3) and contractions over
-K ~ 2 npw ~ 10^3 (random-walk growth ~ sqrt(K) = 30), so its relative error is
-at most ~1e-6 (measured: 2e-8); the bound is 2e-5.
+Apply: FP32 unit roundoff u = 2^-24 = 6e-8.  One apply chains ~13 radix
+stages per 3D FFT (20^3) and contractions over K ~ 2 npw ~ 10^3 (random-walk
+growth ~ sqrt(K) = 30), so its relative error is at most ~1e-6 (measured:
+2e-8); the bound is 2e-5.
 
-Spectrum: the strongest peak of |Im chi| moves by at most 0.05 meV (1 % of
-eta = 5 meV).  For the spectrum as a whole, an FP32 apply is L plus a
-perturbation of norm ~ u ||L|| (||L|| ~ Lambda = 4.8 Ha here), which moves
-poles by up to ~1e-7 Ha; with eta = 1.8e-4 Ha that changes Im chi near a
-peak by ~ shift / eta ~ 1e-3 relative, and the recursion amplifies it further
-along a 60-step chain.  The bound on ||Im chi_32 - Im chi_64|| / ||Im chi_64||
-over 400 frequencies from 0 to 1.995 eV is therefore 1e-2 (measured: 3.9e-3
-for the transverse m_+ chain, 4.6e-5 for the longitudinal m_z chain).
+Spectrum: the bounds come from an error model run on the FP64 oracle
+(tests/fp32_noise.py; values in tests/golden/fp32_bound.json, written by
+tests/golden/make_fp32_bound.py): every apply of the oracle chain returns
+L x plus a random perturbation of norm 2^-24 Lam ||x||, over eight seeds; the
+bound is twice the largest deviation seen (pseudo-Hermitian m_+: relative L2
+of Im chi 3.7e-2, strongest peak 0.26 meV; non-Hermitian m_z: 8.8e-4, and no
+interior peak to track).  The model overstates the single-precision apply
+error about fivefold, so the GPU values sit well inside.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -24,6 +27,7 @@ from gpu_util import desc_from_problem, from_gpu, rel_err, say, to_gpu
 pytestmark = pytest.mark.gpu
 
 EV = 27.211386245988
+BOUNDS = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fp32_bound.json")))
 
 
 @pytest.fixture(scope="module")
@@ -71,14 +75,16 @@ def peak(tm, coeffs, m, omega0, eta, comp):
 
 
 def strongest_peak(chi, omega):
-    """(component, frequency) of the largest interior local maximum of |Im chi|."""
+    """(component, frequency) of the largest interior local maximum of |Im chi|
+    above zero, or None (a spectrum that only falls off has no peak to track)."""
     a = np.abs(chi.imag)
-    best = (0, 0, -1.0)
+    best = None
     for c in range(a.shape[0]):
         for i in range(1, a.shape[1] - 1):
-            if a[c, i] >= a[c, i - 1] and a[c, i] >= a[c, i + 1] and a[c, i] > best[2]:
+            if a[c, i] > 0 and a[c, i] >= a[c, i - 1] and a[c, i] >= a[c, i + 1] and (
+                    best is None or a[c, i] > best[2]):
                 best = (c, i, a[c, i])
-    return best[0], omega[best[1]]
+    return None if best is None else (best[0], omega[best[1]])
 
 
 @pytest.mark.parametrize("flavour,mu", [("pH", "+"), ("nH", "z")])
@@ -94,12 +100,18 @@ def test_fp32_spectrum_within_bounds(cubic, flavour, mu):
     x64 = tm.tm_chi(c64, m, omega, eta)
     x32 = tm.tm_chi(c32, m, omega, eta)
     l2 = np.linalg.norm(x32.imag - x64.imag) / np.linalg.norm(x64.imag)
-    comp, w0 = strongest_peak(x64, omega)
-    dpeak = abs(peak(tm, c32, m, w0, eta, comp) - peak(tm, c64, m, w0, eta, comp)) * EV * 1e3
-    say(f"  L2 {l2:.2e}, peak shift {dpeak:.4f} meV at {w0 * EV * 1e3:.1f} meV (component {comp}), "
+    bound = BOUNDS["chains"][f"{flavour}{mu}"]
+    pk = strongest_peak(x64, omega)
+    say(f"  L2 {l2:.2e} (bound {bound['bound_l2']}), "
         f"beta rel diff {np.abs(c32['beta'] - c64['beta']).max() / c64['beta'].max():.2e}")
-    assert l2 <= 1e-2, l2
-    assert dpeak <= 0.05, dpeak
+    assert l2 <= bound["bound_l2"], l2
+    assert (pk is None) == (bound["bound_peak_shift_meV"] is None)
+    if pk is not None:
+        comp, w0 = pk
+        dpeak = abs(peak(tm, c32, m, w0, eta, comp) - peak(tm, c64, m, w0, eta, comp)) * EV * 1e3
+        say(f"  peak shift {dpeak:.4f} meV at {w0 * EV * 1e3:.1f} meV (component {comp}), "
+            f"bound {bound['bound_peak_shift_meV']}")
+        assert dpeak <= bound["bound_peak_shift_meV"], dpeak
 
 
 def test_fp32_needs_resident_ground_state(cubic):
