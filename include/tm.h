@@ -168,6 +168,38 @@ int tm_system_set_resident_limit(tm_system* sys, long long bytes);
 int tm_system_resident_bytes(const tm_system* sys, long long* bytes);
 
 /*
+ * Device memory of a system (an implementation figure, not part of the
+ * method): what a scheduler needs to admit work by device-memory footprint.
+ *   tables            ground-state bands, occupied partners, projector and
+ *                     sphere tables, fields: allocated by tm_system_create
+ *   resident          resident real-space ground state now held
+ *   resident_full     bytes the complete resident copy needs (0 when the grid
+ *                     has no fixed-size plane kernel)
+ *   columns           z-transformed ground-state columns now held (the path
+ *                     without the resident copy)
+ *   columns_full      bytes those columns need for the largest q set
+ *   workspace         apply workspaces of every chain slot now held
+ *   workspace_per_rhs one slot's workspace for one right-hand side (a chain
+ *                     of L lanes needs about L times this in each slot)
+ *   chain_slots       workspace slots the system's chains are spread over
+ * out: caller-owned host struct.  TM_EINVAL on a null argument.
+ */
+typedef struct {
+    long long tables, resident, resident_full, columns, columns_full, workspace, workspace_per_rhs;
+    int chain_slots;
+} tm_memory_info;
+int tm_system_memory(const tm_system* sys, tm_memory_info* out);
+
+/*
+ * The same figures for a system not yet created, from its descriptor alone
+ * (host work only, nothing is allocated): resident_full, columns_full and
+ * workspace_per_rhs as tm_system_memory will report them; tables an upper
+ * estimate (its large items summed, 5 % and 16 MiB added); the "now held"
+ * fields and chain_slots are 0.  TM_EINVAL on a null or empty descriptor.
+ */
+int tm_system_footprint(const tm_system_desc* desc, tm_memory_info* out);
+
+/*
  * tm_liouvillian_apply: xy_out = L_q xy_in (Eqs. Liouvillian_BR_q and
  * liouvillian_blocks; one projector P, P+ applied to the sum of the D and K
  * parts, lower row multiplied by -1).

@@ -25,7 +25,7 @@ FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
             "tm_system_set_chain_slots",
-            "tm_system_resident_bytes", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
+            "tm_system_resident_bytes", "tm_system_memory", "tm_system_footprint", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
             "tm_chain_begin_multi", "tm_chain_lanes", "tm_tensor_run", "tm_liouvillian_apply_multi",
@@ -55,6 +55,12 @@ class _Desc(C.Structure):
 class _QInfo(C.Structure):
     _fields_ = [("nk", C.c_int), ("nbnd", C.c_int), ("npw_pad", C.c_int), ("nelem", C.c_longlong),
                 ("lam", C.c_double)]
+
+
+class _MemInfo(C.Structure):
+    _fields_ = [("tables", C.c_longlong), ("resident", C.c_longlong), ("resident_full", C.c_longlong),
+                ("columns", C.c_longlong), ("columns_full", C.c_longlong), ("workspace", C.c_longlong),
+                ("workspace_per_rhs", C.c_longlong), ("chain_slots", C.c_int)]
 
 
 class _Coeffs(C.Structure):
@@ -97,6 +103,8 @@ def load(path: str = LIB_PATH):
     lib.tm_structure_factor.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_int,
                                         C.POINTER(C.c_double)]
     lib.tm_system_resident_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_longlong)]
+    lib.tm_system_memory.argtypes = [C.c_void_p, C.POINTER(_MemInfo)]
+    lib.tm_system_footprint.argtypes = [C.POINTER(_Desc), C.POINTER(_MemInfo)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_liouvillian_apply_multi.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                                C.c_void_p]
@@ -159,10 +167,8 @@ class SystemDesc:
     keep: list = field(default_factory=list)
 
 
-def tm_system_create(d: SystemDesc):
-    """Upload a system; returns an opaque handle (int)."""
-    lib = load()
-    keep = []
+def _marshal_desc(d: SystemDesc, keep: list):
+    """A tm_system_desc over host arrays of d (kept alive in `keep`)."""
 
     def c(a, dt):
         a = np.ascontiguousarray(a, dtype=dt)
@@ -213,9 +219,26 @@ def tm_system_create(d: SystemDesc):
     if d.shifts is not None:
         sh = c(d.shifts, np.int32)
         desc.shifts = _iptr(sh)
+    return desc
+
+
+def tm_system_create(d: SystemDesc):
+    """Upload a system; returns an opaque handle (int)."""
+    lib = load()
+    keep = []
+    desc = _marshal_desc(d, keep)
     h = C.c_void_p()
     _check(lib.tm_system_create(C.byref(desc), C.byref(h)))
     return h.value
+
+
+def tm_system_footprint(d: SystemDesc) -> dict:
+    """Device bytes a system will hold, from its descriptor (nothing allocated; see tm.h)."""
+    keep = []
+    desc = _marshal_desc(d, keep)
+    m = _MemInfo()
+    _check(load().tm_system_footprint(C.byref(desc), C.byref(m)))
+    return {k: getattr(m, k) for k, _ in _MemInfo._fields_}
 
 
 def tm_system_destroy(h):
@@ -244,6 +267,13 @@ def tm_system_resident_bytes(h) -> int:
     out = C.c_longlong(0)
     _check(load().tm_system_resident_bytes(C.c_void_p(h), C.byref(out)))
     return int(out.value)
+
+
+def tm_system_memory(h) -> dict:
+    """Device bytes of a system (tables, resident copy, columns, workspaces; see tm.h)."""
+    m = _MemInfo()
+    _check(load().tm_system_memory(C.c_void_p(h), C.byref(m)))
+    return {k: getattr(m, k) for k, _ in _MemInfo._fields_}
 
 
 def _stream(stream):

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <set>
 #include <unordered_map>
 
 #include "lanczos_dev.h"
@@ -447,19 +448,9 @@ static void select_slot(System& s, int j) {
     s.wcur = j;
 }
 
-// Sized for nrhs right-hand sides over all q sets.  Growing it frees the old
-// buffers (after the device is idle) and bumps the epoch, so chains re-capture
-// their step graphs, which hold its pointers.
-void ensure_workspace(System& s, const QSet&, int nrhs) {
-    Workspace& w = s.ws;
-    if (w.rho && w.width >= nrhs) return;
-    if (w.rho) {
-        TM_HIP(hipDeviceSynchronize());
-        const int epoch = w.epoch;
-        free_workspace(w);
-        w.epoch = epoch + 1;
-    }
-    w.width = nrhs;
+// Buffer sizes of a workspace for nrhs right-hand sides over all q sets
+// (element counts in w.cap_*, w.nchunk); returns the device bytes it holds.
+static size_t plan_workspace(const System& s, int nrhs, Workspace& w) {
     const int nb = s.nbnd;
     int nb2 = 0, ncol_max = 0, npw_pad = 0;
     for (const QSet& q : s.qs) {
@@ -480,6 +471,27 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
     w.cap_gpart = R * std::max(gemm_partial_elems(nb2, nb, nb, 2 * npw_pad),
                                gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, npw_pad));
     w.cap_gsmall = R * std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
+    w.bytes = (w.cap_xcols + w.cap_rho_part + w.cap_gpart + w.cap_gsmall + R * 9 * s.N) * sizeof(double2);
+    size_t all = w.bytes + (64 + 1024 * 8) * sizeof(double2);
+    if (plane_fixed_supported(s.n1, s.n2)) all += R * 6 * s.N * sizeof(double2);
+    return all;
+}
+
+// Sized for nrhs right-hand sides over all q sets.  Growing it frees the old
+// buffers (after the device is idle) and bumps the epoch, so chains re-capture
+// their step graphs, which hold its pointers.
+void ensure_workspace(System& s, const QSet&, int nrhs) {
+    Workspace& w = s.ws;
+    if (w.rho && w.width >= nrhs) return;
+    if (w.rho) {
+        TM_HIP(hipDeviceSynchronize());
+        const int epoch = w.epoch;
+        free_workspace(w);
+        w.epoch = epoch + 1;
+    }
+    w.width = nrhs;
+    const size_t R = (size_t)nrhs;
+    const size_t all = plan_workspace(s, nrhs, w);
     auto grab = [&](void** p, size_t bytes) {
         if (hipMalloc(p, bytes) != hipSuccess) {
             (void)hipGetLastError();
@@ -495,7 +507,7 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
     grab((void**)&w.dots, 64 * sizeof(double2));
     grab((void**)&w.dotpart, 1024 * 8 * sizeof(double2));
     if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, R * 6 * s.N * sizeof(double2));
-    w.bytes = (w.cap_xcols + w.cap_rho_part + w.cap_gpart + w.cap_gsmall + R * 9 * s.N) * sizeof(double2);
+    w.alloc_bytes = all;
     grab((void**)&w.rho, R * 4 * s.N * sizeof(double2));  // last: marks the workspace complete
 }
 
@@ -534,6 +546,7 @@ static void ensure_ground(System& s, QSet& q, hipStream_t st) {
     if (!q.ucols) {
         const size_t need = (size_t)2 * q.nk * 2 * s.nbnd * s.n3 * q.ncol_u_max;
         TM_HIP(hipMalloc(&q.ucols, need * sizeof(double2)));
+        q.ucols_bytes = need * sizeof(double2);
         launch_zpass_inv(s, q, true, nullptr, 0, 2 * s.nbnd, 0, q.ucols, st);
     }
     if (s.ureal_mode == 1) {
@@ -541,6 +554,7 @@ static void ensure_ground(System& s, QSet& q, hipStream_t st) {
         TM_HIP(hipStreamSynchronize(st));
         TM_HIP(hipFree(q.ucols));
         q.ucols = nullptr;
+        q.ucols_bytes = 0;
     }
     q.ground_ready = true;
 }
@@ -1304,6 +1318,109 @@ int tm_system_resident_bytes(const tm_system* sys, long long* bytes) {
     return guarded([&]() -> int {
         TM_CHECK(sys && bytes, TM_EINVAL, "null argument");
         *bytes = (long long)sys->s.ureal_bytes;
+        return TM_OK;
+    });
+}
+
+int tm_system_memory(const tm_system* sys, tm_memory_info* out) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && out, TM_EINVAL, "null argument");
+        const System& s = sys->s;
+        tm_memory_info m{};
+        m.tables = (long long)s.table_bytes;
+        m.resident = (long long)s.ureal_bytes;
+        const size_t NP = (size_t)s.n1 * s.n2;
+        m.resident_full = plane_fixed_supported(s.n1, s.n2)
+                              ? (long long)(s.uslot_of.size() * (size_t)s.nbnd * s.n3 * 2 * NP * sizeof(double2))
+                              : 0;
+        for (const QSet& q : s.qs) {
+            m.columns += (long long)q.ucols_bytes;
+            m.columns_full = std::max(m.columns_full,
+                                      (long long)((size_t)2 * q.nk * 2 * s.nbnd * s.n3 * q.ncol_u_max * sizeof(double2)));
+        }
+        for (int j = 0; j < (int)s.wslot.size(); ++j)
+            if (j != s.wcur) m.workspace += (long long)s.wslot[j].alloc_bytes;
+        m.workspace += (long long)s.ws.alloc_bytes;
+        Workspace one;
+        m.workspace_per_rhs = (long long)plan_workspace(s, 1, one);
+        m.chain_slots = s.nslots > 0 ? s.nslots : s.slot_cap;
+        *out = m;
+        return TM_OK;
+    });
+}
+
+// Device bytes a system will hold, from its descriptor alone (nothing is
+// allocated): the workspace uses the same sizing as the real allocation; the
+// tables sum their large items (bands, occupied partners, projector tables,
+// sphere maps, fields) with a small allowance for the rest.
+int tm_system_footprint(const tm_system_desc* d, tm_memory_info* out) {
+    return guarded([&]() -> int {
+        TM_CHECK(d && out, TM_EINVAL, "null argument");
+        TM_CHECK(d->nbnd > 0 && d->npts > 0 && d->nq > 0 && d->nk > 0, TM_EINVAL, "empty system");
+        for (int c = 0; c < 3; ++c) TM_CHECK(d->fft[c] > 0, TM_EINVAL, "FFT lengths must be positive");
+        System s;
+        s.n1 = d->fft[0];
+        s.n2 = d->fft[1];
+        s.n3 = d->fft[2];
+        s.N = (long long)s.n1 * s.n2 * s.n3;
+        s.nbnd = d->nbnd;
+        s.nproj = d->nproj;
+        const size_t nb = (size_t)d->nbnd, NP = (size_t)s.n1 * s.n2;
+        // distinct (m1, m2) columns of each point's sphere (a G shift moves them all alike)
+        std::vector<int> ncol(d->npts);
+        double tables = 0;
+        for (int p = 0; p < d->npts; ++p) {
+            std::unordered_map<long long, int> cols;
+            for (int g = 0; g < d->npw[p]; ++g) cols.emplace(mkey(d->mill[p][3 * g], d->mill[p][3 * g + 1], 0), 0);
+            ncol[p] = (int)cols.size();
+            tables += (double)nb * 2 * d->npw[p] * sizeof(double2) + (double)d->nproj * d->npw[p] * sizeof(double2) +
+                      3.0 * d->npw[p] * sizeof(int) + nb * sizeof(double);
+        }
+        std::set<std::array<int, 5>> uslots;
+        s.qs.resize(d->nq);
+        for (int iq = 0; iq < d->nq; ++iq) {
+            QSet& q = s.qs[iq];
+            q.nk = d->nk;
+            int npw_max = 0;
+            q.ncol_max = q.ncol_u_max = 0;
+            for (int ik = 0; ik < d->nk; ++ik) {
+                const int* r = d->roles + ((size_t)iq * d->nk + ik) * 4;
+                const int* sh = d->shifts ? d->shifts + ((size_t)iq * d->nk + ik) * 12 : nullptr;
+                for (int t = 0; t < 4; ++t) TM_CHECK(r[t] >= 0 && r[t] < d->npts, TM_EINVAL, "role index out of range");
+                npw_max = std::max(npw_max, d->npw[r[2]]);
+                q.ncol_max = std::max(q.ncol_max, ncol[r[2]]);
+                q.ncol_u_max = std::max({q.ncol_u_max, ncol[r[0]], ncol[r[1]]});
+                for (int side = 0; side < 2; ++side) {
+                    const int* gsh = sh ? sh + 3 * side : nullptr;
+                    uslots.insert({r[side], gsh ? gsh[0] : 0, gsh ? gsh[1] : 0, gsh ? gsh[2] : 0, side});
+                }
+            }
+            q.npw_pad = (npw_max + 15) / 16 * 16;
+            const double P = q.npw_pad;
+            // per k: occupied partners of both sides, padded projectors, maps and kinetic
+            // energies, three sphere maps, the plane-position column index
+            for (int ik = 0; ik < d->nk; ++ik) {
+                const int* r = d->roles + ((size_t)iq * d->nk + ik) * 4;
+                tables += 2.0 * nb * 2 * P * sizeof(double2) + (double)d->nproj * P * sizeof(double2) +
+                          P * (2 * sizeof(int) + sizeof(double)) + NP * sizeof(short) +
+                          2.0 * (d->npw[r[2]] + d->npw[r[0]] + d->npw[r[1]]) * sizeof(int);
+            }
+            tables += (double)s.N * sizeof(double);  // Coulomb multiplier
+        }
+        tables += (double)s.N * (4 + 10) * sizeof(double);  // potentials and kernel fields
+        tables = tables * 1.05 + (16 << 20);
+        tm_memory_info m{};
+        m.tables = (long long)tables;
+        m.resident_full = plane_fixed_supported(s.n1, s.n2)
+                              ? (long long)(uslots.size() * nb * s.n3 * 2 * NP * sizeof(double2))
+                              : 0;
+        for (const QSet& q : s.qs)
+            m.columns_full = std::max(m.columns_full,
+                                      (long long)((size_t)2 * q.nk * 2 * nb * s.n3 * q.ncol_u_max * sizeof(double2)));
+        Workspace one;
+        m.workspace_per_rhs = (long long)plan_workspace(s, 1, one);
+        m.chain_slots = 0;
+        *out = m;
         return TM_OK;
     });
 }

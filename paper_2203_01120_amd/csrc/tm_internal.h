@@ -177,11 +177,13 @@ struct QSet {
     short** d_colidx_kq = nullptr;  // [2nk] plane position -> column of the k+q sphere, or -1
     // lazily built caches
     double2* ucols = nullptr;     // z-transformed ground-state columns [b][nb*2][n3][ncol_u_max]
+    size_t ucols_bytes = 0;
     bool ground_ready = false;    // ucols or the resident real-space slots of this set are built
 };
 
 struct Workspace {
-    size_t bytes = 0;
+    size_t bytes = 0;             // the large buffers (decides whether chains spread over slots)
+    size_t alloc_bytes = 0;       // everything the workspace holds on the device
     int epoch = 0;                // bumped whenever the buffers are reallocated
     double2* xcols = nullptr;     // [2nk][nb*2][n3][ncol_max] (also reused for phi columns)
     double2* rho_part = nullptr;  // [nslot][4][N]
@@ -246,6 +248,7 @@ struct System {
     int slot_cap = 3;                  // at most this many (tm_system_set_chain_slots)
     int next_slot = 0;
     std::vector<void*> allocs;
+    size_t table_bytes = 0;            // device bytes of everything in `allocs`
 };
 
 template <typename T>
@@ -257,6 +260,7 @@ T* dev_alloc(System& s, size_t count) {
         throw Error{TM_ENOMEM, std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
                                    " bytes failed: " + hipGetErrorString(e)};
     s.allocs.push_back(p);
+    s.table_bytes += count * sizeof(T);
     return static_cast<T*>(p);
 }
 template <typename T>
