@@ -278,7 +278,9 @@ def run_qpath(args, tm, torch):
         chains = [tm.tm_chain_begin(h, iq, mu, "pH", m, prec) for iq, mu in specs]
         tm.tm_chains_step(chains, m)
         coeffs = [tm.tm_chain_coeffs(c, m) for c in chains]
-    spectra = [tm.tm_chi(co, co["steps_done"], omega, eta) for co in coeffs]
+    # a chain that broke down before its first step has no spectrum (zeros)
+    spectra = [tm.tm_chi(co, co["steps_done"], omega, eta) if co["steps_done"] > 0 else
+               np.zeros((3, omega.size), complex) for co in coeffs]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     for c in chains:
@@ -312,66 +314,87 @@ def run_qpath(args, tm, torch):
     print(json.dumps(out))
 
 
+def serving_pool(tm, seed):
+    """The served systems: name -> (SystemDef, q vectors, weight).  Cubic a = 10 bohr
+    cell on 20^3 / 8 bands / Gamma, 24^3 / 16 bands / 2x2x1 k, 32^3 / 32 bands /
+    3x3x1 k, and a CrI3-shaped slab (hexagonal a = 13, c = 16.5 bohr) on
+    48x48x96 / 64 bands / 4x4x1 k; two q sets each; drawn 8:4:2:1."""
+    import synth
+    slab = synth.make_hexslab(c=16.5, fft=(48, 48, 96), nbnd=64, nk=4)
+    qc = np.array([[0.1, 0.0, 0.0], [0.0, 0.15, 0.05]]) * 2 * np.pi / 10.0
+    return {"cubic20": (synth.make_cubic20(), qc, 8.0), "cubic24": (synth.make_cubic(24, 16, 2), qc, 4.0),
+            "cubic32": (synth.make_cubic(32, 32, 3), qc, 2.0),
+            "slab96": (slab, np.array([synth.cart_from_frac(slab, [0.25, 0.0, 0.0]),
+                                       synth.cart_from_frac(slab, [0.0, 0.25, 0.0])]), 1.0)}
+
+
 def run_serving(args, tm, torch):
-    """Poisson arrivals of chi requests on a pool of systems (cubic a = 10 bohr cell:
-    20^3 / 8 bands / Gamma, 24^3 / 16 bands / 2x2x1 k, 32^3 / 32 bands / 3x3x1 k;
-    two q sets each), drawn 4:2:1 toward the small ones; direction uniform over
-    x, y, z, +, -; flavour uniform over pH, nH; 500..3000 steps.  The
-    continuous-batching server is compared with the plain one-at-a-time path
-    (FIFO, tm_lanczos_run with directly issued kernels) on the same requests."""
+    """Poisson arrivals of chi requests on a pool of systems (serving_pool) that
+    the server creates on demand and evicts under a device-memory budget that
+    counts every system's footprint (tables, ground state -- resident
+    real-space copy capped per system, or columns -- and workspaces) and every
+    chain; direction uniform over x, y, z, +, -; flavour uniform over pH, nH;
+    500..3000 steps.  The continuous-batching server is compared with the
+    plain one-at-a-time path (FIFO, tm_lanczos_run with directly issued
+    kernels, systems created and evicted under the same budget) on the same
+    requests, and every chi of the two is compared."""
     import synth
     from paper_2203_01120_amd import serving as sv
-    pool = {"cubic20": synth.make_cubic20(), "cubic24": synth.make_cubic(24, 16, 2),
-            "cubic32": synth.make_cubic(32, 32, 3)}
-    weights = np.array([4.0, 2.0, 1.0]) / 7.0
-    slots = {}
-    for name, sysd in pool.items():
-        qs = np.array([[0.1, 0.0, 0.0], [0.0, 0.15, 0.05]]) * 2 * np.pi / 10.0
-        inp = synth.synthetic_inputs_multi(sysd, qs, seed=args.seed)
-        pts = [tm.Point(xk=p, mill=m, evc=e, et=et, vkb=v) for (p, m, e, et, v) in inp["points"]]
-        desc = tm.SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=sysd.nbnd, points=pts, vrs=inp["vrs"],
-                             rho=inp["rho"], dvan=inp["dvan"], xq=inp["xq"], roles=inp["roles"],
-                             shifts=inp["shifts"])
-        h = tm.tm_system_create(desc)
-        nelem = {iq: tm.tm_qset_info_get(h, iq)["nelem"] for iq in range(len(qs))}
-        for iq in range(len(qs)):   # builds the per-q caches outside the timed runs
-            tm.tm_lanczos_run(h, iq, "z", "nH", 3)
-        slots[name] = sv.SystemSlot(handle=h, nelem=nelem)
-        log(f"system {name}: fft {sysd.fft}, {sysd.nbnd} bands, {len(sysd.kmesh)} k")
-    torch.cuda.synchronize()
+    pool = serving_pool(tm, args.seed)
+    specs = {}
+    for name, (sysd, qs, _) in pool.items():
+        def make(sysd=sysd, qs=qs):
+            inp = synth.synthetic_inputs_multi(sysd, qs, seed=args.seed)
+            pts = [tm.Point(xk=p, mill=m, evc=e, et=et, vkb=v) for (p, m, e, et, v) in inp["points"]]
+            return tm.SystemDesc(cell=sysd.cell, fft=sysd.fft, nbnd=sysd.nbnd, points=pts, vrs=inp["vrs"],
+                                 rho=inp["rho"], dvan=inp["dvan"], xq=inp["xq"], roles=inp["roles"],
+                                 shifts=inp["shifts"])
+        specs[name] = sv.SystemSpec(make_desc=make, resident_cap=int(args.serving_resident_cap * 1e9))
+    budget = int(args.serving_budget * 1e9)
+    names = list(pool)
+    weights = np.array([pool[n][2] for n in names])
+    weights /= weights.sum()
     omega = np.arange(400) * 5e-3 / EV
     eta = 5e-3 / EV
-    names = list(pool)
+    # descriptors are host work done once (kept by the pools); footprints from them
+    probe = sv.SystemPool({}, budget, specs, lanes=args.serving_lanes, chain_slots=args.serving_chain_slots)
+    for n in names:
+        log(f"system {n}: fft {pool[n][0].fft}, {pool[n][0].nbnd} bands, {len(pool[n][0].kmesh)} k, "
+            f"footprint {probe.footprint(n) / 1e9:.2f} GB")
+    descs = {n: probe.desc(n) for n in names}
+    specs = {n: sv.SystemSpec(make_desc=(lambda d=descs[n]: d), resident_cap=specs[n].resident_cap) for n in names}
     results = []
     maxdiff = 0.0
     for rate in [float(r) for r in args.rates.split(",")]:
         rng = np.random.default_rng(5000 + int(round(rate * 10)))
         t = np.cumsum(rng.exponential(1.0 / rate, args.requests))
 
-        def make():
+        def make_requests():
             out = []
             for i in range(args.requests):
                 r2 = np.random.default_rng(7000 + 1000 * int(round(rate * 10)) + i)
-                out.append(sv.Request(rid=i, system=names[r2.choice(3, p=weights)], iq=int(r2.integers(2)),
+                out.append(sv.Request(rid=i, system=names[r2.choice(len(names), p=weights)], iq=int(r2.integers(2)),
                                       direction=str(r2.choice(["x", "y", "z", "+", "-"])),
                                       flavour=str(r2.choice(["pH", "nH"])), nsteps=int(r2.integers(500, 3001)),
                                       omega=omega, eta=eta, arrival=float(t[i])))
             return out
         log(f"rate {rate}/s: {args.requests} requests, batched server")
-        server = sv.Server(slots, budget_bytes=32 << 30, lanes=args.serving_lanes, max_chains=args.serving_max_chains,
-                           chain_slots=args.serving_chain_slots)
-        batched = server.run(make())
+        server = sv.Server({}, budget_bytes=budget, lanes=args.serving_lanes, max_chains=args.serving_max_chains,
+                           chain_slots=args.serving_chain_slots, specs=specs)
+        try:
+            batched = server.run(make_requests())
+        finally:
+            server.close()
         log(f"rate {rate}/s: one at a time")
-        plain = sv.run_one_at_a_time(slots, make())
+        plain = sv.run_one_at_a_time({}, make_requests(), specs=specs, budget_bytes=budget)
         by_id = {r.rid: r for r in plain}
         for r in batched:
             ref = by_id[r.rid].chi
             maxdiff = max(maxdiff, float(np.abs(r.chi - ref).max() / max(np.abs(ref).max(), 1e-300)))
         sb, sp = sv.summary(batched), sv.summary(plain)
+        sb.update(systems_created=server.pool.created, systems_evicted=server.pool.evicted)
         log(f"rate {rate}: batched {sb}  plain {sp}")
         results.append({"rate_per_s": rate, "batched": sb, "one_at_a_time": sp})
-    for s in slots.values():
-        tm.tm_system_destroy(s.handle)
     best = max(results, key=lambda r: r["batched"]["spectra_per_s"])
     out = {
         "metric": "chi(q,omega) spectra/s and p50/p99 latency under Poisson load",
@@ -379,17 +402,20 @@ def run_serving(args, tm, torch):
         "unit": "spectra/s",
         "n_gpus": 1,
         "steps": None,
-        "warmup": 3,
+        "warmup": 0,
         "ms_per_step": None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "serving: pool 20^3/8/1k, 24^3/16/4k, 32^3/32/9k (cubic a=10 bohr), 4:2:1, "
-                               "500..3000 steps, pH|nH, x|y|z|+|-, chi on 400 omega",
+        "config": {"workload": "serving: pool 20^3/8/1k, 24^3/16/4k, 32^3/32/9k (cubic a=10 bohr), "
+                               "48x48x96/64/16k (hexagonal slab a=13 c=16.5 bohr), drawn 8:4:2:1, "
+                               "500..3000 steps, pH|nH, x|y|z|+|-, chi on 400 omega; systems created on demand",
                    "rates_per_s": [r["rate_per_s"] for r in results], "requests_per_rate": args.requests,
+                   "budget_GB": args.serving_budget, "resident_cap_GB": args.serving_resident_cap,
                    "lanes_per_chain_max": args.serving_lanes, "chains_per_system_max": args.serving_max_chains},
+        "footprints_GB": {n: round(probe.footprint(n) / 1e9, 3) for n in names},
         "per_rate": results,
         "chi_max_rel_diff_batched_vs_alone": maxdiff,
     }
@@ -439,8 +465,12 @@ def main():
     ap.add_argument("--chain-steps", type=int, default=2000, help="qpath: steps per chain")
     ap.add_argument("--qpath-lanes", type=int, default=3, choices=[1, 3],
                     help="qpath: directions per chain object (3: one batched apply per q set and step)")
-    ap.add_argument("--rates", default="0.5,1,2", help="serving: Poisson arrival rates (requests/s)")
-    ap.add_argument("--requests", type=int, default=40, help="serving: requests per rate")
+    ap.add_argument("--rates", default="0.2,0.5,1", help="serving: Poisson arrival rates (requests/s)")
+    ap.add_argument("--requests", type=int, default=20, help="serving: requests per rate")
+    ap.add_argument("--serving-budget", type=float, default=48.0,
+                    help="serving: device-memory budget in GB (system footprints + chains)")
+    ap.add_argument("--serving-resident-cap", type=float, default=16.0,
+                    help="serving: largest resident real-space ground state per system, GB")
     ap.add_argument("--serving-lanes", type=int, default=4, choices=[1, 2, 3, 4],
                     help="serving: pending requests of one system, q set and flavour share a chain (lanes)")
     ap.add_argument("--chain-slots", type=int, default=3,

@@ -194,7 +194,7 @@ int tm_system_memory(const tm_system* sys, tm_memory_info* out);
  * The same figures for a system not yet created, from its descriptor alone
  * (host work only, nothing is allocated): resident_full, columns_full and
  * workspace_per_rhs as tm_system_memory will report them; tables an upper
- * estimate (its large items summed, 5 % and 16 MiB added); the "now held"
+ * estimate (its items summed, 5 % and 1 MiB added); the "now held"
  * fields and chain_slots are 0.  TM_EINVAL on a null or empty descriptor.
  */
 int tm_system_footprint(const tm_system_desc* desc, tm_memory_info* out);

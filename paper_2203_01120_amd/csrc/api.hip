@@ -1401,14 +1401,22 @@ int tm_system_footprint(const tm_system_desc* d, tm_memory_info* out) {
             // energies, three sphere maps, the plane-position column index
             for (int ik = 0; ik < d->nk; ++ik) {
                 const int* r = d->roles + ((size_t)iq * d->nk + ik) * 4;
-                tables += 2.0 * nb * 2 * P * sizeof(double2) + (double)d->nproj * P * sizeof(double2) +
-                          P * (2 * sizeof(int) + sizeof(double)) + NP * sizeof(short) +
-                          2.0 * (d->npw[r[2]] + d->npw[r[0]] + d->npw[r[1]]) * sizeof(int);
+                const double npw = d->npw[r[2]];
+                // occupied partners, projector tables (the point's and the padded copy),
+                // restriction maps, kinetic energies, Miller indices, eigenvalues,
+                // plane-position column index, three sphere maps
+                tables += 2.0 * nb * 2 * P * sizeof(double2) + (double)d->nproj * (P + npw) * sizeof(double2) +
+                          (2 * P + npw) * sizeof(int) + P * sizeof(double) + 3 * npw * sizeof(int) +
+                          2.0 * nb * sizeof(double) + NP * sizeof(short) +
+                          2.0 * (npw + d->npw[r[0]] + d->npw[r[1]] + ncol[r[2]] + ncol[r[0]] + ncol[r[1]] + 3) *
+                              sizeof(int);
             }
             tables += (double)s.N * sizeof(double);  // Coulomb multiplier
         }
-        tables += (double)s.N * (4 + 10) * sizeof(double);  // potentials and kernel fields
-        tables = tables * 1.05 + (16 << 20);
+        // potentials, density and magnetisation, kernel fields; twiddles and permutations
+        tables += (double)s.N * (4 + 4 + 10) * sizeof(double) +
+                  (double)(s.n1 + s.n2 + s.n3) * (sizeof(double2) + sizeof(float2) + sizeof(int));
+        tables = tables * 1.05 + (1 << 20);
         tm_memory_info m{};
         m.tables = (long long)tables;
         m.resident_full = plane_fixed_supported(s.n1, s.n2)
