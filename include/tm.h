@@ -226,6 +226,26 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
                                tm_precision prec, void* stream);
 
 /*
+ * tm_liouvillian_apply_noalloc: tm_liouvillian_apply (one right-hand side,
+ * same kernels, same result) for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  It calls no hipMalloc, hipFree or allocating routine: its apply
+ * workspace is a static device array of 64 MiB inside the library, one copy
+ * per device, held until the process ends.  Systems whose one-right-hand-side
+ * workspace (tm_system_memory's workspace_per_rhs, rounded up per buffer) is
+ * larger get TM_EUNSUPPORTED (the 20^3 / 8-band system needs about 7 MB).
+ * The q set's ground-state caches must already exist -- one ordinary
+ * tm_liouvillian_apply of that q set builds them -- else TM_EINVAL; the
+ * current device must be the system's (TM_EINVAL).  Every call on a device
+ * shares that device's array, which keeps the last call's contents; calls
+ * that overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  Arguments, layout and the other errors as for
+ * tm_liouvillian_apply.
+ */
+int tm_liouvillian_apply_noalloc(tm_system* sys, int iq, const void* xy_in, void* xy_out,
+                                 tm_precision prec, void* stream);
+
+/*
  * tm_start_vectors: the BR vectors of Sec. 2.5 (below Eq. off-diag-resolvent):
  *   u^dir = ( sigma U~_{n,k}, -sigma T U~_{n,-k} ),
  *   v^dir = ( P sigma U~_{n,k}, P+ sigma T U~_{n,-k} ),

@@ -25,7 +25,7 @@ FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
             "tm_system_set_chain_slots",
-            "tm_system_resident_bytes", "tm_system_memory", "tm_system_footprint", "tm_liouvillian_apply", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
+            "tm_system_resident_bytes", "tm_system_memory", "tm_system_footprint", "tm_liouvillian_apply", "tm_liouvillian_apply_noalloc", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
             "tm_chain_begin_multi", "tm_chain_lanes", "tm_tensor_run", "tm_liouvillian_apply_multi",
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
     lib.tm_system_memory.argtypes = [C.c_void_p, C.POINTER(_MemInfo)]
     lib.tm_system_footprint.argtypes = [C.POINTER(_Desc), C.POINTER(_MemInfo)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    lib.tm_liouvillian_apply_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_liouvillian_apply_multi.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                                C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -296,6 +297,15 @@ def tm_liouvillian_apply(h, iq: int, xy_in, xy_out, prec: int = TM_FP64, stream=
     _check_tensor(xy_out, nelem)
     _check(load().tm_liouvillian_apply(C.c_void_p(h), iq, C.c_void_p(xy_in.data_ptr()),
                                        C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
+
+
+def tm_liouvillian_apply_noalloc(h, iq: int, xy_in, xy_out, prec: int = TM_FP64, stream=None):
+    """xy_out = L xy_in without any device allocation (library scratch; see tm.h)."""
+    nelem = tm_qset_info_get(h, iq)["nelem"]
+    _check_tensor(xy_in, nelem)
+    _check_tensor(xy_out, nelem)
+    _check(load().tm_liouvillian_apply_noalloc(C.c_void_p(h), iq, C.c_void_p(xy_in.data_ptr()),
+                                               C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
 
 
 def tm_liouvillian_apply_multi(h, iq: int, nrhs: int, xy_in, xy_out, prec: int = TM_FP64, stream=None):

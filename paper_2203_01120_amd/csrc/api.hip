@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <set>
 #include <unordered_map>
 
@@ -571,6 +572,63 @@ static void reset_ground(System& s) {
     for (QSet& q : s.qs) q.ground_ready = false;
 }
 
+// ---- the allocation-free apply ---------------------------------------------------
+// Apply workspace of tm_liouvillian_apply_noalloc: a static device array, one copy
+// per device (each GPU the library runs on holds it until the process ends).
+// Host code never uses its name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::unordered_map<int, char*> g_scratch_ptr;  // device -> address of its scratch copy
+
+char* scratch_address(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) return it->second;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        throw Error{TM_EDEVICE, std::string("hipGetSymbolAddress of the apply scratch failed: ") +
+                                    hipGetErrorString(e)};
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+    return static_cast<char*>(ptr);
+}
+
+// a one-right-hand-side workspace carved out of `base` (256-byte aligned pieces)
+Workspace scratch_workspace(const System& s, char* base, size_t cap) {
+    Workspace w;
+    plan_workspace(s, 1, w);
+    size_t off = 0;
+    auto take = [&](size_t elems) {
+        double2* p = reinterpret_cast<double2*>(base + off);
+        off += (elems * sizeof(double2) + 255) / 256 * 256;
+        return p;
+    };
+    w.xcols = take(w.cap_xcols);
+    w.rho_part = take(w.cap_rho_part);
+    w.gpart = take(w.cap_gpart);
+    w.gsmall = take(w.cap_gsmall);
+    w.W = take(4 * (size_t)s.N);
+    w.work = take((size_t)s.N);
+    w.dots = take(64);
+    w.dotpart = take(1024 * 8);
+    if (plane_fixed_supported(s.n1, s.n2)) w.fields = take(6 * (size_t)s.N);
+    w.rho = take(4 * (size_t)s.N);
+    w.width = 1;
+    w.alloc_bytes = off;
+    TM_CHECK(off <= cap, TM_EUNSUPPORTED,
+             "the system's apply workspace (" + std::to_string(off) + " bytes) exceeds the " +
+                 std::to_string(cap) + "-byte scratch of the allocation-free apply");
+    return w;
+}
+}  // namespace
+
+static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st,
+                          int nrhs);
+
 // out = L_q in.  fp32: the FFTs, densities, point-wise products and the
 // nonlocal/projector contractions run in single precision (FP32 MFMA, FP32
 // accumulation); the potential (Hartree + kernel), the kinetic term and the
@@ -582,6 +640,14 @@ void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipS
     if (fp32)
         TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
                  "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
+    apply_l_ready(s, iq, in, out, fp32, st, nrhs);
+}
+
+// the launches of one apply; the workspace (s.ws) and the ground-state caches
+// of the q set are in place (nothing is allocated here)
+static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st,
+                          int nrhs) {
+    QSet& q = s.qs[iq];
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
     launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st, fp32, nrhs);
     launch_density(s, q, st, fp32, nrhs);
@@ -1455,6 +1521,43 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
 int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,
                          void* stream) {
     return tm_liouvillian_apply_multi(sys, iq, 1, xy_in, xy_out, prec, stream);
+}
+
+int tm_liouvillian_apply_noalloc(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,
+                                 void* stream) {
+    return guarded([&]() -> int {
+        TM_CHECK(sys && xy_in && xy_out, TM_EINVAL, "null argument");
+        System& s = sys->s;
+        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
+        TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
+        QSet& q = s.qs[iq];
+        const size_t bytes = (size_t)2 * q.nk * s.nbnd * 2 * q.npw_pad * sizeof(double2);
+        const char* a = static_cast<const char*>(xy_in);
+        const char* b = static_cast<const char*>(xy_out);
+        TM_CHECK(a + bytes <= b || b + bytes <= a, TM_EINVAL, "xy_in and xy_out overlap");
+        int dev = -1;
+        TM_HIP(hipGetDevice(&dev));
+        TM_CHECK(dev == s.device, TM_EINVAL, "the current device is not the system's device");
+        // the ground-state caches are built (and allocated) by an ordinary apply
+        TM_CHECK(q.ground_ready && (s.ureal_mode == 1 || q.ucols), TM_EINVAL,
+                 "the q set's ground-state caches are not built: call tm_liouvillian_apply once first");
+        if (prec == TM_FP32)
+            TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
+                     "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
+        Workspace w = scratch_workspace(s, scratch_address(dev), kNoallocScratchBytes);
+        w.epoch = s.ws.epoch;
+        const Workspace saved = s.ws;
+        s.ws = w;
+        try {
+            apply_l_ready(s, iq, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out),
+                          prec == TM_FP32, static_cast<hipStream_t>(stream), 1);
+        } catch (...) {
+            s.ws = saved;
+            throw;
+        }
+        s.ws = saved;
+        return TM_OK;
+    });
 }
 
 int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void* stream) {
