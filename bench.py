@@ -310,6 +310,7 @@ def run_qpath(args, tm, torch):
                    "lanes_per_chain": lanes},
         "applies_per_s": round((steps + len(specs)) / dt, 1),
         "breakdowns": nbroken,
+        "autotune": tm.tm_autotune_report(),
     }
     print(json.dumps(out))
 
@@ -710,6 +711,7 @@ def main():
         "roofline": roof,
         "step_roofline": step_roof,
         "kernels": kernels,
+        "autotune": tm.tm_autotune_report(),
         "cpu_baseline": cpu,
     }
     tm.tm_system_destroy(h)

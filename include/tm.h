@@ -226,6 +226,34 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
                                tm_precision prec, void* stream);
 
 /*
+ * Autotuning of launch shapes (an implementation device, not part of the
+ * method).  Several launches of the apply exist as compiled variants that
+ * split the same work differently: the plane density and apply kernels
+ * (butterflies per load group, columns per wave, row loads in flight), the z
+ * passes (threads, columns and items per block) and the projector / P_c
+ * contractions (K split).  At a system's first FP64 apply (outside a stream
+ * capture) every variant is timed on that system's data and the fastest is
+ * kept for that shape for the rest of the process; later systems of the same
+ * shape reuse it.  Plane and z-pass variants give identical results; the
+ * contraction variants sum K in different splits (results equal up to
+ * rounding).
+ *   tm_autotune_enable(on): on (the default) or off (variant 0, the
+ *     hand-picked default, for shapes not yet tuned).
+ *   tm_autotune_force(op, variant): use `variant` of operation op for every
+ *     shape (op: 0 plane density, 1 plane apply, 2 z inverse, 3 z forward,
+ *     4 contraction); -1 returns to the tuned choice.  A variant beyond a
+ *     shape's count makes that apply fail with TM_EINVAL.  For tests.
+ *   tm_autotune_report(buf, cap, needed): the tuned shapes as text, one line
+ *     each: operation, shape, number of variants, chosen variant, measured
+ *     microseconds per variant (tab-separated).  Writes at most cap bytes
+ *     (NUL-terminated) to the caller's buf (may be NULL) and the full size in
+ *     *needed.
+ */
+int tm_autotune_enable(int on);
+int tm_autotune_force(int op, int variant);
+int tm_autotune_report(char* buf, size_t cap, size_t* needed);
+
+/*
  * tm_liouvillian_apply_noalloc: tm_liouvillian_apply (one right-hand side,
  * same kernels, same result) for callers that cannot allocate device memory:
  * code under HIP graph capture, tight serving loops, harnesses that forbid

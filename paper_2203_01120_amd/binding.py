@@ -25,7 +25,8 @@ FLAVOURS = {"nH": 0, "non_hermitian": 0, "pH": 1, "pseudo_hermitian": 1}
 
 EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_system_set_resident_limit",
             "tm_system_set_chain_slots",
-            "tm_system_resident_bytes", "tm_system_memory", "tm_system_footprint", "tm_liouvillian_apply", "tm_liouvillian_apply_noalloc", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
+            "tm_system_resident_bytes", "tm_system_memory", "tm_system_footprint", "tm_liouvillian_apply", "tm_liouvillian_apply_noalloc",
+            "tm_autotune_enable", "tm_autotune_force", "tm_autotune_report", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
             "tm_chain_begin_multi", "tm_chain_lanes", "tm_tensor_run", "tm_liouvillian_apply_multi",
@@ -107,6 +108,9 @@ def load(path: str = LIB_PATH):
     lib.tm_system_footprint.argtypes = [C.POINTER(_Desc), C.POINTER(_MemInfo)]
     lib.tm_liouvillian_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
     lib.tm_liouvillian_apply_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p]
+    lib.tm_autotune_enable.argtypes = [C.c_int]
+    lib.tm_autotune_force.argtypes = [C.c_int, C.c_int]
+    lib.tm_autotune_report.argtypes = [C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]
     lib.tm_liouvillian_apply_multi.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int,
                                                C.c_void_p]
     lib.tm_start_vectors.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
@@ -306,6 +310,33 @@ def tm_liouvillian_apply_noalloc(h, iq: int, xy_in, xy_out, prec: int = TM_FP64,
     _check_tensor(xy_out, nelem)
     _check(load().tm_liouvillian_apply_noalloc(C.c_void_p(h), iq, C.c_void_p(xy_in.data_ptr()),
                                                C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
+
+
+TUNE_OPS = {"plane_density": 0, "plane_apply": 1, "zpass_inverse": 2, "zpass_forward": 3, "contraction": 4}
+
+
+def tm_autotune_enable(on: bool) -> None:
+    _check(load().tm_autotune_enable(1 if on else 0))
+
+
+def tm_autotune_force(op: str, variant: int) -> None:
+    """Force `variant` of a tunable operation for every shape (-1: the tuned choice)."""
+    _check(load().tm_autotune_force(TUNE_OPS[op], int(variant)))
+
+
+def tm_autotune_report() -> list:
+    """The tuned shapes: dicts(op, shape, variants, chosen, us[])."""
+    lib = load()
+    need = C.c_size_t(0)
+    _check(lib.tm_autotune_report(None, 0, C.byref(need)))
+    buf = C.create_string_buffer(need.value)
+    _check(lib.tm_autotune_report(buf, need.value, C.byref(need)))
+    out = []
+    for line in buf.value.decode().splitlines():
+        op, shape, nv, ch, us = line.split("\t")
+        out.append({"op": op, "shape": shape, "variants": int(nv.split()[1]), "chosen": int(ch.split()[1]),
+                    "us": [round(float(x), 1) for x in us.split()[1:]]})
+    return out
 
 
 def tm_liouvillian_apply_multi(h, iq: int, nrhs: int, xy_in, xy_out, prec: int = TM_FP64, stream=None):

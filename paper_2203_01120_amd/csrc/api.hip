@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <set>
 #include <unordered_map>
@@ -79,6 +80,46 @@ ProfScope::ProfScope(const char* name, hipStream_t s) : slot(-1), st(s) {
 
 ProfScope::~ProfScope() {
     if (slot >= 0) (void)hipEventRecord(g_prof_pending[slot].b, st);
+}
+
+// ---- autotuning registry -----------------------------------------------------------
+namespace {
+struct TuneEntry {
+    int op;
+    long long key;
+    int nvariants = 0;
+    int chosen = 0;
+    std::vector<float> us;      // timed microseconds per variant
+    std::string shape;          // human-readable shape
+};
+std::mutex g_tune_mu;
+std::map<std::pair<int, long long>, TuneEntry> g_tuned;
+int g_force[kTuneOps] = {-1, -1, -1, -1, -1};
+int g_trial[kTuneOps] = {-1, -1, -1, -1, -1};   // the variant being timed
+long long g_seen_key[kTuneOps];
+int g_seen_n[kTuneOps];
+bool g_autotune = true;
+const char* const kTuneNames[kTuneOps] = {"plane_density", "plane_apply", "zpass_inverse", "zpass_forward",
+                                           "contraction"};
+}  // namespace
+
+int tune_pick(int op, long long key, int nvariants) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_seen_key[op] = key;
+    g_seen_n[op] = nvariants;
+    int v = 0;
+    if (g_force[op] >= 0) {
+        v = g_force[op];
+    } else if (g_trial[op] >= 0) {
+        v = g_trial[op];
+    } else {
+        auto it = g_tuned.find({op, key});
+        if (it != g_tuned.end()) v = it->second.chosen;
+    }
+    TM_CHECK(v >= 0 && v < nvariants, TM_EINVAL,
+             std::string("variant ") + std::to_string(v) + " of " + kTuneNames[op] + " out of range (" +
+                 std::to_string(nvariants) + " variants for this shape)");
+    return v;
 }
 
 void check_launch(const char* what) {
@@ -629,6 +670,85 @@ Workspace scratch_workspace(const System& s, char* base, size_t cap) {
 static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st,
                           int nrhs);
 
+// ---- the autotuner ---------------------------------------------------------------
+// Times every compiled variant of each tunable launch of one FP64 apply on the
+// system's own data (three runs each after a warm-up, HIP events on the
+// apply's stream) and keeps the fastest per shape, once per shape and process:
+// plane density and apply kernels, the two z passes, the projector and P_c
+// contractions.  `out` (one right-hand side) is scratch here; the caller's
+// apply recomputes it with the chosen variants.
+static void autotune(System& s, int iq, const double2* in, double2* out, hipStream_t st) {
+    QSet& q = s.qs[iq];
+    hipEvent_t e0, e1;
+    TM_HIP(hipEventCreate(&e0));
+    TM_HIP(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    apply_l_ready(s, iq, in, out, false, st, 1);  // every buffer holds this system's data
+    const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
+    struct Op {
+        int op;
+        const char* what;
+        std::function<void()> run;
+    };
+    const Op ops[] = {
+        {kTuneZInv, "z inverse", [&] { launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st); }},
+        {kTuneDensity, "density planes", [&] { launch_density(s, q, st); }},
+        {kTuneApply, "apply planes", [&] { launch_apply_planes(s, q, st); }},
+        {kTuneZFwd, "z forward", [&] { launch_zpass_fwd(s, q, s.ws.xcols, in, out, st); }},
+        {kTuneGemm, "P_c contraction", [&] { launch_project(s, q, out, st); }},
+        {kTuneGemm, "projector contraction", [&] { launch_nonlocal(s, q, in, out, st); }},
+    };
+    for (const Op& o : ops) {
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_seen_n[o.op] = 0;
+        }
+        o.run();  // the default variant; records the launch's shape key and variant count
+        long long key;
+        int n;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            key = g_seen_key[o.op];
+            n = g_seen_n[o.op];
+            if (n <= 1 || g_force[o.op] >= 0 || g_tuned.count({o.op, key})) continue;
+        }
+        std::vector<float> us(n);
+        try {
+            for (int v = 0; v < n; ++v) {
+                g_trial[o.op] = v;
+                o.run();
+                TM_HIP(hipEventRecord(e0, st));
+                for (int r = 0; r < 3; ++r) o.run();
+                TM_HIP(hipEventRecord(e1, st));
+                TM_HIP(hipEventSynchronize(e1));
+                float ms = 0;
+                TM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                us[v] = ms * 1000.0f / 3.0f;
+            }
+        } catch (...) {
+            g_trial[o.op] = -1;
+            throw;
+        }
+        g_trial[o.op] = -1;
+        TuneEntry t;
+        t.op = o.op;
+        t.key = key;
+        t.nvariants = n;
+        t.chosen = (int)(std::min_element(us.begin(), us.end()) - us.begin());
+        t.us = us;
+        t.shape = std::string(o.what) + " grid " + std::to_string(s.n1) + "x" + std::to_string(s.n2) + "x" +
+                  std::to_string(s.n3) + ", " + std::to_string(s.nbnd) + " bands, " + std::to_string(q.nk) + " k";
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[{o.op, key}] = t;
+    }
+}
+
 // out = L_q in.  fp32: the FFTs, densities, point-wise products and the
 // nonlocal/projector contractions run in single precision (FP32 MFMA, FP32
 // accumulation); the potential (Hartree + kernel), the kinetic term and the
@@ -640,6 +760,14 @@ void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipS
     if (fp32)
         TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
                  "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
+    if (!s.tuned && !fp32 && g_autotune) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        TM_HIP(hipStreamIsCapturing(st, &cs));
+        if (cs == hipStreamCaptureStatusNone) {  // (timing is impossible inside a capture)
+            autotune(s, iq, in, out, st);
+            s.tuned = true;
+        }
+    }
     apply_l_ready(s, iq, in, out, fp32, st, nrhs);
 }
 
@@ -1521,6 +1649,44 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
 int tm_liouvillian_apply(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,
                          void* stream) {
     return tm_liouvillian_apply_multi(sys, iq, 1, xy_in, xy_out, prec, stream);
+}
+
+int tm_autotune_enable(int on) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_autotune = on != 0;
+    return TM_OK;
+}
+
+int tm_autotune_force(int op, int variant) {
+    return guarded([&]() -> int {
+        TM_CHECK(op >= 0 && op < kTuneOps, TM_EINVAL, "unknown tunable operation");
+        TM_CHECK(variant >= -1, TM_EINVAL, "variant must be -1 (tuned) or an index");
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_force[op] = variant;
+        return TM_OK;
+    });
+}
+
+int tm_autotune_report(char* buf, size_t cap, size_t* needed) {
+    return guarded([&]() -> int {
+        TM_CHECK(needed != nullptr, TM_EINVAL, "null argument");
+        std::string r;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const auto& kv : g_tuned) {
+            const TuneEntry& t = kv.second;
+            r += std::string(kTuneNames[t.op]) + "\t" + t.shape + "\tvariants " + std::to_string(t.nvariants) +
+                 "\tchosen " + std::to_string(t.chosen) + "\tus";
+            for (float u : t.us) r += " " + std::to_string(u);
+            r += "\n";
+        }
+        *needed = r.size() + 1;
+        if (buf && cap > 0) {
+            const size_t n = std::min(cap - 1, r.size());
+            std::memcpy(buf, r.data(), n);
+            buf[n] = 0;
+        }
+        return TM_OK;
+    });
 }
 
 int tm_liouvillian_apply_noalloc(tm_system* sys, int iq, const void* xy_in, void* xy_out, tm_precision prec,

@@ -332,16 +332,17 @@ bool cn_lds_fits(int M, int Nn) {
 }
 
 // K range per block: about 4 blocks per CU over all batches, a multiple of the LDS chunk
-int cn_lds_kchunk(int K, int nbatch) {
-    const int ks = std::max(1, 1024 / std::max(1, nbatch));
+// K chunk per block: about `target` blocks over the batches of one right-hand
+// side (the autotuner times 1024, 512 and 2048)
+int cn_lds_kchunk(int K, int nbatch, int target = 1024) {
+    const int ks = std::max(1, target / std::max(1, nbatch));
     int kc = (K + ks - 1) / ks;
     kc = std::max(kCnChunk * 4, (kc + kCnChunk - 1) / kCnChunk * kCnChunk);
     return kc;
 }
 
-int choose_kchunk(int K, long long tiles_times_batch) {
+int choose_kchunk(int K, long long tiles_times_batch, long long target = 8192) {
     // enough waves to fill the chip, but chunks of at least 64
-    long long target = 8192;
     int ks = (int)std::max<long long>(1, target / std::max<long long>(1, tiles_times_batch));
     int kc = (K + ks - 1) / ks;
     kc = std::max(64, (kc + 3) / 4 * 4);
@@ -377,8 +378,12 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
         }
         return;
     }
+    // the K split the autotuner picked for this contraction shape (per right-hand
+    // side, so that every right-hand side is summed as when alone); FP64 only
+    constexpr int kTargets[3] = {1024, 512, 2048};
+    const int tv = f32 ? 0 : tune_pick(kTuneGemm, tune_key(M, Nn, K, nbatch), 3);
     if (cn_lds_fits(M, Nn)) {
-        g.kchunk = cn_lds_kchunk(K, nbatch);
+        g.kchunk = cn_lds_kchunk(K, nbatch, kTargets[tv]);
         g.ksplit = (K + g.kchunk - 1) / g.kchunk;
         TM_CHECK((size_t)nrhs * nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL,
                  "GEMM partial buffer too small");
@@ -393,7 +398,7 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
             TM_LAUNCH(k_gemm_cn_lds<double>, grid, dim3(kCnThreads), shm, st, g, mt);
         }
     } else {
-        g.kchunk = choose_kchunk(K, (long long)mt * g.nt * nbatch);
+        g.kchunk = choose_kchunk(K, (long long)mt * g.nt * nbatch, 8LL * kTargets[tv]);
         g.ksplit = (K + g.kchunk - 1) / g.kchunk;
         TM_CHECK((size_t)nrhs * nbatch * g.ksplit * M * Nn <= s.ws.cap_gpart, TM_EINVAL,
                  "GEMM partial buffer too small");
@@ -440,9 +445,10 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
 
 }  // namespace
 
+// partial sums of the finest K split any variant uses
 size_t gemm_partial_elems(int nbatch, int M, int Nn, int K) {
     int mt = (M + 15) / 16, nt = (Nn + 15) / 16;
-    int kc = cn_lds_fits(M, Nn) ? cn_lds_kchunk(K, nbatch) : choose_kchunk(K, (long long)mt * nt * nbatch);
+    int kc = cn_lds_fits(M, Nn) ? cn_lds_kchunk(K, nbatch, 2048) : choose_kchunk(K, (long long)mt * nt * nbatch, 16384);
     int ks = (K + kc - 1) / kc;
     return (size_t)nbatch * ks * M * Nn;
 }

@@ -614,14 +614,15 @@ __device__ __forceinline__ void wfft_dif(T2* pl, const WL& L, int nl, const WTw<
     }
 }
 
-template <int N, int SIGN, int MAXL, int BT, int STAGE, class WL, class T2>
+// stages STAGE, STAGE - 1, ..., STOP of the plan
+template <int N, int SIGN, int MAXL, int BT, int STAGE, int STOP = 0, class WL, class T2>
 __device__ __forceinline__ void wfft_dit(T2* pl, const WL& L, int nl, const WTw<N, T2>& tw, int lane) {
     constexpr CPlan cp = cplan(N);
-    if constexpr (STAGE >= 0) {
+    if constexpr (STAGE >= STOP) {
         constexpr int R = cp.rad[STAGE];
         constexpr int LB = N / cp.pre[STAGE];
         wpass<N, STAGE, R, LB, SIGN, false, false, MAXL, BT>(pl, L, nl, tw, lane);
-        wfft_dit<N, SIGN, MAXL, BT, STAGE - 1>(pl, L, nl, tw, lane);
+        wfft_dit<N, SIGN, MAXL, BT, STAGE - 1, STOP>(pl, L, nl, tw, lane);
     }
 }
 
@@ -706,9 +707,13 @@ struct WTail {
     __device__ static bool live(int lane, int i) { return lane + 64 * i < SLOTS; }
 };
 
-template <int N1, int N2, int BT_, int CPW_, class T2, int NBUF_, int FCH_ = 64>
+template <int N1, int N2, int BT_, int CPW_, class T2, int NBUF_, int FCH_ = 64, bool FUSE_ = false>
 struct WaveKernel {
     using G = Geom<N1, N2>;
+    // FUSE: the row fill is fused with the first inverse row stage, and the last
+    // forward row stage with the output (a row's values skip one LDS round trip
+    // at each end)
+    static constexpr bool FUSE = FUSE_;
     static constexpr int NBUF = NBUF_;              // LDS buffers alternating between bands (1 or 2)
     static constexpr int CPW = CPW_;                // columns per wave
     static constexpr int NW = N2 / CPW;             // waves
@@ -786,8 +791,109 @@ struct WaveKernel {
     // FCH > 1: the table reads and column loads of FCH elements are issued
     // before their LDS stores, so that a lane's elements do not wait on each
     // other (more registers); FCH = 1: one element at a time.
+    // The row fill fused with the first (DIF) stage of the inverse row
+    // transform: the lane of butterfly j of row line li loads that row's
+    // elements j + t M (t < R) straight from the z-transformed columns (zero
+    // outside the sphere), all of its butterflies' loads in flight together,
+    // transforms and twiddles them exactly as the stage does in LDS, and stores
+    // the R results; then the remaining stages.
+    __device__ static void rows_inverse_fused(const Smem& m, const T2* cx, long long cs, int nlw, int w, int boff,
+                                              int lane, const WTw<N2, T2>& gtw2, Rows rl) {
+        constexpr CPlan cp = cplan(N2);
+        constexpr int R = cp.rad[0];
+        constexpr int M = N2 / R;                  // butterflies per line; stage 0 has LB = N2
+        constexpr int SPL = wslots(M);
+        constexpr int IT = cdiv(MAXR * SPL, 64);
+        const int ns = nlw * SPL;
+        T2 u[IT][R];
+        int base[IT], jv[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int sl = lane + it * 64;
+            const int li = sl / SPL, j = sl - li * SPL;
+            base[it] = -1;
+            jv[it] = j;
+            if (sl < ns && j < M) {
+                const int l = w + li * NW;
+                const int info = m.rowinfo[l];
+                const int s = info / N1, row = info - s * N1;
+                const short* ci = m.colidx + row * N2;
+                base[it] = boff + m.rowbase[l] + j;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const int c = ci[j + t * M];
+                    u[it][t] = c >= 0 ? cx[s * cs + c] : Cx<T2>::mk(0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            if (base[it] >= 0) {
+                dft_small<R>(u[it], +1);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    T2 y = u[it][r];
+                    if (r > 0 && jv[it] > 0) {
+                        T2 wv = gtw2.template get<0, N2>(r, jv[it]);
+                        wv.y = -wv.y;
+                        y = cmul(y, wv);
+                    }
+                    m.pl[base[it] + r * M] = y;
+                }
+            }
+        }
+        wave_sync();
+        rl.boff = boff;
+        wfft_dif<N2, +1, false, MAXR, BT, cp.nrad, 1, N2 / R>(m.pl, rl, nlw, gtw2, lane);
+    }
+
+    // The forward row transform of the wave's rows of buffer boff with its last
+    // (DIT) stage fused with the output: the lane of butterfly j reads its R
+    // inputs from LDS, twiddles and transforms them exactly as the stage does
+    // in LDS, and stores the results that lie on the sphere to co.
+    __device__ static void rows_forward_out(const Smem& m, T2* co, long long cs, int nlw, int w, int boff, int lane,
+                                            const WTw<N2, T2>& gtw2, Rows rl) {
+        constexpr CPlan cp = cplan(N2);
+        rl.boff = boff;
+        wfft_dit<N2, -1, MAXR, BT, cp.nrad - 1, 1>(m.pl, rl, nlw, gtw2, lane);
+        constexpr int R = cp.rad[0];
+        constexpr int M = N2 / R;
+        constexpr int SPL = wslots(M);
+        constexpr int IT = cdiv(MAXR * SPL, 64);
+        const int ns = nlw * SPL;
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int sl = lane + it * 64;
+            const int li = sl / SPL, j = sl - li * SPL;
+            if (sl < ns && j < M) {
+                const int l = w + li * NW;
+                const int info = m.rowinfo[l];
+                const int s = info / N1, row = info - s * N1;
+                const short* ci = m.colidx + row * N2;
+                const T2* px = m.pl + boff + m.rowbase[l] + j;
+                T2 u[R];
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    T2 x = px[t * M];
+                    if (t > 0 && j > 0) x = cmul(x, gtw2.template get<0, N2>(t, j));
+                    u[t] = x;
+                }
+                dft_small<R>(u, -1);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int c = ci[j + r * M];
+                    if (c >= 0) co[s * cs + c] = u[r];
+                }
+            }
+        }
+    }
+
     __device__ static void rows_inverse(const Smem& m, const T2* cx, long long cs, int nlw, int w, int boff,
                                         int lane, const WTw<N2, T2>& gtw2, Rows rl) {
+        if constexpr (FUSE) {
+            rows_inverse_fused(m, cx, cs, nlw, w, boff, lane, gtw2, rl);
+            return;
+        }
         if constexpr (FCH == 1) {
             for (int k = lane; k < nlw * N2; k += 64) {
                 const int li = k / N2, p2 = k - li * N2;
@@ -835,9 +941,9 @@ struct WaveKernel {
 
 // MINW: waves per SIMD the register allocation must leave room for; FCH: row
 // elements per lane whose loads are in flight together
-template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH>
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH>;
+    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH, FUSE>;
     using G = typename K::G;
     using TL = WTail<N1, N2, CPW>;
     constexpr int R = TL::R, IT = TL::IT;
@@ -968,9 +1074,9 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH>
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, PlaneTabs t) {
-    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH>;
+    using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH, FUSE>;
     using G = typename K::G;
     using TL = WTail<N1, N2, CPW>;
     constexpr int PPL = cdiv(K::WPTS, 64);
@@ -1058,12 +1164,16 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
         __syncthreads();
         // rows: forward along i2 on the occupied rows of the k+q sphere, then
         // the output columns
-        constexpr CPlan c2 = cplan(N2);
-        typename K::Rows rlb = rl;
-        rlb.boff = boff;
-        wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rlb, nlw, tw2, lane);
-        K::rows_out(m, xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max, cs, nlw, w, boff,
-                    lane);
+        T2* co = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        if constexpr (K::FUSE) {
+            K::rows_forward_out(m, co, cs, nlw, w, boff, lane, tw2, rl);
+        } else {
+            constexpr CPlan c2 = cplan(N2);
+            typename K::Rows rlb = rl;
+            rlb.boff = boff;
+            wfft_dit<N2, -1, K::MAXR, K::BT, c2.nrad - 1>(m.pl, rlb, nlw, tw2, lane);
+            K::rows_out(m, co, cs, nlw, w, boff, lane);
+        }
         // no barrier here: with two buffers the next band works in the other
         // one; with one, each wave rewrites only the rows it has just finished
     }
@@ -1084,24 +1194,70 @@ void launch_with_lds(F kernel, const char* name, size_t shm, dim3 grid, int nt, 
     check_launch(name);
 }
 
+// Variants of the FP64 wave plane kernels that the autotuner times, variant 0
+// being the hand-picked default: BT butterflies per load group, CPW columns
+// per wave, FCH row elements in flight per lane, fused first / last row
+// stages (all with two LDS buffers and no occupancy floor).  They split the
+// work differently and do the same arithmetic per point in the same order,
+// so their results are identical.
+template <int N1, int N2>
+struct WaveVariants {  // 8x8, 24x24, 32x32
+    static constexpr int n = 3;
+    static constexpr int bt[n] = {2, 1, 2}, cpw[n] = {4, 4, 4}, fch[n] = {1, 1, 1};
+    static constexpr bool fuse[n] = {false, false, true};
+};
+template <>
+struct WaveVariants<48, 48> {
+    static constexpr int n = 6;
+    static constexpr int bt[n] = {2, 1, 4, 2, 2, 1}, cpw[n] = {4, 4, 4, 4, 4, 4}, fch[n] = {1, 1, 1, 4, 1, 1};
+    static constexpr bool fuse[n] = {false, false, false, false, true, true};
+};
+template <>
+struct WaveVariants<20, 20> {
+    static constexpr int n = 5;
+    static constexpr int bt[n] = {2, 2, 1, 2, 2}, cpw[n] = {5, 4, 5, 10, 5}, fch[n] = {1, 1, 1, 1, 1};
+    static constexpr bool fuse[n] = {false, false, false, false, true};
+};
+
+template <int N1, int N2, int V>
+void launch_wave_one(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 wgrid, hipStream_t st) {
+    using VV = WaveVariants<N1, N2>;
+    constexpr int BT = VV::bt[V], CPW = VV::cpw[V], FCH = VV::fch[V];
+    constexpr bool FU = VV::fuse[V];
+    using K = WaveKernel<N1, N2, BT, CPW, double2, 2, FCH, FU>;
+    if (density)
+        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU>, "k_density_w", K::bytes(), wgrid,
+                        K::NT, st, a, t);
+    else
+        launch_with_lds(k_apply_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU>, "k_apply_w", K::bytes(), wgrid, K::NT,
+                        st, a, t);
+}
+
+// launches variant v (0 .. V) of the FP64 density or apply
+template <int N1, int N2, int V>
+void launch_wave_v(bool density, int v, const PlaneArgs& a, const PlaneTabs& t, dim3 wgrid, hipStream_t st, int) {
+    if constexpr (V >= 0) {
+        if (v == V) return launch_wave_one<N1, N2, V>(density, a, t, wgrid, st);
+        launch_wave_v<N1, N2, V - 1>(density, v, a, t, wgrid, st, 0);
+    }
+}
+
 // NT: threads of the block-synchronous kernels (column path, builder)
 template <int N1, int N2, int NT>
 void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStream_t st, bool fp32) {
-    // 4 columns per wave (12 waves for 48 x 48; 3 columns and 16 waves measured
-    // slower: idle lanes in the column stages and register spills at 128 VGPRs;
-    // one buffer with 6 or 8 columns, or 6 waves per SIMD, spill in FP64).  The
-    // single-precision apply at 48 x 48 runs 6 columns per wave and 4 waves per
-    // SIMD (2 blocks per CU in 2 x 81 KB of LDS, no spills): 7 % faster.
-    // 20 x 20 planes: 5 columns per wave (4 waves), 1-2 % faster than 4 (5 waves) on
-    // the 20^3 system, 2 columns 7 % slower
-    constexpr int CPW = N2 == 20 ? 5 : 4, CPW32 = N2 == 20 ? 5 : 4, CPWA32 = N2 == 48 ? 6 : N2 == 20 ? 5 : 4;
+    // FP64: the variants of WaveVariants, picked per shape by the autotuner
+    // (defaults: 4 columns per wave, 12 waves for 48 x 48 -- 3 columns and 16
+    // waves measured slower: idle lanes in the column stages and register
+    // spills at 128 VGPRs; one buffer with 6 or 8 columns, or 6 waves per SIMD,
+    // spill in FP64; 20 x 20 planes: 5 columns per wave).  Single precision
+    // (fixed): the apply at 48 x 48 runs 6 columns per wave and 4 waves per
+    // SIMD (2 blocks per CU in 2 x 81 KB of LDS, no spills): 7 % faster; the
+    // density's row fill keeps all of a lane's loads in flight together
+    // (FCH = 64, 10 % faster at 48 x 48); the 6-column apply would spill with it.
+    constexpr int CPW32 = N2 == 20 ? 5 : 4, CPWA32 = N2 == 48 ? 6 : N2 == 20 ? 5 : 4;
     constexpr int BTD = 2, BTA = 2;
-    constexpr int NBUF = 2, MINW = 1, NBUF32 = 2, MINW32 = 1, MINWA32 = N2 == 48 ? 4 : 1;
-    // Row fill with all of a lane's loads in flight together (FCH = 64) in the
-    // single-precision density (10 % faster at 48 x 48); element by element
-    // (FCH = 1) elsewhere: the FP64 density and the 6-column FP32 apply would
-    // spill, and the FP64 apply measured 2 % slower.
-    constexpr int FCHD = 1, FCHA = 1, FCHD32 = 64, FCHA32 = 1;
+    constexpr int NBUF32 = 2, MINW32 = 1, MINWA32 = N2 == 48 ? 4 : 1;
+    constexpr int FCHD32 = 64, FCHA32 = 1;
     if (op == kOpUreal) {
         launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
     } else if (a.ureal) {
@@ -1122,17 +1278,17 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
             }
             return;
         }
-        using WD = WaveKernel<N1, N2, BTD, CPW, double2, NBUF>;
-        using WA = WaveKernel<N1, N2, BTA, CPW, double2, NBUF>;
+        // FP64: the variant the autotuner picked for this shape (plane, planes, bands and sides)
+        const long long key = tune_key(N1 * 1000 + N2, a.n3, a.nb, a.nb2);
         if (op == kOpDensity) {
-            launch_with_lds(k_density_w<N1, N2, BTD, CPW, double2, NBUF, MINW, FCHD>, "k_density_w", WD::bytes(), wgrid,
-                            WD::NT, st, a, t);
+            constexpr int NV = WaveVariants<N1, N2>::n;
+            launch_wave_v<N1, N2, NV - 1>(true, tune_pick(kTuneDensity, key, NV), a, t, wgrid, st, nrhs);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                       a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
-            launch_with_lds(k_apply_w<N1, N2, BTA, CPW, double2, NBUF, MINW, FCHA>, "k_apply_w", WA::bytes(), wgrid,
-                            WA::NT, st, a, t);
+            constexpr int NV = WaveVariants<N1, N2>::n;
+            launch_wave_v<N1, N2, NV - 1>(false, tune_pick(kTuneApply, key, NV), a, t, wgrid, st, nrhs);
         }
     } else {
         TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision plane kernels need the resident ground state");
@@ -1303,16 +1459,54 @@ bool zpass_fixed_supported(int n3) {
     return n3 == 8 || n3 == 20 || n3 == 24 || n3 == 32 || n3 == 48 || n3 == 96 || n3 == 180;
 }
 
+// Launch shapes of the fixed-length z passes (threads NT, columns CT and items
+// IT per block) that the autotuner times, variant 0 the hand-picked default
+// (20: 7710 applies/s with 128 / 16 / 1 against 7519 with 256 / 16 / 4 on the
+// 20^3 system).  Every line is transformed alike, so the results are identical.
+namespace {
+template <int N3, int NT, int CT, int IT>
+struct ZV {};
+template <int N3, class... V>
+struct ZVariants {
+    static constexpr int n = sizeof...(V);
+};
+
+template <int N3, int NT, int CT, int IT, class... Rest>
+void launch_z_v(int v, bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStream_t st, bool fp32,
+                ZV<N3, NT, CT, IT>, Rest... rest) {
+    if (v == 0) return launch_z<N3, NT, CT, IT>(inverse, a, ncolmax, nbatch, st, fp32);
+    if constexpr (sizeof...(Rest) > 0) launch_z_v(v - 1, inverse, a, ncolmax, nbatch, st, fp32, rest...);
+}
+
+template <class... V>
+void launch_z_tuned(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st, bool fp32,
+                    V... vs) {
+    constexpr int n = sizeof...(V);
+    // single precision keeps the default; FP64 takes the tuned variant of this shape
+    const int v = fp32 ? 0 : tune_pick(inverse ? kTuneZInv : kTuneZFwd, tune_key(n3, ncolmax, nbatch, a.nitems), n);
+    launch_z_v(v, inverse, a, ncolmax, nbatch, st, fp32, vs...);
+}
+}  // namespace
+
 void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, int n3, hipStream_t st,
                         bool fp32) {
     switch (n3) {
-        case 8: launch_z<8, 256, 16, 4>(inverse, a, ncolmax, nbatch, st, fp32); break;
-        case 20: launch_z<20, 128, 16, 1>(inverse, a, ncolmax, nbatch, st, fp32); break;  // 7710 vs 7519 applies/s (256, 16, 4)
-        case 24: launch_z<24, 256, 16, 4>(inverse, a, ncolmax, nbatch, st, fp32); break;
-        case 32: launch_z<32, 256, 16, 2>(inverse, a, ncolmax, nbatch, st, fp32); break;
-        case 48: launch_z<48, 256, 16, 2>(inverse, a, ncolmax, nbatch, st, fp32); break;
-        case 96: launch_z<96, 256, 16, 1>(inverse, a, ncolmax, nbatch, st, fp32); break;
-        case 180: launch_z<180, 256, 16, 1>(inverse, a, ncolmax, nbatch, st, fp32); break;
+        case 8: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<8, 256, 16, 4>{}, ZV<8, 128, 16, 2>{}); break;
+        case 20:
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<20, 128, 16, 1>{}, ZV<20, 256, 16, 4>{},
+                           ZV<20, 64, 16, 1>{});
+            break;
+        case 24: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<24, 256, 16, 4>{}, ZV<24, 128, 16, 2>{}); break;
+        case 32: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<32, 256, 16, 2>{}, ZV<32, 128, 16, 1>{}); break;
+        case 48: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<48, 256, 16, 2>{}, ZV<48, 128, 16, 1>{}); break;
+        case 96:
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<96, 256, 16, 1>{}, ZV<96, 128, 16, 1>{},
+                           ZV<96, 512, 32, 1>{});
+            break;
+        case 180:
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<180, 256, 16, 1>{}, ZV<180, 128, 16, 1>{},
+                           ZV<180, 512, 32, 1>{});
+            break;
         default: throw Error{TM_EUNSUPPORTED, "no fixed-size z pass for this grid"};
     }
 }

@@ -49,6 +49,25 @@ struct ProfScope {
         ::tml::check_launch(#kern);                                         \
     } while (0)
 
+// ---------------------------------------------------------------- autotuning
+// Launch shapes picked per problem shape by timing.  A launcher with several
+// compiled variants of one operation asks tune_pick(op, key, n) which of its
+// n variants to use for shape `key`: a variant forced for tests, the one
+// chosen by the last timing of that shape, or 0 (the hand-picked default).
+// Variants of the plane kernels and z passes do the same arithmetic in the
+// same order (only the work split differs), so their results are identical;
+// the contraction's variants split K differently (rounding-level differences).
+enum TuneOp { kTuneDensity = 0, kTuneApply = 1, kTuneZInv = 2, kTuneZFwd = 3, kTuneGemm = 4, kTuneOps = 5 };
+int tune_pick(int op, long long key, int nvariants);
+inline long long tune_key(long long a, long long b = 0, long long c = 0, long long d = 0) {
+    unsigned long long h = 1469598103934665603ULL;  // FNV-1a over the four values
+    for (long long v : {a, b, c, d}) {
+        h ^= (unsigned long long)v;
+        h *= 1099511628211ULL;
+    }
+    return (long long)(h >> 1);
+}
+
 // ---------------------------------------------------------------- complex
 __host__ __device__ inline double2 cmk(double r, double i) { return make_double2(r, i); }
 __host__ __device__ inline double2 cadd(double2 a, double2 b) { return cmk(a.x + b.x, a.y + b.y); }
@@ -249,6 +268,7 @@ struct System {
     int next_slot = 0;
     std::vector<void*> allocs;
     size_t table_bytes = 0;            // device bytes of everything in `allocs`
+    bool tuned = false;                // the autotuner has timed this system's launches
 };
 
 template <typename T>

@@ -96,6 +96,39 @@ def test_fullsize_apply_matches_oracle(slab1k):
 
 
 @pytest.mark.timeout(ORACLE_TIMEOUT)
+def test_fullsize_every_tuned_variant_matches_oracle(slab1k):
+    """Each autotuner candidate of this shape (plane kernels of 48 x 48, z
+    passes of 180, the 104-band contractions), forced in turn, against one
+    oracle apply at 1e-12."""
+    import torch
+    from gpu_util import from_gpu, rel_err, to_gpu
+    tm, h, info, prob = slab1k
+    x = prob.random_projected(3)
+    xin = to_gpu(x, info["npw_pad"])
+    out = torch.empty_like(xin)
+    tm.tm_liouvillian_apply(h, 0, xin, out)
+    torch.cuda.synchronize()
+    say("one-point slab: oracle apply for the variants")
+    ref = prob.apply(x)
+    entries = [e for e in tm.tm_autotune_report() if "grid 48x48x180, 104 bands, 1 k" in e["shape"]]
+    say("tuned: " + "; ".join(f"{e['op']} {e['chosen']}/{e['variants']} {e['us']}" for e in entries))
+    assert {e["op"] for e in entries} >= {"plane_density", "plane_apply", "zpass_inverse", "zpass_forward",
+                                          "contraction"}
+    for e in entries:
+        try:
+            for v in range(e["variants"]):
+                tm.tm_autotune_force(e["op"], v)
+                tm.tm_liouvillian_apply(h, 0, xin, out)
+                torch.cuda.synchronize()
+                got, _ = from_gpu(out, (2, 1, prob.nb, 2, info["npw_pad"]), prob.npw_pad)
+                err = rel_err(got, ref)
+                say(f"  {e['op']} variant {v}: rel err {err:.2e}")
+                assert err <= 1e-12, (e["op"], v, err)
+        finally:
+            tm.tm_autotune_force(e["op"], -1)
+
+
+@pytest.mark.timeout(ORACLE_TIMEOUT)
 @pytest.mark.parametrize("flavour,mu,m", [("pH", "+", 3), ("nH", "-", 2)], ids=["pH+3", "nH-2"])
 def test_fullsize_chain_matches_oracle(slab1k, flavour, mu, m):
     from oracle import lanczos as olanczos
