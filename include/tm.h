@@ -231,12 +231,22 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
  * split the same work differently: the plane density and apply kernels
  * (butterflies per load group, columns per wave, row loads in flight), the z
  * passes (threads, columns and items per block) and the projector / P_c
- * contractions (K split).  At a system's first FP64 apply (outside a stream
- * capture) every variant is timed on that system's data and the fastest is
+ * contractions (K split).  Before a system's first tunable launch -- its
+ * first FP64 apply, start vector with a projection (tm_start_vectors with
+ * v), FP64 chain begin or restore -- outside a stream capture, every variant
+ * is timed on that system's data (the first apply's own vectors, else two
+ * scratch vectors allocated and freed for the purpose) and the fastest is
  * kept for that shape for the rest of the process; later systems of the same
- * shape reuse it.  Plane and z-pass variants give identical results; the
+ * shape reuse it.  So every result of a system comes from the same variants,
+ * whichever call came first.  Plane and z-pass variants give identical results; the
  * contraction variants sum K in different splits (results equal up to
- * rounding).
+ * rounding), so two processes may differ in the last bits -- forcing the
+ * contraction variant (tm_autotune_force(4, 0)) makes results reproducible
+ * bit for bit across processes, e.g. for a chain saved in one and restored in
+ * another.  A first call issued under stream capture is not timed (timing
+ * needs synchronisation); the system is tuned at its next such call outside
+ * a capture, and launches captured before that keep the variants in force
+ * when they were captured.
  *   tm_autotune_enable(on): on (the default) or off (variant 0, the
  *     hand-picked default, for shapes not yet tuned).
  *   tm_autotune_force(op, variant): use `variant` of operation op for every
@@ -278,7 +288,9 @@ int tm_liouvillian_apply_noalloc(tm_system* sys, int iq, const void* xy_in, void
  *   u^dir = ( sigma U~_{n,k}, -sigma T U~_{n,-k} ),
  *   v^dir = ( P sigma U~_{n,k}, P+ sigma T U~_{n,-k} ),
  * U~ = coefficients restricted to the sphere of k+q.  u, v: device BR vectors
- * (either may be NULL).  Asynchronous on stream.
+ * (either may be NULL).  Asynchronous on stream, except that with v on a
+ * system not yet tuned it first builds the ground-state caches and runs the
+ * autotuner (see tm_autotune_enable), which synchronises.
  */
 int tm_start_vectors(tm_system* sys, int iq, tm_dir dir, void* u, void* v, void* stream);
 

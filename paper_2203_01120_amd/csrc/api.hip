@@ -672,8 +672,9 @@ static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bo
 
 // ---- the autotuner ---------------------------------------------------------------
 // Times every compiled variant of each tunable launch of one FP64 apply on the
-// system's own data (three runs each after a warm-up, HIP events on the
-// apply's stream) and keeps the fastest per shape, once per shape and process:
+// system's own data (after a warm-up, at least three runs each and about 2 ms
+// of runs for short launches; HIP events on the apply's stream) and keeps the
+// fastest per shape, once per shape and process:
 // plane density and apply kernels, the two z passes, the projector and P_c
 // contractions.  `out` (one right-hand side) is scratch here; the caller's
 // apply recomputes it with the chosen variants.
@@ -719,17 +720,25 @@ static void autotune(System& s, int iq, const double2* in, double2* out, hipStre
             if (n <= 1 || g_force[o.op] >= 0 || g_tuned.count({o.op, key})) continue;
         }
         std::vector<float> us(n);
+        // runs per variant: at least 3, and for short launches enough for about
+        // 2 ms, so that launch gaps and timer resolution do not decide
+        auto timed = [&](int reps) {
+            TM_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) o.run();
+            TM_HIP(hipEventRecord(e1, st));
+            TM_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            TM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return ms * 1000.0f / (float)reps;
+        };
         try {
+            g_trial[o.op] = 0;
+            const float t1 = timed(1);
+            const int reps = (int)std::min(200.0f, std::max(3.0f, 2000.0f / std::max(t1, 1.0f)));
             for (int v = 0; v < n; ++v) {
                 g_trial[o.op] = v;
                 o.run();
-                TM_HIP(hipEventRecord(e0, st));
-                for (int r = 0; r < 3; ++r) o.run();
-                TM_HIP(hipEventRecord(e1, st));
-                TM_HIP(hipEventSynchronize(e1));
-                float ms = 0;
-                TM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                us[v] = ms * 1000.0f / 3.0f;
+                us[v] = timed(reps);
             }
         } catch (...) {
             g_trial[o.op] = -1;
@@ -749,6 +758,49 @@ static void autotune(System& s, int iq, const double2* in, double2* out, hipStre
     }
 }
 
+static void start_vectors_raw(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st);
+
+// Runs the autotuner on the system (once; FP64; never inside a graph capture,
+// where nothing can be timed) before any tunable launch of it produces a
+// result: the start vectors' projection, the first apply, a chain's first
+// step.  Every result of a tuned system then comes from the same launch
+// variants, so it does not depend on which call happened to come first.
+// in/out: one right-hand side to time on (out is overwritten), or null for
+// scratch vectors allocated here and freed before returning.
+static void ensure_tuned(System& s, int iq, hipStream_t st, const double2* in = nullptr, double2* out = nullptr) {
+    if (s.tuned || !g_autotune) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TM_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return;
+    QSet& q = s.qs[iq];
+    ensure_workspace(s, q, 1);
+    ensure_ground(s, q, st);
+    if (in && out) {
+        autotune(s, iq, in, out, st);
+        s.tuned = true;
+        return;
+    }
+    const size_t bytes = (size_t)2 * q.nk * s.nbnd * 2 * q.npw_pad * sizeof(double2);
+    struct Scratch {
+        double2* p[2] = {nullptr, nullptr};
+        hipStream_t st;
+        ~Scratch() {
+            (void)hipStreamSynchronize(st);
+            for (double2* x : p)
+                if (x) (void)hipFree(x);
+        }
+    } sc{{nullptr, nullptr}, st};
+    for (double2*& x : sc.p)
+        if (hipMalloc((void**)&x, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            x = nullptr;
+            throw Error{TM_ENOMEM, "hipMalloc of the autotuner's vectors failed"};
+        }
+    start_vectors_raw(s, iq, TM_DIR_Z, nullptr, sc.p[0], st);
+    autotune(s, iq, sc.p[0], sc.p[1], st);
+    s.tuned = true;
+}
+
 // out = L_q in.  fp32: the FFTs, densities, point-wise products and the
 // nonlocal/projector contractions run in single precision (FP32 MFMA, FP32
 // accumulation); the potential (Hartree + kernel), the kinetic term and the
@@ -760,14 +812,8 @@ void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipS
     if (fp32)
         TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
                  "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
-    if (!s.tuned && !fp32 && g_autotune) {
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        TM_HIP(hipStreamIsCapturing(st, &cs));
-        if (cs == hipStreamCaptureStatusNone) {  // (timing is impossible inside a capture)
-            autotune(s, iq, in, out, st);
-            s.tuned = true;
-        }
-    }
+    else
+        ensure_tuned(s, iq, st, in, out);
     apply_l_ready(s, iq, in, out, fp32, st, nrhs);
 }
 
@@ -786,7 +832,7 @@ static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bo
     launch_project(s, q, out, st, fp32, nrhs);
 }
 
-void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st) {
+static void start_vectors_raw(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st) {
     QSet& q = s.qs[iq];
     ensure_workspace(s, q);
     dim3 gr((q.npw_pad + 127) / 128, s.nbnd, 2 * q.nk);
@@ -796,6 +842,11 @@ void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream
     TM_LAUNCH(k_start, gr, dim3(128), 0, st, q.d_ucoef, q.d_npw_u, (const int* const*)q.d_maps, q.nk,
                        s.nbnd, q.npw_pad, dir, t, -t, u, v);
     if (v) launch_project_signed(s, q, v, 1.0, 1.0, st);
+}
+
+void start_vectors(System& s, int iq, int dir, double2* u, double2* v, hipStream_t st) {
+    if (v) ensure_tuned(s, iq, st);  // the projection of v is a tuned contraction
+    start_vectors_raw(s, iq, dir, u, v, st);
 }
 
 // Steps after which the vector roles of a chain return to their initial
@@ -901,6 +952,7 @@ static void chain_begin(Chain& c, hipStream_t st) {
     TM_CHECK(c.lanes >= 1 && c.lanes <= kMaxLanes, TM_EINVAL, "1 to 4 lanes per chain");
     chain_bind_slot(c, q);
     ensure_ground(s, q, st);  // before any step, so steps never allocate or synchronise
+    if (!c.fp32) ensure_tuned(s, c.iq, st);  // before the chain's vectors exist (its scratch is freed)
     c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
     c.half = c.n / 2;
     c.w = 1.0 / q.nk;
@@ -1126,7 +1178,7 @@ struct ChainBlobHeader {
 static size_t blob_bytes(int lanes, int cap, int nvec, long long n) {
     const size_t L = (size_t)lanes;
     return sizeof(ChainBlobHeader) + L * sizeof(ChainState) +
-           L * (size_t)cap * (3 * sizeof(double2) + sizeof(double) + kNMeasure * sizeof(double2)) +
+           L * (size_t)cap * (2 * sizeof(double2) + sizeof(double) + kNMeasure * sizeof(double2)) +
            (L * nvec + kNMeasure) * (size_t)n * sizeof(double2);
 }
 
@@ -1199,6 +1251,7 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     QSet& qm = s.qs[c.iq];
     chain_bind_slot(c, qm);
     ensure_ground(s, qm, st);
+    if (!c.fp32) ensure_tuned(s, c.iq, st);  // the first step's projection is a tuned contraction
     c.half = c.n / 2;
     c.w = 1.0 / qm.nk;
     chain_alloc(c);

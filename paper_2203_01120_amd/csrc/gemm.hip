@@ -378,10 +378,14 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
         }
         return;
     }
-    // the K split the autotuner picked for this contraction shape (per right-hand
-    // side, so that every right-hand side is summed as when alone); FP64 only
+    // the K split the autotuner picked for this contraction (per right-hand side,
+    // so that every right-hand side is summed as when alone); FP64 only.  The
+    // key is the output shape and the batch count, not K: the q sets of a
+    // system differ only in K, so all of them take the choice made at the
+    // system's first apply, and a chain's arithmetic does not depend on which
+    // q set happened to be applied first.
     constexpr int kTargets[3] = {1024, 512, 2048};
-    const int tv = f32 ? 0 : tune_pick(kTuneGemm, tune_key(M, Nn, K, nbatch), 3);
+    const int tv = f32 ? 0 : tune_pick(kTuneGemm, tune_key(M, Nn, nbatch), 3);
     if (cn_lds_fits(M, Nn)) {
         g.kchunk = cn_lds_kchunk(K, nbatch, kTargets[tv]);
         g.ksplit = (K + g.kchunk - 1) / g.kchunk;
