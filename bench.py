@@ -244,9 +244,11 @@ EV = 27.211386245988  # eV per Hartree
 def run_qpath(args, tm, torch):
     """Batched chains: the cubic20 system with 24 q along Gamma-M-K-Gamma, three
     directions each (m_+, m_-, m_z), 72 pseudo-Hermitian chains stepped
-    together on one stream, then chi on 400 omega per chain.  With
-    --qpath-lanes 3 the three directions of a q set run as the lanes of one
-    chain (one batched apply per step for all three)."""
+    together, then chi on 400 omega per chain.  --qpath-lanes 3: the three
+    directions of a q set run as the lanes of one chain (24 chains over the
+    workspace slots); 6, 12, 24, 72: the three directions of 2, 4, 8 or all
+    24 q sets as the lanes of one chain (tm_chain_begin_lanes), so that each
+    kernel of a step runs once for all of them; 1: one chain per direction."""
     import synth
     sysd = synth.make_cubic20()
     qfrac = synth.q_path(24)
@@ -272,6 +274,12 @@ def run_qpath(args, tm, torch):
     t0 = time.perf_counter()
     if lanes == 3:
         chains = [tm.tm_chain_begin_multi(h, iq, ["+", "-", "z"], "pH", m, prec) for iq in range(len(qs))]
+        tm.tm_chains_step(chains, m)
+        coeffs = [co for c in chains for co in tm.tm_chain_coeffs_lanes(c, m)]
+    elif lanes > 3:
+        per = lanes // 3  # q sets per chain
+        chains = [tm.tm_chain_begin_lanes(h, [iq for iq in range(k, k + per) for _ in range(3)],
+                                          ["+", "-", "z"] * per, "pH", m, prec) for k in range(0, len(qs), per)]
         tm.tm_chains_step(chains, m)
         coeffs = [co for c in chains for co in tm.tm_chain_coeffs_lanes(c, m)]
     else:
@@ -464,8 +472,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="hexslab", choices=["hexslab", "cubic20", "qpath", "serving"])
     ap.add_argument("--chain-steps", type=int, default=2000, help="qpath: steps per chain")
-    ap.add_argument("--qpath-lanes", type=int, default=3, choices=[1, 3],
-                    help="qpath: directions per chain object (3: one batched apply per q set and step)")
+    ap.add_argument("--qpath-lanes", type=int, default=3, choices=[1, 3, 6, 12, 24, 72],
+                    help="qpath: lanes per chain object (3: the directions of one q set; 6 .. 72: those of "
+                         "2 .. 24 q sets, one launch per kernel for all of them)")
     ap.add_argument("--rates", default="0.2,0.5,1", help="serving: Poisson arrival rates (requests/s)")
     ap.add_argument("--requests", type=int, default=20, help="serving: requests per rate")
     ap.add_argument("--serving-budget", type=float, default=48.0,

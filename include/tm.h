@@ -23,7 +23,9 @@
  *       [2 sides][nk][nbnd][2 spins][npw_pad]
  *     (side 0 = X, side 1 = Y of Eq. batch_rho), each (side, k) block on the
  *     plane-wave sphere of the point k+q of mesh point k, in the Miller order
- *     of that point, zero-padded to npw_pad (see tm_qset_info);
+ *     of that point, zero-padded to npw_pad (see tm_qset_info; one value for
+ *     every q set of a system: the longest k+q sphere of all of them, rounded
+ *     up to 16);
  *   - inner product (a, b) = (1/nk) sum conj(a) b.
  *
  * Errors: every call returns an int, TM_OK (0) on success and a negative
@@ -120,7 +122,8 @@ typedef struct {
 typedef struct {
     int nk;                     /* mesh points                                            */
     int nbnd;                   /* bands                                                  */
-    int npw_pad;                /* padded sphere length of every (side, k) block          */
+    int npw_pad;                /* padded sphere length of every (side, k) block (the same
+                                   for every q set of the system)                          */
     long long nelem;            /* complex elements of one BR vector = 2 nk nbnd 2 npw_pad */
     double lam;                 /* scale of L used by the breakdown rule: the largest
                                    |k+q+G|^2/2 on the response spheres (Ha)               */
@@ -378,6 +381,25 @@ int tm_tensor_run(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavo
  * The system's apply workspace grows to ndir right-hand sides (its
  * reallocation makes other chains of the system re-capture their graphs).
  * tm_chain_begin is tm_chain_begin_multi with one direction.
+ *
+ * Many chains in one launch (a q path, Sec. 5: the spectra of many q, each
+ * a chain of its own): tm_chain_begin_lanes starts one chain with nlanes
+ * lanes (1..96), lane r the recursion for q set iqs[r] and direction
+ * dirs[r] (the same q set may appear in several lanes).  Every step runs each
+ * kernel once for all lanes -- z passes, plane kernels, potential, nonlocal
+ * and projector contractions, update and inner products -- with the lanes as
+ * extra batches: each batch reads the sphere, column, plane-row and resident
+ * ground-state tables of its lane's q set from tables laid out lane after
+ * lane (built once per distinct list iqs, kept with the system), and each
+ * lane has its own measure vectors u^lambda.  Each lane's coefficients equal
+ * those of a single chain of its q set and direction bit for bit.  Lanes of
+ * different q sets need the resident real-space ground state (fixed-size
+ * plane kernels and room for it; TM_EUNSUPPORTED otherwise).  The BR vectors
+ * of every q set of a system have one layout (the spheres are padded to the
+ * longest of all q sets; tm_qset_info_get), so lane r's vectors sit at
+ * r nelem in each of the chain's buffers.  The system's apply workspace
+ * grows to nlanes right-hand sides.  tm_chain_begin_multi is
+ * tm_chain_begin_lanes with every lane on q set iq.
  */
 typedef struct tm_chain tm_chain;
 /* Steps are replayed from a captured HIP graph of one period of steps (6
@@ -389,6 +411,8 @@ int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precisio
                    void* stream, tm_chain** out);
 int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, tm_precision prec,
                          int capacity, void* stream, tm_chain** out);
+int tm_chain_begin_lanes(tm_system* sys, int nlanes, const int* iqs, const tm_dir* dirs, tm_flavour f,
+                         tm_precision prec, int capacity, void* stream, tm_chain** out);
 int tm_chain_lanes(const tm_chain* chain, int* lanes);
 int tm_chains_step(tm_chain* const* chains, int n, int k_steps, void* stream);
 /* tm_system_set_chain_slots: at most nslots (1..16, default 3) workspace
@@ -406,8 +430,9 @@ int tm_chain_end(tm_chain* chain);
  * vectors, the three u^lambda, the coefficients and the device scale/step
  * state -- as one host blob.
  * tm_chain_state_size: bytes of the blob (per lane 5 BR vectors pseudo-Hermitian
- *   or 9 non-Hermitian and 104 bytes per step of capacity, plus the 4 shared
- *   measure vectors and a header).
+ *   or 9 non-Hermitian and 104 bytes per step of capacity, plus the 4 measure
+ *   vectors -- shared, or per lane when the lanes carry different q sets --
+ *   and a header).
  * tm_chain_save: waits for the chain's last stream and copies its state into
  *   `host` (caller-owned, at least tm_chain_state_size bytes); the chain stays
  *   usable.

@@ -29,7 +29,7 @@ EXPORTED = ["tm_system_create", "tm_system_destroy", "tm_qset_info_get", "tm_sys
             "tm_autotune_enable", "tm_autotune_force", "tm_autotune_report", "tm_chain_begin", "tm_chains_step", "tm_chains_use_graphs",
             "tm_chain_coeffs", "tm_chain_end", "tm_chi_extrapolated", "tm_structure_factor",
             "tm_chain_state_size", "tm_chain_save", "tm_chain_restore", "tm_chi_tensor",
-            "tm_chain_begin_multi", "tm_chain_lanes", "tm_tensor_run", "tm_liouvillian_apply_multi",
+            "tm_chain_begin_multi", "tm_chain_begin_lanes", "tm_chain_lanes", "tm_tensor_run", "tm_liouvillian_apply_multi",
             "tm_start_vectors", "tm_lanczos_run", "tm_chi", "tm_profile_enable", "tm_profile_reset",
             "tm_profile_count", "tm_profile_get", "tm_last_error"]
 
@@ -119,6 +119,8 @@ def load(path: str = LIB_PATH):
                                   C.POINTER(_Coeffs)]
     lib.tm_chain_begin_multi.argtypes = [C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.c_int, C.c_int,
                                          C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.tm_chain_begin_lanes.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int,
+                                         C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
     lib.tm_chain_lanes.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
     lib.tm_chi.argtypes = [C.POINTER(_Coeffs), C.c_int, C.POINTER(C.c_double), C.c_int, C.c_double,
                            C.POINTER(C.c_double)]
@@ -446,6 +448,19 @@ def tm_chain_begin_multi(h, iq: int, directions, flavour: str, capacity: int, pr
     out = C.c_void_p()
     _check(load().tm_chain_begin_multi(C.c_void_p(h), iq, len(directions), d, FLAVOURS[flavour], prec,
                                        int(capacity), _stream(stream), C.byref(out)))
+    return out.value
+
+
+def tm_chain_begin_lanes(h, iqs, directions, flavour: str, capacity: int, prec: int = TM_FP64,
+                         stream=None) -> int:
+    """One chain whose lane r runs q set iqs[r] and direction directions[r]."""
+    if len(iqs) != len(directions):
+        raise ValueError("one q set per direction")
+    q = (C.c_int * len(iqs))(*[int(i) for i in iqs])
+    d = (C.c_int * len(directions))(*[DIRS[x] for x in directions])
+    out = C.c_void_p()
+    _check(load().tm_chain_begin_lanes(C.c_void_p(h), len(iqs), q, d, FLAVOURS[flavour], prec, int(capacity),
+                                       _stream(stream), C.byref(out)))
     return out.value
 
 

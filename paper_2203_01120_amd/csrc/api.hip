@@ -300,18 +300,27 @@ void transpose_to_planes(const System& s, const double* src, std::vector<double>
                         src[(size_t)c * s.N + ((size_t)i1 * s.n2 + i2) * s.n3 + i3];
 }
 
-void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
+// The padded sphere length of every q set of a system: the largest k+q sphere
+// over all of them, rounded up to 16, so that the BR vectors of all q sets
+// share one layout and the lanes of one chain may carry different q sets.
+int system_npw_pad(const tm_system_desc* d) {
+    int npw_max = 0;
+    for (int iq = 0; iq < d->nq; ++iq)
+        for (int ik = 0; ik < d->nk; ++ik) {
+            const int* r = d->roles + ((size_t)iq * d->nk + ik) * 4;
+            for (int t = 0; t < 4; ++t) TM_CHECK(r[t] >= 0 && r[t] < d->npts, TM_EINVAL, "role index out of range");
+            npw_max = std::max(npw_max, d->npw[r[2]]);
+        }
+    return (npw_max + 15) / 16 * 16;
+}
+
+void build_qset(System& s, const tm_system_desc* d, int iq, int npw_pad, QSet& q) {
     const int nk = d->nk;
     q.nk = nk;
+    q.tmod = 2 * nk;
     for (int c = 0; c < 3; ++c) q.xq[c] = d->xq[3 * iq + c];
     q.kb.resize(nk);
-    int npw_max = 0;
-    for (int ik = 0; ik < nk; ++ik) {
-        const int* r = d->roles + ((size_t)iq * nk + ik) * 4;
-        for (int t = 0; t < 4; ++t) TM_CHECK(r[t] >= 0 && r[t] < d->npts, TM_EINVAL, "role index out of range");
-        npw_max = std::max(npw_max, d->npw[r[2]]);
-    }
-    q.npw_pad = (npw_max + 15) / 16 * 16;
+    q.npw_pad = npw_pad;
     const int P = q.npw_pad, nb = s.nbnd;
     hipStream_t st = nullptr;
     q.ncol_max = 0;
@@ -468,6 +477,9 @@ void build_qset(System& s, const tm_system_desc* d, int iq, QSet& q) {
     q.d_maps = upload_table(s, t_maps);
     q.hq = dev_alloc<double>(s, s.N);
     launch_coulomb_setup(s, q, st);
+    const double* hq = q.hq;
+    q.d_hqt = dev_upload(s, &hq, 1);
+    q.hmod = 1;
 }
 
 }  // namespace
@@ -601,6 +613,77 @@ static void ensure_ground(System& s, QSet& q, hipStream_t st) {
     q.ground_ready = true;
 }
 
+// The batch tables of a lane group: a chain whose lane r carries q set
+// iqs[r].  Every per-batch table the resident apply reads (spheres, columns,
+// kinetic energies and eigenvalues, occupied partners, projectors, plane rows
+// and resident slots) is laid out lane after lane, so that batch b of the
+// group (lane b / 2nk, side and k point b % 2nk) finds its row at b; the
+// Coulomb multiplier is per lane.  Built once per distinct list of q sets and
+// kept with the system.
+template <class T>
+static T* cat_table(System& s, const std::vector<int>& iqs, T* QSet::*f, int nb2) {
+    std::vector<T> h(iqs.size() * (size_t)nb2);
+    for (size_t r = 0; r < iqs.size(); ++r)
+        TM_HIP(hipMemcpy(h.data() + r * nb2, s.qs[iqs[r]].*f, nb2 * sizeof(T), hipMemcpyDeviceToHost));
+    return dev_upload(s, h.data(), h.size());
+}
+
+static QSet& lane_group(System& s, const std::vector<int>& iqs) {
+    auto it = s.groups.find(iqs);
+    if (it != s.groups.end()) return *it->second;
+    auto g = std::make_unique<QSet>();
+    const QSet& q0 = s.qs[iqs[0]];
+    const int nb2 = 2 * q0.nk;
+    g->nk = q0.nk;
+    g->npw_pad = q0.npw_pad;
+    g->tmod = (int)iqs.size() * nb2;
+    g->members = iqs;
+    g->ncol_max = 0;
+    g->ncol_u_max = 0;
+    g->lam = 0.0;
+    for (int iq : iqs) {
+        g->ncol_max = std::max(g->ncol_max, s.qs[iq].ncol_max);
+        g->ncol_u_max = std::max(g->ncol_u_max, s.qs[iq].ncol_u_max);
+    }
+    g->d_colptr_kq = cat_table(s, iqs, &QSet::d_colptr_kq, nb2);
+    g->d_entg_kq = cat_table(s, iqs, &QSet::d_entg_kq, nb2);
+    g->d_enti3_kq = cat_table(s, iqs, &QSet::d_enti3_kq, nb2);
+    g->d_colpos_kq = cat_table(s, iqs, &QSet::d_colpos_kq, nb2);
+    g->d_ncol_kq = cat_table(s, iqs, &QSet::d_ncol_kq, nb2);
+    g->d_npw_kq = cat_table(s, iqs, &QSet::d_npw_kq, nb2);
+    g->d_kin = cat_table(s, iqs, &QSet::d_kin, nb2);
+    g->d_eps = cat_table(s, iqs, &QSet::d_eps, nb2);
+    g->d_occ = cat_table(s, iqs, &QSet::d_occ, nb2);
+    g->d_vkb = cat_table(s, iqs, &QSet::d_vkb, nb2);
+    g->d_nrows_kq = cat_table(s, iqs, &QSet::d_nrows_kq, nb2);
+    g->d_rmask_kq = cat_table(s, iqs, &QSet::d_rmask_kq, nb2);
+    g->d_rows_kq = cat_table(s, iqs, &QSet::d_rows_kq, nb2);
+    g->d_colidx_kq = cat_table(s, iqs, &QSet::d_colidx_kq, nb2);
+    g->d_uslot = cat_table(s, iqs, &QSet::d_uslot, nb2);
+    std::vector<const double*> hq(iqs.size());
+    for (size_t r = 0; r < iqs.size(); ++r) hq[r] = s.qs[iqs[r]].hq;
+    g->d_hqt = dev_upload(s, hq.data(), hq.size());
+    g->hmod = (int)iqs.size();
+    QSet& ref = *g;
+    s.groups.emplace(iqs, std::move(g));
+    return ref;
+}
+
+// the ground-state caches an apply on q needs (a lane group: those of its
+// q sets, which must be resident)
+static void ensure_ground_q(System& s, QSet& q, hipStream_t st) {
+    if (q.members.empty()) return ensure_ground(s, q, st);
+    for (int iq : q.members) ensure_ground(s, s.qs[iq], st);
+    TM_CHECK(s.ureal_mode == 1, TM_EUNSUPPORTED,
+             "lanes with different q sets need the resident real-space ground state (fixed-size plane kernels "
+             "and room for it on the device)");
+}
+
+// index of a q set of the system; a lane group: that of its first lane
+static int qset_index(const System& s, const QSet& q) {
+    return q.members.empty() ? (int)(&q - s.qs.data()) : q.members[0];
+}
+
 // drops the resident real-space ground state (the next apply decides again)
 static void reset_ground(System& s) {
     if (s.ureal) {
@@ -667,7 +750,7 @@ Workspace scratch_workspace(const System& s, char* base, size_t cap) {
 }
 }  // namespace
 
-static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st,
+static void apply_l_ready(System& s, QSet& q, const double2* in, double2* out, bool fp32, hipStream_t st,
                           int nrhs);
 
 // ---- the autotuner ---------------------------------------------------------------
@@ -690,7 +773,7 @@ static void autotune(System& s, int iq, const double2* in, double2* out, hipStre
             (void)hipEventDestroy(b);
         }
     } ev{e0, e1};
-    apply_l_ready(s, iq, in, out, false, st, 1);  // every buffer holds this system's data
+    apply_l_ready(s, q, in, out, false, st, 1);  // every buffer holds this system's data
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
     struct Op {
         int op;
@@ -805,23 +888,27 @@ static void ensure_tuned(System& s, int iq, hipStream_t st, const double2* in = 
 // nonlocal/projector contractions run in single precision (FP32 MFMA, FP32
 // accumulation); the potential (Hartree + kernel), the kinetic term and the
 // vectors stay FP64.  Needs the fixed-size kernels and the resident ground state.
-void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st, int nrhs) {
-    QSet& q = s.qs[iq];
+// q: a q set of the system (every right-hand side on it) or a lane group
+// (right-hand side r on q set q.members[r])
+static void apply_l(System& s, QSet& q, const double2* in, double2* out, bool fp32, hipStream_t st, int nrhs) {
     ensure_workspace(s, q, nrhs);
-    ensure_ground(s, q, st);
+    ensure_ground_q(s, q, st);
     if (fp32)
         TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
                  "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
     else
-        ensure_tuned(s, iq, st, in, out);
-    apply_l_ready(s, iq, in, out, fp32, st, nrhs);
+        ensure_tuned(s, qset_index(s, q), st, in, out);
+    apply_l_ready(s, q, in, out, fp32, st, nrhs);
+}
+
+void apply_l(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st, int nrhs) {
+    apply_l(s, s.qs[iq], in, out, fp32, st, nrhs);
 }
 
 // the launches of one apply; the workspace (s.ws) and the ground-state caches
 // of the q set are in place (nothing is allocated here)
-static void apply_l_ready(System& s, int iq, const double2* in, double2* out, bool fp32, hipStream_t st,
+static void apply_l_ready(System& s, QSet& q, const double2* in, double2* out, bool fp32, hipStream_t st,
                           int nrhs) {
-    QSet& q = s.qs[iq];
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
     launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st, fp32, nrhs);
     launch_density(s, q, st, fp32, nrhs);
@@ -865,15 +952,18 @@ constexpr int kPeriodPH = 6, kPeriodNH = 3;
 // until its coefficients are read.
 struct Chain {
     System* s = nullptr;
-    int iq = 0, flavour = 0, cap = 0;
+    int iq = 0, flavour = 0, cap = 0;  // iq: the q set of lane 0
     int lanes = 1;
-    int dir[kMaxLanes] = {};
+    int dir[kMaxChainLanes] = {};
+    int lane_iq[kMaxChainLanes] = {};  // the q set of each lane
+    QSet* qa = nullptr;        // what the applies run on: the lanes' q set, or their lane group
+    long long ustride = 0;     // 0: measure vectors shared by the lanes (one q set); n: one per lane
     bool fp32 = false;         // single-precision applies (recurrence and dots stay FP64)
     long long n = 0, half = 0;
     double w = 1.0;
     std::vector<double2*> vec;  // work vectors (5 pH, 9 nH), each [lanes][n]
     int ix[9] = {0, 1, 2, 3, 4, 5, 6, 7, 8};  // current role -> vector
-    double2* u[kNMeasure] = {};  // measure vectors u^l, l = x, y, z, n (shared by the lanes)
+    double2* u[kNMeasure] = {};  // measure vectors u^l, l = x, y, z, n (lane r's at u[l] + r ustride)
     Coeffs co{};               // [lanes] coefficient arrays
     ChainState* cs = nullptr;  // [lanes]
     double2* dots = nullptr;   // [lanes][kDotStride] reduced inner products
@@ -910,7 +1000,8 @@ struct Chain {
 static void chain_alloc(Chain& c) {
     const size_t L = (size_t)c.lanes, cap = (size_t)c.cap;
     for (int i = 0; i < c.nvec(); ++i) c.vec.push_back(static_cast<double2*>(c.alloc(L * c.n * sizeof(double2))));
-    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(c.n * sizeof(double2)));
+    const size_t UL = c.ustride ? L : 1;
+    for (int l = 0; l < kNMeasure; ++l) c.u[l] = static_cast<double2*>(c.alloc(UL * c.n * sizeof(double2)));
     c.co.cap = c.cap;
     c.co.alpha = static_cast<double2*>(c.alloc(L * cap * sizeof(double2)));
     c.co.beta = static_cast<double*>(c.alloc(L * cap * sizeof(double)));
@@ -946,36 +1037,61 @@ static void chain_bind_slot(Chain& c, const QSet& q) {
     ensure_workspace(s, q, c.lanes);
 }
 
-static void chain_begin(Chain& c, hipStream_t st) {
+// Lane q sets of a chain (c.lane_iq, c.lanes set): the q set of lane 0, the
+// vector length, and what the applies run on -- the lanes' common q set, or
+// the lane group of their q sets (then each lane has its own measure vectors)
+static void chain_qsets(Chain& c) {
     System& s = *c.s;
-    QSet& q = s.qs[c.iq];
-    TM_CHECK(c.lanes >= 1 && c.lanes <= kMaxLanes, TM_EINVAL, "1 to 4 lanes per chain");
-    chain_bind_slot(c, q);
-    ensure_ground(s, q, st);  // before any step, so steps never allocate or synchronise
-    if (!c.fp32) ensure_tuned(s, c.iq, st);  // before the chain's vectors exist (its scratch is freed)
-    c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;
+    TM_CHECK(c.lanes >= 1 && c.lanes <= kMaxChainLanes, TM_EINVAL,
+             "1 to " + std::to_string(kMaxChainLanes) + " lanes per chain");
+    bool mixed = false;
+    for (int r = 0; r < c.lanes; ++r) {
+        TM_CHECK(c.lane_iq[r] >= 0 && c.lane_iq[r] < (int)s.qs.size(), TM_EINVAL, "lane q set out of range");
+        mixed |= c.lane_iq[r] != c.lane_iq[0];
+    }
+    c.iq = c.lane_iq[0];
+    const QSet& q = s.qs[c.iq];
+    c.n = 2LL * q.nk * s.nbnd * 2 * q.npw_pad;  // the same for every q set of the system
     c.half = c.n / 2;
     c.w = 1.0 / q.nk;
+    c.qa = mixed ? &lane_group(s, std::vector<int>(c.lane_iq, c.lane_iq + c.lanes)) : &s.qs[c.iq];
+    c.ustride = mixed ? c.n : 0;
+}
+
+static void chain_begin(Chain& c, hipStream_t st) {
+    System& s = *c.s;
+    chain_qsets(c);
+    QSet& q = s.qs[c.iq];
+    chain_bind_slot(c, q);
+    ensure_ground_q(s, *c.qa, st);  // before any step, so steps never allocate or synchronise
+    if (!c.fp32) ensure_tuned(s, c.iq, st);  // before the chain's vectors exist (its scratch is freed)
     chain_alloc(c);
     c.last = st;
     chain_clear_coeffs(c, st);
     std::vector<ChainState> h(c.lanes);
-    for (ChainState& x : h) x.lam = q.lam;
+    for (int r = 0; r < c.lanes; ++r) h[r].lam = s.qs[c.lane_iq[r]].lam;
     TM_HIP(hipMemcpyAsync(c.cs, h.data(), h.size() * sizeof(ChainState), hipMemcpyHostToDevice, st));
     TM_HIP(hipStreamSynchronize(st));  // h is released on return
     const int mdir[kNMeasure] = {TM_DIR_X, TM_DIR_Y, TM_DIR_Z, TM_DIR_N};
-    for (int l = 0; l < kNMeasure; ++l) start_vectors(s, c.iq, mdir[l], c.u[l], nullptr, st);
-    const long long n = c.n, half = c.half, L = c.lanes;
+    for (int l = 0; l < kNMeasure; ++l) {
+        if (c.ustride == 0) {
+            start_vectors(s, c.iq, mdir[l], c.u[l], nullptr, st);
+        } else {
+            for (int r = 0; r < c.lanes; ++r)
+                start_vectors(s, c.lane_iq[r], mdir[l], c.u[l] + r * c.ustride, nullptr, st);
+        }
+    }
+    const long long n = c.n, half = c.half, L = c.lanes, us = c.ustride;
     double2* d = c.dots;
     if (c.flavour == TM_PSEUDOHERMITIAN) {
         // roles: 0 q_prev, 1 q, 2 Lq, 3 r, 4 Lr
         TM_HIP(hipMemsetAsync(c.V(0), 0, L * n * sizeof(double2), st));
-        for (int r = 0; r < c.lanes; ++r) start_vectors(s, c.iq, c.dir[r], nullptr, c.V(1) + r * n, st);
-        apply_l(s, c.iq, c.V(1), c.V(2), c.fp32, st, c.lanes);
+        for (int r = 0; r < c.lanes; ++r) start_vectors(s, c.lane_iq[r], c.dir[r], nullptr, c.V(1) + r * n, st);
+        apply_l(s, *c.qa, c.V(1), c.V(2), c.fp32, st, c.lanes);
         DotSet<7> ds0{{c.V(1), c.V(1), c.V(2), c.u[0], c.u[1], c.u[2], c.u[3]},
                       {c.V(2), c.V(1), c.V(2), c.V(1), c.V(1), c.V(1), c.V(1)},
                       {1, 0, 1, 0, 0, 0, 0},
-                      {n, n, n, 0, 0, 0, 0},
+                      {n, n, n, us, us, us, us},
                       {n, n, n, n, n, n, n}};
         run_multidot<7>(ds0, n, half, c.w, c.part, d, st, c.lanes);
         ctl_ph_start(c.cs, d, c.co, st, c.lanes);
@@ -983,12 +1099,12 @@ static void chain_begin(Chain& c, hipStream_t st) {
         // roles: 0 q_prev, 1 q, 2 p_prev, 3 p, 4 Lq, 5 L^dag p, 6 J p, 7 q^, 8 p^
         TM_HIP(hipMemsetAsync(c.V(0), 0, L * n * sizeof(double2), st));
         TM_HIP(hipMemsetAsync(c.V(2), 0, L * n * sizeof(double2), st));
-        for (int r = 0; r < c.lanes; ++r) start_vectors(s, c.iq, c.dir[r], nullptr, c.V(1) + r * n, st);
+        for (int r = 0; r < c.lanes; ++r) start_vectors(s, c.lane_iq[r], c.dir[r], nullptr, c.V(1) + r * n, st);
         TM_HIP(hipMemcpyAsync(c.V(3), c.V(1), L * n * sizeof(double2), hipMemcpyDeviceToDevice, st));
         DotSet<5> ds0{{c.V(1), c.u[0], c.u[1], c.u[2], c.u[3]},
                       {c.V(1), c.V(1), c.V(1), c.V(1), c.V(1)},
                       {0, 0, 0, 0, 0},
-                      {n, 0, 0, 0, 0},
+                      {n, us, us, us, us},
                       {n, n, n, n, n}};
         run_multidot<5>(ds0, n, half, c.w, c.part, d, st, c.lanes);
         ctl_nh_start(c.cs, d, c.co, st, c.lanes);
@@ -1008,11 +1124,11 @@ static void chain_step(Chain& c, hipStream_t st) {
         // multidot, side by side in c.part; both summed by the step control
         double2* part_up = c.part;
         double2* part_md = c.part + (size_t)L * kPartBlocks * kNMeasure;
-        run_ph_update(c.cs, LQ, Q, QP, R, uc, n, part_up, st, L);
+        run_ph_update(c.cs, LQ, Q, QP, R, uc, c.ustride, n, part_up, st, L);
         // back onto the empty manifold: removes rounding-level occupied parts
         // that the metric JL cannot see (identity in exact arithmetic)
-        launch_project_signed(s, s.qs[c.iq], R, 1.0, 1.0, st, false, L);
-        apply_l(s, c.iq, R, LR, c.fp32, st, L);
+        launch_project_signed(s, *c.qa, R, 1.0, 1.0, st, false, L);
+        apply_l(s, *c.qa, R, LR, c.fp32, st, L);
         DotSet<3> ds{{R, R, LR}, {LR, R, LR}, {1, 0, 1}, {n, n, n}, {n, n, n}};
         run_multidot<3>(ds, n, half, c.w, part_md, d, st, L, false);
         ctl_ph_step_sums(c.cs, part_md, part_up, n, c.w, d, d + 8, c.co, st, L);
@@ -1027,15 +1143,15 @@ static void chain_step(Chain& c, hipStream_t st) {
         double2 *QP = c.V(0), *Q = c.V(1), *PP = c.V(2), *Pv = c.V(3), *LQ = c.V(4), *LTP = c.V(5),
                 *TMP = c.V(6), *QH = c.V(7), *PH = c.V(8);
         // q_i, p_i back onto the empty manifold (see the pH step)
-        launch_project_signed(s, s.qs[c.iq], Q, 1.0, 1.0, st, false, L);
-        launch_project_signed(s, s.qs[c.iq], Pv, 1.0, 1.0, st, false, L);
-        apply_l(s, c.iq, Q, LQ, c.fp32, st, L);
+        launch_project_signed(s, *c.qa, Q, 1.0, 1.0, st, false, L);
+        launch_project_signed(s, *c.qa, Pv, 1.0, 1.0, st, false, L);
+        apply_l(s, *c.qa, Q, LQ, c.fp32, st, L);
         run_jcopy(Pv, TMP, n, half, st, L);
-        apply_l(s, c.iq, TMP, LTP, c.fp32, st, L);
+        apply_l(s, *c.qa, TMP, LTP, c.fp32, st, L);
         DotSet<1> da{{Pv}, {LQ}, {0}, {n}, {n}};
         run_multidot<1>(da, n, half, c.w, c.part, d, st, L, false);
         ctl_nh_alpha_sums(c.cs, c.part, n, c.w, d, c.co, st, L);
-        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, n, half, c.part, st, L);
+        run_nh_update(c.cs, LQ, Q, QP, LTP, Pv, PP, QH, PH, uc, c.ustride, n, half, c.part, st, L);
         ctl_nh_step_sums(c.cs, c.part, n, c.w, d + 8, c.co, st, L);
         // q_prev <- q, q <- q^, p_prev <- p, p <- p^
         const int oqp = c.ix[0], opp = c.ix[2];
@@ -1168,26 +1284,36 @@ static int chain_coeffs(Chain& c, tm_coeffs* out) {
 
 // ---- checkpoint: header, per-lane device state, coefficients, vectors
 struct ChainBlobHeader {
-    char magic[8];       // "TMCHAIN3"
+    char magic[8];       // "TMCHAIN4"
     int iq, flavour, fp32, cap, issued, nvec, lanes;
-    int dir[kMaxLanes];
+    int dir[kMaxChainLanes];
+    int lane_iq[kMaxChainLanes];
     int ix[9];
     long long n;
 };
 
-static size_t blob_bytes(int lanes, int cap, int nvec, long long n) {
+// ulanes: measure vector sets saved (1 shared, or one per lane)
+static size_t blob_bytes(int lanes, int cap, int nvec, long long n, int ulanes) {
     const size_t L = (size_t)lanes;
     return sizeof(ChainBlobHeader) + L * sizeof(ChainState) +
            L * (size_t)cap * (2 * sizeof(double2) + sizeof(double) + kNMeasure * sizeof(double2)) +
-           (L * nvec + kNMeasure) * (size_t)n * sizeof(double2);
+           (L * nvec + (size_t)kNMeasure * ulanes) * (size_t)n * sizeof(double2);
 }
 
-static size_t chain_blob_bytes(const Chain& c) { return blob_bytes(c.lanes, c.cap, c.nvec(), c.n); }
+static int ulanes_of(const int* lane_iq, int lanes) {
+    for (int r = 1; r < lanes; ++r)
+        if (lane_iq[r] != lane_iq[0]) return lanes;
+    return 1;
+}
+
+static size_t chain_blob_bytes(const Chain& c) {
+    return blob_bytes(c.lanes, c.cap, c.nvec(), c.n, c.ustride ? c.lanes : 1);
+}
 
 static void chain_save(Chain& c, char* out) {
     TM_HIP(hipStreamSynchronize(c.last));
     ChainBlobHeader h{};
-    std::memcpy(h.magic, "TMCHAIN3", 8);
+    std::memcpy(h.magic, "TMCHAIN4", 8);
     h.iq = c.iq;
     h.flavour = c.flavour;
     h.fp32 = c.fp32 ? 1 : 0;
@@ -1195,7 +1321,8 @@ static void chain_save(Chain& c, char* out) {
     h.issued = c.issued;
     h.nvec = c.nvec();
     h.lanes = c.lanes;
-    std::copy(c.dir, c.dir + kMaxLanes, h.dir);
+    std::copy(c.dir, c.dir + kMaxChainLanes, h.dir);
+    std::copy(c.lane_iq, c.lane_iq + kMaxChainLanes, h.lane_iq);
     std::copy(c.ix, c.ix + 9, h.ix);
     h.n = c.n;
     const size_t L = (size_t)c.lanes, cap = (size_t)c.cap;
@@ -1212,7 +1339,8 @@ static void chain_save(Chain& c, char* out) {
     put(c.co.gamma, L * cap * sizeof(double2));
     put(c.co.z, L * kNMeasure * cap * sizeof(double2));
     for (double2* v : c.vec) put(v, L * c.n * sizeof(double2));
-    for (int l = 0; l < kNMeasure; ++l) put(c.u[l], c.n * sizeof(double2));
+    const size_t UL = c.ustride ? L : 1;
+    for (int l = 0; l < kNMeasure; ++l) put(c.u[l], UL * c.n * sizeof(double2));
 }
 
 // rebuilds a chain from a checkpoint of a chain of the same system; capacity
@@ -1221,16 +1349,20 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     ChainBlobHeader h{};
     TM_CHECK(bytes >= sizeof(h), TM_EINVAL, "checkpoint too short");
     std::memcpy(&h, in, sizeof(h));
-    TM_CHECK(std::memcmp(h.magic, "TMCHAIN3", 8) == 0, TM_EINVAL, "not a chain checkpoint");
+    TM_CHECK(std::memcmp(h.magic, "TMCHAIN4", 8) == 0, TM_EINVAL, "not a chain checkpoint");
     System& s = *c.s;
     TM_CHECK(h.iq >= 0 && h.iq < (int)s.qs.size(), TM_EINVAL, "checkpoint q set not in this system");
     const QSet& q = s.qs[h.iq];
     TM_CHECK(h.n == 2LL * q.nk * s.nbnd * 2 * q.npw_pad, TM_EINVAL, "checkpoint vectors do not fit this system");
     TM_CHECK(h.flavour == TM_PSEUDOHERMITIAN || h.flavour == TM_NONHERMITIAN, TM_EINVAL, "bad flavour");
     TM_CHECK(h.nvec == (h.flavour == TM_PSEUDOHERMITIAN ? 5 : 9), TM_EINVAL, "bad vector count");
-    TM_CHECK(h.lanes >= 1 && h.lanes <= kMaxLanes, TM_EINVAL, "bad lane count");
-    for (int r = 0; r < h.lanes; ++r)
+    TM_CHECK(h.lanes >= 1 && h.lanes <= kMaxChainLanes, TM_EINVAL, "bad lane count");
+    for (int r = 0; r < h.lanes; ++r) {
         TM_CHECK(h.dir[r] >= TM_DIR_X && h.dir[r] <= TM_DIR_N, TM_EINVAL, "bad direction");
+        TM_CHECK(h.lane_iq[r] >= 0 && h.lane_iq[r] < (int)s.qs.size(), TM_EINVAL,
+                 "checkpoint lane q set not in this system");
+    }
+    TM_CHECK(h.lane_iq[0] == h.iq, TM_EINVAL, "checkpoint lane q sets inconsistent");
     TM_CHECK(h.cap >= 1 && capacity >= 0, TM_EINVAL, "bad capacity");
     TM_CHECK(h.issued >= 0 && h.issued <= h.cap, TM_EINVAL, "bad step count");
     {
@@ -1240,20 +1372,19 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
             seen |= 1 << h.ix[i];
         }
     }
-    TM_CHECK(bytes >= blob_bytes(h.lanes, h.cap, h.nvec, h.n), TM_EINVAL, "checkpoint truncated");
-    c.iq = h.iq;
+    TM_CHECK(bytes >= blob_bytes(h.lanes, h.cap, h.nvec, h.n, ulanes_of(h.lane_iq, h.lanes)), TM_EINVAL,
+             "checkpoint truncated");
     c.flavour = h.flavour;
     c.fp32 = h.fp32 != 0;
     c.lanes = h.lanes;
-    std::copy(h.dir, h.dir + kMaxLanes, c.dir);
+    std::copy(h.dir, h.dir + kMaxChainLanes, c.dir);
+    std::copy(h.lane_iq, h.lane_iq + kMaxChainLanes, c.lane_iq);
     c.cap = std::max(capacity, h.cap);
-    c.n = h.n;
+    chain_qsets(c);
     QSet& qm = s.qs[c.iq];
     chain_bind_slot(c, qm);
-    ensure_ground(s, qm, st);
+    ensure_ground_q(s, *c.qa, st);
     if (!c.fp32) ensure_tuned(s, c.iq, st);  // the first step's projection is a tuned contraction
-    c.half = c.n / 2;
-    c.w = 1.0 / qm.nk;
     chain_alloc(c);
     c.last = st;
     std::copy(h.ix, h.ix + 9, c.ix);
@@ -1275,7 +1406,8 @@ static void chain_restore(Chain& c, const char* in, size_t bytes, int capacity, 
     for (size_t r = 0; r < L; ++r)
         for (int l = 0; l < kNMeasure; ++l) get(c.co.z + (r * kNMeasure + l) * ccap, hcap * sizeof(double2));
     for (double2* v : c.vec) get(v, L * c.n * sizeof(double2));
-    for (int l = 0; l < kNMeasure; ++l) get(c.u[l], c.n * sizeof(double2));
+    const size_t UL = c.ustride ? L : 1;
+    for (int l = 0; l < kNMeasure; ++l) get(c.u[l], UL * c.n * sizeof(double2));
     // a lane saved at its capacity holds the coefficients of its next index
     // only in the state struct (alpha for pH; z for both): grown capacity gets them
     if (ccap > hcap && h.issued == h.cap) {
@@ -1302,6 +1434,7 @@ static int run_chain(System& s, int iq, int lanes, const int* dirs, int flavour,
     c.iq = iq;
     c.lanes = lanes;
     std::copy(dirs, dirs + lanes, c.dir);
+    std::fill(c.lane_iq, c.lane_iq + lanes, iq);
     c.flavour = flavour;
     c.cap = nsteps;
     chain_begin(c, st);
@@ -1494,7 +1627,8 @@ int tm_system_create(const tm_system_desc* d, tm_system** out) {
         launch_fxc_setup(s, rho_d, nullptr);
         // q-sets
         s.qs.resize(d->nq);
-        for (int iq = 0; iq < d->nq; ++iq) build_qset(s, d, iq, s.qs[iq]);
+        const int npw_pad = system_npw_pad(d);
+        for (int iq = 0; iq < d->nq; ++iq) build_qset(s, d, iq, npw_pad, s.qs[iq]);
         TM_HIP(hipDeviceSynchronize());
         *out = ts.release();
         return TM_OK;
@@ -1625,16 +1759,14 @@ int tm_system_footprint(const tm_system_desc* d, tm_memory_info* out) {
         }
         std::set<std::array<int, 5>> uslots;
         s.qs.resize(d->nq);
+        const int npw_pad = system_npw_pad(d);
         for (int iq = 0; iq < d->nq; ++iq) {
             QSet& q = s.qs[iq];
             q.nk = d->nk;
-            int npw_max = 0;
             q.ncol_max = q.ncol_u_max = 0;
             for (int ik = 0; ik < d->nk; ++ik) {
                 const int* r = d->roles + ((size_t)iq * d->nk + ik) * 4;
                 const int* sh = d->shifts ? d->shifts + ((size_t)iq * d->nk + ik) * 12 : nullptr;
-                for (int t = 0; t < 4; ++t) TM_CHECK(r[t] >= 0 && r[t] < d->npts, TM_EINVAL, "role index out of range");
-                npw_max = std::max(npw_max, d->npw[r[2]]);
                 q.ncol_max = std::max(q.ncol_max, ncol[r[2]]);
                 q.ncol_u_max = std::max({q.ncol_u_max, ncol[r[0]], ncol[r[1]]});
                 for (int side = 0; side < 2; ++side) {
@@ -1642,7 +1774,7 @@ int tm_system_footprint(const tm_system_desc* d, tm_memory_info* out) {
                     uslots.insert({r[side], gsh ? gsh[0] : 0, gsh ? gsh[1] : 0, gsh ? gsh[2] : 0, side});
                 }
             }
-            q.npw_pad = (npw_max + 15) / 16 * 16;
+            q.npw_pad = npw_pad;
             const double P = q.npw_pad;
             // per k: occupied partners of both sides, padded projectors, maps and kinetic
             // energies, three sphere maps, the plane-position column index
@@ -1768,7 +1900,7 @@ int tm_liouvillian_apply_noalloc(tm_system* sys, int iq, const void* xy_in, void
         const Workspace saved = s.ws;
         s.ws = w;
         try {
-            apply_l_ready(s, iq, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out),
+            apply_l_ready(s, q, static_cast<const double2*>(xy_in), static_cast<double2*>(xy_out),
                           prec == TM_FP32, static_cast<hipStream_t>(stream), 1);
         } catch (...) {
             s.ws = saved;
@@ -1832,25 +1964,30 @@ int tm_tensor_run(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavo
     });
 }
 
-int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, tm_precision prec,
-                         int capacity, void* stream, tm_chain** out) {
+int tm_chain_begin_lanes(tm_system* sys, int nlanes, const int* iqs, const tm_dir* dirs, tm_flavour f,
+                         tm_precision prec, int capacity, void* stream, tm_chain** out) {
     return guarded([&]() -> int {
-        TM_CHECK(sys && out && dirs, TM_EINVAL, "null argument");
+        TM_CHECK(sys && out && dirs && iqs, TM_EINVAL, "null argument");
         *out = nullptr;
         System& s = sys->s;
-        TM_CHECK(iq >= 0 && iq < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
-        TM_CHECK(ndir >= 1 && ndir <= kMaxLanes, TM_EINVAL, "1 to 4 directions");
-        for (int r = 0; r < ndir; ++r)
+        TM_CHECK(nlanes >= 1 && nlanes <= kMaxChainLanes, TM_EINVAL,
+                 "1 to " + std::to_string(kMaxChainLanes) + " lanes");
+        for (int r = 0; r < nlanes; ++r) {
+            TM_CHECK(iqs[r] >= 0 && iqs[r] < (int)s.qs.size(), TM_EINVAL, "q-set index out of range");
             TM_CHECK(dirs[r] >= TM_DIR_X && dirs[r] <= TM_DIR_N, TM_EINVAL, "bad direction");
+        }
         TM_CHECK(f == TM_NONHERMITIAN || f == TM_PSEUDOHERMITIAN, TM_EINVAL, "bad flavour");
         TM_CHECK(capacity >= 1, TM_EINVAL, "capacity must be >= 1");
         TM_CHECK(prec == TM_FP64 || prec == TM_FP32, TM_EINVAL, "bad precision");
         std::unique_ptr<tm_chain> h(new tm_chain());
         Chain& c = h->c;
         c.s = &s;
-        c.iq = iq;
-        c.lanes = ndir;
-        for (int r = 0; r < ndir; ++r) c.dir[r] = (int)dirs[r];
+        c.lanes = nlanes;
+        for (int r = 0; r < nlanes; ++r) {
+            c.dir[r] = (int)dirs[r];
+            c.lane_iq[r] = iqs[r];
+        }
+        c.iq = iqs[0];
         c.flavour = (int)f;
         c.cap = capacity;
         c.fp32 = prec == TM_FP32;
@@ -1859,6 +1996,17 @@ int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, t
         *out = h.release();
         return TM_OK;
     });
+}
+
+int tm_chain_begin_multi(tm_system* sys, int iq, int ndir, const tm_dir* dirs, tm_flavour f, tm_precision prec,
+                         int capacity, void* stream, tm_chain** out) {
+    if (ndir < 1 || ndir > kMaxLanes) {
+        set_error("1 to 4 directions");
+        return TM_EINVAL;
+    }
+    int iqs[kMaxLanes];
+    std::fill(iqs, iqs + ndir, iq);
+    return tm_chain_begin_lanes(sys, ndir, iqs, dirs, f, prec, capacity, stream, out);
 }
 
 int tm_chain_begin(tm_system* sys, int iq, tm_dir dir, tm_flavour f, tm_precision prec, int capacity, void* stream,

@@ -38,11 +38,12 @@ __device__ inline void plane_inverse(double2* plane, const double2* cols, const 
     lds_fft(plane, a.n2, 1, a.n2, p1, +1);  // along i1 for every i2
 }
 
-// b: batch (columns of x); bt = b % nb2: side and k point (sphere tables, u)
-__device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, int b, int bt, int n, int i3,
-                                       const PlaneArgs& a, const FFTPlan& p1, const FFTPlan& p2) {
-    const int* cpos_x = a.colpos_kq[bt];
-    const int ncx = a.ncol_kq[bt];
+// b: batch (columns of x); bt = b % nb2: side and k point (u columns and
+// tables of the q set); tb = b % tmod: the k+q sphere tables
+__device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, int b, int bt, int tb, int n,
+                                       int i3, const PlaneArgs& a, const FFTPlan& p1, const FFTPlan& p2) {
+    const int* cpos_x = a.colpos_kq[tb];
+    const int ncx = a.ncol_kq[tb];
     const int* cpos_u = a.colpos_u[bt];
     const int ncu = a.ncol_u[bt];
 #pragma unroll
@@ -72,7 +73,7 @@ __device__ inline void load_components(double2 (&val)[4][kPts], double2* plane, 
 
 __global__ void k_density(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
     extern __shared__ double2 plane[];
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2, tb = b % a.tmod;
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     double2 acc[4][kPts];
@@ -82,7 +83,7 @@ __global__ void k_density(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
         for (int j = 0; j < kPts; ++j) acc[c][j] = cmk(0.0, 0.0);
     for (int n = n0; n < n1e; ++n) {
         double2 val[4][kPts];
-        load_components(val, plane, b, bt, n, i3, a, p1, p2);
+        load_components(val, plane, b, bt, tb, n, i3, a, p1, p2);
 #pragma unroll
         for (int j = 0; j < kPts; ++j) {
             double2 xu = val[0][j], xd = val[1][j], uu = val[2][j], ud = val[3][j];
@@ -134,9 +135,11 @@ __global__ void k_copy_scale(const double2* rho, double2* dst, long long n) {
     if (i < n) dst[i] = rho[i];
 }
 
-__global__ void k_mul_real(double2* data, const double* h, long long n) {
+// right-hand side blockIdx.y times its multiplier hqt[blockIdx.y % hmod]
+__global__ void k_mul_real(double2* data, const double* const* hqt, int hmod, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     data += blockIdx.y * n;
+    const double* h = hqt[blockIdx.y % hmod];
     if (i < n) data[i] = cscale(data[i], h[i]);
 }
 
@@ -162,7 +165,7 @@ __global__ void k_assemble_W(const double2* rho, const double2* vH, const double
 
 __global__ void k_apply_planes(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
     extern __shared__ double2 plane[];
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2, tb = b % a.tmod;
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const double sg = bt < a.nk ? 1.0 : -1.0;
@@ -194,7 +197,7 @@ __global__ void k_apply_planes(PlaneArgs a, FFTPlan p1, FFTPlan p2) {
     const int ncx = a.ncol_kq[bt];
     for (int n = n0; n < n1e; ++n) {
         double2 val[4][kPts];
-        load_components(val, plane, b, bt, n, i3, a, p1, p2);
+        load_components(val, plane, b, bt, tb, n, i3, a, p1, p2);
         double2 phi[2][kPts];
 #pragma unroll
         for (int j = 0; j < kPts; ++j) {
@@ -304,10 +307,12 @@ PlaneArgs plane_args(const System& s, const QSet& q) {
     a.n1 = s.n1; a.n2 = s.n2; a.n3 = s.n3; a.NP = s.n1 * s.n2;
     a.nk = q.nk; a.nb = s.nbnd; a.nitems = 2 * s.nbnd;
     a.nb2 = 2 * q.nk;
+    a.tmod = q.tmod;
     a.wstride = 4 * s.N;
     a.fstride = 6 * s.N;
     a.nchunk = s.ws.nchunk;
     a.bpc = (s.nbnd + a.nchunk - 1) / a.nchunk;
+    a.cpb = 1;
     a.xcols = s.ws.xcols;
     a.ncol_max = q.ncol_max;
     a.ucols = q.ucols;
@@ -473,9 +478,10 @@ template <int N1>
 constexpr int pot_threads() { return N1 == 20 ? 512 : N1 > 0 ? 1024 : kPotThreads; }
 
 template <int N1, int N2, int N3>
-__global__ void __launch_bounds__(pot_threads<N1>()) k_potential_lds(const double2* rho, const double* hq,
-                                                                     const double* fxc, double2* W, int n1, int n2,
-                                                                     int n3, FFTPlan p1, FFTPlan p2, FFTPlan p3) {
+__global__ void __launch_bounds__(pot_threads<N1>()) k_potential_lds(const double2* rho, const double* const* hqt,
+                                                                     int hmod, const double* fxc, double2* W, int n1,
+                                                                     int n2, int n3, FFTPlan p1, FFTPlan p2,
+                                                                     FFTPlan p3) {
     constexpr int NT = pot_threads<N1>();
     extern __shared__ double2 g[];
     if constexpr (N1 > 0) {
@@ -486,6 +492,7 @@ __global__ void __launch_bounds__(pot_threads<N1>()) k_potential_lds(const doubl
     const int N = n1 * n2 * n3;
     rho += (size_t)blockIdx.y * 4 * N;
     W += (size_t)blockIdx.y * 4 * N;
+    const double* hq = hqt[blockIdx.y % hmod];  // the right-hand side's q set's Coulomb multiplier
     if (blockIdx.x > 0) {
         const int per = (N + kPotParts - 1) / kPotParts;
         const int i0 = (blockIdx.x - 1) * per, i1 = min(N, i0 + per);
@@ -589,8 +596,9 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) 
                      hipSuccess,
                  TM_EDEVICE, "cannot raise the LDS limit of k_potential_lds");
         ProfScope ps("k_potential_lds", st);
-        hipLaunchKernelGGL(kern, dim3(1 + kPotParts, nrhs), dim3(nt), shm, st, s.ws.rho, q.hq, s.fxc,
-                           s.ws.W, s.n1, s.n2, s.n3, s.plan[0], s.plan[1], s.plan[2]);
+        hipLaunchKernelGGL(kern, dim3(1 + kPotParts, nrhs), dim3(nt), shm, st, s.ws.rho,
+                           (const double* const*)q.d_hqt, q.hmod, s.fxc, s.ws.W, s.n1, s.n2, s.n3, s.plan[0],
+                           s.plan[1], s.plan[2]);
         check_launch("k_potential_lds");
         return;
     }
@@ -598,7 +606,7 @@ void launch_potential(const System& s, const QSet& q, hipStream_t st, int nrhs) 
     const dim3 grid((unsigned)((N + 255) / 256), nrhs);
     TM_LAUNCH(k_copy_scale, grid, dim3(256), 0, st, s.ws.rho, s.ws.work, N);
     launch_fft3d_full(s, s.ws.work, -1, st, nrhs);
-    TM_LAUNCH(k_mul_real, grid, dim3(256), 0, st, s.ws.work, q.hq, N);
+    TM_LAUNCH(k_mul_real, grid, dim3(256), 0, st, s.ws.work, (const double* const*)q.d_hqt, q.hmod, N);
     launch_fft3d_full(s, s.ws.work, +1, st, nrhs);
     TM_LAUNCH(k_assemble_W, grid, dim3(256), 0, st, s.ws.rho, s.ws.work, s.fxc, s.ws.W, N);
 }

@@ -19,6 +19,8 @@ struct ZArgs {
     // per batch b (side*nk + ik, plus 2nk per further right-hand side):
     // coefficients of item 0 at coef_table[b % nb2] when the table is given,
     // else at coef_base + b * coef_bstride; sphere tables are per b % nb2
+    // (nb2: the table period, 2 nk or 2 nk times the right-hand sides when
+    // each has its own q set)
     int nb2;
     const double2* const* coef_table;
     const double2* coef_base;
@@ -199,7 +201,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
     const int nb2 = 2 * q.nk;
     TM_CHECK(nrhs == 1 || !ucols, TM_EINVAL, "ground-state columns have one right-hand side");
     ZArgs a;
-    a.nb2 = nb2;
+    a.nb2 = q.tmod;  // the table period
     a.nitems = nitems;
     a.coef_item_stride = item_stride;
     if (ucols) {
@@ -228,7 +230,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
     int ncolmax = ucols ? q.ncol_u_max : q.ncol_max;
     if (zpass_fixed_supported(n3)) {
         ZPassArgs z{};
-        z.nb2 = nb2;
+        z.nb2 = q.tmod;
         z.coef_table = a.coef_table;
         z.coef_base = a.coef_base;
         z.coef_bstride = a.coef_bstride;
@@ -261,7 +263,7 @@ void launch_zpass_inv(const System& s, const QSet& q, bool ucols, const double2*
 void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const double2* xin, double2* out,
                       hipStream_t st, bool fp32, int nrhs) {
     ZFwdArgs a;
-    a.nb2 = 2 * q.nk;
+    a.nb2 = q.tmod;  // the table period
     a.cols = cols;
     a.ncol_stride = q.ncol_max;
     a.colptr = q.d_colptr_kq;
@@ -278,7 +280,7 @@ void launch_zpass_fwd(const System& s, const QSet& q, const double2* cols, const
     const int n3 = s.n3;
     if (zpass_fixed_supported(n3)) {
         ZPassArgs z{};
-        z.nb2 = 2 * q.nk;
+        z.nb2 = q.tmod;
         z.colptr = a.colptr;
         z.entg = a.entg;
         z.enti3 = a.enti3;

@@ -262,7 +262,8 @@ struct GemmUpd {
     const double2* C_base;        // per batch C_base + b*c_bstride, [Minner][Nout]
     long long c_bstride;
     int ldc;
-    const double2* const* A_tab;  // per batch b % (2 nk)
+    const double2* const* A_tab;  // per batch b % tmod
+    int tmod;
     int lda;
     int Nout, K, Minner;
     double cs;
@@ -278,8 +279,8 @@ __global__ void __launch_bounds__(1024) k_gemm_update(GemmUpd g) {
     const int b = blockIdx.z;
     const int n0 = (threadIdx.x >> 6) * 16, k0 = blockIdx.y * 16;
     const int l = threadIdx.x & 63, i = l & 15, kk = l >> 4;
-    const int bt = b % (2 * g.nk);
-    const double2* A = g.A_tab[bt];
+    const int bt = b % (2 * g.nk);  // side and k point (the output sign)
+    const double2* A = g.A_tab[b % g.tmod];
     const double2* C = g.C_base + (long long)b * g.c_bstride;
     double2* Y = g.Y_base + (long long)b * g.y_bstride;
     typename MF<R>::V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
@@ -350,13 +351,14 @@ int choose_kchunk(int K, long long tiles_times_batch, long long target = 8192) {
 }
 
 // nbatch batches per right-hand side, nrhs right-hand sides (the K chunking
-// depends on nbatch only, so each right-hand side is summed as when alone)
-void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const double2* B_base, long long b_bstride,
-                 int ldb, int M, int Nn, int K, int nbatch, int nrhs, double2* out, hipStream_t st,
-                 bool f32 = false) {
+// depends on nbatch only, so each right-hand side is summed as when alone);
+// batch b takes A_tab[b % amod]
+void run_gemm_cn(const System& s, const double2* const* A_tab, int amod, int lda, const double2* B_base,
+                 long long b_bstride, int ldb, int M, int Nn, int K, int nbatch, int nrhs, double2* out,
+                 hipStream_t st, bool f32 = false) {
     GemmCN g;
     g.A_tab = A_tab;
-    g.amod = nbatch;
+    g.amod = amod;
     g.A_base = nullptr;
     g.a_bstride = 0;
     g.lda = lda;
@@ -419,9 +421,10 @@ void run_gemm_cn(const System& s, const double2* const* A_tab, int lda, const do
 }
 
 void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C, long long c_bstride, int ldc,
-                     const double2* const* A_tab, int lda, int Nout, int K, int Minner, double cs, double osx,
-                     double osy, int nk, int nrhs, hipStream_t st, bool f32 = false) {
+                     const double2* const* A_tab, int tmod, int lda, int Nout, int K, int Minner, double cs,
+                     double osx, double osy, int nk, int nrhs, hipStream_t st, bool f32 = false) {
     GemmUpd g;
+    g.tmod = tmod;
     g.Y_base = Y;
     g.y_bstride = y_bstride;
     g.ldy = ldy;
@@ -465,12 +468,12 @@ void launch_nonlocal(const System& s, const QSet& q, const double2* x, double2* 
     const long long bstride = (long long)nb * 2 * P;
     double2* Bm = s.ws.gsmall;
     double2* Wm = s.ws.gsmall + (size_t)nrhs * nbatch * s.nproj * 2 * nb;
-    run_gemm_cn(s, q.d_vkb, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, nrhs, Bm, st, f32);
+    run_gemm_cn(s, q.d_vkb, q.tmod, P, x, bstride, P, s.nproj, 2 * nb, P, nbatch, nrhs, Bm, st, f32);
     long long tot = (long long)nrhs * nbatch * s.nproj * 2 * nb;
     TM_LAUNCH(k_dmat, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Bm, s.dvan, Wm, s.nproj, nb,
                        nrhs * nbatch);
-    run_gemm_update(out, bstride, P, Wm, (long long)s.nproj * 2 * nb, 2 * nb, q.d_vkb, P, 2 * nb, P, s.nproj, 1.0,
-                    1.0, 1.0, q.nk, nrhs, st, f32);
+    run_gemm_update(out, bstride, P, Wm, (long long)s.nproj * 2 * nb, 2 * nb, q.d_vkb, q.tmod, P, 2 * nb, P,
+                    s.nproj, 1.0, 1.0, 1.0, q.nk, nrhs, st, f32);
 }
 
 void launch_project_signed(const System& s, const QSet& q, double2* phi, double osx, double osy, hipStream_t st,
@@ -478,10 +481,10 @@ void launch_project_signed(const System& s, const QSet& q, double2* phi, double 
     const int nb = s.nbnd, P = q.npw_pad, nbatch = 2 * q.nk;
     const long long bstride = (long long)nb * 2 * P;
     double2* S = s.ws.gsmall;
-    run_gemm_cn(s, (const double2* const*)q.d_occ, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, nrhs, S, st,
-                f32);
-    run_gemm_update(phi, bstride, 2 * P, S, (long long)nb * nb, nb, (const double2* const*)q.d_occ, 2 * P, nb,
-                    2 * P, nb, -1.0, osx, osy, q.nk, nrhs, st, f32);
+    run_gemm_cn(s, (const double2* const*)q.d_occ, q.tmod, 2 * P, phi, bstride, 2 * P, nb, nb, 2 * P, nbatch, nrhs,
+                S, st, f32);
+    run_gemm_update(phi, bstride, 2 * P, S, (long long)nb * nb, nb, (const double2* const*)q.d_occ, q.tmod, 2 * P,
+                    nb, 2 * P, nb, -1.0, osx, osy, q.nk, nrhs, st, f32);
 }
 
 void launch_project(const System& s, const QSet& q, double2* out, hipStream_t st, bool f32, int nrhs) {

@@ -105,12 +105,18 @@ __global__ void k_dot_final(const double2* part, int nblk, int nd, double w, dou
 }
 
 // pH residual: r = slq Lq - alpha sq q - beta sprev qprev; partials of (u_l, r)
-// for the measure vectors l = x, y, z, n
+// for the measure vectors l = x, y, z, n (lane blockIdx.y's at u_l + lane ustride)
 __global__ void __launch_bounds__(kRedThreads) k_ph_update(const ChainState* cs, const double2* Lq, const double2* q,
                                                             const double2* qp, double2* r, const double2* u0,
                                                             const double2* u1, const double2* u2,
-                                                            const double2* u3, long long n, double2* part) {
+                                                            const double2* u3, long long ustride, long long n,
+                                                            double2* part) {
     const long long lo = (long long)blockIdx.y * n;  // lane blockIdx.y
+    const long long uo = (long long)blockIdx.y * ustride;
+    u0 += uo;
+    u1 += uo;
+    u2 += uo;
+    u3 += uo;
     cs += blockIdx.y;
     Lq += lo;
     q += lo;
@@ -146,9 +152,14 @@ __global__ void __launch_bounds__(kRedThreads) k_nh_update(const ChainState* cs,
                                                             const double2* qp, const double2* Ltp, const double2* p,
                                                             const double2* pp, double2* qh, double2* ph,
                                                             const double2* u0, const double2* u1, const double2* u2,
-                                                            const double2* u3, long long n, long long half,
-                                                            double2* part) {
+                                                            const double2* u3, long long ustride, long long n,
+                                                            long long half, double2* part) {
     const long long lo = (long long)blockIdx.y * n;  // lane blockIdx.y
+    const long long uo = (long long)blockIdx.y * ustride;
+    u0 += uo;
+    u1 += uo;
+    u2 += uo;
+    u3 += uo;
     cs += blockIdx.y;
     Lq += lo;
     q += lo;
@@ -387,18 +398,19 @@ static int red_blocks(long long n) {
 }
 
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
-                   const double2* const* u, long long n, double2* part, hipStream_t st, int lanes) {
+                   const double2* const* u, long long ustride, long long n, double2* part, hipStream_t st,
+                   int lanes) {
     int nblk = red_blocks(n);
-    TM_LAUNCH(k_ph_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3], n,
-              part);
+    TM_LAUNCH(k_ph_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, r, u[0], u[1], u[2], u[3],
+              ustride, n, part);
 }
 
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
-                   long long n, long long half, double2* part, hipStream_t st, int lanes) {
+                   long long ustride, long long n, long long half, double2* part, hipStream_t st, int lanes) {
     int nblk = red_blocks(n);
     TM_LAUNCH(k_nh_update, dim3(nblk, lanes), dim3(kRedThreads), 0, st, cs, Lq, q, qp, Ltp, p, pp, qh, ph, u[0],
-              u[1], u[2], u[3], n, half, part);
+              u[1], u[2], u[3], ustride, n, half, part);
 }
 
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes) {

@@ -10,8 +10,10 @@ constexpr double kBreakdownTol = 1e-10;
 
 // measure vectors u^l of a chain: l = x, y, z (spin) and n (charge)
 constexpr int kNMeasure = 4;
-// field directions one chain can run together (lanes)
+// field directions one chain can run together on one q set (lanes)
 constexpr int kMaxLanes = 4;
+// lanes of a chain whose lanes carry their own q sets (a lane group)
+constexpr int kMaxChainLanes = 96;
 // reduced inner products kept per lane (a lane is one recursion of a chain
 // that runs several field directions together)
 constexpr int kDotStride = 16;
@@ -65,11 +67,13 @@ template <int ND>
 void run_multidot(const DotSet<ND>& ds, long long n, long long half, double w, double2* part, double2* out,
                   hipStream_t st, int lanes = 1, bool final = true);
 // the updates write the block partials of their inner products to part
+// u: the four measure vectors; lane r's are at u[l] + r ustride (0: shared by the lanes)
 void run_ph_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, double2* r,
-                   const double2* const* u, long long n, double2* part, hipStream_t st, int lanes = 1);
+                   const double2* const* u, long long ustride, long long n, double2* part, hipStream_t st,
+                   int lanes = 1);
 void run_nh_update(const ChainState* cs, const double2* Lq, const double2* q, const double2* qp, const double2* Ltp,
                    const double2* p, const double2* pp, double2* qh, double2* ph, const double2* const* u,
-                   long long n, long long half, double2* part, hipStream_t st, int lanes = 1);
+                   long long ustride, long long n, long long half, double2* part, hipStream_t st, int lanes = 1);
 void run_jcopy(const double2* src, double2* dst, long long n, long long half, hipStream_t st, int lanes = 1);
 void ctl_ph_start(ChainState* cs, const double2* d, const Coeffs& co, hipStream_t st, int lanes = 1);
 // The step controls add the block partials of their inner products (over

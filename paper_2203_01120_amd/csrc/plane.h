@@ -6,12 +6,16 @@
 namespace tml {
 
 // Several right-hand sides run as one batch: batch b of the grid is side and
-// k point b % nb2 of right-hand side b / nb2.  Sphere tables are per b % nb2;
-// columns, densities, fields and W are per b (or per right-hand side).
+// k point b % nb2 of right-hand side b / nb2.  Sphere tables are per b % tmod
+// (tmod = nb2 when every right-hand side has the same q set; nb2 times the
+// right-hand sides when each has its own); columns, densities, fields and W
+// are per b (or per right-hand side).
 struct PlaneArgs {
     int n1, n2, n3, NP;
     int nk, nb, nitems, bpc, nchunk;
+    int cpb;            // chunks of bands per block of the wave kernels (grid.y = nchunk / cpb, rounded up)
     int nb2;            // 2 nk: batches of one right-hand side
+    int tmod;           // sphere and slot tables are per b % tmod
     long long wstride;  // elements between the W (and rho) of consecutive right-hand sides (4 N)
     long long fstride;  // elements between the local field tables of consecutive right-hand sides (6 N)
     double2* xcols;
@@ -61,7 +65,8 @@ std::vector<int> digit_reversal(int n);
 
 // arguments of the fixed-size z passes (sphere <-> columns along i3)
 struct ZPassArgs {
-    int nb2;                           // batches of one right-hand side (tables are per b % nb2)
+    int nb2;                           // the table period: sphere and per-batch tables are per b % nb2
+                                       // (2 nk, or 2 nk times the right-hand sides when each has its own q set)
     const double2* const* coef_table;  // inverse: per-batch coefficient base, or null
     const double2* coef_base;          //          else coef_base + b * coef_bstride
     long long coef_bstride;

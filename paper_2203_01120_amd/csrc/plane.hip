@@ -253,7 +253,8 @@ struct PlaneKernel {
 
     // band n at plane i3 -> real space in the LDS planes, stored at
     // digit-reversed positions along both axes
-    __device__ static void inverse(const Smem& m, const PlaneArgs& a, int b, int bt, int n, int i3, const Rows& R) {
+    __device__ static void inverse(const Smem& m, const PlaneArgs& a, int b, int bt, int tb, int n, int i3,
+                                   const Rows& R) {
         double2* pl = m.pl;
         for (int i = threadIdx.x; i < R.nrl * N2; i += NT) {  // clear the occupied rows
             const int l = i / N2;
@@ -262,7 +263,7 @@ struct PlaneKernel {
         __syncthreads();
         if (SET == kXU) {
             const double2* cx = a.xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-            scatter(pl, 0, cx, (long long)a.n3 * a.ncol_max, a.ncol_kq[bt], a.colpos_kq[bt]);
+            scatter(pl, 0, cx, (long long)a.n3 * a.ncol_max, a.ncol_kq[tb], a.colpos_kq[tb]);
         }
         const double2* cu = a.ucols + (((long long)bt * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_u_max;
         scatter(pl, SET == kXU ? 2 : 0, cu, (long long)a.n3 * a.ncol_u_max, a.ncol_u[bt], a.colpos_u[bt]);
@@ -293,8 +294,9 @@ __global__ void __launch_bounds__(NT) k_density_t(PlaneArgs a, PlaneTabs t) {
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     double2* pl = m.pl;
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
-    const typename K::Rows R = K::setup(t, bt, m);
+    // bt: side and k point (and the row of the q set's ground-state columns); tb: sphere tables
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2, tb = b % a.tmod;
+    const typename K::Rows R = K::setup(t, tb, m);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const bool yside = bt >= a.nk;
@@ -304,7 +306,7 @@ __global__ void __launch_bounds__(NT) k_density_t(PlaneArgs a, PlaneTabs t) {
 #pragma unroll
         for (int j = 0; j < PTS; ++j) acc[c][j] = cmk(0.0, 0.0);
     for (int n = n0; n < n1e; ++n) {
-        K::inverse(m, a, b, bt, n, i3, R);
+        K::inverse(m, a, b, bt, tb, n, i3, R);
 #pragma unroll
         for (int j = 0; j < PTS; ++j) {
             const int pt = threadIdx.x + j * NT;
@@ -344,8 +346,9 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     double2* pl = m.pl;
-    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2;
-    const typename K::Rows R = K::setup(t, bt, m);
+    // bt: side and k point (and the row of the q set's ground-state columns); tb: sphere tables
+    const int i3 = blockIdx.x, chunk = blockIdx.y, b = blockIdx.z, bt = b % a.nb2, tb = b % a.tmod;
+    const typename K::Rows R = K::setup(t, tb, m);
     const int n0 = chunk * a.bpc;
     const int n1e = min(a.nb, n0 + a.bpc);
     const double sg = bt < a.nk ? 1.0 : -1.0;
@@ -376,10 +379,10 @@ __global__ void __launch_bounds__(NT) k_apply_t(PlaneArgs a, PlaneTabs t) {
             w0[j] = wx[j] = wy[j] = wz[j] = cmk(0.0, 0.0);
         }
     }
-    const int ncx = a.ncol_kq[bt];
-    const int* cpx = a.colpos_kq[bt];
+    const int ncx = a.ncol_kq[tb];
+    const int* cpx = a.colpos_kq[tb];
     for (int n = n0; n < n1e; ++n) {
-        K::inverse(m, a, b, bt, n, i3, R);
+        K::inverse(m, a, b, bt, tb, n, i3, R);
 #pragma unroll
         for (int j = 0; j < PTS; ++j) {
             const int pt = threadIdx.x + j * NT;
@@ -447,7 +450,7 @@ __global__ void __launch_bounds__(NT) k_ureal_t(PlaneArgs a, PlaneTabs t) {
     const int n1e = min(a.nb, n0 + a.bpc);
     const bool yside = b >= a.nk;
     for (int n = n0; n < n1e; ++n) {
-        K::inverse(m, a, b, b, n, i3, R);
+        K::inverse(m, a, b, b, b, n, i3, R);
         double2* out = a.ureal + (((long long)a.uslot[b] * a.nb + n) * a.n3 + i3) * 2 * G::NP;
         for (int idx = threadIdx.x; idx < G::NP; idx += NT) {
             const int p2 = idx / N1, p1 = wrow<N1>(idx - p2 * N1);
@@ -950,88 +953,95 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     const T2* xcols = pick<T2>(a.xcols, a.xcols32);
-    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z, bt = b % a.nb2;
+    // bt: side and k point of the batch; tb: its row in the sphere and slot tables
+    const int b = blockIdx.x, i3 = blockIdx.z, bt = b % a.nb2, tb = b % a.tmod;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     WTw<N1, T2> tw1{pick<T2>(t.tw1, t.tw1f)};
     // equal lengths share one table, so the two register sets are one
     WTw<N2, T2> tw2{N1 == N2 ? pick<T2>(t.tw1, t.tw1f) : pick<T2>(t.tw2, t.tw2f)};
     tw1.init(lane);
     tw2.init(lane);
-    const int nrx = K::setup(t, bt, m);
-    const unsigned long long mask = t.rmask_kq[bt];
+    const int nrx = K::setup(t, tb, m);
+    const unsigned long long mask = t.rmask_kq[tb];
     const int nlw = K::wave_rows(2 * nrx, w);
-    const int n0 = chunk * a.bpc;
-    const int n1e = min(a.nb, n0 + a.bpc);
     const long long cs = (long long)a.n3 * a.ncol_max;
     // the side's resident slot, read once (the loop's stores could alias it)
-    const double2* ub = a.ureal + (long long)a.uslot[bt] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
+    const double2* ub = a.ureal + (long long)a.uslot[tb] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
     TL tl;
     tl.init(w, lane);
     const typename K::Rows rl(m.rowbase, w, nlw, lane);
-    T2 acc[4][IT][R];
+    const long long N = (long long)G::NP * a.n3;
+    // the block's chunks of bands, each summed into its own partial density
+    // exactly as when it has a block of its own
+    const int ch0 = blockIdx.y * a.cpb, ch1 = min(a.nchunk, ch0 + a.cpb);
+    for (int chunk = ch0; chunk < ch1; ++chunk) {
+        const int n0 = chunk * a.bpc;
+        const int n1e = min(a.nb, n0 + a.bpc);
+        T2 acc[4][IT][R];
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-        for (int i = 0; i < IT; ++i)
+            for (int i = 0; i < IT; ++i)
 #pragma unroll
-            for (int r = 0; r < R; ++r) acc[c][i][r] = Cx<T2>::mk(0, 0);
-    for (int n = n0; n < n1e; ++n) {
-        const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
-        const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-        const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
-        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
-        __syncthreads();
-        // the band's ground state, in flight during the column stages
-        T2 uu[IT][R], ud[IT][R];
+                for (int r = 0; r < R; ++r) acc[c][i][r] = Cx<T2>::mk(0, 0);
+        for (int n = n0; n < n1e; ++n) {
+            const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
+            const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+            const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
+            K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
+            __syncthreads();
+            // the band's ground state, in flight during the column stages
+            T2 uu[IT][R], ud[IT][R];
 #pragma unroll
-        for (int i = 0; i < IT; ++i)
+            for (int i = 0; i < IT; ++i)
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                uu[i][r] = Cx<T2>::from(ur[tl.lq[i] + r * TL::BPC]);
-                ud[i][r] = Cx<T2>::from(ur[G::NP + tl.lq[i] + r * TL::BPC]);
+                for (int r = 0; r < R; ++r) {
+                    uu[i][r] = Cx<T2>::from(ur[tl.lq[i] + r * TL::BPC]);
+                    ud[i][r] = Cx<T2>::from(ur[G::NP + tl.lq[i] + r * TL::BPC]);
+                }
+            WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
+            wfft_dif<N1, +1, true, 2 * CPW, K::BT, TL::cp.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
+            // last inverse stage in registers, then the four density components
+#pragma unroll
+            for (int i = 0; i < IT; ++i) {
+                if (TL::live(lane, i)) {
+                    const T2* px = m.pl + boff + tl.lo[i];
+                    T2 xu[R], xd[R];
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        xu[r] = px[r * G::N2P];
+                        xd[r] = px[G::PS + r * G::N2P];
+                    }
+                    dft_small<R>(xu, +1);
+                    dft_small<R>(xd, +1);
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const T2 uu_xu = cmulc(uu[i][r], xu[r]), ud_xd = cmulc(ud[i][r], xd[r]);
+                        const T2 uu_xd = cmulc(uu[i][r], xd[r]), ud_xu = cmulc(ud[i][r], xu[r]);
+                        acc[0][i][r] = cadd(acc[0][i][r], cadd(uu_xu, ud_xd));
+                        acc[1][i][r] = cadd(acc[1][i][r], cadd(uu_xd, ud_xu));
+                        acc[2][i][r] = cadd(acc[2][i][r], cmuli(csub(ud_xu, uu_xd)));
+                        acc[3][i][r] = cadd(acc[3][i][r], csub(uu_xu, ud_xd));
+                    }
+                }
             }
-        WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
-        wfft_dif<N1, +1, true, 2 * CPW, K::BT, TL::cp.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
-        // last inverse stage in registers, then the four density components
+            // one buffer: the next band's rows may not overwrite columns still being read
+            if (NBUF == 1) __syncthreads();
+        }
+        T2* out = pick<T2>(a.rho_part, a.rho_part32) + ((long long)b * a.nchunk + chunk) * 4 * N +
+                  (long long)i3 * G::NP;
 #pragma unroll
         for (int i = 0; i < IT; ++i) {
             if (TL::live(lane, i)) {
-                const T2* px = m.pl + boff + tl.lo[i];
-                T2 xu[R], xd[R];
+                const int sl = lane + 64 * i;
+                const int cc = sl / TL::BPC, blk = sl - cc * TL::BPC;
+                const int g2 = m.perm2[w * CPW + cc];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    xu[r] = px[r * G::N2P];
-                    xd[r] = px[G::PS + r * G::N2P];
+                    const int g = m.perm1[blk * R + r] * N2 + g2;
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) out[c * N + g] = acc[c][i][r];
                 }
-                dft_small<R>(xu, +1);
-                dft_small<R>(xd, +1);
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const T2 uu_xu = cmulc(uu[i][r], xu[r]), ud_xd = cmulc(ud[i][r], xd[r]);
-                    const T2 uu_xd = cmulc(uu[i][r], xd[r]), ud_xu = cmulc(ud[i][r], xu[r]);
-                    acc[0][i][r] = cadd(acc[0][i][r], cadd(uu_xu, ud_xd));
-                    acc[1][i][r] = cadd(acc[1][i][r], cadd(uu_xd, ud_xu));
-                    acc[2][i][r] = cadd(acc[2][i][r], cmuli(csub(ud_xu, uu_xd)));
-                    acc[3][i][r] = cadd(acc[3][i][r], csub(uu_xu, ud_xd));
-                }
-            }
-        }
-        // one buffer: the next band's rows may not overwrite columns still being read
-        if (NBUF == 1) __syncthreads();
-    }
-    const long long N = (long long)G::NP * a.n3;
-    T2* out = pick<T2>(a.rho_part, a.rho_part32) + ((long long)b * a.nchunk + chunk) * 4 * N + (long long)i3 * G::NP;
-#pragma unroll
-    for (int i = 0; i < IT; ++i) {
-        if (TL::live(lane, i)) {
-            const int sl = lane + 64 * i;
-            const int cc = sl / TL::BPC, blk = sl - cc * TL::BPC;
-            const int g2 = m.perm2[w * CPW + cc];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int g = m.perm1[blk * R + r] * N2 + g2;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) out[c * N + g] = acc[c][i][r];
             }
         }
     }
@@ -1084,21 +1094,23 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
     extern __shared__ double2 lds[];
     const typename K::Smem m = K::carve(lds);
     T2* xcols = pick<T2>(a.xcols, a.xcols32);
-    const int b = blockIdx.x, chunk = blockIdx.y, i3 = blockIdx.z, bt = b % a.nb2;
+    // bt: side and k point of the batch; tb: its row in the sphere and slot tables
+    const int b = blockIdx.x, i3 = blockIdx.z, bt = b % a.nb2, tb = b % a.tmod;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     WTw<N1, T2> tw1{pick<T2>(t.tw1, t.tw1f)};
     // equal lengths share one table, so the two register sets are one
     WTw<N2, T2> tw2{N1 == N2 ? pick<T2>(t.tw1, t.tw1f) : pick<T2>(t.tw2, t.tw2f)};
     tw1.init(lane);
     tw2.init(lane);
-    const int nrx = K::setup(t, bt, m);
-    const unsigned long long mask = t.rmask_kq[bt];
+    const int nrx = K::setup(t, tb, m);
+    const unsigned long long mask = t.rmask_kq[tb];
     const int nlw = K::wave_rows(2 * nrx, w);
-    const int n0 = chunk * a.bpc;
-    const int n1e = min(a.nb, n0 + a.bpc);
+    // the bands of the block's chunks (the apply of a band does not depend on its chunk)
+    const int n0 = blockIdx.y * a.cpb * a.bpc;
+    const int n1e = min(a.nb, n0 + a.cpb * a.bpc);
     const long long cs = (long long)a.n3 * a.ncol_max;
     // the side's resident slot, read once (the loop's stores could alias it)
-    const double2* ub = a.ureal + (long long)a.uslot[bt] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
+    const double2* ub = a.ureal + (long long)a.uslot[tb] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
     const bool yside = bt >= a.nk;
     // the lane's points q = lane + 64 j of the wave (column cc, row position
     // r = t B + blk in the point order): LDS offset, and field table offset
@@ -1262,19 +1274,25 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
         launch_with_lds(k_ureal_t<N1, N2, NT>, "k_ureal_t", PlaneKernel<N1, N2, NT, kU>::bytes(), grid, NT, st, a, t);
     } else if (a.ureal) {
         TM_CHECK(t.colidx_kq != nullptr, TM_EINVAL, "missing column index tables");
-        const dim3 wgrid(grid.z, grid.y, grid.x);  // (b, chunk, i3)
+        // several chunks of bands per block once the grid has blocks to spare
+        // (their set-up -- tables, twiddle registers -- is then shared), as
+        // long as about 2048 blocks remain; the results do not change
+        PlaneArgs aw = a;
+        const long long blocks = (long long)grid.x * grid.y * grid.z;
+        aw.cpb = (int)std::max<long long>(1, std::min<long long>(a.nchunk, blocks / 2048));
+        const dim3 wgrid(grid.z, (a.nchunk + aw.cpb - 1) / aw.cpb, grid.x);  // (b, chunk group, i3)
         const int nrhs = (int)grid.z / a.nb2;
         if (fp32) {
             using WD = WaveKernel<N1, N2, BTD, CPW32, float2, NBUF32>;
             using WA = WaveKernel<N1, N2, BTA, CPWA32, float2, NBUF32>;
             if (op == kOpDensity) {
                 launch_with_lds(k_density_w<N1, N2, BTD, CPW32, float2, NBUF32, MINW32, FCHD32>, "k_density_w32",
-                                WD::bytes(), wgrid, WD::NT, st, a, t);
+                                WD::bytes(), wgrid, WD::NT, st, aw, t);
             } else {
                 TM_LAUNCH((k_fields_w<N1, N2, float2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                           a.vrs, a.W, t.perm1, t.perm2, a.fields32, a.n3, a.wstride, a.fstride);
                 launch_with_lds(k_apply_w<N1, N2, BTA, CPWA32, float2, NBUF32, MINWA32, FCHA32>, "k_apply_w32",
-                                WA::bytes(), wgrid, WA::NT, st, a, t);
+                                WA::bytes(), wgrid, WA::NT, st, aw, t);
             }
             return;
         }
@@ -1282,13 +1300,13 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
         const long long key = tune_key(N1 * 1000 + N2, a.n3, a.nb, a.nb2);
         if (op == kOpDensity) {
             constexpr int NV = WaveVariants<N1, N2>::n;
-            launch_wave_v<N1, N2, NV - 1>(true, tune_pick(kTuneDensity, key, NV), a, t, wgrid, st, nrhs);
+            launch_wave_v<N1, N2, NV - 1>(true, tune_pick(kTuneDensity, key, NV), aw, t, wgrid, st, nrhs);
         } else {
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                       a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
             constexpr int NV = WaveVariants<N1, N2>::n;
-            launch_wave_v<N1, N2, NV - 1>(false, tune_pick(kTuneApply, key, NV), a, t, wgrid, st, nrhs);
+            launch_wave_v<N1, N2, NV - 1>(false, tune_pick(kTuneApply, key, NV), aw, t, wgrid, st, nrhs);
         }
     } else {
         TM_CHECK(!fp32, TM_EUNSUPPORTED, "single-precision plane kernels need the resident ground state");

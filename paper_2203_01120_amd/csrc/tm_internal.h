@@ -161,7 +161,11 @@ struct KBlock {
 struct QSet {
     double xq[3];
     int nk;
-    int npw_pad;
+    int npw_pad;                  // the system's: every q set pads its spheres to the same length
+    int tmod = 0;                 // table period of the batches: 2 nk (a lane group: 2 nk times its lanes)
+    const double** d_hqt = nullptr;  // Coulomb multiplier of right-hand side r: d_hqt[r % hmod]
+    int hmod = 1;
+    std::vector<int> members;     // a lane group: the q set of each right-hand side (empty otherwise)
     int ncol_max;                 // max columns over the k+q spheres
     int ncol_u_max;               // max columns over the u spheres
     double lam;
@@ -268,6 +272,9 @@ struct System {
     int next_slot = 0;
     std::vector<void*> allocs;
     size_t table_bytes = 0;            // device bytes of everything in `allocs`
+    // lane groups: the batch tables of chains whose lanes have their own q
+    // sets, one per distinct list of lane q sets (kept until the system ends)
+    std::map<std::vector<int>, std::unique_ptr<QSet>> groups;
     bool tuned = false;                // the autotuner has timed this system's launches
 };
 

@@ -116,3 +116,72 @@ def test_qpath_batched_lanes_equal_single_chains_and_oracle(qpath):
         err = np.abs(cgot - cref).max() / cmax
         say(f"  chi rel err {err:.2e} (oracle drift {own:.2e})")
         assert err <= max(100 * own, 1e-10), (iq, err, own)
+
+
+def test_lane_group_chain_equals_single_chains(qpath):
+    """One chain whose 72 lanes are the three directions of all 24 q sets
+    (every kernel of a step runs once for all of them) gives, lane by lane,
+    the coefficients of the single chain of that q set and direction."""
+    tm, h, inp, sysd = qpath
+    nq = inp["xq"].shape[0]
+    iqs = [iq for iq in range(nq) for _ in DIRS]
+    dirs = DIRS * nq
+    say(f"lane group: one chain of {len(iqs)} lanes x {STEPS} steps")
+    c = tm.tm_chain_begin_lanes(h, iqs, dirs, "pH", STEPS)
+    try:
+        assert tm.tm_chain_lanes(c) == len(iqs)
+        tm.tm_chains_step([c], STEPS)
+        lanes = tm.tm_chain_coeffs_lanes(c, STEPS)
+    finally:
+        tm.tm_chain_end(c)
+    assert all(co["steps_done"] == STEPS and not co["breakdown"] for co in lanes)
+    for g in (0, 4, 17, 35, 52, 71):
+        alone = tm.tm_lanczos_run(h, iqs[g], dirs[g], "pH", STEPS)
+        for k in ("alpha", "beta", "gamma", "z", "zn"):
+            assert np.array_equal(lanes[g][k], alone[k]), (g, iqs[g], dirs[g], k)
+        assert lanes[g]["n1"] == alone["n1"]
+
+
+@pytest.mark.parametrize("flavour,m,cut", [("pH", 30, 13), ("nH", 12, 5)])
+def test_lane_group_mixed_order_and_restart(qpath, flavour, m, cut):
+    """Lanes in any order, the same q set in several lanes, the charge
+    channel among them; a checkpoint taken part-way continues exactly."""
+    tm, h, inp, sysd = qpath
+    iqs = [5, 0, 5, 23, 11, 0]
+    dirs = ["z", "+", "-", "z", "n", "x"]
+    say(f"lane group {flavour}: lanes {list(zip(iqs, dirs))}, {m} steps, checkpoint after {cut}")
+    c = tm.tm_chain_begin_lanes(h, iqs, dirs, flavour, m)
+    try:
+        tm.tm_chains_step([c], m)
+        whole = tm.tm_chain_coeffs_lanes(c, m)
+    finally:
+        tm.tm_chain_end(c)
+    for g in range(len(iqs)):
+        alone = tm.tm_lanczos_run(h, iqs[g], dirs[g], flavour, m)
+        for k in ("alpha", "beta", "gamma", "z", "zn"):
+            assert np.array_equal(whole[g][k], alone[k]), (g, k)
+    c = tm.tm_chain_begin_lanes(h, iqs, dirs, flavour, m)
+    try:
+        tm.tm_chains_step([c], cut)
+        blob = tm.tm_chain_save(c)
+    finally:
+        tm.tm_chain_end(c)
+    r = tm.tm_chain_restore(h, blob)
+    try:
+        assert tm.tm_chain_lanes(r) == len(iqs)
+        tm.tm_chains_step([r], m - cut)
+        resumed = tm.tm_chain_coeffs_lanes(r, m)
+    finally:
+        tm.tm_chain_end(r)
+    for g in range(len(iqs)):
+        for k in ("alpha", "beta", "gamma", "z", "zn"):
+            assert np.array_equal(resumed[g][k], whole[g][k]), (g, k)
+
+
+def test_lane_group_invalid_arguments(qpath):
+    tm, h, inp, sysd = qpath
+    nq = inp["xq"].shape[0]
+    for iqs, dirs in (([], []), ([0] * 97, ["z"] * 97), ([0, nq], ["z", "z"]), ([-1], ["x"])):
+        with pytest.raises(tm.TmError) as e:
+            tm.tm_chain_begin_lanes(h, iqs, dirs, "pH", 4)
+        assert e.value.code == tm.TM_EINVAL
