@@ -241,6 +241,32 @@ def cpu_baseline(workload: str, seed: int, nk_full: int):
 EV = 27.211386245988  # eV per Hartree
 
 
+def qpath_accuracy(tm, got, ref, omega, eta):
+    """FP32 spectra against FP64 ones of the same chains: relative L2 error of
+    Im chi per chain (the measured component of each direction), and the shift
+    of each chain's strongest interior peak of |Im chi| located on a 0.01 meV
+    grid; the largest and the median over the chains."""
+    l2, shift = [], []
+    for g, r in zip(got, ref):
+        m = min(g["steps_done"], r["steps_done"])
+        if m == 0:
+            continue
+        x32, x64 = tm.tm_chi(g, m, omega, eta), tm.tm_chi(r, m, omega, eta)
+        a = np.abs(x64.imag)
+        c = int(np.argmax(a.max(axis=1)))
+        l2.append(float(np.linalg.norm(x32.imag[c] - x64.imag[c]) / np.linalg.norm(x64.imag[c])))
+        peaks = [(a[c, i], i) for i in range(1, a.shape[1] - 1) if a[c, i] >= a[c, i - 1] and a[c, i] >= a[c, i + 1]]
+        if peaks:
+            w0 = omega[max(peaks)[1]]
+            wf = w0 + np.arange(-1000, 1001) * 1e-5 / EV
+            p32 = wf[int(np.argmax(np.abs(tm.tm_chi(g, m, wf, eta)[c].imag)))]
+            p64 = wf[int(np.argmax(np.abs(tm.tm_chi(r, m, wf, eta)[c].imag)))]
+            shift.append(abs(p32 - p64) * EV * 1e3)
+    return {"l2_rel_im_chi_max": max(l2), "l2_rel_im_chi_median": float(np.median(l2)),
+            "peak_shift_meV_max": max(shift) if shift else None, "chains": len(l2),
+            "omega": "400 points 0-1.995 eV, eta 5 meV; per chain its strongest component"}
+
+
 def run_qpath(args, tm, torch):
     """Batched chains: the cubic20 system with 24 q along Gamma-M-K-Gamma, three
     directions each (m_+, m_-, m_z), 72 pseudo-Hermitian chains stepped
@@ -293,6 +319,18 @@ def run_qpath(args, tm, torch):
     dt = time.perf_counter() - t0
     for c in chains:
         tm.tm_chain_end(c)
+    accuracy = None
+    if prec == tm.TM_FP32:  # every spectrum again in FP64 (untimed): the error of the FP32 bulk path
+        per = len(qs) // 8
+        ref = []
+        for k in range(0, len(qs), per):
+            c = tm.tm_chain_begin_lanes(h, [iq for iq in range(k, k + per) for _ in range(3)], ["+", "-", "z"] * per,
+                                        "pH", m, tm.TM_FP64)
+            tm.tm_chains_step([c], m)
+            ref += tm.tm_chain_coeffs_lanes(c, m)
+            tm.tm_chain_end(c)
+        accuracy = qpath_accuracy(tm, coeffs, ref, omega, eta)
+        log(f"fp32 vs fp64: {accuracy}")
     tm.tm_system_destroy(h)
     nbroken = sum(int(co["breakdown"]) for co in coeffs)
     steps = sum(int(co["steps_done"]) for co in coeffs)
@@ -318,6 +356,7 @@ def run_qpath(args, tm, torch):
                    "lanes_per_chain": lanes},
         "applies_per_s": round((steps + len(specs)) / dt, 1),
         "breakdowns": nbroken,
+        "fp32_accuracy": accuracy,
         "autotune": tm.tm_autotune_report(),
     }
     print(json.dumps(out))
@@ -472,7 +511,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="hexslab", choices=["hexslab", "cubic20", "qpath", "serving"])
     ap.add_argument("--chain-steps", type=int, default=2000, help="qpath: steps per chain")
-    ap.add_argument("--qpath-lanes", type=int, default=3, choices=[1, 3, 6, 12, 24, 72],
+    ap.add_argument("--qpath-lanes", type=int, default=24, choices=[1, 3, 6, 12, 24, 72],
                     help="qpath: lanes per chain object (3: the directions of one q set; 6 .. 72: those of "
                          "2 .. 24 q sets, one launch per kernel for all of them)")
     ap.add_argument("--rates", default="0.2,0.5,1", help="serving: Poisson arrival rates (requests/s)")

@@ -18,10 +18,11 @@ life) and specs that the server creates when a request needs them and
 destroys, least recently used first, when another system needs the memory
 and they have no chain running.
 
-Pending requests of the same system, q set and flavour with similar step
-counts are admitted together as the lanes of one chain
-(tm_chain_begin_multi, up to `lanes` of them): each step then applies L to
-all of them in one pass.  The server advances every admitted chain in rounds
+Pending requests of the same system and flavour with similar step counts
+are admitted together as the lanes of one chain (tm_chain_begin_lanes, up to
+`lanes` of them; requests on different q sets of a system share a chain once
+the system holds its ground state resident in real space, which lanes of
+different q sets need): each step then applies L to all of them in one pass.  The server advances every admitted chain in rounds
 (whole step periods, more of them per round for the faster systems; the
 chains of one system on that system's stream, different systems on different
 streams so that their kernels run concurrently), and finishes a request --
@@ -96,10 +97,11 @@ class SystemSlot:
     last_used: float = 0.0
 
 
-def chain_bytes(nelem: int, flavour: str, nsteps: int, lanes: int = 1) -> int:
+def chain_bytes(nelem: int, flavour: str, nsteps: int, lanes: int = 1, mixed: bool = False) -> int:
     """Device bytes of one chain: per lane its BR vectors (pH 5, nH 9) and
-    coefficients, plus the 4 shared measure vectors."""
-    nvec = lanes * (5 if flavour == "pH" else 9) + 4
+    coefficients, plus the 4 measure vectors (one set per lane when the lanes
+    carry different q sets)."""
+    nvec = lanes * (5 if flavour == "pH" else 9) + 4 * (lanes if mixed else 1)
     return nvec * nelem * 16 + lanes * nsteps * 104
 
 
@@ -283,16 +285,25 @@ class Server:
 
     def _bytes(self, group: List[Request]) -> int:
         head = group[0]
-        return chain_bytes(self._nelem(head), head.flavour, max(r.nsteps for r in group), len(group))
+        return chain_bytes(self._nelem(head), head.flavour, max(r.nsteps for r in group), len(group),
+                           any(r.iq != head.iq for r in group))
+
+    def _mixable(self, system: str) -> bool:
+        """Whether lanes of different q sets may share a chain of this system:
+        its ground state is resident in real space (decided at its first apply)."""
+        slot = self.systems.get(system)
+        return slot is not None and tb.tm_system_resident_bytes(slot.handle) > 0
 
     def _group(self, head: Request, room: int) -> List[Request]:
         """The head request and up to lanes-1 pending partners for one chain
-        (same system, q set and flavour, similar step counts, within `room` bytes)."""
+        (same system and flavour -- and q set unless the system is resident --,
+        similar step counts, within `room` bytes)."""
         group = [head]
+        mix = self._mixable(head.system)
         for r in self.pending:
             if len(group) == self.lanes:
                 break
-            if (r.system, r.iq, r.flavour) != (head.system, head.iq, head.flavour):
+            if (r.system, r.flavour) != (head.system, head.flavour) or (r.iq != head.iq and not mix):
                 continue
             steps = [q.nsteps for q in group] + [r.nsteps]
             if max(steps) > self.lane_slack * min(steps):
@@ -332,8 +343,8 @@ class Server:
                 self.pending.remove(r)
             cap = max(r.nsteps for r in group)
             try:
-                h = tb.tm_chain_begin_multi(slot.handle, head.iq, [r.direction for r in group], head.flavour, cap,
-                                            stream=slot.stream.cuda_stream)
+                h = tb.tm_chain_begin_lanes(slot.handle, [r.iq for r in group], [r.direction for r in group],
+                                            head.flavour, cap, stream=slot.stream.cuda_stream)
             except Exception:
                 self.pool.release(nb)
                 raise
@@ -440,7 +451,8 @@ def _nelem_of_desc(d, iq: int) -> int:
     """Complex elements of a BR vector of q set iq, from a descriptor (tm_qset_info's nelem)."""
     roles = np.asarray(d.roles)
     nk = roles.shape[1]
-    npw = max(d.points[int(roles[iq, ik, 2])].mill.shape[0] for ik in range(nk))
+    # every q set of a system pads its spheres to the longest of all of them
+    npw = max(d.points[int(roles[jq, ik, 2])].mill.shape[0] for jq in range(roles.shape[0]) for ik in range(nk))
     return 2 * nk * d.nbnd * 2 * ((npw + 15) // 16 * 16)
 
 
