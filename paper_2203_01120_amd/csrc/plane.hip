@@ -772,7 +772,7 @@ struct WaveKernel {
 
     static constexpr int FIT = cdiv(MAXR * N2, 64);  // row elements per lane, at most
     static constexpr int FCH = FCH_ < FIT ? FCH_ : FIT;  // of them in flight together
-    using Rows = WRows<NW, N2, MAXR, (FCH > 1)>;        // line bases in registers with FCH > 1
+    using Rows = WRows<NW, N2, MAXR, true>;             // line bases in registers (when lane-fixed)
 
     // row element k = lane + 64 it of the wave: LDS offset within a buffer, and
     // sphere column (spin plane s, column c; c < 0 outside the sphere)
