@@ -241,30 +241,47 @@ def cpu_baseline(workload: str, seed: int, nk_full: int):
 EV = 27.211386245988  # eV per Hartree
 
 
+def peak_shift(tm, got, ref, m, eta):
+    """Position (meV) of the strongest interior peak of |Im chi| of the FP64
+    chain `ref` -- searched over -10..10 eV on a 5 meV grid (a transverse
+    chain's poles may sit at negative frequency), its strongest component --
+    and how far the FP32 chain `got` moves it, both located on a 0.01 meV grid
+    within 10 meV; (None, None) when there is no interior peak."""
+    wide = (np.arange(4001) - 2000) * 5e-3 / EV
+    a = np.abs(tm.tm_chi(ref, m, wide, eta).imag)
+    c = int(np.argmax(a.max(axis=1)))
+    peaks = [(a[c, i], i) for i in range(1, a.shape[1] - 1) if a[c, i] > a[c, i - 1] and a[c, i] > a[c, i + 1]]
+    if not peaks:
+        return None, None
+    w0 = wide[max(peaks)[1]]
+    wf = w0 + np.arange(-1000, 1001) * 1e-5 / EV
+    p32 = wf[int(np.argmax(np.abs(tm.tm_chi(got, m, wf, eta)[c].imag)))]
+    p64 = wf[int(np.argmax(np.abs(tm.tm_chi(ref, m, wf, eta)[c].imag)))]
+    return float(p64 * EV * 1e3), float(abs(p32 - p64) * EV * 1e3)
+
+
 def qpath_accuracy(tm, got, ref, omega, eta):
     """FP32 spectra against FP64 ones of the same chains: relative L2 error of
-    Im chi per chain (the measured component of each direction), and the shift
-    of each chain's strongest interior peak of |Im chi| located on a 0.01 meV
-    grid; the largest and the median over the chains."""
-    l2, shift = [], []
+    Im chi on the benchmark's frequencies per chain (its strongest component),
+    and the shift of each chain's strongest peak (peak_shift); the largest and
+    the median over the chains."""
+    l2, shift, where = [], [], []
     for g, r in zip(got, ref):
         m = min(g["steps_done"], r["steps_done"])
         if m == 0:
             continue
         x32, x64 = tm.tm_chi(g, m, omega, eta), tm.tm_chi(r, m, omega, eta)
-        a = np.abs(x64.imag)
-        c = int(np.argmax(a.max(axis=1)))
+        c = int(np.argmax(np.abs(x64.imag).max(axis=1)))
         l2.append(float(np.linalg.norm(x32.imag[c] - x64.imag[c]) / np.linalg.norm(x64.imag[c])))
-        peaks = [(a[c, i], i) for i in range(1, a.shape[1] - 1) if a[c, i] >= a[c, i - 1] and a[c, i] >= a[c, i + 1]]
-        if peaks:
-            w0 = omega[max(peaks)[1]]
-            wf = w0 + np.arange(-1000, 1001) * 1e-5 / EV
-            p32 = wf[int(np.argmax(np.abs(tm.tm_chi(g, m, wf, eta)[c].imag)))]
-            p64 = wf[int(np.argmax(np.abs(tm.tm_chi(r, m, wf, eta)[c].imag)))]
-            shift.append(abs(p32 - p64) * EV * 1e3)
+        w0, d = peak_shift(tm, g, r, m, eta)
+        if w0 is not None:
+            where.append(w0)
+            shift.append(d)
     return {"l2_rel_im_chi_max": max(l2), "l2_rel_im_chi_median": float(np.median(l2)),
-            "peak_shift_meV_max": max(shift) if shift else None, "chains": len(l2),
-            "omega": "400 points 0-1.995 eV, eta 5 meV; per chain its strongest component"}
+            "peak_shift_meV_max": max(shift) if shift else None,
+            "peak_meV_range": [min(where), max(where)] if where else None, "chains": len(l2),
+            "omega": "L2 on 400 points 0-1.995 eV, eta 5 meV, per chain its strongest component; "
+                     "peaks searched over -10..10 eV"}
 
 
 def run_qpath(args, tm, torch):
@@ -633,19 +650,12 @@ def main():
         om = np.arange(400) * 5e-3 / EV
         eta = 5e-3 / EV
         x32, x64 = tm.tm_chi(res, m, om, eta), tm.tm_chi(ref, m, om, eta)
-        a = np.abs(x64.imag)
-        interior = [(a[c, i], c, i) for c in range(3) for i in range(1, a.shape[1] - 1)
-                    if a[c, i] > 0 and a[c, i] >= a[c, i - 1] and a[c, i] >= a[c, i + 1]]
         accuracy = {"l2_rel_im_chi": float(np.linalg.norm(x32.imag - x64.imag) / np.linalg.norm(x64.imag)),
                     "steps": int(m), "omega": "400 points 0-1.995 eV, eta 5 meV"}
-        if interior:
-            _, comp, i0 = max(interior)
-            w0 = om[i0]
-            wf = w0 + np.arange(-1000, 1001) * 1e-5 / EV
-            p32 = wf[int(np.argmax(np.abs(tm.tm_chi(res, m, wf, eta)[comp].imag)))]
-            p64 = wf[int(np.argmax(np.abs(tm.tm_chi(ref, m, wf, eta)[comp].imag)))]
-            accuracy.update(peak_shift_meV=float(abs(p32 - p64) * EV * 1e3), peak_meV=float(w0 * EV * 1e3),
-                            peak="strongest interior peak of |Im chi|, located on a 0.01 meV grid")
+        w0, d = peak_shift(tm, res, ref, m, eta)
+        if w0 is not None:
+            accuracy.update(peak_shift_meV=d, peak_meV=w0,
+                            peak="strongest interior peak of |Im chi| over -10..10 eV, located on a 0.01 meV grid")
         log(f"fp32 vs fp64: {accuracy}")
     prof = {}
     for k, (ms, cnt) in tm.tm_profile_read().items():
