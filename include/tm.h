@@ -241,7 +241,12 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
  * scratch vectors allocated and freed for the purpose) and the fastest is
  * kept for that shape for the rest of the process; later systems of the same
  * shape reuse it.  So every result of a system comes from the same variants,
- * whichever call came first.  Plane and z-pass variants give identical results; the
+ * whichever call came first.  The plane and z-pass launches of several
+ * right-hand sides (lanes) are timed again, on the caller's vectors, at the
+ * system's first FP64 apply of that many (one size class per power of two):
+ * their best shapes change once the grid fills the device.  Their variants
+ * give identical results, so this changes no result; the contractions keep
+ * the one-right-hand-side choice.  Plane and z-pass variants give identical results; the
  * contraction variants sum K in different splits (results equal up to
  * rounding), so two processes may differ in the last bits -- forcing the
  * contraction variant (tm_autotune_force(4, 0)) makes results reproducible

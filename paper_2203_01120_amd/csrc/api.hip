@@ -761,8 +761,12 @@ static void apply_l_ready(System& s, QSet& q, const double2* in, double2* out, b
 // plane density and apply kernels, the two z passes, the projector and P_c
 // contractions.  `out` (one right-hand side) is scratch here; the caller's
 // apply recomputes it with the chosen variants.
-static void autotune(System& s, int iq, const double2* in, double2* out, hipStream_t st) {
-    QSet& q = s.qs[iq];
+// nrhs > 1 (a chain's first apply with that many lanes): the plane and
+// z-pass launches of that many right-hand sides, whose best shapes differ
+// from one right-hand side's once the grid fills the device; the
+// contractions keep the one-right-hand-side choice (their K split decides
+// the rounding, and a lane must round as its chain alone does).
+static void autotune(System& s, QSet& q, const double2* in, double2* out, hipStream_t st, int nrhs) {
     hipEvent_t e0, e1;
     TM_HIP(hipEventCreate(&e0));
     TM_HIP(hipEventCreate(&e1));
@@ -773,7 +777,7 @@ static void autotune(System& s, int iq, const double2* in, double2* out, hipStre
             (void)hipEventDestroy(b);
         }
     } ev{e0, e1};
-    apply_l_ready(s, q, in, out, false, st, 1);  // every buffer holds this system's data
+    apply_l_ready(s, q, in, out, false, st, nrhs);  // every buffer holds this system's data
     const long long bstride = (long long)s.nbnd * 2 * q.npw_pad;
     struct Op {
         int op;
@@ -781,14 +785,16 @@ static void autotune(System& s, int iq, const double2* in, double2* out, hipStre
         std::function<void()> run;
     };
     const Op ops[] = {
-        {kTuneZInv, "z inverse", [&] { launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st); }},
-        {kTuneDensity, "density planes", [&] { launch_density(s, q, st); }},
-        {kTuneApply, "apply planes", [&] { launch_apply_planes(s, q, st); }},
-        {kTuneZFwd, "z forward", [&] { launch_zpass_fwd(s, q, s.ws.xcols, in, out, st); }},
+        {kTuneZInv, "z inverse",
+         [&] { launch_zpass_inv(s, q, false, in, bstride, 2 * s.nbnd, q.npw_pad, s.ws.xcols, st, false, nrhs); }},
+        {kTuneDensity, "density planes", [&] { launch_density(s, q, st, false, nrhs); }},
+        {kTuneApply, "apply planes", [&] { launch_apply_planes(s, q, st, false, nrhs); }},
+        {kTuneZFwd, "z forward", [&] { launch_zpass_fwd(s, q, s.ws.xcols, in, out, st, false, nrhs); }},
         {kTuneGemm, "P_c contraction", [&] { launch_project(s, q, out, st); }},
         {kTuneGemm, "projector contraction", [&] { launch_nonlocal(s, q, in, out, st); }},
     };
     for (const Op& o : ops) {
+        if (nrhs > 1 && o.op == kTuneGemm) continue;
         {
             std::lock_guard<std::mutex> lock(g_tune_mu);
             g_seen_n[o.op] = 0;
@@ -835,7 +841,8 @@ static void autotune(System& s, int iq, const double2* in, double2* out, hipStre
         t.chosen = (int)(std::min_element(us.begin(), us.end()) - us.begin());
         t.us = us;
         t.shape = std::string(o.what) + " grid " + std::to_string(s.n1) + "x" + std::to_string(s.n2) + "x" +
-                  std::to_string(s.n3) + ", " + std::to_string(s.nbnd) + " bands, " + std::to_string(q.nk) + " k";
+                  std::to_string(s.n3) + ", " + std::to_string(s.nbnd) + " bands, " + std::to_string(q.nk) + " k" +
+                  (nrhs > 1 ? ", " + std::to_string(nrhs) + " right-hand sides" : "");
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[{o.op, key}] = t;
     }
@@ -859,7 +866,7 @@ static void ensure_tuned(System& s, int iq, hipStream_t st, const double2* in = 
     ensure_workspace(s, q, 1);
     ensure_ground(s, q, st);
     if (in && out) {
-        autotune(s, iq, in, out, st);
+        autotune(s, q, in, out, st, 1);
         s.tuned = true;
         return;
     }
@@ -880,8 +887,20 @@ static void ensure_tuned(System& s, int iq, hipStream_t st, const double2* in = 
             throw Error{TM_ENOMEM, "hipMalloc of the autotuner's vectors failed"};
         }
     start_vectors_raw(s, iq, TM_DIR_Z, nullptr, sc.p[0], st);
-    autotune(s, iq, sc.p[0], sc.p[1], st);
+    autotune(s, q, sc.p[0], sc.p[1], st, 1);
     s.tuned = true;
+}
+
+// the launch shapes of nrhs right-hand sides, timed at the system's first
+// FP64 apply of that many (one size class per power of two), on the caller's
+// vectors (out is recomputed by the caller's apply)
+static void ensure_tuned_rhs(System& s, QSet& q, const double2* in, double2* out, hipStream_t st, int nrhs) {
+    if (nrhs <= 1 || !g_autotune || s.tuned_rhs.count(rhs_class(nrhs))) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    TM_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return;
+    autotune(s, q, in, out, st, nrhs);
+    s.tuned_rhs.insert(rhs_class(nrhs));
 }
 
 // out = L_q in.  fp32: the FFTs, densities, point-wise products and the
@@ -896,8 +915,10 @@ static void apply_l(System& s, QSet& q, const double2* in, double2* out, bool fp
     if (fp32)
         TM_CHECK(s.ureal_mode == 1 && zpass_fixed_supported(s.n3), TM_EUNSUPPORTED,
                  "TM_FP32 needs fixed-size plane and z kernels and the resident ground state");
-    else
+    else {
         ensure_tuned(s, qset_index(s, q), st, in, out);
+        ensure_tuned_rhs(s, q, in, out, st, nrhs);
+    }
     apply_l_ready(s, q, in, out, fp32, st, nrhs);
 }
 

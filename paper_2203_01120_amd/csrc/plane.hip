@@ -1296,8 +1296,9 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
             }
             return;
         }
-        // FP64: the variant the autotuner picked for this shape (plane, planes, bands and sides)
-        const long long key = tune_key(N1 * 1000 + N2, a.n3, a.nb, a.nb2);
+        // FP64: the variant the autotuner picked for this shape (plane, planes,
+        // bands and sides, and the size class of the right-hand side count)
+        const long long key = tune_key(N1 * 1000 + N2, a.n3, a.nb, a.nb2 * 64 + rhs_class(nrhs));
         if (op == kOpDensity) {
             constexpr int NV = WaveVariants<N1, N2>::n;
             launch_wave_v<N1, N2, NV - 1>(true, tune_pick(kTuneDensity, key, NV), aw, t, wgrid, st, nrhs);

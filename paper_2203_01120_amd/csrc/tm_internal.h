@@ -10,6 +10,7 @@
 #include <string>
 #include <array>
 #include <map>
+#include <set>
 #include <vector>
 
 #include "../../include/tm.h"
@@ -59,6 +60,16 @@ struct ProfScope {
 // the contraction's variants split K differently (rounding-level differences).
 enum TuneOp { kTuneDensity = 0, kTuneApply = 1, kTuneZInv = 2, kTuneZFwd = 3, kTuneGemm = 4, kTuneOps = 5 };
 int tune_pick(int op, long long key, int nvariants);
+// size class of a right-hand side count for the launch-shape keys: 0 for 1,
+// 1 for 2-3, 2 for 4-7, ...
+inline int rhs_class(int nrhs) {
+    int c = 0;
+    while (nrhs > 1) {
+        nrhs >>= 1;
+        ++c;
+    }
+    return c;
+}
 inline long long tune_key(long long a, long long b = 0, long long c = 0, long long d = 0) {
     unsigned long long h = 1469598103934665603ULL;  // FNV-1a over the four values
     for (long long v : {a, b, c, d}) {
@@ -276,6 +287,7 @@ struct System {
     // sets, one per distinct list of lane q sets (kept until the system ends)
     std::map<std::vector<int>, std::unique_ptr<QSet>> groups;
     bool tuned = false;                // the autotuner has timed this system's launches
+    std::set<int> tuned_rhs;           // ... and those of these classes of right-hand side counts (rhs_class)
 };
 
 template <typename T>
