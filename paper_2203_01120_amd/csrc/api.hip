@@ -300,6 +300,12 @@ void transpose_to_planes(const System& s, const double* src, std::vector<double>
                         src[(size_t)c * s.N + ((size_t)i1 * s.n2 + i2) * s.n3 + i3];
 }
 
+// Column stride of the z-transformed column buffers: the most columns of any
+// k+q sphere, rounded up to 8 so that a run of 8 columns (128 bytes in FP64)
+// starting at a multiple of 8 fills whole cache lines (the forward z pass
+// reads 8-column runs).
+static int col_stride(int ncol) { return (ncol + 7) / 8 * 8; }
+
 // The padded sphere length of every q set of a system: the largest k+q sphere
 // over all of them, rounded up to 16, so that the BR vectors of all q sets
 // share one layout and the lanes of one chain may carry different q sets.
@@ -449,6 +455,7 @@ void build_qset(System& s, const tm_system_desc* d, int iq, int npw_pad, QSet& q
             t_uslot[b] = it->second;
         }
     }
+    q.ncol_max = col_stride(q.ncol_max);
     q.d_uslot = dev_upload(s, t_uslot.data(), t_uslot.size());
     q.d_colidx_kq = upload_table(s, t_colidx);
     q.d_rows_kq = upload_table(s, t_rows_kq);
@@ -1795,6 +1802,7 @@ int tm_system_footprint(const tm_system_desc* d, tm_memory_info* out) {
                     uslots.insert({r[side], gsh ? gsh[0] : 0, gsh ? gsh[1] : 0, gsh ? gsh[2] : 0, side});
                 }
             }
+            q.ncol_max = col_stride(q.ncol_max);
             q.npw_pad = npw_pad;
             const double P = q.npw_pad;
             // per k: occupied partners of both sides, padded projectors, maps and kinetic

@@ -943,8 +943,11 @@ struct WaveKernel {
 };
 
 // MINW: waves per SIMD the register allocation must leave room for; FCH: row
-// elements per lane whose loads are in flight together
-template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false>
+// elements per lane whose loads are in flight together; EARLY: the band's
+// ground-state loads are issued before its row phase instead of after it
+// (longer in flight, more registers held through the row stages)
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false,
+          bool EARLY = false>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a, PlaneTabs t) {
     using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH, FUSE>;
     using G = typename K::G;
@@ -988,17 +991,22 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a
             const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
             const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
             const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
+            // the band's ground state, in flight during the column stages (and
+            // with EARLY the row stages)
+            T2 uu[IT][R], ud[IT][R];
+            auto load_u = [&] {
+#pragma unroll
+                for (int i = 0; i < IT; ++i)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        uu[i][r] = Cx<T2>::from(ur[tl.lq[i] + r * TL::BPC]);
+                        ud[i][r] = Cx<T2>::from(ur[G::NP + tl.lq[i] + r * TL::BPC]);
+                    }
+            };
+            if constexpr (EARLY) load_u();
             K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
             __syncthreads();
-            // the band's ground state, in flight during the column stages
-            T2 uu[IT][R], ud[IT][R];
-#pragma unroll
-            for (int i = 0; i < IT; ++i)
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    uu[i][r] = Cx<T2>::from(ur[tl.lq[i] + r * TL::BPC]);
-                    ud[i][r] = Cx<T2>::from(ur[G::NP + tl.lq[i] + r * TL::BPC]);
-                }
+            if constexpr (!EARLY) load_u();
             WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
             wfft_dif<N1, +1, true, 2 * CPW, K::BT, TL::cp.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
             // last inverse stage in registers, then the four density components
@@ -1209,36 +1217,42 @@ void launch_with_lds(F kernel, const char* name, size_t shm, dim3 grid, int nt, 
 // Variants of the FP64 wave plane kernels that the autotuner times, variant 0
 // being the hand-picked default: BT butterflies per load group, CPW columns
 // per wave, FCH row elements in flight per lane, fused first / last row
-// stages (all with two LDS buffers and no occupancy floor).  They split the
-// work differently and do the same arithmetic per point in the same order,
-// so their results are identical.
+// stages, the density's ground-state loads issued before the row phase (all
+// with two LDS buffers and no occupancy floor).  They split the work
+// differently and do the same arithmetic per point in the same order, so
+// their results are identical.  The apply times the first napply of them.
 template <int N1, int N2>
 struct WaveVariants {  // 8x8, 24x24, 32x32
     static constexpr int n = 3;
     static constexpr int bt[n] = {2, 1, 2}, cpw[n] = {4, 4, 4}, fch[n] = {1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, true};
+    static constexpr bool fuse[n] = {false, false, true}, early[n] = {false, false, false};
+    static constexpr int napply = n;
 };
 template <>
 struct WaveVariants<48, 48> {
-    static constexpr int n = 6;
-    static constexpr int bt[n] = {2, 1, 4, 2, 2, 1}, cpw[n] = {4, 4, 4, 4, 4, 4}, fch[n] = {1, 1, 1, 4, 1, 1};
-    static constexpr bool fuse[n] = {false, false, false, false, true, true};
+    static constexpr int n = 8;
+    static constexpr int bt[n] = {2, 1, 4, 2, 2, 1, 1, 2}, cpw[n] = {4, 4, 4, 4, 4, 4, 4, 4},
+                         fch[n] = {1, 1, 1, 4, 1, 1, 1, 1};
+    static constexpr bool fuse[n] = {false, false, false, false, true, true, true, true},
+                          early[n] = {false, false, false, false, false, false, true, true};
+    static constexpr int napply = 6;  // the apply has no early loads: its loads already precede the row phase
 };
 template <>
 struct WaveVariants<20, 20> {
     static constexpr int n = 5;
     static constexpr int bt[n] = {2, 2, 1, 2, 2}, cpw[n] = {5, 4, 5, 10, 5}, fch[n] = {1, 1, 1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, false, false, true};
+    static constexpr bool fuse[n] = {false, false, false, false, true}, early[n] = {false, false, false, false, false};
+    static constexpr int napply = n;
 };
 
 template <int N1, int N2, int V>
 void launch_wave_one(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 wgrid, hipStream_t st) {
     using VV = WaveVariants<N1, N2>;
     constexpr int BT = VV::bt[V], CPW = VV::cpw[V], FCH = VV::fch[V];
-    constexpr bool FU = VV::fuse[V];
+    constexpr bool FU = VV::fuse[V], EA = VV::early[V];
     using K = WaveKernel<N1, N2, BT, CPW, double2, 2, FCH, FU>;
     if (density)
-        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU>, "k_density_w", K::bytes(), wgrid,
+        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, EA>, "k_density_w", K::bytes(), wgrid,
                         K::NT, st, a, t);
     else
         launch_with_lds(k_apply_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU>, "k_apply_w", K::bytes(), wgrid, K::NT,
@@ -1306,7 +1320,8 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                       a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
-            constexpr int NV = WaveVariants<N1, N2>::n;
+            // the variants that differ only in the density's load order are not timed again
+            constexpr int NV = WaveVariants<N1, N2>::napply;
             launch_wave_v<N1, N2, NV - 1>(false, tune_pick(kTuneApply, key, NV), aw, t, wgrid, st, nrhs);
         }
     } else {
@@ -1482,6 +1497,11 @@ bool zpass_fixed_supported(int n3) {
 // IT per block) that the autotuner times, variant 0 the hand-picked default
 // (20: 7710 applies/s with 128 / 16 / 1 against 7519 with 256 / 16 / 4 on the
 // 20^3 system).  Every line is transformed alike, so the results are identical.
+// Longer lines: more waves per CU pay (the passes wait on memory, one block
+// per tile of lines); at 180 the inverse pass keeps 256-byte column runs
+// (16 columns, 512 threads) and the forward pass takes 8 columns with 512
+// threads (4.1 and 4.2 ms on the 48 x 48 x 180 slab against 4.4 and 5.9 ms
+// for 256 / 16 / 1).
 namespace {
 template <int N3, int NT, int CT, int IT>
 struct ZV {};
@@ -1520,11 +1540,12 @@ void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatc
         case 48: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<48, 256, 16, 2>{}, ZV<48, 128, 16, 1>{}); break;
         case 96:
             launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<96, 256, 16, 1>{}, ZV<96, 128, 16, 1>{},
-                           ZV<96, 512, 32, 1>{});
+                           ZV<96, 512, 32, 1>{}, ZV<96, 256, 8, 1>{}, ZV<96, 512, 16, 1>{}, ZV<96, 512, 8, 1>{});
             break;
         case 180:
             launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<180, 256, 16, 1>{}, ZV<180, 128, 16, 1>{},
-                           ZV<180, 512, 32, 1>{});
+                           ZV<180, 512, 32, 1>{}, ZV<180, 256, 8, 1>{}, ZV<180, 128, 8, 1>{}, ZV<180, 512, 16, 1>{},
+                           ZV<180, 512, 8, 1>{});
             break;
         default: throw Error{TM_EUNSUPPORTED, "no fixed-size z pass for this grid"};
     }
