@@ -1458,7 +1458,188 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
     }
 }
 
-template <int N3, int NT, int CT, int IT>
+// digit-reversed position -> natural index of the in-place transforms of
+// length N (the radix plan's digits reversed; the same map as the host table)
+template <int N>
+__device__ __forceinline__ int dperm(int pos) {
+    constexpr CPlan cp = cplan(N);
+    int rem = pos, k = 0, weight = 1, place = N;
+#pragma unroll
+    for (int s = 0; s < cp.nrad; ++s) {
+        place /= cp.rad[s];
+        const int d = rem / place;
+        rem -= d * place;
+        k += d * weight;
+        weight *= cp.rad[s];
+    }
+    return k;
+}
+
+// The z passes with every global load of a tile issued up front.  A thread
+// owns a fixed share of one line's sphere entries (at most EPT of them, the
+// loop fully unrolled), so the table reads, the coefficient gathers and (in
+// the forward pass) the vector and kinetic-energy reads of all of them are
+// in flight together instead of one dependent chain per entry; the digit
+// reversal of a line position is computed, not read.  Same per-line
+// arithmetic as k_zinv_t / k_zfwd_t, so the results are identical.
+template <int N3, int NT, int CT, int IT, class T2>
+__global__ void __launch_bounds__(NT) k_zinv_p(ZPassArgs a) {
+    constexpr int L = CT * IT;
+    constexpr int LS = N3 + 1;
+    static_assert(NT % L == 0, "a line's entries take NT / L threads");
+    constexpr int PER = NT / L;
+    constexpr int EPT = cdiv(N3, PER);  // a column holds at most N3 entries
+    extern __shared__ double2 lds_raw[];
+    T2* lds = reinterpret_cast<T2*>(lds_raw);
+    T2* tw = lds + L * LS;
+    const T2* gtw = pick<T2>(a.tw, a.tw32);
+    const int b = blockIdx.z, bt = b % a.nb2;
+    const int ncol = a.ncol[bt];
+    const int col0 = blockIdx.x * CT;
+    if (col0 >= ncol) return;
+    const int item0 = blockIdx.y * IT;
+    const int l = threadIdx.x / PER, sub = threadIdx.x - l * PER;
+    const int c = col0 + l % CT, item = item0 + l / CT;
+    const bool live = c < ncol && item < a.nitems;
+    int e0 = 0, e1 = 0;
+    if (live) {
+        const int* cp = a.colptr[bt];
+        e0 = cp[c];
+        e1 = cp[c + 1];
+    }
+    const int* eg = a.entg[bt];
+    const int* ei = a.enti3[bt];
+    int g[EPT], z[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int en = e0 + sub + k * PER;
+        g[k] = -1;
+        if (en < e1) {
+            g[k] = eg[en];
+            z[k] = ei[en];
+        }
+    }
+    const double2* coef = a.coef_table ? a.coef_table[bt] : a.coef_base + (long long)b * a.coef_bstride;
+    const long long istr = a.istride_tab ? a.istride_tab[bt] : a.istride;
+    const double2* src = coef + (long long)item * istr;
+    double2 v[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (g[k] >= 0) v[k] = src[g[k]];
+    // while the gathers are in flight: twiddles and the zero lines
+    for (int i = threadIdx.x; i < N3; i += NT) tw[i] = gtw[i];
+    for (int i = threadIdx.x; i < L * LS; i += NT) lds[i] = Cx<T2>::mk(0, 0);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (g[k] >= 0) lds[l * LS + z[k]] = Cx<T2>::from(v[k]);
+    __syncthreads();
+    fft_dif<N3, +1, NT, false>(lds, L, ZLines<LS>{}, tw);
+    T2* out = pick<T2>(a.cols, a.cols32) + (long long)b * a.nitems * N3 * a.ncol_stride;
+    for (int i = threadIdx.x; i < L * N3; i += NT) {
+        const int cl = i % CT, rest = i / CT;
+        const int p = rest % N3, il = rest / N3;
+        const int cc = col0 + cl, it = item0 + il;
+        if (cc < ncol && it < a.nitems)
+            out[((long long)it * N3 + dperm<N3>(p)) * a.ncol_stride + cc] = lds[(il * CT + cl) * LS + p];
+    }
+}
+
+template <int N3, int NT, int CT, int IT, class T2>
+__global__ void __launch_bounds__(NT) k_zfwd_p(ZPassArgs a) {
+    constexpr int L = CT * IT;
+    constexpr int LS = N3 + 1;
+    static_assert(NT % L == 0, "a line's entries take NT / L threads");
+    constexpr int PER = NT / L;
+    constexpr int EPT = cdiv(N3, PER);
+    constexpr int VPT = cdiv(L * N3, NT);  // line values per thread
+    extern __shared__ double2 lds_raw[];
+    T2* lds = reinterpret_cast<T2*>(lds_raw);
+    T2* tw = lds + L * LS;
+    const T2* gtw = pick<T2>(a.tw, a.tw32);
+    const int b = blockIdx.z, bt = b % a.nb2;
+    const int ncol = a.ncol[bt];
+    const int col0 = blockIdx.x * CT;
+    const int item0 = blockIdx.y * IT;
+    const long long bbase = (long long)b * a.nitems * a.npw_pad;
+    if (blockIdx.x == 0) {  // the first column tile clears the padding of its items
+        const int npw = a.npw[bt], padn = a.npw_pad - npw;
+        for (int i = threadIdx.x; i < IT * padn; i += NT) {
+            const int item = item0 + i / padn;
+            if (item < a.nitems) a.out[bbase + (long long)item * a.npw_pad + npw + i % padn] = cmk(0.0, 0.0);
+        }
+    }
+    if (col0 >= ncol) return;
+    // the tile's column values (a line position's natural index computed in registers)
+    const T2* cin = pick<T2>(a.cols, a.cols32) + (long long)b * a.nitems * N3 * a.ncol_stride;
+    T2 v[VPT];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = threadIdx.x + j * NT;
+        v[j] = Cx<T2>::mk(0, 0);
+        if (i < L * N3) {
+            const int cl = i % CT, rest = i / CT;
+            const int p = rest % N3, il = rest / N3;
+            const int cc = col0 + cl, it = item0 + il;
+            if (cc < ncol && it < a.nitems) v[j] = cin[((long long)it * N3 + dperm<N3>(p)) * a.ncol_stride + cc];
+        }
+    }
+    // the thread's sphere entries: table rows, then the input vector and the kinetic energies
+    const int l = threadIdx.x / PER, sub = threadIdx.x - l * PER;
+    const int c = col0 + l % CT, item = item0 + l / CT;
+    const bool live = c < ncol && item < a.nitems;
+    int e0 = 0, e1 = 0;
+    double e = 0.0;
+    if (live) {
+        const int* cp = a.colptr[bt];
+        e0 = cp[c];
+        e1 = cp[c + 1];
+        e = a.eps[bt][item >> 1];
+    }
+    const int* eg = a.entg[bt];
+    const int* ei = a.enti3[bt];
+    int g[EPT], z[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+        const int en = e0 + sub + k * PER;
+        g[k] = -1;
+        if (en < e1) {
+            g[k] = eg[en];
+            z[k] = ei[en];
+        }
+    }
+    const double* kin = a.kin[bt];
+    const long long off = bbase + (long long)item * a.npw_pad;
+    double2 x[EPT];
+    double kv[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (g[k] >= 0) {
+            x[k] = a.xin[off + g[k]];
+            kv[k] = kin[g[k]];
+        }
+    for (int i = threadIdx.x; i < N3; i += NT) tw[i] = gtw[i];
+#pragma unroll
+    for (int j = 0; j < VPT; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (i < L * N3) {
+            const int cl = i % CT, rest = i / CT;
+            const int p = rest % N3, il = rest / N3;
+            lds[(il * CT + cl) * LS + p] = v[j];
+        }
+    }
+    __syncthreads();
+    fft_dit_all<N3, -1, NT>(lds, L, ZLines<LS>{}, tw);
+#pragma unroll
+    for (int k = 0; k < EPT; ++k)
+        if (g[k] >= 0) {
+            const double2 f = cscale(Cx<double2>::from(lds[l * LS + z[k]]), a.inv_n);
+            const double s = kv[k] - e;
+            a.out[off + g[k]] = cmk(f.x + s * x[k].x, f.y + s * x[k].y);
+        }
+}
+
+template <int N3, int NT, int CT, int IT, bool PF = false>
 void launch_z(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStream_t st, bool fp32) {
     constexpr int L = CT * IT;
     const size_t esz = fp32 ? sizeof(float2) : sizeof(double2);
@@ -1477,6 +1658,14 @@ void launch_z(bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStre
         } else {
             lds((const void*)k_zfwd_t<N3, NT, CT, IT, float2>);
             TM_LAUNCH((k_zfwd_t<N3, NT, CT, IT, float2>), grid, dim3(NT), shm, st, a);
+        }
+    } else if constexpr (PF) {
+        if (inverse) {
+            lds((const void*)k_zinv_p<N3, NT, CT, IT, double2>);
+            TM_LAUNCH((k_zinv_p<N3, NT, CT, IT, double2>), grid, dim3(NT), shm, st, a);
+        } else {
+            lds((const void*)k_zfwd_p<N3, NT, CT, IT, double2>);
+            TM_LAUNCH((k_zfwd_p<N3, NT, CT, IT, double2>), grid, dim3(NT), shm, st, a);
         }
     } else if (inverse) {
         lds((const void*)k_zinv_t<N3, NT, CT, IT, double2>);
@@ -1498,22 +1687,22 @@ bool zpass_fixed_supported(int n3) {
 // (20: 7710 applies/s with 128 / 16 / 1 against 7519 with 256 / 16 / 4 on the
 // 20^3 system).  Every line is transformed alike, so the results are identical.
 // Longer lines: more waves per CU pay (the passes wait on memory, one block
-// per tile of lines); at 180 the inverse pass keeps 256-byte column runs
-// (16 columns, 512 threads) and the forward pass takes 8 columns with 512
-// threads (4.1 and 4.2 ms on the 48 x 48 x 180 slab against 4.4 and 5.9 ms
-// for 256 / 16 / 1).
+// per tile of lines), and so do the prefetching kernels (the last three
+// shapes of 96 and 180): on the 48 x 48 x 180 slab 3.5 ms inverse (512 / 16 /
+// 1) and 3.7 ms forward (256 / 8 / 1) against 4.6 and 5.9 ms for 256 / 16 / 1.
+// (128 / 16 / 1, 512 / 32 / 1 and 128 / 8 / 1 never won at 180.)
 namespace {
-template <int N3, int NT, int CT, int IT>
+template <int N3, int NT, int CT, int IT, bool PF = false>
 struct ZV {};
 template <int N3, class... V>
 struct ZVariants {
     static constexpr int n = sizeof...(V);
 };
 
-template <int N3, int NT, int CT, int IT, class... Rest>
+template <int N3, int NT, int CT, int IT, bool PF, class... Rest>
 void launch_z_v(int v, bool inverse, const ZPassArgs& a, int ncolmax, int nbatch, hipStream_t st, bool fp32,
-                ZV<N3, NT, CT, IT>, Rest... rest) {
-    if (v == 0) return launch_z<N3, NT, CT, IT>(inverse, a, ncolmax, nbatch, st, fp32);
+                ZV<N3, NT, CT, IT, PF>, Rest... rest) {
+    if (v == 0) return launch_z<N3, NT, CT, IT, PF>(inverse, a, ncolmax, nbatch, st, fp32);
     if constexpr (sizeof...(Rest) > 0) launch_z_v(v - 1, inverse, a, ncolmax, nbatch, st, fp32, rest...);
 }
 
@@ -1533,19 +1722,26 @@ void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatc
         case 8: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<8, 256, 16, 4>{}, ZV<8, 128, 16, 2>{}); break;
         case 20:
             launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<20, 128, 16, 1>{}, ZV<20, 256, 16, 4>{},
-                           ZV<20, 64, 16, 1>{});
+                           ZV<20, 64, 16, 1>{}, ZV<20, 128, 16, 1, true>{}, ZV<20, 256, 16, 4, true>{});
             break;
-        case 24: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<24, 256, 16, 4>{}, ZV<24, 128, 16, 2>{}); break;
-        case 32: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<32, 256, 16, 2>{}, ZV<32, 128, 16, 1>{}); break;
+        case 24:
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<24, 256, 16, 4>{}, ZV<24, 128, 16, 2>{},
+                           ZV<24, 256, 16, 4, true>{}, ZV<24, 256, 16, 1, true>{});
+            break;
+        case 32:
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<32, 256, 16, 2>{}, ZV<32, 128, 16, 1>{},
+                           ZV<32, 256, 16, 2, true>{}, ZV<32, 256, 16, 1, true>{});
+            break;
         case 48: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<48, 256, 16, 2>{}, ZV<48, 128, 16, 1>{}); break;
         case 96:
             launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<96, 256, 16, 1>{}, ZV<96, 128, 16, 1>{},
-                           ZV<96, 512, 32, 1>{}, ZV<96, 256, 8, 1>{}, ZV<96, 512, 16, 1>{}, ZV<96, 512, 8, 1>{});
+                           ZV<96, 512, 32, 1>{}, ZV<96, 256, 8, 1>{}, ZV<96, 512, 16, 1>{}, ZV<96, 512, 8, 1>{},
+                           ZV<96, 512, 8, 1, true>{}, ZV<96, 256, 8, 1, true>{}, ZV<96, 512, 16, 1, true>{});
             break;
         case 180:
-            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<180, 256, 16, 1>{}, ZV<180, 128, 16, 1>{},
-                           ZV<180, 512, 32, 1>{}, ZV<180, 256, 8, 1>{}, ZV<180, 128, 8, 1>{}, ZV<180, 512, 16, 1>{},
-                           ZV<180, 512, 8, 1>{});
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<180, 256, 16, 1>{}, ZV<180, 256, 8, 1>{},
+                           ZV<180, 512, 16, 1>{}, ZV<180, 512, 8, 1>{}, ZV<180, 512, 8, 1, true>{},
+                           ZV<180, 256, 8, 1, true>{}, ZV<180, 512, 16, 1, true>{});
             break;
         default: throw Error{TM_EUNSUPPORTED, "no fixed-size z pass for this grid"};
     }

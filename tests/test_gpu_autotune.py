@@ -3,10 +3,11 @@
 Every compiled variant of every tunable launch, forced in turn, gives the
 oracle's apply at 1e-12 on systems that reach them: the 20^3 system (20 x 20
 plane kernels, z passes of 20), a cubic cell on a 48^3 grid (the benchmark's
-48 x 48 plane kernels, z passes of 48) and a 24^3 grid with 48 bands (the
-LDS-staged contractions and their K splits).  Plane and z-pass variants only
-split the work differently, so their outputs are identical to variant 0's;
-the contraction variants sum K in other splits.  The full-size system's
+48 x 48 plane kernels, z passes of 48), the serving pool's 48 x 48 x 96 slab (z
+passes of 96), a 32^3 grid and a 24^3 grid with 48 bands (the LDS-staged
+contractions and their K splits).  Plane and z-pass variants only split the work differently,
+so their outputs are identical to variant 0's; the contraction variants sum K
+in other splits.  The full-size system's
 variants (z passes of 180, 104-band contractions) are checked in the
 full-size tests.
 """
@@ -83,7 +84,7 @@ def test_variants_cubic20(lib, cubic_gs, cubic_q):
         lib.tm_system_destroy(h)
 
 
-@pytest.mark.parametrize("n,nb", [(48, 4), (24, 48)], ids=["48^3-4bands", "24^3-48bands"])
+@pytest.mark.parametrize("n,nb", [(48, 4), (24, 48), (32, 4)], ids=["48^3-4bands", "24^3-48bands", "32^3-4bands"])
 def test_variants_synthetic(lib, n, nb):
     prob = _synthetic_problem(synth.make_cubic(n, nb, 1), np.array([0.1, 0.05, 0.0]) * 2 * np.pi / 10.0, 5)
     h = lib.tm_system_create(desc_from_problem(prob))
@@ -92,6 +93,19 @@ def test_variants_synthetic(lib, n, nb):
         if nb == 48:
             ops.append("contraction")
         check_every_variant(lib, h, prob, f"grid {n}x{n}x{n}, {nb} bands, 1 k", ops)
+    finally:
+        lib.tm_system_destroy(h)
+
+
+def test_variants_slab96(lib):
+    """The 48 x 48 x 96 slab of the serving pool (4 bands, Gamma only): the
+    plane kernels of 48 x 48 and the z passes of 96."""
+    sd = synth.make_hexslab(c=16.5, fft=(48, 48, 96), nbnd=4, nk=1)
+    prob = _synthetic_problem(sd, synth.cart_from_frac(sd, [0.25, 0.0, 0.0]), 3)
+    h = lib.tm_system_create(desc_from_problem(prob))
+    try:
+        check_every_variant(lib, h, prob, "grid 48x48x96, 4 bands, 1 k",
+                            ["plane_density", "plane_apply", "zpass_inverse", "zpass_forward"])
     finally:
         lib.tm_system_destroy(h)
 
