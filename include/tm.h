@@ -233,8 +233,9 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
  * method).  Several launches of the apply exist as compiled variants that
  * split the same work differently: the plane density and apply kernels
  * (butterflies per load group, columns per wave, row loads in flight), the z
- * passes (threads, columns and items per block) and the projector / P_c
- * contractions (K split).  Before a system's first tunable launch -- its
+ * passes (threads, columns and items per block), the projector / P_c
+ * contractions (K split) and their updates (loads grouped ahead of the
+ * products or not).  Before a system's first tunable launch -- its
  * first FP64 apply, start vector with a projection (tm_start_vectors with
  * v), FP64 chain begin or restore -- outside a stream capture, every variant
  * is timed on that system's data (the first apply's own vectors, else two
@@ -245,9 +246,10 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
  * right-hand sides (lanes) are timed again, on the caller's vectors, at the
  * system's first FP64 apply of that many (one size class per power of two):
  * their best shapes change once the grid fills the device.  Their variants
- * give identical results, so this changes no result; the contractions keep
- * the one-right-hand-side choice.  Plane and z-pass variants give identical results; the
- * contraction variants sum K in different splits (results equal up to
+ * give identical results, so this changes no result; the contractions and
+ * updates keep the one-right-hand-side choice.  Plane, z-pass and update
+ * variants give identical results; the contraction variants sum K in
+ * different splits (results equal up to
  * rounding), so two processes may differ in the last bits -- forcing the
  * contraction variant (tm_autotune_force(4, 0)) makes results reproducible
  * bit for bit across processes, e.g. for a chain saved in one and restored in
@@ -259,7 +261,7 @@ int tm_liouvillian_apply_multi(tm_system* sys, int iq, int nrhs, const void* xy_
  *     hand-picked default, for shapes not yet tuned).
  *   tm_autotune_force(op, variant): use `variant` of operation op for every
  *     shape (op: 0 plane density, 1 plane apply, 2 z inverse, 3 z forward,
- *     4 contraction); -1 returns to the tuned choice.  A variant beyond a
+ *     4 contraction, 5 update); -1 returns to the tuned choice.  A variant beyond a
  *     shape's count makes that apply fail with TM_EINVAL.  For tests.
  *   tm_autotune_report(buf, cap, needed): the tuned shapes as text, one line
  *     each: operation, shape, number of variants, chosen variant, measured

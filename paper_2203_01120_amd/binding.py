@@ -314,7 +314,8 @@ def tm_liouvillian_apply_noalloc(h, iq: int, xy_in, xy_out, prec: int = TM_FP64,
                                                C.c_void_p(xy_out.data_ptr()), prec, _stream(stream)))
 
 
-TUNE_OPS = {"plane_density": 0, "plane_apply": 1, "zpass_inverse": 2, "zpass_forward": 3, "contraction": 4}
+TUNE_OPS = {"plane_density": 0, "plane_apply": 1, "zpass_inverse": 2, "zpass_forward": 3, "contraction": 4,
+            "update": 5}
 
 
 def tm_autotune_enable(on: bool) -> None:

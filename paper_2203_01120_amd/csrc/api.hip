@@ -94,13 +94,13 @@ struct TuneEntry {
 };
 std::mutex g_tune_mu;
 std::map<std::pair<int, long long>, TuneEntry> g_tuned;
-int g_force[kTuneOps] = {-1, -1, -1, -1, -1};
-int g_trial[kTuneOps] = {-1, -1, -1, -1, -1};   // the variant being timed
+int g_force[kTuneOps] = {-1, -1, -1, -1, -1, -1};
+int g_trial[kTuneOps] = {-1, -1, -1, -1, -1, -1};   // the variant being timed
 long long g_seen_key[kTuneOps];
 int g_seen_n[kTuneOps];
 bool g_autotune = true;
 const char* const kTuneNames[kTuneOps] = {"plane_density", "plane_apply", "zpass_inverse", "zpass_forward",
-                                           "contraction"};
+                                           "contraction", "update"};
 }  // namespace
 
 int tune_pick(int op, long long key, int nvariants) {
@@ -799,9 +799,11 @@ static void autotune(System& s, QSet& q, const double2* in, double2* out, hipStr
         {kTuneZFwd, "z forward", [&] { launch_zpass_fwd(s, q, s.ws.xcols, in, out, st, false, nrhs); }},
         {kTuneGemm, "P_c contraction", [&] { launch_project(s, q, out, st); }},
         {kTuneGemm, "projector contraction", [&] { launch_nonlocal(s, q, in, out, st); }},
+        {kTuneUpd, "P_c update", [&] { launch_project(s, q, out, st); }},
+        {kTuneUpd, "projector update", [&] { launch_nonlocal(s, q, in, out, st); }},
     };
     for (const Op& o : ops) {
-        if (nrhs > 1 && o.op == kTuneGemm) continue;
+        if (nrhs > 1 && (o.op == kTuneGemm || o.op == kTuneUpd)) continue;
         {
             std::lock_guard<std::mutex> lock(g_tune_mu);
             g_seen_n[o.op] = 0;

@@ -156,6 +156,13 @@ constexpr int kCnTilesPerWave = 7;    // (mt * nt) / 8 waves, at most
 constexpr int kCnMaxTilesSum = 16;   // mt + nt, at most
 constexpr int kCnStage = kCnMaxTilesSum * 16 * kCnChunk / kCnThreads;  // staged elements per thread
 
+__device__ double2 g_zero2;  // zero-initialised, never written
+// a complex value as a native vector, and a pointer to one in global memory
+// (operands reached through pointer tables would otherwise be read with flat
+// loads, which make every wait a wait for all loads, LDS included)
+typedef double __attribute__((ext_vector_type(2))) DVec2;
+typedef const DVec2 __attribute__((address_space(1))) GlobalD2;
+
 template <class R>
 struct LdsC {
     R re, im;
@@ -192,10 +199,14 @@ __global__ void __launch_bounds__(kCnThreads) k_gemm_cn_lds(GemmCN g, int mt) {
             const int row = e / kCnChunk, kx = k0 + (e - row * kCnChunk);
             const bool isA = row < Mp;
             const int r = isA ? row : row - Mp;
-            double2 v = cmk(0.0, 0.0);
-            if (e < nst && kx < kend && (isA ? r < g.M : r < g.Nn))
-                v = isA ? A[(long long)r * g.lda + kx] : B[(long long)r * g.ldb + kx];
-            stage[j] = v;
+            // unconditional global loads (an element outside the operands is
+            // read from a zero in device memory): no branch around a load, and
+            // no flat load, whose pending count would also hold up the LDS reads
+            // of the products below
+            const bool in = e < nst && kx < kend && (isA ? r < g.M : r < g.Nn);
+            const double2* p = !in ? &g_zero2 : isA ? A + (long long)r * g.lda + kx : B + (long long)r * g.ldb + kx;
+            const DVec2 v = *(const GlobalD2*)p;
+            stage[j] = cmk(v.x, v.y);
         }
     };
     fetch(kbeg);
@@ -273,8 +284,14 @@ struct GemmUpd {
 
 // One block per 16 rows k of A and batch; its waves take the 16-wide tiles of
 // n, so that the A rows are fetched once (into one XCD's L2 and the CU's L1)
-// for all of them.
-template <class R>
+// for all of them.  U = 0: one step of 4 at a time (loads, then products);
+// U > 0: the inner dimension goes in groups of U steps, two register groups
+// in turn, the loads of the next group issued before the products of the
+// current one and the outputs' current values read at the start, so that a
+// wave does not wait a full memory latency per step (more registers, fewer
+// waves per CU).  The products run in the same order in every variant, so the
+// results are identical; the autotuner picks per shape.
+template <class R, int U>
 __global__ void __launch_bounds__(1024) k_gemm_update(GemmUpd g) {
     const int b = blockIdx.z;
     const int n0 = (threadIdx.x >> 6) * 16, k0 = blockIdx.y * 16;
@@ -285,24 +302,77 @@ __global__ void __launch_bounds__(1024) k_gemm_update(GemmUpd g) {
     double2* Y = g.Y_base + (long long)b * g.y_bstride;
     typename MF<R>::V dr = {0, 0, 0, 0}, di = {0, 0, 0, 0};
     const bool ncol = (n0 + i) < g.Nout, kcol = (k0 + i) < g.K;
-    for (int m = 0; m < g.Minner; m += 4) {
-        int mm = m + kk;
-        double2 c = (mm < g.Minner && ncol) ? C[(long long)mm * g.ldc + n0 + i] : cmk(0.0, 0.0);
-        double2 a = (mm < g.Minner && kcol) ? A[(long long)mm * g.lda + k0 + i] : cmk(0.0, 0.0);
-        const R cx = (R)c.x, cy = (R)c.y, ax = (R)a.x, ay = (R)a.y;
-        dr = mfma(cx, ax, dr);
-        dr = mfma(-cy, ay, dr);
-        di = mfma(cx, ay, di);
-        di = mfma(cy, ax, di);
-    }
     const double os = bt < g.nk ? g.os_x : g.os_y;
+    if constexpr (U == 0) {
+        for (int m = 0; m < g.Minner; m += 4) {
+            int mm = m + kk;
+            double2 c = (mm < g.Minner && ncol) ? C[(long long)mm * g.ldc + n0 + i] : cmk(0.0, 0.0);
+            double2 a = (mm < g.Minner && kcol) ? A[(long long)mm * g.lda + k0 + i] : cmk(0.0, 0.0);
+            const R cx = (R)c.x, cy = (R)c.y, ax = (R)a.x, ay = (R)a.y;
+            dr = mfma(cx, ax, dr);
+            dr = mfma(-cy, ay, dr);
+            di = mfma(cx, ay, di);
+            di = mfma(cy, ax, di);
+        }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        int n = n0 + MF<R>::row(v, kk), k = k0 + i;
-        if (n < g.Nout && k < g.K) {
-            double2* y = Y + (long long)n * g.ldy + k;
-            double2 cur = *y;
-            *y = cmk(os * (cur.x + g.cs * (double)dr[v]), os * (cur.y + g.cs * (double)di[v]));
+        for (int v = 0; v < 4; ++v) {
+            int n = n0 + MF<R>::row(v, kk), k = k0 + i;
+            if (n < g.Nout && k < g.K) {
+                double2* y = Y + (long long)n * g.ldy + k;
+                double2 cur = *y;
+                *y = cmk(os * (cur.x + g.cs * (double)dr[v]), os * (cur.y + g.cs * (double)di[v]));
+            }
+        }
+    } else {
+        // every load is issued unconditionally (an element outside the
+        // operands is read from a zero in device memory), so that no branch
+        // separates the loads from their uses and a group's products wait only
+        // for that group's loads
+        auto load = [&](int m, double2* c, double2* a) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int mm = m + 4 * u + kk;
+                const double2* pc = (mm < g.Minner && ncol) ? C + (long long)mm * g.ldc + n0 + i : &g_zero2;
+                const double2* pa = (mm < g.Minner && kcol) ? A + (long long)mm * g.lda + k0 + i : &g_zero2;
+                const DVec2 cv = *(const GlobalD2*)pc, av = *(const GlobalD2*)pa;
+                c[u] = cmk(cv.x, cv.y);
+                a[u] = cmk(av.x, av.y);
+            }
+        };
+        auto products = [&](int m, const double2* c, const double2* a) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (m + 4 * u < g.Minner) {
+                    const R cx = (R)c[u].x, cy = (R)c[u].y, ax = (R)a[u].x, ay = (R)a[u].y;
+                    dr = mfma(cx, ax, dr);
+                    dr = mfma(-cy, ay, dr);
+                    di = mfma(cx, ay, di);
+                    di = mfma(cy, ax, di);
+                }
+            }
+        };
+        DVec2 ycur[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = n0 + MF<R>::row(v, kk), k = k0 + i;
+            const double2* py = (n < g.Nout && k < g.K) ? Y + (long long)n * g.ldy + k : &g_zero2;
+            ycur[v] = *(const GlobalD2*)py;
+        }
+        // two register groups in turn (no copies, which would wait for the loads)
+        double2 c0[U], a0[U], c1[U], a1[U];
+        load(0, c0, a0);
+        for (int m = 0; m < g.Minner; m += 8 * U) {
+            load(m + 4 * U, c1, a1);  // in flight during the products below (past the end: zeros, unused)
+            products(m, c0, a0);
+            load(m + 8 * U, c0, a0);
+            products(m + 4 * U, c1, a1);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int n = n0 + MF<R>::row(v, kk), k = k0 + i;
+            if (n < g.Nout && k < g.K)
+                Y[(long long)n * g.ldy + k] =
+                    cmk(os * (ycur[v].x + g.cs * (double)dr[v]), os * (ycur[v].y + g.cs * (double)di[v]));
         }
     }
 }
@@ -444,9 +514,15 @@ void run_gemm_update(double2* Y, long long y_bstride, int ldy, const double2* C,
     TM_CHECK(ntile <= 16, TM_EUNSUPPORTED, "more than 256 output columns per batch");
     dim3 grid(1, (K + 15) / 16, 2 * nk * nrhs);
     if (f32) {
-        TM_LAUNCH(k_gemm_update<float>, grid, dim3(64 * ntile), 0, st, g);
-    } else {
-        TM_LAUNCH(k_gemm_update<double>, grid, dim3(64 * ntile), 0, st, g);
+        TM_LAUNCH((k_gemm_update<float, 0>), grid, dim3(64 * ntile), 0, st, g);
+        return;
+    }
+    // the variant the autotuner picked for this shape (tuned with one
+    // right-hand side; every variant gives the same result)
+    switch (tune_pick(kTuneUpd, tune_key(Nout, Minner, 2 * nk), 3)) {
+        case 0: TM_LAUNCH((k_gemm_update<double, 0>), grid, dim3(64 * ntile), 0, st, g); break;
+        case 1: TM_LAUNCH((k_gemm_update<double, 2>), grid, dim3(64 * ntile), 0, st, g); break;
+        default: TM_LAUNCH((k_gemm_update<double, 3>), grid, dim3(64 * ntile), 0, st, g); break;
     }
 }
 

@@ -58,7 +58,7 @@ struct ProfScope {
 // Variants of the plane kernels and z passes do the same arithmetic in the
 // same order (only the work split differs), so their results are identical;
 // the contraction's variants split K differently (rounding-level differences).
-enum TuneOp { kTuneDensity = 0, kTuneApply = 1, kTuneZInv = 2, kTuneZFwd = 3, kTuneGemm = 4, kTuneOps = 5 };
+enum TuneOp { kTuneDensity = 0, kTuneApply = 1, kTuneZInv = 2, kTuneZFwd = 3, kTuneGemm = 4, kTuneUpd = 5, kTuneOps = 6 };
 int tune_pick(int op, long long key, int nvariants);
 // size class of a right-hand side count for the launch-shape keys: 0 for 1,
 // 1 for 2-3, 2 for 4-7, ...

@@ -5,9 +5,9 @@ oracle's apply at 1e-12 on systems that reach them: the 20^3 system (20 x 20
 plane kernels, z passes of 20), a cubic cell on a 48^3 grid (the benchmark's
 48 x 48 plane kernels, z passes of 48), the serving pool's 48 x 48 x 96 slab (z
 passes of 96), a 32^3 grid and a 24^3 grid with 48 bands (the LDS-staged
-contractions and their K splits).  Plane and z-pass variants only split the work differently,
-so their outputs are identical to variant 0's; the contraction variants sum K
-in other splits.  The full-size system's
+contractions and their K splits).  Plane, z-pass and update variants only split the work or
+order the loads differently, so their outputs are identical to variant 0's;
+the contraction variants sum K in other splits.  The full-size system's
 variants (z passes of 180, 104-band contractions) are checked in the
 full-size tests.
 """
@@ -21,7 +21,7 @@ from gpu_util import desc_from_problem, from_gpu, rel_err, say, to_gpu
 
 pytestmark = pytest.mark.gpu
 
-BITWISE = ("plane_density", "plane_apply", "zpass_inverse", "zpass_forward")
+BITWISE = ("plane_density", "plane_apply", "zpass_inverse", "zpass_forward", "update")
 
 
 def _synthetic_problem(sd, qcart, seed):
@@ -91,7 +91,7 @@ def test_variants_synthetic(lib, n, nb):
     try:
         ops = ["plane_density", "plane_apply", "zpass_inverse", "zpass_forward"]
         if nb == 48:
-            ops.append("contraction")
+            ops += ["contraction", "update"]
         check_every_variant(lib, h, prob, f"grid {n}x{n}x{n}, {nb} bands, 1 k", ops)
     finally:
         lib.tm_system_destroy(h)
