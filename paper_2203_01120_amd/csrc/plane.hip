@@ -1458,6 +1458,15 @@ __global__ void __launch_bounds__(NT) k_zfwd_t(ZPassArgs a) {
     }
 }
 
+// A pointer read from a pointer table, as a global-memory pointer: the
+// compiler cannot tell the address space of such a pointer once the kernel
+// has stored to global memory, and would issue flat loads through it, whose
+// pending count also holds up LDS operations.
+template <class T>
+__device__ __forceinline__ const T __attribute__((address_space(1)))* gptr(const T* p) {
+    return (const T __attribute__((address_space(1)))*)p;
+}
+
 // digit-reversed position -> natural index of the in-place transforms of
 // length N (the radix plan's digits reversed; the same map as the host table)
 template <int N>
@@ -1591,13 +1600,13 @@ __global__ void __launch_bounds__(NT) k_zfwd_p(ZPassArgs a) {
     int e0 = 0, e1 = 0;
     double e = 0.0;
     if (live) {
-        const int* cp = a.colptr[bt];
+        const auto cp = gptr(a.colptr[bt]);
         e0 = cp[c];
         e1 = cp[c + 1];
-        e = a.eps[bt][item >> 1];
+        e = gptr(a.eps[bt])[item >> 1];
     }
-    const int* eg = a.entg[bt];
-    const int* ei = a.enti3[bt];
+    const auto eg = gptr(a.entg[bt]);
+    const auto ei = gptr(a.enti3[bt]);
     int g[EPT], z[EPT];
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
@@ -1608,7 +1617,7 @@ __global__ void __launch_bounds__(NT) k_zfwd_p(ZPassArgs a) {
             z[k] = ei[en];
         }
     }
-    const double* kin = a.kin[bt];
+    const auto kin = gptr(a.kin[bt]);
     const long long off = bbase + (long long)item * a.npw_pad;
     double2 x[EPT];
     double kv[EPT];
