@@ -850,6 +850,67 @@ struct WaveKernel {
         wfft_dif<N2, +1, false, MAXR, BT, cp.nrad, 1, N2 / R>(m.pl, rl, nlw, gtw2, lane);
     }
 
+    // The fused row fill split in two, for a band's row elements loaded ahead
+    // (during the previous band's forward row stage): fill_load issues the
+    // loads of the lane's butterflies into registers, fill_finish transforms
+    // and stores them into buffer boff exactly as rows_inverse_fused does, then
+    // runs the remaining stages.
+    struct Fill {
+        static constexpr CPlan cp = cplan(N2);
+        static constexpr int R = cp.rad[0];
+        static constexpr int M = N2 / R;
+        static constexpr int SPL = wslots(M);
+        static constexpr int IT = cdiv(MAXR * SPL, 64);
+        T2 u[IT][R];
+        int base[IT], jv[IT];
+    };
+    __device__ static void fill_load(const Smem& m, const T2* cx, long long cs, int nlw, int w, int lane, Fill& f) {
+        constexpr int R = Fill::R, M = Fill::M, SPL = Fill::SPL;
+        const int ns = nlw * SPL;
+#pragma unroll
+        for (int it = 0; it < Fill::IT; ++it) {
+            const int sl = lane + it * 64;
+            const int li = sl / SPL, j = sl - li * SPL;
+            f.base[it] = -1;
+            f.jv[it] = j;
+            if (sl < ns && j < M) {
+                const int l = w + li * NW;
+                const int info = m.rowinfo[l];
+                const int s = info / N1, row = info - s * N1;
+                const short* ci = m.colidx + row * N2;
+                f.base[it] = m.rowbase[l] + j;
+#pragma unroll
+                for (int t = 0; t < R; ++t) {
+                    const int c = ci[j + t * M];
+                    f.u[it][t] = c >= 0 ? cx[s * cs + c] : Cx<T2>::mk(0, 0);
+                }
+            }
+        }
+    }
+    __device__ static void fill_finish(const Smem& m, int nlw, int boff, int lane, const WTw<N2, T2>& gtw2, Rows rl,
+                                       Fill& f) {
+        constexpr int R = Fill::R, M = Fill::M;
+#pragma unroll
+        for (int it = 0; it < Fill::IT; ++it) {
+            if (f.base[it] >= 0) {
+                dft_small<R>(f.u[it], +1);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    T2 y = f.u[it][r];
+                    if (r > 0 && f.jv[it] > 0) {
+                        T2 wv = gtw2.template get<0, N2>(r, f.jv[it]);
+                        wv.y = -wv.y;
+                        y = cmul(y, wv);
+                    }
+                    m.pl[boff + f.base[it] + r * M] = y;
+                }
+            }
+        }
+        wave_sync();
+        rl.boff = boff;
+        wfft_dif<N2, +1, false, MAXR, BT, Fill::cp.nrad, 1, N2 / R>(m.pl, rl, nlw, gtw2, lane);
+    }
+
     // The forward row transform of the wave's rows of buffer boff with its last
     // (DIT) stage fused with the output: the lane of butterfly j reads its R
     // inputs from LDS, twiddles and transforms them exactly as the stage does
@@ -1092,7 +1153,11 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false>
+// AHEAD (with FUSE): the next band's row elements are loaded during this
+// band's forward row stage, so that its row fill does not wait for them (nor,
+// the memory counter being in order, for this band's output stores).
+template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false,
+          bool AHEAD = false>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, PlaneTabs t) {
     using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH, FUSE>;
     using G = typename K::G;
@@ -1134,6 +1199,12 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
     const T2* fw = pick<T2>(a.fields, a.fields32) + (long long)(b / a.nb2) * a.fstride +
                    ((long long)i3 * N2 + w * CPW) * 6 * N1;
     const typename K::Rows rl(m.rowbase, w, nlw, lane);
+    static_assert(!AHEAD || FUSE, "row elements loaded ahead need the fused row fill");
+    typename K::Fill fill;
+    if constexpr (AHEAD)
+        if (n0 < n1e)
+            K::fill_load(m, xcols + (((long long)b * a.nitems + 2 * n0) * a.n3 + i3) * a.ncol_max, cs, nlw, w, lane,
+                         fill);
     for (int n = n0; n < n1e; ++n) {
         const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
@@ -1147,7 +1218,10 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
                 ud[j] = Cx<T2>::from(ur[G::NP + q]);
             }
         }
-        K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
+        if constexpr (AHEAD)
+            K::fill_finish(m, nlw, boff, lane, tw2, rl, fill);
+        else
+            K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
         __syncthreads();
         // columns: inverse along i1, point-wise products, forward along i1
         WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
@@ -1185,6 +1259,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
         // rows: forward along i2 on the occupied rows of the k+q sphere, then
         // the output columns
         T2* co = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
+        if constexpr (AHEAD)
+            if (n + 1 < n1e) K::fill_load(m, co + 2 * a.n3 * a.ncol_max, cs, nlw, w, lane, fill);
         if constexpr (K::FUSE) {
             K::rows_forward_out(m, co, cs, nlw, w, boff, lane, tw2, rl);
         } else {
@@ -1217,16 +1293,16 @@ void launch_with_lds(F kernel, const char* name, size_t shm, dim3 grid, int nt, 
 // Variants of the FP64 wave plane kernels that the autotuner times, variant 0
 // being the hand-picked default: BT butterflies per load group, CPW columns
 // per wave, FCH row elements in flight per lane, fused first / last row
-// stages, the density's ground-state loads issued before the row phase (all
-// with two LDS buffers and no occupancy floor).  They split the work
-// differently and do the same arithmetic per point in the same order, so
-// their results are identical.  The apply times the first napply of them.
+// stages, loads issued ahead (the density: a band's ground state before its
+// row phase; the apply: the next band's row elements during this band's
+// forward row stage; all with two LDS buffers and no occupancy floor).  They
+// split the work differently and do the same arithmetic per point in the same
+// order, so their results are identical.
 template <int N1, int N2>
 struct WaveVariants {  // 8x8, 24x24, 32x32
     static constexpr int n = 3;
     static constexpr int bt[n] = {2, 1, 2}, cpw[n] = {4, 4, 4}, fch[n] = {1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, true}, early[n] = {false, false, false};
-    static constexpr int napply = n;
+    static constexpr bool fuse[n] = {false, false, true}, ahead[n] = {false, false, false};
 };
 template <>
 struct WaveVariants<48, 48> {
@@ -1234,29 +1310,27 @@ struct WaveVariants<48, 48> {
     static constexpr int bt[n] = {2, 1, 4, 2, 2, 1, 1, 2}, cpw[n] = {4, 4, 4, 4, 4, 4, 4, 4},
                          fch[n] = {1, 1, 1, 4, 1, 1, 1, 1};
     static constexpr bool fuse[n] = {false, false, false, false, true, true, true, true},
-                          early[n] = {false, false, false, false, false, false, true, true};
-    static constexpr int napply = 6;  // the apply has no early loads: its loads already precede the row phase
+                          ahead[n] = {false, false, false, false, false, false, true, true};
 };
 template <>
 struct WaveVariants<20, 20> {
     static constexpr int n = 5;
     static constexpr int bt[n] = {2, 2, 1, 2, 2}, cpw[n] = {5, 4, 5, 10, 5}, fch[n] = {1, 1, 1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, false, false, true}, early[n] = {false, false, false, false, false};
-    static constexpr int napply = n;
+    static constexpr bool fuse[n] = {false, false, false, false, true}, ahead[n] = {false, false, false, false, false};
 };
 
 template <int N1, int N2, int V>
 void launch_wave_one(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 wgrid, hipStream_t st) {
     using VV = WaveVariants<N1, N2>;
     constexpr int BT = VV::bt[V], CPW = VV::cpw[V], FCH = VV::fch[V];
-    constexpr bool FU = VV::fuse[V], EA = VV::early[V];
+    constexpr bool FU = VV::fuse[V], AH = VV::ahead[V];
     using K = WaveKernel<N1, N2, BT, CPW, double2, 2, FCH, FU>;
     if (density)
-        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, EA>, "k_density_w", K::bytes(), wgrid,
+        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, AH>, "k_density_w", K::bytes(), wgrid,
                         K::NT, st, a, t);
     else
-        launch_with_lds(k_apply_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU>, "k_apply_w", K::bytes(), wgrid, K::NT,
-                        st, a, t);
+        launch_with_lds(k_apply_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, AH>, "k_apply_w", K::bytes(), wgrid,
+                        K::NT, st, a, t);
 }
 
 // launches variant v (0 .. V) of the FP64 density or apply
@@ -1320,8 +1394,7 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
             TM_CHECK(a.fields != nullptr, TM_EINVAL, "missing field table");
             TM_LAUNCH((k_fields_w<N1, N2, double2>), dim3((N1 * N2 + 255) / 256, a.n3, nrhs), dim3(256), 0, st,
                       a.vrs, a.W, t.perm1, t.perm2, a.fields, a.n3, a.wstride, a.fstride);
-            // the variants that differ only in the density's load order are not timed again
-            constexpr int NV = WaveVariants<N1, N2>::napply;
+            constexpr int NV = WaveVariants<N1, N2>::n;
             launch_wave_v<N1, N2, NV - 1>(false, tune_pick(kTuneApply, key, NV), aw, t, wgrid, st, nrhs);
         }
     } else {
