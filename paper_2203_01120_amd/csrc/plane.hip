@@ -1153,11 +1153,12 @@ __global__ void k_fields_w(const double* __restrict__ vrs, const double2* __rest
 
 // grid: (batch b, chunk, plane i3), so that the blocks in flight share a few
 // planes and their field tables stay in L2
-// AHEAD (with FUSE): the next band's row elements are loaded during this
+// AHEAD (with FUSE): 1, the next band's row elements are loaded during this
 // band's forward row stage, so that its row fill does not wait for them (nor,
-// the memory counter being in order, for this band's output stores).
+// the memory counter being in order, for this band's output stores); 2, the
+// next band's ground state too, right after this band's products.
 template <int N1, int N2, int BT, int CPW, class T2, int NBUF, int MINW, int FCH, bool FUSE = false,
-          bool AHEAD = false>
+          int AHEAD = 0>
 __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, PlaneTabs t) {
     using K = WaveKernel<N1, N2, BT, CPW, T2, NBUF, FCH, FUSE>;
     using G = typename K::G;
@@ -1201,24 +1202,45 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
     const typename K::Rows rl(m.rowbase, w, nlw, lane);
     static_assert(!AHEAD || FUSE, "row elements loaded ahead need the fused row fill");
     typename K::Fill fill;
-    if constexpr (AHEAD)
+    // AHEAD 2: the next band's ground state at the lane's points, loaded ahead
+    T2 nu[PPL], nd[PPL];
+    auto load_next_u = [&](int n) {
+        const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
+#pragma unroll
+        for (int j = 0; j < PPL; ++j) {
+            const int q = min(lane + 64 * j, K::WPTS - 1);
+            nu[j] = Cx<T2>::from(ur[q]);
+            nd[j] = Cx<T2>::from(ur[G::NP + q]);
+        }
+    };
+    if constexpr (AHEAD > 0)
         if (n0 < n1e)
             K::fill_load(m, xcols + (((long long)b * a.nitems + 2 * n0) * a.n3 + i3) * a.ncol_max, cs, nlw, w, lane,
                          fill);
+    if constexpr (AHEAD > 1)
+        if (n0 < n1e) load_next_u(n0);
     for (int n = n0; n < n1e; ++n) {
         const int boff = NBUF == 2 ? (n & 1) * K::BUF : 0;
         const T2* cx = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
         const double2* ur = ub + ((long long)n * a.n3 + i3) * 2 * G::NP;
         T2 uu[PPL], ud[PPL];
+        if constexpr (AHEAD > 1) {
 #pragma unroll
-        for (int j = 0; j < PPL; ++j) {
-            const int q = lane + 64 * j;
-            if (q < K::WPTS) {
-                uu[j] = Cx<T2>::from(ur[q]);
-                ud[j] = Cx<T2>::from(ur[G::NP + q]);
+            for (int j = 0; j < PPL; ++j) {
+                uu[j] = nu[j];
+                ud[j] = nd[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < PPL; ++j) {
+                const int q = lane + 64 * j;
+                if (q < K::WPTS) {
+                    uu[j] = Cx<T2>::from(ur[q]);
+                    ud[j] = Cx<T2>::from(ur[G::NP + q]);
+                }
             }
         }
-        if constexpr (AHEAD)
+        if constexpr (AHEAD > 0)
             K::fill_finish(m, nlw, boff, lane, tw2, rl, fill);
         else
             K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
@@ -1252,6 +1274,8 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
                 px[G::PS] = pd;
             }
         }
+        if constexpr (AHEAD > 1)
+            if (n + 1 < n1e) load_next_u(n + 1);
         wave_sync();
         constexpr CPlan c1 = cplan(N1);
         wfft_dit<N1, -1, 2 * CPW, K::BT, c1.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
@@ -1259,7 +1283,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
         // rows: forward along i2 on the occupied rows of the k+q sphere, then
         // the output columns
         T2* co = xcols + (((long long)b * a.nitems + 2 * n) * a.n3 + i3) * a.ncol_max;
-        if constexpr (AHEAD)
+        if constexpr (AHEAD > 0)
             if (n + 1 < n1e) K::fill_load(m, co + 2 * a.n3 * a.ncol_max, cs, nlw, w, lane, fill);
         if constexpr (K::FUSE) {
             K::rows_forward_out(m, co, cs, nlw, w, boff, lane, tw2, rl);
@@ -1302,32 +1326,34 @@ template <int N1, int N2>
 struct WaveVariants {  // 8x8, 24x24, 32x32
     static constexpr int n = 3;
     static constexpr int bt[n] = {2, 1, 2}, cpw[n] = {4, 4, 4}, fch[n] = {1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, true}, ahead[n] = {false, false, false};
+    static constexpr bool fuse[n] = {false, false, true};
+    static constexpr int ahead[n] = {0, 0, 0};
 };
 template <>
 struct WaveVariants<48, 48> {
-    static constexpr int n = 8;
-    static constexpr int bt[n] = {2, 1, 4, 2, 2, 1, 1, 2}, cpw[n] = {4, 4, 4, 4, 4, 4, 4, 4},
-                         fch[n] = {1, 1, 1, 4, 1, 1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, false, false, true, true, true, true},
-                          ahead[n] = {false, false, false, false, false, false, true, true};
+    static constexpr int n = 9;
+    static constexpr int bt[n] = {2, 1, 4, 2, 2, 1, 1, 2, 1}, cpw[n] = {4, 4, 4, 4, 4, 4, 4, 4, 4},
+                         fch[n] = {1, 1, 1, 4, 1, 1, 1, 1, 1}, ahead[n] = {0, 0, 0, 0, 0, 0, 1, 1, 2};
+    static constexpr bool fuse[n] = {false, false, false, false, true, true, true, true, true};
 };
 template <>
 struct WaveVariants<20, 20> {
     static constexpr int n = 5;
     static constexpr int bt[n] = {2, 2, 1, 2, 2}, cpw[n] = {5, 4, 5, 10, 5}, fch[n] = {1, 1, 1, 1, 1};
-    static constexpr bool fuse[n] = {false, false, false, false, true}, ahead[n] = {false, false, false, false, false};
+    static constexpr bool fuse[n] = {false, false, false, false, true};
+    static constexpr int ahead[n] = {0, 0, 0, 0, 0};
 };
 
 template <int N1, int N2, int V>
 void launch_wave_one(bool density, const PlaneArgs& a, const PlaneTabs& t, dim3 wgrid, hipStream_t st) {
     using VV = WaveVariants<N1, N2>;
     constexpr int BT = VV::bt[V], CPW = VV::cpw[V], FCH = VV::fch[V];
-    constexpr bool FU = VV::fuse[V], AH = VV::ahead[V];
+    constexpr bool FU = VV::fuse[V];
+    constexpr int AH = VV::ahead[V];
     using K = WaveKernel<N1, N2, BT, CPW, double2, 2, FCH, FU>;
     if (density)
-        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, AH>, "k_density_w", K::bytes(), wgrid,
-                        K::NT, st, a, t);
+        launch_with_lds(k_density_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, (AH > 0)>, "k_density_w", K::bytes(),
+                        wgrid, K::NT, st, a, t);
     else
         launch_with_lds(k_apply_w<N1, N2, BT, CPW, double2, 2, 1, FCH, FU, AH>, "k_apply_w", K::bytes(), wgrid,
                         K::NT, st, a, t);
