@@ -61,6 +61,19 @@ struct GemmCN {
     double2* part;                // [b][ks][M][Nn]
 };
 
+__device__ double2 g_zero2;  // zero-initialised, never written
+// a complex value as a native vector, and a pointer to one in global memory
+// (operands reached through pointer tables would otherwise be read with flat
+// loads, which make every wait a wait for all loads, LDS included)
+typedef double __attribute__((ext_vector_type(2))) DVec2;
+typedef const DVec2 __attribute__((address_space(1))) GlobalD2;
+
+// *p as a global-memory load
+__device__ __forceinline__ double2 gload(const double2* p) {
+    const DVec2 v = *(const GlobalD2*)p;
+    return cmk(v.x, v.y);
+}
+
 template <class R>
 __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     const int b = blockIdx.z, ks = blockIdx.y;
@@ -75,15 +88,27 @@ __global__ void __launch_bounds__(64) k_gemm_cn(GemmCN g) {
     const bool arow = (m0 + i) < g.M, brow = (n0 + i) < g.Nn;
     const double2* Ap = A + (long long)(m0 + i) * g.lda;
     const double2* Bp = B + (long long)(n0 + i) * g.ldb;
-    for (int k = kbeg; k < kend; k += 4) {
-        int kx = k + kk;
-        double2 a = (arow && kx < kend) ? Ap[kx] : cmk(0.0, 0.0);
-        double2 bv = (brow && kx < kend) ? Bp[kx] : cmk(0.0, 0.0);
-        const R ax = (R)a.x, ay = (R)a.y, bx = (R)bv.x, by = (R)bv.y;
-        cr = mfma(ax, bx, cr);
-        cr = mfma(ay, by, cr);
-        ci = mfma(ax, by, ci);
-        ci = mfma(-ay, bx, ci);
+    // KU steps' loads in flight together (global loads, an element outside
+    // the operands read from a zero); the products run in step order
+    constexpr int KU = 4;
+    for (int k = kbeg; k < kend; k += 4 * KU) {
+        double2 a[KU], bv[KU];
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            const int kx = k + 4 * u + kk;
+            a[u] = gload((arow && kx < kend) ? Ap + kx : &g_zero2);
+            bv[u] = gload((brow && kx < kend) ? Bp + kx : &g_zero2);
+        }
+#pragma unroll
+        for (int u = 0; u < KU; ++u) {
+            if (k + 4 * u < kend) {
+                const R ax = (R)a[u].x, ay = (R)a[u].y, bx = (R)bv[u].x, by = (R)bv[u].y;
+                cr = mfma(ax, bx, cr);
+                cr = mfma(ay, by, cr);
+                ci = mfma(ax, by, ci);
+                ci = mfma(-ay, bx, ci);
+            }
+        }
     }
     double2* out = g.part + ((long long)b * g.ksplit + ks) * g.M * g.Nn;
 #pragma unroll
@@ -119,8 +144,8 @@ __global__ void __launch_bounds__(64 * kSmallWaves) k_gemm_cn_small(GemmCN g, do
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
             const int kx = k0 + u * KS + kk;
-            a[u] = (arow && kx < g.K) ? Ap[kx] : cmk(0.0, 0.0);
-            bv[u] = (brow && kx < g.K) ? Bp[kx] : cmk(0.0, 0.0);
+            a[u] = gload((arow && kx < g.K) ? Ap + kx : &g_zero2);
+            bv[u] = gload((brow && kx < g.K) ? Bp + kx : &g_zero2);
         }
 #pragma unroll
         for (int u = 0; u < KU; ++u) {
@@ -155,13 +180,6 @@ constexpr int kMaxTiles1D = 14;       // M, Nn up to 224
 constexpr int kCnTilesPerWave = 7;    // (mt * nt) / 8 waves, at most
 constexpr int kCnMaxTilesSum = 16;   // mt + nt, at most
 constexpr int kCnStage = kCnMaxTilesSum * 16 * kCnChunk / kCnThreads;  // staged elements per thread
-
-__device__ double2 g_zero2;  // zero-initialised, never written
-// a complex value as a native vector, and a pointer to one in global memory
-// (operands reached through pointer tables would otherwise be read with flat
-// loads, which make every wait a wait for all loads, LDS included)
-typedef double __attribute__((ext_vector_type(2))) DVec2;
-typedef const DVec2 __attribute__((address_space(1))) GlobalD2;
 
 template <class R>
 struct LdsC {
@@ -204,9 +222,7 @@ __global__ void __launch_bounds__(kCnThreads) k_gemm_cn_lds(GemmCN g, int mt) {
             // no flat load, whose pending count would also hold up the LDS reads
             // of the products below
             const bool in = e < nst && kx < kend && (isA ? r < g.M : r < g.Nn);
-            const double2* p = !in ? &g_zero2 : isA ? A + (long long)r * g.lda + kx : B + (long long)r * g.ldb + kx;
-            const DVec2 v = *(const GlobalD2*)p;
-            stage[j] = cmk(v.x, v.y);
+            stage[j] = gload(!in ? &g_zero2 : isA ? A + (long long)r * g.lda + kx : B + (long long)r * g.ldb + kx);
         }
     };
     fetch(kbeg);
@@ -334,9 +350,8 @@ __global__ void __launch_bounds__(1024) k_gemm_update(GemmUpd g) {
                 const int mm = m + 4 * u + kk;
                 const double2* pc = (mm < g.Minner && ncol) ? C + (long long)mm * g.ldc + n0 + i : &g_zero2;
                 const double2* pa = (mm < g.Minner && kcol) ? A + (long long)mm * g.lda + k0 + i : &g_zero2;
-                const DVec2 cv = *(const GlobalD2*)pc, av = *(const GlobalD2*)pa;
-                c[u] = cmk(cv.x, cv.y);
-                a[u] = cmk(av.x, av.y);
+                c[u] = gload(pc);
+                a[u] = gload(pa);
             }
         };
         auto products = [&](int m, const double2* c, const double2* a) {

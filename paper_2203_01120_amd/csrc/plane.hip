@@ -1791,14 +1791,15 @@ bool zpass_fixed_supported(int n3) {
 }
 
 // Launch shapes of the fixed-length z passes (threads NT, columns CT and items
-// IT per block) that the autotuner times, variant 0 the hand-picked default
-// (20: 7710 applies/s with 128 / 16 / 1 against 7519 with 256 / 16 / 4 on the
-// 20^3 system).  Every line is transformed alike, so the results are identical.
+// IT per block; P: the prefetching kernels) that the autotuner times.
+// Variant 0 is the default, taken untuned and in single precision: a
+// prefetching shape that measured well in both directions for 20, 24, 32, 96
+// and 180.  Every line is transformed alike, so the results are identical.
 // Longer lines: more waves per CU pay (the passes wait on memory, one block
-// per tile of lines), and so do the prefetching kernels (the last three
-// shapes of 96 and 180): on the 48 x 48 x 180 slab 3.5 ms inverse (512 / 16 /
-// 1) and 3.7 ms forward (256 / 8 / 1) against 4.6 and 5.9 ms for 256 / 16 / 1.
-// (128 / 16 / 1, 512 / 32 / 1 and 128 / 8 / 1 never won at 180.)
+// per tile of lines), and so does prefetching: on the 48 x 48 x 180 slab
+// 3.5 ms inverse (P 512 / 16 / 1) and 3.7 ms forward (P 256 / 8 / 1) against
+// 4.6 and 5.9 ms for 256 / 16 / 1.  (128 / 16 / 1, 512 / 32 / 1 and 128 / 8 /
+// 1 never won at 180.)
 namespace {
 template <int N3, int NT, int CT, int IT, bool PF = false>
 struct ZV {};
@@ -1829,27 +1830,27 @@ void launch_zpass_fixed(bool inverse, const ZPassArgs& a, int ncolmax, int nbatc
     switch (n3) {
         case 8: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<8, 256, 16, 4>{}, ZV<8, 128, 16, 2>{}); break;
         case 20:
-            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<20, 128, 16, 1>{}, ZV<20, 256, 16, 4>{},
-                           ZV<20, 64, 16, 1>{}, ZV<20, 128, 16, 1, true>{}, ZV<20, 256, 16, 4, true>{});
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<20, 128, 16, 1, true>{}, ZV<20, 128, 16, 1>{},
+                           ZV<20, 256, 16, 4>{}, ZV<20, 64, 16, 1>{}, ZV<20, 256, 16, 4, true>{});
             break;
         case 24:
-            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<24, 256, 16, 4>{}, ZV<24, 128, 16, 2>{},
-                           ZV<24, 256, 16, 4, true>{}, ZV<24, 256, 16, 1, true>{});
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<24, 256, 16, 1, true>{}, ZV<24, 256, 16, 4>{},
+                           ZV<24, 128, 16, 2>{}, ZV<24, 256, 16, 4, true>{});
             break;
         case 32:
-            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<32, 256, 16, 2>{}, ZV<32, 128, 16, 1>{},
-                           ZV<32, 256, 16, 2, true>{}, ZV<32, 256, 16, 1, true>{});
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<32, 256, 16, 1, true>{}, ZV<32, 256, 16, 2>{},
+                           ZV<32, 128, 16, 1>{}, ZV<32, 256, 16, 2, true>{});
             break;
         case 48: launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<48, 256, 16, 2>{}, ZV<48, 128, 16, 1>{}); break;
         case 96:
-            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<96, 256, 16, 1>{}, ZV<96, 128, 16, 1>{},
-                           ZV<96, 512, 32, 1>{}, ZV<96, 256, 8, 1>{}, ZV<96, 512, 16, 1>{}, ZV<96, 512, 8, 1>{},
-                           ZV<96, 512, 8, 1, true>{}, ZV<96, 256, 8, 1, true>{}, ZV<96, 512, 16, 1, true>{});
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<96, 256, 8, 1, true>{}, ZV<96, 256, 16, 1>{},
+                           ZV<96, 128, 16, 1>{}, ZV<96, 512, 32, 1>{}, ZV<96, 256, 8, 1>{}, ZV<96, 512, 16, 1>{},
+                           ZV<96, 512, 8, 1>{}, ZV<96, 512, 8, 1, true>{}, ZV<96, 512, 16, 1, true>{});
             break;
         case 180:
-            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<180, 256, 16, 1>{}, ZV<180, 256, 8, 1>{},
-                           ZV<180, 512, 16, 1>{}, ZV<180, 512, 8, 1>{}, ZV<180, 512, 8, 1, true>{},
-                           ZV<180, 256, 8, 1, true>{}, ZV<180, 512, 16, 1, true>{});
+            launch_z_tuned(inverse, a, ncolmax, nbatch, n3, st, fp32, ZV<180, 256, 8, 1, true>{},
+                           ZV<180, 256, 16, 1>{}, ZV<180, 256, 8, 1>{}, ZV<180, 512, 16, 1>{}, ZV<180, 512, 8, 1>{},
+                           ZV<180, 512, 8, 1, true>{}, ZV<180, 512, 16, 1, true>{});
             break;
         default: throw Error{TM_EUNSUPPORTED, "no fixed-size z pass for this grid"};
     }
