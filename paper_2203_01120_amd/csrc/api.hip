@@ -533,7 +533,7 @@ static size_t plan_workspace(const System& s, int nrhs, Workspace& w) {
                                gemm_partial_elems(nb2, std::max(s.nproj, 1), 2 * nb, npw_pad));
     w.cap_gsmall = R * std::max((size_t)nb2 * nb * nb, (size_t)2 * nb2 * std::max(s.nproj, 1) * 2 * nb);
     w.bytes = (w.cap_xcols + w.cap_rho_part + w.cap_gpart + w.cap_gsmall + R * 9 * s.N) * sizeof(double2);
-    size_t all = w.bytes + (64 + 1024 * 8) * sizeof(double2);
+    size_t all = w.bytes + (64 + kPartBlocks * 8) * sizeof(double2);
     if (plane_fixed_supported(s.n1, s.n2)) all += R * 6 * s.N * sizeof(double2);
     return all;
 }
@@ -566,7 +566,7 @@ void ensure_workspace(System& s, const QSet&, int nrhs) {
     grab((void**)&w.W, R * 4 * s.N * sizeof(double2));
     grab((void**)&w.work, R * s.N * sizeof(double2));
     grab((void**)&w.dots, 64 * sizeof(double2));
-    grab((void**)&w.dotpart, 1024 * 8 * sizeof(double2));
+    grab((void**)&w.dotpart, kPartBlocks * 8 * sizeof(double2));
     if (plane_fixed_supported(s.n1, s.n2)) grab((void**)&w.fields, R * 6 * s.N * sizeof(double2));
     w.alloc_bytes = all;
     grab((void**)&w.rho, R * 4 * s.N * sizeof(double2));  // last: marks the workspace complete
@@ -745,7 +745,7 @@ Workspace scratch_workspace(const System& s, char* base, size_t cap) {
     w.W = take(4 * (size_t)s.N);
     w.work = take((size_t)s.N);
     w.dots = take(64);
-    w.dotpart = take(1024 * 8);
+    w.dotpart = take(kPartBlocks * 8);
     if (plane_fixed_supported(s.n1, s.n2)) w.fields = take(6 * (size_t)s.N);
     w.rho = take(4 * (size_t)s.N);
     w.width = 1;
