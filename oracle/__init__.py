@@ -14,6 +14,7 @@ it.  Everything here is plain, slow, obviously-correct NumPy/SciPy in FP64:
 * ``chi``         susceptibility from the tridiagonal matrix, plus Kubo K=0 sum
 
 Pins against things other than itself live in ``tests/test_oracle_*.py``.
-The SCF ground state (absolute energies of the synthetic system) is "parity
-unpinned" except through self-consistency and the Goldstone check.
+The SCF ground state is pinned by its homogeneous-electron-gas limit (closed
+form), self-consistency and the Goldstone check; the absolute energies of
+the atom-laden synthetic systems have no published values to compare with.
 """
