@@ -1381,7 +1381,7 @@ void launch_t(int op, const PlaneArgs& a, const PlaneTabs& t, dim3 grid, hipStre
     // density's row fill keeps all of a lane's loads in flight together
     // (FCH = 64, 10 % faster at 48 x 48); the 6-column apply would spill with it.
     constexpr int CPW32 = N2 == 20 ? 5 : 4, CPWA32 = N2 == 48 ? 6 : N2 == 20 ? 5 : 4;
-    constexpr int BTD = 2, BTA = 2;
+    constexpr int BTD = 2, BTA = N2 == 48 ? 1 : 2;  // 48: two butterflies per load group spill at 128 registers
     constexpr int NBUF32 = 2, MINW32 = 1, MINWA32 = N2 == 48 ? 4 : 1;
     constexpr int FCHD32 = 64, FCHA32 = 1;
     if (op == kOpUreal) {
