@@ -672,12 +672,15 @@ struct WRows {
 
 // columns c0 .. c0 + CPW - 1 of x planes 0 and 1; rows outside `mask` are
 // read as zero by a masked first stage
-template <int N1, int N2, int CPW>
+// (ILV: line li is spin plane li % 2 of column c0 + li / 2, so that the two
+// 16-lane groups of each half-wave hold one column of both spin planes)
+template <int N1, int N2, int CPW, bool ILV = false>
 struct WCols {
     static constexpr int ES = Geom<N1, N2>::N2P;
     int c0, boff;
     unsigned long long mask;
     __device__ int base(int li, int) const {
+        if constexpr (ILV) return boff + (li & 1) * Geom<N1, N2>::PS + c0 + (li >> 1);
         const int s = li / CPW;
         return boff + s * Geom<N1, N2>::PS + c0 + (li - s * CPW);
     }
@@ -713,6 +716,13 @@ struct WTail {
 template <int N1, int N2, int BT_, int CPW_, class T2, int NBUF_, int FCH_ = 64, bool FUSE_ = false>
 struct WaveKernel {
     using G = Geom<N1, N2>;
+    // FP64 48 x 48: the lines a wave works on together come in spin pairs (a
+    // row or a column of both planes in the two 16-lane groups of each
+    // half-wave).  The four lines of a 16-byte LDS access then take no extra
+    // cycles; adjacent columns or rows of one plane in those groups take 4
+    // extra cycles per access (measured with a probe).
+    static constexpr bool ILV = sizeof(T2) == 16 && N2 == 48;
+    using Cols = WCols<N1, N2, CPW_, ILV>;
     // FUSE: the row fill is fused with the first inverse row stage, and the last
     // forward row stage with the output (a row's values skip one LDS round trip
     // at each end)
@@ -723,6 +733,7 @@ struct WaveKernel {
     static constexpr int NT = 64 * NW;
     static constexpr int WPTS = CPW * N1;           // points of a wave (per plane)
     static constexpr int MAXR = cdiv(2 * N1, NW);   // row lines of a wave, at most
+    static_assert(!ILV || 2 * cdiv(N1, NW) <= MAXR, "row pairs of a wave");
     static constexpr int BUF = 2 * G::PS;           // one buffer: planes x_up, x_dn
     static constexpr int BT = BT_;                  // butterflies per load group
     static_assert(N2 % CPW == 0 && NW <= 16, "plane shape");
@@ -756,11 +767,24 @@ struct WaveKernel {
         const short* ci = t.colidx_kq[b];
         for (int i = threadIdx.x; i < N1; i += NT) m.perm1[i] = t.perm1[i];
         for (int i = threadIdx.x; i < N2; i += NT) m.perm2[i] = t.perm2[i];
-        for (int i = threadIdx.x; i < 2 * nrx; i += NT) {
-            const int s = i >= nrx;
-            const int row = rx[i - s * nrx];
-            m.rowbase[i] = s * G::PS + row * G::N2P;
-            m.rowinfo[i] = s * N1 + row;
+        if constexpr (ILV) {
+            // line l = w + k NW of wave w is spin k % 2 of row pair w + (k / 2) NW
+            for (int l = threadIdx.x; l < 2 * N1; l += NT) {
+                const int w = l % NW, k = l / NW;
+                const int pr = w + (k >> 1) * NW, s = k & 1;
+                if (pr < nrx) {
+                    const int row = rx[pr];
+                    m.rowbase[l] = s * G::PS + row * G::N2P;
+                    m.rowinfo[l] = s * N1 + row;
+                }
+            }
+        } else {
+            for (int i = threadIdx.x; i < 2 * nrx; i += NT) {
+                const int s = i >= nrx;
+                const int row = rx[i - s * nrx];
+                m.rowbase[i] = s * G::PS + row * G::N2P;
+                m.rowinfo[i] = s * N1 + row;
+            }
         }
         for (int i = threadIdx.x; i < N1 * N2; i += NT) m.colidx[i] = ci[i];
         __syncthreads();
@@ -769,6 +793,11 @@ struct WaveKernel {
 
     // row lines of wave w among nrl
     __device__ static int wave_rows(int nrl, int w) { return w < nrl ? (nrl - 1 - w) / NW + 1 : 0; }
+    // row lines of wave w for nrx occupied rows of each of the two planes
+    __device__ static int wave_lines(int nrx, int w) {
+        if constexpr (ILV) return 2 * wave_rows(nrx, w);
+        return wave_rows(2 * nrx, w);
+    }
 
     static constexpr int FIT = cdiv(MAXR * N2, 64);  // row elements per lane, at most
     static constexpr int FCH = FCH_ < FIT ? FCH_ : FIT;  // of them in flight together
@@ -1027,7 +1056,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a
     tw2.init(lane);
     const int nrx = K::setup(t, tb, m);
     const unsigned long long mask = t.rmask_kq[tb];
-    const int nlw = K::wave_rows(2 * nrx, w);
+    const int nlw = K::wave_lines(nrx, w);
     const long long cs = (long long)a.n3 * a.ncol_max;
     // the side's resident slot, read once (the loop's stores could alias it)
     const double2* ub = a.ureal + (long long)a.uslot[tb] * a.nb * a.n3 * 2 * G::NP + w * K::WPTS;
@@ -1068,7 +1097,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_density_w(PlaneArgs a
             K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
             __syncthreads();
             if constexpr (!EARLY) load_u();
-            WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
+            typename K::Cols cl{w * CPW, boff, mask};
             wfft_dif<N1, +1, true, 2 * CPW, K::BT, TL::cp.nrad - 1>(m.pl, cl, 2 * CPW, tw1, lane);
             // last inverse stage in registers, then the four density components
 #pragma unroll
@@ -1178,7 +1207,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
     tw2.init(lane);
     const int nrx = K::setup(t, tb, m);
     const unsigned long long mask = t.rmask_kq[tb];
-    const int nlw = K::wave_rows(2 * nrx, w);
+    const int nlw = K::wave_lines(nrx, w);
     // the bands of the block's chunks (the apply of a band does not depend on its chunk)
     const int n0 = blockIdx.y * a.cpb * a.bpc;
     const int n1e = min(a.nb, n0 + a.cpb * a.bpc);
@@ -1246,7 +1275,7 @@ __global__ void __launch_bounds__(64 * (N2 / CPW), MINW) k_apply_w(PlaneArgs a, 
             K::rows_inverse(m, cx, cs, nlw, w, boff, lane, tw2, rl);
         __syncthreads();
         // columns: inverse along i1, point-wise products, forward along i1
-        WCols<N1, N2, CPW> cl{w * CPW, boff, mask};
+        typename K::Cols cl{w * CPW, boff, mask};
         wfft_dif<N1, +1, true, 2 * CPW, K::BT>(m.pl, cl, 2 * CPW, tw1, lane);
 #pragma unroll
         for (int j = 0; j < PPL; ++j) {
