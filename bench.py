@@ -393,6 +393,10 @@ def serving_pool(tm, seed):
                                        synth.cart_from_frac(slab, [0.0, 0.25, 0.0])]), 1.0)}
 
 
+SERVING_LABELS = {"cubic20": "20^3/8/1k (cubic a=10 bohr)", "cubic24": "24^3/16/4k (cubic)",
+                  "cubic32": "32^3/32/9k (cubic)", "slab96": "48x48x96/64/16k (hexagonal slab a=13 c=16.5 bohr)"}
+
+
 def run_serving(args, tm, torch):
     """Poisson arrivals of chi requests on a pool of systems (serving_pool) that
     the server creates on demand and evicts under a device-memory budget that
@@ -406,6 +410,10 @@ def run_serving(args, tm, torch):
     import synth
     from paper_2203_01120_amd import serving as sv
     pool = serving_pool(tm, args.seed)
+    keep = [n for n in args.serving_systems.split(",") if n]
+    if not keep or set(keep) - set(pool):
+        raise SystemExit(f"--serving-systems: choose from {','.join(pool)}")
+    pool = {n: pool[n] for n in keep}
     specs = {}
     for name, (sysd, qs, _) in pool.items():
         def make(sysd=sysd, qs=qs):
@@ -474,9 +482,9 @@ def run_serving(args, tm, torch):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "serving: pool 20^3/8/1k, 24^3/16/4k, 32^3/32/9k (cubic a=10 bohr), "
-                               "48x48x96/64/16k (hexagonal slab a=13 c=16.5 bohr), drawn 8:4:2:1, "
-                               "500..3000 steps, pH|nH, x|y|z|+|-, chi on 400 omega; systems created on demand",
+        "config": {"workload": "serving: pool " + ", ".join(SERVING_LABELS[n] for n in names) + ", drawn "
+                               + ":".join(f"{pool[n][2]:g}" for n in names) + ", 500..3000 steps, pH|nH, "
+                               "x|y|z|+|-, chi on 400 omega; systems created on demand",
                    "rates_per_s": [r["rate_per_s"] for r in results], "requests_per_rate": args.requests,
                    "budget_GB": args.serving_budget, "resident_cap_GB": args.serving_resident_cap,
                    "lanes_per_chain_max": args.serving_lanes, "chains_per_system_max": args.serving_max_chains},
@@ -537,6 +545,8 @@ def main():
                     help="serving: device-memory budget in GB (system footprints + chains)")
     ap.add_argument("--serving-resident-cap", type=float, default=16.0,
                     help="serving: largest resident real-space ground state per system, GB")
+    ap.add_argument("--serving-systems", default="cubic20,cubic24,cubic32,slab96",
+                    help="serving: the systems of the pool that requests are drawn from (their weights kept)")
     ap.add_argument("--serving-lanes", type=int, default=4, choices=[1, 2, 3, 4],
                     help="serving: pending requests of one system, q set and flavour share a chain (lanes)")
     ap.add_argument("--chain-slots", type=int, default=3,
