@@ -70,3 +70,55 @@ def test_nan_in_inputs_is_rejected_before_the_device():
             assert "non-finite" in str(e)
         else:
             raise AssertionError("expected TM_EINVAL")
+
+
+def _footprint_case(fft, kmesh, q_frac, folded=False):
+    import sys
+    import synth
+    from oracle import liouvillian as lv
+    from oracle import scf
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_util import desc_from_problem
+    gs = scf.scf(synth.make_tiny(fft=fft, kmesh=kmesh, seed=11), tol=1e-10, beta=0.5)
+    if folded:   # q on the mesh: sister points folded onto it with Miller shifts
+        return desc_from_problem(lv.Problem(gs, synth.qset_folded(gs.sysd, q_frac)))
+    return desc_from_problem(lv.build_problem(gs, synth.cart_from_frac(gs.sysd, q_frac)))
+
+
+def test_footprint_from_the_descriptor_without_a_device():
+    """tm_system_footprint is host work (the serving scheduler admits by it
+    before a system exists).  Its resident and column figures follow the
+    layouts they describe, recomputed here from the descriptor alone:
+    * the resident real-space ground state holds one slot per distinct
+      (point, Miller shift, side) among the q sets' roles (X side: k, Y side:
+      -k), each nbnd bands x n3 planes x 2 spins x n1 n2 complex doubles; 0 on
+      grids without fixed-size plane kernels (10^3 here);
+    * the column cache holds, per side and k, nbnd bands x 2 spins x n3
+      planes x the largest number of distinct (m1, m2) columns among the k
+      and -k spheres, complex doubles."""
+    import numpy as np
+    import paper_2203_01120_amd as tm
+    cases = [((8, 8, 8), ((0.0, 0.0, 0.0),), (0.1, 0.05, 0.0), False),
+             ((8, 8, 8), ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0)), (0.5, 0.0, 0.0), True),
+             ((8, 8, 8), ((0.0, 0.0, 0.0), (0.5, 0.0, 0.0)), (0.1, 0.0, 0.0), False),
+             ((10, 10, 10), ((0.0, 0.0, 0.0),), (0.1, 0.0, 0.0), False)]
+    for fft, kmesh, qf, folded in cases:
+        d = _footprint_case(fft, kmesh, qf, folded)
+        got = tm.tm_system_footprint(d)
+        n1, n2, n3 = d.fft
+        roles = np.asarray(d.roles)
+        shifts = np.zeros(roles.shape + (3,), int) if d.shifts is None else np.asarray(d.shifts)
+        nq, nk = roles.shape[:2]
+        slots = {(int(roles[iq, ik, s]), tuple(int(v) for v in shifts[iq, ik, s]), s)
+                 for iq in range(nq) for ik in range(nk) for s in (0, 1)}
+        fixed = (n1, n2) in {(8, 8), (20, 20), (24, 24), (32, 32), (48, 48)}
+        want_res = len(slots) * d.nbnd * n3 * 2 * n1 * n2 * 16 if fixed else 0
+        ncol = [len({(int(a), int(b)) for a, b, _ in p.mill}) for p in d.points]
+        cols_u = max(max(ncol[roles[iq, ik, 0]], ncol[roles[iq, ik, 1]]) for iq in range(nq) for ik in range(nk))
+        want_cols = 2 * nk * 2 * d.nbnd * n3 * cols_u * 16
+        assert got["resident_full"] == want_res, (fft, kmesh, got, want_res)
+        assert got["columns_full"] == want_cols, (fft, kmesh, got, want_cols)
+        assert got["tables"] > 0 and got["workspace_per_rhs"] > 0
+        assert got["resident"] == got["columns"] == got["workspace"] == got["chain_slots"] == 0
+        if folded:
+            assert np.any(shifts != 0)   # the shift is part of a slot's identity
