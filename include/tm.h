@@ -137,8 +137,10 @@ typedef struct {
  * Returns TM_EINVAL for inconsistent input (e.g. the sphere of -k-q is not the
  * negative of the sphere of k+q) and for a NaN or Inf in any floating-point
  * input (checked on the host before the device is touched), TM_EUNSUPPORTED
- * for unsupported grid sizes,
- * TM_ENOMEM / TM_EDEVICE for device failures.  *out owns all device memory.
+ * for unsupported grid sizes (a length with a prime factor other than 2, 3, 5,
+ * or planes of more than 4096 points; also checked before the device is
+ * touched), TM_ENOMEM / TM_EDEVICE for device failures.  *out owns all device
+ * memory.
  */
 int tm_system_create(const tm_system_desc* desc, tm_system** out);
 
@@ -198,7 +200,9 @@ int tm_system_memory(const tm_system* sys, tm_memory_info* out);
  * (host work only, nothing is allocated): resident_full, columns_full and
  * workspace_per_rhs as tm_system_memory will report them; tables an upper
  * estimate (its items summed, 5 % and 1 MiB added); the "now held"
- * fields and chain_slots are 0.  TM_EINVAL on a null or empty descriptor.
+ * fields and chain_slots are 0.  TM_EINVAL on a null or empty descriptor;
+ * TM_EUNSUPPORTED for a grid tm_system_create refuses (a length with a prime
+ * factor other than 2, 3, 5, or planes of more than 4096 points).
  */
 int tm_system_footprint(const tm_system_desc* desc, tm_memory_info* out);
 

@@ -144,6 +144,18 @@ bool make_radices(int n, FFTPlan& p) {
 
 namespace {
 
+// Grid lengths the kernels take (host check, no device needed): positive,
+// products of 2, 3 and 5, and planes of at most 4096 points.
+void check_grid(const int* fft) {
+    for (int i = 0; i < 3; ++i) {
+        TM_CHECK(fft[i] > 0, TM_EINVAL, "FFT lengths must be positive");
+        FFTPlan p;
+        TM_CHECK(make_radices(fft[i], p), TM_EUNSUPPORTED, "FFT length must factor into 2, 3, 5");
+    }
+    TM_CHECK((long long)fft[0] * fft[1] <= 4 * 1024, TM_EUNSUPPORTED,
+             "n1*n2 above 4096 is not supported by the plane kernels");
+}
+
 inline long long mkey(int a, int b, int c) {
     return ((long long)(a + (1 << 20)) << 42) | ((long long)(b + (1 << 20)) << 21) | (long long)(c + (1 << 20));
 }
@@ -1575,6 +1587,7 @@ int tm_system_create(const tm_system_desc* d, tm_system** out) {
         // host-side validation first: it needs no device
         TM_CHECK(d->nbnd > 0 && d->npts > 0 && d->nq >= 0 && d->nk > 0, TM_EINVAL, "bad sizes");
         TM_CHECK(d->fft[0] > 0 && d->fft[1] > 0 && d->fft[2] > 0, TM_EINVAL, "bad FFT grid");
+        check_grid(d->fft);
         TM_CHECK(d->nproj >= 0, TM_EINVAL, "bad nproj");
         TM_CHECK(d->npw && d->mill && d->evc && d->et, TM_EINVAL, "missing ground-state points");
         check_finite(d);
@@ -1768,7 +1781,7 @@ int tm_system_footprint(const tm_system_desc* d, tm_memory_info* out) {
     return guarded([&]() -> int {
         TM_CHECK(d && out, TM_EINVAL, "null argument");
         TM_CHECK(d->nbnd > 0 && d->npts > 0 && d->nq > 0 && d->nk > 0, TM_EINVAL, "empty system");
-        for (int c = 0; c < 3; ++c) TM_CHECK(d->fft[c] > 0, TM_EINVAL, "FFT lengths must be positive");
+        check_grid(d->fft);
         System s;
         s.n1 = d->fft[0];
         s.n2 = d->fft[1];

@@ -122,3 +122,29 @@ def test_footprint_from_the_descriptor_without_a_device():
         assert got["resident"] == got["columns"] == got["workspace"] == got["chain_slots"] == 0
         if folded:
             assert np.any(shifts != 0)   # the shift is part of a slot's identity
+
+
+def test_unsupported_grids_refused_on_the_host():
+    """Grid lengths with a prime factor other than 2, 3, 5, or planes of more
+    than 4096 points: tm_system_create refuses them with TM_EUNSUPPORTED before
+    it looks for a device, and tm_system_footprint refuses the same grids (the
+    scheduler must not charge the budget for a system that cannot exist)."""
+    import numpy as np
+    import paper_2203_01120_amd as tm
+
+    def desc(fft):
+        return tm.SystemDesc(cell=np.eye(3) * 5, fft=fft, nbnd=1,
+                             points=[tm.Point(xk=np.zeros(3), mill=np.zeros((1, 3), np.int32),
+                                              evc=np.ones((1, 2, 1), complex), et=np.zeros(1))],
+                             vrs=np.zeros((4,) + tuple(fft)), rho=np.zeros((4,) + tuple(fft)), dvan=None,
+                             xq=np.zeros((1, 3)), roles=np.zeros((1, 1, 4), np.int32))
+
+    for fft in ((7, 8, 8), (8, 8, 14), (48, 96, 8)):
+        for call in (tm.tm_system_create, tm.tm_system_footprint):
+            try:
+                call(desc(fft))
+            except tm.TmError as e:
+                assert e.code == -5, (fft, call.__name__, e.code)
+            else:
+                raise AssertionError(f"{call.__name__} accepted the grid {fft}")
+    assert tm.tm_system_footprint(desc((8, 8, 30)))["tables"] > 0   # 2 x 3 x 5 is fine
