@@ -323,14 +323,18 @@ class Server:
             if slot is not None and self.max_chains and len(slot.active) >= self.max_chains:
                 i += 1
                 continue
-            sysb = 0 if slot is not None else self.pool.footprint(head.system)
+            try:
+                sysb = 0 if slot is not None else self.pool.footprint(head.system)
+            except tb.TmError as e:
+                # the library refuses the system (e.g. an unsupported grid): fail
+                # its request rather than the server
+                del self.pending[i]
+                self._fail(head, f"system cannot be created: {e}")
+                continue
             if sysb + self._bytes([head]) > self.budget:
                 # can never fit: fail it rather than block the queue
                 del self.pending[i]
-                head.error = "does not fit the device-memory budget"
-                head.chi = np.full((3, len(head.omega)), np.nan, dtype=np.complex128)
-                head.t_admit = head.t_done = self.now()
-                self.done.append(head)
+                self._fail(head, "does not fit the device-memory budget")
                 continue
             del self.pending[i]
             group = self._group(head, self.budget - self.used - sysb)
@@ -352,6 +356,12 @@ class Server:
             for r in group:
                 r.t_admit = now
             slot.active.append(_Active(group, h, head.flavour, cap, 0, nb, [False] * len(group)))
+
+    def _fail(self, req: Request, msg: str) -> None:
+        req.error = msg
+        req.chi = np.full((3, len(req.omega)), np.nan, dtype=np.complex128)
+        req.t_admit = req.t_done = self.now()
+        self.done.append(req)
 
     def _finish_lanes(self, a: _Active) -> None:
         """Finishes every request whose lane has run its steps."""
@@ -472,9 +482,13 @@ def run_one_at_a_time(systems: Dict[str, SystemSlot], requests: List[Request], s
             req.t_admit = time.perf_counter() - t0
             nb = chain_bytes(pool.systems[req.system].nelem[req.iq] if req.system in pool.systems
                              else _nelem_of_desc(pool.desc(req.system), req.iq), req.flavour, req.nsteps)
-            slot = pool.acquire(req.system, nb)
+            try:
+                slot = pool.acquire(req.system, nb)
+                err = None if slot is not None else "does not fit the device-memory budget"
+            except tb.TmError as e:
+                slot, err = None, f"system cannot be created: {e}"
             if slot is None:
-                req.error = "does not fit the device-memory budget"
+                req.error = err
                 req.chi = np.full((3, len(req.omega)), np.nan, dtype=np.complex128)
             else:
                 try:
