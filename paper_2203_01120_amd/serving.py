@@ -339,7 +339,13 @@ class Server:
             del self.pending[i]
             group = self._group(head, self.budget - self.used - sysb)
             nb = self._bytes(group)
-            slot = self.pool.acquire(head.system, nb)
+            try:
+                slot = self.pool.acquire(head.system, nb)
+            except tb.TmError as e:
+                # creation failed (nothing was charged): this request fails, its
+                # would-be partners stay pending
+                self._fail(head, f"system cannot be created: {e}")
+                continue
             if slot is None:
                 self.pending.insert(i, head)
                 return

@@ -53,9 +53,10 @@ class FakeLib:
 
     # ---- set-up of fake systems --------------------------------------------
     def add(self, name, nk, nbnd, npw, nq=1, tables=1 * GB, resident=4 * GB, columns=2 * GB, ws=1 * GB,
-            breakdown=None, refused=False):
+            breakdown=None, refused=False, create_fails=False):
         """breakdown: {(iq, direction, flavour): step at which that lane stops};
-        refused: the library refuses the system (as for an unsupported grid)"""
+        refused: the library refuses the system (as for an unsupported grid);
+        create_fails: its footprint is known but creation fails (out of memory)"""
         pts = [SimpleNamespace(mill=np.zeros((npw, 3), dtype=int)) for _ in range(nq + 1)]
         roles = np.zeros((nq, nk, 4), dtype=int)
         for jq in range(nq):
@@ -64,7 +65,7 @@ class FakeLib:
         self.specs[name] = dict(nelem=2 * nk * nbnd * 2 * ((npw + 15) // 16 * 16), nq=nq,
                                 mem=dict(tables=tables, resident_full=resident, columns_full=columns,
                                          workspace_per_rhs=ws),
-                                breakdown=dict(breakdown or {}), refused=refused)
+                                breakdown=dict(breakdown or {}), refused=refused, create_fails=create_fails)
         return desc
 
     def _check_budget(self):
@@ -76,6 +77,8 @@ class FakeLib:
     def tm_system_create(self, d):
         if self.specs[d.name]["refused"]:
             raise self.TmError(-5, "FFT length must factor into 2, 3, 5")
+        if self.specs[d.name]["create_fails"]:
+            raise self.TmError(-2, "device allocation failed")
         self._check_budget()
         self.next += 1
         self.systems[self.next] = dict(name=d.name, limit=-1, stepped=False)
@@ -381,21 +384,23 @@ def test_error_in_a_round_ends_every_chain(fake):
 
 def test_a_system_the_library_refuses_fails_only_its_requests(fake):
     """A spec system whose footprint query (and creation) the library refuses,
-    as for a grid length with a prime factor other than 2, 3, 5: its requests
-    finish with an error and chi = NaN; the other requests run, in the server
-    and one at a time alike."""
+    as for a grid length with a prime factor other than 2, 3, 5, and one whose
+    creation fails (out of device memory) after its footprint was admitted:
+    their requests finish with an error and chi = NaN, nothing stays charged,
+    and the other requests run, in the server and one at a time alike."""
     d = fake.add("A", nk=1, nbnd=4, npw=64)
     dbad = fake.add("BAD", nk=1, nbnd=4, npw=64, refused=True)
-    specs = {"BAD": sv.SystemSpec(make_desc=lambda: dbad)}
+    doom = fake.add("OOM", nk=1, nbnd=4, npw=64, create_fails=True)
+    specs = {"BAD": sv.SystemSpec(make_desc=lambda: dbad), "OOM": sv.SystemSpec(make_desc=lambda: doom)}
     slot = sv.SystemSlot(handle=fake.tm_system_create(d), nelem={0: fake.specs["A"]["nelem"]})
-    reqs = [_req(0, "BAD", 0, "+", "pH", 12), _req(1, "A", 0, "+", "pH", 12), _req(2, "BAD", 0, "z", "nH", 6),
-            _req(3, "A", 0, "z", "nH", 9)]
+    reqs = [_req(0, "BAD", 0, "+", "pH", 12), _req(1, "A", 0, "+", "pH", 12), _req(2, "OOM", 0, "z", "nH", 6),
+            _req(3, "A", 0, "z", "nH", 9), _req(4, "OOM", 0, "+", "nH", 6)]
     srv = _server(fake, {"A": slot}, 64 * GB, specs=specs, lanes=2)
     base = srv.used
     out = {r.rid: r for r in srv.run(_copy(reqs))}
     ref = {r.rid: r for r in sv.run_one_at_a_time({"A": slot}, _copy(reqs), specs=specs, budget_bytes=64 * GB)}
     for res in (out, ref):
-        for rid in (0, 2):
+        for rid in (0, 2, 4):
             assert "cannot be created" in res[rid].error and np.all(np.isnan(res[rid].chi))
         for rid in (1, 3):
             assert res[rid].error is None and res[rid].coeffs["steps_done"] == reqs[rid].nsteps
