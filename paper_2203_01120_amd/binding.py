@@ -174,6 +174,43 @@ class SystemDesc:
     keep: list = field(default_factory=list)
 
 
+def _check_shapes(d: SystemDesc, nproj: int) -> None:
+    """The extents the library reads through the descriptor's plain pointers
+    (ValueError otherwise, before any pointer is handed over): per point
+    mill (npw, 3), evc (>= nbnd, 2, npw) (the first nbnd bands are read), et
+    (>= nbnd,), vkb (nproj, npw); vrs and rho (4, n1, n2, n3); dvan
+    (nproj, nproj, 2, 2); roles (nq, nk, 4) indexing the points; shifts
+    (nq, nk, 4, 3)."""
+    def need(ok, msg):
+        if not ok:
+            raise ValueError(msg)
+    fft = tuple(int(x) for x in d.fft)
+    nb = int(d.nbnd)
+    need(len(fft) == 3 and len(d.points) > 0, "fft needs 3 lengths and there must be ground-state points")
+    for i, p in enumerate(d.points):
+        mill, evc, et = np.asarray(p.mill), np.asarray(p.evc), np.asarray(p.et)
+        need(mill.ndim == 2 and mill.shape[1] == 3, f"point {i}: mill must be (npw, 3)")
+        npw = mill.shape[0]
+        need(np.asarray(p.xk).size == 3, f"point {i}: xk must hold 3 components")
+        need(evc.ndim == 3 and evc.shape[0] >= nb and evc.shape[1:] == (2, npw),
+             f"point {i}: evc must be (>= nbnd, 2, npw) = (>= {nb}, 2, {npw}), got {evc.shape}")
+        need(et.ndim == 1 and et.shape[0] >= nb, f"point {i}: et must hold at least nbnd = {nb} values")
+        if nproj:
+            need(p.vkb is not None and np.asarray(p.vkb).shape == (nproj, npw),
+                 f"point {i}: vkb must be (nproj, npw) = ({nproj}, {npw})")
+    for name in ("vrs", "rho"):
+        need(np.asarray(getattr(d, name)).shape == (4,) + fft, f"{name} must be (4, n1, n2, n3) = {(4,) + fft}")
+    if nproj:
+        need(np.asarray(d.dvan).shape == (nproj, nproj, 2, 2), "dvan must be (nproj, nproj, 2, 2)")
+    nq = np.atleast_2d(d.xq).shape[0]
+    need(np.atleast_2d(d.xq).shape[1] == 3, "xq must be (nq, 3)")
+    roles = np.asarray(d.roles)
+    need(roles.ndim == 3 and roles.shape[0] == nq and roles.shape[2] == 4, "roles must be (nq, nk, 4)")
+    need(roles.size > 0 and roles.min() >= 0 and roles.max() < len(d.points), "roles must index the points")
+    if d.shifts is not None:
+        need(np.asarray(d.shifts).shape == roles.shape + (3,), "shifts must be (nq, nk, 4, 3)")
+
+
 def _marshal_desc(d: SystemDesc, keep: list):
     """A tm_system_desc over host arrays of d (kept alive in `keep`)."""
 
@@ -184,6 +221,7 @@ def _marshal_desc(d: SystemDesc, keep: list):
 
     npts = len(d.points)
     nproj = 0 if d.dvan is None else int(d.dvan.shape[0])
+    _check_shapes(d, nproj)
     desc = _Desc()
     desc.cell[:] = list(np.asarray(d.cell, dtype=float).ravel())
     desc.fft[:] = [int(x) for x in d.fft]

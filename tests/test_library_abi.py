@@ -148,3 +148,44 @@ def test_unsupported_grids_refused_on_the_host():
             else:
                 raise AssertionError(f"{call.__name__} accepted the grid {fft}")
     assert tm.tm_system_footprint(desc((8, 8, 30)))["tables"] > 0   # 2 x 3 x 5 is fine
+
+
+def test_descriptor_extents_checked_before_the_library_reads_them():
+    """The library reads the descriptor's arrays through plain pointers, so
+    the binding checks their extents first: each too-short or misshapen array
+    raises ValueError (never reaches the library), a valid one passes."""
+    import numpy as np
+    import pytest
+    import paper_2203_01120_amd as tm
+
+    fft = (4, 4, 4)
+
+    def desc(**over):
+        pt = dict(xk=np.zeros(3), mill=np.zeros((2, 3), np.int32), evc=np.ones((1, 2, 2), complex),
+                  et=np.zeros(1), vkb=np.ones((2, 2), complex))
+        pt.update(over.pop("pt", {}))
+        kw = dict(cell=np.eye(3) * 5, fft=fft, nbnd=1, points=[tm.Point(**pt)], vrs=np.zeros((4,) + fft),
+                  rho=np.zeros((4,) + fft), dvan=np.zeros((2, 2, 2, 2), complex), xq=np.zeros((1, 3)),
+                  roles=np.zeros((1, 1, 4), np.int32), shifts=np.zeros((1, 1, 4, 3), np.int32))
+        kw.update(over)
+        return tm.SystemDesc(**kw)
+
+    assert tm.tm_system_footprint(desc())["tables"] > 0
+    bad = [dict(pt=dict(evc=np.ones((1, 2, 1), complex))),      # fewer coefficients than the sphere
+           dict(pt=dict(evc=np.ones((1, 1, 2), complex))),      # one spin component
+           dict(nbnd=2),                                        # evc and et hold one band
+           dict(pt=dict(et=np.zeros(0))),
+           dict(pt=dict(mill=np.zeros((2, 2), np.int32))),
+           dict(pt=dict(vkb=np.ones((1, 2), complex))),         # dvan says 2 projectors
+           dict(pt=dict(vkb=None)),
+           dict(vrs=np.zeros((4, 4, 4))),
+           dict(rho=np.zeros((3,) + fft)),
+           dict(dvan=np.zeros((2, 2, 2), complex)),
+           dict(roles=np.ones((1, 1, 4), np.int32)),            # points 0 .. 0 only
+           dict(roles=np.zeros((2, 1, 4), np.int32)),           # two q sets, one q vector
+           dict(shifts=np.zeros((1, 1, 4), np.int32))]
+    for over in bad:
+        with pytest.raises(ValueError):
+            tm.tm_system_footprint(desc(**over))
+        with pytest.raises(ValueError):
+            tm.tm_system_create(desc(**over))
