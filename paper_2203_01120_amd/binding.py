@@ -420,6 +420,14 @@ def _coeffs_in(coeffs: dict):
     zn = coeffs.get("zn")
     if zn is not None:
         keep["zn"] = np.ascontiguousarray(zn, dtype=np.complex128)
+    # the library reads every array to the capacity (alpha's length): check
+    # their extents before handing the pointers over
+    cap = keep["alpha"].shape[0] if keep["alpha"].ndim == 1 else -1
+    shapes = {k: v.shape for k, v in keep.items()}
+    if (cap < 1 or shapes["beta"] != (cap,) or shapes["gamma"] != (cap,) or shapes["z"] != (3, cap)
+            or shapes.get("zn", (cap,)) != (cap,) or not 0 <= int(coeffs["steps_done"]) <= cap):
+        raise ValueError(f"coefficients must be alpha, beta, gamma (M,), z (3, M), zn (M,) with "
+                         f"0 <= steps_done <= M; got {shapes}, steps_done {coeffs['steps_done']}")
     co = _Coeffs(keep["alpha"].shape[0], int(coeffs["steps_done"]), float(coeffs["n1"]), _cptr(keep["alpha"]),
                  _cptr(keep["beta"]), _cptr(keep["gamma"]), _cptr(keep["z"]),
                  _cptr(keep["zn"]) if "zn" in keep else None)

@@ -189,3 +189,30 @@ def test_descriptor_extents_checked_before_the_library_reads_them():
             tm.tm_system_footprint(desc(**over))
         with pytest.raises(ValueError):
             tm.tm_system_create(desc(**over))
+
+
+def test_coefficient_extents_checked_before_the_library_reads_them():
+    """tm_chi and its variants read alpha, beta, gamma, z[3] and zn up to the
+    capacity (alpha's length): inconsistent arrays raise ValueError in the
+    binding, before any pointer reaches the library."""
+    import numpy as np
+    import pytest
+    import paper_2203_01120_amd as tm
+    M = 6
+
+    def co(**over):
+        d = dict(alpha=np.zeros(M, complex), beta=np.ones(M), gamma=np.ones(M, complex),
+                 z=np.zeros((3, M), complex), zn=np.zeros(M, complex), n1=1.0, steps_done=M)
+        d.update(over)
+        return d
+
+    w = np.zeros(3)
+    for bad in (dict(beta=np.ones(M - 1)), dict(gamma=np.ones(M + 1, complex)), dict(z=np.zeros((3, M - 1), complex)),
+                dict(z=np.zeros((2, M), complex)), dict(zn=np.zeros(M - 2, complex)), dict(steps_done=M + 1),
+                dict(alpha=np.zeros((1, M), complex))):
+        with pytest.raises(ValueError):
+            tm.tm_chi(co(**bad), 1, w, 0.1)
+        with pytest.raises(ValueError):
+            tm.tm_chi_extrapolated(co(**bad), 1, 10, "constant", w, 0.1)
+        with pytest.raises(ValueError):
+            tm.tm_chi_tensor(co(**bad), 1, w, 0.1)
