@@ -550,7 +550,7 @@ def tm_chain_end(chain) -> None:
 def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:
     """chi[l][w] for l = x, y, z from the Lanczos coefficients (runs on the GPU)."""
     co, _keep = _coeffs_in(coeffs)
-    om = np.ascontiguousarray(omega, dtype=np.float64)
+    om = _omega(omega)
     out = np.zeros((3, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi(C.byref(co), int(m_use), _dptr(om), om.shape[0], float(eta),
                          out.ctypes.data_as(C.POINTER(C.c_double))))
@@ -560,10 +560,17 @@ def tm_chi(coeffs: dict, m_use: int, omega, eta: float) -> np.ndarray:
 EXTRAP = {"no": 0, "constant": 1, "osc": 2}
 
 
+def _omega(omega) -> np.ndarray:
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    if om.ndim != 1:
+        raise ValueError(f"omega must be a 1-D frequency grid, got shape {om.shape}")
+    return om
+
+
 def tm_chi_extrapolated(coeffs: dict, m_use: int, m_total: int, mode: str, omega, eta: float) -> np.ndarray:
     """chi[l][w] with the tridiagonal matrix extended to m_total ('no', 'constant', 'osc')."""
     co, _keep = _coeffs_in(coeffs)
-    om = np.ascontiguousarray(omega, dtype=np.float64)
+    om = _omega(omega)
     out = np.zeros((3, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi_extrapolated(C.byref(co), int(m_use), int(m_total), EXTRAP[mode], _dptr(om),
                                       om.shape[0], float(eta), out.ctypes.data_as(C.POINTER(C.c_double))))
@@ -573,7 +580,7 @@ def tm_chi_extrapolated(coeffs: dict, m_use: int, m_total: int, mode: str, omega
 def tm_chi_tensor(coeffs: dict, m_use: int, omega, eta: float, m_total: int = 0, mode: str = "no") -> np.ndarray:
     """One column of the 4 x 4 susceptibility: chi[l][w], rows l = n, x, y, z."""
     co, _keep = _coeffs_in(coeffs)
-    om = np.ascontiguousarray(omega, dtype=np.float64)
+    om = _omega(omega)
     out = np.zeros((4, om.shape[0]), dtype=np.complex128)
     _check(load().tm_chi_tensor(C.byref(co), int(m_use), int(m_total or m_use), EXTRAP[mode], _dptr(om),
                                 om.shape[0], float(eta), out.ctypes.data_as(C.POINTER(C.c_double))))
@@ -584,7 +591,8 @@ def tm_structure_factor(q, chi) -> np.ndarray:
     """S(q, w) = -Im Tr[P_perp(q) chi(w)] from chi[lambda][mu][w] (complex 3 x 3 x nomega)."""
     qv = np.ascontiguousarray(q, dtype=np.float64)
     ch = np.ascontiguousarray(chi, dtype=np.complex128)
-    assert ch.shape[:2] == (3, 3)
+    if qv.size != 3 or ch.ndim != 3 or ch.shape[:2] != (3, 3):
+        raise ValueError(f"q must hold 3 components and chi be (3, 3, nomega); got {qv.shape}, {ch.shape}")
     out = np.zeros(ch.shape[2])
     _check(load().tm_structure_factor(_dptr(qv), ch.ctypes.data_as(C.POINTER(C.c_double)), ch.shape[2],
                                       _dptr(out)))

@@ -216,3 +216,21 @@ def test_coefficient_extents_checked_before_the_library_reads_them():
             tm.tm_chi_extrapolated(co(**bad), 1, 10, "constant", w, 0.1)
         with pytest.raises(ValueError):
             tm.tm_chi_tensor(co(**bad), 1, w, 0.1)
+
+
+def test_frequency_grid_and_tensor_shapes_checked_in_the_binding():
+    """A frequency grid must be 1-D (a scalar is a one-point grid); S(q, w)
+    needs three components of q and chi of shape (3, 3, nomega)."""
+    import numpy as np
+    import pytest
+    import paper_2203_01120_amd as tm
+    co = dict(alpha=np.zeros(2, complex), beta=np.ones(2), gamma=np.ones(2, complex), z=np.zeros((3, 2), complex),
+              n1=1.0, steps_done=2)
+    for call in (lambda w: tm.tm_chi(co, 2, w, 0.1), lambda w: tm.tm_chi_extrapolated(co, 2, 4, "constant", w, 0.1),
+                 lambda w: tm.tm_chi_tensor(co, 2, w, 0.1)):
+        with pytest.raises(ValueError):
+            call(np.zeros((2, 3)))
+    with pytest.raises(ValueError):
+        tm.tm_structure_factor(np.zeros(2), np.zeros((3, 3, 4), complex))
+    with pytest.raises(ValueError):
+        tm.tm_structure_factor(np.ones(3), np.zeros((3, 4), complex))
